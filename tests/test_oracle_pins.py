@@ -1,0 +1,366 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed form,
+a worked example, a textbook/library routine (brute force, assignment, LP,
+Sinkhorn), an identity or an error bound stated in the paper, or finite
+differences.  CPU only.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize_scalar
+from scipy.special import logsumexp
+
+from oracle import exact
+from oracle import lamp as L
+from oracle import stream
+from paper_2511_11359_amd import workloads as W
+
+
+def _problem(n, m, d, seed, uniform=False):
+    wl = W.random_small(n, m, d, seed, uniform=uniform)
+    x, y = wl.x.astype(np.float64), wl.y.astype(np.float64)
+    s = 1.0 / L.max_sqdist(x, y)
+    C = L.sqeuclid_cost(x, y, s)
+    return C, wl.r, wl.c, x, y, s
+
+
+# ---------------------------------------------------------------- schedule
+
+
+@pytest.mark.parametrize("eta", [0.0, 1e-3, 1e-2, 0.3])
+def test_inverse_temperature_closed_form(eta):
+    """eta_t^-1 = (1 - (1 - tau1 eta)^t)/eta, -> tau1 t as eta -> 0 (remark after Alg. 2)."""
+    tau1 = 0.5
+    lam = L.inv_eta_schedule(400, tau1, eta)
+    t = np.arange(401)
+    ref = tau1 * t if eta == 0 else (1.0 - (1.0 - tau1 * eta) ** t) / eta
+    assert lam[1] == pytest.approx(tau1, rel=1e-15)
+    np.testing.assert_allclose(lam, ref, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------- mirror maps
+
+
+def test_dual_mirror_map_is_the_argmax():
+    """The closed form (def:closed_form_opt) maximises tau<grad G, theta> - D_{H_c^alpha}(theta||theta0)
+    coordinate by coordinate (def:mirror_maps); solved here by a bounded 1-D search."""
+    g = np.random.default_rng(0)
+    m, cnorm, tau = 7, 1.7, 0.3
+    c = g.dirichlet(np.ones(m))
+    calpha = c + 0.01 / m
+    theta0 = g.uniform(-0.8, 0.8, m)
+    colp = g.dirichlet(np.ones(m))
+    closed = L.dual_mirror_map(theta0, colp, c, calpha, tau, cnorm)
+    grad = 2.0 * cnorm * (colp - c)      # gradient of K(X, .) in theta (problem spp)
+    for j in range(m):
+        def neg(th):
+            a = (th + 1) / 2 * math.log((th + 1) / (theta0[j] + 1))
+            b = (1 - th) / 2 * math.log((1 - th) / (1 - theta0[j]))
+            return -(tau * grad[j] * th - calpha[j] * (a + b))
+        res = minimize_scalar(neg, bounds=(-1 + 1e-12, 1 - 1e-12), method="bounded",
+                              options=dict(xatol=1e-13))
+        assert res.x == pytest.approx(closed[j], abs=1e-7)
+
+
+def test_primal_mirror_map_optimality_conditions():
+    """M_tau^eta(p0; theta) (def:closed_form_opt) satisfies the optimality conditions of its
+    definition (def:mirror_maps): within each row, tau r_i (C + eta(log p0 + 1) + K theta)_ij
+    + r_i log(p_ij / p0_ij) is constant in j, and p is row-stochastic."""
+    g = np.random.default_rng(1)
+    n, m, tau, eta, cnorm = 4, 6, 0.4, 0.05, 2.0
+    C = g.random((n, m)) * cnorm
+    r = g.dirichlet(np.ones(n))
+    p0 = g.dirichlet(np.ones(m), size=n)
+    theta = g.uniform(-1, 1, m)
+    p = L.primal_mirror_map(p0, theta, C, tau, eta, cnorm)
+    np.testing.assert_allclose(p.sum(axis=1), 1.0, atol=1e-14)
+    grad = r[:, None] * (C + eta * (np.log(p0) + 1.0) + 2.0 * cnorm * theta[None, :])
+    stat = tau * grad + r[:, None] * np.log(p / p0)
+    np.testing.assert_allclose(stat - stat[:, :1], 0.0, atol=1e-12)
+
+
+def test_lemma_primal_md_eq_dual_avg():
+    """p^{eta'}(theta') = M_tau^eta(p^gamma(theta_a); theta_b) with eta' = gamma/(1 + tau(gamma - eta)),
+    theta' = theta_a + tau eta' (theta_b - theta_a)  (Lemma primal_md_eq_dual_avg)."""
+    g = np.random.default_rng(2)
+    n, m, cnorm = 5, 8, 1.3
+    C = g.random((n, m)) * cnorm
+    for eta, gamma, tau in [(0.0, 0.7, 0.4), (0.05, 0.2, 0.5), (0.5, 3.0, 1.9)]:
+        assert tau * eta <= 1
+        ta, tb = g.uniform(-1, 1, m), g.uniform(-1, 1, m)
+        eta_p = gamma / (1.0 + tau * (gamma - eta))
+        theta_p = ta + tau * eta_p * (tb - ta)
+        lhs = L.dual_to_primal(C, theta_p, 1.0 / eta_p, cnorm)
+        rhs = L.primal_mirror_map(L.dual_to_primal(C, ta, 1.0 / gamma, cnorm), tb, C, tau, eta, cnorm)
+        np.testing.assert_allclose(lhs, rhs, rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------- LAMP == PDMP
+
+
+@pytest.mark.parametrize("eta", [0.0, 1e-3, 1e-2, 0.2])
+def test_lamp_equals_pdmp(eta):
+    """p^t = p^{eta_t}(nu^t) and pbar^{t+1} = p^{eta_{t+1}}(nubar^{t+1}) (Proposition equivalence):
+    Algorithm 2 (dual-only) against Algorithm 1 (explicit primal iterates), n != m."""
+    C, r, c, *_ = _problem(9, 6, 2, seed=3)
+    cnorm = float(C.max())
+    prm = L.Params(eta=eta)
+    T = 60
+    ps, pbars, thetas = L.pdmp_dense(C, r, c, prm, T, cnorm)
+    st, tr = L.lamp_dense(C, r, c, prm, T, cnorm)
+    lam = L.inv_eta_schedule(T, prm.resolved(cnorm).tau1, eta)
+    nu = np.zeros(6)
+    for t in range(T):
+        np.testing.assert_allclose(L.dual_to_primal(C, nu, lam[t], cnorm), ps[t], rtol=1e-10, atol=1e-13)
+        np.testing.assert_allclose(L.dual_to_primal(C, tr.nubar[t], lam[t + 1], cnorm), pbars[t + 1],
+                                   rtol=1e-10, atol=1e-13)
+        np.testing.assert_allclose(tr.theta[t], thetas[t + 1], atol=1e-12)
+        nu = tr.nu[t]
+
+
+def test_first_iterate_closed_form():
+    """eta_0 = inf: p^{eta_0}(0) = 1/m, so col(X^0) = 1/m, thetabar^1 = tanh(kappa (1/m - c)/c^alpha),
+    w_1 = 1 so nu^1 = thetabar^1 and nubar^1 = theta^0 = 0 (Alg. 2, proof of Prop. equivalence)."""
+    C, r, c, *_ = _problem(7, 5, 3, seed=4)
+    cnorm = float(C.max())
+    prm = L.Params(eta=1e-3)
+    st, tr = L.lamp_dense(C, r, c, prm, 1, cnorm)
+    m = 5
+    calpha = c + 0.01 / m
+    kappa = 2 * (1 / (2 * cnorm)) * cnorm
+    np.testing.assert_allclose(tr.colA[0], np.full(m, 1.0 / m), rtol=1e-14)
+    np.testing.assert_allclose(tr.theta_bar[0], np.tanh(kappa * (1 / m - c) / calpha), rtol=1e-13)
+    np.testing.assert_allclose(st.nu, tr.theta_bar[0], rtol=1e-13)
+    np.testing.assert_array_equal(tr.nubar[0], np.zeros(m))
+    np.testing.assert_allclose(tr.logZA[0], np.full(7, math.log(m)), rtol=1e-14)
+
+
+def test_symmetric_two_by_two_worked_example():
+    """C = [[0,1],[1,0]], r = c = (1/2, 1/2), eta = 0: by symmetry col(X^t) = c, so theta = nu = 0
+    for all t, lam_t = t/2 and <C, X^t> = e^{-t/2}/(1 + e^{-t/2}); the bound of Proposition
+    infeas_bound(a) is 2 log 2 / t."""
+    C = np.array([[0.0, 1.0], [1.0, 0.0]])
+    r = c = np.array([0.5, 0.5])
+    prm = L.Params(eta=0.0)
+    st = L.lamp_init(2)
+    for t in range(1, 40):
+        st = L.lamp_step(C, r, c, st, prm.resolved(1.0), 1.0)
+        assert st.t == t and st.lam == pytest.approx(t / 2, rel=1e-15)
+        np.testing.assert_allclose(st.theta, 0.0, atol=1e-14)
+        np.testing.assert_allclose(st.nu, 0.0, atol=1e-14)
+        X = L.plan(C, r, st, 1.0)
+        e = math.exp(-t / 2)
+        assert float(np.sum(C * X)) == pytest.approx(e / (1 + e), rel=1e-13)
+        assert float(np.sum(C * L.round_plan(X, r, c))) <= L.prop_bound(0.0, t, 2, 1.0)
+
+
+def test_circulant_polygon_closed_form():
+    """Regular n-gon, x = y, uniform marginals: the cost is circulant, so every column of X^t sums
+    to 1/n, theta = nu = 0 and log Z_i = LSE_j(-lam_t C_0j) for every i."""
+    n = 12
+    ang = 2 * np.pi * np.arange(n) / n
+    x = np.stack([np.cos(ang), np.sin(ang)], 1)
+    C = L.sqeuclid_cost(x, x, 0.25)              # ||C||_inf = 1
+    r = c = np.full(n, 1.0 / n)
+    st, tr = L.lamp_dense(C, r, c, L.Params(eta=1e-2), 50, 1.0)
+    for t in range(50):
+        np.testing.assert_allclose(tr.colA[t], 1.0 / n, rtol=1e-12)
+        np.testing.assert_allclose(tr.theta[t], 0.0, atol=1e-12)
+        np.testing.assert_allclose(tr.logZA[t], logsumexp(-tr.lam[t] * C[0]), rtol=1e-13)
+
+
+def test_row_feasibility():
+    """row(X^t) = r for every t (eq:row_feasible)."""
+    C, r, c, *_ = _problem(10, 7, 2, seed=5)
+    cnorm = float(C.max())
+    st = L.lamp_init(7)
+    prm = L.Params(eta=0.0).resolved(cnorm)
+    for _ in range(30):
+        st = L.lamp_step(C, r, c, st, prm, cnorm)
+        X = L.plan(C, r, st, cnorm)
+        np.testing.assert_allclose(L.row(X), r, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- Round
+
+
+def test_round_feasible_and_l1_bound():
+    """Round(X, r, c) is in Pi(r, c) and ||X - Round X||_1 <= 2(||row - r||_1 + ||col - c||_1)
+    (Algorithm 3, Lemma jason_rounding)."""
+    g = np.random.default_rng(6)
+    for _ in range(20):
+        n, m = g.integers(2, 9, 2)
+        X = g.random((n, m)) ** 3
+        X /= X.sum() * g.uniform(0.7, 1.3)
+        r, c = g.dirichlet(np.ones(n)), g.dirichlet(np.ones(m))
+        Xt = L.round_plan(X, r, c)
+        assert Xt.min() >= -1e-15
+        np.testing.assert_allclose(Xt.sum(1), r, atol=1e-14)
+        np.testing.assert_allclose(Xt.sum(0), c, atol=1e-14)
+        rr, cc, _ = L.residuals(X, r, c)
+        assert np.abs(X - Xt).sum() <= 2 * (rr + cc) + 1e-13
+
+
+# ---------------------------------------------------------------- ground truth
+
+
+def test_exact_solvers_agree():
+    """Brute force over permutations, the assignment solver and the HiGHS LP agree (Birkhoff)."""
+    g = np.random.default_rng(7)
+    for n in [2, 3, 5, 7]:
+        C = g.random((n, n))
+        u = np.full(n, 1.0 / n)
+        bf = exact.brute_force_ot_uniform(C)
+        assert exact.assignment_ot_uniform(C) == pytest.approx(bf, rel=1e-12)
+        assert exact.lp_ot(C, u, u)[0] == pytest.approx(bf, rel=1e-8)
+
+
+@pytest.mark.parametrize("eta,beta", [(0.0, 1.1), (0.0, math.log(3)), (1e-2, 1.1)])
+def test_certificate_ordering_and_last_iterate_bound(eta, beta):
+    """For every t >= 1: D(theta^t) <= OPT <= <C, Round X^t> <= P(X^t) (Appendix B duality,
+    Lemma jason_rounding), and for eta = 0 the last-iterate bounds of Proposition infeas_bound(a):
+    <C, Round X^t> - OPT <= 4||C||_inf ||col(X^t) - c||_1 + 2||C||_inf log m / t, and the
+    intermediate bound <C, X^t - X*> <= 2||C||_inf <-nu^t, col - c> + 2||C||_inf KL(X*||X^0)/t."""
+    n = m = 6
+    C, r, c, *_ = _problem(n, m, 2, seed=8)
+    cnorm = float(C.max())
+    opt, Xstar = exact.lp_ot(C, r, c)
+    prm = L.Params(eta=eta, beta=beta).resolved(cnorm)
+    X0 = r[:, None] * np.full((n, m), 1.0 / m)
+    klstar = L.kl(np.maximum(Xstar, 0), X0)
+    st = L.lamp_init(m)
+    for t in range(1, 400):
+        st = L.lamp_step(C, r, c, st, prm, cnorm)
+        cert = L.certificate(C, r, c, st, prm, cnorm)
+        assert cert["dual_theta"] <= opt + 1e-12
+        assert cert["dual_nu"] <= opt + 1e-12
+        assert opt <= cert["rounded_cost"] + 1e-12
+        assert cert["rounded_cost"] <= cert["primal_penalized"] + 1e-12
+        if eta == 0.0:
+            assert cert["rounded_cost"] - opt <= cert["prop_bound"] + 1e-12
+            X = L.plan(C, r, st, cnorm)
+            ib = L.intermediate_bound(L.col(X), c, st.nu, klstar, t, cnorm)
+            assert cert["cost"] - opt <= ib + 1e-12
+
+
+def test_lamp_converges_to_assignment_optimum():
+    """eta = 0 on uniform n = m = 5 (brute-force OPT): the certificate gap closes."""
+    g = np.random.default_rng(9)
+    x, y = g.random((5, 2)), g.random((5, 2))
+    C = L.sqeuclid_cost(x, y, 1.0 / L.max_sqdist(x, y))
+    u = np.full(5, 0.2)
+    opt = exact.brute_force_ot_uniform(C)
+    st, _ = L.lamp_dense(C, u, u, L.Params(eta=0.0), 20000, 1.0, trace=False)
+    cert = L.certificate(C, u, u, st, L.Params(eta=0.0).resolved(1.0), 1.0)
+    assert cert["rounded_cost"] - opt <= cert["prop_bound"]
+    assert cert["rounded_cost"] == pytest.approx(opt, abs=5e-4)
+    assert max(cert["dual_theta"], cert["dual_nu"]) == pytest.approx(opt, abs=5e-4)
+
+
+def test_eot_fixed_point_is_the_sinkhorn_plan():
+    """For 0 < eta <= ||C||_inf / log(max_j 1/c_j) the penalised problem and EOT share their unique
+    minimiser (Lemma l1_prob_equiv(b)); LAMP's plan converges to the Sinkhorn EOT plan."""
+    C, r, c, *_ = _problem(5, 4, 2, seed=10)
+    cnorm = float(C.max())
+    eta = 0.05
+    assert eta <= cnorm / math.log(1 / c.min())
+    Xs = exact.sinkhorn_eot(C, r, c, eta)
+    st, _ = L.lamp_dense(C, r, c, L.Params(eta=eta), 20000, cnorm, trace=False)
+    X = L.plan(C, r, st, cnorm)
+    np.testing.assert_allclose(X, Xs, atol=1e-7)
+
+
+def test_pd_obj_relation_identity():
+    """-<r, log Z^t(theta)> - t<col(X~), theta> = (t/2)<C, X~> - H(X~) + H(r) with ||C||_inf = 1,
+    X~ = diag(r) p^{eta_t}(theta), eta_t = 2/t (Lemma pd_obj_relation)."""
+    C, r, c, *_ = _problem(6, 9, 2, seed=11)
+    g = np.random.default_rng(12)
+    for t in [1, 3, 17]:
+        theta = g.uniform(-1, 1, 9)
+        Xt = r[:, None] * L.dual_to_primal(C, theta, t / 2.0, 1.0)
+        logZ = logsumexp(-t * (C / 2.0 + theta[None, :]), axis=1)
+        lhs = -(r @ logZ) - t * (L.col(Xt) @ theta)
+        rhs = t / 2.0 * np.sum(C * Xt) - L.entropy(Xt) + L.entropy(r[:, None])
+        assert lhs == pytest.approx(rhs, rel=1e-12, abs=1e-12)
+
+
+# ---------------------------------------------------------------- gradient
+
+
+def test_envelope_gradient_matches_finite_differences():
+    """grad_{x_i} sum_j X_ij C_ij at frozen (nu, lam, s) equals the derivative of
+    r_i softmin_j(C_ij + K nu_j) (Danskin); central differences in FP64."""
+    g = np.random.default_rng(13)
+    x, y = g.random((6, 3)), g.random((8, 3))
+    r = g.dirichlet(np.ones(6))
+    nu = g.uniform(-0.5, 0.5, 8)
+    s, lam, cnorm = 0.7, 40.0, 1.0
+    G = L.envelope_grad_x(x, y, r, s, nu, lam, cnorm)
+    h = 1e-6
+    for i in range(6):
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd = (L.envelope_value_rows(xp, y, r, s, nu, lam, cnorm)[i]
+                  - L.envelope_value_rows(xm, y, r, s, nu, lam, cnorm)[i]) / (2 * h)
+            assert G[i, k] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
+def test_envelope_gradient_of_the_eot_value():
+    """At LAMP's EOT fixed point the envelope gradient equals d/dx of the re-solved EOT value
+    V(x) = min_{X in Pi(r,c)} <C(x), X> - eta H(X) (Sinkhorn re-solve per perturbation)."""
+    g = np.random.default_rng(14)
+    x, y = g.random((4, 2)), g.random((4, 2))
+    r, c = np.full(4, 0.25), np.full(4, 0.25)
+    s = 1.0 / L.max_sqdist(x, y)
+    eta = 0.05
+    C = L.sqeuclid_cost(x, y, s)
+    st, _ = L.lamp_dense(C, r, c, L.Params(eta=eta), 20000, 1.0, trace=False)
+    G = L.envelope_grad_x(x, y, r, s, st.nu, st.lam, 1.0)
+
+    def V(xx):
+        Cx = L.sqeuclid_cost(xx, y, s)
+        X = exact.sinkhorn_eot(Cx, r, c, eta)
+        return float(np.sum(Cx * X) - eta * L.entropy(X))
+
+    h = 1e-5
+    for i, k in itertools.product(range(4), range(2)):
+        xp, xm = x.copy(), x.copy()
+        xp[i, k] += h
+        xm[i, k] -= h
+        assert G[i, k] == pytest.approx((V(xp) - V(xm)) / (2 * h), rel=1e-4, abs=1e-7)
+
+
+# ---------------------------------------------------------------- streaming form
+
+
+def test_stream_step_matches_dense_step():
+    """The row-block evaluation gives the same iteration as the dense one (n != m, several blocks
+    with a ragged tail)."""
+    wl = W.random_small(150, 70, 3, seed=15)
+    x, y = wl.x.astype(np.float64), wl.y.astype(np.float64)
+    s = 1.0 / L.max_sqdist(x, y)
+    C = L.sqeuclid_cost(x, y, s)
+    prm = L.Params(eta=1e-3)
+    st, tr = L.lamp_dense(C, wl.r, wl.c, prm, 25, 1.0)
+    lam = st.lam
+    lam2, nu2, th2, info = stream.lamp_step_stream(x, y, wl.r, wl.c, s, 1.0, st.t, lam, st.nu,
+                                                   st.theta, prm, block=64)
+    st2, tr2 = L.lamp_dense(C, wl.r, wl.c, prm, 1, 1.0, state=st)
+    np.testing.assert_allclose(nu2, st2.nu, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(th2, st2.theta, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(info["logZA"], tr2.logZA[0], rtol=1e-13)
+    np.testing.assert_allclose(info["colB"], tr2.colB[0], rtol=1e-11)
+    rows = [0, 63, 64, 149]
+    np.testing.assert_allclose(stream.row_log_normalisers(x, y, s, 1.0, st.nu, lam, rows),
+                               tr2.logZA[0][rows], rtol=1e-13)
+
+
+def test_cmax_c_routine_matches_numpy():
+    from oracle import cmax
+    wl = W.random_small(300, 211, 5, seed=16)
+    assert cmax.max_sqdist(wl.x, wl.y) == L.max_sqdist(wl.x.astype(np.float64), wl.y.astype(np.float64))
