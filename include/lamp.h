@@ -1,0 +1,189 @@
+/*
+ * lamp.h -- C ABI of the MI355X (gfx950) implementation of Log-Averaged
+ * Mirror Prox (LAMP, arXiv 2511.11359) for discrete optimal transport with a
+ * squared-Euclidean cost generated on the fly from point clouds.
+ *
+ * Problem (Section 1, problem primal_ot / primal_eot):
+ *     min_{X in Pi(r,c)} <C, X> - eta H(X),   C_ij = s * ||x_i - y_j||^2,
+ * solved through the saddle form (problem spp) by Algorithm 2 (LAMP).  Only the
+ * O(n + m) dual state (nu^t, theta^t, t, lam_t = 1/eta_t) is stored; the plan
+ * X^t = diag(r) p^{eta_t}(nu^t) (equation def:dual_to_primal) is implicit.
+ *
+ * Conventions shared by every entry point:
+ *  - Every array argument is a DEVICE pointer owned by the caller; the library
+ *    never frees caller memory and never aborts.  Scratch memory is the caller's
+ *    workspace `ws` of `ws_bytes` bytes (size from lamp_workspace_bytes), 256-byte
+ *    aligned.
+ *  - `stream` is a hipStream_t (NULL: the default stream).  Work is enqueued on
+ *    it; the calls that return host values (step with res_out, solve,
+ *    certificate, cost_scale) synchronise that stream before returning.
+ *  - Concurrent calls are safe when they use distinct workspaces and states.
+ *  - Errors are returned as negative lamp_status codes; lamp_last_error() gives
+ *    a thread-local message for the last non-OK status of the calling thread.
+ */
+#ifndef LAMP_H
+#define LAMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LAMP_OK = 0,
+    LAMP_NOT_CONVERGED = 1,  /* max_iter reached before tol; the state is valid   */
+    LAMP_EINVAL = -1,        /* null pointer, n, m or d < 1, eta < 0, tau1*eta > 1,
+                                tol < 0, unknown precision, bad state (t < 0)      */
+    LAMP_EDOMAIN = -2,       /* r or c has an entry <= 0 or a sum off 1 by > 1e-9  */
+    LAMP_ENOMEM = -3,        /* ws_bytes < lamp_workspace_bytes(...)               */
+    LAMP_EDEVICE = -4,       /* a HIP runtime call failed                          */
+    LAMP_ENUMERIC = -5       /* a non-finite value appeared in the dual update     */
+} lamp_status;
+
+typedef enum {
+    LAMP_FP32 = 0,           /* cost and exponent arguments assembled in FP64 on the
+                                vector ALU, exponentials and their sums in FP32,
+                                duals FP64: the reference-accuracy form           */
+    LAMP_FP32_MFMA = 1,      /* x.y^T tiles on FP32 matrix cores, exponent assembled
+                                in FP32, duals FP64                               */
+    LAMP_BF16_MFMA = 2,      /* x.y^T tiles from BF16 points on matrix cores with
+                                FP32 accumulation; exponentials and sums FP32      */
+    LAMP_FP16_MFMA = 3       /* as LAMP_BF16_MFMA with FP16 points                 */
+} lamp_precision;           /* matrix-core forms need d <= 128                     */
+
+/* Problem data (Section 1; Algorithm 2, REQUIRE line).
+ *   x: n x d, y: m x d, row-major FP32 point clouds (device).
+ *   r: n, c: m, FP64 marginals (device), strictly positive, each summing to 1
+ *      (the paper adds 1e-6 and renormalises to get full support, Appendix E).
+ *   cost_scale: s in C_ij = s ||x_i - y_j||^2.  <= 0: s = 1 / max_ij ||x_i - y_j||^2
+ *      is computed on the device (then ||C||_inf = 1).
+ *   cost_norm: ||C||_inf = max_ij C_ij.  <= 0: computed on the device.  Only
+ *      trusted as given when both cost_scale and cost_norm are > 0. */
+typedef struct {
+    int64_t n, m;
+    int32_t d, reserved;
+    const float *x, *y;
+    const double *r, *c;
+    double cost_scale;
+    double cost_norm;
+} lamp_problem;
+
+/* Algorithm parameters (Algorithm 2; defaults from Appendix E, "for all LAMP
+ * testing": alpha = 0.01, beta = 1.1, tau1 = tau2 = 1/(2||C||_inf)).
+ *   eta >= 0: entropic regularisation; tau1 * eta <= 1 is required
+ *      (Lemma primal_md_eq_dual_avg, Proposition equivalence).
+ *   tol: stop when ||col(X^t) - c||_1 <= tol (row(X^t) = r by construction,
+ *      eq:row_feasible); 0 runs exactly max_iter iterations.
+ *   alpha, beta, tau1, tau2: <= 0 selects the default.
+ *   check_every: iterations per host check of the stopping flag in lamp_solve
+ *      (<= 0: 64).  The tolerance itself is tested on the device every iteration. */
+typedef struct {
+    double eta, tol;
+    int64_t max_iter;
+    double alpha, beta, tau1, tau2;
+    int32_t precision, check_every;
+} lamp_params;
+
+/* O(n + m) state of Algorithm 2 after t iterations (caller-owned).
+ *   nu, theta: m FP64 each (device): nu^t, theta^t.  t = 0 with zeros is the
+ *      start of Algorithm 2 (theta^0 = nu^0 = 0, eta_0 = infinity).
+ *   t: iterations done; inv_eta: lam_t = 1/eta_t (0 at t = 0).
+ * The state fully determines the rest of the run: checkpointing is copying it. */
+typedef struct {
+    double *nu, *theta;
+    int64_t t;
+    double inv_eta;
+} lamp_state;
+
+/* Optional per-iteration outputs of lamp_step (device, nullable each):
+ *   log_za[n], log_zb[n]: natural log Z_i of p^{eta_t}(nu^t) and p^{eta_{t+1}}(nubar^{t+1})
+ *      (Section 4.1, first display);
+ *   col_a[m], col_b[m]: col_r of the same two maps (Section 4.1, second display);
+ *   theta_bar[m], theta_hat[m]: the two dual mirror steps (step:lamp_mid_theta,
+ *      step:lamp_main_theta). */
+typedef struct {
+    double *log_za, *log_zb, *col_a, *col_b, *theta_bar, *theta_hat;
+} lamp_trace;
+
+/* Certificate of X^t = diag(r) p^{eta_t}(nu^t) (Proposition infeas_bound; Appendix B). */
+typedef struct {
+    double col_res;          /* ||col(X^t) - c||_1                                   */
+    double row_res;          /* ||row(X^t) - r||_1, measured                          */
+    double cost;             /* <C, X^t>                                              */
+    double dual_theta;       /* D(theta^t) (def:dual_spp), a lower bound on OPT       */
+    double dual_nu;          /* D(nu^t)                                               */
+    double primal_penalized; /* <C,X^t> + 2||C||_inf (row_res + col_res) >= OPT       */
+    double gap;              /* primal_penalized - max(dual_theta, dual_nu)           */
+    double prop_bound;       /* 4||C||_inf col_res + 2||C||_inf log(m) / t (t >= 1)   */
+    double cost_scale;       /* s used                                                */
+    double cost_norm;        /* ||C||_inf used                                        */
+    int64_t t;
+} lamp_cert;
+
+typedef struct {
+    int64_t iters;           /* iterations performed by this call                     */
+    int64_t t;               /* state.t on return                                     */
+    double seconds;          /* wall time of the call                                 */
+    double final_res;        /* ||col(X^t) - c||_1 of the returned iterate            */
+    double cost_scale;       /* s used                                                */
+    double cost_norm;        /* ||C||_inf used                                        */
+    int32_t converged;       /* 1 if final_res <= tol                                 */
+    int32_t row_fallbacks;   /* rows whose normaliser was recomputed exactly          */
+} lamp_report;
+
+/* Bytes of workspace needed for this problem and these parameters. */
+size_t lamp_workspace_bytes(const lamp_problem *prob, const lamp_params *params);
+
+/* s = 1 / max_ij ||x_i - y_j||^2 (FP64 from the FP32 points), the normalisation
+ * that makes ||C||_inf = 1.  *max_sqdist_out (host, nullable) gets the maximum. */
+lamp_status lamp_cost_scale(const lamp_problem *prob, void *ws, size_t ws_bytes, void *stream,
+                            double *s_out, double *max_sqdist_out);
+
+/* One iteration t -> t+1 of Algorithm 2 (steps step:eta_update ... tclip), in
+ * place on `state`.  res_out (host, nullable) receives ||col(X^t) - c||_1 of the
+ * iterate X^t the step started from.  trace (nullable) receives intermediates. */
+lamp_status lamp_step(const lamp_problem *prob, const lamp_params *params, lamp_state *state,
+                      void *ws, size_t ws_bytes, void *stream, const lamp_trace *trace,
+                      double *res_out);
+
+/* Runs Algorithm 2 from `state` (t = 0: a fresh start; t > 0: resumes) until
+ * ||col(X^t) - c||_1 <= tol or max_iter iterations of this call.  On LAMP_OK the
+ * state holds the iterate that met the tolerance (that iteration's update is not
+ * applied); on LAMP_NOT_CONVERGED it holds the last iterate.  The iteration loop
+ * runs as a captured HIP graph replayed in chunks of check_every iterations. */
+lamp_status lamp_solve(const lamp_problem *prob, const lamp_params *params, lamp_state *state,
+                       void *ws, size_t ws_bytes, void *stream, lamp_report *out);
+
+/* Certificate of the state's iterate (Proposition infeas_bound(a), def:dual_spp,
+ * problem l1_ot_primal); out is a host pointer. */
+lamp_status lamp_certificate(const lamp_problem *prob, const lamp_params *params,
+                             const lamp_state *state, void *ws, size_t ws_bytes, void *stream,
+                             lamp_cert *out);
+
+/* Envelope gradient of the transport cost with respect to the source points at
+ * the state's iterate (not in the paper; the derivative sum_j X_ij dC_ij/dx_i of
+ * <C, X> with X = X^t held fixed, C_ij = s||x_i - y_j||^2 at fixed s):
+ *     grad_x[i, :] = grad_out * 2 s r_i sum_j p_ij (x_i - y_j),
+ * written to grad_x (device, n x d, FP32, row-major).  Requires state->t >= 1. */
+lamp_status lamp_backward(const lamp_problem *prob, const lamp_params *params,
+                          const lamp_state *state, double grad_out, float *grad_x, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Measurement support (not part of the method): average device time in ms of one
+ * row sweep and one column sweep of iteration state->t (the two O(nm) kernels of
+ * Section 4.1), each launched `reps` times back to back between HIP events on
+ * `stream`.  The state is not modified. */
+lamp_status lamp_sweep_times(const lamp_problem *prob, const lamp_params *params,
+                             const lamp_state *state, void *ws, size_t ws_bytes, void *stream,
+                             int32_t reps, double *row_ms, double *col_ms);
+
+/* Message for the last non-OK status returned to the calling thread. */
+const char *lamp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAMP_H */

@@ -1,0 +1,10 @@
+"""MI355X (gfx950) implementation of Log-Averaged Mirror Prox (LAMP, arXiv 2511.11359).
+
+The solver lives in liblamp.so (HIP kernels + C ABI, include/lamp.h); this
+package only marshals arguments.  ``workloads`` draws seeded synthetic inputs.
+"""
+from .api import (LampError, LampOT, Problem, State, backward, certificate, cost_scale, make_params,
+                  solve, step, sweep_times)
+
+__all__ = ["LampError", "LampOT", "Problem", "State", "backward", "certificate", "cost_scale",
+           "make_params", "solve", "step", "sweep_times"]

@@ -1,0 +1,215 @@
+"""Python binding of the LAMP C ABI.  PyTorch provides device memory and the
+stream; every step of the method runs in the HIP kernels of liblamp.so, and a
+missing library raises (there is no fallback path)."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+class LampError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        lib = L.load()
+        raise LampError(status, lib.lamp_last_error().decode(errors="replace"))
+    return status
+
+
+def _stream_handle(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+class Problem:
+    """Device-resident problem data (Section 1): x (n x d) and y (m x d) FP32 point clouds,
+    r and c FP64 marginals, and the workspace the library works in."""
+
+    def __init__(self, x, y, r, c, cost_scale: float = 0.0, cost_norm: float = 0.0,
+                 device: str | torch.device = "cuda"):
+        dev = torch.device(device)
+        self.device = dev
+        self.x = torch.as_tensor(x, dtype=torch.float32).to(dev).contiguous()
+        self.y = torch.as_tensor(y, dtype=torch.float32).to(dev).contiguous()
+        self.r = torch.as_tensor(r, dtype=torch.float64).to(dev).contiguous()
+        self.c = torch.as_tensor(c, dtype=torch.float64).to(dev).contiguous()
+        assert self.x.dim() == 2 and self.y.dim() == 2 and self.x.shape[1] == self.y.shape[1]
+        self.n, self.d = self.x.shape
+        self.m = self.y.shape[0]
+        self.cost_scale = float(cost_scale)
+        self.cost_norm = float(cost_norm)
+        self._ws = None
+
+    def struct(self) -> L.Problem:
+        return L.Problem(self.n, self.m, self.d, 0, self.x.data_ptr(), self.y.data_ptr(),
+                         self.r.data_ptr(), self.c.data_ptr(), self.cost_scale, self.cost_norm)
+
+    def workspace(self, params: L.Params) -> tuple[int, int]:
+        lib = L.load()
+        prob = self.struct()
+        need = int(lib.lamp_workspace_bytes(ctypes.byref(prob), ctypes.byref(params)))
+        if self._ws is None or self._ws.numel() < need + 256:
+            self._ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        return aligned, need
+
+
+def make_params(eta: float = 0.0, tol: float = 0.0, max_iter: int = 1000, alpha: float = 0.0,
+                beta: float = 0.0, tau1: float = 0.0, tau2: float = 0.0,
+                check_every: int = 64, precision: str = "fp32") -> L.Params:
+    """Algorithm 2 parameters; zeros select the defaults of Appendix E.  precision is one of
+    fp32 (FP64 arguments, FP32 exponentials), fp32_mfma, bf16_mfma, fp16_mfma."""
+    return L.Params(eta, tol, int(max_iter), alpha, beta, tau1, tau2, L.PRECISIONS[precision],
+                    int(check_every))
+
+
+@dataclass
+class State:
+    """O(n + m) state: nu^t, theta^t (FP64 device), t and lam_t = 1/eta_t."""
+    nu: torch.Tensor
+    theta: torch.Tensor
+    t: int = 0
+    inv_eta: float = 0.0
+
+    @staticmethod
+    def fresh(m: int, device="cuda") -> "State":
+        z = torch.zeros(m, dtype=torch.float64, device=device)
+        return State(z, z.clone(), 0, 0.0)
+
+    def struct(self) -> L.State:
+        return L.State(self.nu.data_ptr(), self.theta.data_ptr(), self.t, self.inv_eta)
+
+    def update(self, s: L.State) -> None:
+        self.t = int(s.t)
+        self.inv_eta = float(s.inv_eta)
+
+    def clone(self) -> "State":
+        return State(self.nu.clone(), self.theta.clone(), self.t, self.inv_eta)
+
+
+def cost_scale(prob: Problem) -> tuple[float, float]:
+    """(s, max_ij ||x_i - y_j||^2) with s = 1/max: the normalisation ||C||_inf = 1."""
+    lib = L.load()
+    params = make_params()
+    ws, nb = prob.workspace(params)
+    s = ctypes.c_double()
+    md = ctypes.c_double()
+    p = prob.struct()
+    _check(lib.lamp_cost_scale(ctypes.byref(p), ws, nb, _stream_handle(prob.device), ctypes.byref(s),
+                               ctypes.byref(md)))
+    return s.value, md.value
+
+
+def step(prob: Problem, params: L.Params, state: State, trace: bool = False):
+    """One iteration of Algorithm 2 in place.  Returns (||col(X^t) - c||_1, trace dict or None)."""
+    lib = L.load()
+    ws, nb = prob.workspace(params)
+    tr = None
+    trs = None
+    if trace:
+        dd = dict(device=prob.device, dtype=torch.float64)
+        tr = dict(log_za=torch.empty(prob.n, **dd), log_zb=torch.empty(prob.n, **dd),
+                  col_a=torch.empty(prob.m, **dd), col_b=torch.empty(prob.m, **dd),
+                  theta_bar=torch.empty(prob.m, **dd), theta_hat=torch.empty(prob.m, **dd))
+        trs = L.Trace(*(tr[k].data_ptr() for k in ["log_za", "log_zb", "col_a", "col_b",
+                                                    "theta_bar", "theta_hat"]))
+    p = prob.struct()
+    s = state.struct()
+    res = ctypes.c_double()
+    _check(lib.lamp_step(ctypes.byref(p), ctypes.byref(params), ctypes.byref(s), ws, nb,
+                         _stream_handle(prob.device), ctypes.byref(trs) if trs is not None else None,
+                         ctypes.byref(res)))
+    state.update(s)
+    return res.value, tr
+
+
+def solve(prob: Problem, params: L.Params, state: State | None = None):
+    """Runs Algorithm 2 (resuming from `state` if given).  Returns (state, report dict, status)."""
+    lib = L.load()
+    if state is None:
+        state = State.fresh(prob.m, prob.device)
+    ws, nb = prob.workspace(params)
+    p = prob.struct()
+    s = state.struct()
+    rep = L.Report()
+    st = _check(lib.lamp_solve(ctypes.byref(p), ctypes.byref(params), ctypes.byref(s), ws, nb,
+                               _stream_handle(prob.device), ctypes.byref(rep)))
+    state.update(s)
+    report = {k: getattr(rep, k) for k, _ in L.Report._fields_}
+    return state, report, st
+
+
+def certificate(prob: Problem, params: L.Params, state: State) -> dict:
+    """Certificate of X^t (Proposition infeas_bound, def:dual_spp)."""
+    lib = L.load()
+    ws, nb = prob.workspace(params)
+    p = prob.struct()
+    s = state.struct()
+    cert = L.Cert()
+    _check(lib.lamp_certificate(ctypes.byref(p), ctypes.byref(params), ctypes.byref(s), ws, nb,
+                                _stream_handle(prob.device), ctypes.byref(cert)))
+    return {k: getattr(cert, k) for k, _ in L.Cert._fields_}
+
+
+def backward(prob: Problem, params: L.Params, state: State, grad_out: float = 1.0) -> torch.Tensor:
+    """grad_out * sum_j X_ij dC_ij/dx_i at the state's iterate (envelope gradient), n x d FP32."""
+    lib = L.load()
+    ws, nb = prob.workspace(params)
+    g = torch.empty(prob.n, prob.d, dtype=torch.float32, device=prob.device)
+    p = prob.struct()
+    s = state.struct()
+    _check(lib.lamp_backward(ctypes.byref(p), ctypes.byref(params), ctypes.byref(s), float(grad_out),
+                             g.data_ptr(), ws, nb, _stream_handle(prob.device)))
+    return g
+
+
+def sweep_times(prob: Problem, params: L.Params, state: State, reps: int = 10) -> tuple[float, float]:
+    """Average device milliseconds of one row sweep and one column sweep (HIP events)."""
+    lib = L.load()
+    ws, nb = prob.workspace(params)
+    p = prob.struct()
+    s = state.struct()
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    _check(lib.lamp_sweep_times(ctypes.byref(p), ctypes.byref(params), ctypes.byref(s), ws, nb,
+                                _stream_handle(prob.device), int(reps), ctypes.byref(a),
+                                ctypes.byref(b)))
+    return a.value, b.value
+
+
+class LampOT(torch.autograd.Function):
+    """Transport cost <C, X^T> of the LAMP iterate as a differentiable function of the source
+    points x (envelope gradient at fixed duals and fixed cost scale)."""
+
+    @staticmethod
+    def forward(ctx, x, y, r, c, eta: float, tol: float, max_iter: int, cost_scale: float):
+        prob = Problem(x.detach(), y.detach(), r, c, cost_scale=cost_scale, device=x.device)
+        if cost_scale <= 0:
+            prob.cost_scale, _ = cost_scale_of(prob)
+            prob.cost_norm = 1.0
+        params = make_params(eta=eta, tol=tol, max_iter=max_iter)
+        state, report, _ = solve(prob, params)
+        cert = certificate(prob, params, state)
+        ctx.lamp = (prob, params, state)
+        return torch.tensor(cert["cost"], dtype=torch.float64, device=x.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        prob, params, state = ctx.lamp
+        gx = backward(prob, params, state, float(g))
+        return gx, None, None, None, None, None, None, None
+
+
+cost_scale_of = cost_scale

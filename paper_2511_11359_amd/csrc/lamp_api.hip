@@ -1,0 +1,863 @@
+// C ABI of the LAMP library (declared in include/lamp.h): argument checking,
+// workspace layout, the FP64 inverse-temperature schedule, kernel dispatch and
+// the graph-captured iteration loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lamp.h"
+#include "lamp_kernels.hpp"
+#include "lamp_mfma.hpp"
+
+using namespace lampk;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lamp_status fail(lamp_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(LAMP_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                  \
+    } while (0)
+
+constexpr int TAB = 4096;              // schedule entries per epoch
+constexpr int64_t TARGET_BLOCKS = 1024;  // 256 CUs x 4 blocks of 4 waves
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Split of the streamed extent `len` for `owned` lanes: returns elements per split.
+int64_t choose_split(int64_t owned, int64_t len) {
+    const int64_t blocks = cdiv(owned, BLOCK);
+    int64_t P = cdiv(TARGET_BLOCKS, blocks);
+    P = std::max<int64_t>(1, std::min<int64_t>(P, cdiv(len, 128)));
+    return cdiv(len, P);
+}
+
+struct Layout {
+    size_t ctrl, sched, xc, yc, ycf, xn2, yn2, gtab, H, rowvar, rpart, cpart, nu1, th1, respart,
+        scratch, small, xop, yop, kf, wAf, wBf, total;
+    int64_t split_r, P_r, split_c, P_c;
+    // matrix-core forms
+    int prec, KP, esize;
+    int64_t n_pad, m_pad, tps_r, P_rm, tps_c, P_cm;
+};
+
+bool is_mfma(int prec) { return prec == LAMP_FP32_MFMA || prec == LAMP_BF16_MFMA || prec == LAMP_FP16_MFMA; }
+
+// Smallest supported operand width >= d for the matrix-core forms (0: unsupported).
+int mfma_kp(int prec, int d) {
+    if (prec == LAMP_FP32_MFMA) {
+        for (int kp : {4, 16, 64, 128})
+            if (d <= kp) return kp;
+        return 0;
+    }
+    for (int kp : {16, 64, 128})
+        if (d <= kp) return kp;
+    return 0;
+}
+
+// Splits of the streamed tile range for the matrix-core sweeps: a multiple of 8 so that
+// split p runs on XCD p mod 8, enough blocks to fill the chip.
+void mfma_split(int64_t owned_pad, int64_t streamed_tiles, int64_t* tps, int64_t* P) {
+    const int64_t blocks = owned_pad / 128;
+    int64_t want = cdiv(TARGET_BLOCKS * 2, blocks);
+    want = std::max<int64_t>(8, cdiv(want, 8) * 8);
+    want = std::min<int64_t>(want, streamed_tiles);
+    *tps = cdiv(streamed_tiles, want);
+    *P = cdiv(streamed_tiles, *tps);
+}
+
+Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32) {
+    Layout L{};
+    L.split_r = choose_split(n, m);
+    L.P_r = cdiv(m, L.split_r);
+    L.split_c = choose_split(m, n);
+    L.P_c = cdiv(n, L.split_c);
+    L.prec = prec;
+    L.n_pad = cdiv(n, 128) * 128;
+    L.m_pad = cdiv(m, 128) * 128;
+    if (is_mfma(prec)) {
+        L.KP = mfma_kp(prec, d);
+        L.esize = prec == LAMP_FP32_MFMA ? 4 : 2;
+        mfma_split(L.n_pad, L.m_pad / 32, &L.tps_r, &L.P_rm);
+        mfma_split(L.m_pad, L.n_pad / 32, &L.tps_c, &L.P_cm);
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    // row partials: [P][n] double2 for the sweeps, [P_r][n][d+1] for the adjoint,
+    // [4][n] for the certificate rows
+    size_t rpart_d = std::max<size_t>((size_t)L.P_r * n * std::max(2, d + 1), (size_t)4 * n);
+    size_t cpart_d2 = (size_t)L.P_c * m;
+    if (is_mfma(prec)) {
+        rpart_d = std::max<size_t>(rpart_d, (size_t)L.P_rm * n * 2);
+        cpart_d2 = std::max<size_t>(cpart_d2, (size_t)L.P_cm * m);
+    }
+    L.ctrl = take(sizeof(Ctrl));
+    L.sched = take(sizeof(Sched) * (TAB + 2));
+    L.xc = take(sizeof(double) * n * d);
+    L.yc = take(sizeof(double) * m * d);
+    L.ycf = take(sizeof(float) * m * d);
+    L.xn2 = take(sizeof(double) * n);
+    L.yn2 = take(sizeof(double) * m);
+    L.gtab = take(sizeof(double2) * 2 * m);
+    L.H = take(sizeof(double) * n);
+    L.rowvar = take(sizeof(RowVar) * n);
+    L.rpart = take(sizeof(double) * rpart_d);
+    L.cpart = take(sizeof(double2) * cpart_d2);
+    L.nu1 = take(sizeof(double) * m);
+    L.th1 = take(sizeof(double) * m);
+    L.respart = take(sizeof(double) * cdiv(m, BLOCK));
+    L.scratch = take(sizeof(double) * 4 * std::max(n, m));
+    L.small = take(sizeof(double) * 64);
+    if (is_mfma(prec)) {
+        L.xop = take((size_t)L.esize * L.n_pad * L.KP);
+        L.yop = take((size_t)L.esize * L.m_pad * L.KP);
+        L.kf = take(sizeof(float) * L.n_pad);
+        L.wAf = take(sizeof(float) * L.n_pad);
+        L.wBf = take(sizeof(float) * L.n_pad);
+    }
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+struct Resolved {
+    double s, cnorm, K, tau1, tau2, alpha, beta, kappa, clipb;
+};
+
+lamp_status check_problem(const lamp_problem* p) {
+    if (!p) return fail(LAMP_EINVAL, "problem is NULL");
+    if (p->n < 1 || p->m < 1 || p->d < 1)
+        return fail(LAMP_EINVAL, "n, m and d must be >= 1 (got %lld, %lld, %d)", (long long)p->n,
+                    (long long)p->m, p->d);
+    if (!p->x || !p->y || !p->r || !p->c) return fail(LAMP_EINVAL, "a problem array is NULL");
+    return LAMP_OK;
+}
+
+lamp_status check_params(const lamp_params* q) {
+    if (!q) return fail(LAMP_EINVAL, "params is NULL");
+    if (!(q->eta >= 0.0) || !std::isfinite(q->eta)) return fail(LAMP_EINVAL, "eta must be >= 0");
+    if (!(q->tol >= 0.0)) return fail(LAMP_EINVAL, "tol must be >= 0");
+    if (q->max_iter < 0) return fail(LAMP_EINVAL, "max_iter must be >= 0");
+    if (q->precision != LAMP_FP32 && !is_mfma(q->precision))
+        return fail(LAMP_EINVAL, "unknown precision %d", q->precision);
+    return LAMP_OK;
+}
+
+lamp_status check_ws(const lamp_problem* p, void* ws, size_t ws_bytes, int prec = LAMP_FP32) {
+    if (is_mfma(prec) && mfma_kp(prec, p->d) == 0)
+        return fail(LAMP_EINVAL, "the matrix-core forms support d <= 128 (got %d)", p->d);
+    const Layout L = layout(p->n, p->m, p->d, prec);
+    if (!ws) return fail(LAMP_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(LAMP_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(LAMP_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    return LAMP_OK;
+}
+
+// Marginals must be strictly positive and sum to 1 (r in Delta^n, c in Delta^m with full support).
+lamp_status check_marginals(const lamp_problem* p) {
+    std::vector<double> h((size_t)std::max(p->n, p->m));
+    const double* arrs[2] = {p->r, p->c};
+    const int64_t lens[2] = {p->n, p->m};
+    const char* names[2] = {"r", "c"};
+    for (int q = 0; q < 2; ++q) {
+        HIPCHK(hipMemcpy(h.data(), arrs[q], sizeof(double) * lens[q], hipMemcpyDeviceToHost));
+        double sum = 0.0;
+        for (int64_t i = 0; i < lens[q]; ++i) {
+            if (!(h[i] > 0.0) || !std::isfinite(h[i]))
+                return fail(LAMP_EDOMAIN, "%s[%lld] = %g is not a positive finite mass", names[q],
+                            (long long)i, h[i]);
+            sum += h[i];
+        }
+        if (std::fabs(sum - 1.0) > 1e-9) return fail(LAMP_EDOMAIN, "%s sums to %.17g, not 1", names[q], sum);
+    }
+    return LAMP_OK;
+}
+
+dim3 grid1(int64_t cnt) { return dim3((unsigned)cdiv(cnt, BLOCK)); }
+
+template <typename T>
+void prep_ops(const lamp_problem* p, const Layout& L, void* ws, hipStream_t st) {
+    hipLaunchKernelGGL(prep_operands<T>, grid1(L.n_pad * L.KP), dim3(BLOCK), 0, st, at<double>(ws, L.xc), p->n,
+                       p->d, L.KP, L.n_pad, at<T>(ws, L.xop));
+    hipLaunchKernelGGL(prep_operands<T>, grid1(L.m_pad * L.KP), dim3(BLOCK), 0, st, at<double>(ws, L.yc), p->m,
+                       p->d, L.KP, L.m_pad, at<T>(ws, L.yop));
+}
+
+lamp_status prep(const lamp_problem* p, void* ws, hipStream_t st, int prec = LAMP_FP32) {
+    const Layout L = layout(p->n, p->m, p->d, prec);
+    hipLaunchKernelGGL(prep_points, grid1(p->n), dim3(BLOCK), 0, st, p->x, p->n, p->d, p->x, p->y,
+                       at<double>(ws, L.xc), at<double>(ws, L.xn2), (float*)nullptr);
+    hipLaunchKernelGGL(prep_points, grid1(p->m), dim3(BLOCK), 0, st, p->y, p->m, p->d, p->x, p->y,
+                       at<double>(ws, L.yc), at<double>(ws, L.yn2), at<float>(ws, L.ycf));
+    if (is_mfma(prec)) {
+        if (prec == LAMP_FP32_MFMA) prep_ops<float>(p, L, ws, st);
+        else if (prec == LAMP_BF16_MFMA) prep_ops<__bf16>(p, L, ws, st);
+        else prep_ops<_Float16>(p, L, ws, st);
+        if (L.n_pad > p->n)
+            hipLaunchKernelGGL(pad_rows, grid1(L.n_pad - p->n), dim3(BLOCK), 0, st, p->n, L.n_pad,
+                               at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf));
+    }
+    HIPCHK(hipGetLastError());
+    return LAMP_OK;
+}
+
+// ------------------------------------------------------------------ dispatch by d
+#define LAMP_FOR_D(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(16)
+
+void launch_row_extreme(const Layout& L, Consts kc, int d, void* ws, const double* a, double sgn,
+                        hipStream_t st) {
+    dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
+    double* part = at<double>(ws, L.rpart);
+    switch (d) {
+#define CASE(D) \
+    case D: hipLaunchKernelGGL(row_extreme<D>, g, dim3(BLOCK), 0, st, kc, at<double>(ws, L.xc), at<double>(ws, L.yc), a, sgn, part, L.split_r); return;
+        LAMP_FOR_D(CASE)
+#undef CASE
+        default:
+            hipLaunchKernelGGL(row_extreme_dyn, g, dim3(BLOCK), 0, st, kc, d, at<double>(ws, L.xc),
+                               at<double>(ws, L.yc), a, sgn, part, L.split_r);
+    }
+}
+
+template <typename T, int KP>
+void row_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
+    const int64_t n_waves = L.n_pad / 32;
+    dim3 g((unsigned)(cdiv(n_waves, 4) * L.P_rm));
+    hipLaunchKernelGGL((row_sweep_mfma<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<double2>(ws, L.gtab), at<double>(ws, L.H),
+                       at<double2>(ws, L.rpart), L.tps_r, (int)L.P_rm, L.m_pad / 32, n_waves);
+}
+
+template <typename T, int KP>
+void col_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
+    const int64_t m_waves = L.m_pad / 32;
+    dim3 g((unsigned)(cdiv(m_waves, 4) * L.P_cm));
+    hipLaunchKernelGGL((col_sweep_mfma<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<double2>(ws, L.gtab), at<float>(ws, L.kf),
+                       at<float>(ws, L.wAf), at<float>(ws, L.wBf), at<double2>(ws, L.cpart), L.tps_c,
+                       (int)L.P_cm, L.n_pad / 32, m_waves);
+}
+
+template <bool ROW>
+void sweep_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
+#define MF(T, K) \
+    if (ROW) row_mfma<T, K>(L, kc, ws, st); else col_mfma<T, K>(L, kc, ws, st); return;
+    if (L.prec == LAMP_FP32_MFMA) {
+        switch (L.KP) {
+            case 4: MF(float, 4)
+            case 16: MF(float, 16)
+            case 64: MF(float, 64)
+            default: MF(float, 128)
+        }
+    } else if (L.prec == LAMP_BF16_MFMA) {
+        switch (L.KP) {
+            case 16: MF(__bf16, 16)
+            case 64: MF(__bf16, 64)
+            default: MF(__bf16, 128)
+        }
+    } else {
+        switch (L.KP) {
+            case 16: MF(_Float16, 16)
+            case 64: MF(_Float16, 64)
+            default: MF(_Float16, 128)
+        }
+    }
+#undef MF
+}
+
+// Number of row partials written by the row sweep of this layout.
+int row_parts(const Layout& L) { return (int)(is_mfma(L.prec) ? L.P_rm : L.P_r); }
+int col_parts(const Layout& L) { return (int)(is_mfma(L.prec) ? L.P_cm : L.P_c); }
+
+void launch_row_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
+    if (is_mfma(L.prec)) {
+        sweep_mfma<true>(L, kc, ws, st);
+        return;
+    }
+    dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
+    const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+    const Sched* sch = at<Sched>(ws, L.sched);
+    switch (d) {
+#define CASE(D) \
+    case D: hipLaunchKernelGGL(row_sweep<D>, g, dim3(BLOCK), 0, st, ctrl, sch, kc, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), at<double>(ws, L.H), at<double2>(ws, L.rpart), L.split_r); return;
+        LAMP_FOR_D(CASE)
+#undef CASE
+        default:
+            hipLaunchKernelGGL(row_sweep_dyn, g, dim3(BLOCK), 0, st, ctrl, sch, kc, d, at<double>(ws, L.xc),
+                               at<double>(ws, L.yc), at<double2>(ws, L.gtab), at<double>(ws, L.H),
+                               at<double2>(ws, L.rpart), L.split_r);
+    }
+}
+
+void launch_col_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
+    if (is_mfma(L.prec)) {
+        sweep_mfma<false>(L, kc, ws, st);
+        return;
+    }
+    dim3 g((unsigned)cdiv(kc.m, BLOCK), (unsigned)L.P_c);
+    const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+    const Sched* sch = at<Sched>(ws, L.sched);
+    switch (d) {
+#define CASE(D) \
+    case D: hipLaunchKernelGGL(col_sweep<D>, g, dim3(BLOCK), 0, st, ctrl, sch, kc, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), at<RowVar>(ws, L.rowvar), at<double2>(ws, L.cpart), L.split_c); return;
+        LAMP_FOR_D(CASE)
+#undef CASE
+        default:
+            hipLaunchKernelGGL(col_sweep_dyn, g, dim3(BLOCK), 0, st, ctrl, sch, kc, d, at<double>(ws, L.xc),
+                               at<double>(ws, L.yc), at<double2>(ws, L.gtab), at<RowVar>(ws, L.rowvar),
+                               at<double2>(ws, L.cpart), L.split_c);
+    }
+}
+
+void launch_adjoint(const Layout& L, Consts kc, int d, void* ws, double cA, const double* gA,
+                    hipStream_t st) {
+    dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
+    double* part = at<double>(ws, L.rpart);
+    switch (d) {
+#define CASE(D) \
+    case D: hipLaunchKernelGGL(adjoint_sweep<D>, g, dim3(BLOCK), 0, st, kc, cA, at<double>(ws, L.xc), at<double>(ws, L.yc), at<float>(ws, L.ycf), gA, at<double>(ws, L.H), part, L.split_r); return;
+        LAMP_FOR_D(CASE)
+#undef CASE
+        default:
+            hipLaunchKernelGGL(adjoint_sweep_dyn, g, dim3(BLOCK), 0, st, kc, d, cA, at<double>(ws, L.xc),
+                               at<double>(ws, L.yc), at<float>(ws, L.ycf), gA, at<double>(ws, L.H), part,
+                               L.split_r);
+    }
+}
+
+__global__ void fill_scaled(int64_t cnt, double f, const double* __restrict__ in, double* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) out[i] = f * in[i];
+}
+
+lamp_status max_sqdist(const lamp_problem* p, void* ws, hipStream_t st, double* out_host, int prec) {
+    const Layout L = layout(p->n, p->m, p->d, prec);
+    Consts kc{};
+    kc.n = p->n;
+    kc.m = p->m;
+    double* a = at<double>(ws, L.scratch);
+    double* rowmax = a + std::max(p->n, p->m);
+    hipLaunchKernelGGL(fill_scaled, grid1(p->m), dim3(BLOCK), 0, st, p->m, -0.5, at<double>(ws, L.yn2), a);
+    launch_row_extreme(L, kc, p->d, ws, a, +1.0, st);
+    hipLaunchKernelGGL(row_extreme_merge, grid1(p->n), dim3(BLOCK), 0, st, kc, at<double>(ws, L.rpart),
+                       (int)L.P_r, at<double>(ws, L.xn2), 1, rowmax);
+    hipLaunchKernelGGL(reduce_max, dim3(1), dim3(1024), 0, st, rowmax, p->n, at<double>(ws, L.small));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out_host, at<double>(ws, L.small), sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return LAMP_OK;
+}
+
+lamp_status resolve(const lamp_problem* p, const lamp_params* q, void* ws, hipStream_t st, Resolved* R) {
+    double s = p->cost_scale, cn = p->cost_norm;
+    if (!(s > 0.0) || !(cn > 0.0)) {
+        double md = 0.0;
+        lamp_status e = max_sqdist(p, ws, st, &md, q->precision);
+        if (e != LAMP_OK) return e;
+        if (!(md > 0.0)) return fail(LAMP_EDOMAIN, "all pairwise distances are zero");
+        if (!(s > 0.0)) {
+            s = 1.0 / md;
+            cn = 1.0;
+        } else {
+            cn = s * md;
+        }
+    }
+    R->s = s;
+    R->cnorm = cn;
+    R->K = 2.0 * cn;
+    R->tau1 = q->tau1 > 0.0 ? q->tau1 : 1.0 / (2.0 * cn);
+    R->tau2 = q->tau2 > 0.0 ? q->tau2 : 1.0 / (2.0 * cn);
+    R->alpha = q->alpha > 0.0 ? q->alpha : 0.01;
+    R->beta = q->beta > 0.0 ? q->beta : 1.1;
+    R->kappa = 2.0 * R->tau2 * cn;
+    R->clipb = std::tanh(R->beta / 2.0);
+    if (R->tau1 * q->eta > 1.0) return fail(LAMP_EINVAL, "tau1 * eta = %g > 1", R->tau1 * q->eta);
+    return LAMP_OK;
+}
+
+Consts make_consts(const lamp_problem* p, const Resolved& R) {
+    Consts kc;
+    kc.n = p->n;
+    kc.m = p->m;
+    kc.s = R.s;
+    kc.K = R.K;
+    kc.kappa = R.kappa;
+    kc.alpha_m = R.alpha / (double)p->m;
+    kc.clipb = R.clipb;
+    return kc;
+}
+
+// lam_{t+1} = tau1 + lam_t (1 - tau1 eta): the inverse form of step:eta_update.
+#pragma clang fp contract(off)
+double next_lam(double lam, double tau1, double eta) { return tau1 + lam * (1.0 - tau1 * eta); }
+#pragma clang fp contract(on)
+
+// Fills `cnt` schedule entries starting at lam_t0; returns lam_{t0 + cnt}.
+double fill_sched(std::vector<Sched>& tab, int cnt, double lam0, double tau1, double eta) {
+    tab.assign((size_t)cnt, Sched{});
+    double l0 = lam0;
+    for (int k = 0; k < cnt; ++k) {
+        double l1 = next_lam(l0, tau1, eta);
+        double l2 = next_lam(l1, tau1, eta);
+        tab[k].lamA = l0;
+        tab[k].lamB = l1;
+        tab[k].w = tau1 / l1;
+        tab[k].lamC = l2;
+        tab[k].w2 = tau1 / l2;
+        l0 = l1;
+    }
+    return l0;
+}
+
+// Exact offsets for the first row sweep of a call: h_i = min_j(-g^B_j/cfac^B - x~.y~).
+void launch_offsets(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
+    double* a = at<double>(ws, L.scratch);
+    hipLaunchKernelGGL(offset_coeffs, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl),
+                       at<Sched>(ws, L.sched), kc, at<double2>(ws, L.gtab), a);
+    launch_row_extreme(L, kc, d, ws, a, -1.0, st);
+    hipLaunchKernelGGL(row_extreme_merge, grid1(kc.n), dim3(BLOCK), 0, st, kc, at<double>(ws, L.rpart),
+                       (int)L.P_r, (const double*)nullptr, 0, at<double>(ws, L.H));
+}
+
+struct IterArgs {
+    DualBufs buf;
+    TraceCols tc;
+    double* log_za;
+    double* log_zb;
+};
+
+void launch_iteration(const lamp_problem* p, const Layout& L, Consts kc, void* ws, const IterArgs& ia,
+                      hipStream_t st) {
+    Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+    const Sched* sch = at<Sched>(ws, L.sched);
+    launch_row_sweep(L, kc, p->d, ws, st);
+    RowVarF32 rf{nullptr, nullptr, nullptr, 0};
+    if (is_mfma(L.prec)) rf = RowVarF32{at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf), 1};
+    hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, ctrl, sch, kc, p->d, at<double>(ws, L.xc),
+                       at<double>(ws, L.yc), at<double2>(ws, L.gtab), p->r, at<double>(ws, L.xn2),
+                       at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H), at<RowVar>(ws, L.rowvar),
+                       ia.log_za, ia.log_zb, rf);
+    launch_col_sweep(L, kc, p->d, ws, st);
+    hipLaunchKernelGGL(dual_update, grid1(kc.m), dim3(BLOCK), 0, st, ctrl, sch, kc, at<double2>(ws, L.cpart),
+                       col_parts(L), p->c, at<double>(ws, L.yn2), ia.buf, at<double2>(ws, L.gtab),
+                       at<double>(ws, L.respart), ia.tc);
+}
+
+lamp_status upload_ctrl(void* ws, const Layout& L, int64_t t, int64_t t_end, int64_t t_base, double tol,
+                        hipStream_t st, Ctrl* host) {
+    host->t = t;
+    host->t_end = t_end;
+    host->t_base = t_base;
+    host->t_done = -1;
+    host->done = 0;
+    host->err = 0;
+    host->fallbacks = 0;
+    host->counter = 0;
+    host->tol = tol;
+    host->res_last = -1.0;
+    HIPCHK(hipMemcpyAsync(at<Ctrl>(ws, L.ctrl), host, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+    return LAMP_OK;
+}
+
+lamp_status common_setup(const lamp_problem* p, const lamp_params* q, void* ws, size_t ws_bytes,
+                         hipStream_t st, Resolved* R) {
+    lamp_status e;
+    if ((e = check_problem(p)) != LAMP_OK) return e;
+    if ((e = check_params(q)) != LAMP_OK) return e;
+    if ((e = check_ws(p, ws, ws_bytes, q->precision)) != LAMP_OK) return e;
+    if ((e = check_marginals(p)) != LAMP_OK) return e;
+    if ((e = prep(p, ws, st, q->precision)) != LAMP_OK) return e;
+    return resolve(p, q, ws, st, R);
+}
+
+lamp_status check_state(const lamp_state* s) {
+    if (!s || !s->nu || !s->theta) return fail(LAMP_EINVAL, "state or its arrays are NULL");
+    if (s->t < 0 || !(s->inv_eta >= 0.0)) return fail(LAMP_EINVAL, "state has t < 0 or inv_eta < 0");
+    return LAMP_OK;
+}
+
+// Runs an A-only row pass at the state's iterate (lam_t, nu^t): afterwards
+// H = -sigma^A / cfac^A and gtab2[t&1] = (g^A, g^A); returns cfac^A.
+lamp_status state_normalisers(const lamp_problem* p, const lamp_params* q, const Resolved& R,
+                              const lamp_state* s, void* ws, hipStream_t st, double* cA_out) {
+    // the workspace is laid out for q->precision; the normalisers always use the FP64-argument sweeps
+    Layout L = layout(p->n, p->m, p->d, q->precision);
+    L.prec = LAMP_FP32;
+    const Consts kc = make_consts(p, R);
+    Ctrl hc;
+    lamp_status e = upload_ctrl(ws, L, s->t, s->t + 1, s->t, 0.0, st, &hc);
+    if (e != LAMP_OK) return e;
+    Sched sc{};
+    sc.lamA = sc.lamB = sc.lamC = s->inv_eta;
+    sc.w = sc.w2 = 0.0;   // nubar = nu: both halves evaluate p^{eta_t}(nu^t)
+    HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), &sc, sizeof(Sched), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));   // the uploads read host locals of this frame
+    hipLaunchKernelGGL(col_table_init, grid1(p->m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl),
+                       at<Sched>(ws, L.sched), kc, at<double>(ws, L.yn2), s->nu, s->theta, at<double2>(ws, L.gtab));
+    launch_offsets(L, kc, p->d, ws, st);
+    launch_row_sweep(L, kc, p->d, ws, st);
+    hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, p->d, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), p->r,
+                       at<double>(ws, L.xn2), at<double2>(ws, L.rpart), (int)L.P_r, at<double>(ws, L.H),
+                       at<RowVar>(ws, L.rowvar), (double*)nullptr, (double*)nullptr,
+                       RowVarF32{nullptr, nullptr, nullptr, 0});
+    HIPCHK(hipGetLastError());
+    *cA_out = 2.0 * R.s * s->inv_eta * LOG2E;
+    return LAMP_OK;
+}
+
+__global__ void gA_extract(int64_t m, int64_t par, const double2* __restrict__ gtab2, double* __restrict__ gA) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) gA[j] = gtab2[par * m + j].x;
+}
+
+__global__ void col_residual(Consts kc, const double2* __restrict__ cpart, int P, const double* __restrict__ c,
+                             double* __restrict__ out) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kc.m) return;
+    double col = 0.0;
+    for (int p = 0; p < P; ++p) col += cpart[(int64_t)p * kc.m + j].x;
+    out[j] = fabs(col - c[j]);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char* lamp_last_error(void) { return g_err; }
+
+size_t lamp_workspace_bytes(const lamp_problem* prob, const lamp_params* params) {
+    if (!prob || prob->n < 1 || prob->m < 1 || prob->d < 1) return 0;
+    const int prec = params ? params->precision : LAMP_FP32;
+    if (is_mfma(prec) && mfma_kp(prec, prob->d) == 0) return 0;
+    return layout(prob->n, prob->m, prob->d, prec).total;
+}
+
+lamp_status lamp_cost_scale(const lamp_problem* prob, void* ws, size_t ws_bytes, void* stream,
+                            double* s_out, double* max_sqdist_out) {
+    hipStream_t st = (hipStream_t)stream;
+    lamp_status e;
+    if ((e = check_problem(prob)) != LAMP_OK) return e;
+    if ((e = check_ws(prob, ws, ws_bytes)) != LAMP_OK) return e;
+    if ((e = prep(prob, ws, st)) != LAMP_OK) return e;
+    double md = 0.0;
+    if ((e = max_sqdist(prob, ws, st, &md, LAMP_FP32)) != LAMP_OK) return e;
+    if (!(md > 0.0)) return fail(LAMP_EDOMAIN, "all pairwise distances are zero");
+    if (s_out) *s_out = 1.0 / md;
+    if (max_sqdist_out) *max_sqdist_out = md;
+    return LAMP_OK;
+}
+
+lamp_status lamp_step(const lamp_problem* prob, const lamp_params* params, lamp_state* state, void* ws,
+                      size_t ws_bytes, void* stream, const lamp_trace* trace, double* res_out) {
+    hipStream_t st = (hipStream_t)stream;
+    lamp_status e;
+    if ((e = check_state(state)) != LAMP_OK) return e;
+    Resolved R;
+    if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Consts kc = make_consts(prob, R);
+    const int64_t t = state->t;
+    std::vector<Sched> tab;
+    fill_sched(tab, 1, state->inv_eta, R.tau1, params->eta);
+    HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched), hipMemcpyHostToDevice, st));
+    Ctrl hc;
+    if ((e = upload_ctrl(ws, L, t, t + 1, t, 0.0, st, &hc)) != LAMP_OK) return e;
+    IterArgs ia{};
+    ia.buf.nu[t & 1] = state->nu;
+    ia.buf.theta[t & 1] = state->theta;
+    ia.buf.nu[(t + 1) & 1] = at<double>(ws, L.nu1);
+    ia.buf.theta[(t + 1) & 1] = at<double>(ws, L.th1);
+    if (trace) {
+        ia.tc = TraceCols{trace->col_a, trace->col_b, trace->theta_bar, trace->theta_hat};
+        ia.log_za = trace->log_za;
+        ia.log_zb = trace->log_zb;
+    }
+    hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab));
+    launch_offsets(L, kc, prob->d, ws, st);
+    launch_iteration(prob, L, kc, ws, ia, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(state->nu, at<double>(ws, L.nu1), sizeof(double) * kc.m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(state->theta, at<double>(ws, L.th1), sizeof(double) * kc.m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(&hc, at<Ctrl>(ws, L.ctrl), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hc.err) return fail(LAMP_ENUMERIC, "non-finite value in the dual update at t = %lld", (long long)t);
+    if (res_out) *res_out = hc.res_last;
+    state->t = t + 1;
+    state->inv_eta = tab[0].lamB;
+    return LAMP_OK;
+}
+
+lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp_state* state, void* ws,
+                       size_t ws_bytes, void* stream, lamp_report* out) {
+    const auto t_start = std::chrono::steady_clock::now();
+    lamp_status e;
+    if ((e = check_state(state)) != LAMP_OK) return e;
+    // graph capture needs a non-default stream: use a private one when given NULL
+    hipStream_t st = (hipStream_t)stream;
+    hipStream_t own = nullptr;
+    if (!st) {
+        HIPCHK(hipStreamSynchronize(nullptr));
+        HIPCHK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        st = own;
+    }
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() {
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+            }
+        }
+    } guard{own};
+    Resolved R;
+    if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Consts kc = make_consts(prob, R);
+    const int64_t t0 = state->t;
+    const int64_t t_stop = t0 + params->max_iter;
+    const int K = params->check_every > 0 ? params->check_every : 64;
+
+    IterArgs ia{};
+    ia.buf.nu[t0 & 1] = state->nu;
+    ia.buf.theta[t0 & 1] = state->theta;
+    ia.buf.nu[(t0 + 1) & 1] = at<double>(ws, L.nu1);
+    ia.buf.theta[(t0 + 1) & 1] = at<double>(ws, L.th1);
+
+    std::vector<Sched> tab;
+    double lam_epoch = state->inv_eta;   // lam at t_base of the current epoch
+    int64_t t_base = t0;
+    double lam_next_epoch = fill_sched(tab, TAB, lam_epoch, R.tau1, params->eta);
+    HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice, st));
+    Ctrl hc;
+    int64_t t_end = std::min(t_stop, t_base + TAB);
+    if ((e = upload_ctrl(ws, L, t0, t_end, t_base, params->tol, st, &hc)) != LAMP_OK) return e;
+
+    hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab));
+    launch_offsets(L, kc, prob->d, ws, st);
+    HIPCHK(hipGetLastError());
+
+    // capture K iterations once; the kernels read t, the schedule and the stop flag
+    // from device memory, so the same graph is replayed for every chunk
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (t_stop > t0) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < K; ++k) launch_iteration(prob, L, kc, ws, ia, st);
+        hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (ce != hipSuccess) return fail(LAMP_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+        HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    int64_t t_cur = t0;
+    lamp_status result = LAMP_OK;
+    while (t_cur < t_stop) {
+        // two chunks in flight: the kernels of a chunk that starts after the stop exit at once
+        HIPCHK(hipGraphLaunch(exec, st));
+        HIPCHK(hipGraphLaunch(exec, st));
+        HIPCHK(hipMemcpyAsync(&hc, at<Ctrl>(ws, L.ctrl), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hc.err) {
+            result = fail(LAMP_ENUMERIC, "non-finite value in the dual update at t = %lld", (long long)hc.t_done);
+            t_cur = hc.t_done;
+            break;
+        }
+        if (hc.done) {
+            t_cur = hc.t_done;
+            break;
+        }
+        if (hc.t == t_cur && hc.t < hc.t_end)
+            return fail(LAMP_EDEVICE, "iteration counter did not advance past t = %lld", (long long)t_cur);
+        t_cur = hc.t;
+        if (t_cur >= t_stop) break;
+        if (t_cur >= hc.t_end) {
+            // new schedule epoch
+            t_base = t_cur;
+            lam_epoch = lam_next_epoch;
+            lam_next_epoch = fill_sched(tab, TAB, lam_epoch, R.tau1, params->eta);
+            HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice, st));
+            hc.t_end = std::min(t_stop, t_base + TAB);
+            hc.t_base = t_base;
+            HIPCHK(hipMemcpyAsync(at<Ctrl>(ws, L.ctrl), &hc, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+        }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    // the iterate of t_cur lives in buffer t_cur & 1
+    if (t_cur != t0 && (t_cur & 1) != (t0 & 1)) {
+        HIPCHK(hipMemcpyAsync(state->nu, at<double>(ws, L.nu1), sizeof(double) * kc.m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(state->theta, at<double>(ws, L.th1), sizeof(double) * kc.m, hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    // lam at t_cur (continue the recursion from the epoch base)
+    double lam = lam_epoch;
+    for (int64_t k = t_base; k < t_cur; ++k) lam = next_lam(lam, R.tau1, params->eta);
+    state->t = t_cur;
+    state->inv_eta = lam;
+    if (out) {
+        out->iters = t_cur - t0;
+        out->t = t_cur;
+        out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        out->final_res = hc.res_last;
+        out->cost_scale = R.s;
+        out->cost_norm = R.cnorm;
+        out->converged = hc.done && !hc.err;
+        out->row_fallbacks = hc.fallbacks;
+    }
+    if (result != LAMP_OK) return result;
+    return (hc.done || params->tol == 0.0) ? LAMP_OK : LAMP_NOT_CONVERGED;
+}
+
+lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
+                             void* ws, size_t ws_bytes, void* stream, lamp_cert* out) {
+    hipStream_t st = (hipStream_t)stream;
+    lamp_status e;
+    if ((e = check_state(state)) != LAMP_OK) return e;
+    if (state->t < 1 || !(state->inv_eta > 0.0)) return fail(LAMP_EINVAL, "the certificate needs t >= 1");
+    if (!out) return fail(LAMP_EINVAL, "out is NULL");
+    Resolved R;
+    if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Consts kc = make_consts(prob, R);
+    double cA = 0.0;
+    if ((e = state_normalisers(prob, params, R, state, ws, st, &cA)) != LAMP_OK) return e;
+    // column marginal col(X^t): the column sweep evaluates both (identical) halves
+    Layout LV = L;
+    LV.prec = LAMP_FP32;
+    launch_col_sweep(LV, kc, prob->d, ws, st);
+    double* sc = at<double>(ws, L.scratch);
+    const int64_t nm = std::max(kc.n, kc.m);
+    double* gA = sc;                 // m
+    double* colres = sc + nm;        // m
+    double* prods = sc + 2 * nm;     // 2m
+    double* vals = at<double>(ws, L.rpart);  // 4n
+    double* small = at<double>(ws, L.small);
+    hipLaunchKernelGGL(col_residual, grid1(kc.m), dim3(BLOCK), 0, st, kc, at<double2>(ws, L.cpart), (int)L.P_c,
+                       prob->c, colres);
+    hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
+                       at<double2>(ws, L.gtab), gA);
+    hipLaunchKernelGGL(cert_rows, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, cA, at<double>(ws, L.xc),
+                       at<double>(ws, L.yc), at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA, at<double>(ws, L.H),
+                       prob->r, state->nu, state->theta, vals);
+    hipLaunchKernelGGL(col_products, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->c, state->theta, state->nu, prods);
+    hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, vals, kc.n, kc.n, 4, small);
+    hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, colres, kc.m, kc.m, 1, small + 4);
+    hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, prods, kc.m, kc.m, 2, small + 5);
+    HIPCHK(hipGetLastError());
+    double h[8];
+    HIPCHK(hipMemcpyAsync(h, small, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out->row_res = h[0];
+    out->cost = h[1];
+    out->dual_theta = h[2] - R.K * h[5];
+    out->dual_nu = h[3] - R.K * h[6];
+    out->col_res = h[4];
+    out->primal_penalized = out->cost + R.K * (out->row_res + out->col_res);
+    out->gap = out->primal_penalized - std::max(out->dual_theta, out->dual_nu);
+    out->prop_bound = 4.0 * R.cnorm * out->col_res + 2.0 * R.cnorm * std::log((double)kc.m) / (double)state->t;
+    out->cost_scale = R.s;
+    out->cost_norm = R.cnorm;
+    out->t = state->t;
+    return LAMP_OK;
+}
+
+lamp_status lamp_backward(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
+                          double grad_out, float* grad_x, void* ws, size_t ws_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    lamp_status e;
+    if ((e = check_state(state)) != LAMP_OK) return e;
+    if (state->t < 1 || !(state->inv_eta > 0.0)) return fail(LAMP_EINVAL, "the gradient needs t >= 1");
+    if (!grad_x) return fail(LAMP_EINVAL, "grad_x is NULL");
+    Resolved R;
+    if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Consts kc = make_consts(prob, R);
+    double cA = 0.0;
+    if ((e = state_normalisers(prob, params, R, state, ws, st, &cA)) != LAMP_OK) return e;
+    double* gA = at<double>(ws, L.scratch);
+    hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
+                       at<double2>(ws, L.gtab), gA);
+    launch_adjoint(L, kc, prob->d, ws, cA, gA, st);
+    hipLaunchKernelGGL(adjoint_finish, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, (int)L.P_r,
+                       grad_out * 2.0 * R.s, at<double>(ws, L.xc), prob->r, at<double>(ws, L.rpart), grad_x);
+    HIPCHK(hipGetLastError());
+    return LAMP_OK;
+}
+
+lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
+                             void* ws, size_t ws_bytes, void* stream, int32_t reps, double* row_ms,
+                             double* col_ms) {
+    hipStream_t st = (hipStream_t)stream;
+    lamp_status e;
+    if ((e = check_state(state)) != LAMP_OK) return e;
+    if (reps < 1) return fail(LAMP_EINVAL, "reps must be >= 1");
+    Resolved R;
+    if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Consts kc = make_consts(prob, R);
+    std::vector<Sched> tab;
+    fill_sched(tab, 1, state->inv_eta, R.tau1, params->eta);
+    HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched), hipMemcpyHostToDevice, st));
+    Ctrl hc;
+    if ((e = upload_ctrl(ws, L, state->t, state->t + 1, state->t, 0.0, st, &hc)) != LAMP_OK) return e;
+    hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab));
+    launch_offsets(L, kc, prob->d, ws, st);
+    launch_row_sweep(L, kc, prob->d, ws, st);
+    hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched), kc,
+                       prob->d, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), prob->r,
+                       at<double>(ws, L.xn2), at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H),
+                       at<RowVar>(ws, L.rowvar), (double*)nullptr, (double*)nullptr,
+                       is_mfma(L.prec) ? RowVarF32{at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf), 1}
+                                       : RowVarF32{nullptr, nullptr, nullptr, 0});
+    HIPCHK(hipGetLastError());
+    hipEvent_t ev[4];
+    for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+    HIPCHK(hipEventRecord(ev[0], st));
+    for (int k = 0; k < reps; ++k) launch_row_sweep(L, kc, prob->d, ws, st);
+    HIPCHK(hipEventRecord(ev[1], st));
+    HIPCHK(hipEventRecord(ev[2], st));
+    for (int k = 0; k < reps; ++k) launch_col_sweep(L, kc, prob->d, ws, st);
+    HIPCHK(hipEventRecord(ev[3], st));
+    HIPCHK(hipEventSynchronize(ev[3]));
+    float a = 0.f, b = 0.f;
+    HIPCHK(hipEventElapsedTime(&a, ev[0], ev[1]));
+    HIPCHK(hipEventElapsedTime(&b, ev[2], ev[3]));
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (row_ms) *row_ms = a / reps;
+    if (col_ms) *col_ms = b / reps;
+    return LAMP_OK;
+}
+
+}  // extern "C"

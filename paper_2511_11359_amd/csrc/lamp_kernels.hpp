@@ -1,0 +1,791 @@
+// HIP kernels (gfx950) of the LAMP iteration: Algorithm 2 with the log-domain
+// marginals of Section 4.1, for the cost C_ij = s ||x_i - y_j||^2 generated on
+// the fly.
+//
+// Notation (all logarithms of probabilities are kept in base 2; LOG2E = 1/ln 2):
+//   points are centred, x~_i = x_i - mu, y~_j = y_j - mu (C is translation
+//   invariant), stored as FP64, with squared norms xn2_i, yn2_j;
+//   for a dual vector v and inverse temperature lam (= 1/eta),
+//     e_ij = -lam LOG2E (C_ij + K v_j)                                  K = 2||C||_inf
+//          = q_i + g_j + cfac * (x~_i . y~_j)
+//     q_i  = -lam LOG2E s xn2_i,  g_j = -lam LOG2E (s yn2_j + K v_j),  cfac = 2 s lam LOG2E.
+//   The row log-normaliser (Section 4.1, first display) in base 2 is
+//     l_i = q_i + sigma_i,   sigma_i = log2 sum_j 2^(g_j + cfac x~_i.y~_j).
+//   Iteration t evaluates two couplings: A = p^{eta_t}(nu^t) and B = p^{eta_{t+1}}(nubar^{t+1}).
+//
+// Row sweep: a per-row offset h_i (in dot-product units) is shared by A and B;
+//     S_i = sum_j 2^(cfac (h_i + x~_i.y~_j) + g_j) = 2^(cfac h_i + sigma_i).
+// h_i is the previous iteration's -sigma^B_i / cfac^B, which keeps every
+// exponent within a few units of 0 (the per-iteration change of the exponents
+// is bounded by tau1 ||C||_inf-scaled terms); rows whose sums leave a safe range
+// are recomputed exactly.  No running max is needed.
+//
+// Column sweep (Section 4.1, second display): with k_i = -sigma^B_i / cfac^B,
+//     p^B_ij = 2^(cfac^B (k_i + x~.y~) + g^B_j)
+//     p^A_ij = 2^(rho sigma^B_i - sigma^A_i) * 2^(cfac^A (k_i + x~.y~) + g^A_j),  rho = cfac^A/cfac^B,
+// so col_j = sum_i w_i 2^(...) with per-row weights w^B_i = r_i, w^A_i = r_i 2^(rho sigma^B - sigma^A).
+//
+// Every (i, j) exponent is assembled in FP64 (full-rate FMA on CDNA4), converted
+// to FP32 and exponentiated with v_exp_f32; sums run in FP32 within short chunks
+// and are carried in FP64.  The streamed side of each sweep (columns for the row
+// sweep, rows for the column sweep) is wave-uniform and is read through scalar
+// loads; the owned side lives in VGPRs, one row (or column) per lane.  Partial
+// sums over splits of the streamed range go to a workspace and are merged in a
+// fixed order, so results are deterministic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lampk {
+
+constexpr double LOG2E = 1.4426950408889634074;
+constexpr double LN2 = 0.69314718055994530942;
+constexpr int BLOCK = 256;
+constexpr int UNROLL = 8;
+
+// Device-side control block (lives in the workspace).
+struct Ctrl {
+    int64_t t;          // index of the iteration the next kernels execute
+    int64_t t_end;      // exclusive end of this call's iterations
+    int64_t t_base;     // schedule index base: sched[t - t_base]
+    int64_t t_done;     // iteration whose residual met tol (-1 otherwise)
+    int32_t done;       // 1 once res_t <= tol
+    int32_t err;        // bit 0: non-finite value in the dual update
+    int32_t fallbacks;  // rows recomputed exactly
+    uint32_t counter;   // last-block detection of dual_update
+    double tol;         // 0: never stop early
+    double res_last;    // ||col(X^t) - c||_1 of the last completed iteration
+};
+
+// Per-iteration scalars, filled on the host in FP64 by the recursion of step:eta_update.
+struct Sched {
+    double lamA;   // lam_t
+    double lamB;   // lam_{t+1}
+    double w;      // tau1 / lam_{t+1}  (= tau1 eta_{t+1})
+    double lamC;   // lam_{t+2}
+    double w2;     // tau1 / lam_{t+2}
+    double pad[3];
+};
+
+// Per-solve constants.
+struct Consts {
+    int64_t n, m;
+    double s;       // cost scale
+    double K;       // 2 ||C||_inf
+    double kappa;   // 2 tau2 ||C||_inf
+    double alpha_m; // alpha / m
+    double clipb;   // tanh(beta / 2)
+};
+
+// Row data streamed by the column sweep.
+struct RowVar {
+    double k;   // -sigma^B_i / cfac^B
+    float wA;   // r_i 2^(rho sigma^B_i - sigma^A_i)
+    float wB;   // r_i
+};
+
+__device__ __forceinline__ bool halted(const Ctrl* ctrl) {
+    return ctrl->done != 0 || ctrl->t >= ctrl->t_end;
+}
+
+__device__ __forceinline__ float fexp2(double e) {
+    return __builtin_amdgcn_exp2f(static_cast<float>(e));
+}
+
+// ---------------------------------------------------------------------------
+// Preparation: centred FP64 copies, squared norms.
+// ---------------------------------------------------------------------------
+__global__ void prep_points(const float* __restrict__ pts, int64_t cnt, int d,
+                            const float* __restrict__ mu_src_a, const float* __restrict__ mu_src_b,
+                            double* __restrict__ out, double* __restrict__ nrm2,
+                            float* __restrict__ outf) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        // centre mu = (x_0 + y_0) / 2: any fixed point works, this one keeps
+        // the coordinates of both clouds within one diameter of the origin
+        double mu = 0.5 * ((double)mu_src_a[k] + (double)mu_src_b[k]);
+        double v = (double)pts[i * d + k] - mu;
+        out[i * d + k] = v;
+        if (outf) outf[i * d + k] = (float)v;
+        acc = fma(v, v, acc);
+    }
+    nrm2[i] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Column table of iteration t from the state (nu^t, theta^t):
+//   g^A_j = -lam_t LOG2E (s yn2_j + K nu_j),  g^B_j = -lam_{t+1} LOG2E (s yn2_j + K nubar_j),
+//   nubar = nu + w (theta - nu)  (step:lamp_mid_nu).
+// ---------------------------------------------------------------------------
+__global__ void col_table_init(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                               const double* __restrict__ yn2, const double* __restrict__ nu,
+                               const double* __restrict__ theta, double2* __restrict__ gtab2) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kc.m) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    double nb = nu[j] + sc.w * (theta[j] - nu[j]);
+    double base = kc.s * yn2[j];
+    double2 g;
+    g.x = -sc.lamA * LOG2E * (base + kc.K * nu[j]);
+    g.y = -sc.lamB * LOG2E * (base + kc.K * nb);
+    gtab2[(t & 1) * kc.m + j] = g;
+}
+
+// a_j = -g^B_j / cfac^B for the exact offset initialisation.
+__global__ void offset_coeffs(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                              const double2* __restrict__ gtab2, double* __restrict__ a) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kc.m) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    a[j] = -gtab2[(t & 1) * kc.m + j].y / cB;
+}
+
+// ---------------------------------------------------------------------------
+// Row extreme sweep: out_i = min_j (a_j + sgn * x~_i . y~_j), FP64, exact.
+// Used for the exact offsets, D(theta) and the cost maximum.
+// part: [P][n] partial minima over column splits.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(BLOCK) void row_extreme(Consts kc, const double* __restrict__ xc,
+                                                     const double* __restrict__ yc,
+                                                     const double* __restrict__ a, double sgn,
+                                                     double* __restrict__ part, int64_t split) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t j0 = p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
+    const int64_t ii = i < kc.n ? i : kc.n - 1;
+    double x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = sgn * xc[ii * D + k];
+    double best = __builtin_inf();
+    for (int64_t j = j0; j < j1; ++j) {
+        double dot = a[j];
+#pragma unroll
+        for (int k = 0; k < D; ++k) dot = fma(x[k], yc[j * D + k], dot);
+        best = fmin(best, dot);
+    }
+    if (i < kc.n) part[p * kc.n + i] = best;
+}
+
+// Generic-d version: coordinates read per pair.
+__global__ __launch_bounds__(BLOCK) void row_extreme_dyn(Consts kc, int D, const double* __restrict__ xc,
+                                                         const double* __restrict__ yc,
+                                                         const double* __restrict__ a, double sgn,
+                                                         double* __restrict__ part, int64_t split) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t j0 = p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
+    const int64_t ii = i < kc.n ? i : kc.n - 1;
+    double best = __builtin_inf();
+    for (int64_t j = j0; j < j1; ++j) {
+        double dot = a[j];
+        for (int k = 0; k < D; ++k) dot = fma(sgn * xc[ii * D + k], yc[j * D + k], dot);
+        best = fmin(best, dot);
+    }
+    if (i < kc.n) part[p * kc.n + i] = best;
+}
+
+// Merge the partial minima (exact, order independent); optionally transform.
+//   mode 0: out_i = min            (offset init, writes H)
+//   mode 1: out_i = xn2_i - 2 min  (squared distance maximum of row i)
+__global__ void row_extreme_merge(Consts kc, const double* __restrict__ part, int P,
+                                  const double* __restrict__ xn2, int mode,
+                                  double* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    double best = part[i];
+    for (int p = 1; p < P; ++p) best = fmin(best, part[(int64_t)p * kc.n + i]);
+    out[i] = (mode == 0) ? best : xn2[i] - 2.0 * best;
+}
+
+// ---------------------------------------------------------------------------
+// Row sweep: the two row sums S^A_i, S^B_i with the shared offset h_i.
+// part: [P][n] double2.
+// ---------------------------------------------------------------------------
+// e = a * b + c with c wave-uniform (an SGPR pair).  The VOP3 form takes the
+// scalar operand directly; the compiler otherwise copies c into VGPRs for the
+// two-address v_fmac_f64 form, costing two extra VALU moves per use.
+__device__ __forceinline__ double fma_su(double a, double b, double c_uniform) {
+    double e;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(e) : "v"(a), "v"(b), "s"(c_uniform));
+    return e;
+}
+
+// One column j of the row sweep for this lane's row: returns 2^eA, 2^eB.
+template <int D>
+__device__ __forceinline__ void row_terms(const double (&x)[D], double h, const double* __restrict__ yj,
+                                          double2 g, double cA, double cB, float& pA, float& pB) {
+    double dot = h;
+#pragma unroll
+    for (int k = 0; k < D; ++k) dot = fma(x[k], yj[k], dot);
+    pA = fexp2(fma_su(dot, cA, g.x));
+    pB = fexp2(fma_su(dot, cB, g.y));
+}
+
+template <int D>
+__global__ __launch_bounds__(BLOCK) void row_sweep(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                   const double* __restrict__ xc,
+                                                   const double* __restrict__ yc,
+                                                   const double2* __restrict__ gtab2,
+                                                   const double* __restrict__ H,
+                                                   double2* __restrict__ part, int64_t split) {
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
+
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t j0 = p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
+    const int64_t ii = i < kc.n ? i : kc.n - 1;
+    double x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = xc[ii * D + k];
+    const double h = H[ii];
+
+    double sumA = 0.0, sumB = 0.0;
+    const int nfull = (int)((j1 - j0) / UNROLL);
+    const double* __restrict__ yp = yc + j0 * D;
+    const double2* __restrict__ gp = g + j0;
+    for (int c = 0; c < nfull; ++c, yp += UNROLL * D, gp += UNROLL) {
+        float pA[UNROLL], pB[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) row_terms<D>(x, h, yp + u * D, gp[u], cA, cB, pA[u], pB[u]);
+        float accA = pA[0], accB = pB[0];
+#pragma unroll
+        for (int u = 1; u < UNROLL; ++u) {
+            accA += pA[u];
+            accB += pB[u];
+        }
+        sumA += (double)accA;
+        sumB += (double)accB;
+    }
+    {
+        const int rem = (int)((j1 - j0) - (int64_t)nfull * UNROLL);
+        float accA = 0.f, accB = 0.f;
+        for (int u = 0; u < rem; ++u) {
+            float a, b;
+            row_terms<D>(x, h, yp + u * D, gp[u], cA, cB, a, b);
+            accA += a;
+            accB += b;
+        }
+        sumA += (double)accA;
+        sumB += (double)accB;
+    }
+    if (i < kc.n) part[p * kc.n + i] = make_double2(sumA, sumB);
+}
+
+__global__ __launch_bounds__(BLOCK) void row_sweep_dyn(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+                                                       const double* __restrict__ xc,
+                                                       const double* __restrict__ yc,
+                                                       const double2* __restrict__ gtab2,
+                                                       const double* __restrict__ H,
+                                                       double2* __restrict__ part, int64_t split) {
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t j0 = p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
+    const int64_t ii = i < kc.n ? i : kc.n - 1;
+    const double h = H[ii];
+    double sumA = 0.0, sumB = 0.0;
+    for (int64_t jb = j0; jb < j1; jb += UNROLL) {
+        float accA = 0.f, accB = 0.f;
+        const int64_t je = min(j1, jb + UNROLL);
+        for (int64_t j = jb; j < je; ++j) {
+            double dot = h;
+            for (int k = 0; k < D; ++k) dot = fma(xc[ii * D + k], yc[j * D + k], dot);
+            accA += fexp2(fma(cA, dot, g[j].x));
+            accB += fexp2(fma(cB, dot, g[j].y));
+        }
+        sumA += (double)accA;
+        sumB += (double)accB;
+    }
+    if (i < kc.n) part[p * kc.n + i] = make_double2(sumA, sumB);
+}
+
+// Exact recomputation of sigma_i = log2 sum_j 2^(g_j + cfac x~_i.y~_j) (two passes, FP64 max).
+__device__ double exact_sigma(const double* __restrict__ xi, const double* __restrict__ yc, int D,
+                              int64_t m, const double2* __restrict__ g, int which, double cfac) {
+    double mx = -__builtin_inf();
+    for (int64_t j = 0; j < m; ++j) {
+        double dot = 0.0;
+        for (int k = 0; k < D; ++k) dot = fma(xi[k], yc[j * D + k], dot);
+        double e = fma(cfac, dot, which ? g[j].y : g[j].x);
+        mx = fmax(mx, e);
+    }
+    double s = 0.0;
+    for (int64_t j = 0; j < m; ++j) {
+        double dot = 0.0;
+        for (int k = 0; k < D; ++k) dot = fma(xi[k], yc[j * D + k], dot);
+        double e = fma(cfac, dot, which ? g[j].y : g[j].x);
+        s += exp2(e - mx);
+    }
+    return mx + log2(s);
+}
+
+// Merge the row partials; derive sigma^A, sigma^B, the next offsets and the
+// column-sweep row data; optional natural-log normalisers.
+// FP32 row data of the matrix-core column sweep (nullable): k rounded to FP32,
+// with the rounding error folded exactly into the weights.  f32_offsets: the row
+// sweep applied (float)H, so that value is the one to subtract.
+struct RowVarF32 {
+    float* k;
+    float* wA;
+    float* wB;
+    int f32_offsets;
+};
+
+__global__ void row_finish(Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+                           const double* __restrict__ xc, const double* __restrict__ yc,
+                           const double2* __restrict__ gtab2, const double* __restrict__ r,
+                           const double* __restrict__ xn2, const double2* __restrict__ part, int P,
+                           double* __restrict__ H, RowVar* __restrict__ rowvar,
+                           double* __restrict__ log_za, double* __restrict__ log_zb, RowVarF32 rf) {
+    if (halted(ctrl)) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    double SA = 0.0, SB = 0.0;
+    for (int p = 0; p < P; ++p) {
+        double2 v = part[(int64_t)p * kc.n + i];
+        SA += v.x;
+        SB += v.y;
+    }
+    const double h = rf.f32_offsets ? (double)(float)H[i] : H[i];
+    double sigA, sigB;
+    const double lo = 0x1p-60, hi = 0x1p+60;
+    if (SA >= lo && SA <= hi && SB >= lo && SB <= hi) {
+        sigA = log2(SA) - cA * h;
+        sigB = log2(SB) - cB * h;
+    } else {
+        const double2* g = gtab2 + (t & 1) * kc.m;
+        sigA = exact_sigma(xc + i * D, yc, D, kc.m, g, 0, cA);
+        sigB = exact_sigma(xc + i * D, yc, D, kc.m, g, 1, cB);
+        atomicAdd(&ctrl->fallbacks, 1);
+    }
+    const double hnew = -sigB / cB;
+    const double rho = cA / cB;
+    double ew = rho * sigB - sigA;
+    ew = fmin(fmax(ew, -1000.0), 1000.0);
+    H[i] = hnew;
+    RowVar rv;
+    rv.k = hnew;
+    rv.wA = (float)(r[i] * exp2(ew));
+    rv.wB = (float)r[i];
+    rowvar[i] = rv;
+    if (rf.k) {
+        const float kf = (float)hnew;
+        const double dk = hnew - (double)kf;
+        rf.k[i] = kf;
+        rf.wA[i] = (float)(r[i] * exp2(fmin(fmax(ew + cA * dk, -1000.0), 1000.0)));
+        rf.wB[i] = (float)(r[i] * exp2(cB * dk));
+    }
+    if (log_za) log_za[i] = LN2 * (-sc.lamA * LOG2E * kc.s * xn2[i] + sigA);
+    if (log_zb) log_zb[i] = LN2 * (-sc.lamB * LOG2E * kc.s * xn2[i] + sigB);
+}
+
+// ---------------------------------------------------------------------------
+// Column sweep: col^A_j, col^B_j.  cpart: [P][m] double2.
+// ---------------------------------------------------------------------------
+// One row i of the column sweep for this lane's column: w^A 2^eA, w^B 2^eB are
+// accumulated with the row weights as the scalar multiplicand.
+template <int D>
+__device__ __forceinline__ void col_terms(const double (&y)[D], const double* __restrict__ xi, RowVar rv,
+                                          double gA, double gB, double cA, double cB, float& accA,
+                                          float& accB) {
+    double dot = y[0] * xi[0];
+#pragma unroll
+    for (int k = 1; k < D; ++k) dot = fma(y[k], xi[k], dot);
+    dot = dot + rv.k;
+    accA = fmaf(rv.wA, fexp2(fma(dot, cA, gA)), accA);
+    accB = fmaf(rv.wB, fexp2(fma(dot, cB, gB)), accB);
+}
+
+template <int D>
+__global__ __launch_bounds__(BLOCK) void col_sweep(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                   const double* __restrict__ xc,
+                                                   const double* __restrict__ yc,
+                                                   const double2* __restrict__ gtab2,
+                                                   const RowVar* __restrict__ rowvar,
+                                                   double2* __restrict__ cpart, int64_t split) {
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t i0 = p * split;
+    const int64_t i1 = min(kc.n, i0 + split);
+    const int64_t jj = j < kc.m ? j : kc.m - 1;
+    double y[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) y[k] = yc[jj * D + k];
+    const double2 g = gtab2[(t & 1) * kc.m + jj];
+
+    double sumA = 0.0, sumB = 0.0;
+    const int nfull = (int)((i1 - i0) / UNROLL);
+    const double* __restrict__ xp = xc + i0 * D;
+    const RowVar* __restrict__ rp = rowvar + i0;
+    for (int c = 0; c < nfull; ++c, xp += UNROLL * D, rp += UNROLL) {
+        float accA = 0.f, accB = 0.f;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) col_terms<D>(y, xp + u * D, rp[u], g.x, g.y, cA, cB, accA, accB);
+        sumA += (double)accA;
+        sumB += (double)accB;
+    }
+    {
+        const int rem = (int)((i1 - i0) - (int64_t)nfull * UNROLL);
+        float accA = 0.f, accB = 0.f;
+        for (int u = 0; u < rem; ++u) col_terms<D>(y, xp + u * D, rp[u], g.x, g.y, cA, cB, accA, accB);
+        sumA += (double)accA;
+        sumB += (double)accB;
+    }
+    if (j < kc.m) cpart[p * kc.m + j] = make_double2(sumA, sumB);
+}
+
+__global__ __launch_bounds__(BLOCK) void col_sweep_dyn(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+                                                       const double* __restrict__ xc,
+                                                       const double* __restrict__ yc,
+                                                       const double2* __restrict__ gtab2,
+                                                       const RowVar* __restrict__ rowvar,
+                                                       double2* __restrict__ cpart, int64_t split) {
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t i0 = p * split;
+    const int64_t i1 = min(kc.n, i0 + split);
+    const int64_t jj = j < kc.m ? j : kc.m - 1;
+    const double2 g = gtab2[(t & 1) * kc.m + jj];
+    double sumA = 0.0, sumB = 0.0;
+    for (int64_t ib = i0; ib < i1; ib += UNROLL) {
+        float accA = 0.f, accB = 0.f;
+        const int64_t ie = min(i1, ib + UNROLL);
+        for (int64_t i = ib; i < ie; ++i) {
+            const RowVar rv = rowvar[i];
+            double dot = rv.k;
+            for (int k = 0; k < D; ++k) dot = fma(yc[jj * D + k], xc[i * D + k], dot);
+            accA = fmaf(rv.wA, fexp2(fma(cA, dot, g.x)), accA);
+            accB = fmaf(rv.wB, fexp2(fma(cB, dot, g.y)), accB);
+        }
+        sumA += (double)accA;
+        sumB += (double)accB;
+    }
+    if (j < kc.m) cpart[p * kc.m + j] = make_double2(sumA, sumB);
+}
+
+// ---------------------------------------------------------------------------
+// Dual update (S5-S6 of Algorithm 2), residual, next column table, stop flag.
+// State is double-buffered by iteration parity: iteration t reads buffer t&1 and
+// writes buffer (t+1)&1, so the iterate that met the tolerance is never
+// overwritten.
+// ---------------------------------------------------------------------------
+struct DualBufs {
+    double* nu[2];
+    double* theta[2];
+};
+
+struct TraceCols {
+    double *col_a, *col_b, *theta_bar, *theta_hat;
+};
+
+__global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                     const double2* __restrict__ cpart, int P,
+                                                     const double* __restrict__ c,
+                                                     const double* __restrict__ yn2, DualBufs buf,
+                                                     double2* __restrict__ gtab2,
+                                                     double* __restrict__ respart, TraceCols tr) {
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double res = 0.0;
+    int bad = 0;
+    if (j < kc.m) {
+        double colA = 0.0, colB = 0.0;
+        for (int p = 0; p < P; ++p) {
+            double2 v = cpart[(int64_t)p * kc.m + j];
+            colA += v.x;
+            colB += v.y;
+        }
+        const double* nu_r = buf.nu[t & 1];
+        const double* th_r = buf.theta[t & 1];
+        double* nu_w = buf.nu[(t + 1) & 1];
+        double* th_w = buf.theta[(t + 1) & 1];
+        const double cj = c[j];
+        const double calpha = cj + kc.alpha_m;       // c^alpha = c + (alpha/m) 1
+        const double nu = nu_r[j], th = th_r[j];
+        const double a = atanh(th);
+        // closed form of the dual mirror map (def:closed_form_opt)
+        const double tbar = tanh(a + kc.kappa * (colA - cj) / calpha);
+        const double that = tanh(a + kc.kappa * (colB - cj) / calpha);
+        const double nun = nu + sc.w * (tbar - nu);            // step:lamp_main_nu
+        const double thn = fmin(fmax(that, -kc.clipb), kc.clipb);  // tclip
+        nu_w[j] = nun;
+        th_w[j] = thn;
+        // column table of iteration t+1
+        const double nbn = nun + sc.w2 * (thn - nun);          // step:lamp_mid_nu at t+1
+        const double base = kc.s * yn2[j];
+        double2 gn;
+        gn.x = -sc.lamB * LOG2E * (base + kc.K * nun);
+        gn.y = -sc.lamC * LOG2E * (base + kc.K * nbn);
+        gtab2[((t + 1) & 1) * kc.m + j] = gn;
+        res = fabs(colA - cj);
+        bad = !(isfinite(nun) && isfinite(thn) && isfinite(colA) && isfinite(colB)) || fabs(th) >= 1.0;
+        if (tr.col_a) tr.col_a[j] = colA;
+        if (tr.col_b) tr.col_b[j] = colB;
+        if (tr.theta_bar) tr.theta_bar[j] = tbar;
+        if (tr.theta_hat) tr.theta_hat[j] = that;
+    }
+    // block reduction of the residual (fixed order: deterministic)
+    __shared__ double sh[BLOCK];
+    __shared__ int shbad;
+    if (threadIdx.x == 0) shbad = 0;
+    __syncthreads();
+    if (bad) atomicOr(&shbad, 1);
+    sh[threadIdx.x] = res;
+    __syncthreads();
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        respart[blockIdx.x] = sh[0];
+        if (shbad) atomicOr(&ctrl->err, 1);
+        __threadfence();
+        unsigned prev = atomicAdd(&ctrl->counter, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    // the last block: total residual in block order, stop decision, advance t
+    __threadfence();
+    double tot = 0.0;
+    if (threadIdx.x == 0) {
+        for (unsigned b = 0; b < gridDim.x; ++b) tot += __hip_atomic_load(&respart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ctrl->res_last = tot;
+        ctrl->counter = 0;
+        if (ctrl->err) {
+            ctrl->done = 1;
+            ctrl->t_done = t;
+        } else if (ctrl->tol > 0.0 && tot <= ctrl->tol) {
+            ctrl->done = 1;
+            ctrl->t_done = t;
+        } else {
+            ctrl->t = t + 1;
+        }
+        __threadfence();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic single-block reductions.
+// ---------------------------------------------------------------------------
+// out[k] = sum_i v_k(i) for the certificate: mode selects the terms.
+__global__ void reduce_max(const double* __restrict__ v, int64_t n, double* __restrict__ out) {
+    __shared__ double sh[1024];
+    double best = -__builtin_inf();
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) best = fmax(best, v[i]);
+    sh[threadIdx.x] = best;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// sums[q] = sum_i vals[q * stride + i] for q < Q (each a fixed-order tree).
+__global__ void reduce_sums(const double* __restrict__ vals, int64_t n, int64_t stride, int Q,
+                            double* __restrict__ out) {
+    __shared__ double sh[1024];
+    for (int q = 0; q < Q; ++q) {
+        double acc = 0.0;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += vals[q * stride + i];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[q] = sh[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Certificate row sweep at the state's iterate (offsets from an A-only
+// row_finish so that log2 p_ij = cfac (h_i + x~.y~) + g_j exactly):
+//   vals[0][i] = r_i |sum_j p_ij - 1|                 (row infeasibility)
+//   vals[1][i] = r_i sum_j C_ij p_ij                  (<C, X^t>)
+//   vals[2][i] = r_i min_j (C_ij + K theta_j)         (D(theta), def:dual_spp)
+//   vals[3][i] = r_i min_j (C_ij + K nu_j)            (D(nu))
+// FP64 throughout (including the exponential); not on the iteration path.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int D, double cA,
+                                                   const double* __restrict__ xc,
+                                                   const double* __restrict__ yc,
+                                                   const double* __restrict__ xn2,
+                                                   const double* __restrict__ yn2,
+                                                   const double* __restrict__ gA,
+                                                   const double* __restrict__ H,
+                                                   const double* __restrict__ r,
+                                                   const double* __restrict__ nu,
+                                                   const double* __restrict__ theta,
+                                                   double* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= kc.n) return;
+    const double h = H[i];
+    double psum = 0.0, csum = 0.0, mth = __builtin_inf(), mnu = __builtin_inf();
+    for (int64_t j = 0; j < kc.m; ++j) {
+        double dot = 0.0;
+        for (int k = 0; k < D; ++k) dot = fma(xc[i * D + k], yc[j * D + k], dot);
+        const double pij = exp2(fma(cA, h + dot, gA[j]));
+        const double cij = kc.s * (xn2[i] + yn2[j] - 2.0 * dot);
+        psum += pij;
+        csum = fma(cij, pij, csum);
+        mth = fmin(mth, cij + kc.K * theta[j]);
+        mnu = fmin(mnu, cij + kc.K * nu[j]);
+    }
+    const double ri = r[i];
+    vals[i] = ri * fabs(psum - 1.0);
+    vals[kc.n + i] = ri * csum;
+    vals[2 * kc.n + i] = ri * mth;
+    vals[3 * kc.n + i] = ri * mnu;
+}
+
+// g^A_j for an arbitrary (lam, v): gA_j = -lam LOG2E (s yn2_j + K v_j).
+__global__ void col_table_single(Consts kc, double lam, const double* __restrict__ yn2,
+                                 const double* __restrict__ v, double* __restrict__ gA) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kc.m) return;
+    gA[j] = -lam * LOG2E * (kc.s * yn2[j] + kc.K * v[j]);
+}
+
+// c_j * theta_j products for <c, theta>, <c, nu>.
+__global__ void col_products(Consts kc, const double* __restrict__ c, const double* __restrict__ a,
+                             const double* __restrict__ b, double* __restrict__ out) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kc.m) return;
+    out[j] = c[j] * a[j];
+    out[kc.m + j] = c[j] * b[j];
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint sweep (envelope gradient): per row i, with p_ij = 2^(cfac (h_i + x~.y~) + g_j),
+//   S0_i = sum_j p_ij,  S1_i = sum_j p_ij y~_j;  grad_i = scale r_i (S0_i x~_i - S1_i).
+// part: [P][n][D+1] partial sums over column splits.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, const double* __restrict__ xc,
+                                                       const double* __restrict__ yc,
+                                                       const float* __restrict__ ycf,
+                                                       const double* __restrict__ gA,
+                                                       const double* __restrict__ H,
+                                                       double* __restrict__ part, int64_t split) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t j0 = p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
+    const int64_t ii = i < kc.n ? i : kc.n - 1;
+    double x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = xc[ii * D + k];
+    const double h = H[ii];
+    double s0 = 0.0, s1[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) s1[k] = 0.0;
+    for (int64_t jb = j0; jb < j1; jb += UNROLL) {
+        float a0 = 0.f, a1[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) a1[k] = 0.f;
+        const int64_t je = min(j1, jb + UNROLL);
+        for (int64_t j = jb; j < je; ++j) {
+            double dot = h;
+#pragma unroll
+            for (int k = 0; k < D; ++k) dot = fma(x[k], yc[j * D + k], dot);
+            const float pij = fexp2(fma(cA, dot, gA[j]));
+            a0 += pij;
+#pragma unroll
+            for (int k = 0; k < D; ++k) a1[k] = fmaf(pij, ycf[j * D + k], a1[k]);
+        }
+        s0 += (double)a0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s1[k] += (double)a1[k];
+    }
+    if (i < kc.n) {
+        double* o = part + (p * kc.n + i) * (D + 1);
+        o[0] = s0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) o[1 + k] = s1[k];
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void adjoint_sweep_dyn(Consts kc, int D, double cA,
+                                                           const double* __restrict__ xc,
+                                                           const double* __restrict__ yc,
+                                                           const float* __restrict__ ycf,
+                                                           const double* __restrict__ gA,
+                                                           const double* __restrict__ H,
+                                                           double* __restrict__ part, int64_t split) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t j0 = p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
+    const int64_t ii = i < kc.n ? i : kc.n - 1;
+    const double h = H[ii];
+    double* o = part + (p * kc.n + ii) * (D + 1);
+    double s0 = 0.0;
+    if (i < kc.n)
+        for (int k = 0; k < D; ++k) o[1 + k] = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        double dot = h;
+        for (int k = 0; k < D; ++k) dot = fma(xc[ii * D + k], yc[j * D + k], dot);
+        const double pij = (double)fexp2(fma(cA, dot, gA[j]));
+        s0 += pij;
+        if (i < kc.n)
+            for (int k = 0; k < D; ++k) o[1 + k] += pij * (double)ycf[j * D + k];
+    }
+    if (i < kc.n) o[0] = s0;
+}
+
+__global__ void adjoint_finish(Consts kc, int D, int P, double scale, const double* __restrict__ xc,
+                               const double* __restrict__ r, const double* __restrict__ part,
+                               float* __restrict__ grad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    double s0 = 0.0;
+    for (int p = 0; p < P; ++p) s0 += part[((int64_t)p * kc.n + i) * (D + 1)];
+    for (int k = 0; k < D; ++k) {
+        double s1 = 0.0;
+        for (int p = 0; p < P; ++p) s1 += part[((int64_t)p * kc.n + i) * (D + 1) + 1 + k];
+        grad[i * D + k] = (float)(scale * r[i] * (s0 * xc[i * D + k] - s1));
+    }
+}
+
+}  // namespace lampk

@@ -145,3 +145,10 @@ WORKLOADS = {
     "gmm64d_65536": gmm64,
     "sphere_cube_262144": sphere_cube,
 }
+
+
+def synthetic_duals(m: int, seed: int, amp: float = 0.4):
+    """A seeded dual state (nu, theta), each coordinate uniform in [-amp, amp]: a starting point
+    for single-iteration parity checks at large sizes, where no reference trajectory exists."""
+    g = _rng(seed)
+    return g.uniform(-amp, amp, m), g.uniform(-amp, amp, m)

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every function include/lamp.h declares, and
+the ctypes structures have the C layout (no compute calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2511_11359_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lamp.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lamp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ["lamp_solve", "lamp_step", "lamp_certificate", "lamp_backward",
+                     "lamp_workspace_bytes", "lamp_last_error", "lamp_cost_scale"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("liblamp.so not built")
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SYMBOLS, f"{name} has no ctypes declaration"
+
+
+def test_ctypes_layout_matches_c(tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "lamp.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "sizeof(lamp_problem), sizeof(lamp_params), sizeof(lamp_state), sizeof(lamp_trace),"
+        "sizeof(lamp_cert), sizeof(lamp_report), offsetof(lamp_problem, cost_norm),"
+        "offsetof(lamp_params, check_every), offsetof(lamp_report, row_fallbacks));return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(_lib.Problem), ctypes.sizeof(_lib.Params), ctypes.sizeof(_lib.State),
+            ctypes.sizeof(_lib.Trace), ctypes.sizeof(_lib.Cert), ctypes.sizeof(_lib.Report),
+            _lib.Problem.cost_norm.offset, _lib.Params.check_every.offset,
+            _lib.Report.row_fallbacks.offset]
+    assert got == want

@@ -1,0 +1,277 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (derived in DESIGN.md, "Tolerances"): duals theta, nu, thetabar,
+thetahat within 1e-6 norm-wise relative; column marginals within 1e-6 relative
+in l1; row log-normalisers within 2e-6 absolute; transport cost within 1e-5
+relative.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lamp as OL
+from oracle import stream as OS
+from paper_2511_11359_amd import workloads as W
+from tests.gpu_util import gpu_problem, oracle_problem, rel_inf, rel_l1, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2511_11359_amd as P  # noqa: E402
+
+DUAL_TOL = 1e-6
+COL_TOL = 1e-6
+LOGZ_ATOL = 2e-6
+COST_TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare_step(tr_gpu, tr_or, k, st_gpu, st_or, tag):
+    errs = dict(
+        logZA=np.max(np.abs(to_np(tr_gpu["log_za"]) - tr_or.logZA[k])),
+        logZB=np.max(np.abs(to_np(tr_gpu["log_zb"]) - tr_or.logZB[k])),
+        colA=rel_l1(to_np(tr_gpu["col_a"]), tr_or.colA[k]),
+        colB=rel_l1(to_np(tr_gpu["col_b"]), tr_or.colB[k]),
+        theta_bar=rel_inf(to_np(tr_gpu["theta_bar"]), tr_or.theta_bar[k]),
+        theta_hat=rel_inf(to_np(tr_gpu["theta_hat"]), tr_or.theta_hat[k]),
+        nu=rel_inf(to_np(st_gpu.nu), st_or.nu),
+        theta=rel_inf(to_np(st_gpu.theta), st_or.theta),
+    )
+    _say(tag, {k2: f"{v:.2e}" for k2, v in errs.items()})
+    assert errs["logZA"] <= LOGZ_ATOL and errs["logZB"] <= LOGZ_ATOL, errs
+    assert errs["colA"] <= COL_TOL and errs["colB"] <= COL_TOL, errs
+    for key in ["theta_bar", "theta_hat", "nu", "theta"]:
+        assert errs[key] <= DUAL_TOL, (key, errs)
+
+
+def _gpu_state(nu, theta, t, lam):
+    dev = "cuda"
+    return P.State(torch.tensor(nu, dtype=torch.float64, device=dev),
+                   torch.tensor(theta, dtype=torch.float64, device=dev), t, lam)
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 2), (300, 173, 3), (97, 1031, 1), (517, 64, 5),
+                                   (130, 260, 16), (70, 90, 20)])
+def test_first_steps_match_oracle(shape):
+    """Iterations 0..4 from the fresh state, several tiles and ragged tails, each dimension path."""
+    n, m, d = shape
+    wl = W.random_small(n, m, d, seed=100 + d, eta=1e-2)
+    _say("case", wl.name)
+    x, y, s, C = oracle_problem(wl)
+    prm = OL.Params(eta=wl.eta)
+    st_or, tr_or = OL.lamp_dense(C, wl.r, wl.c, prm, 5, 1.0)
+    prob = gpu_problem(wl, s)
+    params = P.make_params(eta=wl.eta)
+    st = P.State.fresh(m)
+    ost = OL.lamp_init(m)
+    for k in range(5):
+        res, tr = P.step(prob, params, st, trace=True)
+        ost = OL.LampState(k + 1, 0.0, tr_or.nu[k], tr_or.theta[k])
+        assert st.t == k + 1
+        assert res == pytest.approx(tr_or.res[k], rel=1e-6, abs=1e-12)
+        _compare_step(tr, tr_or, k, st, ost, f"{wl.name} t={k}")
+
+
+@pytest.mark.parametrize("t", [10, 100, 499])
+def test_step_from_oracle_state(t):
+    """256 x 256 uniform square, eta = 1e-2: one GPU step from the oracle's FP64 state at t."""
+    wl = W.uniform_square()
+    x, y, s, C = oracle_problem(wl)
+    prm = OL.Params(eta=wl.eta)
+    st_or, _ = OL.lamp_dense(C, wl.r, wl.c, prm, t, 1.0, trace=False)
+    st_next, tr_or = OL.lamp_dense(C, wl.r, wl.c, prm, 1, 1.0, state=st_or)
+    prob = gpu_problem(wl, s)
+    st = _gpu_state(st_or.nu, st_or.theta, st_or.t, st_or.lam)
+    res, tr = P.step(prob, P.make_params(eta=wl.eta), st, trace=True)
+    assert st.inv_eta == st_next.lam
+    _compare_step(tr, tr_or, 0, st, st_next, f"uniform t={t}")
+
+
+def test_trajectory_500_and_certificate():
+    """The small parity workload: 500 iterations with the graph-captured loop, then the
+    certificate.  Duals within 1e-6, cost within 1e-5 of the oracle."""
+    wl = W.uniform_square()
+    x, y, s, C = oracle_problem(wl)
+    prm = OL.Params(eta=wl.eta)
+    st_or, _ = OL.lamp_dense(C, wl.r, wl.c, prm, 500, 1.0, trace=False)
+    cert_or = OL.certificate(C, wl.r, wl.c, st_or, prm.resolved(1.0), 1.0)
+    prob = gpu_problem(wl, s)
+    params = P.make_params(eta=wl.eta, tol=0.0, max_iter=500, check_every=50)
+    st, rep, status = P.solve(prob, params)
+    assert status == 0 and st.t == 500 and rep["iters"] == 500
+    e_nu = rel_inf(to_np(st.nu), st_or.nu)
+    e_th = rel_inf(to_np(st.theta), st_or.theta)
+    cert = P.certificate(prob, params, st)
+    e_cost = abs(cert["cost"] - cert_or["cost"]) / abs(cert_or["cost"])
+    _say("trajectory 500", f"nu {e_nu:.2e} theta {e_th:.2e} cost {e_cost:.2e}",
+         "col_res", cert["col_res"], cert_or["col_res"], "row_res", cert["row_res"])
+    assert e_nu <= DUAL_TOL and e_th <= DUAL_TOL
+    assert e_cost <= COST_TOL
+    assert abs(cert["col_res"] - cert_or["col_res"]) <= 1e-6 * max(cert_or["col_res"], 1e-3)
+    assert cert["row_res"] <= 1e-6
+    for key in ["dual_theta", "dual_nu", "primal_penalized", "prop_bound"]:
+        assert cert[key] == pytest.approx(cert_or[key], rel=1e-5, abs=1e-9), key
+    assert cert["dual_theta"] <= cert["primal_penalized"]
+
+
+def test_solve_stops_at_tolerance_and_resume():
+    """Solve to a tolerance: the returned iterate meets it; resuming from a checkpoint reproduces
+    the uninterrupted run; two runs are bitwise identical."""
+    wl = W.random_small(400, 350, 3, seed=7, eta=1e-3)
+    x, y, s, C = oracle_problem(wl)
+    prob = gpu_problem(wl, s)
+    params = P.make_params(eta=wl.eta, tol=5e-3, max_iter=20000, check_every=32)
+    st, rep, status = P.solve(prob, params)
+    _say("solve", rep)
+    assert status == 0 and rep["converged"] == 1
+    # the certified iterate: recompute its residual on the oracle
+    ost = OL.LampState(st.t, st.inv_eta, to_np(st.nu), to_np(st.theta))
+    X = OL.plan(C, wl.r, ost, 1.0)
+    rr, cc, _ = OL.residuals(X, wl.r, wl.c)
+    assert cc <= 5e-3 * (1 + 1e-6)
+    assert cc == pytest.approx(rep["final_res"], rel=1e-5)
+    st2, rep2, _ = P.solve(prob, params)
+    assert st2.t == st.t and torch.equal(st2.nu, st.nu) and torch.equal(st2.theta, st.theta)
+    # checkpoint / resume: 60 + 60 iterations against 120
+    p60 = P.make_params(eta=wl.eta, max_iter=60, check_every=16)
+    a, _, _ = P.solve(prob, p60)
+    a, _, _ = P.solve(prob, p60, a)
+    b, _, _ = P.solve(prob, P.make_params(eta=wl.eta, max_iter=120, check_every=16))
+    assert a.t == b.t == 120 and a.inv_eta == b.inv_eta
+    assert rel_inf(to_np(a.nu), to_np(b.nu)) <= 1e-9
+    assert rel_inf(to_np(a.theta), to_np(b.theta)) <= 1e-9
+
+
+def test_cost_scale_matches_oracle():
+    for (n, m, d) in [(256, 256, 2), (1000, 777, 3), (123, 456, 16), (50, 60, 20)]:
+        wl = W.random_small(n, m, d, seed=n)
+        s, md = P.cost_scale(P.Problem(wl.x, wl.y, wl.r, wl.c))
+        ref = OL.max_sqdist(wl.x.astype(np.float64), wl.y.astype(np.float64))
+        assert md == pytest.approx(ref, rel=1e-13)
+
+
+def test_backward_matches_oracle_gradient():
+    """Envelope gradient at the GPU-independent oracle state (t = 60) against the oracle's."""
+    wl = W.random_small(200, 150, 3, seed=11, eta=1e-2)
+    x, y, s, C = oracle_problem(wl)
+    prm = OL.Params(eta=wl.eta)
+    st_or, _ = OL.lamp_dense(C, wl.r, wl.c, prm, 60, 1.0, trace=False)
+    g_or = OL.envelope_grad_x(x, y, wl.r, s, st_or.nu, st_or.lam, 1.0)
+    prob = gpu_problem(wl, s)
+    st = _gpu_state(st_or.nu, st_or.theta, st_or.t, st_or.lam)
+    g = to_np(P.backward(prob, P.make_params(eta=wl.eta), st, grad_out=1.0))
+    err = rel_inf(g, g_or)
+    _say("grad err", err)
+    assert err <= 1e-5
+
+
+def test_status_codes():
+    wl = W.random_small(20, 30, 2, seed=3)
+    bad_r = wl.r.copy()
+    bad_r[0] = -bad_r[0]
+    with pytest.raises(P.LampError) as e:
+        P.step(P.Problem(wl.x, wl.y, bad_r, wl.c), P.make_params(), P.State.fresh(30))
+    assert e.value.status == -2
+    with pytest.raises(P.LampError) as e:
+        P.step(P.Problem(wl.x, wl.y, wl.r * 1.01, wl.c), P.make_params(), P.State.fresh(30))
+    assert e.value.status == -2
+    with pytest.raises(P.LampError) as e:
+        P.step(P.Problem(wl.x, wl.y, wl.r, wl.c), P.make_params(eta=5.0), P.State.fresh(30))
+    assert e.value.status == -1
+    st = P.State.fresh(30)
+    st.theta[3] = 1.0   # atanh(1) = inf
+    st.t, st.inv_eta = 5, 2.5
+    with pytest.raises(P.LampError) as e:
+        P.step(P.Problem(wl.x, wl.y, wl.r, wl.c), P.make_params(), st)
+    assert e.value.status == -5
+
+
+def test_circulant_polygon_large():
+    """Regular 16384-gon, x = y, uniform marginals, eta = 0: col(X^t) = c, theta = nu = 0 up to
+    the FP32 rounding of the vertex coordinates, log Z_i the same for every row."""
+    n = 16384
+    wl = W.regular_polygon(n)
+    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=0.25, cost_norm=1.0)
+    params = P.make_params(eta=0.0, max_iter=40)
+    st, rep, status = P.solve(prob, params)
+    assert status == 0 and st.t == 40
+    th = to_np(st.theta)
+    assert np.max(np.abs(th)) <= 1e-4
+    res, tr = P.step(prob, params, st, trace=True)
+    lz = to_np(tr["log_za"])
+    ref = OS.row_log_normalisers(wl.x.astype(np.float64), wl.y.astype(np.float64), 0.25, 1.0,
+                                 np.zeros(n), 40 * 0.5, [0])[0]
+    _say("polygon", np.max(np.abs(th)), lz.min(), lz.max(), ref, res)
+    assert np.max(np.abs(lz - ref)) <= 1e-3
+    assert res <= 1e-4
+
+
+# ---------------------------------------------------------------- matrix-core forms
+
+def _rounded_cost(wl, s, dtype):
+    """The cost the matrix-core forms evaluate: points centred on mu = (x_0 + y_0)/2 in FP64,
+    rounded to the operand type, dot products exact, norms from the unrounded centred points."""
+    x = wl.x.astype(np.float64)
+    y = wl.y.astype(np.float64)
+    mu = 0.5 * (x[0] + y[0])
+    xc, yc = x - mu, y - mu
+    xr = torch.tensor(xc).to(dtype).to(torch.float64).numpy()
+    yr = torch.tensor(yc).to(dtype).to(torch.float64).numpy()
+    nx = np.sum(xc * xc, axis=1)
+    ny = np.sum(yc * yc, axis=1)
+    return s * (nx[:, None] + ny[None, :] - 2.0 * xr @ yr.T)
+
+
+MFMA_FORMS = [("fp32_mfma", torch.float32), ("bf16_mfma", torch.bfloat16),
+              ("fp16_mfma", torch.float16)]
+
+
+@pytest.mark.parametrize("form,dtype", MFMA_FORMS)
+@pytest.mark.parametrize("shape", [(256, 256, 2), (300, 173, 3), (160, 200, 64), (97, 130, 16)])
+def test_mfma_step_matches_oracle_on_rounded_cost(form, dtype, shape):
+    """One step of each matrix-core form from an oracle state (t = 20, eta = 1e-2) against the
+    oracle run on the cost those forms evaluate (operands rounded to the operand type).  The
+    remaining differences are FP32 accumulation and exponent assembly: tolerance 1e-4."""
+    n, m, d = shape
+    wl = W.random_small(n, m, d, seed=300 + d, eta=1e-2)
+    _say("case", form, wl.name)
+    x, y, s, C = oracle_problem(wl)
+    Cr = _rounded_cost(wl, s, dtype)
+    prm = OL.Params(eta=wl.eta)
+    st_or, _ = OL.lamp_dense(Cr, wl.r, wl.c, prm, 20, 1.0, trace=False)
+    st_next, tr_or = OL.lamp_dense(Cr, wl.r, wl.c, prm, 1, 1.0, state=st_or)
+    prob = gpu_problem(wl, s)
+    st = _gpu_state(st_or.nu, st_or.theta, st_or.t, st_or.lam)
+    res, tr = P.step(prob, P.make_params(eta=wl.eta, precision=form), st, trace=True)
+    errs = dict(
+        colA=rel_l1(to_np(tr["col_a"]), tr_or.colA[0]),
+        colB=rel_l1(to_np(tr["col_b"]), tr_or.colB[0]),
+        theta_bar=rel_inf(to_np(tr["theta_bar"]), tr_or.theta_bar[0]),
+        theta_hat=rel_inf(to_np(tr["theta_hat"]), tr_or.theta_hat[0]),
+        nu=rel_inf(to_np(st.nu), st_next.nu),
+        theta=rel_inf(to_np(st.theta), st_next.theta))
+    _say(form, wl.name, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1e-4, (k, errs)
+
+
+@pytest.mark.parametrize("form", ["fp32_mfma", "bf16_mfma"])
+def test_mfma_solve_runs_graph(form):
+    """The graph-captured loop with a matrix-core form: 200 iterations, residual decreasing."""
+    wl = W.random_small(700, 650, 3, seed=21, eta=1e-2)
+    x, y, s, C = oracle_problem(wl)
+    prob = gpu_problem(wl, s)
+    st, rep, status = P.solve(prob, P.make_params(eta=wl.eta, max_iter=200, precision=form,
+                                                  check_every=25))
+    _say(form, rep)
+    assert status == 0 and st.t == 200
+    assert rep["final_res"] < 0.05
