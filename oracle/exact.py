@@ -53,6 +53,22 @@ def lp_ot(C: np.ndarray, r: np.ndarray, c: np.ndarray):
     return float(res.fun), res.x.reshape(n, m)
 
 
+def lp_ot_duals(C: np.ndarray, r: np.ndarray, c: np.ndarray):
+    """Optimal LP duals (y_r, y_c) of the marginal constraints (HiGHS marginals):
+    max <r, y_r> + <c, y_c> s.t. y_r,i + y_c,j <= C_ij."""
+    n, m = C.shape
+    A_eq = np.zeros((n + m, n * m))
+    for i in range(n):
+        A_eq[i, i * m:(i + 1) * m] = 1.0
+    for j in range(m):
+        A_eq[n + j, j::m] = 1.0
+    res = linprog(C.ravel(), A_eq=A_eq, b_eq=np.concatenate([r, c]), bounds=(0, None),
+                  method="highs")
+    assert res.status == 0, res.message
+    y = res.eqlin.marginals
+    return float(res.fun), y[:n], y[n:]
+
+
 def sinkhorn_eot(C: np.ndarray, r: np.ndarray, c: np.ndarray, eta: float, iters: int = 200000,
                  tol: float = 1e-14) -> np.ndarray:
     """Log-domain Sinkhorn for min <C,X> - eta H(X) over Pi(r, c) (problem primal_eot).

@@ -53,7 +53,7 @@ int64_t choose_split(int64_t owned, int64_t len) {
 
 struct Layout {
     size_t ctrl, sched, xc, yc, ycf, xn2, yn2, gtab, H, rowvar, rpart, cpart, nu1, th1, respart,
-        scratch, small, xop, yop, kf, wAf, wBf, total;
+        scratch, small, xop, yop, kf, wAf, wBf, gtabf, total;
     int64_t split_r, P_r, split_c, P_c;
     // matrix-core forms
     int prec, KP, esize;
@@ -137,6 +137,7 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32) {
         L.kf = take(sizeof(float) * L.n_pad);
         L.wAf = take(sizeof(float) * L.n_pad);
         L.wBf = take(sizeof(float) * L.n_pad);
+        L.gtabf = take(sizeof(float2) * 2 * L.m_pad);
     }
     L.total = off;
     return L;
@@ -146,6 +147,8 @@ template <typename T>
 T* at(void* ws, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
+
+float2* gtabf_ptr(const Layout& L, void* ws) { return is_mfma(L.prec) ? at<float2>(ws, L.gtabf) : nullptr; }
 
 struct Resolved {
     double s, cnorm, K, tau1, tau2, alpha, beta, kappa, clipb;
@@ -221,6 +224,9 @@ lamp_status prep(const lamp_problem* p, void* ws, hipStream_t st, int prec = LAM
         if (prec == LAMP_FP32_MFMA) prep_ops<float>(p, L, ws, st);
         else if (prec == LAMP_BF16_MFMA) prep_ops<__bf16>(p, L, ws, st);
         else prep_ops<_Float16>(p, L, ws, st);
+        if (L.m_pad > p->m)
+            hipLaunchKernelGGL(pad_gtabf, grid1(L.m_pad - p->m), dim3(BLOCK), 0, st, p->m, L.m_pad,
+                               at<float2>(ws, L.gtabf));
         if (L.n_pad > p->n)
             hipLaunchKernelGGL(pad_rows, grid1(L.n_pad - p->n), dim3(BLOCK), 0, st, p->n, L.n_pad,
                                at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf));
@@ -252,7 +258,7 @@ void row_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
     const int64_t n_waves = L.n_pad / 32;
     dim3 g((unsigned)(cdiv(n_waves, 4) * L.P_rm));
     hipLaunchKernelGGL((row_sweep_mfma<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
-                       kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<double2>(ws, L.gtab), at<double>(ws, L.H),
+                       kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<float2>(ws, L.gtabf), L.m_pad, at<double>(ws, L.H),
                        at<double2>(ws, L.rpart), L.tps_r, (int)L.P_rm, L.m_pad / 32, n_waves);
 }
 
@@ -261,7 +267,7 @@ void col_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
     const int64_t m_waves = L.m_pad / 32;
     dim3 g((unsigned)(cdiv(m_waves, 4) * L.P_cm));
     hipLaunchKernelGGL((col_sweep_mfma<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
-                       kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<double2>(ws, L.gtab), at<float>(ws, L.kf),
+                       kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<float2>(ws, L.gtabf), L.m_pad, at<float>(ws, L.kf),
                        at<float>(ws, L.wAf), at<float>(ws, L.wBf), at<double2>(ws, L.cpart), L.tps_c,
                        (int)L.P_cm, L.n_pad / 32, m_waves);
 }
@@ -468,7 +474,7 @@ void launch_iteration(const lamp_problem* p, const Layout& L, Consts kc, void* w
     launch_col_sweep(L, kc, p->d, ws, st);
     hipLaunchKernelGGL(dual_update, grid1(kc.m), dim3(BLOCK), 0, st, ctrl, sch, kc, at<double2>(ws, L.cpart),
                        col_parts(L), p->c, at<double>(ws, L.yn2), ia.buf, at<double2>(ws, L.gtab),
-                       at<double>(ws, L.respart), ia.tc);
+                       gtabf_ptr(L, ws), L.m_pad, at<double>(ws, L.respart), ia.tc);
 }
 
 lamp_status upload_ctrl(void* ws, const Layout& L, int64_t t, int64_t t_end, int64_t t_base, double tol,
@@ -521,7 +527,7 @@ lamp_status state_normalisers(const lamp_problem* p, const lamp_params* q, const
     HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), &sc, sizeof(Sched), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));   // the uploads read host locals of this frame
     hipLaunchKernelGGL(col_table_init, grid1(p->m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl),
-                       at<Sched>(ws, L.sched), kc, at<double>(ws, L.yn2), s->nu, s->theta, at<double2>(ws, L.gtab));
+                       at<Sched>(ws, L.sched), kc, at<double>(ws, L.yn2), s->nu, s->theta, at<double2>(ws, L.gtab), (float2*)nullptr, L.m_pad);
     launch_offsets(L, kc, p->d, ws, st);
     launch_row_sweep(L, kc, p->d, ws, st);
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
@@ -604,7 +610,7 @@ lamp_status lamp_step(const lamp_problem* prob, const lamp_params* params, lamp_
         ia.log_zb = trace->log_zb;
     }
     hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
-                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab));
+                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab), gtabf_ptr(L, ws), L.m_pad);
     launch_offsets(L, kc, prob->d, ws, st);
     launch_iteration(prob, L, kc, ws, ia, st);
     HIPCHK(hipGetLastError());
@@ -665,7 +671,7 @@ lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp
     if ((e = upload_ctrl(ws, L, t0, t_end, t_base, params->tol, st, &hc)) != LAMP_OK) return e;
 
     hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
-                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab));
+                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab), gtabf_ptr(L, ws), L.m_pad);
     launch_offsets(L, kc, prob->d, ws, st);
     HIPCHK(hipGetLastError());
 
@@ -832,7 +838,7 @@ lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params
     Ctrl hc;
     if ((e = upload_ctrl(ws, L, state->t, state->t + 1, state->t, 0.0, st, &hc)) != LAMP_OK) return e;
     hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
-                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab));
+                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab), gtabf_ptr(L, ws), L.m_pad);
     launch_offsets(L, kc, prob->d, ws, st);
     launch_row_sweep(L, kc, prob->d, ws, st);
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched), kc,

@@ -122,7 +122,8 @@ __global__ void prep_points(const float* __restrict__ pts, int64_t cnt, int d,
 // ---------------------------------------------------------------------------
 __global__ void col_table_init(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                const double* __restrict__ yn2, const double* __restrict__ nu,
-                               const double* __restrict__ theta, double2* __restrict__ gtab2) {
+                               const double* __restrict__ theta, double2* __restrict__ gtab2,
+                               float2* __restrict__ gtabf, int64_t m_pad) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= kc.m) return;
     const int64_t t = ctrl->t;
@@ -133,6 +134,7 @@ __global__ void col_table_init(const Ctrl* ctrl, const Sched* sched, Consts kc,
     g.x = -sc.lamA * LOG2E * (base + kc.K * nu[j]);
     g.y = -sc.lamB * LOG2E * (base + kc.K * nb);
     gtab2[(t & 1) * kc.m + j] = g;
+    if (gtabf) gtabf[(t & 1) * m_pad + j] = make_float2((float)g.x, (float)g.y);
 }
 
 // a_j = -g^B_j / cfac^B for the exact offset initialisation.
@@ -518,6 +520,7 @@ __global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sc
                                                      const double* __restrict__ c,
                                                      const double* __restrict__ yn2, DualBufs buf,
                                                      double2* __restrict__ gtab2,
+                                                     float2* __restrict__ gtabf, int64_t m_pad,
                                                      double* __restrict__ respart, TraceCols tr) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
@@ -554,6 +557,7 @@ __global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sc
         gn.x = -sc.lamB * LOG2E * (base + kc.K * nun);
         gn.y = -sc.lamC * LOG2E * (base + kc.K * nbn);
         gtab2[((t + 1) & 1) * kc.m + j] = gn;
+        if (gtabf) gtabf[((t + 1) & 1) * m_pad + j] = make_float2((float)gn.x, (float)gn.y);
         res = fabs(colA - cj);
         bad = !(isfinite(nun) && isfinite(thn) && isfinite(colA) && isfinite(colB)) || fabs(th) >= 1.0;
         if (tr.col_a) tr.col_a[j] = colA;

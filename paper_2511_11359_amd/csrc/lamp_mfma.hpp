@@ -83,7 +83,7 @@ __global__ void pad_rows(int64_t n, int64_t n_pad, float* __restrict__ kf, float
 template <typename T, int KP>
 __global__ __launch_bounds__(BLOCK) void row_sweep_mfma(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                         const T* __restrict__ xop, const T* __restrict__ yop,
-                                                        const double2* __restrict__ gtab2,
+                                                        const float2* __restrict__ gtabf, int64_t m_pad,
                                                         const double* __restrict__ H,
                                                         double2* __restrict__ part, int64_t tiles_per_split,
                                                         int P, int64_t m_tiles, int64_t n_waves) {
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma(const Ctrl* ctrl, const 
     const Sched sc = sched[t - ctrl->t_base];
     const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E);
     const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
-    const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
+    const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
     const int lane = threadIdx.x & 63;
     const int hf = lane >> 5, c32 = lane & 31;
     const int64_t b = blockIdx.x;
@@ -122,17 +122,27 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma(const Ctrl* ctrl, const 
 
     const int64_t jt0 = (int64_t)p * tiles_per_split;
     const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
-    for (int64_t jt = jt0; jt < jt1; ++jt) {
-        const int64_t j = jt * 32 + c32;
+    // software pipeline: operands of tile jt+1 load while tile jt computes
+    vec bn[NS];
+    float2 gn = make_float2(PAD_NEG, PAD_NEG);
+    if (jt0 < jt1) {
+        const int64_t j = jt0 * 32 + c32;
         const vec* bp = reinterpret_cast<const vec*>(yop + j * KP + hf * (KP / 2));
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bn[s] = bp[s];
+        gn = g[j];
+    }
+    for (int64_t jt = jt0; jt < jt1; ++jt) {
         vec bv[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
-        float gA = PAD_NEG, gB = PAD_NEG;
-        if (j < kc.m) {
-            const double2 gg = g[j];
-            gA = (float)gg.x;
-            gB = (float)gg.y;
+        for (int s = 0; s < NS; ++s) bv[s] = bn[s];
+        const float gA = gn.x, gB = gn.y;
+        if (jt + 1 < jt1) {
+            const int64_t j = (jt + 1) * 32 + c32;
+            const vec* bp = reinterpret_cast<const vec*>(yop + j * KP + hf * (KP / 2));
+#pragma unroll
+            for (int s = 0; s < NS; ++s) bn[s] = bp[s];
+            gn = g[j];
         }
         floatx16 d = Op::mma(a[0], bv[0], hv);
 #pragma unroll
@@ -159,13 +169,42 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma(const Ctrl* ctrl, const 
     }
 }
 
+// Operands and row data of one 32-row tile of the column sweep.
+template <typename T, int KP>
+struct ColTile {
+    typename MfmaOp<T>::vec a[KP / MfmaOp<T>::KSTEP];
+    floatx16 kv;
+    float wa[16], wb[16];
+};
+
+template <typename T, int KP>
+__device__ __forceinline__ void load_col_tile(ColTile<T, KP>& ct, const T* __restrict__ xop,
+                                              const float* __restrict__ kf, const float* __restrict__ wAf,
+                                              const float* __restrict__ wBf, int64_t it, int hf, int c32) {
+    using vec = typename MfmaOp<T>::vec;
+    constexpr int NS = KP / MfmaOp<T>::KSTEP;
+    const vec* ap = reinterpret_cast<const vec*>(xop + (it * 32 + c32) * KP + hf * (KP / 2));
+#pragma unroll
+    for (int s = 0; s < NS; ++s) ct.a[s] = ap[s];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t rbase = it * 32 + 8 * q + 4 * hf;   // rows of registers 4q .. 4q+3
+        const float4 k4 = *reinterpret_cast<const float4*>(kf + rbase);
+        const float4 a4 = *reinterpret_cast<const float4*>(wAf + rbase);
+        const float4 b4 = *reinterpret_cast<const float4*>(wBf + rbase);
+        ct.kv[4 * q + 0] = k4.x; ct.kv[4 * q + 1] = k4.y; ct.kv[4 * q + 2] = k4.z; ct.kv[4 * q + 3] = k4.w;
+        ct.wa[4 * q + 0] = a4.x; ct.wa[4 * q + 1] = a4.y; ct.wa[4 * q + 2] = a4.z; ct.wa[4 * q + 3] = a4.w;
+        ct.wb[4 * q + 0] = b4.x; ct.wb[4 * q + 1] = b4.y; ct.wb[4 * q + 2] = b4.z; ct.wb[4 * q + 3] = b4.w;
+    }
+}
+
 // Column sweep: wave owns columns [32 cw, 32 cw + 32), streams row tiles of split p.
 // The per-row offsets k_i enter as the MFMA accumulator input; the row weights
 // w^A_i, w^B_i multiply the exponentials.
 template <typename T, int KP>
 __global__ __launch_bounds__(BLOCK) void col_sweep_mfma(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                         const T* __restrict__ xop, const T* __restrict__ yop,
-                                                        const double2* __restrict__ gtab2,
+                                                        const float2* __restrict__ gtabf, int64_t m_pad,
                                                         const float* __restrict__ kf,
                                                         const float* __restrict__ wAf,
                                                         const float* __restrict__ wBf,
@@ -193,40 +232,23 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma(const Ctrl* ctrl, const 
 #pragma unroll
         for (int s = 0; s < NS; ++s) bv[s] = bp[s];
     }
-    float gA = PAD_NEG, gB = PAD_NEG;
-    if (j < kc.m) {
-        const double2 gg = gtab2[(t & 1) * kc.m + j];
-        gA = (float)gg.x;
-        gB = (float)gg.y;
-    }
+    const float2 gg = gtabf[(t & 1) * m_pad + j];
+    const float gA = gg.x, gB = gg.y;
     float accA[4] = {0.f, 0.f, 0.f, 0.f}, accB[4] = {0.f, 0.f, 0.f, 0.f};
     const int64_t it0 = (int64_t)p * tiles_per_split;
     const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
+    ColTile<T, KP> nx;
+    if (it0 < it1) load_col_tile<T, KP>(nx, xop, kf, wAf, wBf, it0, hf, c32);
     for (int64_t it = it0; it < it1; ++it) {
-        const int64_t i = it * 32 + c32;
-        const vec* ap = reinterpret_cast<const vec*>(xop + i * KP + hf * (KP / 2));
-        vec a[NS];
+        const ColTile<T, KP> ct = nx;
+        if (it + 1 < it1) load_col_tile<T, KP>(nx, xop, kf, wAf, wBf, it + 1, hf, c32);
+        floatx16 d = Op::mma(ct.a[0], bv[0], ct.kv);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) a[s] = ap[s];
-        floatx16 kv;
-        float wa[16], wb[16];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t rbase = it * 32 + 8 * q + 4 * hf;   // rows of registers 4q .. 4q+3
-            const float4 k4 = *reinterpret_cast<const float4*>(kf + rbase);
-            const float4 a4 = *reinterpret_cast<const float4*>(wAf + rbase);
-            const float4 b4 = *reinterpret_cast<const float4*>(wBf + rbase);
-            kv[4 * q + 0] = k4.x; kv[4 * q + 1] = k4.y; kv[4 * q + 2] = k4.z; kv[4 * q + 3] = k4.w;
-            wa[4 * q + 0] = a4.x; wa[4 * q + 1] = a4.y; wa[4 * q + 2] = a4.z; wa[4 * q + 3] = a4.w;
-            wb[4 * q + 0] = b4.x; wb[4 * q + 1] = b4.y; wb[4 * q + 2] = b4.z; wb[4 * q + 3] = b4.w;
-        }
-        floatx16 d = Op::mma(a[0], bv[0], kv);
-#pragma unroll
-        for (int s = 1; s < NS; ++s) d = Op::mma(a[s], bv[s], d);
+        for (int s = 1; s < NS; ++s) d = Op::mma(ct.a[s], bv[s], d);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            accA[r & 3] = fmaf(wa[r], __builtin_amdgcn_exp2f(fmaf(d[r], cA, gA)), accA[r & 3]);
-            accB[r & 3] = fmaf(wb[r], __builtin_amdgcn_exp2f(fmaf(d[r], cB, gB)), accB[r & 3]);
+            accA[r & 3] = fmaf(ct.wa[r], __builtin_amdgcn_exp2f(fmaf(d[r], cA, gA)), accA[r & 3]);
+            accB[r & 3] = fmaf(ct.wb[r], __builtin_amdgcn_exp2f(fmaf(d[r], cB, gB)), accB[r & 3]);
         }
     }
     float sA = (accA[0] + accA[1]) + (accA[2] + accA[3]);
@@ -234,6 +256,14 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma(const Ctrl* ctrl, const 
     sA += __shfl_xor(sA, 32, 64);
     sB += __shfl_xor(sB, 32, 64);
     if (hf == 0 && j < kc.m) cpart[(int64_t)p * kc.m + j] = make_double2(sA, sB);
+}
+
+// Padded entries of the FP32 column tables (both parities): zero weight in every sum.
+__global__ void pad_gtabf(int64_t m, int64_t m_pad, float2* __restrict__ gtabf) {
+    int64_t j = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m_pad) return;
+    gtabf[j] = make_float2(PAD_NEG, PAD_NEG);
+    gtabf[m_pad + j] = make_float2(PAD_NEG, PAD_NEG);
 }
 
 }  // namespace lampk

@@ -1,0 +1,136 @@
+"""The oracle's pins are sensitive: each test plants one plausible mistake in an oracle
+function (on the CPU, through monkeypatch) and checks that a pin in test_oracle_pins
+fails.  Nothing here runs on a GPU."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lamp as L
+from tests import test_oracle_pins as pins
+
+
+def _fails(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_pin_tclip_radius():
+    """beta = log 3 clips at exactly 1/2 (Algorithm 4)."""
+    th = np.array([-0.9, -0.5, 0.2, 0.7])
+    np.testing.assert_allclose(L.tclip(th, math.log(3.0)), [-0.5, -0.5, 0.2, 0.5], rtol=1e-15)
+
+
+def test_mutation_dual_map_sign(monkeypatch):
+    orig = L.dual_mirror_map
+    monkeypatch.setattr(L, "dual_mirror_map",
+                        lambda th0, colp, c, ca, tau, cn: orig(th0, 2 * c - colp, c, ca, tau, cn))
+    _fails(pins.test_dual_mirror_map_is_the_argmax)
+
+
+def test_mutation_dual_map_without_alpha(monkeypatch):
+    orig = L.dual_mirror_map
+    monkeypatch.setattr(L, "dual_mirror_map",
+                        lambda th0, colp, c, ca, tau, cn: orig(th0, colp, c, c, tau, cn))
+    _fails(pins.test_dual_mirror_map_is_the_argmax)
+
+
+def test_mutation_tclip_radius(monkeypatch):
+    monkeypatch.setattr(L, "tclip", lambda th, beta: np.clip(th, -math.tanh(beta), math.tanh(beta)))
+    _fails(test_pin_tclip_radius)
+
+
+def test_mutation_schedule_drops_decay(monkeypatch):
+    def bad(T, tau1, eta):
+        lam = np.zeros(T + 1)
+        for t in range(T):
+            lam[t + 1] = tau1 + lam[t]
+        return lam
+    monkeypatch.setattr(L, "inv_eta_schedule", bad)
+    _fails(pins.test_inverse_temperature_closed_form, 1e-2)
+
+
+def test_mutation_averaging_weight_uses_old_temperature(monkeypatch):
+    orig_step = L.lamp_step
+
+    def bad_step(C, r, c, state, prm, cnorm, trace=None):
+        # w = tau1 / lam_t instead of tau1 / lam_{t+1}
+        m = c.shape[0]
+        calpha = c + prm.alpha / m
+        lam_next = prm.tau1 + state.lam * (1.0 - prm.tau1 * prm.eta)
+        w = prm.tau1 / max(state.lam, prm.tau1)
+        nu, theta = state.nu, state.theta
+        nubar = nu + w * (theta - nu)
+        colA = L.col_r(L.dual_to_primal(C, nu, state.lam, cnorm), r)
+        tb = L.dual_mirror_map(theta, colA, c, calpha, prm.tau2, cnorm)
+        nu_next = nu + w * (tb - nu)
+        colB = L.col_r(L.dual_to_primal(C, nubar, lam_next, cnorm), r)
+        th = L.tclip(L.dual_mirror_map(theta, colB, c, calpha, prm.tau2, cnorm), prm.beta)
+        if trace is not None:
+            trace.nubar.append(nubar)
+            trace.nu.append(nu_next)
+            trace.theta.append(th)
+        return L.LampState(state.t + 1, lam_next, nu_next, th)
+
+    monkeypatch.setattr(L, "lamp_step", bad_step)
+    assert orig_step is not bad_step
+    _fails(pins.test_lamp_equals_pdmp, 1e-2)
+
+
+def test_mutation_midpoint_uses_thetabar(monkeypatch):
+    """nubar^{t+1} built from thetabar^{t+1} instead of theta^t."""
+    def bad_step(C, r, c, state, prm, cnorm, trace=None):
+        m = c.shape[0]
+        calpha = c + prm.alpha / m
+        lam_next = prm.tau1 + state.lam * (1.0 - prm.tau1 * prm.eta)
+        w = prm.tau1 / lam_next
+        nu, theta = state.nu, state.theta
+        colA = L.col_r(L.dual_to_primal(C, nu, state.lam, cnorm), r)
+        tb = L.dual_mirror_map(theta, colA, c, calpha, prm.tau2, cnorm)
+        nubar = nu + w * (tb - nu)
+        nu_next = nu + w * (tb - nu)
+        colB = L.col_r(L.dual_to_primal(C, nubar, lam_next, cnorm), r)
+        th = L.tclip(L.dual_mirror_map(theta, colB, c, calpha, prm.tau2, cnorm), prm.beta)
+        if trace is not None:
+            trace.nubar.append(nubar)
+            trace.nu.append(nu_next)
+            trace.theta.append(th)
+        return L.LampState(state.t + 1, lam_next, nu_next, th)
+
+    monkeypatch.setattr(L, "lamp_step", bad_step)
+    _fails(pins.test_lamp_equals_pdmp, 0.0)
+
+
+def test_mutation_column_normalised_map(monkeypatch):
+    """Normalising p^eta(theta) over columns instead of rows (a transposed operand)."""
+    from scipy.special import logsumexp
+
+    def bad(C, theta, lam, cnorm):
+        a = -lam * (C + 2.0 * cnorm * theta[None, :])
+        return np.exp(a - logsumexp(a, axis=0, keepdims=True))
+    monkeypatch.setattr(L, "dual_to_primal", bad)
+    _fails(pins.test_row_feasibility)
+
+
+def test_mutation_round_skips_column_scaling(monkeypatch):
+    def bad(X, r, c):
+        xr = np.minimum(r / L.row(X), 1.0)
+        X2 = xr[:, None] * X
+        dr = r - L.row(X2)
+        dc = c - L.col(X2)
+        return X2 + np.outer(dr, dc) / np.abs(dr).sum()
+    monkeypatch.setattr(L, "round_plan", bad)
+    _fails(pins.test_round_feasible_and_l1_bound)
+
+
+def test_mutation_dual_drops_linear_term(monkeypatch):
+    def bad(C, r, c, theta, cnorm):
+        return float(r @ np.min(C + 2.0 * cnorm * theta[None, :], axis=1))
+    monkeypatch.setattr(L, "dual_D", bad)
+    _fails(pins.test_dual_function_attains_lp_optimum)
+
+
+def test_mutation_gradient_factor(monkeypatch):
+    orig = L.envelope_grad_x
+    monkeypatch.setattr(L, "envelope_grad_x", lambda *a: 0.5 * orig(*a))
+    _fails(pins.test_envelope_gradient_matches_finite_differences)

@@ -246,6 +246,18 @@ def test_certificate_ordering_and_last_iterate_bound(eta, beta):
             assert cert["cost"] - opt <= ib + 1e-12
 
 
+def test_dual_function_attains_lp_optimum():
+    """Strong duality for the saddle dual (def:dual_spp): with the LP's optimal column dual y_c,
+    D(theta) at K theta = -y_c equals OPT (proof of Lemma b_choice), and D is invariant to
+    adding a constant to theta (r and c both sum to 1)."""
+    C, r, c, *_ = _problem(6, 5, 2, seed=17)
+    cnorm = float(C.max())
+    opt, yr, yc = exact.lp_ot_duals(C, r, c)
+    theta = -yc / (2.0 * cnorm)
+    assert L.dual_D(C, r, c, theta, cnorm) == pytest.approx(opt, rel=1e-9, abs=1e-12)
+    assert L.dual_D(C, r, c, theta + 0.1, cnorm) == pytest.approx(opt, rel=1e-9, abs=1e-12)
+
+
 def test_lamp_converges_to_assignment_optimum():
     """eta = 0 on uniform n = m = 5 (brute-force OPT): the certificate gap closes."""
     g = np.random.default_rng(9)
