@@ -1,13 +1,19 @@
 """Benchmark of the LAMP iteration on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision P]
+                    [--time-to-tol] [--no-cpu]
 
 A step is one LAMP iteration t -> t+1 (Algorithm 2: both marginal sweeps of
 Section 4.1, the dual mirror steps, averaging, clipping and the residual) over
 the whole problem.  One iteration evaluates 4 n m coupling entries (two row
 log-sum-exp sweeps and two column sums): the pair-eval count.  The timed
 region is one lamp_solve call that runs exactly K iterations from a warmed-up
-state, inputs resident in HBM.  Prints one JSON line.
+state, inputs resident in HBM.
+
+The default workload is n = m = 2^16 points in d = 64 (8-component Gaussian
+mixture), eta = 1e-3, in the BF16 matrix-core form; the other forms of the same
+workload (FP32 matrix-core tiles, and the reference-accuracy form with FP64 dot
+products) are measured beside it.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -20,15 +26,30 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published figures used for the roofline: 256 CUs at 2.4 GHz, 4 SIMD16 per CU.
-# v_exp_f32 issues at half the full VALU rate on CDNA4: 32 lanes per clock per CU.
+# MI355X published figures: 256 CUs at 2.4 GHz, 4 SIMD16 per CU.  v_exp_f32 issues at half
+# the full VALU rate on CDNA4 (32 lanes per clock per CU).  Dense matrix peaks: FP64 78.6,
+# FP32 157.3, BF16/FP16 2500 TFLOP/s.
 CUS, CLOCK = 256, 2.4e9
 EXP_PEAK = CUS * 32 * CLOCK          # 1.966e13 exp/s
+MFMA_PEAK = {"fp32": 78.6e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2500e12, "fp16_mfma": 2500e12}
+FORM_DTYPE = {"fp32": "f64/f32", "fp32_mfma": "f32", "bf16_mfma": "bf16/f32", "fp16_mfma": "f16/f32"}
+FORM_DESC = {
+    "fp32": "x.y and exponent arguments in FP64, exponentials and sums FP32, duals FP64",
+    "fp32_mfma": "x.y tiles on FP32 matrix cores, exponent assembled in FP32, duals FP64",
+    "bf16_mfma": "x.y tiles from BF16 points on matrix cores (FP32 accumulate), FP32 exponent "
+                 "and sums, FP64 duals",
+    "fp16_mfma": "x.y tiles from FP16 points on matrix cores (FP32 accumulate), FP32 exponent "
+                 "and sums, FP64 duals",
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def cpu_baseline(wl, s, seconds_target: float = 15.0):
-    """The FP64 oracle (row-block evaluation of one marginal sweep pair) timed on a bounded
-    sample of rows of the same workload; pair-evals counted like the GPU's."""
+    """The FP64 oracle (row-block evaluation of one marginal pass) timed on a bounded sample of
+    rows of the same workload; pair-evals counted like the GPU's."""
     import numpy as np
 
     from oracle import stream as OS
@@ -50,18 +71,88 @@ def cpu_baseline(wl, s, seconds_target: float = 15.0):
                       f"{wl.m} columns, d={wl.d}, FP64 NumPy, single thread, {dt:.1f} s"}
 
 
+def measure_form(P, prob, wl, form, steps, warmup, reps):
+    """Throughput of `steps` iterations of one precision form, and its sweep kernel times."""
+    import torch
+    dev = prob.device
+    st = P.State.fresh(wl.m, dev)
+    if warmup:
+        st, _, _ = P.solve(prob, P.make_params(eta=wl.eta, max_iter=warmup,
+                                               check_every=max(1, warmup // 2), precision=form), st)
+    params = P.make_params(eta=wl.eta, tol=0.0, max_iter=steps, check_every=max(1, steps // 2),
+                           precision=form)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rep, _ = P.solve(prob, params, st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert rep["iters"] == steps, rep
+    row_ms, col_ms = P.sweep_times(prob, params, st, reps=reps)
+    log(f"{form}: {steps} iterations in {dt:.3f} s ({dt * 1e3 / steps:.3f} ms/iteration), "
+        f"row sweep {row_ms:.3f} ms, column sweep {col_ms:.3f} ms, residual {rep['final_res']:.3e}")
+    return {"pair_evals_per_s": 4.0 * wl.n * wl.m * steps / dt, "ms_per_step": dt * 1e3 / steps,
+            "row_sweep_ms": row_ms, "col_sweep_ms": col_ms, "residual_after": rep["final_res"],
+            "t_after": st.t}
+
+
+def roofline(wl, form, m):
+    """Roofline of the slower sweep kernel of a form: the exponential (VALU) bound for the
+    vector-ALU and half-precision forms, the matrix-core bound where the dot products dominate."""
+    dom_name, dom_ms = ("row_sweep", m["row_sweep_ms"])
+    if m["col_sweep_ms"] > dom_ms:
+        dom_name, dom_ms = ("col_sweep", m["col_sweep_ms"])
+    mfma_bound = (form == "fp32" and wl.d > 16) or form == "fp32_mfma"
+    if mfma_bound:
+        flops = 2.0 * wl.n * wl.m * wl.d          # one d-dimensional dot product per pair
+        ach = flops / (dom_ms * 1e-3)
+        return {"bound": "mfma", "kernel": dom_name, "achieved": ach / 1e12,
+                "peak": MFMA_PEAK[form] / 1e12, "unit": "TFLOP/s", "frac": ach / MFMA_PEAK[form],
+                "traffic": None, "per_launch": f"2*n*m*d = {flops:.3e} flop",
+                "row_sweep_ms": m["row_sweep_ms"], "col_sweep_ms": m["col_sweep_ms"]}
+    exps = 2.0 * wl.n * wl.m                      # both couplings, one exponential per pair each
+    ach = exps / (dom_ms * 1e-3)
+    return {"bound": "alu", "kernel": dom_name, "achieved": ach / 1e12, "peak": EXP_PEAK / 1e12,
+            "unit": "Texp/s", "frac": ach / EXP_PEAK, "traffic": None,
+            "per_launch": f"2*n*m = {exps:.3e} exponentials",
+            "row_sweep_ms": m["row_sweep_ms"], "col_sweep_ms": m["col_sweep_ms"]}
+
+
+def time_to_tol(P, prob, wl, form, tol, max_iter):
+    import torch
+    params = P.make_params(eta=wl.eta, tol=tol, max_iter=max_iter, check_every=64, precision=form)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rep, status = P.solve(prob, params)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"{form}: time to ||col - c||_1 <= {tol}: {rep['iters']} iterations, {dt:.2f} s, "
+        f"converged={rep['converged']}, final residual {rep['final_res']:.3e}")
+    return {"tol": tol, "iters": rep["iters"], "seconds": dt, "converged": bool(rep["converged"]),
+            "final_res": rep["final_res"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", default="gmm64d_65536")
+    ap.add_argument("--precision", default="bf16_mfma",
+                    choices=["fp32", "fp32_mfma", "bf16_mfma", "fp16_mfma"])
+    ap.add_argument("--compare", default="fp32_mfma,fp32",
+                    help="other forms measured beside the primary one (comma list, '' for none)")
+    ap.add_argument("--compare-steps", type=int, default=10)
+    ap.add_argument("--time-to-tol", action="store_true")
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--reps", type=int, default=5, help="launches per kernel for the roofline timing")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "see DESIGN.md for how the path would shard", file=sys.stderr)
+              "DESIGN.md describes how the path would shard", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -71,59 +162,46 @@ def main():
 
     wl = W.WORKLOADS[args.workload]()
     dev = torch.device("cuda:0")
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prob = P.Problem(wl.x, wl.y, wl.r, wl.c, device=dev)   # cost scale computed on the device
     s, _ = P.cost_scale(prob)
-    print(f"[bench] {wl.name}: n={wl.n} m={wl.m} d={wl.d} eta={wl.eta} s={s:.6e}", file=sys.stderr,
-          flush=True)
+    prob.cost_scale, prob.cost_norm = s, 1.0
+    log(f"{wl.name}: n={wl.n} m={wl.m} d={wl.d} eta={wl.eta} s={s:.9e}")
 
-    # warmup (also compiles nothing: the library is prebuilt)
-    st = P.State.fresh(wl.m, dev)
-    st, rep, _ = P.solve(prob, P.make_params(eta=wl.eta, max_iter=args.warmup, check_every=16), st)
-    torch.cuda.synchronize()
-
-    params = P.make_params(eta=wl.eta, tol=0.0, max_iter=args.steps, check_every=16)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, rep, _ = P.solve(prob, params, st)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert rep["iters"] == args.steps, rep
-    pair_evals = 4.0 * wl.n * wl.m * args.steps
-    value = pair_evals / dt
-    print(f"[bench] {args.steps} iterations in {dt:.3f} s, residual {rep['final_res']:.3e}",
-          file=sys.stderr, flush=True)
-
-    # dominant kernels, timed with HIP events on the stream they run on
-    row_ms, col_ms = P.sweep_times(prob, params, st, reps=args.reps)
-    dom_name, dom_ms = ("row_sweep", row_ms) if row_ms >= col_ms else ("col_sweep", col_ms)
-    exps_per_launch = 2.0 * wl.n * wl.m
-    achieved = exps_per_launch / (dom_ms * 1e-3)
-    roof = {"bound": "alu", "kernel": dom_name, "achieved": achieved / 1e12, "peak": EXP_PEAK / 1e12,
-            "unit": "Texp/s", "frac": achieved / EXP_PEAK, "traffic": None,
-            "row_sweep_ms": row_ms, "col_sweep_ms": col_ms,
-            "per_launch": f"2*n*m = {exps_per_launch:.3e} exponentials"}
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(wl, s)
+    main_m = measure_form(P, prob, wl, args.precision, args.steps, args.warmup, args.reps)
+    others = {}
+    for form in [f for f in args.compare.split(",") if f and f != args.precision]:
+        others[form] = measure_form(P, prob, wl, form, args.compare_steps, 2, max(2, args.reps // 2))
+        others[form]["roofline"] = roofline(wl, form, others[form])
+    ttt = None
+    if args.time_to_tol:
+        ttt = {args.precision: time_to_tol(P, prob, wl, args.precision, args.tol, args.max_iter)}
+    cpu = None if args.no_cpu else cpu_baseline(wl, s)
 
     out = {
         "metric": "pair-evals/s",
-        "value": value,
+        "value": main_m["pair_evals_per_s"],
         "unit": "pair-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
+        "ms_per_step": main_m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": FORM_DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "n": wl.n, "m": wl.m, "d": wl.d, "eta": wl.eta,
-                   "precision": "fp32 exponentials and sums, fp64 arguments and duals"},
-        "roofline": roof,
+                   "form": args.precision, "precision": FORM_DESC[args.precision]},
+        "roofline": roofline(wl, args.precision, main_m),
         "cpu_baseline": cpu,
+        "forms": others,
+        "time_to_tol": ttt,
     }
     print(json.dumps(out), flush=True)
 

@@ -179,6 +179,22 @@ lamp_status lamp_sweep_times(const lamp_problem *prob, const lamp_params *params
                              const lamp_state *state, void *ws, size_t ws_bytes, void *stream,
                              int32_t reps, double *row_ms, double *col_ms);
 
+/* Batching form: `count` independent problems of any n, m, d advance together.  Each
+ * phase of an iteration (row sweep, row finish, column sweep, dual update) is one
+ * launch for the whole batch: a persistent grid loops over a work list of
+ * (problem, tile) items.  The iteration loop is a captured HIP graph.  A problem whose
+ * residual meets tol stops there (its items exit at once) while the others continue.
+ * The launch shape (sweep items per phase, grid size) is chosen by timing candidate
+ * shapes on the batch (autotuner, cached per batch shape for the process).
+ *   probs[count], states[count], outs[count] (host arrays of the structs above);
+ *   all problems run LAMP_FP32 with the same params; their costs must share one
+ *   ||C||_inf (e.g. all normalised: cost_scale <= 0) and their states one t and lam_t.
+ * The workspace (lamp_batch_workspace_bytes) holds every problem's scratch. */
+size_t lamp_batch_workspace_bytes(const lamp_problem *probs, int32_t count, const lamp_params *params);
+lamp_status lamp_solve_batched(const lamp_problem *probs, int32_t count, const lamp_params *params,
+                               lamp_state *states, void *ws, size_t ws_bytes, void *stream,
+                               lamp_report *outs);
+
 /* Message for the last non-OK status returned to the calling thread. */
 const char *lamp_last_error(void);
 

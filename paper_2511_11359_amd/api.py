@@ -189,6 +189,28 @@ def sweep_times(prob: Problem, params: L.Params, state: State, reps: int = 10) -
     return a.value, b.value
 
 
+def solve_batched(probs: list, params: L.Params, states: list | None = None):
+    """Batching form: all problems advance together, one launch per phase for the whole batch.
+    Returns (states, reports, status)."""
+    lib = L.load()
+    count = len(probs)
+    dev = probs[0].device
+    if states is None:
+        states = [State.fresh(p.m, dev) for p in probs]
+    parr = (L.Problem * count)(*[p.struct() for p in probs])
+    sarr = (L.State * count)(*[s.struct() for s in states])
+    rarr = (L.Report * count)()
+    need = int(lib.lamp_batch_workspace_bytes(parr, count, ctypes.byref(params)))
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    base = (ws.data_ptr() + 255) & ~255
+    st = _check(lib.lamp_solve_batched(parr, count, ctypes.byref(params), sarr, base, need,
+                                       _stream_handle(dev), rarr))
+    for s, sc in zip(states, sarr):
+        s.update(sc)
+    reports = [{k: getattr(r, k) for k, _ in L.Report._fields_} for r in rarr]
+    return states, reports, st
+
+
 class LampOT(torch.autograd.Function):
     """Transport cost <C, X^T> of the LAMP iterate as a differentiable function of the source
     points x (envelope gradient at fixed duals and fixed cost scale)."""

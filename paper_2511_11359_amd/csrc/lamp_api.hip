@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
+#include <map>
+#include <mutex>
+#include <string>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -14,6 +18,7 @@
 #include "../../include/lamp.h"
 #include "lamp_kernels.hpp"
 #include "lamp_mfma.hpp"
+#include "lamp_batch.hpp"
 
 using namespace lampk;
 
@@ -44,20 +49,25 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Split of the streamed extent `len` for `owned` lanes: returns elements per split.
-int64_t choose_split(int64_t owned, int64_t len) {
+int64_t choose_split(int64_t owned, int64_t len, int64_t target = TARGET_BLOCKS) {
     const int64_t blocks = cdiv(owned, BLOCK);
-    int64_t P = cdiv(TARGET_BLOCKS, blocks);
+    int64_t P = cdiv(target, blocks);
     P = std::max<int64_t>(1, std::min<int64_t>(P, cdiv(len, 128)));
     return cdiv(len, P);
 }
 
 struct Layout {
     size_t ctrl, sched, xc, yc, ycf, xn2, yn2, gtab, H, rowvar, rpart, cpart, nu1, th1, respart,
-        scratch, small, xop, yop, kf, wAf, wBf, gtabf, total;
+        scratch, small, xop, yop, kf, wAf, wBf, gtabf, rowq, total;
     int64_t split_r, P_r, split_c, P_c;
     // matrix-core forms
     int prec, KP, esize;
     int64_t n_pad, m_pad, tps_r, P_rm, tps_c, P_cm;
+    // FP64 matrix-core sweeps of the reference-accuracy form (d > 16)
+    bool use64;
+    int KP64;
+    int64_t n_pad64, m_pad64, tps_r64, P_r64, tps_c64, P_c64;
+    size_t xop64, yop64;
 };
 
 bool is_mfma(int prec) { return prec == LAMP_FP32_MFMA || prec == LAMP_BF16_MFMA || prec == LAMP_FP16_MFMA; }
@@ -74,10 +84,18 @@ int mfma_kp(int prec, int d) {
     return 0;
 }
 
+// FP64 matrix-core operand width for the reference-accuracy form (0: vector-ALU sweeps).
+int fp64_kp(int d) {
+    if (d <= 16) return 0;
+    for (int kp : {32, 64, 128})
+        if (d <= kp) return kp;
+    return 0;
+}
+
 // Splits of the streamed tile range for the matrix-core sweeps: a multiple of 8 so that
 // split p runs on XCD p mod 8, enough blocks to fill the chip.
-void mfma_split(int64_t owned_pad, int64_t streamed_tiles, int64_t* tps, int64_t* P) {
-    const int64_t blocks = owned_pad / 128;
+void mfma_split(int64_t owned_pad, int64_t streamed_tiles, int64_t* tps, int64_t* P, int64_t rows_per_block = 128) {
+    const int64_t blocks = owned_pad / rows_per_block;
     int64_t want = cdiv(TARGET_BLOCKS * 2, blocks);
     want = std::max<int64_t>(8, cdiv(want, 8) * 8);
     want = std::min<int64_t>(want, streamed_tiles);
@@ -85,11 +103,11 @@ void mfma_split(int64_t owned_pad, int64_t streamed_tiles, int64_t* tps, int64_t
     *P = cdiv(streamed_tiles, *tps);
 }
 
-Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32) {
+Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target = TARGET_BLOCKS) {
     Layout L{};
-    L.split_r = choose_split(n, m);
+    L.split_r = choose_split(n, m, target);
     L.P_r = cdiv(m, L.split_r);
-    L.split_c = choose_split(m, n);
+    L.split_c = choose_split(m, n, target);
     L.P_c = cdiv(n, L.split_c);
     L.prec = prec;
     L.n_pad = cdiv(n, 128) * 128;
@@ -99,6 +117,14 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32) {
         L.esize = prec == LAMP_FP32_MFMA ? 4 : 2;
         mfma_split(L.n_pad, L.m_pad / 32, &L.tps_r, &L.P_rm);
         mfma_split(L.m_pad, L.n_pad / 32, &L.tps_c, &L.P_cm);
+    }
+    L.KP64 = fp64_kp(d);
+    L.use64 = L.KP64 > 0;
+    L.n_pad64 = cdiv(n, 64) * 64;
+    L.m_pad64 = cdiv(m, 64) * 64;
+    if (L.use64) {
+        mfma_split(L.n_pad64, L.m_pad64 / 16, &L.tps_r64, &L.P_r64, 64);
+        mfma_split(L.m_pad64, L.n_pad64 / 16, &L.tps_c64, &L.P_c64, 64);
     }
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -113,6 +139,10 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32) {
     if (is_mfma(prec)) {
         rpart_d = std::max<size_t>(rpart_d, (size_t)L.P_rm * n * 2);
         cpart_d2 = std::max<size_t>(cpart_d2, (size_t)L.P_cm * m);
+    }
+    if (L.use64) {
+        rpart_d = std::max<size_t>(rpart_d, (size_t)L.P_r64 * n * 2);
+        cpart_d2 = std::max<size_t>(cpart_d2, (size_t)L.P_c64 * m);
     }
     L.ctrl = take(sizeof(Ctrl));
     L.sched = take(sizeof(Sched) * (TAB + 2));
@@ -138,6 +168,11 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32) {
         L.wAf = take(sizeof(float) * L.n_pad);
         L.wBf = take(sizeof(float) * L.n_pad);
         L.gtabf = take(sizeof(float2) * 2 * L.m_pad);
+        L.rowq = take(sizeof(float4) * L.n_pad);
+    }
+    if (L.use64) {
+        L.xop64 = take(sizeof(double) * L.n_pad64 * L.KP64);
+        L.yop64 = take(sizeof(double) * L.m_pad64 * L.KP64);
     }
     L.total = off;
     return L;
@@ -149,6 +184,10 @@ T* at(void* ws, size_t off) {
 }
 
 float2* gtabf_ptr(const Layout& L, void* ws) { return is_mfma(L.prec) ? at<float2>(ws, L.gtabf) : nullptr; }
+
+RowVarF32 rowvar_f32(const Layout& L, void* ws) {
+    return RowVarF32{at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf), at<float4>(ws, L.rowq), 1};
+}
 
 struct Resolved {
     double s, cnorm, K, tau1, tau2, alpha, beta, kappa, clipb;
@@ -214,12 +253,18 @@ void prep_ops(const lamp_problem* p, const Layout& L, void* ws, hipStream_t st) 
                        p->d, L.KP, L.m_pad, at<T>(ws, L.yop));
 }
 
-lamp_status prep(const lamp_problem* p, void* ws, hipStream_t st, int prec = LAMP_FP32) {
-    const Layout L = layout(p->n, p->m, p->d, prec);
+lamp_status prep_L(const lamp_problem* p, const Layout& L, void* ws, hipStream_t st) {
+    const int prec = L.prec;
     hipLaunchKernelGGL(prep_points, grid1(p->n), dim3(BLOCK), 0, st, p->x, p->n, p->d, p->x, p->y,
                        at<double>(ws, L.xc), at<double>(ws, L.xn2), (float*)nullptr);
     hipLaunchKernelGGL(prep_points, grid1(p->m), dim3(BLOCK), 0, st, p->y, p->m, p->d, p->x, p->y,
                        at<double>(ws, L.yc), at<double>(ws, L.yn2), at<float>(ws, L.ycf));
+    if (L.use64) {
+        hipLaunchKernelGGL(prep_operands64, grid1(L.n_pad64 * L.KP64), dim3(BLOCK), 0, st, at<double>(ws, L.xc),
+                           p->n, p->d, L.KP64, L.n_pad64, at<double>(ws, L.xop64));
+        hipLaunchKernelGGL(prep_operands64, grid1(L.m_pad64 * L.KP64), dim3(BLOCK), 0, st, at<double>(ws, L.yc),
+                           p->m, p->d, L.KP64, L.m_pad64, at<double>(ws, L.yop64));
+    }
     if (is_mfma(prec)) {
         if (prec == LAMP_FP32_MFMA) prep_ops<float>(p, L, ws, st);
         else if (prec == LAMP_BF16_MFMA) prep_ops<__bf16>(p, L, ws, st);
@@ -227,19 +272,45 @@ lamp_status prep(const lamp_problem* p, void* ws, hipStream_t st, int prec = LAM
         if (L.m_pad > p->m)
             hipLaunchKernelGGL(pad_gtabf, grid1(L.m_pad - p->m), dim3(BLOCK), 0, st, p->m, L.m_pad,
                                at<float2>(ws, L.gtabf));
-        if (L.n_pad > p->n)
+        if (L.n_pad > p->n) {
             hipLaunchKernelGGL(pad_rows, grid1(L.n_pad - p->n), dim3(BLOCK), 0, st, p->n, L.n_pad,
                                at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf));
+            hipLaunchKernelGGL(pad_rowq, grid1(L.n_pad - p->n), dim3(BLOCK), 0, st, p->n, L.n_pad,
+                               at<float4>(ws, L.rowq));
+        }
     }
     HIPCHK(hipGetLastError());
     return LAMP_OK;
 }
 
+lamp_status prep(const lamp_problem* p, void* ws, hipStream_t st, int prec = LAMP_FP32) {
+    return prep_L(p, layout(p->n, p->m, p->d, prec), ws, st);
+}
+
 // ------------------------------------------------------------------ dispatch by d
 #define LAMP_FOR_D(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(16)
 
+template <int KP>
+void row_extreme64(const Layout& L, Consts kc, void* ws, const double* a, double sgn, hipStream_t st) {
+    const int64_t n_waves = L.n_pad64 / 16;
+    dim3 g((unsigned)(cdiv(n_waves, 4) * L.P_r64));
+    hipLaunchKernelGGL((row_extreme_mfma64<KP>), g, dim3(BLOCK), 0, st, kc, at<double>(ws, L.xop64),
+                       at<double>(ws, L.yop64), a, sgn, at<double>(ws, L.rpart), L.tps_r64, (int)L.P_r64,
+                       L.m_pad64 / 16, n_waves);
+}
+
+// Number of partial minima written by launch_row_extreme.
+int extreme_parts(const Layout& L) { return (int)(L.use64 ? L.P_r64 : L.P_r); }
+
 void launch_row_extreme(const Layout& L, Consts kc, int d, void* ws, const double* a, double sgn,
                         hipStream_t st) {
+    if (L.use64) {
+        switch (L.KP64) {
+            case 32: row_extreme64<32>(L, kc, ws, a, sgn, st); return;
+            case 64: row_extreme64<64>(L, kc, ws, a, sgn, st); return;
+            default: row_extreme64<128>(L, kc, ws, a, sgn, st); return;
+        }
+    }
     dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
     double* part = at<double>(ws, L.rpart);
     switch (d) {
@@ -257,7 +328,7 @@ template <typename T, int KP>
 void row_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
     const int64_t n_waves = L.n_pad / 32;
     dim3 g((unsigned)(cdiv(n_waves, 4) * L.P_rm));
-    hipLaunchKernelGGL((row_sweep_mfma<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+    hipLaunchKernelGGL((row_sweep_mfma_lds<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
                        kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<float2>(ws, L.gtabf), L.m_pad, at<double>(ws, L.H),
                        at<double2>(ws, L.rpart), L.tps_r, (int)L.P_rm, L.m_pad / 32, n_waves);
 }
@@ -266,6 +337,13 @@ template <typename T, int KP>
 void col_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
     const int64_t m_waves = L.m_pad / 32;
     dim3 g((unsigned)(cdiv(m_waves, 4) * L.P_cm));
+    if (!std::is_same<T, float>::value) {
+        hipLaunchKernelGGL((col_sweep_mfma_t_lds<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl),
+                           at<Sched>(ws, L.sched), kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<float2>(ws, L.gtabf),
+                           L.m_pad, at<float4>(ws, L.rowq), at<double2>(ws, L.cpart), L.tps_c, (int)L.P_cm,
+                           L.n_pad / 32, m_waves);
+        return;
+    }
     hipLaunchKernelGGL((col_sweep_mfma<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
                        kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<float2>(ws, L.gtabf), L.m_pad, at<float>(ws, L.kf),
                        at<float>(ws, L.wAf), at<float>(ws, L.wBf), at<double2>(ws, L.cpart), L.tps_c,
@@ -299,13 +377,50 @@ void sweep_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
 #undef MF
 }
 
-// Number of row partials written by the row sweep of this layout.
-int row_parts(const Layout& L) { return (int)(is_mfma(L.prec) ? L.P_rm : L.P_r); }
-int col_parts(const Layout& L) { return (int)(is_mfma(L.prec) ? L.P_cm : L.P_c); }
+template <int KP>
+void row_mfma64(const Layout& L, Consts kc, void* ws, hipStream_t st) {
+    const int64_t n_waves = L.n_pad64 / 16;
+    dim3 g((unsigned)(cdiv(n_waves, 4) * L.P_r64));
+    hipLaunchKernelGGL((row_sweep_mfma64_lds<KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, at<double>(ws, L.xop64), at<double>(ws, L.yop64), at<double2>(ws, L.gtab),
+                       at<double>(ws, L.H), at<double2>(ws, L.rpart), L.tps_r64, (int)L.P_r64, L.m_pad64 / 16,
+                       n_waves);
+}
+
+template <int KP>
+void col_mfma64(const Layout& L, Consts kc, void* ws, hipStream_t st) {
+    const int64_t m_waves = L.m_pad64 / 16;
+    dim3 g((unsigned)(cdiv(m_waves, 4) * L.P_c64));
+    hipLaunchKernelGGL((col_sweep_mfma64_lds<KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, at<double>(ws, L.xop64), at<double>(ws, L.yop64), at<double2>(ws, L.gtab),
+                       at<RowVar>(ws, L.rowvar), at<double2>(ws, L.cpart), L.tps_c64, (int)L.P_c64,
+                       L.n_pad64 / 16, m_waves);
+}
+
+template <bool ROW>
+void sweep_mfma64(const Layout& L, Consts kc, void* ws, hipStream_t st) {
+    switch (L.KP64) {
+        case 32: if (ROW) row_mfma64<32>(L, kc, ws, st); else col_mfma64<32>(L, kc, ws, st); return;
+        case 64: if (ROW) row_mfma64<64>(L, kc, ws, st); else col_mfma64<64>(L, kc, ws, st); return;
+        default: if (ROW) row_mfma64<128>(L, kc, ws, st); else col_mfma64<128>(L, kc, ws, st); return;
+    }
+}
+
+// Number of row / column partials written by the sweeps of this layout.
+int row_parts(const Layout& L) {
+    return (int)(is_mfma(L.prec) ? L.P_rm : (L.use64 ? L.P_r64 : L.P_r));
+}
+int col_parts(const Layout& L) {
+    return (int)(is_mfma(L.prec) ? L.P_cm : (L.use64 ? L.P_c64 : L.P_c));
+}
 
 void launch_row_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
     if (is_mfma(L.prec)) {
         sweep_mfma<true>(L, kc, ws, st);
+        return;
+    }
+    if (L.use64) {
+        sweep_mfma64<true>(L, kc, ws, st);
         return;
     }
     dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
@@ -326,6 +441,10 @@ void launch_row_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t s
 void launch_col_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
     if (is_mfma(L.prec)) {
         sweep_mfma<false>(L, kc, ws, st);
+        return;
+    }
+    if (L.use64) {
+        sweep_mfma64<false>(L, kc, ws, st);
         return;
     }
     dim3 g((unsigned)cdiv(kc.m, BLOCK), (unsigned)L.P_c);
@@ -364,8 +483,7 @@ __global__ void fill_scaled(int64_t cnt, double f, const double* __restrict__ in
     if (i < cnt) out[i] = f * in[i];
 }
 
-lamp_status max_sqdist(const lamp_problem* p, void* ws, hipStream_t st, double* out_host, int prec) {
-    const Layout L = layout(p->n, p->m, p->d, prec);
+lamp_status max_sqdist_L(const lamp_problem* p, const Layout& L, void* ws, hipStream_t st, double* out_host) {
     Consts kc{};
     kc.n = p->n;
     kc.m = p->m;
@@ -374,7 +492,7 @@ lamp_status max_sqdist(const lamp_problem* p, void* ws, hipStream_t st, double* 
     hipLaunchKernelGGL(fill_scaled, grid1(p->m), dim3(BLOCK), 0, st, p->m, -0.5, at<double>(ws, L.yn2), a);
     launch_row_extreme(L, kc, p->d, ws, a, +1.0, st);
     hipLaunchKernelGGL(row_extreme_merge, grid1(p->n), dim3(BLOCK), 0, st, kc, at<double>(ws, L.rpart),
-                       (int)L.P_r, at<double>(ws, L.xn2), 1, rowmax);
+                       extreme_parts(L), at<double>(ws, L.xn2), 1, rowmax);
     hipLaunchKernelGGL(reduce_max, dim3(1), dim3(1024), 0, st, rowmax, p->n, at<double>(ws, L.small));
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out_host, at<double>(ws, L.small), sizeof(double), hipMemcpyDeviceToHost, st));
@@ -382,11 +500,16 @@ lamp_status max_sqdist(const lamp_problem* p, void* ws, hipStream_t st, double* 
     return LAMP_OK;
 }
 
-lamp_status resolve(const lamp_problem* p, const lamp_params* q, void* ws, hipStream_t st, Resolved* R) {
+lamp_status max_sqdist(const lamp_problem* p, void* ws, hipStream_t st, double* out_host, int prec) {
+    return max_sqdist_L(p, layout(p->n, p->m, p->d, prec), ws, st, out_host);
+}
+
+lamp_status resolve_L(const lamp_problem* p, const lamp_params* q, const Layout& L, void* ws, hipStream_t st,
+                      Resolved* R) {
     double s = p->cost_scale, cn = p->cost_norm;
     if (!(s > 0.0) || !(cn > 0.0)) {
         double md = 0.0;
-        lamp_status e = max_sqdist(p, ws, st, &md, q->precision);
+        lamp_status e = max_sqdist_L(p, L, ws, st, &md);
         if (e != LAMP_OK) return e;
         if (!(md > 0.0)) return fail(LAMP_EDOMAIN, "all pairwise distances are zero");
         if (!(s > 0.0)) {
@@ -407,6 +530,10 @@ lamp_status resolve(const lamp_problem* p, const lamp_params* q, void* ws, hipSt
     R->clipb = std::tanh(R->beta / 2.0);
     if (R->tau1 * q->eta > 1.0) return fail(LAMP_EINVAL, "tau1 * eta = %g > 1", R->tau1 * q->eta);
     return LAMP_OK;
+}
+
+lamp_status resolve(const lamp_problem* p, const lamp_params* q, void* ws, hipStream_t st, Resolved* R) {
+    return resolve_L(p, q, layout(p->n, p->m, p->d, q->precision), ws, st, R);
 }
 
 Consts make_consts(const lamp_problem* p, const Resolved& R) {
@@ -444,13 +571,14 @@ double fill_sched(std::vector<Sched>& tab, int cnt, double lam0, double tau1, do
 }
 
 // Exact offsets for the first row sweep of a call: h_i = min_j(-g^B_j/cfac^B - x~.y~).
-void launch_offsets(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
+void launch_offsets(const Layout& L, Consts kc, int d, void* ws, hipStream_t st, const Ctrl* ctrl = nullptr,
+                    const Sched* sched = nullptr) {
     double* a = at<double>(ws, L.scratch);
-    hipLaunchKernelGGL(offset_coeffs, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl),
-                       at<Sched>(ws, L.sched), kc, at<double2>(ws, L.gtab), a);
+    hipLaunchKernelGGL(offset_coeffs, grid1(kc.m), dim3(BLOCK), 0, st, ctrl ? ctrl : at<Ctrl>(ws, L.ctrl),
+                       sched ? sched : at<Sched>(ws, L.sched), kc, at<double2>(ws, L.gtab), a);
     launch_row_extreme(L, kc, d, ws, a, -1.0, st);
     hipLaunchKernelGGL(row_extreme_merge, grid1(kc.n), dim3(BLOCK), 0, st, kc, at<double>(ws, L.rpart),
-                       (int)L.P_r, (const double*)nullptr, 0, at<double>(ws, L.H));
+                       extreme_parts(L), (const double*)nullptr, 0, at<double>(ws, L.H));
 }
 
 struct IterArgs {
@@ -466,7 +594,7 @@ void launch_iteration(const lamp_problem* p, const Layout& L, Consts kc, void* w
     const Sched* sch = at<Sched>(ws, L.sched);
     launch_row_sweep(L, kc, p->d, ws, st);
     RowVarF32 rf{nullptr, nullptr, nullptr, 0};
-    if (is_mfma(L.prec)) rf = RowVarF32{at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf), 1};
+    if (is_mfma(L.prec)) rf = rowvar_f32(L, ws);
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, ctrl, sch, kc, p->d, at<double>(ws, L.xc),
                        at<double>(ws, L.yc), at<double2>(ws, L.gtab), p->r, at<double>(ws, L.xn2),
                        at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H), at<RowVar>(ws, L.rowvar),
@@ -532,9 +660,9 @@ lamp_status state_normalisers(const lamp_problem* p, const lamp_params* q, const
     launch_row_sweep(L, kc, p->d, ws, st);
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
                        kc, p->d, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), p->r,
-                       at<double>(ws, L.xn2), at<double2>(ws, L.rpart), (int)L.P_r, at<double>(ws, L.H),
+                       at<double>(ws, L.xn2), at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H),
                        at<RowVar>(ws, L.rowvar), (double*)nullptr, (double*)nullptr,
-                       RowVarF32{nullptr, nullptr, nullptr, 0});
+                       RowVarF32{nullptr, nullptr, nullptr, nullptr, 0});
     HIPCHK(hipGetLastError());
     *cA_out = 2.0 * R.s * s->inv_eta * LOG2E;
     return LAMP_OK;
@@ -554,6 +682,258 @@ __global__ void col_residual(Consts kc, const double2* __restrict__ cpart, int P
     out[j] = fabs(col - c[j]);
 }
 
+
+// ------------------------------------------------------------------ batching form
+struct BatchCand {
+    int64_t target_total;   // sweep blocks per phase over the whole batch
+    int grid;               // persistent grid size of the phase kernels
+};
+const BatchCand kBatchCands[] = {{1024, 1024}, {2048, 1024}, {2048, 2048}, {4096, 2048}, {4096, 4096},
+                                 {8192, 4096}};
+constexpr int kNumBatchCands = (int)(sizeof(kBatchCands) / sizeof(kBatchCands[0]));
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;   // batch signature -> candidate index
+
+__global__ void gather_ctrl(const ProbDesc* __restrict__ pd, int count, Ctrl* __restrict__ out) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < count) out[p] = *pd[p].ctrl;
+}
+
+__global__ void set_epoch(const ProbDesc* __restrict__ pd, int count, int64_t t_base, int64_t t_end) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < count) {
+        pd[p].ctrl->t_base = t_base;
+        pd[p].ctrl->t_end = t_end;
+    }
+}
+
+// Rewind every control block to iteration t (used by the autotuner's repeated timing).
+__global__ void rewind_ctrl(const ProbDesc* __restrict__ pd, int count, int64_t t, int64_t t_end) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < count) {
+        Ctrl* c = pd[p].ctrl;
+        c->t = t;
+        c->t_base = t;
+        c->t_end = t_end;
+        c->done = 0;
+        c->err = 0;
+        c->counter = 0u;
+    }
+}
+
+struct BatchPlan {
+    std::vector<Layout> L;
+    std::vector<size_t> sub;      // per-problem sub-workspace offsets
+    size_t descs, items[4], ctrlv, sched, total;
+    int n_items[4];
+};
+
+BatchPlan batch_plan(const lamp_problem* probs, int count, int cand) {
+    BatchPlan B;
+    double wsum = 0.0;
+    for (int p = 0; p < count; ++p) wsum += (double)probs[p].n * (double)probs[p].m;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    for (int k = 0; k < 4; ++k) B.n_items[k] = 0;
+    B.L.resize(count);
+    for (int p = 0; p < count; ++p) {
+        const double share = (double)probs[p].n * (double)probs[p].m / wsum;
+        const int64_t target = std::max<int64_t>(1, (int64_t)std::llround(kBatchCands[cand].target_total * share));
+        B.L[p] = layout(probs[p].n, probs[p].m, probs[p].d, LAMP_FP32, target);
+        const int64_t rb = cdiv(probs[p].n, BLOCK), cb = cdiv(probs[p].m, BLOCK);
+        B.n_items[0] += (int)(rb * B.L[p].P_r);
+        B.n_items[1] += (int)rb;
+        B.n_items[2] += (int)(cb * B.L[p].P_c);
+        B.n_items[3] += (int)cb;
+    }
+    B.descs = take(sizeof(ProbDesc) * count);
+    for (int k = 0; k < 4; ++k) B.items[k] = take(sizeof(Item) * B.n_items[k]);
+    B.ctrlv = take(sizeof(Ctrl) * count);
+    B.sched = take(sizeof(Sched) * (TAB + 2));
+    B.sub.resize(count);
+    for (int p = 0; p < count; ++p) B.sub[p] = take(B.L[p].total);
+    B.total = off;
+    return B;
+}
+
+std::string batch_signature(const lamp_problem* probs, int count) {
+    std::string sig = std::to_string(count);
+    for (int p = 0; p < count; ++p)
+        sig += ":" + std::to_string(probs[p].n) + "x" + std::to_string(probs[p].m) + "x" + std::to_string(probs[p].d);
+    return sig;
+}
+
+struct BatchRun {
+    BatchPlan B;
+    std::vector<ProbDesc> desc;
+    std::vector<Resolved> R;
+    std::vector<double*> nu1, th1;
+    int grid;
+    double tau1;
+};
+
+void* sub_ws(void* ws, const BatchPlan& B, int p) { return static_cast<char*>(ws) + B.sub[p]; }
+
+// Everything up to the first iteration: per-problem preparation and cost scale, the
+// shared schedule, control blocks, column tables, exact offsets, descriptors and work lists.
+lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params* q, const lamp_state* states,
+                        void* ws, hipStream_t st, int cand, int64_t t_stop, BatchRun* run) {
+    run->B = batch_plan(probs, count, cand);
+    const BatchPlan& B = run->B;
+    run->grid = kBatchCands[cand].grid;
+    run->desc.resize(count);
+    run->R.resize(count);
+    run->nu1.resize(count);
+    run->th1.resize(count);
+    lamp_status e;
+    for (int p = 0; p < count; ++p) {
+        void* w = sub_ws(ws, B, p);
+        if ((e = prep_L(&probs[p], B.L[p], w, st)) != LAMP_OK) return e;
+        if ((e = resolve_L(&probs[p], q, B.L[p], w, st, &run->R[p])) != LAMP_OK) return e;
+        if (run->R[p].tau1 != run->R[0].tau1)
+            return fail(LAMP_EINVAL, "batched problems need a common ||C||_inf (problem %d differs)", p);
+    }
+    run->tau1 = run->R[0].tau1;
+    const int64_t t0 = states[0].t;
+    std::vector<Sched> tab;
+    fill_sched(tab, TAB, states[0].inv_eta, run->tau1, q->eta);
+    HIPCHK(hipMemcpyAsync(at<Sched>(ws, B.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice, st));
+    std::vector<Ctrl> hc(count);
+    std::vector<Item> items[4];
+    for (int p = 0; p < count; ++p) {
+        const Layout& L = B.L[p];
+        void* w = sub_ws(ws, B, p);
+        Ctrl& c = hc[p];
+        c = Ctrl{};
+        c.t = t0;
+        c.t_end = std::min(t_stop, t0 + TAB);
+        c.t_base = t0;
+        c.t_done = -1;
+        c.tol = q->tol;
+        c.res_last = -1.0;
+        const Consts kc = make_consts(&probs[p], run->R[p]);
+        ProbDesc& D = run->desc[p];
+        D.ctrl = at<Ctrl>(ws, B.ctrlv) + p;
+        D.kc = kc;
+        D.d = probs[p].d;
+        D.P_r = (int)L.P_r;
+        D.P_c = (int)L.P_c;
+        D.n_dual_blocks = (int)cdiv(probs[p].m, BLOCK);
+        D.split_r = L.split_r;
+        D.split_c = L.split_c;
+        D.xc = at<double>(w, L.xc);
+        D.yc = at<double>(w, L.yc);
+        D.xn2 = at<double>(w, L.xn2);
+        D.yn2 = at<double>(w, L.yn2);
+        D.r = probs[p].r;
+        D.c = probs[p].c;
+        D.gtab = at<double2>(w, L.gtab);
+        D.H = at<double>(w, L.H);
+        D.rowvar = at<RowVar>(w, L.rowvar);
+        D.rpart = at<double2>(w, L.rpart);
+        D.cpart = at<double2>(w, L.cpart);
+        run->nu1[p] = at<double>(w, L.nu1);
+        run->th1[p] = at<double>(w, L.th1);
+        D.buf.nu[t0 & 1] = states[p].nu;
+        D.buf.theta[t0 & 1] = states[p].theta;
+        D.buf.nu[(t0 + 1) & 1] = run->nu1[p];
+        D.buf.theta[(t0 + 1) & 1] = run->th1[p];
+        D.respart = at<double>(w, L.respart);
+        const int64_t rb = cdiv(probs[p].n, BLOCK), cb = cdiv(probs[p].m, BLOCK);
+        for (int64_t y = 0; y < L.P_r; ++y)
+            for (int64_t x = 0; x < rb; ++x) items[0].push_back(Item{p, (int)x, (int)y, 0});
+        for (int64_t x = 0; x < rb; ++x) items[1].push_back(Item{p, (int)x, 0, 0});
+        for (int64_t y = 0; y < L.P_c; ++y)
+            for (int64_t x = 0; x < cb; ++x) items[2].push_back(Item{p, (int)x, (int)y, 0});
+        for (int64_t x = 0; x < cb; ++x) items[3].push_back(Item{p, (int)x, 0, 0});
+    }
+    HIPCHK(hipMemcpyAsync(at<Ctrl>(ws, B.ctrlv), hc.data(), sizeof(Ctrl) * count, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<ProbDesc>(ws, B.descs), run->desc.data(), sizeof(ProbDesc) * count,
+                          hipMemcpyHostToDevice, st));
+    for (int k = 0; k < 4; ++k)
+        HIPCHK(hipMemcpyAsync(at<Item>(ws, B.items[k]), items[k].data(), sizeof(Item) * items[k].size(),
+                              hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));   // the uploads read host vectors of this frame
+    for (int p = 0; p < count; ++p) {
+        const Layout& L = B.L[p];
+        void* w = sub_ws(ws, B, p);
+        const ProbDesc& D = run->desc[p];
+        // the per-problem set-up kernels read the batch control block and schedule
+        hipLaunchKernelGGL(col_table_init, grid1(D.kc.m), dim3(BLOCK), 0, st, D.ctrl, at<Sched>(ws, B.sched), D.kc,
+                           D.yn2, states[p].nu, states[p].theta, D.gtab, (float2*)nullptr, (int64_t)0);
+        launch_offsets(L, D.kc, probs[p].d, w, st, D.ctrl, at<Sched>(ws, B.sched));
+    }
+    HIPCHK(hipGetLastError());
+    return LAMP_OK;
+}
+
+void batch_iteration(const BatchRun& run, void* ws, hipStream_t st) {
+    const BatchPlan& B = run.B;
+    const ProbDesc* pd = at<ProbDesc>(ws, B.descs);
+    const Sched* sch = at<Sched>(ws, B.sched);
+    auto g = [&](int n) { return dim3((unsigned)std::max(1, std::min(run.grid, n))); };
+    hipLaunchKernelGGL(batch_row_sweep, g(B.n_items[0]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[0]),
+                       B.n_items[0], sch);
+    hipLaunchKernelGGL(batch_row_finish, g(B.n_items[1]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[1]),
+                       B.n_items[1], sch);
+    hipLaunchKernelGGL(batch_col_sweep, g(B.n_items[2]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[2]),
+                       B.n_items[2], sch);
+    hipLaunchKernelGGL(batch_dual_update, g(B.n_items[3]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[3]),
+                       B.n_items[3], sch);
+}
+
+// Autotuner: every candidate launch shape runs a few iterations from the callers' start
+// state (writes go to workspace buffers only) and the fastest is cached per batch shape.
+lamp_status batch_tune(const lamp_problem* probs, int count, const lamp_params* q, const lamp_state* states,
+                       void* ws, hipStream_t st, int* best) {
+    const std::string sig = batch_signature(probs, count);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(sig);
+        if (it != g_tune_cache.end()) {
+            *best = it->second;
+            return LAMP_OK;
+        }
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best_c = 0;
+    for (int c = 0; c < kNumBatchCands; ++c) {
+        BatchRun run;
+        lamp_status e = batch_setup(probs, count, q, states, ws, st, c, states[0].t + 1, &run);
+        if (e != LAMP_OK) return e;
+        // the control blocks stop every problem after one iteration: time 3 repetitions of it
+        batch_iteration(run, ws, st);   // warm-up (the real iteration)
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r) {
+            // rerun the same iteration: reset t on the device to the start iteration
+            hipLaunchKernelGGL(rewind_ctrl, dim3(cdiv(count, 64)), dim3(64), 0, st, at<ProbDesc>(ws, run.B.descs),
+                               count, states[0].t, states[0].t + 1);
+            batch_iteration(run, ws, st);
+        }
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[sig] = best_c;
+    *best = best_c;
+    return LAMP_OK;
+}
 }  // namespace
 
 // ====================================================================== C ABI
@@ -769,7 +1149,7 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     double* prods = sc + 2 * nm;     // 2m
     double* vals = at<double>(ws, L.rpart);  // 4n
     double* small = at<double>(ws, L.small);
-    hipLaunchKernelGGL(col_residual, grid1(kc.m), dim3(BLOCK), 0, st, kc, at<double2>(ws, L.cpart), (int)L.P_c,
+    hipLaunchKernelGGL(col_residual, grid1(kc.m), dim3(BLOCK), 0, st, kc, at<double2>(ws, L.cpart), col_parts(LV),
                        prob->c, colres);
     hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
                        at<double2>(ws, L.gtab), gA);
@@ -845,8 +1225,7 @@ lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params
                        prob->d, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), prob->r,
                        at<double>(ws, L.xn2), at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H),
                        at<RowVar>(ws, L.rowvar), (double*)nullptr, (double*)nullptr,
-                       is_mfma(L.prec) ? RowVarF32{at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf), 1}
-                                       : RowVarF32{nullptr, nullptr, nullptr, 0});
+                       is_mfma(L.prec) ? rowvar_f32(L, ws) : RowVarF32{nullptr, nullptr, nullptr, nullptr, 0});
     HIPCHK(hipGetLastError());
     hipEvent_t ev[4];
     for (auto& x : ev) HIPCHK(hipEventCreate(&x));
@@ -864,6 +1243,145 @@ lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params
     if (row_ms) *row_ms = a / reps;
     if (col_ms) *col_ms = b / reps;
     return LAMP_OK;
+}
+
+size_t lamp_batch_workspace_bytes(const lamp_problem* probs, int32_t count, const lamp_params* params) {
+    (void)params;
+    if (!probs || count < 1) return 0;
+    for (int p = 0; p < count; ++p)
+        if (probs[p].n < 1 || probs[p].m < 1 || probs[p].d < 1) return 0;
+    size_t best = 0;
+    for (int c = 0; c < kNumBatchCands; ++c) best = std::max(best, batch_plan(probs, count, c).total);
+    return best + 256;
+}
+
+lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const lamp_params* params,
+                               lamp_state* states, void* ws, size_t ws_bytes, void* stream, lamp_report* outs) {
+    const auto t_start = std::chrono::steady_clock::now();
+    lamp_status e;
+    if (!probs || !states || count < 1) return fail(LAMP_EINVAL, "empty batch or NULL arrays");
+    if ((e = check_params(params)) != LAMP_OK) return e;
+    if (params->precision != LAMP_FP32) return fail(LAMP_EINVAL, "the batching form runs the LAMP_FP32 form");
+    for (int p = 0; p < count; ++p) {
+        if ((e = check_problem(&probs[p])) != LAMP_OK) return e;
+        if ((e = check_state(&states[p])) != LAMP_OK) return e;
+        if (states[p].t != states[0].t || states[p].inv_eta != states[0].inv_eta)
+            return fail(LAMP_EINVAL, "batched states must share t and inv_eta (problem %d differs)", p);
+        if ((e = check_marginals(&probs[p])) != LAMP_OK) return e;
+    }
+    if (!ws) return fail(LAMP_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(LAMP_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = lamp_batch_workspace_bytes(probs, count, params) - 256;
+    if (ws_bytes < need) return fail(LAMP_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    hipStream_t own = nullptr;
+    if (!st) {
+        HIPCHK(hipStreamSynchronize(nullptr));
+        HIPCHK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        st = own;
+    }
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() {
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+            }
+        }
+    } guard{own};
+
+    int cand = 0;
+    if ((e = batch_tune(probs, count, params, states, ws, st, &cand)) != LAMP_OK) return e;
+    const int64_t t0 = states[0].t;
+    const int64_t t_stop = t0 + params->max_iter;
+    BatchRun run;
+    if ((e = batch_setup(probs, count, params, states, ws, st, cand, t_stop, &run)) != LAMP_OK) return e;
+    const BatchPlan& B = run.B;
+    const int K = params->check_every > 0 ? params->check_every : 64;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (t_stop > t0) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < K; ++k) batch_iteration(run, ws, st);
+        hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (ce != hipSuccess) return fail(LAMP_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+        HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    std::vector<Ctrl> hc(count);
+    Ctrl* hc_dev = at<Ctrl>(ws, B.ctrlv);
+    double lam_epoch = states[0].inv_eta;
+    int64_t t_base = t0;
+    std::vector<Sched> tab;
+    double lam_next_epoch = fill_sched(tab, TAB, lam_epoch, run.tau1, params->eta);
+    int64_t t_cur = t0;
+    lamp_status result = LAMP_OK;
+    while (t_cur < t_stop) {
+        HIPCHK(hipGraphLaunch(exec, st));
+        HIPCHK(hipGraphLaunch(exec, st));
+        HIPCHK(hipMemcpyAsync(hc.data(), hc_dev, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool all_done = true, any_err = false;
+        int64_t tmax = t_cur;
+        for (int p = 0; p < count; ++p) {
+            if (hc[p].err) any_err = true;
+            if (!hc[p].done) {
+                all_done = false;
+                tmax = std::max(tmax, hc[p].t);
+            }
+        }
+        if (any_err) {
+            result = fail(LAMP_ENUMERIC, "non-finite value in the dual update of a batched problem");
+            break;
+        }
+        if (all_done) break;
+        if (tmax == t_cur) return fail(LAMP_EDEVICE, "batched iteration counter did not advance past %lld",
+                                       (long long)t_cur);
+        t_cur = tmax;
+        if (t_cur >= t_stop) break;
+        if (t_cur >= t_base + TAB) {
+            t_base = t_cur;
+            lam_epoch = lam_next_epoch;
+            lam_next_epoch = fill_sched(tab, TAB, lam_epoch, run.tau1, params->eta);
+            HIPCHK(hipMemcpyAsync(at<Sched>(ws, B.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice,
+                                  st));
+            hipLaunchKernelGGL(set_epoch, dim3(cdiv(count, 64)), dim3(64), 0, st, at<ProbDesc>(ws, B.descs), count,
+                               t_base, std::min(t_stop, t_base + TAB));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    HIPCHK(hipMemcpyAsync(hc.data(), hc_dev, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    bool all_conv = true;
+    for (int p = 0; p < count; ++p) {
+        const int64_t tp = hc[p].done ? hc[p].t_done : hc[p].t;
+        if ((tp & 1) != (t0 & 1)) {
+            HIPCHK(hipMemcpyAsync(states[p].nu, run.nu1[p], sizeof(double) * probs[p].m, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(states[p].theta, run.th1[p], sizeof(double) * probs[p].m, hipMemcpyDeviceToDevice,
+                                  st));
+        }
+        double lam = states[0].inv_eta;
+        for (int64_t k = t0; k < tp; ++k) lam = next_lam(lam, run.tau1, params->eta);
+        states[p].t = tp;
+        states[p].inv_eta = lam;
+        const bool conv = hc[p].done && !hc[p].err;
+        all_conv = all_conv && conv;
+        if (outs) {
+            outs[p].iters = tp - t0;
+            outs[p].t = tp;
+            outs[p].seconds = secs;
+            outs[p].final_res = hc[p].res_last;
+            outs[p].cost_scale = run.R[p].s;
+            outs[p].cost_norm = run.R[p].cnorm;
+            outs[p].converged = conv;
+            outs[p].row_fallbacks = hc[p].fallbacks;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (result != LAMP_OK) return result;
+    return (all_conv || params->tol == 0.0) ? LAMP_OK : LAMP_NOT_CONVERGED;
 }
 
 }  // extern "C"

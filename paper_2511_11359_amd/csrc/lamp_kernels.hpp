@@ -120,11 +120,11 @@ __global__ void prep_points(const float* __restrict__ pts, int64_t cnt, int d,
 //   g^A_j = -lam_t LOG2E (s yn2_j + K nu_j),  g^B_j = -lam_{t+1} LOG2E (s yn2_j + K nubar_j),
 //   nubar = nu + w (theta - nu)  (step:lamp_mid_nu).
 // ---------------------------------------------------------------------------
-__global__ void col_table_init(const Ctrl* ctrl, const Sched* sched, Consts kc,
+__device__ __forceinline__ void col_table_init_body(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                const double* __restrict__ yn2, const double* __restrict__ nu,
                                const double* __restrict__ theta, double2* __restrict__ gtab2,
-                               float2* __restrict__ gtabf, int64_t m_pad) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                               float2* __restrict__ gtabf, int64_t m_pad, int64_t bx_, int64_t by_, int64_t nb_) {
+    int64_t j = (int64_t)bx_ * blockDim.x + threadIdx.x;
     if (j >= kc.m) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
@@ -137,15 +137,27 @@ __global__ void col_table_init(const Ctrl* ctrl, const Sched* sched, Consts kc,
     if (gtabf) gtabf[(t & 1) * m_pad + j] = make_float2((float)g.x, (float)g.y);
 }
 
+__global__ void col_table_init(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                               const double* __restrict__ yn2, const double* __restrict__ nu,
+                               const double* __restrict__ theta, double2* __restrict__ gtab2,
+                               float2* __restrict__ gtabf, int64_t m_pad) {
+    col_table_init_body(ctrl, sched, kc, yn2, nu, theta, gtab2, gtabf, m_pad, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+}
+
 // a_j = -g^B_j / cfac^B for the exact offset initialisation.
-__global__ void offset_coeffs(const Ctrl* ctrl, const Sched* sched, Consts kc,
-                              const double2* __restrict__ gtab2, double* __restrict__ a) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void offset_coeffs_body(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                              const double2* __restrict__ gtab2, double* __restrict__ a, int64_t bx_, int64_t by_, int64_t nb_) {
+    int64_t j = (int64_t)bx_ * blockDim.x + threadIdx.x;
     if (j >= kc.m) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
     const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
     a[j] = -gtab2[(t & 1) * kc.m + j].y / cB;
+}
+
+__global__ void offset_coeffs(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                              const double2* __restrict__ gtab2, double* __restrict__ a) {
+    offset_coeffs_body(ctrl, sched, kc, gtab2, a, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -154,12 +166,12 @@ __global__ void offset_coeffs(const Ctrl* ctrl, const Sched* sched, Consts kc,
 // part: [P][n] partial minima over column splits.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(BLOCK) void row_extreme(Consts kc, const double* __restrict__ xc,
+__device__ __forceinline__ void row_extreme_body(Consts kc, const double* __restrict__ xc,
                                                      const double* __restrict__ yc,
                                                      const double* __restrict__ a, double sgn,
-                                                     double* __restrict__ part, int64_t split) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+                                                     double* __restrict__ part, int64_t split, int64_t bx_, int64_t by_, int64_t nb_) {
+    const int64_t i = (int64_t)bx_ * BLOCK + threadIdx.x;
+    const int64_t p = by_;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
     const int64_t ii = i < kc.n ? i : kc.n - 1;
@@ -176,13 +188,21 @@ __global__ __launch_bounds__(BLOCK) void row_extreme(Consts kc, const double* __
     if (i < kc.n) part[p * kc.n + i] = best;
 }
 
+template <int D>
+__global__ __launch_bounds__(BLOCK) void row_extreme(Consts kc, const double* __restrict__ xc,
+                                                     const double* __restrict__ yc,
+                                                     const double* __restrict__ a, double sgn,
+                                                     double* __restrict__ part, int64_t split) {
+    row_extreme_body<D>(kc, xc, yc, a, sgn, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+}
+
 // Generic-d version: coordinates read per pair.
-__global__ __launch_bounds__(BLOCK) void row_extreme_dyn(Consts kc, int D, const double* __restrict__ xc,
+__device__ __forceinline__ void row_extreme_dyn_body(Consts kc, int D, const double* __restrict__ xc,
                                                          const double* __restrict__ yc,
                                                          const double* __restrict__ a, double sgn,
-                                                         double* __restrict__ part, int64_t split) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+                                                         double* __restrict__ part, int64_t split, int64_t bx_, int64_t by_, int64_t nb_) {
+    const int64_t i = (int64_t)bx_ * BLOCK + threadIdx.x;
+    const int64_t p = by_;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
     const int64_t ii = i < kc.n ? i : kc.n - 1;
@@ -195,17 +215,30 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_dyn(Consts kc, int D, const
     if (i < kc.n) part[p * kc.n + i] = best;
 }
 
+__global__ __launch_bounds__(BLOCK) void row_extreme_dyn(Consts kc, int D, const double* __restrict__ xc,
+                                                         const double* __restrict__ yc,
+                                                         const double* __restrict__ a, double sgn,
+                                                         double* __restrict__ part, int64_t split) {
+    row_extreme_dyn_body(kc, D, xc, yc, a, sgn, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+}
+
 // Merge the partial minima (exact, order independent); optionally transform.
 //   mode 0: out_i = min            (offset init, writes H)
 //   mode 1: out_i = xn2_i - 2 min  (squared distance maximum of row i)
-__global__ void row_extreme_merge(Consts kc, const double* __restrict__ part, int P,
+__device__ __forceinline__ void row_extreme_merge_body(Consts kc, const double* __restrict__ part, int P,
                                   const double* __restrict__ xn2, int mode,
-                                  double* __restrict__ out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                  double* __restrict__ out, int64_t bx_, int64_t by_, int64_t nb_) {
+    int64_t i = (int64_t)bx_ * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     double best = part[i];
     for (int p = 1; p < P; ++p) best = fmin(best, part[(int64_t)p * kc.n + i]);
     out[i] = (mode == 0) ? best : xn2[i] - 2.0 * best;
+}
+
+__global__ void row_extreme_merge(Consts kc, const double* __restrict__ part, int P,
+                                  const double* __restrict__ xn2, int mode,
+                                  double* __restrict__ out) {
+    row_extreme_merge_body(kc, part, P, xn2, mode, out, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,12 +266,12 @@ __device__ __forceinline__ void row_terms(const double (&x)[D], double h, const 
 }
 
 template <int D>
-__global__ __launch_bounds__(BLOCK) void row_sweep(const Ctrl* ctrl, const Sched* sched, Consts kc,
+__device__ __forceinline__ void row_sweep_body(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                    const double* __restrict__ xc,
                                                    const double* __restrict__ yc,
                                                    const double2* __restrict__ gtab2,
                                                    const double* __restrict__ H,
-                                                   double2* __restrict__ part, int64_t split) {
+                                                   double2* __restrict__ part, int64_t split, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
@@ -246,8 +279,8 @@ __global__ __launch_bounds__(BLOCK) void row_sweep(const Ctrl* ctrl, const Sched
     const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
     const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
 
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+    const int64_t i = (int64_t)bx_ * BLOCK + threadIdx.x;
+    const int64_t p = by_;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
     const int64_t ii = i < kc.n ? i : kc.n - 1;
@@ -288,20 +321,30 @@ __global__ __launch_bounds__(BLOCK) void row_sweep(const Ctrl* ctrl, const Sched
     if (i < kc.n) part[p * kc.n + i] = make_double2(sumA, sumB);
 }
 
-__global__ __launch_bounds__(BLOCK) void row_sweep_dyn(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+template <int D>
+__global__ __launch_bounds__(BLOCK) void row_sweep(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                   const double* __restrict__ xc,
+                                                   const double* __restrict__ yc,
+                                                   const double2* __restrict__ gtab2,
+                                                   const double* __restrict__ H,
+                                                   double2* __restrict__ part, int64_t split) {
+    row_sweep_body<D>(ctrl, sched, kc, xc, yc, gtab2, H, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+}
+
+__device__ __forceinline__ void row_sweep_dyn_body(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
                                                        const double* __restrict__ xc,
                                                        const double* __restrict__ yc,
                                                        const double2* __restrict__ gtab2,
                                                        const double* __restrict__ H,
-                                                       double2* __restrict__ part, int64_t split) {
+                                                       double2* __restrict__ part, int64_t split, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
     const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
     const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
     const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+    const int64_t i = (int64_t)bx_ * BLOCK + threadIdx.x;
+    const int64_t p = by_;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
     const int64_t ii = i < kc.n ? i : kc.n - 1;
@@ -320,6 +363,15 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_dyn(const Ctrl* ctrl, const S
         sumB += (double)accB;
     }
     if (i < kc.n) part[p * kc.n + i] = make_double2(sumA, sumB);
+}
+
+__global__ __launch_bounds__(BLOCK) void row_sweep_dyn(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+                                                       const double* __restrict__ xc,
+                                                       const double* __restrict__ yc,
+                                                       const double2* __restrict__ gtab2,
+                                                       const double* __restrict__ H,
+                                                       double2* __restrict__ part, int64_t split) {
+    row_sweep_dyn_body(ctrl, sched, kc, D, xc, yc, gtab2, H, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 // Exact recomputation of sigma_i = log2 sum_j 2^(g_j + cfac x~_i.y~_j) (two passes, FP64 max).
@@ -351,17 +403,18 @@ struct RowVarF32 {
     float* k;
     float* wA;
     float* wB;
+    float4* q;        // {k, wA, wB, 0} per row for the swapped-operand column sweep (nullable)
     int f32_offsets;
 };
 
-__global__ void row_finish(Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+__device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, Consts kc, int D,
                            const double* __restrict__ xc, const double* __restrict__ yc,
                            const double2* __restrict__ gtab2, const double* __restrict__ r,
                            const double* __restrict__ xn2, const double2* __restrict__ part, int P,
                            double* __restrict__ H, RowVar* __restrict__ rowvar,
-                           double* __restrict__ log_za, double* __restrict__ log_zb, RowVarF32 rf) {
+                           double* __restrict__ log_za, double* __restrict__ log_zb, RowVarF32 rf, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = (int64_t)bx_ * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
@@ -398,12 +451,24 @@ __global__ void row_finish(Ctrl* ctrl, const Sched* sched, Consts kc, int D,
     if (rf.k) {
         const float kf = (float)hnew;
         const double dk = hnew - (double)kf;
+        const float wa = (float)(r[i] * exp2(fmin(fmax(ew + cA * dk, -1000.0), 1000.0)));
+        const float wb = (float)(r[i] * exp2(cB * dk));
         rf.k[i] = kf;
-        rf.wA[i] = (float)(r[i] * exp2(fmin(fmax(ew + cA * dk, -1000.0), 1000.0)));
-        rf.wB[i] = (float)(r[i] * exp2(cB * dk));
+        rf.wA[i] = wa;
+        rf.wB[i] = wb;
+        if (rf.q) rf.q[i] = make_float4(kf, wa, wb, 0.f);
     }
     if (log_za) log_za[i] = LN2 * (-sc.lamA * LOG2E * kc.s * xn2[i] + sigA);
     if (log_zb) log_zb[i] = LN2 * (-sc.lamB * LOG2E * kc.s * xn2[i] + sigB);
+}
+
+__global__ void row_finish(Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+                           const double* __restrict__ xc, const double* __restrict__ yc,
+                           const double2* __restrict__ gtab2, const double* __restrict__ r,
+                           const double* __restrict__ xn2, const double2* __restrict__ part, int P,
+                           double* __restrict__ H, RowVar* __restrict__ rowvar,
+                           double* __restrict__ log_za, double* __restrict__ log_zb, RowVarF32 rf) {
+    row_finish_body(ctrl, sched, kc, D, xc, yc, gtab2, r, xn2, part, P, H, rowvar, log_za, log_zb, rf, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,19 +489,19 @@ __device__ __forceinline__ void col_terms(const double (&y)[D], const double* __
 }
 
 template <int D>
-__global__ __launch_bounds__(BLOCK) void col_sweep(const Ctrl* ctrl, const Sched* sched, Consts kc,
+__device__ __forceinline__ void col_sweep_body(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                    const double* __restrict__ xc,
                                                    const double* __restrict__ yc,
                                                    const double2* __restrict__ gtab2,
                                                    const RowVar* __restrict__ rowvar,
-                                                   double2* __restrict__ cpart, int64_t split) {
+                                                   double2* __restrict__ cpart, int64_t split, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
     const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
     const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
-    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+    const int64_t j = (int64_t)bx_ * BLOCK + threadIdx.x;
+    const int64_t p = by_;
     const int64_t i0 = p * split;
     const int64_t i1 = min(kc.n, i0 + split);
     const int64_t jj = j < kc.m ? j : kc.m - 1;
@@ -466,19 +531,29 @@ __global__ __launch_bounds__(BLOCK) void col_sweep(const Ctrl* ctrl, const Sched
     if (j < kc.m) cpart[p * kc.m + j] = make_double2(sumA, sumB);
 }
 
-__global__ __launch_bounds__(BLOCK) void col_sweep_dyn(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+template <int D>
+__global__ __launch_bounds__(BLOCK) void col_sweep(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                   const double* __restrict__ xc,
+                                                   const double* __restrict__ yc,
+                                                   const double2* __restrict__ gtab2,
+                                                   const RowVar* __restrict__ rowvar,
+                                                   double2* __restrict__ cpart, int64_t split) {
+    col_sweep_body<D>(ctrl, sched, kc, xc, yc, gtab2, rowvar, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+}
+
+__device__ __forceinline__ void col_sweep_dyn_body(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
                                                        const double* __restrict__ xc,
                                                        const double* __restrict__ yc,
                                                        const double2* __restrict__ gtab2,
                                                        const RowVar* __restrict__ rowvar,
-                                                       double2* __restrict__ cpart, int64_t split) {
+                                                       double2* __restrict__ cpart, int64_t split, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
     const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
     const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
-    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+    const int64_t j = (int64_t)bx_ * BLOCK + threadIdx.x;
+    const int64_t p = by_;
     const int64_t i0 = p * split;
     const int64_t i1 = min(kc.n, i0 + split);
     const int64_t jj = j < kc.m ? j : kc.m - 1;
@@ -500,6 +575,15 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_dyn(const Ctrl* ctrl, const S
     if (j < kc.m) cpart[p * kc.m + j] = make_double2(sumA, sumB);
 }
 
+__global__ __launch_bounds__(BLOCK) void col_sweep_dyn(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+                                                       const double* __restrict__ xc,
+                                                       const double* __restrict__ yc,
+                                                       const double2* __restrict__ gtab2,
+                                                       const RowVar* __restrict__ rowvar,
+                                                       double2* __restrict__ cpart, int64_t split) {
+    col_sweep_dyn_body(ctrl, sched, kc, D, xc, yc, gtab2, rowvar, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Dual update (S5-S6 of Algorithm 2), residual, next column table, stop flag.
 // State is double-buffered by iteration parity: iteration t reads buffer t&1 and
@@ -515,17 +599,17 @@ struct TraceCols {
     double *col_a, *col_b, *theta_bar, *theta_hat;
 };
 
-__global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sched, Consts kc,
+__device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched, Consts kc,
                                                      const double2* __restrict__ cpart, int P,
                                                      const double* __restrict__ c,
                                                      const double* __restrict__ yn2, DualBufs buf,
                                                      double2* __restrict__ gtab2,
                                                      float2* __restrict__ gtabf, int64_t m_pad,
-                                                     double* __restrict__ respart, TraceCols tr) {
+                                                     double* __restrict__ respart, TraceCols tr, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
-    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t j = (int64_t)bx_ * BLOCK + threadIdx.x;
     double res = 0.0;
     int bad = 0;
     if (j < kc.m) {
@@ -579,11 +663,11 @@ __global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sc
     }
     __shared__ bool last;
     if (threadIdx.x == 0) {
-        respart[blockIdx.x] = sh[0];
+        respart[bx_] = sh[0];
         if (shbad) atomicOr(&ctrl->err, 1);
         __threadfence();
         unsigned prev = atomicAdd(&ctrl->counter, 1u);
-        last = (prev == gridDim.x - 1);
+        last = (prev == nb_ - 1);
     }
     __syncthreads();
     if (!last) return;
@@ -591,7 +675,7 @@ __global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sc
     __threadfence();
     double tot = 0.0;
     if (threadIdx.x == 0) {
-        for (unsigned b = 0; b < gridDim.x; ++b) tot += __hip_atomic_load(&respart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (unsigned b = 0; b < nb_; ++b) tot += __hip_atomic_load(&respart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ctrl->res_last = tot;
         ctrl->counter = 0;
         if (ctrl->err) {
@@ -605,6 +689,16 @@ __global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sc
         }
         __threadfence();
     }
+}
+
+__global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                     const double2* __restrict__ cpart, int P,
+                                                     const double* __restrict__ c,
+                                                     const double* __restrict__ yn2, DualBufs buf,
+                                                     double2* __restrict__ gtab2,
+                                                     float2* __restrict__ gtabf, int64_t m_pad,
+                                                     double* __restrict__ respart, TraceCols tr) {
+    dual_update_body(ctrl, sched, kc, cpart, P, c, yn2, buf, gtab2, gtabf, m_pad, respart, tr, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -64,7 +64,8 @@ __global__ void prep_operands(const double* __restrict__ src, int64_t cnt, int d
     if (idx >= cnt_pad * KP) return;
     int64_t i = idx / KP;
     int k = (int)(idx % KP);
-    double v = (i < cnt && k < d) ? src[i * d + k] : 0.0;
+    // double -> FP32 -> T: one fixed, documented rounding path for every operand type
+    const float v = (i < cnt && k < d) ? (float)src[i * d + k] : 0.f;
     out[idx] = (T)v;
 }
 
@@ -264,6 +265,839 @@ __global__ void pad_gtabf(int64_t m, int64_t m_pad, float2* __restrict__ gtabf) 
     if (j >= m_pad) return;
     gtabf[j] = make_float2(PAD_NEG, PAD_NEG);
     gtabf[m_pad + j] = make_float2(PAD_NEG, PAD_NEG);
+}
+
+
+// ---------------------------------------------------------------------------
+// FP64 matrix-core sweeps (v_mfma_f64_16x16x4f64) for larger d in the reference-
+// accuracy form: the dot products and the exponent assembly are FP64, only the
+// exponential and the sums are FP32, exactly as in the vector-ALU sweeps.
+// Layout (verified on gfx950): lane l supplies row (l mod 16) of A and column
+// (l mod 16) of B for contraction slot l / 16; D[row][col] sits in lane
+// col + 16 g, register q, with row = 4 q + g (g = l / 16).  Lane group g supplies
+// coordinates [g KP/4, (g+1) KP/4) of its point over the KP/4 instructions.
+// ---------------------------------------------------------------------------
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ doublex4 mma64(double a, double b, doublex4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// FP64 operand copy padded to KP coordinates (multiple of 4) and to a multiple of 64 points.
+__global__ void prep_operands64(const double* __restrict__ src, int64_t cnt, int d, int KP, int64_t cnt_pad,
+                                double* __restrict__ out) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= cnt_pad * KP) return;
+    int64_t i = idx / KP;
+    int k = (int)(idx % KP);
+    out[idx] = (i < cnt && k < d) ? src[i * d + k] : 0.0;
+}
+
+// Row sweep: wave owns 16 rows; block b covers 64 rows (4 waves) of split p = b mod P.
+template <int KP>
+__global__ __launch_bounds__(BLOCK) void row_sweep_mfma64(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                          const double* __restrict__ xop,
+                                                          const double* __restrict__ yop,
+                                                          const double2* __restrict__ gtab2,
+                                                          const double* __restrict__ H,
+                                                          double2* __restrict__ part, int64_t tiles_per_split,
+                                                          int P, int64_t m_tiles, int64_t n_waves) {
+    if (halted(ctrl)) return;
+    constexpr int NS = KP / 4;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, c16 = lane & 15;
+    const int64_t b = blockIdx.x;
+    const int p = (int)(b % P);
+    const int64_t rw = (b / P) * 4 + (threadIdx.x >> 6);
+    if (rw >= n_waves) return;
+    const int64_t i0 = rw * 16;
+    double a[NS];
+    {
+        const double* ap = xop + (i0 + c16) * KP + grp * NS;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = ap[s];
+    }
+    doublex4 hv;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t ii = i0 + 4 * q + grp;
+        hv[q] = H[ii < kc.n ? ii : kc.n - 1];
+    }
+    float accA[4] = {0.f, 0.f, 0.f, 0.f}, accB[4] = {0.f, 0.f, 0.f, 0.f};
+    double sumA[4] = {0.0, 0.0, 0.0, 0.0}, sumB[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t jt0 = (int64_t)p * tiles_per_split;
+    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
+    int cnt = 0;
+    for (int64_t jt = jt0; jt < jt1; ++jt) {
+        const int64_t j = jt * 16 + c16;
+        const double* bp = yop + j * KP + grp * NS;
+        double bv[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
+        double gA = -1e300, gB = -1e300;
+        if (j < kc.m) {
+            const double2 gg = g[j];
+            gA = gg.x;
+            gB = gg.y;
+        }
+        doublex4 d = mma64(a[0], bv[0], hv);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            accA[q] += fexp2(fma(d[q], cA, gA));
+            accB[q] += fexp2(fma(d[q], cB, gB));
+        }
+        if (++cnt == 8) {   // carry in FP64 every 8 terms
+            cnt = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                sumA[q] += (double)accA[q];
+                sumB[q] += (double)accB[q];
+                accA[q] = accB[q] = 0.f;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        sumA[q] += (double)accA[q];
+        sumB[q] += (double)accB[q];
+        // sum over the 16 columns held by the 16 lanes of each group
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            sumA[q] += __shfl_xor(sumA[q], o, 64);
+            sumB[q] += __shfl_xor(sumB[q], o, 64);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t row = i0 + 4 * q + grp;
+        if (c16 == q && row < kc.n) part[(int64_t)p * kc.n + row] = make_double2(sumA[q], sumB[q]);
+    }
+}
+
+// Column sweep: wave owns 16 columns, streams 16-row tiles of split p.
+template <int KP>
+__global__ __launch_bounds__(BLOCK) void col_sweep_mfma64(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                          const double* __restrict__ xop,
+                                                          const double* __restrict__ yop,
+                                                          const double2* __restrict__ gtab2,
+                                                          const RowVar* __restrict__ rowvar,
+                                                          double2* __restrict__ cpart, int64_t tiles_per_split,
+                                                          int P, int64_t n_tiles, int64_t m_waves) {
+    if (halted(ctrl)) return;
+    constexpr int NS = KP / 4;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, c16 = lane & 15;
+    const int64_t b = blockIdx.x;
+    const int p = (int)(b % P);
+    const int64_t cw = (b / P) * 4 + (threadIdx.x >> 6);
+    if (cw >= m_waves) return;
+    const int64_t j = cw * 16 + c16;
+    double bv[NS];
+    {
+        const double* bp = yop + j * KP + grp * NS;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
+    }
+    double gA = -1e300, gB = -1e300;
+    if (j < kc.m) {
+        const double2 gg = gtab2[(t & 1) * kc.m + j];
+        gA = gg.x;
+        gB = gg.y;
+    }
+    float accA = 0.f, accB = 0.f;
+    double sumA = 0.0, sumB = 0.0;
+    const int64_t it0 = (int64_t)p * tiles_per_split;
+    const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
+    for (int64_t it = it0; it < it1; ++it) {
+        const int64_t i = it * 16 + c16;
+        const double* ap = xop + i * KP + grp * NS;
+        double a[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = ap[s];
+        doublex4 kv;
+        float wa[4], wb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = it * 16 + 4 * q + grp;
+            if (row < kc.n) {
+                const RowVar rv = rowvar[row];
+                kv[q] = rv.k;
+                wa[q] = rv.wA;
+                wb[q] = rv.wB;
+            } else {
+                kv[q] = -1e300;
+                wa[q] = wb[q] = 0.f;
+            }
+        }
+        doublex4 d = mma64(a[0], bv[0], kv);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            accA = fmaf(wa[q], fexp2(fma(d[q], cA, gA)), accA);
+            accB = fmaf(wb[q], fexp2(fma(d[q], cB, gB)), accB);
+        }
+        if (((it - it0) & 1) == 1) {   // carry in FP64 every 8 terms
+            sumA += (double)accA;
+            sumB += (double)accB;
+            accA = accB = 0.f;
+        }
+    }
+    sumA += (double)accA;
+    sumB += (double)accB;
+    // the 4 lane groups hold the same column for different rows
+    sumA += __shfl_xor(sumA, 16, 64);
+    sumB += __shfl_xor(sumB, 16, 64);
+    sumA += __shfl_xor(sumA, 32, 64);
+    sumB += __shfl_xor(sumB, 32, 64);
+    if (grp == 0 && j < kc.m) cpart[(int64_t)p * kc.m + j] = make_double2(sumA, sumB);
+}
+
+// Column sweep of the BF16/FP16 forms with the roles of the operands swapped:
+// the wave's 32 columns y_j are the MFMA rows (fixed A operand) and the streamed
+// points x_i are the MFMA columns, so the per-row data (k_i, w^A_i, w^B_i) is one
+// value per lane per tile instead of sixteen.  Each coupling gets its own chain with
+// accumulator input G_j = g_j / c (per register), so that
+//     e = c (G_j + x~_i . y~_j) + c k_i,
+// one FP32 FMA per entry with the per-lane c k_i.  The two chains double the
+// (cheap) half-precision matrix work and remove most of the vector-memory traffic.
+template <typename T, int KP>
+__global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                          const T* __restrict__ xop, const T* __restrict__ yop,
+                                                          const float2* __restrict__ gtabf, int64_t m_pad,
+                                                          const float4* __restrict__ rowq,
+                                                          double2* __restrict__ cpart, int64_t tiles_per_split,
+                                                          int P, int64_t n_tiles, int64_t m_waves) {
+    if (halted(ctrl)) return;
+    using Op = MfmaOp<T>;
+    using vec = typename Op::vec;
+    constexpr int NS = KP / Op::KSTEP;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E);
+    const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
+    const int lane = threadIdx.x & 63;
+    const int hf = lane >> 5, c32 = lane & 31;
+    const int64_t b = blockIdx.x;
+    const int p = (int)(b % P);
+    const int64_t cw = (b / P) * 4 + (threadIdx.x >> 6);
+    if (cw >= m_waves) return;
+    const int64_t j0 = cw * 32;
+    vec a[NS];
+    {
+        const vec* ap = reinterpret_cast<const vec*>(yop + (j0 + c32) * KP + hf * (KP / 2));
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = ap[s];
+    }
+    // G_j = g_j / c for the 16 columns of this lane's registers (0 at c = 0: then e = 0 = g_j)
+    const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
+    floatx16 GA, GB;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float2 gg = g[j0 + mfma_row(r, hf)];
+        GA[r] = cA > 0.f ? gg.x / cA : 0.f;
+        GB[r] = gg.y / cB;
+        if (gg.x <= PAD_NEG) GA[r] = PAD_NEG;
+        if (gg.y <= PAD_NEG) GB[r] = PAD_NEG;
+    }
+    float accA[16], accB[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accA[r] = accB[r] = 0.f;
+    const int64_t it0 = (int64_t)p * tiles_per_split;
+    const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
+    vec bn[NS];
+    float4 qn = make_float4(PAD_NEG, 0.f, 0.f, 0.f);
+    if (it0 < it1) {
+        const int64_t i = it0 * 32 + c32;
+        const vec* bp = reinterpret_cast<const vec*>(xop + i * KP + hf * (KP / 2));
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bn[s] = bp[s];
+        qn = rowq[i];
+    }
+    for (int64_t it = it0; it < it1; ++it) {
+        vec bv[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bv[s] = bn[s];
+        const float4 q = qn;
+        if (it + 1 < it1) {
+            const int64_t i = (it + 1) * 32 + c32;
+            const vec* bp = reinterpret_cast<const vec*>(xop + i * KP + hf * (KP / 2));
+#pragma unroll
+            for (int s = 0; s < NS; ++s) bn[s] = bp[s];
+            qn = rowq[i];
+        }
+        const float ckA = cA * q.x, ckB = cB * q.x;
+        floatx16 dA = Op::mma(a[0], bv[0], GA);
+        floatx16 dB = Op::mma(a[0], bv[0], GB);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) {
+            dA = Op::mma(a[s], bv[s], dA);
+            dB = Op::mma(a[s], bv[s], dB);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            accA[r] = fmaf(q.y, __builtin_amdgcn_exp2f(fmaf(dA[r], cA, ckA)), accA[r]);
+            accB[r] = fmaf(q.z, __builtin_amdgcn_exp2f(fmaf(dB[r], cB, ckB)), accB[r]);
+        }
+    }
+    // sum over the 32 rows held by the 32 lanes of each half
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) {
+            accA[r] += __shfl_xor(accA[r], o, 64);
+            accB[r] += __shfl_xor(accB[r], o, 64);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t j = j0 + mfma_row(r, hf);
+        if (c32 == r && j < kc.m) cpart[(int64_t)p * kc.m + j] = make_double2(accA[r], accB[r]);
+    }
+}
+
+__global__ void pad_rowq(int64_t n, int64_t n_pad, float4* __restrict__ q) {
+    int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_pad) q[i] = make_float4(PAD_NEG, 0.f, 0.f, 0.f);
+}
+
+// Row extreme sweep on FP64 matrix cores: out_i = min_j (a_j + sgn x~_i . y~_j), exact FP64.
+template <int KP>
+__global__ __launch_bounds__(BLOCK) void row_extreme_mfma64(Consts kc, const double* __restrict__ xop,
+                                                            const double* __restrict__ yop,
+                                                            const double* __restrict__ aj, double sgn,
+                                                            double* __restrict__ part, int64_t tiles_per_split,
+                                                            int P, int64_t m_tiles, int64_t n_waves) {
+    constexpr int NS = KP / 4;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, c16 = lane & 15;
+    const int64_t b = blockIdx.x;
+    const int p = (int)(b % P);
+    const int64_t rw = (b / P) * 4 + (threadIdx.x >> 6);
+    if (rw >= n_waves) return;
+    const int64_t i0 = rw * 16;
+    double a[NS];
+    {
+        const double* ap = xop + (i0 + c16) * KP + grp * NS;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = sgn * ap[s];
+    }
+    double best[4] = {__builtin_inf(), __builtin_inf(), __builtin_inf(), __builtin_inf()};
+    const int64_t jt0 = (int64_t)p * tiles_per_split;
+    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
+    for (int64_t jt = jt0; jt < jt1; ++jt) {
+        const int64_t j = jt * 16 + c16;
+        const double* bp = yop + j * KP + grp * NS;
+        double bv[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
+        const double aval = j < kc.m ? aj[j] : __builtin_inf();
+        doublex4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) d = mma64(a[s], bv[s], d);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) best[q] = fmin(best[q], aval + d[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) best[q] = fmin(best[q], __shfl_xor(best[q], o, 64));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t row = i0 + 4 * q + grp;
+        if (c16 == q && row < kc.n) part[(int64_t)p * kc.n + row] = best[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-shared forms of the matrix-core sweeps.  The four waves of a block own
+// 4 x 32 points and stream the same tiles of the other cloud: each tile (32
+// points x KP coordinates, plus its per-point scalars) is loaded once per block
+// into LDS, double-buffered, instead of once per wave, which cuts the L2 traffic
+// of the streamed operand by 4.  LDS rows are padded by 16 bytes so that the 32
+// lanes reading 16-byte pieces of 32 different rows hit distinct banks.
+// ---------------------------------------------------------------------------
+template <typename T, int KP>
+struct LdsTile {
+    static constexpr int ROW_BYTES = KP * (int)sizeof(T);     // one point's operand
+    static constexpr int STRIDE = ROW_BYTES + 16;              // padded LDS row
+    static constexpr int TILE_BYTES = 32 * ROW_BYTES;          // global bytes per tile
+    static constexpr int CHUNKS = TILE_BYTES / 16;             // 16-byte pieces per tile
+    static constexpr int PER_THREAD = (CHUNKS + BLOCK - 1) / BLOCK;
+    static constexpr int BUF = 32 * STRIDE + 32 * 16;          // operand rows + 32 scalar slots
+};
+
+// Global -> registers part of a tile load (16-byte pieces, PER_THREAD per thread).
+template <typename T, int KP>
+__device__ __forceinline__ void tile_fetch(const T* __restrict__ src_rows, int64_t row0, const void* __restrict__ scal,
+                                           int scal_bytes, int4 (&buf)[LdsTile<T, KP>::PER_THREAD], int4& sbuf) {
+    using L = LdsTile<T, KP>;
+    const char* base = reinterpret_cast<const char*>(src_rows + row0 * KP);
+#pragma unroll
+    for (int q = 0; q < L::PER_THREAD; ++q) {
+        const int c = threadIdx.x + q * BLOCK;
+        if (c < L::CHUNKS) buf[q] = *reinterpret_cast<const int4*>(base + (int64_t)c * 16);
+    }
+    // per-point scalars: 32 entries of scal_bytes (8 or 16) bytes
+    if (threadIdx.x < 32) {
+        const char* sp = reinterpret_cast<const char*>(scal) + (row0 + threadIdx.x) * scal_bytes;
+        if (scal_bytes == 16) sbuf = *reinterpret_cast<const int4*>(sp);
+        else {
+            const int2 v = *reinterpret_cast<const int2*>(sp);
+            sbuf = make_int4(v.x, v.y, 0, 0);
+        }
+    }
+}
+
+// Registers -> LDS part of a tile load.
+template <typename T, int KP>
+__device__ __forceinline__ void tile_store(char* lds, const int4 (&buf)[LdsTile<T, KP>::PER_THREAD], const int4& sbuf) {
+    using L = LdsTile<T, KP>;
+#pragma unroll
+    for (int q = 0; q < L::PER_THREAD; ++q) {
+        const int c = threadIdx.x + q * BLOCK;
+        if (c < L::CHUNKS) {
+            const int row = (c * 16) / L::ROW_BYTES;
+            const int off = (c * 16) % L::ROW_BYTES;
+            *reinterpret_cast<int4*>(lds + row * L::STRIDE + off) = buf[q];
+        }
+    }
+    if (threadIdx.x < 32) *reinterpret_cast<int4*>(lds + 32 * L::STRIDE + threadIdx.x * 16) = sbuf;
+}
+
+// The operand vectors of lane (c32, hf) from an LDS tile.
+template <typename T, int KP>
+__device__ __forceinline__ void tile_operands(const char* lds, int c32, int hf,
+                                              typename MfmaOp<T>::vec (&v)[KP / MfmaOp<T>::KSTEP]) {
+    using L = LdsTile<T, KP>;
+    using vec = typename MfmaOp<T>::vec;
+    const vec* p = reinterpret_cast<const vec*>(lds + c32 * L::STRIDE + hf * (L::ROW_BYTES / 2));
+#pragma unroll
+    for (int s = 0; s < KP / MfmaOp<T>::KSTEP; ++s) v[s] = p[s];
+}
+
+// Row sweep, LDS-shared column tiles.  Same arithmetic as row_sweep_mfma.
+template <typename T, int KP>
+__global__ __launch_bounds__(BLOCK) void row_sweep_mfma_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                            const T* __restrict__ xop, const T* __restrict__ yop,
+                                                            const float2* __restrict__ gtabf, int64_t m_pad,
+                                                            const double* __restrict__ H,
+                                                            double2* __restrict__ part, int64_t tiles_per_split,
+                                                            int P, int64_t m_tiles, int64_t n_waves) {
+    using L = LdsTile<T, KP>;
+    using Op = MfmaOp<T>;
+    using vec = typename Op::vec;
+    constexpr int NS = KP / Op::KSTEP;
+    __shared__ __align__(16) char lds[2][L::BUF];
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E);
+    const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
+    const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
+    const int lane = threadIdx.x & 63;
+    const int hf = lane >> 5, c32 = lane & 31;
+    const int64_t b = blockIdx.x;
+    const int p = (int)(b % P);
+    const int64_t rw = (b / P) * 4 + (threadIdx.x >> 6);
+    const bool active = rw < n_waves;   // whole waves; the block still joins every barrier
+    const int64_t i0 = (active ? rw : 0) * 32;
+
+    vec a[NS];
+    {
+        const vec* ap = reinterpret_cast<const vec*>(xop + (i0 + c32) * KP + hf * (KP / 2));
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = ap[s];
+    }
+    floatx16 hv;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int64_t ii = i0 + mfma_row(r, hf);
+        hv[r] = (float)H[ii < kc.n ? ii : kc.n - 1];
+    }
+    float accA[16], accB[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accA[r] = accB[r] = 0.f;
+
+    const int64_t jt0 = (int64_t)p * tiles_per_split;
+    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
+    int4 pf[L::PER_THREAD];
+    int4 spf = make_int4(0, 0, 0, 0);
+    if (jt0 < jt1) {
+        tile_fetch<T, KP>(yop, jt0 * 32, g, 8, pf, spf);
+        tile_store<T, KP>(lds[0], pf, spf);
+    }
+    __syncthreads();
+    for (int64_t jt = jt0; jt < jt1; ++jt) {
+        const int cur = (int)((jt - jt0) & 1);
+        const bool more = jt + 1 < jt1;
+        if (more) tile_fetch<T, KP>(yop, (jt + 1) * 32, g, 8, pf, spf);
+        vec bv[NS];
+        tile_operands<T, KP>(lds[cur], c32, hf, bv);
+        const float2 gg = *reinterpret_cast<const float2*>(lds[cur] + 32 * L::STRIDE + c32 * 16);
+        floatx16 d = Op::mma(a[0], bv[0], hv);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) d = Op::mma(a[s], bv[s], d);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            accA[r] += __builtin_amdgcn_exp2f(fmaf(d[r], cA, gg.x));
+            accB[r] += __builtin_amdgcn_exp2f(fmaf(d[r], cB, gg.y));
+        }
+        if (more) tile_store<T, KP>(lds[cur ^ 1], pf, spf);
+        __syncthreads();
+    }
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) {
+            accA[r] += __shfl_xor(accA[r], o, 64);
+            accB[r] += __shfl_xor(accB[r], o, 64);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = i0 + mfma_row(r, hf);
+        if (c32 == r && row < kc.n) part[(int64_t)p * kc.n + row] = make_double2(accA[r], accB[r]);
+    }
+}
+
+// Column sweep of the half-precision forms (swapped operands), LDS-shared row tiles.
+template <typename T, int KP>
+__global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                              const T* __restrict__ xop, const T* __restrict__ yop,
+                                                              const float2* __restrict__ gtabf, int64_t m_pad,
+                                                              const float4* __restrict__ rowq,
+                                                              double2* __restrict__ cpart, int64_t tiles_per_split,
+                                                              int P, int64_t n_tiles, int64_t m_waves) {
+    using L = LdsTile<T, KP>;
+    using Op = MfmaOp<T>;
+    using vec = typename Op::vec;
+    constexpr int NS = KP / Op::KSTEP;
+    __shared__ __align__(16) char lds[2][L::BUF];
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E);
+    const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
+    const int lane = threadIdx.x & 63;
+    const int hf = lane >> 5, c32 = lane & 31;
+    const int64_t b = blockIdx.x;
+    const int p = (int)(b % P);
+    const int64_t cw = (b / P) * 4 + (threadIdx.x >> 6);
+    const bool active = cw < m_waves;
+    const int64_t j0 = (active ? cw : 0) * 32;
+    vec a[NS];
+    {
+        const vec* ap = reinterpret_cast<const vec*>(yop + (j0 + c32) * KP + hf * (KP / 2));
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = ap[s];
+    }
+    const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
+    floatx16 GA, GB;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float2 gg = g[j0 + mfma_row(r, hf)];
+        GA[r] = cA > 0.f ? gg.x / cA : 0.f;
+        GB[r] = gg.y / cB;
+        if (gg.x <= PAD_NEG) GA[r] = PAD_NEG;
+        if (gg.y <= PAD_NEG) GB[r] = PAD_NEG;
+    }
+    float accA[16], accB[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accA[r] = accB[r] = 0.f;
+    const int64_t it0 = (int64_t)p * tiles_per_split;
+    const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
+    int4 pf[L::PER_THREAD];
+    int4 spf = make_int4(0, 0, 0, 0);
+    if (it0 < it1) {
+        tile_fetch<T, KP>(xop, it0 * 32, rowq, 16, pf, spf);
+        tile_store<T, KP>(lds[0], pf, spf);
+    }
+    __syncthreads();
+    for (int64_t it = it0; it < it1; ++it) {
+        const int cur = (int)((it - it0) & 1);
+        const bool more = it + 1 < it1;
+        if (more) tile_fetch<T, KP>(xop, (it + 1) * 32, rowq, 16, pf, spf);
+        vec bv[NS];
+        tile_operands<T, KP>(lds[cur], c32, hf, bv);
+        const float4 q = *reinterpret_cast<const float4*>(lds[cur] + 32 * L::STRIDE + c32 * 16);
+        const float ckA = cA * q.x, ckB = cB * q.x;
+        floatx16 dA = Op::mma(a[0], bv[0], GA);
+        floatx16 dB = Op::mma(a[0], bv[0], GB);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) {
+            dA = Op::mma(a[s], bv[s], dA);
+            dB = Op::mma(a[s], bv[s], dB);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            accA[r] = fmaf(q.y, __builtin_amdgcn_exp2f(fmaf(dA[r], cA, ckA)), accA[r]);
+            accB[r] = fmaf(q.z, __builtin_amdgcn_exp2f(fmaf(dB[r], cB, ckB)), accB[r]);
+        }
+        if (more) tile_store<T, KP>(lds[cur ^ 1], pf, spf);
+        __syncthreads();
+    }
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) {
+            accA[r] += __shfl_xor(accA[r], o, 64);
+            accB[r] += __shfl_xor(accB[r], o, 64);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t j = j0 + mfma_row(r, hf);
+        if (c32 == r && j < kc.m) cpart[(int64_t)p * kc.m + j] = make_double2(accA[r], accB[r]);
+    }
+}
+
+// FP64 matrix-core sweeps with LDS-shared tiles of 16 points (see the LDS-shared
+// half-precision sweeps above; the 16x16x4 FP64 layout is described with mma64).
+template <int KP>
+struct LdsTile64 {
+    static constexpr int ROW_BYTES = KP * 8;
+    static constexpr int STRIDE = ROW_BYTES + 16;
+    static constexpr int TILE_BYTES = 16 * ROW_BYTES;
+    static constexpr int CHUNKS = TILE_BYTES / 16;
+    static constexpr int PER_THREAD = (CHUNKS + BLOCK - 1) / BLOCK;
+    static constexpr int BUF = 16 * STRIDE + 16 * 16;
+};
+
+template <int KP>
+__device__ __forceinline__ void tile64_fetch(const double* __restrict__ src, int64_t row0, const void* __restrict__ scal,
+                                             int scal_bytes, int64_t scal_rows, int4 (&buf)[LdsTile64<KP>::PER_THREAD],
+                                             int4& sbuf) {
+    using L = LdsTile64<KP>;
+    const char* base = reinterpret_cast<const char*>(src + row0 * KP);
+#pragma unroll
+    for (int q = 0; q < L::PER_THREAD; ++q) {
+        const int c = threadIdx.x + q * BLOCK;
+        if (c < L::CHUNKS) buf[q] = *reinterpret_cast<const int4*>(base + (int64_t)c * 16);
+    }
+    if (threadIdx.x < 16) {
+        const int64_t row = row0 + threadIdx.x;
+        sbuf = make_int4(0, 0, 0, 0);
+        if (row < scal_rows) sbuf = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(scal) + row * scal_bytes);
+    }
+}
+
+template <int KP>
+__device__ __forceinline__ void tile64_store(char* lds, const int4 (&buf)[LdsTile64<KP>::PER_THREAD], const int4& sbuf) {
+    using L = LdsTile64<KP>;
+#pragma unroll
+    for (int q = 0; q < L::PER_THREAD; ++q) {
+        const int c = threadIdx.x + q * BLOCK;
+        if (c < L::CHUNKS) {
+            const int row = (c * 16) / L::ROW_BYTES;
+            const int off = (c * 16) % L::ROW_BYTES;
+            *reinterpret_cast<int4*>(lds + row * L::STRIDE + off) = buf[q];
+        }
+    }
+    if (threadIdx.x < 16) *reinterpret_cast<int4*>(lds + 16 * L::STRIDE + threadIdx.x * 16) = sbuf;
+}
+
+template <int KP>
+__global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                              const double* __restrict__ xop,
+                                                              const double* __restrict__ yop,
+                                                              const double2* __restrict__ gtab2,
+                                                              const double* __restrict__ H,
+                                                              double2* __restrict__ part, int64_t tiles_per_split,
+                                                              int P, int64_t m_tiles, int64_t n_waves) {
+    using L = LdsTile64<KP>;
+    constexpr int NS = KP / 4;
+    __shared__ __align__(16) char lds[2][L::BUF];
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, c16 = lane & 15;
+    const int64_t b = blockIdx.x;
+    const int p = (int)(b % P);
+    const int64_t rw = (b / P) * 4 + (threadIdx.x >> 6);
+    const bool active = rw < n_waves;
+    const int64_t i0 = (active ? rw : 0) * 16;
+    double a[NS];
+    {
+        const double* ap = xop + (i0 + c16) * KP + grp * NS;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = ap[s];
+    }
+    doublex4 hv;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t ii = i0 + 4 * q + grp;
+        hv[q] = H[ii < kc.n ? ii : kc.n - 1];
+    }
+    float accA[4] = {0.f, 0.f, 0.f, 0.f}, accB[4] = {0.f, 0.f, 0.f, 0.f};
+    double sumA[4] = {0.0, 0.0, 0.0, 0.0}, sumB[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t jt0 = (int64_t)p * tiles_per_split;
+    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
+    int4 pf[L::PER_THREAD];
+    int4 spf = make_int4(0, 0, 0, 0);
+    if (jt0 < jt1) {
+        tile64_fetch<KP>(yop, jt0 * 16, g, 16, kc.m, pf, spf);
+        tile64_store<KP>(lds[0], pf, spf);
+    }
+    __syncthreads();
+    int cnt = 0;
+    for (int64_t jt = jt0; jt < jt1; ++jt) {
+        const int cur = (int)((jt - jt0) & 1);
+        const bool more = jt + 1 < jt1;
+        if (more) tile64_fetch<KP>(yop, (jt + 1) * 16, g, 16, kc.m, pf, spf);
+        const double* bp = reinterpret_cast<const double*>(lds[cur] + c16 * L::STRIDE) + grp * NS;
+        double bv[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
+        const int64_t j = jt * 16 + c16;
+        double2 gg = *reinterpret_cast<const double2*>(lds[cur] + 16 * L::STRIDE + c16 * 16);
+        if (j >= kc.m) gg = make_double2(-1e300, -1e300);
+        doublex4 d = mma64(a[0], bv[0], hv);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            accA[q] += fexp2(fma(d[q], cA, gg.x));
+            accB[q] += fexp2(fma(d[q], cB, gg.y));
+        }
+        if (++cnt == 8) {   // carry in FP64 every 8 terms
+            cnt = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                sumA[q] += (double)accA[q];
+                sumB[q] += (double)accB[q];
+                accA[q] = accB[q] = 0.f;
+            }
+        }
+        if (more) tile64_store<KP>(lds[cur ^ 1], pf, spf);
+        __syncthreads();
+    }
+    if (!active) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        sumA[q] += (double)accA[q];
+        sumB[q] += (double)accB[q];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            sumA[q] += __shfl_xor(sumA[q], o, 64);
+            sumB[q] += __shfl_xor(sumB[q], o, 64);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t row = i0 + 4 * q + grp;
+        if (c16 == q && row < kc.n) part[(int64_t)p * kc.n + row] = make_double2(sumA[q], sumB[q]);
+    }
+}
+
+template <int KP>
+__global__ __launch_bounds__(BLOCK) void col_sweep_mfma64_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                              const double* __restrict__ xop,
+                                                              const double* __restrict__ yop,
+                                                              const double2* __restrict__ gtab2,
+                                                              const RowVar* __restrict__ rowvar,
+                                                              double2* __restrict__ cpart, int64_t tiles_per_split,
+                                                              int P, int64_t n_tiles, int64_t m_waves) {
+    using L = LdsTile64<KP>;
+    constexpr int NS = KP / 4;
+    __shared__ __align__(16) char lds[2][L::BUF];
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, c16 = lane & 15;
+    const int64_t b = blockIdx.x;
+    const int p = (int)(b % P);
+    const int64_t cw = (b / P) * 4 + (threadIdx.x >> 6);
+    const bool active = cw < m_waves;
+    const int64_t j = (active ? cw : 0) * 16 + c16;
+    // B operand: the wave's 16 columns y_j (lane c16 holds column j of D)
+    double bv[NS];
+    {
+        const double* bp = yop + j * KP + grp * NS;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
+    }
+    double gA = -1e300, gB = -1e300;
+    if (j < kc.m) {
+        const double2 gg = gtab2[(t & 1) * kc.m + j];
+        gA = gg.x;
+        gB = gg.y;
+    }
+    float accA = 0.f, accB = 0.f;
+    double sumA = 0.0, sumB = 0.0;
+    const int64_t it0 = (int64_t)p * tiles_per_split;
+    const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
+    int4 pf[L::PER_THREAD];
+    int4 spf = make_int4(0, 0, 0, 0);
+    if (it0 < it1) {
+        tile64_fetch<KP>(xop, it0 * 16, rowvar, 16, kc.n, pf, spf);
+        tile64_store<KP>(lds[0], pf, spf);
+    }
+    __syncthreads();
+    for (int64_t it = it0; it < it1; ++it) {
+        const int cur = (int)((it - it0) & 1);
+        const bool more = it + 1 < it1;
+        if (more) tile64_fetch<KP>(xop, (it + 1) * 16, rowvar, 16, kc.n, pf, spf);
+        const double* ap = reinterpret_cast<const double*>(lds[cur] + c16 * L::STRIDE) + grp * NS;
+        double a[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = ap[s];
+        doublex4 kv;
+        float wa[4], wb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * q + grp;
+            const RowVar rv = *reinterpret_cast<const RowVar*>(lds[cur] + 16 * L::STRIDE + r * 16);
+            const bool valid = it * 16 + r < kc.n;
+            kv[q] = valid ? rv.k : -1e300;
+            wa[q] = valid ? rv.wA : 0.f;
+            wb[q] = valid ? rv.wB : 0.f;
+        }
+        doublex4 d = mma64(a[0], bv[0], kv);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            accA = fmaf(wa[q], fexp2(fma(d[q], cA, gA)), accA);
+            accB = fmaf(wb[q], fexp2(fma(d[q], cB, gB)), accB);
+        }
+        if (((it - it0) & 1) == 1) {
+            sumA += (double)accA;
+            sumB += (double)accB;
+            accA = accB = 0.f;
+        }
+        if (more) tile64_store<KP>(lds[cur ^ 1], pf, spf);
+        __syncthreads();
+    }
+    if (!active) return;
+    sumA += (double)accA;
+    sumB += (double)accB;
+    sumA += __shfl_xor(sumA, 16, 64);
+    sumB += __shfl_xor(sumB, 16, 64);
+    sumA += __shfl_xor(sumA, 32, 64);
+    sumB += __shfl_xor(sumB, 32, 64);
+    if (grp == 0 && j < kc.m) cpart[(int64_t)p * kc.m + j] = make_double2(sumA, sumB);
 }
 
 }  // namespace lampk

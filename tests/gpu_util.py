@@ -21,13 +21,24 @@ def gpu_problem(wl, s):
     return P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=s, cost_norm=1.0)
 
 
-def rel_inf(a, ref):
-    """Norm-wise relative error ||a - ref||_inf / ||ref||_inf (exact zero reference: absolute)."""
+def rel_inf(a, ref, floor=0.0):
+    """Norm-wise relative error ||a - ref||_inf / max(||ref||_inf, floor)."""
     a = np.asarray(a, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
-    den = np.max(np.abs(ref))
+    den = max(float(np.max(np.abs(ref))), floor)
     num = np.max(np.abs(a - ref))
     return num / den if den > 0 else num
+
+
+# Duals live in [-1, 1] (theta is clipped to the radius tanh(beta/2) = 0.50052).  Their FP32
+# error is absolute (~1e-7: kappa (col_j error)/c^alpha_j with col_j carrying the ~1e-7
+# relative error of FP32 exponentials), so "relative" is taken against the larger of the
+# reference's norm and the clip radius.
+DUAL_SCALE = 0.5
+
+
+def rel_dual(a, ref):
+    return rel_inf(a, ref, DUAL_SCALE)
 
 
 def rel_l1(a, ref):
