@@ -131,8 +131,52 @@ def time_to_tol(P, prob, wl, form, tol, max_iter):
             "final_res": rep["final_res"]}
 
 
+def batch_mode(args):
+    """The 64-problem batch (n, m log-uniform in [512, 8192], d in {2, 3, 16}): batched solve to
+    the tolerance against the same problems solved one after another."""
+    import torch
+
+    import paper_2511_11359_amd as P
+    from paper_2511_11359_amd import workloads as W
+    dev = torch.device("cuda:0")
+    wls = [W.batch_problem(p) for p in range(args.batch_count)]
+    probs = [P.Problem(w.x, w.y, w.r, w.c, device=dev) for w in wls]
+    pairs = sum(w.n * w.m for w in wls)
+    params = P.make_params(eta=1e-3, tol=args.tol, max_iter=args.max_iter, check_every=32)
+    P.solve_batched(probs, P.make_params(eta=1e-3, max_iter=4, check_every=2))   # tune + warm up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    states, reps, status = P.solve_batched(probs, params)
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    iters = [r["iters"] for r in reps]
+    evals_b = sum(4.0 * w.n * w.m * r["iters"] for w, r in zip(wls, reps))
+    log(f"batched: {args.batch_count} problems, {dt_b:.3f} s, iterations min/max "
+        f"{min(iters)}/{max(iters)}, converged {sum(r['converged'] for r in reps)}")
+    t0 = time.perf_counter()
+    seq = []
+    for prob in probs:
+        _, rep, _ = P.solve(prob, params)
+        seq.append(rep)
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    log(f"sequential: {dt_s:.3f} s")
+    out = {"metric": "pair-evals/s", "value": evals_b / dt_b, "unit": "pair-evals/s", "n_gpus": 1,
+           "steps": max(iters), "warmup": 4, "ms_per_step": dt_b * 1e3 / max(1, max(iters)),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64/f32",
+           "data": "synthetic",
+           "config": {"workload": f"batch{args.batch_count}", "pairs_per_iteration": 4 * pairs,
+                      "eta": 1e-3, "tol": args.tol, "form": "fp32"},
+           "batched_seconds": dt_b, "sequential_seconds": dt_s,
+           "converged": int(sum(r["converged"] for r in reps)),
+           "iterations": {"min": min(iters), "max": max(iters)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", default="single", choices=["single", "batch"])
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=4)
@@ -154,6 +198,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "DESIGN.md describes how the path would shard", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch":
+        batch_mode(args)
+        return
 
     import torch
 

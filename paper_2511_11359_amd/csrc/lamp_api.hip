@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <vector>
 
 #include "../../include/lamp.h"
@@ -43,7 +44,19 @@ lamp_status fail(lamp_status st, const char* fmt, ...) {
     } while (0)
 
 constexpr int TAB = 4096;              // schedule entries per epoch
-constexpr int64_t TARGET_BLOCKS = 1024;  // 256 CUs x 4 blocks of 4 waves
+
+// Sweep blocks in flight per launch of the vector-ALU sweeps: 256 CUs x 8 blocks of
+// 4 waves keeps 8 waves per SIMD to hide the scalar-load and transcendental latency.
+// LAMP_TARGET_BLOCKS overrides it (launch-shape experiments).
+int64_t target_blocks_default() {
+    static const int64_t v = [] {
+        const char* e = std::getenv("LAMP_TARGET_BLOCKS");
+        const long long x = e ? std::atoll(e) : 0;
+        return (int64_t)(x > 0 ? x : 2048);
+    }();
+    return v;
+}
+#define TARGET_BLOCKS (target_blocks_default())
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }

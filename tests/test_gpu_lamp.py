@@ -326,3 +326,19 @@ def test_batched_solve_matches_single_solves():
     st_or, _ = OL.lamp_dense(C, wl.r, wl.c, OL.Params(eta=1e-2), 3000, 1.0, tol=2e-3, trace=False)
     assert states[3].t == st_or.t
     assert rel_dual(to_np(states[3].nu), st_or.nu) <= DUAL_TOL
+
+
+def test_autograd_function_gradient():
+    """LampOT: the transport cost of the solved iterate as a function of x; backward gives the
+    envelope gradient, which matches the oracle's at the oracle's own iterate (same iteration
+    count, so the same state up to the parity tolerance)."""
+    wl = W.random_small(120, 90, 3, seed=51, eta=1e-2)
+    x, y, s, C = oracle_problem(wl)
+    xt = torch.tensor(wl.x, device="cuda", requires_grad=True)
+    cost = P.LampOT.apply(xt, torch.tensor(wl.y, device="cuda"), wl.r, wl.c, 1e-2, 0.0, 80, s)
+    cost.backward()
+    st_or, _ = OL.lamp_dense(C, wl.r, wl.c, OL.Params(eta=1e-2), 80, 1.0, trace=False)
+    g_or = OL.envelope_grad_x(x, y, wl.r, s, st_or.nu, st_or.lam, 1.0)
+    cost_or = float(np.sum(C * OL.plan(C, wl.r, st_or, 1.0)))
+    assert float(cost) == pytest.approx(cost_or, rel=1e-5)
+    assert rel_inf(to_np(xt.grad), g_or) <= 1e-4
