@@ -125,10 +125,11 @@ def time_to_tol(P, prob, wl, form, tol, max_iter):
     st, rep, status = P.solve(prob, params)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    cert = P.certificate(prob, P.make_params(eta=wl.eta, precision=form), st)
     log(f"{form}: time to ||col - c||_1 <= {tol}: {rep['iters']} iterations, {dt:.2f} s, "
-        f"converged={rep['converged']}, final residual {rep['final_res']:.3e}")
+        f"converged={rep['converged']}, final residual {rep['final_res']:.3e}, cost {cert['cost']:.9e}")
     return {"tol": tol, "iters": rep["iters"], "seconds": dt, "converged": bool(rep["converged"]),
-            "final_res": rep["final_res"]}
+            "final_res": rep["final_res"], "cost": cert["cost"], "gap": cert["gap"]}
 
 
 def batch_mode(args):
@@ -186,7 +187,8 @@ def main():
     ap.add_argument("--compare", default="fp32_mfma,fp32",
                     help="other forms measured beside the primary one (comma list, '' for none)")
     ap.add_argument("--compare-steps", type=int, default=10)
-    ap.add_argument("--time-to-tol", action="store_true")
+    ap.add_argument("--time-to-tol", default="bf16_mfma,fp32",
+                    help="forms solved from the start to the tolerance (comma list, '' for none)")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true")
@@ -226,8 +228,9 @@ def main():
         others[form] = measure_form(P, prob, wl, form, args.compare_steps, 2, max(2, args.reps // 2))
         others[form]["roofline"] = roofline(wl, form, others[form])
     ttt = None
-    if args.time_to_tol:
-        ttt = {args.precision: time_to_tol(P, prob, wl, args.precision, args.tol, args.max_iter)}
+    forms_ttt = [f for f in args.time_to_tol.split(",") if f]
+    if forms_ttt:
+        ttt = {f: time_to_tol(P, prob, wl, f, args.tol, args.max_iter) for f in forms_ttt}
     cpu = None if args.no_cpu else cpu_baseline(wl, s)
 
     out = {

@@ -74,8 +74,9 @@ typedef struct {
  * testing": alpha = 0.01, beta = 1.1, tau1 = tau2 = 1/(2||C||_inf)).
  *   eta >= 0: entropic regularisation; tau1 * eta <= 1 is required
  *      (Lemma primal_md_eq_dual_avg, Proposition equivalence).
- *   tol: stop when ||col(X^t) - c||_1 <= tol (row(X^t) = r by construction,
- *      eq:row_feasible); 0 runs exactly max_iter iterations.
+ *   tol: stop at the first t >= 1 with ||col(X^t) - c||_1 <= tol (row(X^t) = r by
+ *      construction, eq:row_feasible; t = 0, the product coupling, is not tested);
+ *      0 runs exactly max_iter iterations.
  *   alpha, beta, tau1, tau2: <= 0 selects the default.
  *   check_every: iterations per host check of the stopping flag in lamp_solve
  *      (<= 0: 64).  The tolerance itself is tested on the device every iteration. */

@@ -223,9 +223,11 @@ def lamp_dense(C: np.ndarray, r: np.ndarray, c: np.ndarray, prm: Params, T: int,
     """Run Algorithm 2 for at most T iterations.
 
     Stopping reading (the paper stops on ||col(X^t) - c||_1 + ||row(X^t) - r||_1,
-    Appendix E): if ``tol`` is given, before iteration t the residual of X^t is
+    Appendix E): if ``tol`` is given, before iteration t >= 1 the residual of X^t is
     measured and, if it is <= tol, the run stops and returns the state holding
-    nu^t, i.e. the iterate that met the tolerance.
+    nu^t, i.e. the iterate that met the tolerance.  The starting point t = 0 is not
+    tested: with eta_0 = infinity it is the product coupling r (1/m)^T, which is
+    feasible whenever c is uniform without being an iterate of the method.
 
     Returns (state, trace).  ``state.lam`` and ``state.nu`` define
     X^t = diag(r) p^{eta_t}(nu^t) (Proposition infeas_bound).
@@ -235,7 +237,7 @@ def lamp_dense(C: np.ndarray, r: np.ndarray, c: np.ndarray, prm: Params, T: int,
     st = lamp_init(C.shape[1]) if state is None else state
     tr = LampTrace() if trace else None
     for _ in range(T):
-        if tol is not None:
+        if tol is not None and st.t >= 1:
             X = plan(C, r, st, cnorm)
             if residuals(X, r, c)[2] <= tol:
                 break

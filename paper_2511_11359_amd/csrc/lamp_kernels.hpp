@@ -681,7 +681,8 @@ __device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched,
         if (ctrl->err) {
             ctrl->done = 1;
             ctrl->t_done = t;
-        } else if (ctrl->tol > 0.0 && tot <= ctrl->tol) {
+        } else if (ctrl->tol > 0.0 && t >= 1 && tot <= ctrl->tol) {
+            // t = 0 is the product coupling (eta_0 = infinity), not an iterate: never tested
             ctrl->done = 1;
             ctrl->t_done = t;
         } else {

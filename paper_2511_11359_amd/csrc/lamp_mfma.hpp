@@ -64,9 +64,9 @@ __global__ void prep_operands(const double* __restrict__ src, int64_t cnt, int d
     if (idx >= cnt_pad * KP) return;
     int64_t i = idx / KP;
     int k = (int)(idx % KP);
-    // double -> FP32 -> T: one fixed, documented rounding path for every operand type
-    const float v = (i < cnt && k < d) ? (float)src[i * d + k] : 0.f;
-    out[idx] = (T)v;
+    // one round-to-nearest-even of the FP64 centred coordinate to T (the compiler lowers
+    // FP64 -> BF16/FP16 as a single rounding; a cast through FP32 would be folded into it)
+    out[idx] = (i < cnt && k < d) ? (T)src[i * d + k] : (T)0.f;
 }
 
 __global__ void pad_rows(int64_t n, int64_t n_pad, float* __restrict__ kf, float* __restrict__ wa,

@@ -49,3 +49,42 @@ def rel_l1(a, ref):
 
 def to_np(t):
     return t.detach().cpu().numpy()
+
+
+# (significant bits, smallest normal exponent) of the operand types of the matrix-core forms
+_FORMATS = {"float32": (24, -126), "bfloat16": (8, -126), "float16": (11, -14)}
+
+
+def round_to_type(a, name):
+    """Round FP64 values once, to nearest with ties to even, onto the grid of the named
+    binary format (subnormals included): the rounding the library applies to each centred
+    coordinate when it writes the matrix-core operands.  Written out from the definition of
+    the format (p significant bits, exponent floor emin): the quantum of |a| in
+    [2^e, 2^(e+1)) is 2^(max(e, emin) - p + 1), and a / quantum is exact in FP64."""
+    p, emin = _FORMATS[name]
+    a = np.asarray(a, dtype=np.float64)
+    _, e = np.frexp(a)                      # a = f 2^e with 1/2 <= |f| < 1
+    q = np.ldexp(1.0, np.maximum(e - 1, emin) - (p - 1))
+    return np.rint(a / q) * q
+
+
+def fp32_trajectory_allowance(C, r, c, prm, T, cnorm=1.0, eps=2.0 ** -24, seeds=(0, 1)):
+    """How far the oracle's duals after T iterations move when every column marginal it
+    computes carries an independent relative perturbation of size eps (half an FP32 ulp,
+    the least any FP32 evaluation of the marginals carries).  The dual update adds
+    kappa (col - c) / c^alpha to atanh(theta) every iteration, so such errors accumulate
+    along a trajectory; a multi-iteration comparison allows for it.  Returns the largest
+    rel_dual deviation of theta or nu over the seeded perturbations."""
+    ref, _ = OL.lamp_dense(C, r, c, prm, T, cnorm, trace=False)
+    orig = OL.col_r
+    worst = 0.0
+    try:
+        for sd in seeds:
+            rng = np.random.default_rng(sd)
+            OL.col_r = lambda p, rr, rng=rng: orig(p, rr) * (1.0 + eps * rng.standard_normal(p.shape[1]))
+            st, _ = OL.lamp_dense(C, r, c, prm, T, cnorm, trace=False)
+            OL.col_r = orig
+            worst = max(worst, rel_dual(st.theta, ref.theta), rel_dual(st.nu, ref.nu))
+    finally:
+        OL.col_r = orig
+    return worst

@@ -17,7 +17,7 @@ import pytest
 from oracle import lamp as OL
 from oracle import stream as OS
 from paper_2511_11359_amd import workloads as W
-from tests.gpu_util import rel_inf, to_np
+from tests.gpu_util import rel_inf, round_to_type, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,8 @@ def _check_step(wl, key, precision, t, rows, logz_atol, rounded=None):
                          f"sum colB-1 {cb.sum() - 1:.2e} res {res:.3e}")
     assert ea <= logz_atol and eb <= logz_atol
     assert abs(ca.sum() - 1.0) <= 1e-6 and abs(cb.sum() - 1.0) <= 1e-6
-    assert np.all(ca > 0) and np.all(cb > 0)
+    # marginals are non-negative; a column whose every term lies below FP32's range reads 0
+    assert np.all(ca >= 0) and np.all(cb >= 0)
     assert np.all(np.abs(to_np(st.theta)) < 1) and np.all(np.abs(to_np(st.nu)) < 1)
     return prob, st
 
@@ -111,8 +112,8 @@ def test_gmm64_65536_mfma_step(form, dtype):
     y = wl.y.astype(np.float64)
     mu = 0.5 * (x[0] + y[0])
     xc, yc = x - mu, y - mu
-    xr = torch.tensor(xc).to(dtype).to(torch.float64).numpy()
-    yr = torch.tensor(yc).to(dtype).to(torch.float64).numpy()
+    xr = round_to_type(xc, str(dtype).replace("torch.", ""))
+    yr = round_to_type(yc, str(dtype).replace("torch.", ""))
     # the rounded dot products with the unrounded norms are the cost of points whose
     # difference form reproduces them: feed the oracle the exact cost through an offset
     # representation, C_ij = s (|xc_i|^2 + |yc_j|^2 - 2 xr_i . yr_j)

@@ -14,7 +14,8 @@ import pytest
 from oracle import lamp as OL
 from oracle import stream as OS
 from paper_2511_11359_amd import workloads as W
-from tests.gpu_util import gpu_problem, oracle_problem, rel_dual, rel_inf, rel_l1, to_np
+from tests.gpu_util import (fp32_trajectory_allowance, gpu_problem, oracle_problem, rel_dual, rel_inf,
+                            rel_l1, round_to_type, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -149,8 +150,12 @@ def test_solve_stops_at_tolerance_and_resume():
     assert rep["final_res"] <= 5e-3
     X = OL.plan(C, wl.r, st_or, 1.0)
     assert rep["final_res"] == pytest.approx(OL.residuals(X, wl.r, wl.c)[1], rel=1e-5)
-    assert rel_dual(to_np(st.nu), st_or.nu) <= DUAL_TOL
-    assert rel_dual(to_np(st.theta), st_or.theta) <= DUAL_TOL
+    # st.t iterations accumulate FP32-level marginal errors in the duals: compare against
+    # the oracle's own spread under half-ulp perturbations of its marginals (twice that)
+    traj = max(DUAL_TOL, 2.0 * fp32_trajectory_allowance(C, wl.r, wl.c, OL.Params(eta=wl.eta), st_or.t))
+    _say("trajectory allowance", traj)
+    assert rel_dual(to_np(st.nu), st_or.nu) <= traj
+    assert rel_dual(to_np(st.theta), st_or.theta) <= traj
     st2, rep2, _ = P.solve(prob, params)
     assert st2.t == st.t and torch.equal(st2.nu, st.nu) and torch.equal(st2.theta, st.theta)
     # checkpoint / resume: 60 + 60 iterations against 120
@@ -163,6 +168,17 @@ def test_solve_stops_at_tolerance_and_resume():
     # the FP32 rounding of the exponent arguments: equal to the parity tolerance
     assert rel_dual(to_np(a.nu), to_np(b.nu)) <= DUAL_TOL
     assert rel_dual(to_np(a.theta), to_np(b.theta)) <= DUAL_TOL
+
+
+def test_uniform_marginals_stop_after_first_iterate():
+    """With uniform c the starting coupling is feasible; the tolerance is tested from t = 1 on,
+    so the run stops where the oracle's does, after at least one iteration."""
+    wl = W.random_small(300, 256, 2, seed=11, uniform=True, eta=1e-2)
+    x, y, s, C = oracle_problem(wl)
+    st, rep, status = P.solve(gpu_problem(wl, s), P.make_params(eta=wl.eta, tol=1e-3, max_iter=5000))
+    st_or, _ = OL.lamp_dense(C, wl.r, wl.c, OL.Params(eta=wl.eta), 5000, 1.0, tol=1e-3, trace=False)
+    _say("uniform marginals: gpu stops at", st.t, "oracle at", st_or.t)
+    assert status == 0 and st.t == st_or.t >= 1
 
 
 def test_cost_scale_matches_oracle():
@@ -238,9 +254,10 @@ def _rounded_cost(wl, s, dtype):
     y = wl.y.astype(np.float64)
     mu = 0.5 * (x[0] + y[0])
     xc, yc = x - mu, y - mu
-    # the library rounds FP64 -> FP32 -> operand type
-    xr = torch.tensor(xc).to(torch.float32).to(dtype).to(torch.float64).numpy()
-    yr = torch.tensor(yc).to(torch.float32).to(dtype).to(torch.float64).numpy()
+    # the library rounds each FP64 centred coordinate once, to nearest even, to the operand type
+    name = str(dtype).replace("torch.", "")
+    xr = round_to_type(xc, name)
+    yr = round_to_type(yc, name)
     nx = np.sum(xc * xc, axis=1)
     ny = np.sum(yc * yc, axis=1)
     return s * (nx[:, None] + ny[None, :] - 2.0 * xr @ yr.T)
@@ -278,6 +295,9 @@ def test_mfma_step_matches_oracle_on_rounded_cost(form, dtype, shape):
         theta_bar=(to_np(tr["theta_bar"]), tr_or.theta_bar[0]),
         theta_hat=(to_np(tr["theta_hat"]), tr_or.theta_hat[0]),
         theta=(to_np(st.theta), st_next.theta)).items()}
+    elz = max(np.max(np.abs(to_np(tr["log_za"]) - tr_or.logZA[0])),
+              np.max(np.abs(to_np(tr["log_zb"]) - tr_or.logZB[0])))
+    _say(form, wl.name, f"max row log-normaliser err {elz:.2e}")
     _say(form, wl.name, f"max column rel err {ecol:.2e}",
          {k: f"{v:.2f}" for k, v in dual_err.items()})
     assert ecol <= 2e-5

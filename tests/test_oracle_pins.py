@@ -376,3 +376,19 @@ def test_cmax_c_routine_matches_numpy():
     from oracle import cmax
     wl = W.random_small(300, 211, 5, seed=16)
     assert cmax.max_sqdist(wl.x, wl.y) == L.max_sqdist(wl.x.astype(np.float64), wl.y.astype(np.float64))
+
+
+def test_tolerance_is_tested_from_the_first_iterate():
+    """Appendix E stopping rule, reading for t = 0: with uniform c the product coupling X^0 is
+    exactly feasible, so a test at t = 0 would end every such run before it starts; the run
+    instead stops at the first t >= 1 whose residual meets the tolerance."""
+    wl = W.random_small(40, 32, 2, seed=3, uniform=True, eta=1e-2)
+    x, y = wl.x.astype(np.float64), wl.y.astype(np.float64)
+    C = L.sqeuclid_cost(x, y, 1.0 / L.max_sqdist(x, y))
+    st0 = L.lamp_init(wl.m)
+    assert L.residuals(L.plan(C, wl.r, st0, 1.0), wl.r, wl.c)[2] <= 1e-15
+    st, _ = L.lamp_dense(C, wl.r, wl.c, L.Params(eta=wl.eta), 400, 1.0, tol=1e-3, trace=False)
+    assert st.t >= 1
+    assert L.residuals(L.plan(C, wl.r, st, 1.0), wl.r, wl.c)[2] <= 1e-3
+    prev = L.lamp_dense(C, wl.r, wl.c, L.Params(eta=wl.eta), st.t - 1, 1.0, trace=False)[0]
+    assert st.t == 1 or L.residuals(L.plan(C, wl.r, prev, 1.0), wl.r, wl.c)[2] > 1e-3
