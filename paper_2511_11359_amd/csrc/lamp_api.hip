@@ -583,9 +583,54 @@ double fill_sched(std::vector<Sched>& tab, int cnt, double lam0, double tau1, do
     return l0;
 }
 
-// Exact offsets for the first row sweep of a call: h_i = min_j(-g^B_j/cfac^B - x~.y~).
+template <typename T, int KP>
+void extreme_mfma(const Layout& L, Consts kc, void* ws, const Ctrl* ctrl, const Sched* sched, hipStream_t st) {
+    const int64_t n_waves = L.n_pad / 32;
+    dim3 g((unsigned)(cdiv(n_waves, 4) * L.P_rm));
+    hipLaunchKernelGGL((row_extreme_mfma_lds<T, KP>), g, dim3(BLOCK), 0, st, ctrl, sched, kc, at<T>(ws, L.xop),
+                       at<T>(ws, L.yop), at<float2>(ws, L.gtabf), L.m_pad, at<double>(ws, L.rpart), L.tps_r,
+                       (int)L.P_rm, L.m_pad / 32, n_waves);
+}
+
+void launch_extreme_mfma(const Layout& L, Consts kc, void* ws, const Ctrl* ctrl, const Sched* sched,
+                         hipStream_t st) {
+#define EX(T, K) \
+    extreme_mfma<T, K>(L, kc, ws, ctrl, sched, st); return;
+    if (L.prec == LAMP_FP32_MFMA) {
+        switch (L.KP) {
+            case 4: EX(float, 4)
+            case 16: EX(float, 16)
+            case 64: EX(float, 64)
+            default: EX(float, 128)
+        }
+    } else if (L.prec == LAMP_BF16_MFMA) {
+        switch (L.KP) {
+            case 16: EX(__bf16, 16)
+            case 64: EX(__bf16, 64)
+            default: EX(__bf16, 128)
+        }
+    } else {
+        switch (L.KP) {
+            case 16: EX(_Float16, 16)
+            case 64: EX(_Float16, 64)
+            default: EX(_Float16, 128)
+        }
+    }
+#undef EX
+}
+
+// Offsets for the first row sweep of a call: h_i = min_j(-g^B_j/cfac^B - x~.y~), exact in
+// FP64 for the FP64-argument form; for the matrix-core forms from their own operand copies
+// and FP32 arithmetic (an offset only has to keep the sums in range).
 void launch_offsets(const Layout& L, Consts kc, int d, void* ws, hipStream_t st, const Ctrl* ctrl = nullptr,
                     const Sched* sched = nullptr) {
+    if (is_mfma(L.prec)) {
+        launch_extreme_mfma(L, kc, ws, ctrl ? ctrl : at<Ctrl>(ws, L.ctrl), sched ? sched : at<Sched>(ws, L.sched),
+                            st);
+        hipLaunchKernelGGL(row_extreme_merge, grid1(kc.n), dim3(BLOCK), 0, st, kc, at<double>(ws, L.rpart),
+                           (int)L.P_rm, (const double*)nullptr, 0, at<double>(ws, L.H));
+        return;
+    }
     double* a = at<double>(ws, L.scratch);
     hipLaunchKernelGGL(offset_coeffs, grid1(kc.m), dim3(BLOCK), 0, st, ctrl ? ctrl : at<Ctrl>(ws, L.ctrl),
                        sched ? sched : at<Sched>(ws, L.sched), kc, at<double2>(ws, L.gtab), a);

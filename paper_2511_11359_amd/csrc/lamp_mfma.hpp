@@ -628,6 +628,15 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_mfma64(Consts kc, const dou
 // into LDS, double-buffered, instead of once per wave, which cuts the L2 traffic
 // of the streamed operand by 4.  LDS rows are padded by 16 bytes so that the 32
 // lanes reading 16-byte pieces of 32 different rows hit distinct banks.
+//
+// Two-stage pipeline per wave: while the exponentials of tile j are evaluated on
+// the vector ALU, the matrix core already computes the dot products of tile j+1
+// (its result is consumed one iteration later), and the global loads of tile j+2
+// are in flight.  At the top of iteration j, LDS buffer (j+1) mod 2 holds tile
+// j+1; tile j+2 goes into buffer j mod 2, whose last reader (the matrix-core
+// stage of the previous iteration) finished before the previous barrier.  The
+// loop body has no branches: past the end of the range the tile index is clamped
+// to the last tile, whose repeated load and dot products are discarded.
 // ---------------------------------------------------------------------------
 template <typename T, int KP>
 struct LdsTile {
@@ -637,44 +646,111 @@ struct LdsTile {
     static constexpr int CHUNKS = TILE_BYTES / 16;             // 16-byte pieces per tile
     static constexpr int PER_THREAD = (CHUNKS + BLOCK - 1) / BLOCK;
     static constexpr int BUF = 32 * STRIDE + 32 * 16;          // operand rows + 32 scalar slots
+    static_assert(PER_THREAD <= 4, "tile larger than the prefetch registers");
 };
 
-// Global -> registers part of a tile load (16-byte pieces, PER_THREAD per thread).
-template <typename T, int KP>
-__device__ __forceinline__ void tile_fetch(const T* __restrict__ src_rows, int64_t row0, const void* __restrict__ scal,
-                                           int scal_bytes, int4 (&buf)[LdsTile<T, KP>::PER_THREAD], int4& sbuf) {
-    using L = LdsTile<T, KP>;
-    const char* base = reinterpret_cast<const char*>(src_rows + row0 * KP);
-#pragma unroll
-    for (int q = 0; q < L::PER_THREAD; ++q) {
-        const int c = threadIdx.x + q * BLOCK;
-        if (c < L::CHUNKS) buf[q] = *reinterpret_cast<const int4*>(base + (int64_t)c * 16);
-    }
-    // per-point scalars: 32 entries of scal_bytes (8 or 16) bytes
-    if (threadIdx.x < 32) {
-        const char* sp = reinterpret_cast<const char*>(scal) + (row0 + threadIdx.x) * scal_bytes;
-        if (scal_bytes == 16) sbuf = *reinterpret_cast<const int4*>(sp);
-        else {
-            const int2 v = *reinterpret_cast<const int2*>(sp);
-            sbuf = make_int4(v.x, v.y, 0, 0);
-        }
+// Registers of one in-flight tile load: up to four 16-byte pieces per thread and one
+// per-point scalar slot.  Named members with compile-time access, so that the
+// prefetch stays in registers (an indexed array here ends up in scratch memory).
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+struct TileRegs {
+    i32x4 r0, r1, r2, r3, s;
+};
+
+template <int I>
+__device__ __forceinline__ i32x4& treg(TileRegs& t) {
+    if constexpr (I == 0) return t.r0;
+    else if constexpr (I == 1) return t.r1;
+    else if constexpr (I == 2) return t.r2;
+    else return t.r3;
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void unroll_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        unroll_for<I + 1, N>(f);
     }
 }
 
-// Registers -> LDS part of a tile load.
-template <typename T, int KP>
-__device__ __forceinline__ void tile_store(char* lds, const int4 (&buf)[LdsTile<T, KP>::PER_THREAD], const int4& sbuf) {
-    using L = LdsTile<T, KP>;
+// Scheduling fences of the pipelined loops.  loads_done(): every outstanding global
+// load has completed (issued once before a loop, so that the loop's own wait counts
+// track only its prefetch).  pin(): the value is computed at this point of the program,
+// so the exponentials of a tile stay ahead of the LDS store of the prefetched tile,
+// which must wait for its global loads.
+__device__ __forceinline__ void loads_done() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0); expcnt and lgkmcnt at their maxima (no wait)
+}
+
+template <int N>
+__device__ __forceinline__ void pin(float (&v)[N]) {
 #pragma unroll
-    for (int q = 0; q < L::PER_THREAD; ++q) {
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i]));
+    asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ void pin(float& a, float& b) {
+    asm volatile("" : "+v"(a), "+v"(b));
+    asm volatile("" ::: "memory");
+}
+
+// Global -> registers part of a tile load of ROWS points of ROW_BYTES bytes each
+// (16-byte pieces, PT per thread) and their SB-byte scalars (SB = 8 or 16).  Every
+// thread loads the scalar of point row0 + (thread mod ROWS), clamped to the last of
+// scal_rows entries: no branch, so no wait on these loads before the LDS store.
+// Consumers mask the scalars of points past the end themselves.
+template <int ROWS, int ROW_BYTES, int PT, int SB>
+__device__ __forceinline__ void fetch_tile(const char* __restrict__ base, const char* __restrict__ scal,
+                                           int64_t row0, int64_t scal_rows, TileRegs& R) {
+    constexpr int CHUNKS = ROWS * ROW_BYTES / 16;
+    unroll_for<0, PT>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
         const int c = threadIdx.x + q * BLOCK;
-        if (c < L::CHUNKS) {
-            const int row = (c * 16) / L::ROW_BYTES;
-            const int off = (c * 16) % L::ROW_BYTES;
-            *reinterpret_cast<int4*>(lds + row * L::STRIDE + off) = buf[q];
-        }
+        constexpr bool full = (q + 1) * BLOCK <= CHUNKS;   // every thread has a piece
+        if (full || c < CHUNKS) treg<q>(R) = *reinterpret_cast<const i32x4*>(base + (int64_t)c * 16);
+    });
+    const int64_t row = min(row0 + (int64_t)(threadIdx.x & (ROWS - 1)), scal_rows - 1);
+    const char* sp = scal + row * SB;
+    if constexpr (SB == 16) {
+        R.s = *reinterpret_cast<const i32x4*>(sp);
+    } else {
+        const i32x2 v = *reinterpret_cast<const i32x2*>(sp);
+        R.s = i32x4{v.x, v.y, 0, 0};
     }
-    if (threadIdx.x < 32) *reinterpret_cast<int4*>(lds + 32 * L::STRIDE + threadIdx.x * 16) = sbuf;
+}
+
+// Registers -> LDS part of a tile load (rows padded to STRIDE bytes, scalars after them).
+template <int ROWS, int ROW_BYTES, int STRIDE, int PT>
+__device__ __forceinline__ void store_tile(char* lds, TileRegs& R) {
+    constexpr int CHUNKS = ROWS * ROW_BYTES / 16;
+    unroll_for<0, PT>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const int c = threadIdx.x + q * BLOCK;
+        constexpr bool full = (q + 1) * BLOCK <= CHUNKS;
+        if (full || c < CHUNKS) {
+            const int row = (c * 16) / ROW_BYTES;
+            const int off = (c * 16) % ROW_BYTES;
+            *reinterpret_cast<i32x4*>(lds + row * STRIDE + off) = treg<q>(R);
+        }
+    });
+    // every thread writes its scalar; the BLOCK / ROWS threads of one slot write the same value
+    *reinterpret_cast<i32x4*>(lds + ROWS * STRIDE + (threadIdx.x & (ROWS - 1)) * 16) = R.s;
+}
+
+template <typename T, int KP, int SB>
+__device__ __forceinline__ void tile_fetch(const T* __restrict__ src_rows, int64_t row0, const void* __restrict__ scal,
+                                           int64_t scal_rows, TileRegs& R) {
+    using L = LdsTile<T, KP>;
+    fetch_tile<32, L::ROW_BYTES, L::PER_THREAD, SB>(reinterpret_cast<const char*>(src_rows + row0 * KP),
+                                                    reinterpret_cast<const char*>(scal), row0, scal_rows, R);
+}
+
+template <typename T, int KP>
+__device__ __forceinline__ void tile_store(char* lds, TileRegs& R) {
+    using L = LdsTile<T, KP>;
+    store_tile<32, L::ROW_BYTES, L::STRIDE, L::PER_THREAD>(lds, R);
 }
 
 // The operand vectors of lane (c32, hf) from an LDS tile.
@@ -686,6 +762,21 @@ __device__ __forceinline__ void tile_operands(const char* lds, int c32, int hf,
     const vec* p = reinterpret_cast<const vec*>(lds + c32 * L::STRIDE + hf * (L::ROW_BYTES / 2));
 #pragma unroll
     for (int s = 0; s < KP / MfmaOp<T>::KSTEP; ++s) v[s] = p[s];
+}
+
+// x~_i . y~_j + C for the 32 x 32 tile held in LDS (B operand) against the wave's rows (A).
+template <typename T, int KP>
+__device__ __forceinline__ floatx16 tile_dot(const char* lds, int c32, int hf,
+                                             const typename MfmaOp<T>::vec (&a)[KP / MfmaOp<T>::KSTEP],
+                                             floatx16 c) {
+    using Op = MfmaOp<T>;
+    constexpr int NS = KP / Op::KSTEP;
+    typename Op::vec bv[NS];
+    tile_operands<T, KP>(lds, c32, hf, bv);
+    floatx16 d = Op::mma(a[0], bv[0], c);
+#pragma unroll
+    for (int s = 1; s < NS; ++s) d = Op::mma(a[s], bv[s], d);
+    return d;
 }
 
 // Row sweep, LDS-shared column tiles.  Same arithmetic as row_sweep_mfma.
@@ -733,30 +824,37 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma_lds(const Ctrl* ctrl, co
 
     const int64_t jt0 = (int64_t)p * tiles_per_split;
     const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
-    int4 pf[L::PER_THREAD];
-    int4 spf = make_int4(0, 0, 0, 0);
+    TileRegs pf;
     if (jt0 < jt1) {
-        tile_fetch<T, KP>(yop, jt0 * 32, g, 8, pf, spf);
-        tile_store<T, KP>(lds[0], pf, spf);
-    }
-    __syncthreads();
-    for (int64_t jt = jt0; jt < jt1; ++jt) {
-        const int cur = (int)((jt - jt0) & 1);
-        const bool more = jt + 1 < jt1;
-        if (more) tile_fetch<T, KP>(yop, (jt + 1) * 32, g, 8, pf, spf);
-        vec bv[NS];
-        tile_operands<T, KP>(lds[cur], c32, hf, bv);
-        const float2 gg = *reinterpret_cast<const float2*>(lds[cur] + 32 * L::STRIDE + c32 * 16);
-        floatx16 d = Op::mma(a[0], bv[0], hv);
-#pragma unroll
-        for (int s = 1; s < NS; ++s) d = Op::mma(a[s], bv[s], d);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            accA[r] += __builtin_amdgcn_exp2f(fmaf(d[r], cA, gg.x));
-            accB[r] += __builtin_amdgcn_exp2f(fmaf(d[r], cB, gg.y));
-        }
-        if (more) tile_store<T, KP>(lds[cur ^ 1], pf, spf);
+        const int64_t jl = jt1 - 1;
+        // prologue: tile jt0 through buffer 0 into the matrix core, tile jt0 + 1 into buffer 1
+        tile_fetch<T, KP, 8>(yop, jt0 * 32, g, m_pad, pf);
+        tile_store<T, KP>(lds[0], pf);
         __syncthreads();
+        floatx16 dc = tile_dot<T, KP>(lds[0], c32, hf, a, hv);
+        float2 gc = *reinterpret_cast<const float2*>(lds[0] + 32 * L::STRIDE + c32 * 16);
+        tile_fetch<T, KP, 8>(yop, min(jt0 + 1, jl) * 32, g, m_pad, pf);
+        tile_store<T, KP>(lds[1], pf);
+        __syncthreads();
+        loads_done();
+#pragma clang loop unroll(disable)
+        for (int64_t jt = jt0; jt < jt1; ++jt) {
+            const int nxt = (int)((jt + 1 - jt0) & 1);
+            tile_fetch<T, KP, 8>(yop, min(jt + 2, jl) * 32, g, m_pad, pf);
+            const floatx16 dn = tile_dot<T, KP>(lds[nxt], c32, hf, a, hv);
+            const float2 gn = *reinterpret_cast<const float2*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                accA[r] += __builtin_amdgcn_exp2f(fmaf(dc[r], cA, gc.x));
+                accB[r] += __builtin_amdgcn_exp2f(fmaf(dc[r], cB, gc.y));
+            }
+            pin(accA);
+            pin(accB);
+            tile_store<T, KP>(lds[nxt ^ 1], pf);
+            __syncthreads();
+            dc = dn;
+            gc = gn;
+        }
     }
     if (!active) return;
 #pragma unroll
@@ -771,6 +869,75 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma_lds(const Ctrl* ctrl, co
     for (int r = 0; r < 16; ++r) {
         const int64_t row = i0 + mfma_row(r, hf);
         if (c32 == r && row < kc.n) part[(int64_t)p * kc.n + row] = make_double2(accA[r], accB[r]);
+    }
+}
+
+// Offsets of the matrix-core forms: part[p][i] = -max_j (c^B x~_i . y~_j + g^B_j) / c^B over
+// the column tiles of split p, from the same operand copies and the same FP32 arithmetic as
+// the row sweep, so that the largest B-half term of the next row sweep is 2^0 up to
+// rounding (the merge takes the minimum over splits).
+template <typename T, int KP>
+__global__ __launch_bounds__(BLOCK) void row_extreme_mfma_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                              const T* __restrict__ xop, const T* __restrict__ yop,
+                                                              const float2* __restrict__ gtabf, int64_t m_pad,
+                                                              double* __restrict__ part, int64_t tiles_per_split,
+                                                              int P, int64_t m_tiles, int64_t n_waves) {
+    using L = LdsTile<T, KP>;
+    using Op = MfmaOp<T>;
+    using vec = typename Op::vec;
+    constexpr int NS = KP / Op::KSTEP;
+    __shared__ __align__(16) char lds[2][L::BUF];
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
+    const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
+    const int lane = threadIdx.x & 63;
+    const int hf = lane >> 5, c32 = lane & 31;
+    const int64_t b = blockIdx.x;
+    const int p = (int)(b % P);
+    const int64_t rw = (b / P) * 4 + (threadIdx.x >> 6);
+    const bool active = rw < n_waves;
+    const int64_t i0 = (active ? rw : 0) * 32;
+    vec a[NS];
+    {
+        const vec* ap = reinterpret_cast<const vec*>(xop + (i0 + c32) * KP + hf * (KP / 2));
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = ap[s];
+    }
+    floatx16 zero;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) zero[r] = 0.f;
+    float mx[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) mx[r] = -__builtin_inff();
+    const int64_t jt0 = (int64_t)p * tiles_per_split;
+    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
+    TileRegs pf;
+    if (jt0 < jt1) {
+        tile_fetch<T, KP, 8>(yop, jt0 * 32, g, m_pad, pf);
+        tile_store<T, KP>(lds[0], pf);
+    }
+    __syncthreads();
+    for (int64_t jt = jt0; jt < jt1; ++jt) {
+        const int cur = (int)((jt - jt0) & 1);
+        if (jt + 1 < jt1) tile_fetch<T, KP, 8>(yop, (jt + 1) * 32, g, m_pad, pf);
+        const floatx16 d = tile_dot<T, KP>(lds[cur], c32, hf, a, zero);
+        const float2 gg = *reinterpret_cast<const float2*>(lds[cur] + 32 * L::STRIDE + c32 * 16);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mx[r] = fmaxf(mx[r], fmaf(d[r], cB, gg.y));
+        if (jt + 1 < jt1) tile_store<T, KP>(lds[cur ^ 1], pf);
+        __syncthreads();
+    }
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) mx[r] = fmaxf(mx[r], __shfl_xor(mx[r], o, 64));
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = i0 + mfma_row(r, hf);
+        if (c32 == r && row < kc.n) part[(int64_t)p * kc.n + row] = -(double)mx[r] / (double)cB;
     }
 }
 
@@ -820,35 +987,52 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
     for (int r = 0; r < 16; ++r) accA[r] = accB[r] = 0.f;
     const int64_t it0 = (int64_t)p * tiles_per_split;
     const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
-    int4 pf[L::PER_THREAD];
-    int4 spf = make_int4(0, 0, 0, 0);
+    const int64_t n_rows = n_tiles * 32;
+    TileRegs pf;
     if (it0 < it1) {
-        tile_fetch<T, KP>(xop, it0 * 32, rowq, 16, pf, spf);
-        tile_store<T, KP>(lds[0], pf, spf);
-    }
-    __syncthreads();
-    for (int64_t it = it0; it < it1; ++it) {
-        const int cur = (int)((it - it0) & 1);
-        const bool more = it + 1 < it1;
-        if (more) tile_fetch<T, KP>(xop, (it + 1) * 32, rowq, 16, pf, spf);
-        vec bv[NS];
-        tile_operands<T, KP>(lds[cur], c32, hf, bv);
-        const float4 q = *reinterpret_cast<const float4*>(lds[cur] + 32 * L::STRIDE + c32 * 16);
-        const float ckA = cA * q.x, ckB = cB * q.x;
-        floatx16 dA = Op::mma(a[0], bv[0], GA);
-        floatx16 dB = Op::mma(a[0], bv[0], GB);
+        const int64_t il = it1 - 1;
+        auto dots = [&](const char* buf, floatx16& dA, floatx16& dB) {
+            typename Op::vec bv[NS];
+            tile_operands<T, KP>(buf, c32, hf, bv);
+            dA = Op::mma(a[0], bv[0], GA);
+            dB = Op::mma(a[0], bv[0], GB);
 #pragma unroll
-        for (int s = 1; s < NS; ++s) {
-            dA = Op::mma(a[s], bv[s], dA);
-            dB = Op::mma(a[s], bv[s], dB);
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            accA[r] = fmaf(q.y, __builtin_amdgcn_exp2f(fmaf(dA[r], cA, ckA)), accA[r]);
-            accB[r] = fmaf(q.z, __builtin_amdgcn_exp2f(fmaf(dB[r], cB, ckB)), accB[r]);
-        }
-        if (more) tile_store<T, KP>(lds[cur ^ 1], pf, spf);
+            for (int s = 1; s < NS; ++s) {
+                dA = Op::mma(a[s], bv[s], dA);
+                dB = Op::mma(a[s], bv[s], dB);
+            }
+        };
+        tile_fetch<T, KP, 16>(xop, it0 * 32, rowq, n_rows, pf);
+        tile_store<T, KP>(lds[0], pf);
         __syncthreads();
+        floatx16 dcA, dcB;
+        dots(lds[0], dcA, dcB);
+        float4 qc = *reinterpret_cast<const float4*>(lds[0] + 32 * L::STRIDE + c32 * 16);
+        tile_fetch<T, KP, 16>(xop, min(it0 + 1, il) * 32, rowq, n_rows, pf);
+        tile_store<T, KP>(lds[1], pf);
+        __syncthreads();
+        loads_done();
+#pragma clang loop unroll(disable)
+        for (int64_t it = it0; it < it1; ++it) {
+            const int nxt = (int)((it + 1 - it0) & 1);
+            tile_fetch<T, KP, 16>(xop, min(it + 2, il) * 32, rowq, n_rows, pf);
+            floatx16 dnA, dnB;
+            dots(lds[nxt], dnA, dnB);
+            const float4 qn = *reinterpret_cast<const float4*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
+            const float ckA = cA * qc.x, ckB = cB * qc.x;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                accA[r] = fmaf(qc.y, __builtin_amdgcn_exp2f(fmaf(dcA[r], cA, ckA)), accA[r]);
+                accB[r] = fmaf(qc.z, __builtin_amdgcn_exp2f(fmaf(dcB[r], cB, ckB)), accB[r]);
+            }
+            pin(accA);
+            pin(accB);
+            tile_store<T, KP>(lds[nxt ^ 1], pf);
+            __syncthreads();
+            dcA = dnA;
+            dcB = dnB;
+            qc = qn;
+        }
     }
     if (!active) return;
 #pragma unroll
@@ -876,39 +1060,37 @@ struct LdsTile64 {
     static constexpr int CHUNKS = TILE_BYTES / 16;
     static constexpr int PER_THREAD = (CHUNKS + BLOCK - 1) / BLOCK;
     static constexpr int BUF = 16 * STRIDE + 16 * 16;
+    static_assert(PER_THREAD <= 4, "tile larger than the prefetch registers");
 };
 
 template <int KP>
 __device__ __forceinline__ void tile64_fetch(const double* __restrict__ src, int64_t row0, const void* __restrict__ scal,
-                                             int scal_bytes, int64_t scal_rows, int4 (&buf)[LdsTile64<KP>::PER_THREAD],
-                                             int4& sbuf) {
+                                             int64_t scal_rows, TileRegs& R) {
     using L = LdsTile64<KP>;
-    const char* base = reinterpret_cast<const char*>(src + row0 * KP);
-#pragma unroll
-    for (int q = 0; q < L::PER_THREAD; ++q) {
-        const int c = threadIdx.x + q * BLOCK;
-        if (c < L::CHUNKS) buf[q] = *reinterpret_cast<const int4*>(base + (int64_t)c * 16);
-    }
-    if (threadIdx.x < 16) {
-        const int64_t row = row0 + threadIdx.x;
-        sbuf = make_int4(0, 0, 0, 0);
-        if (row < scal_rows) sbuf = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(scal) + row * scal_bytes);
-    }
+    fetch_tile<16, L::ROW_BYTES, L::PER_THREAD, 16>(reinterpret_cast<const char*>(src + row0 * KP),
+                                                    reinterpret_cast<const char*>(scal), row0, scal_rows, R);
 }
 
 template <int KP>
-__device__ __forceinline__ void tile64_store(char* lds, const int4 (&buf)[LdsTile64<KP>::PER_THREAD], const int4& sbuf) {
+__device__ __forceinline__ void tile64_store(char* lds, TileRegs& R) {
     using L = LdsTile64<KP>;
+    store_tile<16, L::ROW_BYTES, L::STRIDE, L::PER_THREAD>(lds, R);
+}
+
+// x~ . y~ + C for a 16 x 16 tile: A operand in registers, B operand (16 points) from LDS.
+template <int KP>
+__device__ __forceinline__ doublex4 tile_dot64(const char* lds, int c16, int grp, const double (&a)[KP / 4],
+                                               doublex4 c) {
+    using L = LdsTile64<KP>;
+    constexpr int NS = KP / 4;
+    const double* bp = reinterpret_cast<const double*>(lds + c16 * L::STRIDE) + grp * NS;
+    double bv[NS];
 #pragma unroll
-    for (int q = 0; q < L::PER_THREAD; ++q) {
-        const int c = threadIdx.x + q * BLOCK;
-        if (c < L::CHUNKS) {
-            const int row = (c * 16) / L::ROW_BYTES;
-            const int off = (c * 16) % L::ROW_BYTES;
-            *reinterpret_cast<int4*>(lds + row * L::STRIDE + off) = buf[q];
-        }
-    }
-    if (threadIdx.x < 16) *reinterpret_cast<int4*>(lds + 16 * L::STRIDE + threadIdx.x * 16) = sbuf;
+    for (int s = 0; s < NS; ++s) bv[s] = bp[s];
+    doublex4 d = mma64(a[0], bv[0], c);
+#pragma unroll
+    for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
+    return d;
 }
 
 template <int KP>
@@ -951,44 +1133,52 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, 
     double sumA[4] = {0.0, 0.0, 0.0, 0.0}, sumB[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t jt0 = (int64_t)p * tiles_per_split;
     const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
-    int4 pf[L::PER_THREAD];
-    int4 spf = make_int4(0, 0, 0, 0);
+    TileRegs pf;
+    // column j's table entry; columns past m (padding) never contribute
+    auto scal = [&](const char* buf, int64_t jt) {
+        double2 gg = *reinterpret_cast<const double2*>(buf + 16 * L::STRIDE + c16 * 16);
+        if (jt * 16 + c16 >= kc.m) gg = make_double2(-1e300, -1e300);
+        return gg;
+    };
     if (jt0 < jt1) {
-        tile64_fetch<KP>(yop, jt0 * 16, g, 16, kc.m, pf, spf);
-        tile64_store<KP>(lds[0], pf, spf);
-    }
-    __syncthreads();
-    int cnt = 0;
-    for (int64_t jt = jt0; jt < jt1; ++jt) {
-        const int cur = (int)((jt - jt0) & 1);
-        const bool more = jt + 1 < jt1;
-        if (more) tile64_fetch<KP>(yop, (jt + 1) * 16, g, 16, kc.m, pf, spf);
-        const double* bp = reinterpret_cast<const double*>(lds[cur] + c16 * L::STRIDE) + grp * NS;
-        double bv[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
-        const int64_t j = jt * 16 + c16;
-        double2 gg = *reinterpret_cast<const double2*>(lds[cur] + 16 * L::STRIDE + c16 * 16);
-        if (j >= kc.m) gg = make_double2(-1e300, -1e300);
-        doublex4 d = mma64(a[0], bv[0], hv);
-#pragma unroll
-        for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            accA[q] += fexp2(fma(d[q], cA, gg.x));
-            accB[q] += fexp2(fma(d[q], cB, gg.y));
-        }
-        if (++cnt == 8) {   // carry in FP64 every 8 terms
-            cnt = 0;
+        const int64_t jl = jt1 - 1;
+        tile64_fetch<KP>(yop, jt0 * 16, g, kc.m, pf);
+        tile64_store<KP>(lds[0], pf);
+        __syncthreads();
+        doublex4 dc = tile_dot64<KP>(lds[0], c16, grp, a, hv);
+        double2 gc = scal(lds[0], jt0);
+        tile64_fetch<KP>(yop, min(jt0 + 1, jl) * 16, g, kc.m, pf);
+        tile64_store<KP>(lds[1], pf);
+        __syncthreads();
+        loads_done();
+        int cnt = 0;
+#pragma clang loop unroll(disable)
+        for (int64_t jt = jt0; jt < jt1; ++jt) {
+            const int nxt = (int)((jt + 1 - jt0) & 1);
+            tile64_fetch<KP>(yop, min(jt + 2, jl) * 16, g, kc.m, pf);
+            const doublex4 dn = tile_dot64<KP>(lds[nxt], c16, grp, a, hv);
+            const double2 gn = scal(lds[nxt], min(jt + 1, jl));
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                sumA[q] += (double)accA[q];
-                sumB[q] += (double)accB[q];
-                accA[q] = accB[q] = 0.f;
+                accA[q] += fexp2(fma(dc[q], cA, gc.x));
+                accB[q] += fexp2(fma(dc[q], cB, gc.y));
             }
+            pin(accA);
+            pin(accB);
+            if (++cnt == 8) {   // carry in FP64 every 8 terms
+                cnt = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sumA[q] += (double)accA[q];
+                    sumB[q] += (double)accB[q];
+                    accA[q] = accB[q] = 0.f;
+                }
+            }
+            tile64_store<KP>(lds[nxt ^ 1], pf);
+            __syncthreads();
+            dc = dn;
+            gc = gn;
         }
-        if (more) tile64_store<KP>(lds[cur ^ 1], pf, spf);
-        __syncthreads();
     }
     if (!active) return;
 #pragma unroll
@@ -1031,7 +1221,8 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma64_lds(const Ctrl* ctrl, 
     const int64_t cw = (b / P) * 4 + (threadIdx.x >> 6);
     const bool active = cw < m_waves;
     const int64_t j = (active ? cw : 0) * 16 + c16;
-    // B operand: the wave's 16 columns y_j (lane c16 holds column j of D)
+    // B operand: the wave's 16 columns y_j (lane c16 holds column j of D); the streamed
+    // row tile is the A operand, read from LDS
     double bv[NS];
     {
         const double* bp = yop + j * KP + grp * NS;
@@ -1048,47 +1239,68 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma64_lds(const Ctrl* ctrl, 
     double sumA = 0.0, sumB = 0.0;
     const int64_t it0 = (int64_t)p * tiles_per_split;
     const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
-    int4 pf[L::PER_THREAD];
-    int4 spf = make_int4(0, 0, 0, 0);
-    if (it0 < it1) {
-        tile64_fetch<KP>(xop, it0 * 16, rowvar, 16, kc.n, pf, spf);
-        tile64_store<KP>(lds[0], pf, spf);
-    }
-    __syncthreads();
-    for (int64_t it = it0; it < it1; ++it) {
-        const int cur = (int)((it - it0) & 1);
-        const bool more = it + 1 < it1;
-        if (more) tile64_fetch<KP>(xop, (it + 1) * 16, rowvar, 16, kc.n, pf, spf);
-        const double* ap = reinterpret_cast<const double*>(lds[cur] + c16 * L::STRIDE) + grp * NS;
-        double a[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) a[s] = ap[s];
-        doublex4 kv;
+    // rows of the tile: offsets k (accumulator input of the dot products) and weights
+    struct RowTerms {
+        doublex4 k;
         float wa[4], wb[4];
+    };
+    auto row_terms = [&](const char* buf, int64_t it) {
+        RowTerms rt;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = 4 * q + grp;
-            const RowVar rv = *reinterpret_cast<const RowVar*>(lds[cur] + 16 * L::STRIDE + r * 16);
+            const RowVar rv = *reinterpret_cast<const RowVar*>(buf + 16 * L::STRIDE + r * 16);
             const bool valid = it * 16 + r < kc.n;
-            kv[q] = valid ? rv.k : -1e300;
-            wa[q] = valid ? rv.wA : 0.f;
-            wb[q] = valid ? rv.wB : 0.f;
+            rt.k[q] = valid ? rv.k : -1e300;
+            rt.wa[q] = valid ? rv.wA : 0.f;
+            rt.wb[q] = valid ? rv.wB : 0.f;
         }
-        doublex4 d = mma64(a[0], bv[0], kv);
+        return rt;
+    };
+    auto dot = [&](const char* buf, doublex4 k) {
+        const double* ap = reinterpret_cast<const double*>(buf + c16 * L::STRIDE) + grp * NS;
+        double av[NS];
 #pragma unroll
-        for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
+        for (int s = 0; s < NS; ++s) av[s] = ap[s];
+        doublex4 d = mma64(av[0], bv[0], k);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            accA = fmaf(wa[q], fexp2(fma(d[q], cA, gA)), accA);
-            accB = fmaf(wb[q], fexp2(fma(d[q], cB, gB)), accB);
-        }
-        if (((it - it0) & 1) == 1) {
-            sumA += (double)accA;
-            sumB += (double)accB;
-            accA = accB = 0.f;
-        }
-        if (more) tile64_store<KP>(lds[cur ^ 1], pf, spf);
+        for (int s = 1; s < NS; ++s) d = mma64(av[s], bv[s], d);
+        return d;
+    };
+    TileRegs pf;
+    if (it0 < it1) {
+        const int64_t il = it1 - 1;
+        tile64_fetch<KP>(xop, it0 * 16, rowvar, kc.n, pf);
+        tile64_store<KP>(lds[0], pf);
         __syncthreads();
+        RowTerms rc = row_terms(lds[0], it0);
+        doublex4 dc = dot(lds[0], rc.k);
+        tile64_fetch<KP>(xop, min(it0 + 1, il) * 16, rowvar, kc.n, pf);
+        tile64_store<KP>(lds[1], pf);
+        __syncthreads();
+        loads_done();
+#pragma clang loop unroll(disable)
+        for (int64_t it = it0; it < it1; ++it) {
+            const int nxt = (int)((it + 1 - it0) & 1);
+            tile64_fetch<KP>(xop, min(it + 2, il) * 16, rowvar, kc.n, pf);
+            const RowTerms rn = row_terms(lds[nxt], min(it + 1, il));
+            const doublex4 dn = dot(lds[nxt], rn.k);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                accA = fmaf(rc.wa[q], fexp2(fma(dc[q], cA, gA)), accA);
+                accB = fmaf(rc.wb[q], fexp2(fma(dc[q], cB, gB)), accB);
+            }
+            pin(accA, accB);
+            if (((it - it0) & 1) == 1) {
+                sumA += (double)accA;
+                sumB += (double)accB;
+                accA = accB = 0.f;
+            }
+            tile64_store<KP>(lds[nxt ^ 1], pf);
+            __syncthreads();
+            dc = dn;
+            rc = rn;
+        }
     }
     if (!active) return;
     sumA += (double)accA;

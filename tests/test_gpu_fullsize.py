@@ -138,3 +138,37 @@ def test_gmm64_65536_mfma_step(form, dtype):
     # c ~ 0.37 and |h|, |x.y| ~ 1e3 this is ~1e-4 per term
     assert max(errs) <= 2e-3
     assert abs(ca.sum() - 1.0) <= 1e-5
+
+
+def test_sphere_cube_bf16_forward_then_fp32_adjoint():
+    """The differentiation workload end to end: 2^18 x 2^18, d = 3, BF16-MFMA forward from the
+    start until ||col(X^t) - c||_1 <= 1e-4, then the FP32 adjoint at the final state; 16 random
+    gradient coordinates against the oracle's envelope gradient (exact cost) and against
+    central finite differences of the row term (h = 1e-4)."""
+    key = "sphere_cube_262144"
+    wl = W.sphere_cube()
+    s = GOLD[key]["cost_scale"]
+    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=s, cost_norm=1.0)
+    st, rep, status = P.solve(prob, P.make_params(eta=wl.eta, tol=1e-4, max_iter=20000,
+                                                  precision="bf16_mfma"))
+    _say("bf16 forward", rep)
+    assert status == 0 and rep["converged"] == 1 and rep["final_res"] <= 1e-4
+    g = to_np(P.backward(prob, P.make_params(eta=wl.eta), st, grad_out=1.0))
+    nu = to_np(st.nu)
+    lam = st.inv_eta
+    x = wl.x.astype(np.float64)
+    y = wl.y.astype(np.float64)
+    rng = np.random.default_rng(7)
+    coords = [(int(rng.integers(0, wl.n)), int(rng.integers(0, 3))) for _ in range(16)]
+    for (i, k) in coords:
+        gi = OL.envelope_grad_x(x[i:i + 1], y, wl.r[i:i + 1], s, nu, lam, 1.0)[0, k]
+        h = 1e-4
+        xp, xm = x[i:i + 1].copy(), x[i:i + 1].copy()
+        xp[0, k] += h
+        xm[0, k] -= h
+        fd = (OL.envelope_value_rows(xp, y, wl.r[i:i + 1], s, nu, lam, 1.0)[0]
+              - OL.envelope_value_rows(xm, y, wl.r[i:i + 1], s, nu, lam, 1.0)[0]) / (2 * h)
+        scale = max(abs(gi), 1e-3 * np.max(np.abs(g)))
+        _say(f"grad[{i},{k}] gpu {g[i, k]:.9e} oracle {gi:.9e} fd {fd:.9e}")
+        assert abs(g[i, k] - gi) <= 1e-5 * scale + 1e-12
+        assert abs(fd - gi) <= 1e-4 * scale + 1e-12
