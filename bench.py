@@ -1,7 +1,7 @@
 """Benchmark of the LAMP iteration on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision P]
-                    [--time-to-tol] [--no-cpu]
+                    [--compare FORMS] [--time-to-tol FORMS] [--no-cpu] [--mode batch]
 
 A step is one LAMP iteration t -> t+1 (Algorithm 2: both marginal sweeps of
 Section 4.1, the dual mirror steps, averaging, clipping and the residual) over
@@ -13,11 +13,17 @@ state, inputs resident in HBM.
 The default workload is n = m = 2^16 points in d = 64 (8-component Gaussian
 mixture), eta = 1e-3, in the BF16 matrix-core form; the other forms of the same
 workload (FP32 matrix-core tiles, and the reference-accuracy form with FP64 dot
-products) are measured beside it.  Prints one JSON line.
+products) are measured beside it, and the BF16 and reference-accuracy forms are
+each solved from the start to ||col(X^t) - c||_1 <= 1e-4 (time to tolerance).
+`roofline.traffic` is the HBM bytes per launch of the dominant kernel from the
+committed counter summaries under profiles/, when they match the current kernel
+sources.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -95,6 +101,31 @@ def measure_form(P, prob, wl, form, steps, warmup, reps):
             "t_after": st.t}
 
 
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in ("lamp_mfma.hpp", "lamp_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2511_11359_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, form, kernel):
+    """HBM bytes per launch from the committed counter summaries (profiles/*.md lines
+    'traffic workload=... form=... kernel=... bytes=... kernel_sources_sha256=...'), or None
+    when no summary covers this kernel or the kernel sources changed since it was taken."""
+    want = {"workload": workload, "form": form, "kernel": kernel,
+            "kernel_sources_sha256": kernel_sources_sha256()}
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic "):
+                    continue
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+                if all(kv.get(k) == v for k, v in want.items()):
+                    return int(kv["bytes"])
+    return None
+
+
 def roofline(wl, form, m):
     """Roofline of the slower sweep kernel of a form: the exponential (VALU) bound for the
     vector-ALU and half-precision forms, the matrix-core bound where the dot products dominate."""
@@ -107,12 +138,12 @@ def roofline(wl, form, m):
         ach = flops / (dom_ms * 1e-3)
         return {"bound": "mfma", "kernel": dom_name, "achieved": ach / 1e12,
                 "peak": MFMA_PEAK[form] / 1e12, "unit": "TFLOP/s", "frac": ach / MFMA_PEAK[form],
-                "traffic": None, "per_launch": f"2*n*m*d = {flops:.3e} flop",
+                "traffic": measured_traffic(wl.name, form, dom_name), "per_launch": f"2*n*m*d = {flops:.3e} flop",
                 "row_sweep_ms": m["row_sweep_ms"], "col_sweep_ms": m["col_sweep_ms"]}
     exps = 2.0 * wl.n * wl.m                      # both couplings, one exponential per pair each
     ach = exps / (dom_ms * 1e-3)
     return {"bound": "alu", "kernel": dom_name, "achieved": ach / 1e12, "peak": EXP_PEAK / 1e12,
-            "unit": "Texp/s", "frac": ach / EXP_PEAK, "traffic": None,
+            "unit": "Texp/s", "frac": ach / EXP_PEAK, "traffic": measured_traffic(wl.name, form, dom_name),
             "per_launch": f"2*n*m = {exps:.3e} exponentials",
             "row_sweep_ms": m["row_sweep_ms"], "col_sweep_ms": m["col_sweep_ms"]}
 

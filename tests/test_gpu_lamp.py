@@ -61,9 +61,11 @@ def _gpu_state(nu, theta, t, lam):
 
 
 @pytest.mark.parametrize("shape", [(256, 256, 2), (300, 173, 3), (97, 1031, 1), (517, 64, 5),
-                                   (130, 260, 16), (70, 90, 20)])
+                                   (130, 260, 16), (70, 90, 20),
+                                   (1, 1, 1), (1, 7, 2), (9, 1, 3), (33, 47, 128)])
 def test_first_steps_match_oracle(shape):
-    """Iterations 0..4 from the fresh state, several tiles and ragged tails, each dimension path."""
+    """Iterations 0..4 from the fresh state, several tiles and ragged tails, each dimension path,
+    the degenerate single-row / single-column problems and the largest supported d."""
     n, m, d = shape
     wl = W.random_small(n, m, d, seed=100 + d, eta=1e-2)
     _say("case", wl.name)
@@ -268,7 +270,8 @@ MFMA_FORMS = [("fp32_mfma", torch.float32), ("bf16_mfma", torch.bfloat16),
 
 
 @pytest.mark.parametrize("form,dtype", MFMA_FORMS)
-@pytest.mark.parametrize("shape", [(256, 256, 2), (300, 173, 3), (160, 200, 64), (97, 130, 16)])
+@pytest.mark.parametrize("shape", [(256, 256, 2), (300, 173, 3), (160, 200, 64), (97, 130, 16),
+                                   (3, 5, 1), (40, 33, 128)])
 def test_mfma_step_matches_oracle_on_rounded_cost(form, dtype, shape):
     """One step of each matrix-core form from an oracle state (t = 20, eta = 1e-2) against the
     oracle run on the cost those forms evaluate (operands rounded to the operand type).  The
