@@ -1,7 +1,7 @@
 """Benchmark of the LAMP iteration on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision P]
-                    [--compare FORMS] [--time-to-tol FORMS] [--no-cpu] [--mode batch]
+                    [--compare FORMS] [--time-to-tol FORMS] [--no-cpu] [--mode batch|grad]
 
 A step is one LAMP iteration t -> t+1 (Algorithm 2: both marginal sweeps of
 Section 4.1, the dual mirror steps, averaging, clipping and the residual) over
@@ -160,7 +160,7 @@ def time_to_tol(P, prob, wl, form, tol, max_iter):
     log(f"{form}: time to ||col - c||_1 <= {tol}: {rep['iters']} iterations, {dt:.2f} s, "
         f"converged={rep['converged']}, final residual {rep['final_res']:.3e}, cost {cert['cost']:.9e}")
     return {"tol": tol, "iters": rep["iters"], "seconds": dt, "converged": bool(rep["converged"]),
-            "final_res": rep["final_res"], "cost": cert["cost"], "gap": cert["gap"]}
+            "final_res": rep["final_res"], "cost": cert["cost"], "gap": cert["gap"]}, st
 
 
 def batch_mode(args):
@@ -205,9 +205,43 @@ def batch_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def grad_mode(args):
+    """The differentiation workload: n = m = 2^18, d = 3 (sphere vs cube), BF16-MFMA forward
+    from the start to ||col(X^t) - c||_1 <= tol, then the FP32 adjoint (envelope gradient
+    with respect to x) at the final state.  Reports both times and the adjoint's rate."""
+    import torch
+
+    import paper_2511_11359_amd as P
+    from paper_2511_11359_amd import workloads as W
+    wl = W.sphere_cube()
+    dev = torch.device("cuda:0")
+    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, device=dev)
+    s, _ = P.cost_scale(prob)
+    prob.cost_scale, prob.cost_norm = s, 1.0
+    fwd, st = time_to_tol(P, prob, wl, "bf16_mfma", args.tol, args.max_iter)
+    params = P.make_params(eta=wl.eta)
+    P.backward(prob, params, st)                 # warm-up (workspace, code paths)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = P.backward(prob, params, st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    pairs = float(wl.n) * wl.m
+    log(f"adjoint: {dt * 1e3:.3f} ms per gradient ({pairs / dt:.3e} pairs/s), |g|_max {float(g.abs().max()):.3e}")
+    out = {"metric": "pair-evals/s", "value": pairs / dt, "unit": "pair-evals/s", "n_gpus": 1,
+           "steps": reps, "warmup": 1, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+           "config": {"workload": wl.name + "_gradient", "n": wl.n, "m": wl.m, "d": wl.d,
+                      "eta": wl.eta, "forward": "bf16_mfma", "adjoint": "fp32"},
+           "forward_time_to_tol": fwd, "adjoint_ms": dt * 1e3}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="single", choices=["single", "batch"])
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "grad"])
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
@@ -233,6 +267,9 @@ def main():
         sys.exit(2)
     if args.mode == "batch":
         batch_mode(args)
+        return
+    if args.mode == "grad":
+        grad_mode(args)
         return
 
     import torch
@@ -261,7 +298,7 @@ def main():
     ttt = None
     forms_ttt = [f for f in args.time_to_tol.split(",") if f]
     if forms_ttt:
-        ttt = {f: time_to_tol(P, prob, wl, f, args.tol, args.max_iter) for f in forms_ttt}
+        ttt = {f: time_to_tol(P, prob, wl, f, args.tol, args.max_iter)[0] for f in forms_ttt}
     cpu = None if args.no_cpu else cpu_baseline(wl, s)
 
     out = {

@@ -53,17 +53,28 @@ typedef enum {
     LAMP_FP16_MFMA = 3       /* as LAMP_BF16_MFMA with FP16 points                 */
 } lamp_precision;           /* matrix-core forms need d <= 128                     */
 
+/* Ground cost C_ij = s dist(x_i, y_j) generated from the point clouds: the squared
+ * Euclidean cost of Sections 1 and 4.1, and the l1 and l_inf costs of the
+ * kernelized experiments (Section 5).  The matrix-core forms and the batching form
+ * run the squared Euclidean cost only. */
+typedef enum {
+    LAMP_SQEUCLID = 0,   /* ||x - y||_2^2 */
+    LAMP_L1 = 1,         /* sum_k |x_k - y_k| */
+    LAMP_LINF = 2        /* max_k |x_k - y_k| */
+} lamp_metric;
+
 /* Problem data (Section 1; Algorithm 2, REQUIRE line).
  *   x: n x d, y: m x d, row-major FP32 point clouds (device).
+ *   metric: lamp_metric of the ground cost.
  *   r: n, c: m, FP64 marginals (device), strictly positive, each summing to 1
  *      (the paper adds 1e-6 and renormalises to get full support, Appendix E).
- *   cost_scale: s in C_ij = s ||x_i - y_j||^2.  <= 0: s = 1 / max_ij ||x_i - y_j||^2
- *      is computed on the device (then ||C||_inf = 1).
+ *   cost_scale: s in C_ij = s dist(x_i, y_j).  <= 0: s = 1 / max_ij dist(x_i, y_j) is
+ *      computed on the device (then ||C||_inf = 1).
  *   cost_norm: ||C||_inf = max_ij C_ij.  <= 0: computed on the device.  Only
  *      trusted as given when both cost_scale and cost_norm are > 0. */
 typedef struct {
     int64_t n, m;
-    int32_t d, reserved;
+    int32_t d, metric;
     const float *x, *y;
     const double *r, *c;
     double cost_scale;
@@ -121,6 +132,8 @@ typedef struct {
     double cost_scale;       /* s used                                                */
     double cost_norm;        /* ||C||_inf used                                        */
     int64_t t;
+    double rounded_cost;     /* <C, Round(X^t)>, Round of Algorithm 3 applied to X^t
+                                on the device (FP64), without forming X               */
 } lamp_cert;
 
 typedef struct {
@@ -137,8 +150,9 @@ typedef struct {
 /* Bytes of workspace needed for this problem and these parameters. */
 size_t lamp_workspace_bytes(const lamp_problem *prob, const lamp_params *params);
 
-/* s = 1 / max_ij ||x_i - y_j||^2 (FP64 from the FP32 points), the normalisation
- * that makes ||C||_inf = 1.  *max_sqdist_out (host, nullable) gets the maximum. */
+/* s = 1 / max_ij dist(x_i, y_j) for the problem's ground cost (FP64 from the FP32
+ * points), the normalisation that makes ||C||_inf = 1.  *max_sqdist_out (host,
+ * nullable) gets the maximum. */
 lamp_status lamp_cost_scale(const lamp_problem *prob, void *ws, size_t ws_bytes, void *stream,
                             double *s_out, double *max_sqdist_out);
 
@@ -165,12 +179,25 @@ lamp_status lamp_certificate(const lamp_problem *prob, const lamp_params *params
 
 /* Envelope gradient of the transport cost with respect to the source points at
  * the state's iterate (not in the paper; the derivative sum_j X_ij dC_ij/dx_i of
- * <C, X> with X = X^t held fixed, C_ij = s||x_i - y_j||^2 at fixed s):
- *     grad_x[i, :] = grad_out * 2 s r_i sum_j p_ij (x_i - y_j),
+ * <C, X> with X = X^t held fixed, at fixed s):
+ *     squared Euclidean: grad_x[i, :] = grad_out * 2 s r_i sum_j p_ij (x_i - y_j),
+ *     l1:                grad_x[i, k] = grad_out * s r_i sum_j p_ij sign(x_ik - y_jk),
+ *     l_inf:             the same restricted to the coordinate of max_k |x_ik - y_jk|
+ *                        (the first on ties), sign(0) = 0 (subgradients at kinks),
  * written to grad_x (device, n x d, FP32, row-major).  Requires state->t >= 1. */
 lamp_status lamp_backward(const lamp_problem *prob, const lamp_params *params,
                           const lamp_state *state, double grad_out, float *grad_x, void *ws,
                           size_t ws_bytes, void *stream);
+
+/* Envelope gradient with respect to the target points (the column-side counterpart
+ * of lamp_backward): grad_y[j, :] = grad_out * sum_i X_ij dC_ij/dy_j at the state's
+ * iterate X^t, i.e. 2 s sum_i X_ij (y_j - x_i) for the squared Euclidean cost and the
+ * subgradients -s sign(x_ik - y_jk) (l1; l_inf on the coordinate of the largest
+ * |x_k - y_k|) for the others; written to grad_y (device, m x d, FP32, row-major).
+ * Requires state->t >= 1. */
+lamp_status lamp_backward_y(const lamp_problem *prob, const lamp_params *params,
+                            const lamp_state *state, double grad_out, float *grad_y, void *ws,
+                            size_t ws_bytes, void *stream);
 
 /* Measurement support (not part of the method): average device time in ms of one
  * row sweep and one column sweep of iteration state->t (the two O(nm) kernels of

@@ -34,6 +34,36 @@ def sqeuclid_cost(x: np.ndarray, y: np.ndarray, s: float) -> np.ndarray:
     return s * np.sum(diff * diff, axis=2)
 
 
+def l1_cost(x: np.ndarray, y: np.ndarray, s: float) -> np.ndarray:
+    """C_ij = s * sum_k |x_ik - y_jk| in FP64 (the l1 ground cost of the kernelized DOTmark
+    experiments, Section 5 and Appendix E)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    return s * np.sum(np.abs(x[:, None, :] - y[None, :, :]), axis=2)
+
+
+def linf_cost(x: np.ndarray, y: np.ndarray, s: float) -> np.ndarray:
+    """C_ij = s * max_k |x_ik - y_jk| in FP64 (the l_inf ground cost of the same experiments)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    return s * np.max(np.abs(x[:, None, :] - y[None, :, :]), axis=2)
+
+
+GROUND_COSTS = {"sqeuclid": sqeuclid_cost, "l1": l1_cost, "linf": linf_cost}
+
+
+def ground_cost(x: np.ndarray, y: np.ndarray, s: float, kind: str = "sqeuclid") -> np.ndarray:
+    return GROUND_COSTS[kind](x, y, s)
+
+
+def max_cost(x: np.ndarray, y: np.ndarray, kind: str, block: int = 256) -> float:
+    """max_ij of the unscaled ground cost (row blocks)."""
+    best = 0.0
+    for i0 in range(0, x.shape[0], block):
+        best = max(best, float(np.max(ground_cost(x[i0:i0 + block], y, 1.0, kind))))
+    return best
+
+
 def max_sqdist(x: np.ndarray, y: np.ndarray, block: int = 256) -> float:
     """max_ij ||x_i - y_j||^2 in FP64 (difference form, row blocks)."""
     x = np.asarray(x, dtype=np.float64)
@@ -391,11 +421,58 @@ def combined_gap(C: np.ndarray, X: np.ndarray, r: np.ndarray, c: np.ndarray, opt
 
 
 def envelope_value_rows(x: np.ndarray, y: np.ndarray, r: np.ndarray, s: float, nu: np.ndarray,
-                        lam: float, cnorm: float) -> np.ndarray:
-    """f_i(x_i) = r_i softmin^{1/lam}_j (s||x_i - y_j||^2 + 2||C||_inf nu_j), the i-th row term
-    of D^eta(nu) (equation def:dual_spp_e) with eta = 1/lam and frozen s, ||C||_inf."""
-    C = sqeuclid_cost(x, y, s)
+                        lam: float, cnorm: float, kind: str = "sqeuclid") -> np.ndarray:
+    """f_i(x_i) = r_i softmin^{1/lam}_j (C_ij + 2||C||_inf nu_j), C_ij = s dist(x_i, y_j), the
+    i-th row term of D^eta(nu) (equation def:dual_spp_e) with eta = 1/lam and frozen s,
+    ||C||_inf."""
+    C = ground_cost(x, y, s, kind)
     return r * softmin(C + 2.0 * cnorm * nu[None, :], 1.0 / lam, axis=1)
+
+
+def envelope_grad_x_metric(x: np.ndarray, y: np.ndarray, r: np.ndarray, s: float, nu: np.ndarray,
+                           lam: float, cnorm: float, kind: str) -> np.ndarray:
+    """sum_j X_ij dC_ij/dx_i for the l1 and l_inf costs, X = diag(r) p^{1/lam}(nu):
+    l1: dC_ij/dx_ik = s sign(x_ik - y_jk); l_inf: s sign(x_ik - y_jk) on the coordinate k of
+    max_k |x_ik - y_jk| (the first one on ties), 0 elsewhere; sign(0) = 0.  Written with
+    explicit loops over the pairs."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    C = ground_cost(x, y, s, kind)
+    X = r[:, None] * dual_to_primal(C, nu, lam, cnorm)
+    g = np.zeros_like(x)
+    for i in range(x.shape[0]):
+        for j in range(y.shape[0]):
+            diff = x[i] - y[j]
+            if kind == "l1":
+                g[i] += X[i, j] * s * np.sign(diff)
+            else:
+                k = int(np.argmax(np.abs(diff)))
+                g[i, k] += X[i, j] * s * np.sign(diff[k])
+    return g
+
+
+def envelope_grad_y(x: np.ndarray, y: np.ndarray, r: np.ndarray, s: float, nu: np.ndarray,
+                    lam: float, cnorm: float, kind: str = "sqeuclid") -> np.ndarray:
+    """sum_i X_ij dC_ij/dy_j, X = diag(r) p^{1/lam}(nu): the derivative of
+    D^eta(nu; x, y) = sum_i f_i(x_i) - 2||C||_inf <c, nu> with respect to y at frozen nu (Danskin).
+    Squared Euclidean: dC_ij/dy_j = 2 s (y_j - x_i); l1: s sign(y_jk - x_ik); l_inf: the same on
+    the coordinate of max_k |x_ik - y_jk| (first on ties); sign(0) = 0.  Explicit pair loops."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    C = ground_cost(x, y, s, kind)
+    X = r[:, None] * dual_to_primal(C, nu, lam, cnorm)
+    g = np.zeros_like(y)
+    for j in range(y.shape[0]):
+        for i in range(x.shape[0]):
+            diff = y[j] - x[i]
+            if kind == "sqeuclid":
+                g[j] += X[i, j] * 2.0 * s * diff
+            elif kind == "l1":
+                g[j] += X[i, j] * s * np.sign(diff)
+            else:
+                k = int(np.argmax(np.abs(diff)))
+                g[j, k] += X[i, j] * s * np.sign(diff[k])
+    return g
 
 
 def envelope_grad_x(x: np.ndarray, y: np.ndarray, r: np.ndarray, s: float, nu: np.ndarray,

@@ -22,13 +22,17 @@ LAMP_FP32_MFMA = 1
 LAMP_BF16_MFMA = 2
 LAMP_FP16_MFMA = 3
 PRECISIONS = {"fp32": 0, "fp32_mfma": 1, "bf16_mfma": 2, "fp16_mfma": 3}
+LAMP_SQEUCLID = 0
+LAMP_L1 = 1
+LAMP_LINF = 2
+METRICS = {"sqeuclid": 0, "l1": 1, "linf": 2}
 
 STATUS_NAMES = {0: "LAMP_OK", 1: "LAMP_NOT_CONVERGED", -1: "LAMP_EINVAL", -2: "LAMP_EDOMAIN",
                 -3: "LAMP_ENOMEM", -4: "LAMP_EDEVICE", -5: "LAMP_ENUMERIC"}
 
 
 class Problem(ctypes.Structure):
-    _fields_ = [("n", c_int64), ("m", c_int64), ("d", c_int32), ("reserved", c_int32),
+    _fields_ = [("n", c_int64), ("m", c_int64), ("d", c_int32), ("metric", c_int32),
                 ("x", c_void_p), ("y", c_void_p), ("r", c_void_p), ("c", c_void_p),
                 ("cost_scale", c_double), ("cost_norm", c_double)]
 
@@ -52,7 +56,7 @@ class Cert(ctypes.Structure):
     _fields_ = [("col_res", c_double), ("row_res", c_double), ("cost", c_double),
                 ("dual_theta", c_double), ("dual_nu", c_double), ("primal_penalized", c_double),
                 ("gap", c_double), ("prop_bound", c_double), ("cost_scale", c_double),
-                ("cost_norm", c_double), ("t", c_int64)]
+                ("cost_norm", c_double), ("t", c_int64), ("rounded_cost", c_double)]
 
 
 class Report(ctypes.Structure):
@@ -76,6 +80,9 @@ SYMBOLS = {
     "lamp_backward": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params),
                                 ctypes.POINTER(State), c_double, c_void_p, c_void_p, c_size_t,
                                 c_void_p]),
+    "lamp_backward_y": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params),
+                                  ctypes.POINTER(State), c_double, c_void_p, c_void_p, c_size_t,
+                                  c_void_p]),
     "lamp_sweep_times": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params),
                                    ctypes.POINTER(State), c_void_p, c_size_t, c_void_p, c_int32,
                                    ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),

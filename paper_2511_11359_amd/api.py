@@ -34,10 +34,11 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 
 class Problem:
     """Device-resident problem data (Section 1): x (n x d) and y (m x d) FP32 point clouds,
-    r and c FP64 marginals, and the workspace the library works in."""
+    r and c FP64 marginals, the ground cost (metric: "sqeuclid", "l1" or "linf"), and the
+    workspace the library works in."""
 
     def __init__(self, x, y, r, c, cost_scale: float = 0.0, cost_norm: float = 0.0,
-                 device: str | torch.device = "cuda"):
+                 device: str | torch.device = "cuda", metric: str = "sqeuclid"):
         dev = torch.device(device)
         self.device = dev
         self.x = torch.as_tensor(x, dtype=torch.float32).to(dev).contiguous()
@@ -49,10 +50,11 @@ class Problem:
         self.m = self.y.shape[0]
         self.cost_scale = float(cost_scale)
         self.cost_norm = float(cost_norm)
+        self.metric = metric
         self._ws = None
 
     def struct(self) -> L.Problem:
-        return L.Problem(self.n, self.m, self.d, 0, self.x.data_ptr(), self.y.data_ptr(),
+        return L.Problem(self.n, self.m, self.d, L.METRICS[self.metric], self.x.data_ptr(), self.y.data_ptr(),
                          self.r.data_ptr(), self.c.data_ptr(), self.cost_scale, self.cost_norm)
 
     def workspace(self, params: L.Params) -> tuple[int, int]:
@@ -175,6 +177,19 @@ def backward(prob: Problem, params: L.Params, state: State, grad_out: float = 1.
     return g
 
 
+def backward_y(prob: Problem, params: L.Params, state: State, grad_out: float = 1.0) -> torch.Tensor:
+    """grad_out * sum_i X_ij dC_ij/dy_j at the state's iterate (envelope gradient with respect
+    to the target points), m x d FP32."""
+    lib = L.load()
+    ws, nb = prob.workspace(params)
+    g = torch.empty(prob.m, prob.d, dtype=torch.float32, device=prob.device)
+    p = prob.struct()
+    s = state.struct()
+    _check(lib.lamp_backward_y(ctypes.byref(p), ctypes.byref(params), ctypes.byref(s), float(grad_out),
+                               g.data_ptr(), ws, nb, _stream_handle(prob.device)))
+    return g
+
+
 def sweep_times(prob: Problem, params: L.Params, state: State, reps: int = 10) -> tuple[float, float]:
     """Average device milliseconds of one row sweep and one column sweep (HIP events)."""
     lib = L.load()
@@ -213,11 +228,12 @@ def solve_batched(probs: list, params: L.Params, states: list | None = None):
 
 class LampOT(torch.autograd.Function):
     """Transport cost <C, X^T> of the LAMP iterate as a differentiable function of the source
-    points x (envelope gradient at fixed duals and fixed cost scale)."""
+    and target points x, y (envelope gradients at fixed duals and fixed cost scale)."""
 
     @staticmethod
-    def forward(ctx, x, y, r, c, eta: float, tol: float, max_iter: int, cost_scale: float):
-        prob = Problem(x.detach(), y.detach(), r, c, cost_scale=cost_scale, device=x.device)
+    def forward(ctx, x, y, r, c, eta: float, tol: float, max_iter: int, cost_scale: float,
+                metric: str = "sqeuclid"):
+        prob = Problem(x.detach(), y.detach(), r, c, cost_scale=cost_scale, device=x.device, metric=metric)
         if cost_scale <= 0:
             prob.cost_scale, _ = cost_scale_of(prob)
             prob.cost_norm = 1.0
@@ -230,8 +246,9 @@ class LampOT(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         prob, params, state = ctx.lamp
-        gx = backward(prob, params, state, float(g))
-        return gx, None, None, None, None, None, None, None
+        gx = backward(prob, params, state, float(g)) if ctx.needs_input_grad[0] else None
+        gy = backward_y(prob, params, state, float(g)) if ctx.needs_input_grad[1] else None
+        return gx, gy, None, None, None, None, None, None, None
 
 
 cost_scale_of = cost_scale

@@ -70,7 +70,7 @@ int64_t choose_split(int64_t owned, int64_t len, int64_t target = TARGET_BLOCKS)
 }
 
 struct Layout {
-    size_t ctrl, sched, xc, yc, ycf, xn2, yn2, gtab, H, rowvar, rpart, cpart, nu1, th1, respart,
+    size_t ctrl, sched, xc, yc, xcf, ycf, xn2, yn2, gtab, H, rowvar, rpart, cpart, nu1, th1, respart,
         scratch, small, xop, yop, kf, wAf, wBf, gtabf, rowq, total;
     int64_t split_r, P_r, split_c, P_c;
     // matrix-core forms
@@ -118,7 +118,11 @@ void mfma_split(int64_t owned_pad, int64_t streamed_tiles, int64_t* tps, int64_t
     *P = cdiv(streamed_tiles, *tps);
 }
 
-Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target = TARGET_BLOCKS) {
+static_assert(LAMP_SQEUCLID == METRIC_SQEUCLID && LAMP_L1 == METRIC_L1 && LAMP_LINF == METRIC_LINF,
+              "ground-cost codes of the ABI and the kernels agree");
+
+Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target = TARGET_BLOCKS,
+              int metric = METRIC_SQEUCLID) {
     Layout L{};
     L.split_r = choose_split(n, m, target);
     L.P_r = cdiv(m, L.split_r);
@@ -134,7 +138,7 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
         mfma_split(L.m_pad, L.n_pad / 32, &L.tps_c, &L.P_cm);
     }
     L.KP64 = fp64_kp(d);
-    L.use64 = L.KP64 > 0;
+    L.use64 = L.KP64 > 0 && metric == METRIC_SQEUCLID;   // FP64 matrix cores compute inner products only
     L.n_pad64 = cdiv(n, 64) * 64;
     L.m_pad64 = cdiv(m, 64) * 64;
     if (L.use64) {
@@ -150,7 +154,8 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     // row partials: [P][n] double2 for the sweeps, [P_r][n][d+1] for the adjoint,
     // [4][n] for the certificate rows
     size_t rpart_d = std::max<size_t>((size_t)L.P_r * n * std::max(2, d + 1), (size_t)4 * n);
-    size_t cpart_d2 = (size_t)L.P_c * m;
+    // column partials: [P][m] double2 for the sweeps, [P_c][m][d+1] doubles for the y adjoint
+    size_t cpart_d2 = std::max<size_t>((size_t)L.P_c * m, ((size_t)L.P_c * m * (d + 1) + 1) / 2);
     if (is_mfma(prec)) {
         rpart_d = std::max<size_t>(rpart_d, (size_t)L.P_rm * n * 2);
         cpart_d2 = std::max<size_t>(cpart_d2, (size_t)L.P_cm * m);
@@ -163,6 +168,7 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     L.sched = take(sizeof(Sched) * (TAB + 2));
     L.xc = take(sizeof(double) * n * d);
     L.yc = take(sizeof(double) * m * d);
+    L.xcf = take(sizeof(float) * n * d);
     L.ycf = take(sizeof(float) * m * d);
     L.xn2 = take(sizeof(double) * n);
     L.yn2 = take(sizeof(double) * m);
@@ -174,7 +180,8 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     L.nu1 = take(sizeof(double) * m);
     L.th1 = take(sizeof(double) * m);
     L.respart = take(sizeof(double) * cdiv(m, BLOCK));
-    L.scratch = take(sizeof(double) * 4 * std::max(n, m));
+    // certificate: 4 arrays of max(n, m), Round: 9 more and d + 2 column sums
+    L.scratch = take(sizeof(double) * (13 * std::max(n, m) + d + 2));
     L.small = take(sizeof(double) * 64);
     if (is_mfma(prec)) {
         L.xop = take((size_t)L.esize * L.n_pad * L.KP);
@@ -214,6 +221,8 @@ lamp_status check_problem(const lamp_problem* p) {
         return fail(LAMP_EINVAL, "n, m and d must be >= 1 (got %lld, %lld, %d)", (long long)p->n,
                     (long long)p->m, p->d);
     if (!p->x || !p->y || !p->r || !p->c) return fail(LAMP_EINVAL, "a problem array is NULL");
+    if (p->metric != LAMP_SQEUCLID && p->metric != LAMP_L1 && p->metric != LAMP_LINF)
+        return fail(LAMP_EINVAL, "unknown ground cost %d", p->metric);
     return LAMP_OK;
 }
 
@@ -230,7 +239,9 @@ lamp_status check_params(const lamp_params* q) {
 lamp_status check_ws(const lamp_problem* p, void* ws, size_t ws_bytes, int prec = LAMP_FP32) {
     if (is_mfma(prec) && mfma_kp(prec, p->d) == 0)
         return fail(LAMP_EINVAL, "the matrix-core forms support d <= 128 (got %d)", p->d);
-    const Layout L = layout(p->n, p->m, p->d, prec);
+    if (is_mfma(prec) && p->metric != LAMP_SQEUCLID)
+        return fail(LAMP_EINVAL, "the matrix-core forms need the squared Euclidean cost (inner products)");
+    const Layout L = layout(p->n, p->m, p->d, prec, TARGET_BLOCKS, p->metric);
     if (!ws) return fail(LAMP_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(LAMP_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < L.total)
@@ -271,9 +282,9 @@ void prep_ops(const lamp_problem* p, const Layout& L, void* ws, hipStream_t st) 
 lamp_status prep_L(const lamp_problem* p, const Layout& L, void* ws, hipStream_t st) {
     const int prec = L.prec;
     hipLaunchKernelGGL(prep_points, grid1(p->n), dim3(BLOCK), 0, st, p->x, p->n, p->d, p->x, p->y,
-                       at<double>(ws, L.xc), at<double>(ws, L.xn2), (float*)nullptr);
+                       at<double>(ws, L.xc), at<double>(ws, L.xn2), at<float>(ws, L.xcf), p->metric);
     hipLaunchKernelGGL(prep_points, grid1(p->m), dim3(BLOCK), 0, st, p->y, p->m, p->d, p->x, p->y,
-                       at<double>(ws, L.yc), at<double>(ws, L.yn2), at<float>(ws, L.ycf));
+                       at<double>(ws, L.yc), at<double>(ws, L.yn2), at<float>(ws, L.ycf), p->metric);
     if (L.use64) {
         hipLaunchKernelGGL(prep_operands64, grid1(L.n_pad64 * L.KP64), dim3(BLOCK), 0, st, at<double>(ws, L.xc),
                            p->n, p->d, L.KP64, L.n_pad64, at<double>(ws, L.xop64));
@@ -299,11 +310,46 @@ lamp_status prep_L(const lamp_problem* p, const Layout& L, void* ws, hipStream_t
 }
 
 lamp_status prep(const lamp_problem* p, void* ws, hipStream_t st, int prec = LAMP_FP32) {
-    return prep_L(p, layout(p->n, p->m, p->d, prec), ws, st);
+    return prep_L(p, layout(p->n, p->m, p->d, prec, TARGET_BLOCKS, p->metric), ws, st);
 }
 
 // ------------------------------------------------------------------ dispatch by d
 #define LAMP_FOR_D(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(16)
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Launches the vector-ALU kernel of metric M and dimension d if one is compiled
+// (d in 1..8 and 16 for the squared Euclidean cost, 1..4 for l1 / l_inf):
+// launch(IC<D>) issues it.  Returns false for the generic-d kernel.
+template <int M, typename F>
+bool valu_dispatch(int d, F&& launch) {
+    switch (d) {
+        case 1: launch(IC<1>{}); return true;
+        case 2: launch(IC<2>{}); return true;
+        case 3: launch(IC<3>{}); return true;
+        case 4: launch(IC<4>{}); return true;
+        default: break;
+    }
+    if constexpr (M == METRIC_SQEUCLID) {
+        switch (d) {
+            case 5: launch(IC<5>{}); return true;
+            case 6: launch(IC<6>{}); return true;
+            case 7: launch(IC<7>{}); return true;
+            case 8: launch(IC<8>{}); return true;
+            case 16: launch(IC<16>{}); return true;
+            default: break;
+        }
+    }
+    return false;
+}
+
+// f(IC<M>) for the run-time metric.
+template <typename F>
+bool by_metric(int metric, F&& f) {
+    if (metric == METRIC_L1) return f(IC<METRIC_L1>{});
+    if (metric == METRIC_LINF) return f(IC<METRIC_LINF>{});
+    return f(IC<METRIC_SQEUCLID>{});
+}
 
 template <int KP>
 void row_extreme64(const Layout& L, Consts kc, void* ws, const double* a, double sgn, hipStream_t st) {
@@ -328,15 +374,15 @@ void launch_row_extreme(const Layout& L, Consts kc, int d, void* ws, const doubl
     }
     dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
     double* part = at<double>(ws, L.rpart);
-    switch (d) {
-#define CASE(D) \
-    case D: hipLaunchKernelGGL(row_extreme<D>, g, dim3(BLOCK), 0, st, kc, at<double>(ws, L.xc), at<double>(ws, L.yc), a, sgn, part, L.split_r); return;
-        LAMP_FOR_D(CASE)
-#undef CASE
-        default:
-            hipLaunchKernelGGL(row_extreme_dyn, g, dim3(BLOCK), 0, st, kc, d, at<double>(ws, L.xc),
-                               at<double>(ws, L.yc), a, sgn, part, L.split_r);
-    }
+    const double* xc = at<double>(ws, L.xc);
+    const double* yc = at<double>(ws, L.yc);
+    const bool done = by_metric(kc.metric, [&](auto m) {
+        return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
+            hipLaunchKernelGGL((row_extreme<decltype(m)::value, decltype(dd)::value>), g, dim3(BLOCK), 0, st, kc,
+                               xc, yc, a, sgn, part, L.split_r);
+        });
+    });
+    if (!done) hipLaunchKernelGGL(row_extreme_dyn, g, dim3(BLOCK), 0, st, kc, d, xc, yc, a, sgn, part, L.split_r);
 }
 
 template <typename T, int KP>
@@ -441,16 +487,19 @@ void launch_row_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t s
     dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
     const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
     const Sched* sch = at<Sched>(ws, L.sched);
-    switch (d) {
-#define CASE(D) \
-    case D: hipLaunchKernelGGL(row_sweep<D>, g, dim3(BLOCK), 0, st, ctrl, sch, kc, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), at<double>(ws, L.H), at<double2>(ws, L.rpart), L.split_r); return;
-        LAMP_FOR_D(CASE)
-#undef CASE
-        default:
-            hipLaunchKernelGGL(row_sweep_dyn, g, dim3(BLOCK), 0, st, ctrl, sch, kc, d, at<double>(ws, L.xc),
-                               at<double>(ws, L.yc), at<double2>(ws, L.gtab), at<double>(ws, L.H),
-                               at<double2>(ws, L.rpart), L.split_r);
-    }
+    const double* xc = at<double>(ws, L.xc);
+    const double* yc = at<double>(ws, L.yc);
+    const double2* gt = at<double2>(ws, L.gtab);
+    const double* H = at<double>(ws, L.H);
+    double2* part = at<double2>(ws, L.rpart);
+    const bool done = by_metric(kc.metric, [&](auto m) {
+        return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
+            hipLaunchKernelGGL((row_sweep<decltype(m)::value, decltype(dd)::value>), g, dim3(BLOCK), 0, st, ctrl,
+                               sch, kc, xc, yc, gt, H, part, L.split_r);
+        });
+    });
+    if (!done)
+        hipLaunchKernelGGL(row_sweep_dyn, g, dim3(BLOCK), 0, st, ctrl, sch, kc, d, xc, yc, gt, H, part, L.split_r);
 }
 
 void launch_col_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
@@ -465,32 +514,37 @@ void launch_col_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t s
     dim3 g((unsigned)cdiv(kc.m, BLOCK), (unsigned)L.P_c);
     const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
     const Sched* sch = at<Sched>(ws, L.sched);
-    switch (d) {
-#define CASE(D) \
-    case D: hipLaunchKernelGGL(col_sweep<D>, g, dim3(BLOCK), 0, st, ctrl, sch, kc, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), at<RowVar>(ws, L.rowvar), at<double2>(ws, L.cpart), L.split_c); return;
-        LAMP_FOR_D(CASE)
-#undef CASE
-        default:
-            hipLaunchKernelGGL(col_sweep_dyn, g, dim3(BLOCK), 0, st, ctrl, sch, kc, d, at<double>(ws, L.xc),
-                               at<double>(ws, L.yc), at<double2>(ws, L.gtab), at<RowVar>(ws, L.rowvar),
-                               at<double2>(ws, L.cpart), L.split_c);
-    }
+    const double* xc = at<double>(ws, L.xc);
+    const double* yc = at<double>(ws, L.yc);
+    const double2* gt = at<double2>(ws, L.gtab);
+    const RowVar* rv = at<RowVar>(ws, L.rowvar);
+    double2* part = at<double2>(ws, L.cpart);
+    const bool done = by_metric(kc.metric, [&](auto m) {
+        return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
+            hipLaunchKernelGGL((col_sweep<decltype(m)::value, decltype(dd)::value>), g, dim3(BLOCK), 0, st, ctrl,
+                               sch, kc, xc, yc, gt, rv, part, L.split_c);
+        });
+    });
+    if (!done)
+        hipLaunchKernelGGL(col_sweep_dyn, g, dim3(BLOCK), 0, st, ctrl, sch, kc, d, xc, yc, gt, rv, part, L.split_c);
 }
 
 void launch_adjoint(const Layout& L, Consts kc, int d, void* ws, double cA, const double* gA,
                     hipStream_t st) {
     dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
     double* part = at<double>(ws, L.rpart);
-    switch (d) {
-#define CASE(D) \
-    case D: hipLaunchKernelGGL(adjoint_sweep<D>, g, dim3(BLOCK), 0, st, kc, cA, at<double>(ws, L.xc), at<double>(ws, L.yc), at<float>(ws, L.ycf), gA, at<double>(ws, L.H), part, L.split_r); return;
-        LAMP_FOR_D(CASE)
-#undef CASE
-        default:
-            hipLaunchKernelGGL(adjoint_sweep_dyn, g, dim3(BLOCK), 0, st, kc, d, cA, at<double>(ws, L.xc),
-                               at<double>(ws, L.yc), at<float>(ws, L.ycf), gA, at<double>(ws, L.H), part,
-                               L.split_r);
-    }
+    const double* xc = at<double>(ws, L.xc);
+    const double* yc = at<double>(ws, L.yc);
+    const float* ycf = at<float>(ws, L.ycf);
+    const double* H = at<double>(ws, L.H);
+    const bool done = by_metric(kc.metric, [&](auto m) {
+        return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
+            hipLaunchKernelGGL((adjoint_sweep<decltype(m)::value, decltype(dd)::value>), g, dim3(BLOCK), 0, st, kc,
+                               cA, xc, yc, ycf, gA, H, part, L.split_r);
+        });
+    });
+    if (!done)
+        hipLaunchKernelGGL(adjoint_sweep_dyn, g, dim3(BLOCK), 0, st, kc, d, cA, xc, yc, ycf, gA, H, part, L.split_r);
 }
 
 __global__ void fill_scaled(int64_t cnt, double f, const double* __restrict__ in, double* __restrict__ out) {
@@ -502,6 +556,7 @@ lamp_status max_sqdist_L(const lamp_problem* p, const Layout& L, void* ws, hipSt
     Consts kc{};
     kc.n = p->n;
     kc.m = p->m;
+    kc.metric = p->metric;
     double* a = at<double>(ws, L.scratch);
     double* rowmax = a + std::max(p->n, p->m);
     hipLaunchKernelGGL(fill_scaled, grid1(p->m), dim3(BLOCK), 0, st, p->m, -0.5, at<double>(ws, L.yn2), a);
@@ -516,7 +571,7 @@ lamp_status max_sqdist_L(const lamp_problem* p, const Layout& L, void* ws, hipSt
 }
 
 lamp_status max_sqdist(const lamp_problem* p, void* ws, hipStream_t st, double* out_host, int prec) {
-    return max_sqdist_L(p, layout(p->n, p->m, p->d, prec), ws, st, out_host);
+    return max_sqdist_L(p, layout(p->n, p->m, p->d, prec, TARGET_BLOCKS, p->metric), ws, st, out_host);
 }
 
 lamp_status resolve_L(const lamp_problem* p, const lamp_params* q, const Layout& L, void* ws, hipStream_t st,
@@ -548,7 +603,7 @@ lamp_status resolve_L(const lamp_problem* p, const lamp_params* q, const Layout&
 }
 
 lamp_status resolve(const lamp_problem* p, const lamp_params* q, void* ws, hipStream_t st, Resolved* R) {
-    return resolve_L(p, q, layout(p->n, p->m, p->d, q->precision), ws, st, R);
+    return resolve_L(p, q, layout(p->n, p->m, p->d, q->precision, TARGET_BLOCKS, p->metric), ws, st, R);
 }
 
 Consts make_consts(const lamp_problem* p, const Resolved& R) {
@@ -560,6 +615,7 @@ Consts make_consts(const lamp_problem* p, const Resolved& R) {
     kc.kappa = R.kappa;
     kc.alpha_m = R.alpha / (double)p->m;
     kc.clipb = R.clipb;
+    kc.metric = p->metric;
     return kc;
 }
 
@@ -703,7 +759,7 @@ lamp_status check_state(const lamp_state* s) {
 lamp_status state_normalisers(const lamp_problem* p, const lamp_params* q, const Resolved& R,
                               const lamp_state* s, void* ws, hipStream_t st, double* cA_out) {
     // the workspace is laid out for q->precision; the normalisers always use the FP64-argument sweeps
-    Layout L = layout(p->n, p->m, p->d, q->precision);
+    Layout L = layout(p->n, p->m, p->d, q->precision, TARGET_BLOCKS, p->metric);
     L.prec = LAMP_FP32;
     const Consts kc = make_consts(p, R);
     Ctrl hc;
@@ -748,8 +804,8 @@ struct BatchCand {
     int64_t target_total;   // sweep blocks per phase over the whole batch
     int grid;               // persistent grid size of the phase kernels
 };
-const BatchCand kBatchCands[] = {{1024, 1024}, {2048, 1024}, {2048, 2048}, {4096, 2048}, {4096, 4096},
-                                 {8192, 4096}};
+const BatchCand kBatchCands[] = {{2048, 1024}, {4096, 1024}, {4096, 2048}, {8192, 2048}, {16384, 2048},
+                                 {16384, 4096}};
 constexpr int kNumBatchCands = (int)(sizeof(kBatchCands) / sizeof(kBatchCands[0]));
 
 std::mutex g_tune_mu;
@@ -782,11 +838,24 @@ __global__ void rewind_ctrl(const ProbDesc* __restrict__ pd, int count, int64_t 
     }
 }
 
+// Point dimensions with their own batch sweep kernels (0: every other dimension).
+constexpr int kBatchDims[] = {1, 2, 3, 4, 8, 16, 0};
+constexpr int kNumBatchDims = (int)(sizeof(kBatchDims) / sizeof(kBatchDims[0]));
+
+int batch_dim_group(int d) {
+    for (int g = 0; g < kNumBatchDims - 1; ++g)
+        if (kBatchDims[g] == d) return g;
+    return kNumBatchDims - 1;
+}
+
 struct BatchPlan {
     std::vector<Layout> L;
     std::vector<size_t> sub;      // per-problem sub-workspace offsets
-    size_t descs, items[4], ctrlv, sched, total;
+    size_t descs, items[4], ctrlv, sched, counters, nact, total;
     int n_items[4];
+    // sweep items (phases 0 and 2) are grouped by dimension: group g occupies
+    // [grp_off[k][g], grp_off[k][g] + grp_cnt[k][g]) of the phase's list
+    int grp_off[4][kNumBatchDims], grp_cnt[4][kNumBatchDims];
 };
 
 // Relative cost of one pair in the vector-ALU sweeps: d FP64 FMAs for the dot product
@@ -818,6 +887,17 @@ BatchPlan batch_plan(const lamp_problem* probs, int count, int cand) {
     }
     B.descs = take(sizeof(ProbDesc) * count);
     for (int k = 0; k < 4; ++k) B.items[k] = take(sizeof(Item) * B.n_items[k]);
+    for (int k = 0; k < 4; ++k)
+        for (int g = 0; g < kNumBatchDims; ++g) B.grp_off[k][g] = B.grp_cnt[k][g] = 0;
+    for (int k : {0, 2}) {
+        for (int p = 0; p < count; ++p) {
+            const int64_t blocks = cdiv(k == 0 ? probs[p].n : probs[p].m, BLOCK);
+            B.grp_cnt[k][batch_dim_group(probs[p].d)] += (int)(blocks * (k == 0 ? B.L[p].P_r : B.L[p].P_c));
+        }
+        for (int g = 1; g < kNumBatchDims; ++g) B.grp_off[k][g] = B.grp_off[k][g - 1] + B.grp_cnt[k][g - 1];
+    }
+    B.counters = take(sizeof(unsigned) * 2 * kNumBatchDims);
+    B.nact = take(sizeof(int) * 2 * kNumBatchDims);
     B.ctrlv = take(sizeof(Ctrl) * count);
     B.sched = take(sizeof(Sched) * (TAB + 2));
     B.sub.resize(count);
@@ -835,6 +915,9 @@ std::string batch_signature(const lamp_problem* probs, int count) {
 
 struct BatchRun {
     BatchPlan B;
+    std::vector<Item> sweep_items[2];       // all row / column sweep items, grouped and sorted
+    std::vector<Item> upload[2];            // the active part, as last uploaded
+    std::vector<int> nact_host;             // active item count per (phase, group)
     std::vector<ProbDesc> desc;
     std::vector<Resolved> R;
     std::vector<double*> nu1, th1;
@@ -843,6 +926,43 @@ struct BatchRun {
 };
 
 void* sub_ws(void* ws, const BatchPlan& B, int p) { return static_cast<char*>(ws) + B.sub[p]; }
+
+// Uploads the sweep items of the running problems (active[p] != 0) to the front of each
+// dimension group's segment, in the stored order, and the per-group counts the sweep
+// kernels read; the graph's launch arguments stay valid.  Synchronises the stream.
+lamp_status batch_upload_sweeps(BatchRun* run, const std::vector<char>& active, void* ws, hipStream_t st) {
+    const BatchPlan& B = run->B;
+    run->nact_host.assign(2 * kNumBatchDims, 0);
+    for (int h = 0; h < 2; ++h) {
+        const int k = h == 0 ? 0 : 2;
+        std::vector<Item>& up = run->upload[h];
+        up.clear();
+        const std::vector<Item>& all = run->sweep_items[h];
+        for (int g = 0; g < kNumBatchDims; ++g) {
+            const int beg = B.grp_off[k][g], end = beg + B.grp_cnt[k][g];
+            int n = 0;
+            for (int i = beg; i < end; ++i)
+                if (active[all[i].prob]) {
+                    up.push_back(all[i]);
+                    ++n;
+                }
+            run->nact_host[h * kNumBatchDims + g] = n;
+        }
+        // group g's active items start at its segment offset
+        int pos = 0;
+        for (int g = 0; g < kNumBatchDims; ++g) {
+            const int n = run->nact_host[h * kNumBatchDims + g];
+            if (n > 0)
+                HIPCHK(hipMemcpyAsync(at<Item>(ws, B.items[k]) + B.grp_off[k][g], up.data() + pos, sizeof(Item) * n,
+                                      hipMemcpyHostToDevice, st));
+            pos += n;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(at<int>(ws, B.nact), run->nact_host.data(), sizeof(int) * run->nact_host.size(),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return LAMP_OK;
+}
 
 // Everything up to the first iteration: per-problem preparation and cost scale, the
 // shared schedule, control blocks, column tables, exact offsets, descriptors and work lists.
@@ -917,13 +1037,38 @@ lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params*
             for (int64_t x = 0; x < cb; ++x) items[2].push_back(Item{p, (int)x, (int)y, 0});
         for (int64_t x = 0; x < cb; ++x) items[3].push_back(Item{p, (int)x, 0, 0});
     }
+    // sweep lists: grouped by dimension (the order of kBatchDims), largest items first within
+    // a group; an item's cost is its rows x its columns x the per-pair cost of its dimension.
+    // Only the items of running problems are uploaded (batch_upload_sweeps).
+    for (int k : {0, 2}) {
+        auto cost = [&](const Item& it) {
+            const lamp_problem& q = probs[it.prob];
+            const Layout& L = B.L[it.prob];
+            const int64_t own = k == 0 ? q.n : q.m, other = k == 0 ? q.m : q.n;
+            const int64_t split = k == 0 ? L.split_r : L.split_c;
+            const int64_t rows = std::min<int64_t>(BLOCK, own - (int64_t)it.bx * BLOCK);
+            const int64_t cols = std::min<int64_t>(split, other - (int64_t)it.by * split);
+            return (double)rows * (double)std::max<int64_t>(cols, 0) * pair_cost(q.d);
+        };
+        std::stable_sort(items[k].begin(), items[k].end(), [&](const Item& a, const Item& b) {
+            const int ga = batch_dim_group(probs[a.prob].d), gb = batch_dim_group(probs[b.prob].d);
+            if (ga != gb) return ga < gb;
+            return cost(a) > cost(b);
+        });
+    }
+    const std::vector<unsigned> zeros(2 * kNumBatchDims, 0u);
+    HIPCHK(hipMemcpyAsync(at<unsigned>(ws, B.counters), zeros.data(), sizeof(unsigned) * zeros.size(),
+                          hipMemcpyHostToDevice, st));
+    run->sweep_items[0] = items[0];
+    run->sweep_items[1] = items[2];
     HIPCHK(hipMemcpyAsync(at<Ctrl>(ws, B.ctrlv), hc.data(), sizeof(Ctrl) * count, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(at<ProbDesc>(ws, B.descs), run->desc.data(), sizeof(ProbDesc) * count,
                           hipMemcpyHostToDevice, st));
-    for (int k = 0; k < 4; ++k)
+    for (int k : {1, 3})
         HIPCHK(hipMemcpyAsync(at<Item>(ws, B.items[k]), items[k].data(), sizeof(Item) * items[k].size(),
                               hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));   // the uploads read host vectors of this frame
+    if ((e = batch_upload_sweeps(run, std::vector<char>(count, 1), ws, st)) != LAMP_OK) return e;
     for (int p = 0; p < count; ++p) {
         const Layout& L = B.L[p];
         void* w = sub_ws(ws, B, p);
@@ -937,19 +1082,46 @@ lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params*
     return LAMP_OK;
 }
 
+template <bool ROW>
+void batch_sweeps(const BatchRun& run, void* ws, hipStream_t st) {
+    const BatchPlan& B = run.B;
+    const int k = ROW ? 0 : 2;
+    const ProbDesc* pd = at<ProbDesc>(ws, B.descs);
+    const Sched* sch = at<Sched>(ws, B.sched);
+    unsigned* ctr = at<unsigned>(ws, B.counters) + (ROW ? 0 : kNumBatchDims);
+    for (int g = 0; g < kNumBatchDims; ++g) {
+        const int cnt = B.grp_cnt[k][g];
+        if (cnt == 0) continue;
+        const dim3 grid((unsigned)std::max(1, std::min(run.grid, cnt)));
+        const Item* it = at<Item>(ws, B.items[k]) + B.grp_off[k][g];
+        const int* na = at<int>(ws, B.nact) + (ROW ? 0 : kNumBatchDims) + g;
+        switch (kBatchDims[g]) {
+#define CASE(D)                                                                                             \
+    case D:                                                                                                 \
+        if (ROW) hipLaunchKernelGGL(batch_row_sweep<D>, grid, dim3(BLOCK), 0, st, pd, it, na, sch, ctr + g); \
+        else hipLaunchKernelGGL(batch_col_sweep<D>, grid, dim3(BLOCK), 0, st, pd, it, na, sch, ctr + g);    \
+        break;
+            LAMP_BATCH_D(CASE)
+#undef CASE
+            default:
+                if (ROW) hipLaunchKernelGGL(batch_row_sweep<0>, grid, dim3(BLOCK), 0, st, pd, it, na, sch, ctr + g);
+                else hipLaunchKernelGGL(batch_col_sweep<0>, grid, dim3(BLOCK), 0, st, pd, it, na, sch, ctr + g);
+        }
+    }
+}
+
 void batch_iteration(const BatchRun& run, void* ws, hipStream_t st) {
     const BatchPlan& B = run.B;
     const ProbDesc* pd = at<ProbDesc>(ws, B.descs);
     const Sched* sch = at<Sched>(ws, B.sched);
+    unsigned* ctr = at<unsigned>(ws, B.counters);
     auto g = [&](int n) { return dim3((unsigned)std::max(1, std::min(run.grid, n))); };
-    hipLaunchKernelGGL(batch_row_sweep, g(B.n_items[0]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[0]),
-                       B.n_items[0], sch);
+    batch_sweeps<true>(run, ws, st);
     hipLaunchKernelGGL(batch_row_finish, g(B.n_items[1]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[1]),
-                       B.n_items[1], sch);
-    hipLaunchKernelGGL(batch_col_sweep, g(B.n_items[2]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[2]),
-                       B.n_items[2], sch);
+                       B.n_items[1], sch, ctr, kNumBatchDims);
+    batch_sweeps<false>(run, ws, st);
     hipLaunchKernelGGL(batch_dual_update, g(B.n_items[3]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[3]),
-                       B.n_items[3], sch);
+                       B.n_items[3], sch, ctr + kNumBatchDims, kNumBatchDims);
 }
 
 // Autotuner: every candidate launch shape runs a few iterations from the callers' start
@@ -1011,7 +1183,7 @@ size_t lamp_workspace_bytes(const lamp_problem* prob, const lamp_params* params)
     if (!prob || prob->n < 1 || prob->m < 1 || prob->d < 1) return 0;
     const int prec = params ? params->precision : LAMP_FP32;
     if (is_mfma(prec) && mfma_kp(prec, prob->d) == 0) return 0;
-    return layout(prob->n, prob->m, prob->d, prec).total;
+    return layout(prob->n, prob->m, prob->d, prec, TARGET_BLOCKS, prob->metric).total;
 }
 
 lamp_status lamp_cost_scale(const lamp_problem* prob, void* ws, size_t ws_bytes, void* stream,
@@ -1036,7 +1208,7 @@ lamp_status lamp_step(const lamp_problem* prob, const lamp_params* params, lamp_
     if ((e = check_state(state)) != LAMP_OK) return e;
     Resolved R;
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
-    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
     const Consts kc = make_consts(prob, R);
     const int64_t t = state->t;
     std::vector<Sched> tab;
@@ -1094,7 +1266,7 @@ lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp
     } guard{own};
     Resolved R;
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
-    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
     const Consts kc = make_consts(prob, R);
     const int64_t t0 = state->t;
     const int64_t t_stop = t0 + params->max_iter;
@@ -1199,7 +1371,7 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     if (!out) return fail(LAMP_EINVAL, "out is NULL");
     Resolved R;
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
-    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
     const Consts kc = make_consts(prob, R);
     double cA = 0.0;
     if ((e = state_normalisers(prob, params, R, state, ws, st, &cA)) != LAMP_OK) return e;
@@ -1214,19 +1386,49 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     double* prods = sc + 2 * nm;     // 2m
     double* vals = at<double>(ws, L.rpart);  // 4n
     double* small = at<double>(ws, L.small);
+    double* psum = sc + 4 * nm;      // n
+    double* xr = sc + 5 * nm;        // n
+    double* colp = sc + 6 * nm;      // m
+    double* yf = sc + 7 * nm;        // m
+    double* dc = sc + 8 * nm;        // m
+    double* dr = sc + 9 * nm;        // n
+    double* cpp = sc + 10 * nm;      // n
+    double* tr1 = sc + 11 * nm;      // n
+    double* absdr = sc + 12 * nm;    // n
+    double* S = sc + 13 * nm;        // d + 2
     hipLaunchKernelGGL(col_residual, grid1(kc.m), dim3(BLOCK), 0, st, kc, at<double2>(ws, L.cpart), col_parts(LV),
                        prob->c, colres);
     hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
                        at<double2>(ws, L.gtab), gA);
     hipLaunchKernelGGL(cert_rows, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, cA, at<double>(ws, L.xc),
                        at<double>(ws, L.yc), at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA, at<double>(ws, L.H),
-                       prob->r, state->nu, state->theta, vals);
+                       prob->r, state->nu, state->theta, vals, psum);
     hipLaunchKernelGGL(col_products, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->c, state->theta, state->nu, prods);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, vals, kc.n, kc.n, 4, small);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, colres, kc.m, kc.m, 1, small + 4);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, prods, kc.m, kc.m, 2, small + 5);
+    // Round (Algorithm 3) of the same X and its cost
+    hipLaunchKernelGGL(round_row_factors, grid1(kc.n), dim3(BLOCK), 0, st, kc, psum, xr);
+    hipLaunchKernelGGL(round_cols, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->d, cA, at<double>(ws, L.xc),
+                       at<double>(ws, L.yc), gA, at<double>(ws, L.H), prob->r, xr, colp);
+    hipLaunchKernelGGL(round_col_factors, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->c, colp, yf, dc);
+    hipLaunchKernelGGL(round_rows, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, cA, at<double>(ws, L.xc),
+                       at<double>(ws, L.yc), at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA,
+                       at<double>(ws, L.H), prob->r, xr, yf, dr, cpp);
+    if (kc.metric == METRIC_SQEUCLID) {
+        hipLaunchKernelGGL(round_col_sums, dim3(prob->d + 2), dim3(BLOCK), 0, st, kc, prob->d,
+                           at<double>(ws, L.yc), at<double>(ws, L.yn2), dc, S);
+        hipLaunchKernelGGL(round_rank_one, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, at<double>(ws, L.xc),
+                           at<double>(ws, L.xn2), dr, S, tr1, absdr);
+    } else {
+        hipLaunchKernelGGL(round_rank_one_pairs, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d,
+                           at<double>(ws, L.xc), at<double>(ws, L.yc), dr, dc, tr1, absdr);
+    }
+    hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, cpp, kc.n, kc.n, 1, small + 7);
+    hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, tr1, kc.n, kc.n, 1, small + 8);
+    hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, absdr, kc.n, kc.n, 1, small + 9);
     HIPCHK(hipGetLastError());
-    double h[8];
+    double h[10];
     HIPCHK(hipMemcpyAsync(h, small, sizeof(h), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     out->row_res = h[0];
@@ -1237,6 +1439,8 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     out->primal_penalized = out->cost + R.K * (out->row_res + out->col_res);
     out->gap = out->primal_penalized - std::max(out->dual_theta, out->dual_nu);
     out->prop_bound = 4.0 * R.cnorm * out->col_res + 2.0 * R.cnorm * std::log((double)kc.m) / (double)state->t;
+    // <C, Round(X)>; the rank-one correction is skipped when ||dr||_1 = 0 (then dc = 0 too)
+    out->rounded_cost = h[7] + (h[9] > 0.0 ? h[8] / h[9] : 0.0);
     out->cost_scale = R.s;
     out->cost_norm = R.cnorm;
     out->t = state->t;
@@ -1252,7 +1456,7 @@ lamp_status lamp_backward(const lamp_problem* prob, const lamp_params* params, c
     if (!grad_x) return fail(LAMP_EINVAL, "grad_x is NULL");
     Resolved R;
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
-    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
     const Consts kc = make_consts(prob, R);
     double cA = 0.0;
     if ((e = state_normalisers(prob, params, R, state, ws, st, &cA)) != LAMP_OK) return e;
@@ -1266,6 +1470,45 @@ lamp_status lamp_backward(const lamp_problem* prob, const lamp_params* params, c
     return LAMP_OK;
 }
 
+lamp_status lamp_backward_y(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
+                            double grad_out, float* grad_y, void* ws, size_t ws_bytes, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    lamp_status e;
+    if ((e = check_state(state)) != LAMP_OK) return e;
+    if (state->t < 1 || !(state->inv_eta > 0.0)) return fail(LAMP_EINVAL, "the gradient needs t >= 1");
+    if (!grad_y) return fail(LAMP_EINVAL, "grad_y is NULL");
+    Resolved R;
+    if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
+    const Consts kc = make_consts(prob, R);
+    double cA = 0.0;
+    // row offsets k_i and weights w_i = r_i of X^t (both halves of the set-up are p^{eta_t}(nu^t))
+    if ((e = state_normalisers(prob, params, R, state, ws, st, &cA)) != LAMP_OK) return e;
+    double* gA = at<double>(ws, L.scratch);
+    hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
+                       at<double2>(ws, L.gtab), gA);
+    dim3 g((unsigned)cdiv(kc.m, BLOCK), (unsigned)L.P_c);
+    double* part = at<double>(ws, L.cpart);
+    const double* xc = at<double>(ws, L.xc);
+    const float* xcf = at<float>(ws, L.xcf);
+    const double* yc = at<double>(ws, L.yc);
+    const RowVar* rv = at<RowVar>(ws, L.rowvar);
+    const int d = prob->d;
+    const bool done = by_metric(kc.metric, [&](auto m) {
+        return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
+            hipLaunchKernelGGL((adjoint_y_sweep<decltype(m)::value, decltype(dd)::value>), g, dim3(BLOCK), 0, st,
+                               kc, cA, xc, xcf, yc, gA, rv, part, L.split_c);
+        });
+    });
+    if (!done)
+        hipLaunchKernelGGL(adjoint_y_sweep_dyn, g, dim3(BLOCK), 0, st, kc, d, cA, xc, xcf, yc, gA, rv, part,
+                           L.split_c);
+    hipLaunchKernelGGL(adjoint_y_finish, grid1(kc.m), dim3(BLOCK), 0, st, kc, d, (int)L.P_c, grad_out * 2.0 * R.s,
+                       yc, part, grad_y);
+    HIPCHK(hipGetLastError());
+    return LAMP_OK;
+}
+
 lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
                              void* ws, size_t ws_bytes, void* stream, int32_t reps, double* row_ms,
                              double* col_ms) {
@@ -1275,7 +1518,7 @@ lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params
     if (reps < 1) return fail(LAMP_EINVAL, "reps must be >= 1");
     Resolved R;
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
-    const Layout L = layout(prob->n, prob->m, prob->d, params->precision);
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
     const Consts kc = make_consts(prob, R);
     std::vector<Sched> tab;
     fill_sched(tab, 1, state->inv_eta, R.tau1, params->eta);
@@ -1329,6 +1572,8 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
     if (params->precision != LAMP_FP32) return fail(LAMP_EINVAL, "the batching form runs the LAMP_FP32 form");
     for (int p = 0; p < count; ++p) {
         if ((e = check_problem(&probs[p])) != LAMP_OK) return e;
+        if (probs[p].metric != LAMP_SQEUCLID)
+            return fail(LAMP_EINVAL, "the batching form runs the squared Euclidean cost (problem %d)", p);
         if ((e = check_state(&states[p])) != LAMP_OK) return e;
         if (states[p].t != states[0].t || states[p].inv_eta != states[0].inv_eta)
             return fail(LAMP_EINVAL, "batched states must share t and inv_eta (problem %d differs)", p);
@@ -1373,6 +1618,7 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
         HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     }
     std::vector<Ctrl> hc(count);
+    std::vector<char> active(count, 1);
     Ctrl* hc_dev = at<Ctrl>(ws, B.ctrlv);
     double lam_epoch = states[0].inv_eta;
     int64_t t_base = t0;
@@ -1385,13 +1631,16 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
         HIPCHK(hipGraphLaunch(exec, st));
         HIPCHK(hipMemcpyAsync(hc.data(), hc_dev, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        bool all_done = true, any_err = false;
+        bool all_done = true, any_err = false, newly_done = false;
         int64_t tmax = t_cur;
         for (int p = 0; p < count; ++p) {
             if (hc[p].err) any_err = true;
             if (!hc[p].done) {
                 all_done = false;
                 tmax = std::max(tmax, hc[p].t);
+            } else if (active[p]) {
+                active[p] = 0;
+                newly_done = true;
             }
         }
         if (any_err) {
@@ -1403,6 +1652,9 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
                                        (long long)t_cur);
         t_cur = tmax;
         if (t_cur >= t_stop) break;
+        // problems that stopped leave the sweep work lists (no graph change: the kernels read
+        // the item counts from device memory)
+        if (newly_done && (e = batch_upload_sweeps(&run, active, ws, st)) != LAMP_OK) return e;
         if (t_cur >= t_base + TAB) {
             t_base = t_cur;
             lam_epoch = lam_next_epoch;

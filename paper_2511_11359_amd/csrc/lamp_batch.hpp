@@ -1,7 +1,9 @@
-// Batching form: many independent problems advance together, one launch per phase of
-// the iteration for all of them.  Each phase kernel is a persistent loop of a
-// machine-sized grid over a work list of (problem, tile) items; an item runs the same
-// device body as the single-problem kernels, with that problem's descriptor.  Every
+// Batching form: many independent problems advance together, each phase of the
+// iteration launched once for all of them (the sweeps once per point dimension present,
+// so that every sweep kernel is compiled for its own dimension).  Each phase kernel is a
+// persistent loop of a machine-sized grid over a work list of (problem, tile) items; an
+// item runs the same device body as the single-problem kernels, with that problem's
+// descriptor.  Sweep items are handed out by an atomic counter, largest first.  Every
 // problem keeps its own control block, so a problem that meets its tolerance stops
 // (its items exit at once) while the others continue.
 #pragma once
@@ -31,30 +33,67 @@ struct Item {
 
 #define LAMP_BATCH_D(X) X(1) X(2) X(3) X(4) X(8) X(16)
 
+// The descriptor's pointers are loaded from memory, so the compiler cannot tell their
+// address space (it would use flat loads) nor that the column data are read-only during
+// the sweep.  Re-typing them restores what the single-problem kernels get from their
+// arguments: the streamed column data go through the constant address space (scalar
+// loads when the address is wave-uniform), per-lane data through the global one.
+// (Through an integer: a direct generic -> specific -> generic cast is folded away.)
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+    return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+template <typename T>
+__device__ __forceinline__ const T* as_const(const T* p) {
+    return (const T*)(const __attribute__((address_space(4))) T*)(uintptr_t)p;
+}
+
+// Next work item of a persistent sweep kernel: one atomic increment per block on the
+// phase's counter (largest items come first in the list, so the tail is short).  The
+// counter is returned to zero by the next phase kernel of the iteration.
+__device__ __forceinline__ int next_item(unsigned* counter) {
+    __shared__ int k_sh;
+    if (threadIdx.x == 0) k_sh = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int k = __builtin_amdgcn_readfirstlane(k_sh);   // block-uniform
+    __syncthreads();
+    return k;
+}
+
+__device__ __forceinline__ void reset_counters(unsigned* counters, int n) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < n) counters[threadIdx.x] = 0u;
+}
+
+// Row sweep items of the problems with dimension D (D = 0: any other dimension).
+template <int D>
 __global__ __launch_bounds__(BLOCK) void batch_row_sweep(const ProbDesc* __restrict__ pd,
-                                                         const Item* __restrict__ items, int n_items,
-                                                         const Sched* sched) {
-    for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
+                                                         const Item* __restrict__ items,
+                                                         const int* __restrict__ n_active,
+                                                         const Sched* sched, unsigned* counter) {
+    const int n_items = *n_active;   // items of problems still running (rewritten by the host)
+    if ((int)blockIdx.x >= n_items) return;   // more blocks than items: the surplus leaves at once
+    for (;;) {
+        const int k = next_item(counter);
+        if (k >= n_items) break;
         const Item it = items[k];
         const ProbDesc& P = pd[it.prob];
-        switch (P.d) {
-#define CASE(D)                                                                                         \
-    case D:                                                                                             \
-        row_sweep_body<D>(P.ctrl, sched, P.kc, P.xc, P.yc, P.gtab, P.H, P.rpart, P.split_r, it.bx, it.by, \
-                          0);                                                                            \
-        break;
-            LAMP_BATCH_D(CASE)
-#undef CASE
-            default:
-                row_sweep_dyn_body(P.ctrl, sched, P.kc, P.d, P.xc, P.yc, P.gtab, P.H, P.rpart, P.split_r, it.bx,
-                                   it.by, 0);
-        }
+        const Ctrl* ctrl = as_const(P.ctrl);
+        const double* xc = as_global(P.xc);
+        const double* yc = as_const(P.yc);
+        const double2* gtab = as_const(P.gtab);
+        const double* H = as_global(P.H);
+        double2* rpart = as_global(P.rpart);
+        if constexpr (D > 0)
+            row_sweep_body<METRIC_SQEUCLID, D>(ctrl, sched, P.kc, xc, yc, gtab, H, rpart, P.split_r, it.bx, it.by, 0);
+        else
+            row_sweep_dyn_body(ctrl, sched, P.kc, P.d, xc, yc, gtab, H, rpart, P.split_r, it.bx, it.by, 0);
     }
 }
 
 __global__ __launch_bounds__(BLOCK) void batch_row_finish(const ProbDesc* __restrict__ pd,
                                                           const Item* __restrict__ items, int n_items,
-                                                          const Sched* sched) {
+                                                          const Sched* sched, unsigned* counters, int n_counters) {
+    reset_counters(counters, n_counters);   // the row sweeps of this iteration are complete
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
         const Item it = items[k];
         const ProbDesc& P = pd[it.prob];
@@ -63,30 +102,37 @@ __global__ __launch_bounds__(BLOCK) void batch_row_finish(const ProbDesc* __rest
     }
 }
 
+// Column sweep items of the problems with dimension D (D = 0: any other dimension).
+template <int D>
 __global__ __launch_bounds__(BLOCK) void batch_col_sweep(const ProbDesc* __restrict__ pd,
-                                                         const Item* __restrict__ items, int n_items,
-                                                         const Sched* sched) {
-    for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
+                                                         const Item* __restrict__ items,
+                                                         const int* __restrict__ n_active,
+                                                         const Sched* sched, unsigned* counter) {
+    const int n_items = *n_active;   // items of problems still running (rewritten by the host)
+    if ((int)blockIdx.x >= n_items) return;   // more blocks than items: the surplus leaves at once
+    for (;;) {
+        const int k = next_item(counter);
+        if (k >= n_items) break;
         const Item it = items[k];
         const ProbDesc& P = pd[it.prob];
-        switch (P.d) {
-#define CASE(D)                                                                                          \
-    case D:                                                                                              \
-        col_sweep_body<D>(P.ctrl, sched, P.kc, P.xc, P.yc, P.gtab, P.rowvar, P.cpart, P.split_c, it.bx, it.by, \
-                          0);                                                                             \
-        break;
-            LAMP_BATCH_D(CASE)
-#undef CASE
-            default:
-                col_sweep_dyn_body(P.ctrl, sched, P.kc, P.d, P.xc, P.yc, P.gtab, P.rowvar, P.cpart, P.split_c,
-                                   it.bx, it.by, 0);
-        }
+        const Ctrl* ctrl = as_const(P.ctrl);
+        const double* xc = as_const(P.xc);
+        const double* yc = as_global(P.yc);
+        const double2* gtab = as_global(P.gtab);
+        const RowVar* rowvar = as_const(P.rowvar);
+        double2* cpart = as_global(P.cpart);
+        if constexpr (D > 0)
+            col_sweep_body<METRIC_SQEUCLID, D>(ctrl, sched, P.kc, xc, yc, gtab, rowvar, cpart, P.split_c, it.bx, it.by, 0);
+        else
+            col_sweep_dyn_body(ctrl, sched, P.kc, P.d, xc, yc, gtab, rowvar, cpart, P.split_c, it.bx, it.by, 0);
     }
 }
 
 __global__ __launch_bounds__(BLOCK) void batch_dual_update(const ProbDesc* __restrict__ pd,
                                                            const Item* __restrict__ items, int n_items,
-                                                           const Sched* sched) {
+                                                           const Sched* sched, unsigned* counters,
+                                                           int n_counters) {
+    reset_counters(counters, n_counters);   // the column sweeps of this iteration are complete
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
         const Item it = items[k];
         const ProbDesc& P = pd[it.prob];

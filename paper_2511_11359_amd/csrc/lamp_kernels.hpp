@@ -76,7 +76,53 @@ struct Consts {
     double kappa;   // 2 tau2 ||C||_inf
     double alpha_m; // alpha / m
     double clipb;   // tanh(beta / 2)
+    int metric;     // ground cost, METRIC_*
 };
+
+// ---------------------------------------------------------------------------
+// Ground costs.  Every kernel works with a pair term P(x, y) defined so that
+//     C_ij = s (|x~_i|^2 + |y~_j|^2 - 2 P(x~_i, y~_j)):
+// the inner product with the squared norms for the squared Euclidean cost
+// (Sections 1 and 4.1), and -dist(x, y)/2 with zero norm arrays for the l1 and
+// l_inf costs of the kernelized experiments (Section 5).  The exponent assembly,
+// the offsets, the certificate and the cost maximum are then the same for all three.
+// ---------------------------------------------------------------------------
+enum : int { METRIC_SQEUCLID = 0, METRIC_L1 = 1, METRIC_LINF = 2 };
+
+// init + P(x, y) with x in registers and y streamed.
+template <int M, int D>
+__device__ __forceinline__ double pair_term(const double (&x)[D], const double* __restrict__ y, double init) {
+    if constexpr (M == METRIC_SQEUCLID) {
+        double d = init;
+#pragma unroll
+        for (int k = 0; k < D; ++k) d = fma(x[k], y[k], d);
+        return d;
+    } else {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double t = fabs(x[k] - y[k]);
+            a = (M == METRIC_L1) ? a + t : fmax(a, t);
+        }
+        return fma(-0.5, a, init);
+    }
+}
+
+// init + P(x, y), both operands in memory, metric and dimension at run time.
+__device__ __forceinline__ double pair_term_dyn(int M, int D, const double* __restrict__ x,
+                                                const double* __restrict__ y, double init) {
+    if (M == METRIC_SQEUCLID) {
+        double d = init;
+        for (int k = 0; k < D; ++k) d = fma(x[k], y[k], d);
+        return d;
+    }
+    double a = 0.0;
+    for (int k = 0; k < D; ++k) {
+        const double t = fabs(x[k] - y[k]);
+        a = (M == METRIC_L1) ? a + t : fmax(a, t);
+    }
+    return fma(-0.5, a, init);
+}
 
 // Row data streamed by the column sweep.
 struct RowVar {
@@ -99,7 +145,7 @@ __device__ __forceinline__ float fexp2(double e) {
 __global__ void prep_points(const float* __restrict__ pts, int64_t cnt, int d,
                             const float* __restrict__ mu_src_a, const float* __restrict__ mu_src_b,
                             double* __restrict__ out, double* __restrict__ nrm2,
-                            float* __restrict__ outf) {
+                            float* __restrict__ outf, int metric) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt) return;
     double acc = 0.0;
@@ -112,7 +158,7 @@ __global__ void prep_points(const float* __restrict__ pts, int64_t cnt, int d,
         if (outf) outf[i * d + k] = (float)v;
         acc = fma(v, v, acc);
     }
-    nrm2[i] = acc;
+    nrm2[i] = metric == METRIC_SQEUCLID ? acc : 0.0;   // the l1 / l_inf pair term carries the cost
 }
 
 // ---------------------------------------------------------------------------
@@ -165,7 +211,7 @@ __global__ void offset_coeffs(const Ctrl* ctrl, const Sched* sched, Consts kc,
 // Used for the exact offsets, D(theta) and the cost maximum.
 // part: [P][n] partial minima over column splits.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int M, int D>
 __device__ __forceinline__ void row_extreme_body(Consts kc, const double* __restrict__ xc,
                                                      const double* __restrict__ yc,
                                                      const double* __restrict__ a, double sgn,
@@ -177,23 +223,35 @@ __device__ __forceinline__ void row_extreme_body(Consts kc, const double* __rest
     const int64_t ii = i < kc.n ? i : kc.n - 1;
     double x[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = sgn * xc[ii * D + k];
+    for (int k = 0; k < D; ++k) x[k] = (M == METRIC_SQEUCLID ? sgn : 1.0) * xc[ii * D + k];
+    // a_j + sgn P(x_i, y_j): the inner product takes the sign on x, the distances after
+    auto term = [&](const double* yj, double aj) {
+        return M == METRIC_SQEUCLID ? pair_term<M, D>(x, yj, aj) : fma(sgn, pair_term<M, D>(x, yj, 0.0), aj);
+    };
+    // blocks of UNROLL columns with independent chains, as in the sweeps: the column data
+    // are wave-uniform and their scalar loads overlap the arithmetic of the block
     double best = __builtin_inf();
-    for (int64_t j = j0; j < j1; ++j) {
-        double dot = a[j];
+    const int nfull = (int)((j1 - j0) / UNROLL);
+    const double* __restrict__ yp = yc + j0 * D;
+    const double* __restrict__ ap = a + j0;
+    for (int c = 0; c < nfull; ++c, yp += UNROLL * D, ap += UNROLL) {
+        double v[UNROLL];
 #pragma unroll
-        for (int k = 0; k < D; ++k) dot = fma(x[k], yc[j * D + k], dot);
-        best = fmin(best, dot);
+        for (int u = 0; u < UNROLL; ++u) v[u] = term(yp + u * D, ap[u]);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) best = fmin(best, v[u]);
     }
+    const int rem = (int)((j1 - j0) - (int64_t)nfull * UNROLL);
+    for (int u = 0; u < rem; ++u) best = fmin(best, term(yp + u * D, ap[u]));
     if (i < kc.n) part[p * kc.n + i] = best;
 }
 
-template <int D>
+template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void row_extreme(Consts kc, const double* __restrict__ xc,
                                                      const double* __restrict__ yc,
                                                      const double* __restrict__ a, double sgn,
                                                      double* __restrict__ part, int64_t split) {
-    row_extreme_body<D>(kc, xc, yc, a, sgn, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    row_extreme_body<M, D>(kc, xc, yc, a, sgn, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 // Generic-d version: coordinates read per pair.
@@ -208,9 +266,7 @@ __device__ __forceinline__ void row_extreme_dyn_body(Consts kc, int D, const dou
     const int64_t ii = i < kc.n ? i : kc.n - 1;
     double best = __builtin_inf();
     for (int64_t j = j0; j < j1; ++j) {
-        double dot = a[j];
-        for (int k = 0; k < D; ++k) dot = fma(sgn * xc[ii * D + k], yc[j * D + k], dot);
-        best = fmin(best, dot);
+        best = fmin(best, fma(sgn, pair_term_dyn(kc.metric, D, xc + ii * D, yc + j * D, 0.0), a[j]));
     }
     if (i < kc.n) part[p * kc.n + i] = best;
 }
@@ -255,17 +311,15 @@ __device__ __forceinline__ double fma_su(double a, double b, double c_uniform) {
 }
 
 // One column j of the row sweep for this lane's row: returns 2^eA, 2^eB.
-template <int D>
+template <int M, int D>
 __device__ __forceinline__ void row_terms(const double (&x)[D], double h, const double* __restrict__ yj,
                                           double2 g, double cA, double cB, float& pA, float& pB) {
-    double dot = h;
-#pragma unroll
-    for (int k = 0; k < D; ++k) dot = fma(x[k], yj[k], dot);
+    const double dot = pair_term<M, D>(x, yj, h);
     pA = fexp2(fma_su(dot, cA, g.x));
     pB = fexp2(fma_su(dot, cB, g.y));
 }
 
-template <int D>
+template <int M, int D>
 __device__ __forceinline__ void row_sweep_body(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                    const double* __restrict__ xc,
                                                    const double* __restrict__ yc,
@@ -296,7 +350,7 @@ __device__ __forceinline__ void row_sweep_body(const Ctrl* ctrl, const Sched* sc
     for (int c = 0; c < nfull; ++c, yp += UNROLL * D, gp += UNROLL) {
         float pA[UNROLL], pB[UNROLL];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) row_terms<D>(x, h, yp + u * D, gp[u], cA, cB, pA[u], pB[u]);
+        for (int u = 0; u < UNROLL; ++u) row_terms<M, D>(x, h, yp + u * D, gp[u], cA, cB, pA[u], pB[u]);
         float accA = pA[0], accB = pB[0];
 #pragma unroll
         for (int u = 1; u < UNROLL; ++u) {
@@ -311,7 +365,7 @@ __device__ __forceinline__ void row_sweep_body(const Ctrl* ctrl, const Sched* sc
         float accA = 0.f, accB = 0.f;
         for (int u = 0; u < rem; ++u) {
             float a, b;
-            row_terms<D>(x, h, yp + u * D, gp[u], cA, cB, a, b);
+            row_terms<M, D>(x, h, yp + u * D, gp[u], cA, cB, a, b);
             accA += a;
             accB += b;
         }
@@ -321,14 +375,14 @@ __device__ __forceinline__ void row_sweep_body(const Ctrl* ctrl, const Sched* sc
     if (i < kc.n) part[p * kc.n + i] = make_double2(sumA, sumB);
 }
 
-template <int D>
+template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void row_sweep(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                    const double* __restrict__ xc,
                                                    const double* __restrict__ yc,
                                                    const double2* __restrict__ gtab2,
                                                    const double* __restrict__ H,
                                                    double2* __restrict__ part, int64_t split) {
-    row_sweep_body<D>(ctrl, sched, kc, xc, yc, gtab2, H, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    row_sweep_body<M, D>(ctrl, sched, kc, xc, yc, gtab2, H, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 __device__ __forceinline__ void row_sweep_dyn_body(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
@@ -354,8 +408,7 @@ __device__ __forceinline__ void row_sweep_dyn_body(const Ctrl* ctrl, const Sched
         float accA = 0.f, accB = 0.f;
         const int64_t je = min(j1, jb + UNROLL);
         for (int64_t j = jb; j < je; ++j) {
-            double dot = h;
-            for (int k = 0; k < D; ++k) dot = fma(xc[ii * D + k], yc[j * D + k], dot);
+            const double dot = pair_term_dyn(kc.metric, D, xc + ii * D, yc + j * D, h);
             accA += fexp2(fma(cA, dot, g[j].x));
             accB += fexp2(fma(cB, dot, g[j].y));
         }
@@ -375,19 +428,17 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_dyn(const Ctrl* ctrl, const S
 }
 
 // Exact recomputation of sigma_i = log2 sum_j 2^(g_j + cfac x~_i.y~_j) (two passes, FP64 max).
-__device__ double exact_sigma(const double* __restrict__ xi, const double* __restrict__ yc, int D,
+__device__ double exact_sigma(int M, const double* __restrict__ xi, const double* __restrict__ yc, int D,
                               int64_t m, const double2* __restrict__ g, int which, double cfac) {
     double mx = -__builtin_inf();
     for (int64_t j = 0; j < m; ++j) {
-        double dot = 0.0;
-        for (int k = 0; k < D; ++k) dot = fma(xi[k], yc[j * D + k], dot);
+        const double dot = pair_term_dyn(M, D, xi, yc + j * D, 0.0);
         double e = fma(cfac, dot, which ? g[j].y : g[j].x);
         mx = fmax(mx, e);
     }
     double s = 0.0;
     for (int64_t j = 0; j < m; ++j) {
-        double dot = 0.0;
-        for (int k = 0; k < D; ++k) dot = fma(xi[k], yc[j * D + k], dot);
+        const double dot = pair_term_dyn(M, D, xi, yc + j * D, 0.0);
         double e = fma(cfac, dot, which ? g[j].y : g[j].x);
         s += exp2(e - mx);
     }
@@ -434,8 +485,8 @@ __device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, 
         sigB = log2(SB) - cB * h;
     } else {
         const double2* g = gtab2 + (t & 1) * kc.m;
-        sigA = exact_sigma(xc + i * D, yc, D, kc.m, g, 0, cA);
-        sigB = exact_sigma(xc + i * D, yc, D, kc.m, g, 1, cB);
+        sigA = exact_sigma(kc.metric, xc + i * D, yc, D, kc.m, g, 0, cA);
+        sigB = exact_sigma(kc.metric, xc + i * D, yc, D, kc.m, g, 1, cB);
         atomicAdd(&ctrl->fallbacks, 1);
     }
     const double hnew = -sigB / cB;
@@ -476,19 +527,24 @@ __global__ void row_finish(Ctrl* ctrl, const Sched* sched, Consts kc, int D,
 // ---------------------------------------------------------------------------
 // One row i of the column sweep for this lane's column: w^A 2^eA, w^B 2^eB are
 // accumulated with the row weights as the scalar multiplicand.
-template <int D>
+template <int M, int D>
 __device__ __forceinline__ void col_terms(const double (&y)[D], const double* __restrict__ xi, RowVar rv,
                                           double gA, double gB, double cA, double cB, float& accA,
                                           float& accB) {
-    double dot = y[0] * xi[0];
+    double dot;
+    if constexpr (M == METRIC_SQEUCLID) {
+        dot = y[0] * xi[0];
 #pragma unroll
-    for (int k = 1; k < D; ++k) dot = fma(y[k], xi[k], dot);
+        for (int k = 1; k < D; ++k) dot = fma(y[k], xi[k], dot);
+    } else {
+        dot = pair_term<M, D>(y, xi, 0.0);   // the distances are symmetric
+    }
     dot = dot + rv.k;
     accA = fmaf(rv.wA, fexp2(fma(dot, cA, gA)), accA);
     accB = fmaf(rv.wB, fexp2(fma(dot, cB, gB)), accB);
 }
 
-template <int D>
+template <int M, int D>
 __device__ __forceinline__ void col_sweep_body(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                    const double* __restrict__ xc,
                                                    const double* __restrict__ yc,
@@ -517,28 +573,28 @@ __device__ __forceinline__ void col_sweep_body(const Ctrl* ctrl, const Sched* sc
     for (int c = 0; c < nfull; ++c, xp += UNROLL * D, rp += UNROLL) {
         float accA = 0.f, accB = 0.f;
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) col_terms<D>(y, xp + u * D, rp[u], g.x, g.y, cA, cB, accA, accB);
+        for (int u = 0; u < UNROLL; ++u) col_terms<M, D>(y, xp + u * D, rp[u], g.x, g.y, cA, cB, accA, accB);
         sumA += (double)accA;
         sumB += (double)accB;
     }
     {
         const int rem = (int)((i1 - i0) - (int64_t)nfull * UNROLL);
         float accA = 0.f, accB = 0.f;
-        for (int u = 0; u < rem; ++u) col_terms<D>(y, xp + u * D, rp[u], g.x, g.y, cA, cB, accA, accB);
+        for (int u = 0; u < rem; ++u) col_terms<M, D>(y, xp + u * D, rp[u], g.x, g.y, cA, cB, accA, accB);
         sumA += (double)accA;
         sumB += (double)accB;
     }
     if (j < kc.m) cpart[p * kc.m + j] = make_double2(sumA, sumB);
 }
 
-template <int D>
+template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void col_sweep(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                    const double* __restrict__ xc,
                                                    const double* __restrict__ yc,
                                                    const double2* __restrict__ gtab2,
                                                    const RowVar* __restrict__ rowvar,
                                                    double2* __restrict__ cpart, int64_t split) {
-    col_sweep_body<D>(ctrl, sched, kc, xc, yc, gtab2, rowvar, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    col_sweep_body<M, D>(ctrl, sched, kc, xc, yc, gtab2, rowvar, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 __device__ __forceinline__ void col_sweep_dyn_body(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
@@ -564,8 +620,7 @@ __device__ __forceinline__ void col_sweep_dyn_body(const Ctrl* ctrl, const Sched
         const int64_t ie = min(i1, ib + UNROLL);
         for (int64_t i = ib; i < ie; ++i) {
             const RowVar rv = rowvar[i];
-            double dot = rv.k;
-            for (int k = 0; k < D; ++k) dot = fma(yc[jj * D + k], xc[i * D + k], dot);
+            const double dot = pair_term_dyn(kc.metric, D, yc + jj * D, xc + i * D, rv.k);
             accA = fmaf(rv.wA, fexp2(fma(cA, dot, g.x)), accA);
             accB = fmaf(rv.wB, fexp2(fma(cB, dot, g.y)), accB);
         }
@@ -744,6 +799,7 @@ __global__ void reduce_sums(const double* __restrict__ vals, int64_t n, int64_t 
 //   vals[1][i] = r_i sum_j C_ij p_ij                  (<C, X^t>)
 //   vals[2][i] = r_i min_j (C_ij + K theta_j)         (D(theta), def:dual_spp)
 //   vals[3][i] = r_i min_j (C_ij + K nu_j)            (D(nu))
+//   psum_out[i] = sum_j p_ij                          (row sum of p, for Round)
 // FP64 throughout (including the exponential); not on the iteration path.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int D, double cA,
@@ -756,14 +812,13 @@ __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int D, double cA,
                                                    const double* __restrict__ r,
                                                    const double* __restrict__ nu,
                                                    const double* __restrict__ theta,
-                                                   double* __restrict__ vals) {
+                                                   double* __restrict__ vals, double* __restrict__ psum_out) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= kc.n) return;
     const double h = H[i];
     double psum = 0.0, csum = 0.0, mth = __builtin_inf(), mnu = __builtin_inf();
     for (int64_t j = 0; j < kc.m; ++j) {
-        double dot = 0.0;
-        for (int k = 0; k < D; ++k) dot = fma(xc[i * D + k], yc[j * D + k], dot);
+        const double dot = pair_term_dyn(kc.metric, D, xc + i * D, yc + j * D, 0.0);
         const double pij = exp2(fma(cA, h + dot, gA[j]));
         const double cij = kc.s * (xn2[i] + yn2[j] - 2.0 * dot);
         psum += pij;
@@ -776,6 +831,119 @@ __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int D, double cA,
     vals[kc.n + i] = ri * csum;
     vals[2 * kc.n + i] = ri * mth;
     vals[3 * kc.n + i] = ri * mnu;
+    if (psum_out) psum_out[i] = psum;
+}
+
+// ---------------------------------------------------------------------------
+// Round (Algorithm 3) of the same X = diag(r) p on the device, without forming it:
+//   step 1  xr_i = min(r_i / row_i(X), 1) = min(1 / sum_j p_ij, 1)
+//   step 2  X' = diag(xr) X;  y_j = min(c_j / col_j(X'), 1);  X'' = X' diag(y)
+//   step 3  dr = r - row(X''),  dc = c - col(X'') = c - y * col(X')
+//   step 4  Round(X) = X'' + dr dc^T / ||dr||_1
+// so that <C, Round(X)> = <C, X''> + dr^T C dc / ||dr||_1, where for the squared
+// Euclidean cost on centred points
+//   (C dc)_i = s (||x~_i||^2 sum_j dc_j + sum_j dc_j ||y~_j||^2 - 2 x~_i . sum_j dc_j y~_j)
+// is O(d) per row once the column sums are known.  FP64 throughout.
+// ---------------------------------------------------------------------------
+__global__ void round_row_factors(Consts kc, const double* __restrict__ psum, double* __restrict__ xr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kc.n) xr[i] = fmin(1.0 / psum[i], 1.0);
+}
+
+// colp_j = sum_i xr_i r_i p_ij (one thread per column, rows in order).
+__global__ __launch_bounds__(BLOCK) void round_cols(Consts kc, int D, double cA, const double* __restrict__ xc,
+                                                    const double* __restrict__ yc, const double* __restrict__ gA,
+                                                    const double* __restrict__ H, const double* __restrict__ r,
+                                                    const double* __restrict__ xr, double* __restrict__ colp) {
+    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (j >= kc.m) return;
+    const double g = gA[j];
+    double acc = 0.0;
+    for (int64_t i = 0; i < kc.n; ++i) {
+        const double dot = pair_term_dyn(kc.metric, D, xc + i * D, yc + j * D, 0.0);
+        acc = fma(xr[i] * r[i], exp2(fma(cA, H[i] + dot, g)), acc);
+    }
+    colp[j] = acc;
+}
+
+// y_j = min(c_j / colp_j, 1) and dc_j = c_j - y_j colp_j.
+__global__ void round_col_factors(Consts kc, const double* __restrict__ c, const double* __restrict__ colp,
+                                  double* __restrict__ y, double* __restrict__ dc) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kc.m) return;
+    const double yj = colp[j] > 0.0 ? fmin(c[j] / colp[j], 1.0) : 1.0;
+    y[j] = yj;
+    dc[j] = c[j] - yj * colp[j];
+}
+
+// Rows of X'': dr_i = r_i - xr_i r_i sum_j p_ij y_j and cpp_i = xr_i r_i sum_j C_ij p_ij y_j.
+__global__ __launch_bounds__(BLOCK) void round_rows(Consts kc, int D, double cA, const double* __restrict__ xc,
+                                                    const double* __restrict__ yc, const double* __restrict__ xn2,
+                                                    const double* __restrict__ yn2, const double* __restrict__ gA,
+                                                    const double* __restrict__ H, const double* __restrict__ r,
+                                                    const double* __restrict__ xr, const double* __restrict__ y,
+                                                    double* __restrict__ dr, double* __restrict__ cpp) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= kc.n) return;
+    const double h = H[i];
+    double rs = 0.0, cs = 0.0;
+    for (int64_t j = 0; j < kc.m; ++j) {
+        const double dot = pair_term_dyn(kc.metric, D, xc + i * D, yc + j * D, 0.0);
+        const double q = exp2(fma(cA, h + dot, gA[j])) * y[j];
+        rs += q;
+        cs = fma(kc.s * (xn2[i] + yn2[j] - 2.0 * dot), q, cs);
+    }
+    const double w = xr[i] * r[i];
+    dr[i] = r[i] - w * rs;
+    cpp[i] = w * cs;
+}
+
+// Column sums of dc: S[k] = sum_j dc_j y~_jk (k < D), S[D] = sum_j dc_j,
+// S[D+1] = sum_j dc_j ||y~_j||^2; block b computes S[b] in a fixed order.
+__global__ void round_col_sums(Consts kc, int D, const double* __restrict__ yc, const double* __restrict__ yn2,
+                               const double* __restrict__ dc, double* __restrict__ S) {
+    __shared__ double sh[BLOCK];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t j = threadIdx.x; j < kc.m; j += BLOCK) {
+        const double v = b < D ? yc[j * D + b] : (b == D ? 1.0 : yn2[j]);
+        acc = fma(dc[j], v, acc);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) S[b] = sh[0];
+}
+
+// t_i = dr_i (C dc)_i and |dr_i| by a pass over all pairs (the l1 / l_inf costs, whose
+// C dc has no closed form): C_ij = -2 s P(x~_i, y~_j).
+__global__ __launch_bounds__(BLOCK) void round_rank_one_pairs(Consts kc, int D, const double* __restrict__ xc,
+                                                              const double* __restrict__ yc,
+                                                              const double* __restrict__ dr,
+                                                              const double* __restrict__ dc, double* __restrict__ t,
+                                                              double* __restrict__ absdr) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= kc.n) return;
+    double acc = 0.0;
+    for (int64_t j = 0; j < kc.m; ++j)
+        acc = fma(-2.0 * kc.s * pair_term_dyn(kc.metric, D, xc + i * D, yc + j * D, 0.0), dc[j], acc);
+    t[i] = dr[i] * acc;
+    absdr[i] = fabs(dr[i]);
+}
+
+// t_i = dr_i (C dc)_i and |dr_i|.
+__global__ void round_rank_one(Consts kc, int D, const double* __restrict__ xc, const double* __restrict__ xn2,
+                               const double* __restrict__ dr, const double* __restrict__ S,
+                               double* __restrict__ t, double* __restrict__ absdr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    double xs = 0.0;
+    for (int k = 0; k < D; ++k) xs = fma(xc[i * D + k], S[k], xs);
+    t[i] = dr[i] * kc.s * (xn2[i] * S[D] + S[D + 1] - 2.0 * xs);
+    absdr[i] = fabs(dr[i]);
 }
 
 // g^A_j for an arbitrary (lam, v): gA_j = -lam LOG2E (s yn2_j + K v_j).
@@ -796,11 +964,17 @@ __global__ void col_products(Consts kc, const double* __restrict__ c, const doub
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint sweep (envelope gradient): per row i, with p_ij = 2^(cfac (h_i + x~.y~) + g_j),
-//   S0_i = sum_j p_ij,  S1_i = sum_j p_ij y~_j;  grad_i = scale r_i (S0_i x~_i - S1_i).
-// part: [P][n][D+1] partial sums over column splits.
+// Adjoint sweep (envelope gradient): per row i, with p_ij = 2^(cfac (h_i + P_ij) + g_j),
+// partial sums S0_i, S1_i (d values) such that grad_i = 2 s r_i (S0_i x~_i - S1_i):
+//   squared Euclidean (dC/dx = 2 s (x - y)):  S0 = sum_j p_ij,  S1 = sum_j p_ij y~_j;
+//   l1 (dC/dx_k = s sign(x_k - y_k)):       S0 = 0,  S1_k = -1/2 sum_j p_ij sign(x_k - y_jk);
+//   l_inf (the coordinate k* of the largest |x_k - y_k|, the first one on ties):
+//                                           S0 = 0,  S1_k = -1/2 sum_j p_ij sign(x_k - y_jk) [k = k*].
+// (sign(0) = 0: the subgradient at a kink.)  part: [P][n][D+1] partial sums over column splits.
 // ---------------------------------------------------------------------------
-template <int D>
+__device__ __forceinline__ float sgnf(double v) { return v > 0.0 ? 1.f : (v < 0.0 ? -1.f : 0.f); }
+
+template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, const double* __restrict__ xc,
                                                        const double* __restrict__ yc,
                                                        const float* __restrict__ ycf,
@@ -819,19 +993,46 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, con
     double s0 = 0.0, s1[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) s1[k] = 0.0;
-    for (int64_t jb = j0; jb < j1; jb += UNROLL) {
-        float a0 = 0.f, a1[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) a1[k] = 0.f;
-        const int64_t je = min(j1, jb + UNROLL);
-        for (int64_t j = jb; j < je; ++j) {
-            double dot = h;
-#pragma unroll
-            for (int k = 0; k < D; ++k) dot = fma(x[k], yc[j * D + k], dot);
-            const float pij = fexp2(fma(cA, dot, gA[j]));
+    // one column's contribution to the FP32 block sums
+    auto term = [&](int64_t j, float& a0, float (&a1)[D]) {
+        const double dot = pair_term<M, D>(x, yc + j * D, h);
+        const float pij = fexp2(fma(cA, dot, gA[j]));
+        if constexpr (M == METRIC_SQEUCLID) {
             a0 += pij;
 #pragma unroll
             for (int k = 0; k < D; ++k) a1[k] = fmaf(pij, ycf[j * D + k], a1[k]);
+        } else if constexpr (M == METRIC_L1) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) a1[k] = fmaf(-0.5f * pij, sgnf(x[k] - yc[j * D + k]), a1[k]);
+        } else {
+            int ks = 0;
+            double best = -1.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double t = fabs(x[k] - yc[j * D + k]);
+                if (t > best) {
+                    best = t;
+                    ks = k;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (k == ks) a1[k] = fmaf(-0.5f * pij, sgnf(x[k] - yc[j * D + k]), a1[k]);
+        }
+    };
+    // blocks of UNROLL columns with a compile-time trip count (the column data are
+    // wave-uniform scalar loads, issued together), then the remainder
+    const int64_t nfull = (j1 - j0) / UNROLL;
+    for (int64_t c = 0; c <= nfull; ++c) {
+        const int64_t jb = j0 + c * UNROLL;
+        float a0 = 0.f, a1[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) a1[k] = 0.f;
+        if (c < nfull) {
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) term(jb + u, a0, a1);
+        } else {
+            for (int64_t j = jb; j < j1; ++j) term(j, a0, a1);
         }
         s0 += (double)a0;
 #pragma unroll
@@ -858,19 +1059,173 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep_dyn(Consts kc, int D, dou
     const int64_t j1 = min(kc.m, j0 + split);
     const int64_t ii = i < kc.n ? i : kc.n - 1;
     const double h = H[ii];
+    const double* xi = xc + ii * D;
     double* o = part + (p * kc.n + ii) * (D + 1);
     double s0 = 0.0;
     if (i < kc.n)
         for (int k = 0; k < D; ++k) o[1 + k] = 0.0;
     for (int64_t j = j0; j < j1; ++j) {
-        double dot = h;
-        for (int k = 0; k < D; ++k) dot = fma(xc[ii * D + k], yc[j * D + k], dot);
-        const double pij = (double)fexp2(fma(cA, dot, gA[j]));
-        s0 += pij;
-        if (i < kc.n)
-            for (int k = 0; k < D; ++k) o[1 + k] += pij * (double)ycf[j * D + k];
+        const double* yj = yc + j * D;
+        const double pij = (double)fexp2(fma(cA, pair_term_dyn(kc.metric, D, xi, yj, h), gA[j]));
+        if (kc.metric == METRIC_SQEUCLID) {
+            s0 += pij;
+            if (i < kc.n)
+                for (int k = 0; k < D; ++k) o[1 + k] += pij * (double)ycf[j * D + k];
+        } else if (kc.metric == METRIC_L1) {
+            if (i < kc.n)
+                for (int k = 0; k < D; ++k) o[1 + k] += -0.5 * pij * (double)sgnf(xi[k] - yj[k]);
+        } else {
+            int ks = 0;
+            double best = -1.0;
+            for (int k = 0; k < D; ++k) {
+                const double t = fabs(xi[k] - yj[k]);
+                if (t > best) {
+                    best = t;
+                    ks = k;
+                }
+            }
+            if (i < kc.n) o[1 + ks] += -0.5 * pij * (double)sgnf(xi[ks] - yj[ks]);
+        }
     }
     if (i < kc.n) o[0] = s0;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint with respect to the target points: per column j, with
+// X_ij = w_i 2^(cfac (k_i + P_ij) + g_j) (the column sweep's terms of X^t, w_i = r_i),
+// partial sums S0_j, S1_j (d values) such that grad_y_j = 2 s (S0_j y~_j - S1_j):
+//   squared Euclidean (dC/dy = 2 s (y - x)):  S0 = sum_i X_ij,  S1 = sum_i X_ij x~_i;
+//   l1 (dC/dy_k = -s sign(x_k - y_k)):      S0 = 0,  S1_k = 1/2 sum_i X_ij sign(x_ik - y_k);
+//   l_inf: the same on the coordinate of the largest |x_k - y_k| (first on ties).
+// part: [P][m][D+1] partial sums over row splits.
+// ---------------------------------------------------------------------------
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void adjoint_y_sweep(Consts kc, double cA, const double* __restrict__ xc,
+                                                         const float* __restrict__ xcf,
+                                                         const double* __restrict__ yc,
+                                                         const double* __restrict__ gA,
+                                                         const RowVar* __restrict__ rowvar,
+                                                         double* __restrict__ part, int64_t split) {
+    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t i0 = p * split;
+    const int64_t i1 = min(kc.n, i0 + split);
+    const int64_t jj = j < kc.m ? j : kc.m - 1;
+    double y[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) y[k] = yc[jj * D + k];
+    const double g = gA[jj];
+    double s0 = 0.0, s1[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) s1[k] = 0.0;
+    auto term = [&](int64_t i, float& a0, float (&a1)[D]) {
+        const RowVar rv = rowvar[i];
+        const double* xi = xc + i * D;
+        const double dot = pair_term<M, D>(y, xi, rv.k);   // P is symmetric
+        const float xij = rv.wA * fexp2(fma(cA, dot, g));
+        if constexpr (M == METRIC_SQEUCLID) {
+            a0 += xij;
+#pragma unroll
+            for (int k = 0; k < D; ++k) a1[k] = fmaf(xij, xcf[i * D + k], a1[k]);
+        } else if constexpr (M == METRIC_L1) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) a1[k] = fmaf(0.5f * xij, sgnf(xi[k] - y[k]), a1[k]);
+        } else {
+            int ks = 0;
+            double best = -1.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double t = fabs(xi[k] - y[k]);
+                if (t > best) {
+                    best = t;
+                    ks = k;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (k == ks) a1[k] = fmaf(0.5f * xij, sgnf(xi[k] - y[k]), a1[k]);
+        }
+    };
+    const int64_t nfull = (i1 - i0) / UNROLL;
+    for (int64_t c = 0; c <= nfull; ++c) {
+        const int64_t ib = i0 + c * UNROLL;
+        float a0 = 0.f, a1[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) a1[k] = 0.f;
+        if (c < nfull) {
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) term(ib + u, a0, a1);
+        } else {
+            for (int64_t i = ib; i < i1; ++i) term(i, a0, a1);
+        }
+        s0 += (double)a0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s1[k] += (double)a1[k];
+    }
+    if (j < kc.m) {
+        double* o = part + (p * kc.m + j) * (D + 1);
+        o[0] = s0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) o[1 + k] = s1[k];
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void adjoint_y_sweep_dyn(Consts kc, int D, double cA,
+                                                             const double* __restrict__ xc,
+                                                             const float* __restrict__ xcf,
+                                                             const double* __restrict__ yc,
+                                                             const double* __restrict__ gA,
+                                                             const RowVar* __restrict__ rowvar,
+                                                             double* __restrict__ part, int64_t split) {
+    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t i0 = p * split;
+    const int64_t i1 = min(kc.n, i0 + split);
+    const int64_t jj = j < kc.m ? j : kc.m - 1;
+    const double* yj = yc + jj * D;
+    const double g = gA[jj];
+    double* o = part + (p * kc.m + jj) * (D + 1);
+    double s0 = 0.0;
+    if (j < kc.m)
+        for (int k = 0; k < D; ++k) o[1 + k] = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const RowVar rv = rowvar[i];
+        const double* xi = xc + i * D;
+        const double xij = (double)rv.wA * (double)fexp2(fma(cA, pair_term_dyn(kc.metric, D, yj, xi, rv.k), g));
+        if (kc.metric == METRIC_SQEUCLID) {
+            s0 += xij;
+            if (j < kc.m)
+                for (int k = 0; k < D; ++k) o[1 + k] += xij * (double)xcf[i * D + k];
+        } else if (kc.metric == METRIC_L1) {
+            if (j < kc.m)
+                for (int k = 0; k < D; ++k) o[1 + k] += 0.5 * xij * (double)sgnf(xi[k] - yj[k]);
+        } else {
+            int ks = 0;
+            double best = -1.0;
+            for (int k = 0; k < D; ++k) {
+                const double t = fabs(xi[k] - yj[k]);
+                if (t > best) {
+                    best = t;
+                    ks = k;
+                }
+            }
+            if (j < kc.m) o[1 + ks] += 0.5 * xij * (double)sgnf(xi[ks] - yj[ks]);
+        }
+    }
+    if (j < kc.m) o[0] = s0;
+}
+
+__global__ void adjoint_y_finish(Consts kc, int D, int P, double scale, const double* __restrict__ yc,
+                                 const double* __restrict__ part, float* __restrict__ grad) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kc.m) return;
+    double s0 = 0.0;
+    for (int p = 0; p < P; ++p) s0 += part[((int64_t)p * kc.m + j) * (D + 1)];
+    for (int k = 0; k < D; ++k) {
+        double s1 = 0.0;
+        for (int p = 0; p < P; ++p) s1 += part[((int64_t)p * kc.m + j) * (D + 1) + 1 + k];
+        grad[j * D + k] = (float)(scale * (s0 * yc[j * D + k] - s1));
+    }
 }
 
 __global__ void adjoint_finish(Consts kc, int D, int P, double scale, const double* __restrict__ xc,

@@ -392,3 +392,70 @@ def test_tolerance_is_tested_from_the_first_iterate():
     assert L.residuals(L.plan(C, wl.r, st, 1.0), wl.r, wl.c)[2] <= 1e-3
     prev = L.lamp_dense(C, wl.r, wl.c, L.Params(eta=wl.eta), st.t - 1, 1.0, trace=False)[0]
     assert st.t == 1 or L.residuals(L.plan(C, wl.r, prev, 1.0), wl.r, wl.c)[2] > 1e-3
+
+
+def test_l1_and_linf_costs_by_definition_and_1d_wasserstein():
+    """The l1 / l_inf ground costs: written-out definitions on a tiny case, their relation on
+    the line (both equal |x - y| in d = 1), and the LP optimum with the l1 cost in d = 1 with
+    uniform marginals against the sorted-matching closed form (1/n) sum |x_(i) - y_(i)|."""
+    rng = np.random.default_rng(13)
+    x = rng.random((4, 3))
+    y = rng.random((5, 3))
+    C1 = L.l1_cost(x, y, 2.0)
+    Ci = L.linf_cost(x, y, 2.0)
+    for i in range(4):
+        for j in range(5):
+            diffs = [abs(x[i, k] - y[j, k]) for k in range(3)]
+            assert C1[i, j] == pytest.approx(2.0 * sum(diffs), rel=1e-15)
+            assert Ci[i, j] == pytest.approx(2.0 * max(diffs), rel=1e-15)
+    assert L.max_cost(x, y, "l1") == pytest.approx(float(np.max(C1)) / 2.0)
+    x1 = rng.random((7, 1))
+    y1 = rng.random((7, 1))
+    assert np.allclose(L.l1_cost(x1, y1, 1.0), L.linf_cost(x1, y1, 1.0))
+    u = np.full(7, 1.0 / 7)
+    opt, _ = exact.lp_ot(L.l1_cost(x1, y1, 1.0), u, u)
+    assert opt == pytest.approx(np.mean(np.abs(np.sort(x1[:, 0]) - np.sort(y1[:, 0]))), abs=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["l1", "linf"])
+def test_metric_envelope_gradient_by_finite_differences(kind):
+    """The l1 / l_inf envelope gradient against central differences of the row term at
+    generic points (no kinks within h)."""
+    wl = W.random_small(6, 9, 3, seed=17, eta=1e-1)
+    x, y = wl.x.astype(np.float64), wl.y.astype(np.float64)
+    s = 1.0 / L.max_cost(x, y, kind)
+    rng = np.random.default_rng(2)
+    nu = 0.3 * rng.standard_normal(wl.m)
+    lam = 7.0
+    g = L.envelope_grad_x_metric(x, y, wl.r, s, nu, lam, 1.0, kind)
+    h = 1e-6
+    for i in range(wl.n):
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd = (L.envelope_value_rows(xp, y, wl.r, s, nu, lam, 1.0, kind)[i]
+                  - L.envelope_value_rows(xm, y, wl.r, s, nu, lam, 1.0, kind)[i]) / (2 * h)
+            assert g[i, k] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+@pytest.mark.parametrize("kind", ["sqeuclid", "l1", "linf"])
+def test_envelope_gradient_wrt_targets_by_finite_differences(kind):
+    """The gradient with respect to the target points against central differences of the
+    whole dual value sum_i f_i (every row term depends on each y_j)."""
+    wl = W.random_small(5, 6, 2, seed=23, eta=1e-1)
+    x, y = wl.x.astype(np.float64), wl.y.astype(np.float64)
+    s = 1.0 / L.max_cost(x, y, kind)
+    rng = np.random.default_rng(4)
+    nu = 0.3 * rng.standard_normal(wl.m)
+    lam = 5.0
+    g = L.envelope_grad_y(x, y, wl.r, s, nu, lam, 1.0, kind)
+    h = 1e-6
+    for j in range(wl.m):
+        for k in range(2):
+            yp, ym = y.copy(), y.copy()
+            yp[j, k] += h
+            ym[j, k] -= h
+            fd = (np.sum(L.envelope_value_rows(x, yp, wl.r, s, nu, lam, 1.0, kind))
+                  - np.sum(L.envelope_value_rows(x, ym, wl.r, s, nu, lam, 1.0, kind))) / (2 * h)
+            assert g[j, k] == pytest.approx(fd, rel=1e-5, abs=1e-9)
