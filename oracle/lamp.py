@@ -490,8 +490,21 @@ def envelope_grad_x(x: np.ndarray, y: np.ndarray, r: np.ndarray, s: float, nu: n
 
 
 # --------------------------------------------------------------------------
-# D_t summand (Proposition infeas_bound(b)); parity unpinned beyond its identities
+# The partial sums D_t of Proposition infeas_bound(b)
 # --------------------------------------------------------------------------
+
+
+def dual_entropy(nu: np.ndarray, calpha: np.ndarray) -> float:
+    """H_c^alpha(nu) = sum_j c^alpha_j ((1+nu_j)/2 ln((1+nu_j)/2) + (1-nu_j)/2 ln((1-nu_j)/2)),
+    the negative dual entropy of Section 3.1."""
+    a = (1.0 + nu) / 2.0
+    b = (1.0 - nu) / 2.0
+    return float(calpha @ (a * np.log(a) + b * np.log(b)))
+
+
+def dual_entropy_grad(nu: np.ndarray, calpha: np.ndarray) -> np.ndarray:
+    """grad H_c^alpha(nu) = (1/2) c^alpha * ln((1+nu)/(1-nu))  (def:Ha_grad)."""
+    return 0.5 * calpha * np.log((1.0 + nu) / (1.0 - nu))
 
 
 def bregman_Ha(theta: np.ndarray, nu: np.ndarray, calpha: np.ndarray) -> float:
@@ -499,3 +512,41 @@ def bregman_Ha(theta: np.ndarray, nu: np.ndarray, calpha: np.ndarray) -> float:
     a = (theta + 1.0) / 2.0 * np.log((theta + 1.0) / (nu + 1.0))
     b = (1.0 - theta) / 2.0 * np.log((1.0 - theta) / (1.0 - nu))
     return float(calpha @ (a + b))
+
+
+def dt_sequence(C: np.ndarray, r: np.ndarray, c: np.ndarray, prm: Params, T: int,
+                cnorm: float | None = None):
+    """D_1, ..., D_T along Algorithm 2 from the start (def:sum_condition):
+
+        D_t = sum_{s=0}^{t-1} D_H(thetabar^{s+1} || thetahat^{s+1}) - D_H(thetabar^{s+1} || theta^s)
+                            + KL(Xbar^{s+1} || X^{s+1}) - KL(Xbar^{s+1} || X^s),
+
+    with X^s = diag(r) p^{eta_s}(nu^s) and Xbar^{s+1} = diag(r) p^{eta_{s+1}}(nubar^{s+1})
+    (Proposition infeas_bound), every KL taken on the dense matrices by its definition.
+    Returns (array of D_t, final state, list of the iterates' traces)."""
+    cnorm = float(np.max(np.abs(C))) if cnorm is None else cnorm
+    prm = prm.resolved(cnorm)
+    m = c.shape[0]
+    calpha = c + prm.alpha / m
+    st = lamp_init(m)
+    X_s = plan(C, r, st, cnorm)
+    D = 0.0
+    out = []
+    traces = []
+    for _ in range(T):
+        tr = LampTrace()
+        nxt = lamp_step(C, r, c, st, prm, cnorm, tr)
+        Xbar = r[:, None] * dual_to_primal(C, tr.nubar[0], nxt.lam, cnorm)
+        X_next = plan(C, r, nxt, cnorm)
+        D += (bregman_Ha(tr.theta_bar[0], tr.theta_hat[0], calpha)
+              - bregman_Ha(tr.theta_bar[0], st.theta, calpha)
+              + kl(Xbar, X_next) - kl(Xbar, X_s))
+        out.append(D)
+        traces.append(tr)
+        st, X_s = nxt, X_next
+    return np.array(out), st, traces
+
+
+def midpoint_bound(dt: float, t: int, m: int, alpha: float, cnorm: float) -> float:
+    """Right-hand side of (ineq:spp_midpoint_conv): 2||C||_inf (log m + (1+alpha) log 2 + D_t) / t."""
+    return 2.0 * cnorm * (math.log(m) + (1.0 + alpha) * math.log(2.0) + dt) / t

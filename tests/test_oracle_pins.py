@@ -459,3 +459,137 @@ def test_envelope_gradient_wrt_targets_by_finite_differences(kind):
             fd = (np.sum(L.envelope_value_rows(x, yp, wl.r, s, nu, lam, 1.0, kind))
                   - np.sum(L.envelope_value_rows(x, ym, wl.r, s, nu, lam, 1.0, kind))) / (2 * h)
             assert g[j, k] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+# ---------------------------------------------------------------- D_t (Proposition infeas_bound(b))
+
+
+def test_dt_symmetric_two_by_two_closed_form():
+    """C = [[0,1],[1,0]], r = c = (1/2, 1/2), eta = 0: theta = nu = nubar = 0 for all t, so
+    thetabar = thetahat = theta = 0 (no dual terms), Xbar^{s+1} = X^{s+1}, and each summand of
+    D_t is -KL(X^{s+1} || X^s).  Both rows of X^t are (a_t, 1 - a_t)/2 with
+    a_t = 1/(1 + e^{-t/2}), so D_t = -sum_{s<t} [a_{s+1} ln(a_{s+1}/a_s)
+    + (1 - a_{s+1}) ln((1 - a_{s+1})/(1 - a_s))]."""
+    C = np.array([[0.0, 1.0], [1.0, 0.0]])
+    r = c = np.array([0.5, 0.5])
+    T = 40
+    D, _, _ = L.dt_sequence(C, r, c, L.Params(eta=0.0), T)
+    a = [1.0 / (1.0 + math.exp(-t / 2.0)) for t in range(T + 1)]
+    ref, acc = [], 0.0
+    for s in range(T):
+        p, q = a[s + 1], a[s]
+        acc -= p * math.log(p / q) + (1.0 - p) * math.log((1.0 - p) / (1.0 - q))
+        ref.append(acc)
+    np.testing.assert_allclose(D, ref, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("eta", [0.0, 1e-2])
+def test_dt_kl_difference_matches_lemma_kl_diff(eta):
+    """Lemma kl_diff: with row(Xbar) = r the KL difference of each summand has the closed form
+        KL(Xbar^{s+1}||X^{s+1}) - KL(Xbar^{s+1}||X^s) = (lam_{s+1} - lam_s) <C, Xbar^{s+1}>
+            + K <col(Xbar^{s+1}), lam_{s+1} nu^{s+1} - lam_s nu^s> + <r, log Z^{s+1} - log Z^s>
+    (any eta; K = 2||C||_inf).  For eta = 0 and ||C||_inf = 1 (lam_t = t/2) it is the negative of
+    the printed identity  -<col(Xbar), thetabar^{s+1}> - <C, Xbar>/2 - <r, log Z^{s+1}> + <r, log Z^s>.
+    Both are checked against the dense KL of the oracle."""
+    C, r, c, *_ = _problem(7, 5, 2, seed=23)
+    C = C / C.max()
+    prm = L.Params(eta=eta).resolved(1.0)
+    st = L.lamp_init(5)
+    for s in range(25):
+        tr = L.LampTrace()
+        nxt = L.lamp_step(C, r, c, st, prm, 1.0, tr)
+        Xbar = r[:, None] * L.dual_to_primal(C, tr.nubar[0], nxt.lam, 1.0)
+        X_s, X_n = L.plan(C, r, st, 1.0), L.plan(C, r, nxt, 1.0)
+        dense = L.kl(Xbar, X_n) - L.kl(Xbar, X_s)
+        lz_s = L.log_normaliser(C, st.nu, st.lam, 1.0)
+        lz_n = L.log_normaliser(C, nxt.nu, nxt.lam, 1.0)
+        general = ((nxt.lam - st.lam) * float(np.sum(C * Xbar))
+                   + 2.0 * float(L.col(Xbar) @ (nxt.lam * nxt.nu - st.lam * st.nu))
+                   + float(r @ (lz_n - lz_s)))
+        assert dense == pytest.approx(general, rel=1e-10, abs=1e-13)
+        if eta == 0.0:
+            printed = (-float(L.col(Xbar) @ tr.theta_bar[0]) - 0.5 * float(np.sum(C * Xbar))
+                       - float(r @ lz_n) + float(r @ lz_s))
+            assert dense == pytest.approx(-printed, rel=1e-10, abs=1e-13)
+        st = nxt
+
+
+def test_dual_bregman_divergence_by_definition():
+    """D_H(theta||nu) = H(theta) - H(nu) - <grad H(nu), theta - nu> for the negative dual entropy
+    H_c^alpha of Section 3.1 equals both explicit forms (def:DHa_explicit, def:DHa); the gradient
+    (def:Ha_grad) matches central differences of H."""
+    rng = np.random.default_rng(5)
+    m = 9
+    calpha = rng.dirichlet(np.ones(m)) + 0.01 / m
+    for _ in range(5):
+        th = rng.uniform(-0.95, 0.95, m)
+        nu = rng.uniform(-0.95, 0.95, m)
+        g = L.dual_entropy_grad(nu, calpha)
+        by_def = L.dual_entropy(th, calpha) - L.dual_entropy(nu, calpha) - float(g @ (th - nu))
+        second = float(calpha / 2.0 @ np.log((1.0 - th ** 2) / (1.0 - nu ** 2))
+                       + th @ (L.dual_entropy_grad(th, calpha) - g))
+        assert L.bregman_Ha(th, nu, calpha) == pytest.approx(by_def, rel=1e-11, abs=1e-14)
+        assert second == pytest.approx(by_def, rel=1e-11, abs=1e-14)
+        h = 1e-6
+        fd = np.array([(L.dual_entropy(nu + h * e, calpha) - L.dual_entropy(nu - h * e, calpha)) / (2 * h)
+                       for e in np.eye(m)])
+        np.testing.assert_allclose(fd, g, rtol=1e-7, atol=1e-9)
+
+
+def test_dt_midpoint_bound_holds_at_the_lp_saddle_point():
+    """Proposition infeas_bound(b) with the exact saddle point of problem spp (eta = 0): X* from
+    the LP and theta* = (k - y_c)/(2||C||_inf) from its column duals, centred into [-1/2, 1/2]
+    (then D(theta*) = OPT, the dual function of def:dual_spp).  For every t:
+        min_{1<=s<=t} K(Xbar^s, theta*) - K(X*, thetabar^s) <= 2||C||_inf (log m + (1+a) log 2 + D_t)/t."""
+    for seed, (n, m) in [(31, (6, 5)), (32, (5, 7))]:
+        C, r, c, *_ = _problem(n, m, 2, seed=seed)
+        cnorm = float(C.max())
+        opt, X_star = exact.lp_ot(C, r, c)
+        _, _, yc = exact.lp_ot_duals(C, r, c)
+        k = 0.5 * (yc.max() + yc.min())
+        theta_star = (k - yc) / (2.0 * cnorm)
+        assert np.all(np.abs(theta_star) <= 0.5 + 1e-12)
+        assert L.dual_D(C, r, c, theta_star, cnorm) == pytest.approx(opt, rel=1e-8, abs=1e-12)
+        prm = L.Params(eta=0.0)
+        T = 60
+        D, _, traces = L.dt_sequence(C, r, c, prm, T, cnorm)
+        best = math.inf
+        lam = L.inv_eta_schedule(T, 1.0 / (2.0 * cnorm), 0.0)
+        for s in range(1, T + 1):
+            tr = traces[s - 1]   # the step s-1 -> s produced nubar^s and thetabar^s
+            Xbar = r[:, None] * L.dual_to_primal(C, tr.nubar[0], lam[s], cnorm)
+            gap = (L.saddle_K(C, Xbar, theta_star, c, cnorm)
+                   - L.saddle_K(C, X_star, tr.theta_bar[0], c, cnorm))
+            best = min(best, gap)
+            assert best <= L.midpoint_bound(D[s - 1], s, m, prm.alpha, cnorm) + 1e-12
+
+
+@pytest.mark.parametrize("eta", [0.0, 1e-2])
+def test_dt_summands_match_the_dual_and_primal_identities(eta):
+    """Every increment D_{s+1} - D_s of the oracle's D_t equals a closed form built from other
+    quantities: Lemma Dha_diff at theta* = thetahat^{s+1} gives the dual part,
+        D_H(thetabar||thetahat) - D_H(thetabar||theta^s) = -D_H(thetahat||theta^s)
+                                                           - <thetabar - thetahat, col(Xbar) - c>,
+    and the general-eta form of Lemma kl_diff the primal part (see the test above)."""
+    C, r, c, *_ = _problem(6, 7, 2, seed=41)
+    cnorm = float(C.max())
+    prm = L.Params(eta=eta)
+    T = 30
+    D, _, traces = L.dt_sequence(C, r, c, prm, T, cnorm)
+    res = prm.resolved(cnorm)
+    calpha = c + res.alpha / 7
+    st = L.lamp_init(7)
+    prev = 0.0
+    for s in range(T):
+        tr = traces[s]
+        nxt = L.lamp_step(C, r, c, st, res, cnorm)
+        tbar, that, colB = tr.theta_bar[0], tr.theta_hat[0], tr.colB[0]
+        dual = -L.bregman_Ha(that, st.theta, calpha) - float((tbar - that) @ (colB - c))
+        Xbar = r[:, None] * L.dual_to_primal(C, tr.nubar[0], nxt.lam, cnorm)
+        primal = ((nxt.lam - st.lam) * float(np.sum(C * Xbar))
+                  + 2.0 * cnorm * float(colB @ (nxt.lam * nxt.nu - st.lam * st.nu))
+                  + float(r @ (L.log_normaliser(C, nxt.nu, nxt.lam, cnorm)
+                               - L.log_normaliser(C, st.nu, st.lam, cnorm))))
+        assert D[s] - prev == pytest.approx(dual + primal, rel=1e-9, abs=1e-12)
+        prev = D[s]
+        st = nxt
