@@ -132,12 +132,19 @@ def primal_mirror_map(p0: np.ndarray, theta: np.ndarray, C: np.ndarray, tau: flo
     return np.exp(a - logsumexp(a, axis=1, keepdims=True))
 
 
+def dual_mirror_arg(theta0: np.ndarray, colp: np.ndarray, c: np.ndarray, calpha: np.ndarray,
+                    tau: float, cnorm: float) -> np.ndarray:
+    """The argument of tanh in def:closed_form_opt (the step's natural parameter):
+    2 tau ||C||_inf / c^alpha_j (col_r(p)_j - c_j) + (1/2) log((1 + theta0_j)/(1 - theta0_j))."""
+    return (2.0 * tau * cnorm / calpha * (colp - c)
+            + 0.5 * np.log((1.0 + theta0) / (1.0 - theta0)))
+
+
 def dual_mirror_map(theta0: np.ndarray, colp: np.ndarray, c: np.ndarray, calpha: np.ndarray,
                     tau: float, cnorm: float) -> np.ndarray:
     """M_tau^eta(theta0; p)_j = tanh( 2 tau ||C||_inf / c^alpha_j (col_r(p)_j - c_j)
     + (1/2) log((1 + theta0_j)/(1 - theta0_j)) )  (equation def:closed_form_opt)."""
-    return np.tanh(2.0 * tau * cnorm / calpha * (colp - c)
-                   + 0.5 * np.log((1.0 + theta0) / (1.0 - theta0)))
+    return np.tanh(dual_mirror_arg(theta0, colp, c, calpha, tau, cnorm))
 
 
 def tclip(theta: np.ndarray, beta: float) -> np.ndarray:
@@ -194,6 +201,8 @@ class LampTrace:
     colB: list = field(default_factory=list)      # col_r(p^{eta_{t+1}}(nubar^{t+1}))
     theta_bar: list = field(default_factory=list)
     theta_hat: list = field(default_factory=list)
+    theta_bar_arg: list = field(default_factory=list)   # thetabar = tanh(theta_bar_arg)
+    theta_hat_arg: list = field(default_factory=list)   # thetahat = tanh(theta_hat_arg)
     nubar: list = field(default_factory=list)
     nu: list = field(default_factory=list)        # nu^{t+1}
     theta: list = field(default_factory=list)     # theta^{t+1}
@@ -220,11 +229,13 @@ def lamp_step(C: np.ndarray, r: np.ndarray, c: np.ndarray, state: LampState, prm
     nubar = nu + w * (theta - nu)
     pA = dual_to_primal(C, nu, lam_t, cnorm)
     colA = col_r(pA, r)
-    theta_bar = dual_mirror_map(theta, colA, c, calpha, prm.tau2, cnorm)
+    a_bar = dual_mirror_arg(theta, colA, c, calpha, prm.tau2, cnorm)
+    theta_bar = np.tanh(a_bar)
     nu_next = nu + w * (theta_bar - nu)
     pB = dual_to_primal(C, nubar, lam_next, cnorm)
     colB = col_r(pB, r)
-    theta_hat = dual_mirror_map(theta, colB, c, calpha, prm.tau2, cnorm)
+    a_hat = dual_mirror_arg(theta, colB, c, calpha, prm.tau2, cnorm)
+    theta_hat = np.tanh(a_hat)
     theta_next = tclip(theta_hat, prm.beta)
 
     if trace is not None:
@@ -235,6 +246,8 @@ def lamp_step(C: np.ndarray, r: np.ndarray, c: np.ndarray, state: LampState, prm
         trace.colB.append(colB)
         trace.theta_bar.append(theta_bar)
         trace.theta_hat.append(theta_hat)
+        trace.theta_bar_arg.append(a_bar)
+        trace.theta_hat_arg.append(a_hat)
         trace.nubar.append(nubar)
         trace.nu.append(nu_next)
         trace.theta.append(theta_next)
@@ -514,6 +527,22 @@ def bregman_Ha(theta: np.ndarray, nu: np.ndarray, calpha: np.ndarray) -> float:
     return float(calpha @ (a + b))
 
 
+def softplus(z: np.ndarray) -> np.ndarray:
+    """ln(1 + e^z), evaluated without overflow."""
+    return np.maximum(z, 0.0) + np.log1p(np.exp(-np.abs(z)))
+
+
+def bregman_Ha_natural(a: np.ndarray, b: np.ndarray, calpha: np.ndarray) -> float:
+    """D_{H_c^alpha}(tanh a || tanh b) from the natural parameters a, b (the tanh arguments of
+    the mirror steps).  With theta = tanh a, (1 + theta)/2 = sigma(2a) and (1 - theta)/2 =
+    sigma(-2a), so each coordinate of def:DHa_explicit is the Bernoulli KL
+        sigma(2a) (2a - 2b) - softplus(2a) + softplus(2b),
+    the same value in exact arithmetic, and finite where tanh a rounds to +-1 in floating point
+    (a step with c^alpha_j ~ alpha/m and |col_j - c_j| >> c^alpha_j)."""
+    sig = 0.5 * (1.0 + np.tanh(a))          # sigma(2a)
+    return float(calpha @ (sig * (2.0 * a - 2.0 * b) - softplus(2.0 * a) + softplus(2.0 * b)))
+
+
 def dt_sequence(C: np.ndarray, r: np.ndarray, c: np.ndarray, prm: Params, T: int,
                 cnorm: float | None = None):
     """D_1, ..., D_T along Algorithm 2 from the start (def:sum_condition):
@@ -522,7 +551,9 @@ def dt_sequence(C: np.ndarray, r: np.ndarray, c: np.ndarray, prm: Params, T: int
                             + KL(Xbar^{s+1} || X^{s+1}) - KL(Xbar^{s+1} || X^s),
 
     with X^s = diag(r) p^{eta_s}(nu^s) and Xbar^{s+1} = diag(r) p^{eta_{s+1}}(nubar^{s+1})
-    (Proposition infeas_bound), every KL taken on the dense matrices by its definition.
+    (Proposition infeas_bound), every KL taken on the dense matrices by its definition and the
+    dual divergences from the steps' natural parameters (bregman_Ha_natural; theta^s is clipped
+    to |theta| <= tanh(beta/2), so its parameter is atanh theta^s).
     Returns (array of D_t, final state, list of the iterates' traces)."""
     cnorm = float(np.max(np.abs(C))) if cnorm is None else cnorm
     prm = prm.resolved(cnorm)
@@ -538,8 +569,9 @@ def dt_sequence(C: np.ndarray, r: np.ndarray, c: np.ndarray, prm: Params, T: int
         nxt = lamp_step(C, r, c, st, prm, cnorm, tr)
         Xbar = r[:, None] * dual_to_primal(C, tr.nubar[0], nxt.lam, cnorm)
         X_next = plan(C, r, nxt, cnorm)
-        D += (bregman_Ha(tr.theta_bar[0], tr.theta_hat[0], calpha)
-              - bregman_Ha(tr.theta_bar[0], st.theta, calpha)
+        a_bar, a_hat, b = tr.theta_bar_arg[0], tr.theta_hat_arg[0], np.arctanh(st.theta)
+        D += (bregman_Ha_natural(a_bar, a_hat, calpha)
+              - bregman_Ha_natural(a_bar, b, calpha)
               + kl(Xbar, X_next) - kl(Xbar, X_s))
         out.append(D)
         traces.append(tr)

@@ -593,3 +593,33 @@ def test_dt_summands_match_the_dual_and_primal_identities(eta):
         assert D[s] - prev == pytest.approx(dual + primal, rel=1e-9, abs=1e-12)
         prev = D[s]
         st = nxt
+
+
+def test_dual_bregman_from_natural_parameters_high_precision():
+    """bregman_Ha_natural(a, b) = D_H(tanh a || tanh b): against def:DHa_explicit evaluated with
+    60-digit decimal arithmetic (exact tanh, no rounding of 1 - theta), for moderate and for
+    saturated arguments (|a| up to 60, where tanh a is +-1 in FP64), and against the FP64
+    explicit form where that one is accurate."""
+    import decimal
+    ctx = decimal.Context(prec=60)
+    Dm = decimal.Decimal
+
+    def dha_exact(a, b, w):
+        tot = Dm(0)
+        for ai, bi, wi in zip(a, b, w):
+            ea, eb = ctx.exp(Dm(2 * ai)), ctx.exp(Dm(2 * bi))
+            pa, qa = ea / (ea + 1), 1 / (ea + 1)          # (1 + tanh a)/2, (1 - tanh a)/2
+            pb, qb = eb / (eb + 1), 1 / (eb + 1)
+            tot += Dm(wi) * (pa * ctx.ln(pa / pb) + qa * ctx.ln(qa / qb))
+        return float(tot)
+
+    rng = np.random.default_rng(9)
+    m = 7
+    w = rng.dirichlet(np.ones(m)) + 0.01 / m
+    for scale in [0.5, 3.0, 60.0]:
+        a = rng.uniform(-scale, scale, m)
+        b = rng.uniform(-0.55, 0.55, m)          # a clipped theta^s: |tanh b| <= 0.5
+        got = L.bregman_Ha_natural(a, b, w)
+        assert got == pytest.approx(dha_exact(a, b, w), rel=1e-12, abs=1e-14)
+        if scale <= 3.0:
+            assert got == pytest.approx(L.bregman_Ha(np.tanh(a), np.tanh(b), w), rel=1e-10, abs=1e-13)
