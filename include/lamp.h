@@ -90,23 +90,35 @@ typedef struct {
  *      0 runs exactly max_iter iterations.
  *   alpha, beta, tau1, tau2: <= 0 selects the default.
  *   check_every: iterations per host check of the stopping flag in lamp_solve
- *      (<= 0: 64).  The tolerance itself is tested on the device every iteration. */
+ *      (<= 0: 64).  The tolerance itself is tested on the device every iteration.
+ *   track_dt: 1 accumulates, every iteration, the summand of the partial sums D_t of
+ *      Proposition infeas_bound(b) (def:sum_condition) into lamp_state.dt_partial; it
+ *      adds one pass over the n x m pairs per iteration (the cost <C, Xbar^{t+1}>).
+ *      Only with precision LAMP_FP32 and outside the batched solve (else LAMP_EINVAL).
+ *      0: no tracking (the state's dt_partial becomes NaN once an iteration runs). */
 typedef struct {
     double eta, tol;
     int64_t max_iter;
     double alpha, beta, tau1, tau2;
     int32_t precision, check_every;
+    int32_t track_dt, reserved;
 } lamp_params;
 
 /* O(n + m) state of Algorithm 2 after t iterations (caller-owned).
  *   nu, theta: m FP64 each (device): nu^t, theta^t.  t = 0 with zeros is the
  *      start of Algorithm 2 (theta^0 = nu^0 = 0, eta_0 = infinity).
  *   t: iterations done; inv_eta: lam_t = 1/eta_t (0 at t = 0).
+ *   dt_partial: the part of D_t accumulated by the iterations so far (host value, 0 at
+ *      t = 0): for s < t, D_H(thetabar^{s+1}||thetahat^{s+1}) - D_H(thetabar^{s+1}||theta^s)
+ *      + (lam_{s+1} - lam_s) <C, Xbar^{s+1}> + K <col(Xbar^{s+1}), lam_{s+1} nu^{s+1} - lam_s nu^s>,
+ *      i.e. D_t without the telescoped <r, log Z^t - log Z^0> that lamp_certificate adds
+ *      (Lemma kl_diff, Lemma Dha_diff).  NaN once an iteration ran without track_dt.
  * The state fully determines the rest of the run: checkpointing is copying it. */
 typedef struct {
     double *nu, *theta;
     int64_t t;
     double inv_eta;
+    double dt_partial;
 } lamp_state;
 
 /* Optional per-iteration outputs of lamp_step (device, nullable each):
@@ -134,6 +146,10 @@ typedef struct {
     int64_t t;
     double rounded_cost;     /* <C, Round(X^t)>, Round of Algorithm 3 applied to X^t
                                 on the device (FP64), without forming X               */
+    double dt;               /* D_t (def:sum_condition): state.dt_partial + <r, log Z^t>
+                                - log m; NaN unless every iteration tracked it        */
+    double midpoint_bound;   /* 2||C||_inf (log m + (1 + alpha) log 2 + D_t) / t, the
+                                right-hand side of ineq:spp_midpoint_conv (eta = 0)  */
 } lamp_cert;
 
 typedef struct {
@@ -215,7 +231,7 @@ lamp_status lamp_sweep_times(const lamp_problem *prob, const lamp_params *params
  * The launch shape (sweep items per phase, grid size) is chosen by timing candidate
  * shapes on the batch (autotuner, cached per batch shape for the process).
  *   probs[count], states[count], outs[count] (host arrays of the structs above);
- *   all problems run LAMP_FP32 with the same params; their costs must share one
+ *   all problems run LAMP_FP32 with the same params (track_dt = 0); their costs must share one
  *   ||C||_inf (e.g. all normalised: cost_scale <= 0) and their states one t and lam_t.
  * The workspace (lamp_batch_workspace_bytes) holds every problem's scratch. */
 size_t lamp_batch_workspace_bytes(const lamp_problem *probs, int32_t count, const lamp_params *params);

@@ -40,11 +40,13 @@ class Problem(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("eta", c_double), ("tol", c_double), ("max_iter", c_int64),
                 ("alpha", c_double), ("beta", c_double), ("tau1", c_double), ("tau2", c_double),
-                ("precision", c_int32), ("check_every", c_int32)]
+                ("precision", c_int32), ("check_every", c_int32),
+                ("track_dt", c_int32), ("reserved", c_int32)]
 
 
 class State(ctypes.Structure):
-    _fields_ = [("nu", c_void_p), ("theta", c_void_p), ("t", c_int64), ("inv_eta", c_double)]
+    _fields_ = [("nu", c_void_p), ("theta", c_void_p), ("t", c_int64), ("inv_eta", c_double),
+                ("dt_partial", c_double)]
 
 
 class Trace(ctypes.Structure):
@@ -56,7 +58,8 @@ class Cert(ctypes.Structure):
     _fields_ = [("col_res", c_double), ("row_res", c_double), ("cost", c_double),
                 ("dual_theta", c_double), ("dual_nu", c_double), ("primal_penalized", c_double),
                 ("gap", c_double), ("prop_bound", c_double), ("cost_scale", c_double),
-                ("cost_norm", c_double), ("t", c_int64), ("rounded_cost", c_double)]
+                ("cost_norm", c_double), ("t", c_int64), ("rounded_cost", c_double),
+                ("dt", c_double), ("midpoint_bound", c_double)]
 
 
 class Report(ctypes.Structure):

@@ -70,35 +70,39 @@ class Problem:
 
 def make_params(eta: float = 0.0, tol: float = 0.0, max_iter: int = 1000, alpha: float = 0.0,
                 beta: float = 0.0, tau1: float = 0.0, tau2: float = 0.0,
-                check_every: int = 64, precision: str = "fp32") -> L.Params:
+                check_every: int = 64, precision: str = "fp32", track_dt: bool = False) -> L.Params:
     """Algorithm 2 parameters; zeros select the defaults of Appendix E.  precision is one of
-    fp32 (FP64 arguments, FP32 exponentials), fp32_mfma, bf16_mfma, fp16_mfma."""
+    fp32 (FP64 arguments, FP32 exponentials), fp32_mfma, bf16_mfma, fp16_mfma.  track_dt
+    accumulates the partial sums D_t of Proposition infeas_bound(b) in the state (fp32 only)."""
     return L.Params(eta, tol, int(max_iter), alpha, beta, tau1, tau2, L.PRECISIONS[precision],
-                    int(check_every))
+                    int(check_every), int(bool(track_dt)), 0)
 
 
 @dataclass
 class State:
-    """O(n + m) state: nu^t, theta^t (FP64 device), t and lam_t = 1/eta_t."""
+    """O(n + m) state: nu^t, theta^t (FP64 device), t, lam_t = 1/eta_t and the D_t summands
+    accumulated so far (NaN unless every iteration tracked them)."""
     nu: torch.Tensor
     theta: torch.Tensor
     t: int = 0
     inv_eta: float = 0.0
+    dt_partial: float = 0.0
 
     @staticmethod
     def fresh(m: int, device="cuda") -> "State":
         z = torch.zeros(m, dtype=torch.float64, device=device)
-        return State(z, z.clone(), 0, 0.0)
+        return State(z, z.clone(), 0, 0.0, 0.0)
 
     def struct(self) -> L.State:
-        return L.State(self.nu.data_ptr(), self.theta.data_ptr(), self.t, self.inv_eta)
+        return L.State(self.nu.data_ptr(), self.theta.data_ptr(), self.t, self.inv_eta, self.dt_partial)
 
     def update(self, s: L.State) -> None:
         self.t = int(s.t)
         self.inv_eta = float(s.inv_eta)
+        self.dt_partial = float(s.dt_partial)
 
     def clone(self) -> "State":
-        return State(self.nu.clone(), self.theta.clone(), self.t, self.inv_eta)
+        return State(self.nu.clone(), self.theta.clone(), self.t, self.inv_eta, self.dt_partial)
 
 
 def cost_scale(prob: Problem) -> tuple[float, float]:

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <limits>
 #include <cstring>
 #include <cstdlib>
 #include <vector>
@@ -71,7 +72,7 @@ int64_t choose_split(int64_t owned, int64_t len, int64_t target = TARGET_BLOCKS)
 
 struct Layout {
     size_t ctrl, sched, xc, yc, xcf, ycf, xn2, yn2, gtab, H, rowvar, rpart, cpart, nu1, th1, respart,
-        scratch, small, xop, yop, kf, wAf, wBf, gtabf, rowq, total;
+        dtrow, dtpart, scratch, small, xop, yop, kf, wAf, wBf, gtabf, rowq, total;
     int64_t split_r, P_r, split_c, P_c;
     // matrix-core forms
     int prec, KP, esize;
@@ -180,6 +181,9 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     L.nu1 = take(sizeof(double) * m);
     L.th1 = take(sizeof(double) * m);
     L.respart = take(sizeof(double) * cdiv(m, BLOCK));
+    // D_t tracking: per-row cost terms and per-block summands
+    L.dtrow = take(sizeof(double) * n);
+    L.dtpart = take(sizeof(double) * cdiv(m, BLOCK));
     // certificate: 4 arrays of max(n, m), Round: 9 more and d + 2 column sums
     L.scratch = take(sizeof(double) * (13 * std::max(n, m) + d + 2));
     L.small = take(sizeof(double) * 64);
@@ -233,6 +237,9 @@ lamp_status check_params(const lamp_params* q) {
     if (q->max_iter < 0) return fail(LAMP_EINVAL, "max_iter must be >= 0");
     if (q->precision != LAMP_FP32 && !is_mfma(q->precision))
         return fail(LAMP_EINVAL, "unknown precision %d", q->precision);
+    if (q->track_dt != 0 && q->track_dt != 1) return fail(LAMP_EINVAL, "track_dt must be 0 or 1");
+    if (q->track_dt && q->precision != LAMP_FP32)
+        return fail(LAMP_EINVAL, "D_t tracking runs with precision LAMP_FP32 only");
     return LAMP_OK;
 }
 
@@ -702,13 +709,40 @@ struct IterArgs {
     TraceCols tc;
     double* log_za;
     double* log_zb;
+    bool track_dt;
 };
+
+// <C, Xbar^{t+1}> of the running iteration into ctrl->dt_cost (D_t tracking); runs after
+// the row sweep, with the offsets and column table that sweep used.
+void launch_dt_cost(const lamp_problem* p, const Layout& L, Consts kc, void* ws, hipStream_t st) {
+    Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+    const Sched* sch = at<Sched>(ws, L.sched);
+    const double* xc = at<double>(ws, L.xc);
+    const double* yc = at<double>(ws, L.yc);
+    const double* xn2 = at<double>(ws, L.xn2);
+    const double* yn2 = at<double>(ws, L.yn2);
+    const double2* gt = at<double2>(ws, L.gtab);
+    const double* H = at<double>(ws, L.H);
+    double* out = at<double>(ws, L.dtrow);
+    const int d = p->d;
+    const bool done = by_metric(kc.metric, [&](auto m) {
+        return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
+            hipLaunchKernelGGL((dt_cost_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0,
+                               st, ctrl, sch, kc, xc, yc, xn2, yn2, gt, H, p->r, out);
+        });
+    });
+    if (!done)
+        hipLaunchKernelGGL(dt_cost_rows_dyn, grid1(kc.n), dim3(BLOCK), 0, st, ctrl, sch, kc, d, xc, yc, xn2, yn2, gt,
+                           H, p->r, out);
+    hipLaunchKernelGGL(dt_cost_total, dim3(1), dim3(1024), 0, st, ctrl, (const double*)out, kc.n);
+}
 
 void launch_iteration(const lamp_problem* p, const Layout& L, Consts kc, void* ws, const IterArgs& ia,
                       hipStream_t st) {
     Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
     const Sched* sch = at<Sched>(ws, L.sched);
     launch_row_sweep(L, kc, p->d, ws, st);
+    if (ia.track_dt) launch_dt_cost(p, L, kc, ws, st);
     RowVarF32 rf{nullptr, nullptr, nullptr, 0};
     if (is_mfma(L.prec)) rf = rowvar_f32(L, ws);
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, ctrl, sch, kc, p->d, at<double>(ws, L.xc),
@@ -718,11 +752,14 @@ void launch_iteration(const lamp_problem* p, const Layout& L, Consts kc, void* w
     launch_col_sweep(L, kc, p->d, ws, st);
     hipLaunchKernelGGL(dual_update, grid1(kc.m), dim3(BLOCK), 0, st, ctrl, sch, kc, at<double2>(ws, L.cpart),
                        col_parts(L), p->c, at<double>(ws, L.yn2), ia.buf, at<double2>(ws, L.gtab),
-                       gtabf_ptr(L, ws), L.m_pad, at<double>(ws, L.respart), ia.tc);
+                       gtabf_ptr(L, ws), L.m_pad, at<double>(ws, L.respart), ia.tc,
+                       ia.track_dt ? at<double>(ws, L.dtpart) : (double*)nullptr);
 }
 
 lamp_status upload_ctrl(void* ws, const Layout& L, int64_t t, int64_t t_end, int64_t t_base, double tol,
-                        hipStream_t st, Ctrl* host) {
+                        hipStream_t st, Ctrl* host, double dt_acc = 0.0) {
+    host->dt_acc = dt_acc;
+    host->dt_cost = 0.0;
     host->t = t;
     host->t_end = t_end;
     host->t_base = t_base;
@@ -787,6 +824,17 @@ lamp_status state_normalisers(const lamp_problem* p, const lamp_params* q, const
 __global__ void gA_extract(int64_t m, int64_t par, const double2* __restrict__ gtab2, double* __restrict__ gA) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j < m) gA[j] = gtab2[par * m + j].x;
+}
+
+// r_i log Z_i of X^t from the certificate row pass: with p_ij = 2^(cA (h_i + P_ij) + g^A_j)
+// and psum_i = sum_j p_ij,  log Z_i = ln sum_j exp(-lam (C_ij + K nu_j))
+//                                  = ln psum_i - ln2 cA h_i - lam s |x~_i|^2.
+__global__ void normaliser_terms(Consts kc, double cA, double lam, const double* __restrict__ psum,
+                                 const double* __restrict__ H, const double* __restrict__ xn2,
+                                 const double* __restrict__ r, double* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    out[i] = r[i] * (log(psum[i]) - LN2 * cA * H[i] - lam * kc.s * xn2[i]);
 }
 
 __global__ void col_residual(Consts kc, const double2* __restrict__ cpart, int P, const double* __restrict__ c,
@@ -1215,8 +1263,9 @@ lamp_status lamp_step(const lamp_problem* prob, const lamp_params* params, lamp_
     fill_sched(tab, 1, state->inv_eta, R.tau1, params->eta);
     HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched), hipMemcpyHostToDevice, st));
     Ctrl hc;
-    if ((e = upload_ctrl(ws, L, t, t + 1, t, 0.0, st, &hc)) != LAMP_OK) return e;
+    if ((e = upload_ctrl(ws, L, t, t + 1, t, 0.0, st, &hc, state->dt_partial)) != LAMP_OK) return e;
     IterArgs ia{};
+    ia.track_dt = params->track_dt != 0;
     ia.buf.nu[t & 1] = state->nu;
     ia.buf.theta[t & 1] = state->theta;
     ia.buf.nu[(t + 1) & 1] = at<double>(ws, L.nu1);
@@ -1239,6 +1288,7 @@ lamp_status lamp_step(const lamp_problem* prob, const lamp_params* params, lamp_
     if (res_out) *res_out = hc.res_last;
     state->t = t + 1;
     state->inv_eta = tab[0].lamB;
+    state->dt_partial = ia.track_dt ? hc.dt_acc : std::numeric_limits<double>::quiet_NaN();
     return LAMP_OK;
 }
 
@@ -1273,6 +1323,7 @@ lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp
     const int K = params->check_every > 0 ? params->check_every : 64;
 
     IterArgs ia{};
+    ia.track_dt = params->track_dt != 0;
     ia.buf.nu[t0 & 1] = state->nu;
     ia.buf.theta[t0 & 1] = state->theta;
     ia.buf.nu[(t0 + 1) & 1] = at<double>(ws, L.nu1);
@@ -1285,7 +1336,7 @@ lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp
     HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice, st));
     Ctrl hc;
     int64_t t_end = std::min(t_stop, t_base + TAB);
-    if ((e = upload_ctrl(ws, L, t0, t_end, t_base, params->tol, st, &hc)) != LAMP_OK) return e;
+    if ((e = upload_ctrl(ws, L, t0, t_end, t_base, params->tol, st, &hc, state->dt_partial)) != LAMP_OK) return e;
 
     hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
                        kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab), gtabf_ptr(L, ws), L.m_pad);
@@ -1348,6 +1399,7 @@ lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp
     for (int64_t k = t_base; k < t_cur; ++k) lam = next_lam(lam, R.tau1, params->eta);
     state->t = t_cur;
     state->inv_eta = lam;
+    if (t_cur != t0) state->dt_partial = ia.track_dt ? hc.dt_acc : std::numeric_limits<double>::quiet_NaN();
     if (out) {
         out->iters = t_cur - t0;
         out->t = t_cur;
@@ -1427,8 +1479,13 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, cpp, kc.n, kc.n, 1, small + 7);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, tr1, kc.n, kc.n, 1, small + 8);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, absdr, kc.n, kc.n, 1, small + 9);
+    // <r, log Z^t> for D_t (the telescoped normaliser term of Lemma kl_diff)
+    double* rlz = at<double>(ws, L.dtrow);   // n
+    hipLaunchKernelGGL(normaliser_terms, grid1(kc.n), dim3(BLOCK), 0, st, kc, cA, state->inv_eta, psum,
+                       at<double>(ws, L.H), at<double>(ws, L.xn2), prob->r, rlz);
+    hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, rlz, kc.n, kc.n, 1, small + 10);
     HIPCHK(hipGetLastError());
-    double h[10];
+    double h[11];
     HIPCHK(hipMemcpyAsync(h, small, sizeof(h), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     out->row_res = h[0];
@@ -1441,6 +1498,11 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     out->prop_bound = 4.0 * R.cnorm * out->col_res + 2.0 * R.cnorm * std::log((double)kc.m) / (double)state->t;
     // <C, Round(X)>; the rank-one correction is skipped when ||dr||_1 = 0 (then dc = 0 too)
     out->rounded_cost = h[7] + (h[9] > 0.0 ? h[8] / h[9] : 0.0);
+    // D_t = (summands accumulated by the iterations) + <r, log Z^t> - <r, log Z^0>, log Z^0 = log m
+    const double logm = std::log((double)kc.m);
+    out->dt = state->dt_partial + h[10] - logm;
+    out->midpoint_bound =
+        2.0 * R.cnorm * (logm + (1.0 + R.alpha) * std::log(2.0) + out->dt) / (double)state->t;
     out->cost_scale = R.s;
     out->cost_norm = R.cnorm;
     out->t = state->t;
@@ -1570,6 +1632,7 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
     if (!probs || !states || count < 1) return fail(LAMP_EINVAL, "empty batch or NULL arrays");
     if ((e = check_params(params)) != LAMP_OK) return e;
     if (params->precision != LAMP_FP32) return fail(LAMP_EINVAL, "the batching form runs the LAMP_FP32 form");
+    if (params->track_dt) return fail(LAMP_EINVAL, "D_t tracking is not available in the batching form");
     for (int p = 0; p < count; ++p) {
         if ((e = check_problem(&probs[p])) != LAMP_OK) return e;
         if (probs[p].metric != LAMP_SQEUCLID)
@@ -1672,6 +1735,7 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
     HIPCHK(hipStreamSynchronize(st));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     bool all_conv = true;
+    const double lam0 = states[0].inv_eta;   // every state starts at (t0, lam0); states[0] is rewritten below
     for (int p = 0; p < count; ++p) {
         const int64_t tp = hc[p].done ? hc[p].t_done : hc[p].t;
         if ((tp & 1) != (t0 & 1)) {
@@ -1679,10 +1743,11 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
             HIPCHK(hipMemcpyAsync(states[p].theta, run.th1[p], sizeof(double) * probs[p].m, hipMemcpyDeviceToDevice,
                                   st));
         }
-        double lam = states[0].inv_eta;
+        double lam = lam0;
         for (int64_t k = t0; k < tp; ++k) lam = next_lam(lam, run.tau1, params->eta);
         states[p].t = tp;
         states[p].inv_eta = lam;
+        if (tp != t0) states[p].dt_partial = std::numeric_limits<double>::quiet_NaN();
         const bool conv = hc[p].done && !hc[p].err;
         all_conv = all_conv && conv;
         if (outs) {

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(BLOCK) void batch_dual_update(const ProbDesc* __res
         const Item it = items[k];
         const ProbDesc& P = pd[it.prob];
         dual_update_body(P.ctrl, sched, P.kc, P.cpart, P.P_c, P.c, P.yn2, P.buf, P.gtab, nullptr, 0, P.respart,
-                         TraceCols{nullptr, nullptr, nullptr, nullptr}, it.bx, 0, P.n_dual_blocks);
+                         TraceCols{nullptr, nullptr, nullptr, nullptr}, nullptr, it.bx, 0, P.n_dual_blocks);
     }
 }
 

@@ -56,6 +56,8 @@ struct Ctrl {
     uint32_t counter;   // last-block detection of dual_update
     double tol;         // 0: never stop early
     double res_last;    // ||col(X^t) - c||_1 of the last completed iteration
+    double dt_acc;      // accumulated D_t summands without the normaliser telescope
+    double dt_cost;     // <C, Xbar^{t+1}> of the running iteration (D_t tracking)
 };
 
 // Per-iteration scalars, filled on the host in FP64 by the recursion of step:eta_update.
@@ -640,11 +642,121 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_dyn(const Ctrl* ctrl, const S
 }
 
 // ---------------------------------------------------------------------------
+// D_t tracking (Proposition infeas_bound(b)): <C, Xbar^{t+1}> of the second coupling
+// of iteration t, Xbar^{t+1} = diag(r) p^{eta_{t+1}}(nubar^{t+1}).  Per row, with the
+// row sweep's offset h_i and column table g^B:
+//     S_i = sum_j 2^(cB (h_i + P_ij) + g^B_j),   T_i = sum_j 2^(...) C_ij,
+//     out_i = r_i T_i / S_i  (the normaliser cancels),  C_ij = s (|x~_i|^2 + |y~_j|^2 - 2 P_ij).
+// Same arithmetic as the row sweep (FP64 exponent, FP32 exponential and per-block
+// sums, FP64 across blocks); one thread per row over all columns.
+// ---------------------------------------------------------------------------
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void dt_cost_rows(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                      const double* __restrict__ xc,
+                                                      const double* __restrict__ yc,
+                                                      const double* __restrict__ xn2,
+                                                      const double* __restrict__ yn2,
+                                                      const double2* __restrict__ gtab2,
+                                                      const double* __restrict__ H,
+                                                      const double* __restrict__ r,
+                                                      double* __restrict__ out) {
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t ii = i < kc.n ? i : kc.n - 1;
+    double x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = xc[ii * D + k];
+    const double h = H[ii];
+    const double xa = kc.s * xn2[ii];
+    double S = 0.0, T = 0.0;
+    for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
+        float aS = 0.f, aT = 0.f;
+        const int64_t je = min(kc.m, jb + UNROLL);
+        for (int64_t j = jb; j < je; ++j) {
+            const double dot = pair_term<M, D>(x, yc + j * D, 0.0);
+            const float p = fexp2(fma(cB, h + dot, g[j].y));
+            const double cij = fma(-2.0 * kc.s, dot, xa + kc.s * yn2[j]);
+            aS += p;
+            aT = fmaf(p, (float)cij, aT);
+        }
+        S += (double)aS;
+        T += (double)aT;
+    }
+    if (i < kc.n) out[i] = r[i] * T / S;
+}
+
+__global__ __launch_bounds__(BLOCK) void dt_cost_rows_dyn(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+                                                          const double* __restrict__ xc,
+                                                          const double* __restrict__ yc,
+                                                          const double* __restrict__ xn2,
+                                                          const double* __restrict__ yn2,
+                                                          const double2* __restrict__ gtab2,
+                                                          const double* __restrict__ H,
+                                                          const double* __restrict__ r,
+                                                          double* __restrict__ out) {
+    if (halted(ctrl)) return;
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t ii = i < kc.n ? i : kc.n - 1;
+    const double h = H[ii];
+    const double xa = kc.s * xn2[ii];
+    double S = 0.0, T = 0.0;
+    for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
+        float aS = 0.f, aT = 0.f;
+        const int64_t je = min(kc.m, jb + UNROLL);
+        for (int64_t j = jb; j < je; ++j) {
+            const double dot = pair_term_dyn(kc.metric, D, xc + ii * D, yc + j * D, 0.0);
+            const float p = fexp2(fma(cB, h + dot, g[j].y));
+            const double cij = fma(-2.0 * kc.s, dot, xa + kc.s * yn2[j]);
+            aS += p;
+            aT = fmaf(p, (float)cij, aT);
+        }
+        S += (double)aS;
+        T += (double)aT;
+    }
+    if (i < kc.n) out[i] = r[i] * T / S;
+}
+
+// ctrl->dt_cost = sum_i out_i, one block, fixed order (deterministic).
+__global__ __launch_bounds__(1024) void dt_cost_total(Ctrl* ctrl, const double* __restrict__ vals, int64_t n) {
+    if (halted(ctrl)) return;
+    __shared__ double sh[1024];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) a += vals[i];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctrl->dt_cost = sh[0];
+}
+
+// ---------------------------------------------------------------------------
 // Dual update (S5-S6 of Algorithm 2), residual, next column table, stop flag.
 // State is double-buffered by iteration parity: iteration t reads buffer t&1 and
 // writes buffer (t+1)&1, so the iterate that met the tolerance is never
 // overwritten.
 // ---------------------------------------------------------------------------
+// Dual part of the D_t summand for one column, from the natural parameters of the mirror
+// steps (thetabar = tanh abar, thetahat = tanh ahat, theta^t = tanh a):
+//   D(thetabar||thetahat) - D(thetabar||theta^t)  per coordinate of def:DHa_explicit, with
+//   (1 + tanh x)/2 = sigma(2x), is  2 sigma(2 abar) (a - ahat) + softplus(2 ahat) - softplus(2 a):
+// exact where tanh rounds to +-1 (a step with c^alpha_j ~ alpha/m and |col_j - c_j| >> c^alpha_j).
+__device__ __forceinline__ double softplus(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
+
+__device__ __forceinline__ double dual_dt_term(double abar, double ahat, double a) {
+    const double sig = 0.5 * (1.0 + tanh(abar));   // sigma(2 abar)
+    return 2.0 * sig * (a - ahat) + softplus(2.0 * ahat) - softplus(2.0 * a);
+}
+
 struct DualBufs {
     double* nu[2];
     double* theta[2];
@@ -660,12 +772,13 @@ __device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched,
                                                      const double* __restrict__ yn2, DualBufs buf,
                                                      double2* __restrict__ gtab2,
                                                      float2* __restrict__ gtabf, int64_t m_pad,
-                                                     double* __restrict__ respart, TraceCols tr, int64_t bx_, int64_t by_, int64_t nb_) {
+                                                     double* __restrict__ respart, TraceCols tr,
+                                                     double* __restrict__ dtpart, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
     const int64_t j = (int64_t)bx_ * BLOCK + threadIdx.x;
-    double res = 0.0;
+    double res = 0.0, dtj = 0.0;
     int bad = 0;
     if (j < kc.m) {
         double colA = 0.0, colB = 0.0;
@@ -683,8 +796,10 @@ __device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched,
         const double nu = nu_r[j], th = th_r[j];
         const double a = atanh(th);
         // closed form of the dual mirror map (def:closed_form_opt)
-        const double tbar = tanh(a + kc.kappa * (colA - cj) / calpha);
-        const double that = tanh(a + kc.kappa * (colB - cj) / calpha);
+        const double abar = a + kc.kappa * (colA - cj) / calpha;
+        const double ahat = a + kc.kappa * (colB - cj) / calpha;
+        const double tbar = tanh(abar);
+        const double that = tanh(ahat);
         const double nun = nu + sc.w * (tbar - nu);            // step:lamp_main_nu
         const double thn = fmin(fmax(that, -kc.clipb), kc.clipb);  // tclip
         nu_w[j] = nun;
@@ -699,26 +814,37 @@ __device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched,
         if (gtabf) gtabf[((t + 1) & 1) * m_pad + j] = make_float2((float)gn.x, (float)gn.y);
         res = fabs(colA - cj);
         bad = !(isfinite(nun) && isfinite(thn) && isfinite(colA) && isfinite(colB)) || fabs(th) >= 1.0;
+        if (dtpart) {
+            // D_t summand of this column (Lemma kl_diff, def:DHa_explicit):
+            // c^a (D(tbar||that) - D(tbar||th)) + K colB (lam_{t+1} nu^{t+1} - lam_t nu^t)
+            dtj = calpha * dual_dt_term(abar, ahat, a) + kc.K * colB * (sc.lamB * nun - sc.lamA * nu);
+        }
         if (tr.col_a) tr.col_a[j] = colA;
         if (tr.col_b) tr.col_b[j] = colB;
         if (tr.theta_bar) tr.theta_bar[j] = tbar;
         if (tr.theta_hat) tr.theta_hat[j] = that;
     }
-    // block reduction of the residual (fixed order: deterministic)
+    // block reduction of the residual (and D_t summand; fixed order: deterministic)
     __shared__ double sh[BLOCK];
+    __shared__ double shd[BLOCK];
     __shared__ int shbad;
     if (threadIdx.x == 0) shbad = 0;
     __syncthreads();
     if (bad) atomicOr(&shbad, 1);
     sh[threadIdx.x] = res;
+    shd[threadIdx.x] = dtj;
     __syncthreads();
     for (int o = BLOCK / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if (threadIdx.x < o) {
+            sh[threadIdx.x] += sh[threadIdx.x + o];
+            shd[threadIdx.x] += shd[threadIdx.x + o];
+        }
         __syncthreads();
     }
     __shared__ bool last;
     if (threadIdx.x == 0) {
         respart[bx_] = sh[0];
+        if (dtpart) dtpart[bx_] = shd[0];
         if (shbad) atomicOr(&ctrl->err, 1);
         __threadfence();
         unsigned prev = atomicAdd(&ctrl->counter, 1u);
@@ -741,6 +867,12 @@ __device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched,
             ctrl->done = 1;
             ctrl->t_done = t;
         } else {
+            if (dtpart) {
+                // the step is taken: its D_t summand joins the sum
+                double d = (sc.lamB - sc.lamA) * ctrl->dt_cost;
+                for (unsigned b = 0; b < nb_; ++b) d += __hip_atomic_load(&dtpart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ctrl->dt_acc += d;
+            }
             ctrl->t = t + 1;
         }
         __threadfence();
@@ -753,8 +885,9 @@ __global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sc
                                                      const double* __restrict__ yn2, DualBufs buf,
                                                      double2* __restrict__ gtab2,
                                                      float2* __restrict__ gtabf, int64_t m_pad,
-                                                     double* __restrict__ respart, TraceCols tr) {
-    dual_update_body(ctrl, sched, kc, cpart, P, c, yn2, buf, gtab2, gtabf, m_pad, respart, tr, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+                                                     double* __restrict__ respart, TraceCols tr,
+                                                     double* __restrict__ dtpart) {
+    dual_update_body(ctrl, sched, kc, cpart, P, c, yn2, buf, gtab2, gtabf, m_pad, respart, tr, dtpart, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------

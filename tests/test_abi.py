@@ -39,10 +39,12 @@ def test_ctypes_layout_matches_c(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lamp.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
         "sizeof(lamp_problem), sizeof(lamp_params), sizeof(lamp_state), sizeof(lamp_trace),"
         "sizeof(lamp_cert), sizeof(lamp_report), offsetof(lamp_problem, cost_norm),"
-        "offsetof(lamp_params, check_every), offsetof(lamp_report, row_fallbacks));return 0;}\n")
+        "offsetof(lamp_params, check_every), offsetof(lamp_report, row_fallbacks),"
+        "offsetof(lamp_params, track_dt), offsetof(lamp_state, dt_partial),"
+        "offsetof(lamp_cert, midpoint_bound));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
@@ -50,5 +52,6 @@ def test_ctypes_layout_matches_c(tmp_path):
     want = [ctypes.sizeof(_lib.Problem), ctypes.sizeof(_lib.Params), ctypes.sizeof(_lib.State),
             ctypes.sizeof(_lib.Trace), ctypes.sizeof(_lib.Cert), ctypes.sizeof(_lib.Report),
             _lib.Problem.cost_norm.offset, _lib.Params.check_every.offset,
-            _lib.Report.row_fallbacks.offset]
+            _lib.Report.row_fallbacks.offset, _lib.Params.track_dt.offset, _lib.State.dt_partial.offset,
+            _lib.Cert.midpoint_bound.offset]
     assert got == want

@@ -1,0 +1,124 @@
+"""GPU parity of the D_t tracking (Proposition infeas_bound(b), def:sum_condition) against the
+FP64 oracle, which evaluates every summand from its definition on the dense couplings
+(oracle.lamp.dt_sequence).  Through the C ABI: lamp_step / lamp_solve with track_dt, and
+lamp_certificate, which adds the telescoped normaliser term and the midpoint bound.
+
+Tolerance of one summand (the part the iterations accumulate, without <r, log Z^{t+1} - log Z^t>),
+from the parity tolerances of its inputs: the column term K <col(Xbar), lam' nu' - lam nu> with
+col(Xbar) within COL_TOL in l1 and |lam' nu' - lam nu| <= 1 gives K COL_TOL = 2e-6; the cost term
+(lam' - lam) <C, Xbar> with lam' - lam <= tau1 = 1/2 and <C, Xbar> <= 1 within COST_TOL gives 5e-6;
+the two Bregman terms move by at most ~1e-6 with thetabar, thetahat within DUAL_TOL.  Hence
+DT_STEP_TOL = 1e-5.  Along a trajectory of T iterations the summands add, and each is evaluated at
+GPU iterates within DUAL_TOL of the oracle's (~5e-7 per summand): T (DT_STEP_TOL + 5e-7).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lamp as OL
+from paper_2511_11359_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2511_11359_amd as P  # noqa: E402
+
+DT_STEP_TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _problem(n, m, d, kind, seed, eta=1e-2):
+    wl = W.random_small(n, m, d, seed=seed, eta=eta)
+    x = wl.x.astype(np.float64)
+    y = wl.y.astype(np.float64)
+    s = 1.0 / OL.max_cost(x, y, kind)
+    C = OL.ground_cost(x, y, s, kind)
+    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=s, cost_norm=1.0, metric=kind)
+    return wl, C, prob
+
+
+@pytest.mark.parametrize("shape,kind,steps", [((70, 53, 2), "sqeuclid", [0, 1, 10, 60]),
+                                              ((64, 64, 3), "l1", [0, 5, 40]),
+                                              ((50, 61, 2), "linf", [0, 9]),
+                                              ((45, 38, 20), "sqeuclid", [0, 7]),
+                                              ((1, 9, 2), "sqeuclid", [0, 3])])
+def test_dt_summand_of_one_step_matches_oracle(shape, kind, steps):
+    """One GPU step from the oracle's FP64 state at s, dt_partial starting at 0: the increment is
+    the summand of D_{s+1} without its normaliser telescope.  Covers the templated and generic-d
+    cost passes (d = 20 runs the row sweep on FP64 matrix cores), each ground cost and a single
+    row."""
+    n, m, d = shape
+    wl, C, prob = _problem(n, m, d, kind, seed=300 + n)
+    _say("case", wl.name, kind)
+    prm = OL.Params(eta=wl.eta)
+    T = max(steps) + 1
+    D, _, traces = OL.dt_sequence(C, wl.r, wl.c, prm, T, 1.0)
+    lam = OL.inv_eta_schedule(T, 0.5, wl.eta)
+    params = P.make_params(eta=wl.eta, track_dt=True)
+    for s in steps:
+        nu = np.zeros(m) if s == 0 else traces[s - 1].nu[0]
+        th = np.zeros(m) if s == 0 else traces[s - 1].theta[0]
+        nu_n = traces[s].nu[0]
+        telescope = float(wl.r @ (OL.log_normaliser(C, nu_n, lam[s + 1], 1.0)
+                                  - OL.log_normaliser(C, nu, lam[s], 1.0)))
+        ref = (D[s] - (D[s - 1] if s else 0.0)) - telescope
+        st = P.State(torch.tensor(nu, device="cuda"), torch.tensor(th, device="cuda"), s, float(lam[s]), 0.0)
+        P.step(prob, params, st)
+        err = abs(st.dt_partial - ref)
+        _say(f"  s={s} gpu {st.dt_partial:.9e} oracle {ref:.9e} err {err:.2e}")
+        assert st.t == s + 1
+        assert err <= DT_STEP_TOL * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("kind", ["sqeuclid", "l1"])
+def test_dt_along_a_solve_and_midpoint_bound(kind):
+    """T iterations of the graph-captured loop with tracking (several replayed chunks), then the
+    certificate: D_T and 2||C||_inf (log m + (1 + alpha) log 2 + D_T)/T against the oracle's."""
+    wl, C, prob = _problem(96, 80, 2, kind, seed=71)
+    T = 80
+    D, _, _ = OL.dt_sequence(C, wl.r, wl.c, OL.Params(eta=wl.eta), T, 1.0)
+    params = P.make_params(eta=wl.eta, tol=0.0, max_iter=T, check_every=16, track_dt=True)
+    st, rep, status = P.solve(prob, params)
+    assert status == 0 and st.t == T
+    cert = P.certificate(prob, params, st)
+    ref_bound = OL.midpoint_bound(D[-1], T, 80, 0.01, 1.0)
+    tol = T * (DT_STEP_TOL + 5e-7)
+    _say(kind, f"D_T gpu {cert['dt']:.9e} oracle {D[-1]:.9e} err {abs(cert['dt'] - D[-1]):.2e} (tol {tol:.1e})",
+         f"bound gpu {cert['midpoint_bound']:.6e} oracle {ref_bound:.6e}")
+    assert abs(cert["dt"] - D[-1]) <= tol
+    assert abs(cert["midpoint_bound"] - ref_bound) <= 2.0 * tol / T + 1e-12
+
+
+def test_dt_resume_untracked_and_rejected_forms():
+    """A tracked run split in two calls accumulates the same D_t as one call, to the trajectory
+    tolerance (the second call starts from exact row offsets, which changes the FP32 rounding of
+    the sums, as for the duals of a resumed solve); an untracked iteration makes the partial sum
+    NaN (so the certificate reports NaN); the matrix-core forms and the batching form reject
+    tracking."""
+    wl, _, prob = _problem(120, 100, 3, "sqeuclid", seed=73)
+    params = P.make_params(eta=wl.eta, max_iter=60, check_every=16, track_dt=True)
+    whole, _, _ = P.solve(prob, params)
+    half = P.make_params(eta=wl.eta, max_iter=30, check_every=16, track_dt=True)
+    st, _, _ = P.solve(prob, half)
+    st, _, _ = P.solve(prob, half, st)
+    assert st.t == whole.t == 60
+    _say(f"split {st.dt_partial:.12e} whole {whole.dt_partial:.12e}")
+    assert abs(st.dt_partial - whole.dt_partial) <= 30 * (DT_STEP_TOL + 5e-7)
+    assert math.isfinite(P.certificate(prob, params, st)["dt"])
+    untracked = P.make_params(eta=wl.eta, max_iter=1)
+    st2, _, _ = P.solve(prob, untracked, st)
+    assert st2.t == 61 and math.isnan(st2.dt_partial)
+    assert math.isnan(P.certificate(prob, untracked, st2)["dt"])
+    with pytest.raises(P.LampError):
+        P.solve(prob, P.make_params(eta=wl.eta, max_iter=5, precision="bf16_mfma", track_dt=True))
+    with pytest.raises(P.LampError):
+        P.solve_batched([prob, prob], P.make_params(eta=wl.eta, max_iter=5, track_dt=True))

@@ -364,6 +364,8 @@ def test_batched_solve_matches_single_solves():
     for prob, st, rep, wl in zip(probs, states, reps, probs_w):
         single, srep, _ = P.solve(prob, params)
         assert rep["converged"] == 1 and st.t == single.t, (rep, srep)
+        # lam_t of each returned state follows from its own t (the same host recursion)
+        assert st.inv_eta == single.inv_eta
         assert rel_dual(to_np(st.nu), to_np(single.nu)) <= DUAL_TOL
         assert rel_dual(to_np(st.theta), to_np(single.theta)) <= DUAL_TOL
     # against the oracle for the smallest problem

@@ -134,3 +134,25 @@ def test_mutation_gradient_factor(monkeypatch):
     orig = L.envelope_grad_x
     monkeypatch.setattr(L, "envelope_grad_x", lambda *a: 0.5 * orig(*a))
     _fails(pins.test_envelope_gradient_matches_finite_differences)
+
+
+def test_mutation_dt_kl_arguments_swapped(monkeypatch):
+    """KL(X^{s+1} || Xbar) in place of KL(Xbar || X^{s+1}) in the D_t summand."""
+    orig = L.kl
+    monkeypatch.setattr(L, "kl", lambda X, Y: orig(Y, X))
+    _fails(pins.test_dt_summands_match_the_dual_and_primal_identities, 0.0)
+
+
+def test_mutation_dt_dual_divergence_arguments_swapped(monkeypatch):
+    """D_H(thetahat || thetabar) in place of D_H(thetabar || thetahat)."""
+    orig = L.bregman_Ha_natural
+    monkeypatch.setattr(L, "bregman_Ha_natural", lambda a, b, w: orig(b, a, w))
+    _fails(pins.test_dt_summands_match_the_dual_and_primal_identities, 0.0)
+
+
+def test_mutation_dt_dual_divergence_unweighted(monkeypatch):
+    """The weights c^alpha dropped from the dual divergence."""
+    orig = L.bregman_Ha_natural
+    monkeypatch.setattr(L, "bregman_Ha_natural", lambda a, b, w: orig(a, b, np.ones_like(w)))
+    _fails(pins.test_dt_summands_match_the_dual_and_primal_identities, 0.0)
+    _fails(pins.test_dual_bregman_from_natural_parameters_high_precision)
