@@ -131,7 +131,9 @@ typedef struct {
     double *log_za, *log_zb, *col_a, *col_b, *theta_bar, *theta_hat;
 } lamp_trace;
 
-/* Certificate of X^t = diag(r) p^{eta_t}(nu^t) (Proposition infeas_bound; Appendix B). */
+/* Certificate of X^t = diag(r) p^{eta_t}(nu^t) (Proposition infeas_bound; Appendix B).
+ * Pair terms as in the sweeps (FP64 exponent argument, FP32 exponential, FP32 sums over
+ * blocks of columns, FP64 beyond); the minima of the dual values D(.) in FP64. */
 typedef struct {
     double col_res;          /* ||col(X^t) - c||_1                                   */
     double row_res;          /* ||row(X^t) - r||_1, measured                          */
@@ -145,7 +147,7 @@ typedef struct {
     double cost_norm;        /* ||C||_inf used                                        */
     int64_t t;
     double rounded_cost;     /* <C, Round(X^t)>, Round of Algorithm 3 applied to X^t
-                                on the device (FP64), without forming X               */
+                                on the device, without forming X                      */
     double dt;               /* D_t (def:sum_condition): state.dt_partial + <r, log Z^t>
                                 - log m; NaN unless every iteration tracked it        */
     double midpoint_bound;   /* 2||C||_inf (log m + (1 + alpha) log 2 + D_t) / t, the

@@ -1452,21 +1452,37 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
                        prob->c, colres);
     hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
                        at<double2>(ws, L.gtab), gA);
-    hipLaunchKernelGGL(cert_rows, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, cA, at<double>(ws, L.xc),
-                       at<double>(ws, L.yc), at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA, at<double>(ws, L.H),
-                       prob->r, state->nu, state->theta, vals, psum);
+    // pair passes: the kernel of the problem's metric and dimension, coordinates of the
+    // thread's own point in registers where compiled (run-time form otherwise)
+    auto by_md = [&](auto&& launch) {
+        const bool done = by_metric(kc.metric, [&](auto m) {
+            return valu_dispatch<decltype(m)::value>(prob->d, [&](auto dd) { launch(m, dd); });
+        });
+        if (!done) launch(IC<-1>{}, IC<0>{});
+    };
+    by_md([&](auto m, auto dd) {
+        hipLaunchKernelGGL((cert_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0, st,
+                           kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double>(ws, L.xn2),
+                           at<double>(ws, L.yn2), gA, at<double>(ws, L.H), prob->r, state->nu, state->theta, vals,
+                           psum);
+    });
     hipLaunchKernelGGL(col_products, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->c, state->theta, state->nu, prods);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, vals, kc.n, kc.n, 4, small);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, colres, kc.m, kc.m, 1, small + 4);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, prods, kc.m, kc.m, 2, small + 5);
     // Round (Algorithm 3) of the same X and its cost
     hipLaunchKernelGGL(round_row_factors, grid1(kc.n), dim3(BLOCK), 0, st, kc, psum, xr);
-    hipLaunchKernelGGL(round_cols, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->d, cA, at<double>(ws, L.xc),
-                       at<double>(ws, L.yc), gA, at<double>(ws, L.H), prob->r, xr, colp);
+    by_md([&](auto m, auto dd) {
+        hipLaunchKernelGGL((round_cols<decltype(m)::value, decltype(dd)::value>), grid1(kc.m), dim3(BLOCK), 0, st,
+                           kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc), gA, at<double>(ws, L.H),
+                           prob->r, xr, colp);
+    });
     hipLaunchKernelGGL(round_col_factors, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->c, colp, yf, dc);
-    hipLaunchKernelGGL(round_rows, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, cA, at<double>(ws, L.xc),
-                       at<double>(ws, L.yc), at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA,
-                       at<double>(ws, L.H), prob->r, xr, yf, dr, cpp);
+    by_md([&](auto m, auto dd) {
+        hipLaunchKernelGGL((round_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0, st,
+                           kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double>(ws, L.xn2),
+                           at<double>(ws, L.yn2), gA, at<double>(ws, L.H), prob->r, xr, yf, dr, cpp);
+    });
     if (kc.metric == METRIC_SQEUCLID) {
         hipLaunchKernelGGL(round_col_sums, dim3(prob->d + 2), dim3(BLOCK), 0, st, kc, prob->d,
                            at<double>(ws, L.yc), at<double>(ws, L.yn2), dc, S);

@@ -926,6 +926,32 @@ __global__ void reduce_sums(const double* __restrict__ vals, int64_t n, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// The pair term of the thread's own point against streamed points: coordinates in
+// registers for a compile-time dimension (M, D), read from memory for the run-time
+// metric and dimension (M = -1, D = 0).  The pair term is symmetric in its points.
+// ---------------------------------------------------------------------------
+template <int M, int D>
+struct OwnPoint {
+    double x[D];
+    __device__ __forceinline__ OwnPoint(const double* __restrict__ src, int, int) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = src[k];
+    }
+    __device__ __forceinline__ double pair(const double* __restrict__ y) const { return pair_term<M, D>(x, y, 0.0); }
+};
+
+template <>
+struct OwnPoint<-1, 0> {
+    const double* x;
+    int d, metric;
+    __device__ __forceinline__ OwnPoint(const double* __restrict__ src, int d_, int metric_)
+        : x(src), d(d_), metric(metric_) {}
+    __device__ __forceinline__ double pair(const double* __restrict__ y) const {
+        return pair_term_dyn(metric, d, x, y, 0.0);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Certificate row sweep at the state's iterate (offsets from an A-only
 // row_finish so that log2 p_ij = cfac (h_i + x~.y~) + g_j exactly):
 //   vals[0][i] = r_i |sum_j p_ij - 1|                 (row infeasibility)
@@ -933,9 +959,11 @@ __global__ void reduce_sums(const double* __restrict__ vals, int64_t n, int64_t 
 //   vals[2][i] = r_i min_j (C_ij + K theta_j)         (D(theta), def:dual_spp)
 //   vals[3][i] = r_i min_j (C_ij + K nu_j)            (D(nu))
 //   psum_out[i] = sum_j p_ij                          (row sum of p, for Round)
-// FP64 throughout (including the exponential); not on the iteration path.
+// Terms as in the sweeps: FP64 exponent, FP32 exponential and sums over blocks of
+// UNROLL columns, FP64 across blocks; the two minima in FP64.  Dm = run-time d.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int D, double cA,
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int Dm, double cA,
                                                    const double* __restrict__ xc,
                                                    const double* __restrict__ yc,
                                                    const double* __restrict__ xn2,
@@ -948,16 +976,23 @@ __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int D, double cA,
                                                    double* __restrict__ vals, double* __restrict__ psum_out) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= kc.n) return;
+    const OwnPoint<M, D> own(xc + i * Dm, Dm, kc.metric);
     const double h = H[i];
     double psum = 0.0, csum = 0.0, mth = __builtin_inf(), mnu = __builtin_inf();
-    for (int64_t j = 0; j < kc.m; ++j) {
-        const double dot = pair_term_dyn(kc.metric, D, xc + i * D, yc + j * D, 0.0);
-        const double pij = exp2(fma(cA, h + dot, gA[j]));
-        const double cij = kc.s * (xn2[i] + yn2[j] - 2.0 * dot);
-        psum += pij;
-        csum = fma(cij, pij, csum);
-        mth = fmin(mth, cij + kc.K * theta[j]);
-        mnu = fmin(mnu, cij + kc.K * nu[j]);
+    for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
+        const int64_t je = min(kc.m, jb + UNROLL);
+        float ap = 0.f, ac = 0.f;
+        for (int64_t j = jb; j < je; ++j) {
+            const double dot = own.pair(yc + j * Dm);
+            const float p = fexp2(fma(cA, h + dot, gA[j]));
+            const double cij = kc.s * (xn2[i] + yn2[j] - 2.0 * dot);
+            ap += p;
+            ac = fmaf((float)cij, p, ac);
+            mth = fmin(mth, cij + kc.K * theta[j]);
+            mnu = fmin(mnu, cij + kc.K * nu[j]);
+        }
+        psum += (double)ap;
+        csum += (double)ac;
     }
     const double ri = r[i];
     vals[i] = ri * fabs(psum - 1.0);
@@ -976,7 +1011,8 @@ __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int D, double cA,
 // so that <C, Round(X)> = <C, X''> + dr^T C dc / ||dr||_1, where for the squared
 // Euclidean cost on centred points
 //   (C dc)_i = s (||x~_i||^2 sum_j dc_j + sum_j dc_j ||y~_j||^2 - 2 x~_i . sum_j dc_j y~_j)
-// is O(d) per row once the column sums are known.  FP64 throughout.
+// is O(d) per row once the column sums are known.  The pair passes use the terms of
+// the certificate row sweep (FP32 exponentials, FP64 sums), the O(n + m) steps FP64.
 // ---------------------------------------------------------------------------
 __global__ void round_row_factors(Consts kc, const double* __restrict__ psum, double* __restrict__ xr) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -984,17 +1020,24 @@ __global__ void round_row_factors(Consts kc, const double* __restrict__ psum, do
 }
 
 // colp_j = sum_i xr_i r_i p_ij (one thread per column, rows in order).
-__global__ __launch_bounds__(BLOCK) void round_cols(Consts kc, int D, double cA, const double* __restrict__ xc,
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void round_cols(Consts kc, int Dm, double cA, const double* __restrict__ xc,
                                                     const double* __restrict__ yc, const double* __restrict__ gA,
                                                     const double* __restrict__ H, const double* __restrict__ r,
                                                     const double* __restrict__ xr, double* __restrict__ colp) {
     const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (j >= kc.m) return;
+    const OwnPoint<M, D> own(yc + j * Dm, Dm, kc.metric);
     const double g = gA[j];
     double acc = 0.0;
-    for (int64_t i = 0; i < kc.n; ++i) {
-        const double dot = pair_term_dyn(kc.metric, D, xc + i * D, yc + j * D, 0.0);
-        acc = fma(xr[i] * r[i], exp2(fma(cA, H[i] + dot, g)), acc);
+    for (int64_t ib = 0; ib < kc.n; ib += UNROLL) {
+        const int64_t ie = min(kc.n, ib + UNROLL);
+        float a = 0.f;
+        for (int64_t i = ib; i < ie; ++i) {
+            const double dot = own.pair(xc + i * Dm);
+            a = fmaf((float)(xr[i] * r[i]), fexp2(fma(cA, H[i] + dot, g)), a);
+        }
+        acc += (double)a;
     }
     colp[j] = acc;
 }
@@ -1010,7 +1053,10 @@ __global__ void round_col_factors(Consts kc, const double* __restrict__ c, const
 }
 
 // Rows of X'': dr_i = r_i - xr_i r_i sum_j p_ij y_j and cpp_i = xr_i r_i sum_j C_ij p_ij y_j.
-__global__ __launch_bounds__(BLOCK) void round_rows(Consts kc, int D, double cA, const double* __restrict__ xc,
+// dr is formed as r_i (1 - xr_i psum_i) + xr_i r_i sum_j p_ij (1 - y_j) (the same value)
+// with psum_i recomputed in this pass: no difference of two nearly equal sums.
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void round_rows(Consts kc, int Dm, double cA, const double* __restrict__ xc,
                                                     const double* __restrict__ yc, const double* __restrict__ xn2,
                                                     const double* __restrict__ yn2, const double* __restrict__ gA,
                                                     const double* __restrict__ H, const double* __restrict__ r,
@@ -1018,16 +1064,27 @@ __global__ __launch_bounds__(BLOCK) void round_rows(Consts kc, int D, double cA,
                                                     double* __restrict__ dr, double* __restrict__ cpp) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= kc.n) return;
+    const OwnPoint<M, D> own(xc + i * Dm, Dm, kc.metric);
     const double h = H[i];
-    double rs = 0.0, cs = 0.0;
-    for (int64_t j = 0; j < kc.m; ++j) {
-        const double dot = pair_term_dyn(kc.metric, D, xc + i * D, yc + j * D, 0.0);
-        const double q = exp2(fma(cA, h + dot, gA[j])) * y[j];
-        rs += q;
-        cs = fma(kc.s * (xn2[i] + yn2[j] - 2.0 * dot), q, cs);
+    double ps = 0.0, pq = 0.0, cs = 0.0;
+    for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
+        const int64_t je = min(kc.m, jb + UNROLL);
+        float a = 0.f, b = 0.f, e = 0.f;
+        for (int64_t j = jb; j < je; ++j) {
+            const double dot = own.pair(yc + j * Dm);
+            const float p = fexp2(fma(cA, h + dot, gA[j]));
+            const double yj = y[j];
+            const float py = p * (float)yj;
+            a += p;
+            b = fmaf(p, (float)(1.0 - yj), b);
+            e = fmaf((float)(kc.s * (xn2[i] + yn2[j] - 2.0 * dot)), py, e);
+        }
+        ps += (double)a;
+        pq += (double)b;
+        cs += (double)e;
     }
     const double w = xr[i] * r[i];
-    dr[i] = r[i] - w * rs;
+    dr[i] = r[i] * (1.0 - xr[i] * ps) + w * pq;
     cpp[i] = w * cs;
 }
 
