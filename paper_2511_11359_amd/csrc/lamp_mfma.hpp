@@ -78,98 +78,6 @@ __global__ void pad_rows(int64_t n, int64_t n_pad, float* __restrict__ kf, float
     wb[i] = 0.f;
 }
 
-// Row sweep: wave w of block b owns rows [32 rw, 32 rw + 32), rw = (b / P) * 4 + w,
-// and streams column tiles of split p = b mod P (P a multiple of 8 maps each split to
-// one XCD, whose L2 then holds that split's operand rows).
-template <typename T, int KP>
-__global__ __launch_bounds__(BLOCK) void row_sweep_mfma(const Ctrl* ctrl, const Sched* sched, Consts kc,
-                                                        const T* __restrict__ xop, const T* __restrict__ yop,
-                                                        const float2* __restrict__ gtabf, int64_t m_pad,
-                                                        const double* __restrict__ H,
-                                                        double2* __restrict__ part, int64_t tiles_per_split,
-                                                        int P, int64_t m_tiles, int64_t n_waves) {
-    if (halted(ctrl)) return;
-    using Op = MfmaOp<T>;
-    using vec = typename Op::vec;
-    constexpr int NS = KP / Op::KSTEP;
-    const int64_t t = ctrl->t;
-    const Sched sc = sched[t - ctrl->t_base];
-    const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E);
-    const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
-    const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
-    const int lane = threadIdx.x & 63;
-    const int hf = lane >> 5, c32 = lane & 31;
-    const int64_t b = blockIdx.x;
-    const int p = (int)(b % P);
-    const int64_t rw = (b / P) * 4 + (threadIdx.x >> 6);
-    if (rw >= n_waves) return;
-    const int64_t i0 = rw * 32;
-
-    vec a[NS];
-    {
-        const vec* ap = reinterpret_cast<const vec*>(xop + (i0 + c32) * KP + hf * (KP / 2));
-#pragma unroll
-        for (int s = 0; s < NS; ++s) a[s] = ap[s];
-    }
-    floatx16 hv;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        int64_t ii = i0 + mfma_row(r, hf);
-        hv[r] = (float)H[ii < kc.n ? ii : kc.n - 1];
-    }
-    float accA[16], accB[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) accA[r] = accB[r] = 0.f;
-
-    const int64_t jt0 = (int64_t)p * tiles_per_split;
-    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
-    // software pipeline: operands of tile jt+1 load while tile jt computes
-    vec bn[NS];
-    float2 gn = make_float2(PAD_NEG, PAD_NEG);
-    if (jt0 < jt1) {
-        const int64_t j = jt0 * 32 + c32;
-        const vec* bp = reinterpret_cast<const vec*>(yop + j * KP + hf * (KP / 2));
-#pragma unroll
-        for (int s = 0; s < NS; ++s) bn[s] = bp[s];
-        gn = g[j];
-    }
-    for (int64_t jt = jt0; jt < jt1; ++jt) {
-        vec bv[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) bv[s] = bn[s];
-        const float gA = gn.x, gB = gn.y;
-        if (jt + 1 < jt1) {
-            const int64_t j = (jt + 1) * 32 + c32;
-            const vec* bp = reinterpret_cast<const vec*>(yop + j * KP + hf * (KP / 2));
-#pragma unroll
-            for (int s = 0; s < NS; ++s) bn[s] = bp[s];
-            gn = g[j];
-        }
-        floatx16 d = Op::mma(a[0], bv[0], hv);
-#pragma unroll
-        for (int s = 1; s < NS; ++s) d = Op::mma(a[s], bv[s], d);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            accA[r] += __builtin_amdgcn_exp2f(fmaf(d[r], cA, gA));
-            accB[r] += __builtin_amdgcn_exp2f(fmaf(d[r], cB, gB));
-        }
-    }
-    // sum over the 32 columns held by the 32 lanes of each half
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-#pragma unroll
-        for (int o = 16; o > 0; o >>= 1) {
-            accA[r] += __shfl_xor(accA[r], o, 64);
-            accB[r] += __shfl_xor(accB[r], o, 64);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int64_t row = i0 + mfma_row(r, hf);
-        if (c32 == r && row < kc.n) part[(int64_t)p * kc.n + row] = make_double2(accA[r], accB[r]);
-    }
-}
-
 // Operands and row data of one 32-row tile of the column sweep.
 template <typename T, int KP>
 struct ColTile {
@@ -464,108 +372,6 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma64(const Ctrl* ctrl, cons
     if (grp == 0 && j < kc.m) cpart[(int64_t)p * kc.m + j] = make_double2(sumA, sumB);
 }
 
-// Column sweep of the BF16/FP16 forms with the roles of the operands swapped:
-// the wave's 32 columns y_j are the MFMA rows (fixed A operand) and the streamed
-// points x_i are the MFMA columns, so the per-row data (k_i, w^A_i, w^B_i) is one
-// value per lane per tile instead of sixteen.  Each coupling gets its own chain with
-// accumulator input G_j = g_j / c (per register), so that
-//     e = c (G_j + x~_i . y~_j) + c k_i,
-// one FP32 FMA per entry with the per-lane c k_i.  The two chains double the
-// (cheap) half-precision matrix work and remove most of the vector-memory traffic.
-template <typename T, int KP>
-__global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t(const Ctrl* ctrl, const Sched* sched, Consts kc,
-                                                          const T* __restrict__ xop, const T* __restrict__ yop,
-                                                          const float2* __restrict__ gtabf, int64_t m_pad,
-                                                          const float4* __restrict__ rowq,
-                                                          double2* __restrict__ cpart, int64_t tiles_per_split,
-                                                          int P, int64_t n_tiles, int64_t m_waves) {
-    if (halted(ctrl)) return;
-    using Op = MfmaOp<T>;
-    using vec = typename Op::vec;
-    constexpr int NS = KP / Op::KSTEP;
-    const int64_t t = ctrl->t;
-    const Sched sc = sched[t - ctrl->t_base];
-    const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E);
-    const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
-    const int lane = threadIdx.x & 63;
-    const int hf = lane >> 5, c32 = lane & 31;
-    const int64_t b = blockIdx.x;
-    const int p = (int)(b % P);
-    const int64_t cw = (b / P) * 4 + (threadIdx.x >> 6);
-    if (cw >= m_waves) return;
-    const int64_t j0 = cw * 32;
-    vec a[NS];
-    {
-        const vec* ap = reinterpret_cast<const vec*>(yop + (j0 + c32) * KP + hf * (KP / 2));
-#pragma unroll
-        for (int s = 0; s < NS; ++s) a[s] = ap[s];
-    }
-    // G_j = g_j / c for the 16 columns of this lane's registers (0 at c = 0: then e = 0 = g_j)
-    const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
-    floatx16 GA, GB;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const float2 gg = g[j0 + mfma_row(r, hf)];
-        GA[r] = cA > 0.f ? gg.x / cA : 0.f;
-        GB[r] = gg.y / cB;
-        if (gg.x <= PAD_NEG) GA[r] = PAD_NEG;
-        if (gg.y <= PAD_NEG) GB[r] = PAD_NEG;
-    }
-    float accA[16], accB[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) accA[r] = accB[r] = 0.f;
-    const int64_t it0 = (int64_t)p * tiles_per_split;
-    const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
-    vec bn[NS];
-    float4 qn = make_float4(PAD_NEG, 0.f, 0.f, 0.f);
-    if (it0 < it1) {
-        const int64_t i = it0 * 32 + c32;
-        const vec* bp = reinterpret_cast<const vec*>(xop + i * KP + hf * (KP / 2));
-#pragma unroll
-        for (int s = 0; s < NS; ++s) bn[s] = bp[s];
-        qn = rowq[i];
-    }
-    for (int64_t it = it0; it < it1; ++it) {
-        vec bv[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) bv[s] = bn[s];
-        const float4 q = qn;
-        if (it + 1 < it1) {
-            const int64_t i = (it + 1) * 32 + c32;
-            const vec* bp = reinterpret_cast<const vec*>(xop + i * KP + hf * (KP / 2));
-#pragma unroll
-            for (int s = 0; s < NS; ++s) bn[s] = bp[s];
-            qn = rowq[i];
-        }
-        const float ckA = cA * q.x, ckB = cB * q.x;
-        floatx16 dA = Op::mma(a[0], bv[0], GA);
-        floatx16 dB = Op::mma(a[0], bv[0], GB);
-#pragma unroll
-        for (int s = 1; s < NS; ++s) {
-            dA = Op::mma(a[s], bv[s], dA);
-            dB = Op::mma(a[s], bv[s], dB);
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            accA[r] = fmaf(q.y, __builtin_amdgcn_exp2f(fmaf(dA[r], cA, ckA)), accA[r]);
-            accB[r] = fmaf(q.z, __builtin_amdgcn_exp2f(fmaf(dB[r], cB, ckB)), accB[r]);
-        }
-    }
-    // sum over the 32 rows held by the 32 lanes of each half
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-#pragma unroll
-        for (int o = 16; o > 0; o >>= 1) {
-            accA[r] += __shfl_xor(accA[r], o, 64);
-            accB[r] += __shfl_xor(accB[r], o, 64);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int64_t j = j0 + mfma_row(r, hf);
-        if (c32 == r && j < kc.m) cpart[(int64_t)p * kc.m + j] = make_double2(accA[r], accB[r]);
-    }
-}
 
 __global__ void pad_rowq(int64_t n, int64_t n_pad, float4* __restrict__ q) {
     int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -779,7 +585,10 @@ __device__ __forceinline__ floatx16 tile_dot(const char* lds, int c32, int hf,
     return d;
 }
 
-// Row sweep, LDS-shared column tiles.  Same arithmetic as row_sweep_mfma.
+// Row sweep: wave w of block b owns rows [32 rw, 32 rw + 32), rw = (b / P) * 4 + w,
+// and streams column tiles of split p = b mod P (P a multiple of 8 maps each split to
+// one XCD, whose L2 then holds that split's operand rows).
+// LDS-shared column tiles (see above).
 template <typename T, int KP>
 __global__ __launch_bounds__(BLOCK) void row_sweep_mfma_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                             const T* __restrict__ xop, const T* __restrict__ yop,
@@ -941,7 +750,19 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_mfma_lds(const Ctrl* ctrl, 
     }
 }
 
-// Column sweep of the half-precision forms (swapped operands), LDS-shared row tiles.
+// Column sweep of the BF16/FP16 forms with the roles of the operands swapped, LDS-shared
+// row tiles: the wave's 32 columns y_j are the MFMA rows (fixed A operand) and the
+// streamed points x_i the MFMA columns, so the per-row data (k_i, w^A_i, w^B_i) is one
+// value per lane per tile instead of sixteen.  The column offsets enter as the
+// accumulator input G_j = g_j / c (per register), so that
+//     e = c (G_j + x~_i . y~_j) + c k_i,
+// one FP32 FMA per entry with the per-lane c k_i.  G differs between the couplings:
+// with one matrix-core step per tile (d <= 16) each coupling gets its own chain; with
+// NS >= 4 steps the second chain costs more than one add per term, and one chain
+// (accumulator G^B) serves both:
+//     e^A = c^A (d^B + k_i) + (g^A_j - c^A G^B_j),   d^B = x~_i . y~_j + G^B_j
+// (measured: column sweep 1.49 -> 1.30 ms at n = m = 2^16, d = 64; at d = 3 the two
+// chains are 7% faster than one).
 template <typename T, int KP>
 __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                               const T* __restrict__ xop, const T* __restrict__ yop,
@@ -972,8 +793,10 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
 #pragma unroll
         for (int s = 0; s < NS; ++s) a[s] = ap[s];
     }
+    constexpr bool ONE_CHAIN = NS >= 4;
     const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
     floatx16 GA, GB;
+    float CA[16];   // g^A_j - c^A G^B_j (one-chain form)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const float2 gg = g[j0 + mfma_row(r, hf)];
@@ -981,6 +804,7 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
         GB[r] = gg.y / cB;
         if (gg.x <= PAD_NEG) GA[r] = PAD_NEG;
         if (gg.y <= PAD_NEG) GB[r] = PAD_NEG;
+        CA[r] = gg.x <= PAD_NEG ? PAD_NEG : gg.x - cA * GB[r];
     }
     float accA[16], accB[16];
 #pragma unroll
@@ -994,13 +818,14 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
         auto dots = [&](const char* buf, floatx16& dA, floatx16& dB) {
             typename Op::vec bv[NS];
             tile_operands<T, KP>(buf, c32, hf, bv);
-            dA = Op::mma(a[0], bv[0], GA);
             dB = Op::mma(a[0], bv[0], GB);
+            if constexpr (!ONE_CHAIN) dA = Op::mma(a[0], bv[0], GA);
 #pragma unroll
             for (int s = 1; s < NS; ++s) {
-                dA = Op::mma(a[s], bv[s], dA);
+                if constexpr (!ONE_CHAIN) dA = Op::mma(a[s], bv[s], dA);
                 dB = Op::mma(a[s], bv[s], dB);
             }
+            if constexpr (ONE_CHAIN) dA = dB;
         };
         tile_fetch<T, KP, 16>(xop, it0 * 32, rowq, n_rows, pf);
         tile_store<T, KP>(lds[0], pf);
@@ -1022,7 +847,8 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
             const float ckA = cA * qc.x, ckB = cB * qc.x;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                accA[r] = fmaf(qc.y, __builtin_amdgcn_exp2f(fmaf(dcA[r], cA, ckA)), accA[r]);
+                const float eA = ONE_CHAIN ? fmaf(dcB[r], cA, ckA) + CA[r] : fmaf(dcA[r], cA, ckA);
+                accA[r] = fmaf(qc.y, __builtin_amdgcn_exp2f(eA), accA[r]);
                 accB[r] = fmaf(qc.z, __builtin_amdgcn_exp2f(fmaf(dcB[r], cB, ckB)), accB[r]);
             }
             pin(accA);
