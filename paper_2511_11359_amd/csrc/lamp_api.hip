@@ -72,7 +72,7 @@ int64_t choose_split(int64_t owned, int64_t len, int64_t target = TARGET_BLOCKS)
 
 struct Layout {
     size_t ctrl, sched, xc, yc, xcf, ycf, xn2, yn2, gtab, H, rowvar, rpart, cpart, nu1, th1, respart,
-        dtrow, dtpart, scratch, small, xop, yop, kf, wAf, wBf, gtabf, rowq, total;
+        dtrow, dtpart, scratch, small, xop, yop, gtabf, rowq, total;
     int64_t split_r, P_r, split_c, P_c;
     // matrix-core forms
     int prec, KP, esize;
@@ -190,9 +190,6 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     if (is_mfma(prec)) {
         L.xop = take((size_t)L.esize * L.n_pad * L.KP);
         L.yop = take((size_t)L.esize * L.m_pad * L.KP);
-        L.kf = take(sizeof(float) * L.n_pad);
-        L.wAf = take(sizeof(float) * L.n_pad);
-        L.wBf = take(sizeof(float) * L.n_pad);
         L.gtabf = take(sizeof(float2) * 2 * L.m_pad);
         L.rowq = take(sizeof(float4) * L.n_pad);
     }
@@ -212,7 +209,7 @@ T* at(void* ws, size_t off) {
 float2* gtabf_ptr(const Layout& L, void* ws) { return is_mfma(L.prec) ? at<float2>(ws, L.gtabf) : nullptr; }
 
 RowVarF32 rowvar_f32(const Layout& L, void* ws) {
-    return RowVarF32{at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf), at<float4>(ws, L.rowq), 1};
+    return RowVarF32{at<float4>(ws, L.rowq), 1};
 }
 
 struct Resolved {
@@ -305,12 +302,9 @@ lamp_status prep_L(const lamp_problem* p, const Layout& L, void* ws, hipStream_t
         if (L.m_pad > p->m)
             hipLaunchKernelGGL(pad_gtabf, grid1(L.m_pad - p->m), dim3(BLOCK), 0, st, p->m, L.m_pad,
                                at<float2>(ws, L.gtabf));
-        if (L.n_pad > p->n) {
-            hipLaunchKernelGGL(pad_rows, grid1(L.n_pad - p->n), dim3(BLOCK), 0, st, p->n, L.n_pad,
-                               at<float>(ws, L.kf), at<float>(ws, L.wAf), at<float>(ws, L.wBf));
+        if (L.n_pad > p->n)
             hipLaunchKernelGGL(pad_rowq, grid1(L.n_pad - p->n), dim3(BLOCK), 0, st, p->n, L.n_pad,
                                at<float4>(ws, L.rowq));
-        }
     }
     HIPCHK(hipGetLastError());
     return LAMP_OK;
@@ -405,17 +399,10 @@ template <typename T, int KP>
 void col_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
     const int64_t m_waves = L.m_pad / 32;
     dim3 g((unsigned)(cdiv(m_waves, 4) * L.P_cm));
-    if (!std::is_same<T, float>::value) {
-        hipLaunchKernelGGL((col_sweep_mfma_t_lds<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl),
-                           at<Sched>(ws, L.sched), kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<float2>(ws, L.gtabf),
-                           L.m_pad, at<float4>(ws, L.rowq), at<double2>(ws, L.cpart), L.tps_c, (int)L.P_cm,
-                           L.n_pad / 32, m_waves);
-        return;
-    }
-    hipLaunchKernelGGL((col_sweep_mfma<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
-                       kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<float2>(ws, L.gtabf), L.m_pad, at<float>(ws, L.kf),
-                       at<float>(ws, L.wAf), at<float>(ws, L.wBf), at<double2>(ws, L.cpart), L.tps_c,
-                       (int)L.P_cm, L.n_pad / 32, m_waves);
+    hipLaunchKernelGGL((col_sweep_mfma_t_lds<T, KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl),
+                       at<Sched>(ws, L.sched), kc, at<T>(ws, L.xop), at<T>(ws, L.yop), at<float2>(ws, L.gtabf),
+                       L.m_pad, at<float4>(ws, L.rowq), at<double2>(ws, L.cpart), L.tps_c, (int)L.P_cm,
+                       L.n_pad / 32, m_waves);
 }
 
 template <bool ROW>
@@ -743,7 +730,7 @@ void launch_iteration(const lamp_problem* p, const Layout& L, Consts kc, void* w
     const Sched* sch = at<Sched>(ws, L.sched);
     launch_row_sweep(L, kc, p->d, ws, st);
     if (ia.track_dt) launch_dt_cost(p, L, kc, ws, st);
-    RowVarF32 rf{nullptr, nullptr, nullptr, 0};
+    RowVarF32 rf{nullptr, 0};
     if (is_mfma(L.prec)) rf = rowvar_f32(L, ws);
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, ctrl, sch, kc, p->d, at<double>(ws, L.xc),
                        at<double>(ws, L.yc), at<double2>(ws, L.gtab), p->r, at<double>(ws, L.xn2),
@@ -815,7 +802,7 @@ lamp_status state_normalisers(const lamp_problem* p, const lamp_params* q, const
                        kc, p->d, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), p->r,
                        at<double>(ws, L.xn2), at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H),
                        at<RowVar>(ws, L.rowvar), (double*)nullptr, (double*)nullptr,
-                       RowVarF32{nullptr, nullptr, nullptr, nullptr, 0});
+                       RowVarF32{nullptr, 0});
     HIPCHK(hipGetLastError());
     *cA_out = 2.0 * R.s * s->inv_eta * LOG2E;
     return LAMP_OK;
@@ -1611,7 +1598,7 @@ lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params
                        prob->d, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), prob->r,
                        at<double>(ws, L.xn2), at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H),
                        at<RowVar>(ws, L.rowvar), (double*)nullptr, (double*)nullptr,
-                       is_mfma(L.prec) ? rowvar_f32(L, ws) : RowVarF32{nullptr, nullptr, nullptr, nullptr, 0});
+                       is_mfma(L.prec) ? rowvar_f32(L, ws) : RowVarF32{nullptr, 0});
     HIPCHK(hipGetLastError());
     hipEvent_t ev[4];
     for (auto& x : ev) HIPCHK(hipEventCreate(&x));

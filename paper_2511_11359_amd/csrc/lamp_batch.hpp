@@ -98,7 +98,7 @@ __global__ __launch_bounds__(BLOCK) void batch_row_finish(const ProbDesc* __rest
         const Item it = items[k];
         const ProbDesc& P = pd[it.prob];
         row_finish_body(P.ctrl, sched, P.kc, P.d, P.xc, P.yc, P.gtab, P.r, P.xn2, P.rpart, P.P_r, P.H, P.rowvar,
-                        nullptr, nullptr, RowVarF32{nullptr, nullptr, nullptr, nullptr, 0}, it.bx, it.by, 0);
+                        nullptr, nullptr, RowVarF32{nullptr, 0}, it.bx, it.by, 0);
     }
 }
 

@@ -449,14 +449,11 @@ __device__ double exact_sigma(int M, const double* __restrict__ xi, const double
 
 // Merge the row partials; derive sigma^A, sigma^B, the next offsets and the
 // column-sweep row data; optional natural-log normalisers.
-// FP32 row data of the matrix-core column sweep (nullable): k rounded to FP32,
-// with the rounding error folded exactly into the weights.  f32_offsets: the row
-// sweep applied (float)H, so that value is the one to subtract.
+// FP32 row data of the matrix-core column sweep (nullable): {k, w^A, w^B, 0} per row,
+// k rounded to FP32 with the rounding error folded exactly into the weights.
+// f32_offsets: the row sweep applied (float)H, so that value is the one to subtract.
 struct RowVarF32 {
-    float* k;
-    float* wA;
-    float* wB;
-    float4* q;        // {k, wA, wB, 0} per row for the swapped-operand column sweep (nullable)
+    float4* q;
     int f32_offsets;
 };
 
@@ -501,15 +498,12 @@ __device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, 
     rv.wA = (float)(r[i] * exp2(ew));
     rv.wB = (float)r[i];
     rowvar[i] = rv;
-    if (rf.k) {
+    if (rf.q) {
         const float kf = (float)hnew;
         const double dk = hnew - (double)kf;
         const float wa = (float)(r[i] * exp2(fmin(fmax(ew + cA * dk, -1000.0), 1000.0)));
         const float wb = (float)(r[i] * exp2(cB * dk));
-        rf.k[i] = kf;
-        rf.wA[i] = wa;
-        rf.wB[i] = wb;
-        if (rf.q) rf.q[i] = make_float4(kf, wa, wb, 0.f);
+        rf.q[i] = make_float4(kf, wa, wb, 0.f);
     }
     if (log_za) log_za[i] = LN2 * (-sc.lamA * LOG2E * kc.s * xn2[i] + sigA);
     if (log_zb) log_zb[i] = LN2 * (-sc.lamB * LOG2E * kc.s * xn2[i] + sigB);

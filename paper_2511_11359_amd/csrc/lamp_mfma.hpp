@@ -69,104 +69,6 @@ __global__ void prep_operands(const double* __restrict__ src, int64_t cnt, int d
     out[idx] = (i < cnt && k < d) ? (T)src[i * d + k] : (T)0.f;
 }
 
-__global__ void pad_rows(int64_t n, int64_t n_pad, float* __restrict__ kf, float* __restrict__ wa,
-                         float* __restrict__ wb) {
-    int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pad) return;
-    kf[i] = PAD_NEG;
-    wa[i] = 0.f;
-    wb[i] = 0.f;
-}
-
-// Operands and row data of one 32-row tile of the column sweep.
-template <typename T, int KP>
-struct ColTile {
-    typename MfmaOp<T>::vec a[KP / MfmaOp<T>::KSTEP];
-    floatx16 kv;
-    float wa[16], wb[16];
-};
-
-template <typename T, int KP>
-__device__ __forceinline__ void load_col_tile(ColTile<T, KP>& ct, const T* __restrict__ xop,
-                                              const float* __restrict__ kf, const float* __restrict__ wAf,
-                                              const float* __restrict__ wBf, int64_t it, int hf, int c32) {
-    using vec = typename MfmaOp<T>::vec;
-    constexpr int NS = KP / MfmaOp<T>::KSTEP;
-    const vec* ap = reinterpret_cast<const vec*>(xop + (it * 32 + c32) * KP + hf * (KP / 2));
-#pragma unroll
-    for (int s = 0; s < NS; ++s) ct.a[s] = ap[s];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t rbase = it * 32 + 8 * q + 4 * hf;   // rows of registers 4q .. 4q+3
-        const float4 k4 = *reinterpret_cast<const float4*>(kf + rbase);
-        const float4 a4 = *reinterpret_cast<const float4*>(wAf + rbase);
-        const float4 b4 = *reinterpret_cast<const float4*>(wBf + rbase);
-        ct.kv[4 * q + 0] = k4.x; ct.kv[4 * q + 1] = k4.y; ct.kv[4 * q + 2] = k4.z; ct.kv[4 * q + 3] = k4.w;
-        ct.wa[4 * q + 0] = a4.x; ct.wa[4 * q + 1] = a4.y; ct.wa[4 * q + 2] = a4.z; ct.wa[4 * q + 3] = a4.w;
-        ct.wb[4 * q + 0] = b4.x; ct.wb[4 * q + 1] = b4.y; ct.wb[4 * q + 2] = b4.z; ct.wb[4 * q + 3] = b4.w;
-    }
-}
-
-// Column sweep: wave owns columns [32 cw, 32 cw + 32), streams row tiles of split p.
-// The per-row offsets k_i enter as the MFMA accumulator input; the row weights
-// w^A_i, w^B_i multiply the exponentials.
-template <typename T, int KP>
-__global__ __launch_bounds__(BLOCK) void col_sweep_mfma(const Ctrl* ctrl, const Sched* sched, Consts kc,
-                                                        const T* __restrict__ xop, const T* __restrict__ yop,
-                                                        const float2* __restrict__ gtabf, int64_t m_pad,
-                                                        const float* __restrict__ kf,
-                                                        const float* __restrict__ wAf,
-                                                        const float* __restrict__ wBf,
-                                                        double2* __restrict__ cpart, int64_t tiles_per_split,
-                                                        int P, int64_t n_tiles, int64_t m_waves) {
-    if (halted(ctrl)) return;
-    using Op = MfmaOp<T>;
-    using vec = typename Op::vec;
-    constexpr int NS = KP / Op::KSTEP;
-    const int64_t t = ctrl->t;
-    const Sched sc = sched[t - ctrl->t_base];
-    const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E);
-    const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
-    const int lane = threadIdx.x & 63;
-    const int hf = lane >> 5, c32 = lane & 31;
-    const int64_t b = blockIdx.x;
-    const int p = (int)(b % P);
-    const int64_t cw = (b / P) * 4 + (threadIdx.x >> 6);
-    if (cw >= m_waves) return;
-    const int64_t j = cw * 32 + c32;
-
-    vec bv[NS];
-    {
-        const vec* bp = reinterpret_cast<const vec*>(yop + j * KP + hf * (KP / 2));
-#pragma unroll
-        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
-    }
-    const float2 gg = gtabf[(t & 1) * m_pad + j];
-    const float gA = gg.x, gB = gg.y;
-    float accA[4] = {0.f, 0.f, 0.f, 0.f}, accB[4] = {0.f, 0.f, 0.f, 0.f};
-    const int64_t it0 = (int64_t)p * tiles_per_split;
-    const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
-    ColTile<T, KP> nx;
-    if (it0 < it1) load_col_tile<T, KP>(nx, xop, kf, wAf, wBf, it0, hf, c32);
-    for (int64_t it = it0; it < it1; ++it) {
-        const ColTile<T, KP> ct = nx;
-        if (it + 1 < it1) load_col_tile<T, KP>(nx, xop, kf, wAf, wBf, it + 1, hf, c32);
-        floatx16 d = Op::mma(ct.a[0], bv[0], ct.kv);
-#pragma unroll
-        for (int s = 1; s < NS; ++s) d = Op::mma(ct.a[s], bv[s], d);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            accA[r & 3] = fmaf(ct.wa[r], __builtin_amdgcn_exp2f(fmaf(d[r], cA, gA)), accA[r & 3]);
-            accB[r & 3] = fmaf(ct.wb[r], __builtin_amdgcn_exp2f(fmaf(d[r], cB, gB)), accB[r & 3]);
-        }
-    }
-    float sA = (accA[0] + accA[1]) + (accA[2] + accA[3]);
-    float sB = (accB[0] + accB[1]) + (accB[2] + accB[3]);
-    sA += __shfl_xor(sA, 32, 64);
-    sB += __shfl_xor(sB, 32, 64);
-    if (hf == 0 && j < kc.m) cpart[(int64_t)p * kc.m + j] = make_double2(sA, sB);
-}
-
 // Padded entries of the FP32 column tables (both parities): zero weight in every sum.
 __global__ void pad_gtabf(int64_t m, int64_t m_pad, float2* __restrict__ gtabf) {
     int64_t j = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -200,178 +102,6 @@ __global__ void prep_operands64(const double* __restrict__ src, int64_t cnt, int
     int k = (int)(idx % KP);
     out[idx] = (i < cnt && k < d) ? src[i * d + k] : 0.0;
 }
-
-// Row sweep: wave owns 16 rows; block b covers 64 rows (4 waves) of split p = b mod P.
-template <int KP>
-__global__ __launch_bounds__(BLOCK) void row_sweep_mfma64(const Ctrl* ctrl, const Sched* sched, Consts kc,
-                                                          const double* __restrict__ xop,
-                                                          const double* __restrict__ yop,
-                                                          const double2* __restrict__ gtab2,
-                                                          const double* __restrict__ H,
-                                                          double2* __restrict__ part, int64_t tiles_per_split,
-                                                          int P, int64_t m_tiles, int64_t n_waves) {
-    if (halted(ctrl)) return;
-    constexpr int NS = KP / 4;
-    const int64_t t = ctrl->t;
-    const Sched sc = sched[t - ctrl->t_base];
-    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
-    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
-    const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
-    const int lane = threadIdx.x & 63;
-    const int grp = lane >> 4, c16 = lane & 15;
-    const int64_t b = blockIdx.x;
-    const int p = (int)(b % P);
-    const int64_t rw = (b / P) * 4 + (threadIdx.x >> 6);
-    if (rw >= n_waves) return;
-    const int64_t i0 = rw * 16;
-    double a[NS];
-    {
-        const double* ap = xop + (i0 + c16) * KP + grp * NS;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) a[s] = ap[s];
-    }
-    doublex4 hv;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t ii = i0 + 4 * q + grp;
-        hv[q] = H[ii < kc.n ? ii : kc.n - 1];
-    }
-    float accA[4] = {0.f, 0.f, 0.f, 0.f}, accB[4] = {0.f, 0.f, 0.f, 0.f};
-    double sumA[4] = {0.0, 0.0, 0.0, 0.0}, sumB[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t jt0 = (int64_t)p * tiles_per_split;
-    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
-    int cnt = 0;
-    for (int64_t jt = jt0; jt < jt1; ++jt) {
-        const int64_t j = jt * 16 + c16;
-        const double* bp = yop + j * KP + grp * NS;
-        double bv[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
-        double gA = -1e300, gB = -1e300;
-        if (j < kc.m) {
-            const double2 gg = g[j];
-            gA = gg.x;
-            gB = gg.y;
-        }
-        doublex4 d = mma64(a[0], bv[0], hv);
-#pragma unroll
-        for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            accA[q] += fexp2(fma(d[q], cA, gA));
-            accB[q] += fexp2(fma(d[q], cB, gB));
-        }
-        if (++cnt == 8) {   // carry in FP64 every 8 terms
-            cnt = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                sumA[q] += (double)accA[q];
-                sumB[q] += (double)accB[q];
-                accA[q] = accB[q] = 0.f;
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        sumA[q] += (double)accA[q];
-        sumB[q] += (double)accB[q];
-        // sum over the 16 columns held by the 16 lanes of each group
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-            sumA[q] += __shfl_xor(sumA[q], o, 64);
-            sumB[q] += __shfl_xor(sumB[q], o, 64);
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t row = i0 + 4 * q + grp;
-        if (c16 == q && row < kc.n) part[(int64_t)p * kc.n + row] = make_double2(sumA[q], sumB[q]);
-    }
-}
-
-// Column sweep: wave owns 16 columns, streams 16-row tiles of split p.
-template <int KP>
-__global__ __launch_bounds__(BLOCK) void col_sweep_mfma64(const Ctrl* ctrl, const Sched* sched, Consts kc,
-                                                          const double* __restrict__ xop,
-                                                          const double* __restrict__ yop,
-                                                          const double2* __restrict__ gtab2,
-                                                          const RowVar* __restrict__ rowvar,
-                                                          double2* __restrict__ cpart, int64_t tiles_per_split,
-                                                          int P, int64_t n_tiles, int64_t m_waves) {
-    if (halted(ctrl)) return;
-    constexpr int NS = KP / 4;
-    const int64_t t = ctrl->t;
-    const Sched sc = sched[t - ctrl->t_base];
-    const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
-    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
-    const int lane = threadIdx.x & 63;
-    const int grp = lane >> 4, c16 = lane & 15;
-    const int64_t b = blockIdx.x;
-    const int p = (int)(b % P);
-    const int64_t cw = (b / P) * 4 + (threadIdx.x >> 6);
-    if (cw >= m_waves) return;
-    const int64_t j = cw * 16 + c16;
-    double bv[NS];
-    {
-        const double* bp = yop + j * KP + grp * NS;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) bv[s] = bp[s];
-    }
-    double gA = -1e300, gB = -1e300;
-    if (j < kc.m) {
-        const double2 gg = gtab2[(t & 1) * kc.m + j];
-        gA = gg.x;
-        gB = gg.y;
-    }
-    float accA = 0.f, accB = 0.f;
-    double sumA = 0.0, sumB = 0.0;
-    const int64_t it0 = (int64_t)p * tiles_per_split;
-    const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
-    for (int64_t it = it0; it < it1; ++it) {
-        const int64_t i = it * 16 + c16;
-        const double* ap = xop + i * KP + grp * NS;
-        double a[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) a[s] = ap[s];
-        doublex4 kv;
-        float wa[4], wb[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t row = it * 16 + 4 * q + grp;
-            if (row < kc.n) {
-                const RowVar rv = rowvar[row];
-                kv[q] = rv.k;
-                wa[q] = rv.wA;
-                wb[q] = rv.wB;
-            } else {
-                kv[q] = -1e300;
-                wa[q] = wb[q] = 0.f;
-            }
-        }
-        doublex4 d = mma64(a[0], bv[0], kv);
-#pragma unroll
-        for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            accA = fmaf(wa[q], fexp2(fma(d[q], cA, gA)), accA);
-            accB = fmaf(wb[q], fexp2(fma(d[q], cB, gB)), accB);
-        }
-        if (((it - it0) & 1) == 1) {   // carry in FP64 every 8 terms
-            sumA += (double)accA;
-            sumB += (double)accB;
-            accA = accB = 0.f;
-        }
-    }
-    sumA += (double)accA;
-    sumB += (double)accB;
-    // the 4 lane groups hold the same column for different rows
-    sumA += __shfl_xor(sumA, 16, 64);
-    sumB += __shfl_xor(sumB, 16, 64);
-    sumA += __shfl_xor(sumA, 32, 64);
-    sumB += __shfl_xor(sumB, 32, 64);
-    if (grp == 0 && j < kc.m) cpart[(int64_t)p * kc.m + j] = make_double2(sumA, sumB);
-}
-
 
 __global__ void pad_rowq(int64_t n, int64_t n_pad, float4* __restrict__ q) {
     int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -750,7 +480,7 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_mfma_lds(const Ctrl* ctrl, 
     }
 }
 
-// Column sweep of the BF16/FP16 forms with the roles of the operands swapped, LDS-shared
+// Column sweep of the matrix-core forms with the roles of the operands swapped, LDS-shared
 // row tiles: the wave's 32 columns y_j are the MFMA rows (fixed A operand) and the
 // streamed points x_i the MFMA columns, so the per-row data (k_i, w^A_i, w^B_i) is one
 // value per lane per tile instead of sixteen.  The column offsets enter as the
@@ -878,6 +608,8 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
 
 // FP64 matrix-core sweeps with LDS-shared tiles of 16 points (see the LDS-shared
 // half-precision sweeps above; the 16x16x4 FP64 layout is described with mma64).
+// Row sweep: wave owns 16 rows, a block 64 rows (4 waves) of split p = b mod P;
+// column sweep: wave owns 16 columns and streams 16-row tiles of split p.
 template <int KP>
 struct LdsTile64 {
     static constexpr int ROW_BYTES = KP * 8;
