@@ -79,14 +79,15 @@ def test_dt_summand_of_one_step_matches_oracle(shape, kind, steps):
         assert err <= DT_STEP_TOL * max(1.0, abs(ref))
 
 
-@pytest.mark.parametrize("kind", ["sqeuclid", "l1"])
-def test_dt_along_a_solve_and_midpoint_bound(kind):
+@pytest.mark.parametrize("kind,eta", [("sqeuclid", 1e-2), ("l1", 1e-2), ("sqeuclid", 0.0)])
+def test_dt_along_a_solve_and_midpoint_bound(kind, eta):
     """T iterations of the graph-captured loop with tracking (several replayed chunks), then the
-    certificate: D_T and 2||C||_inf (log m + (1 + alpha) log 2 + D_T)/T against the oracle's."""
-    wl, C, prob = _problem(96, 80, 2, kind, seed=71)
+    certificate: D_T and 2||C||_inf (log m + (1 + alpha) log 2 + D_T)/T against the oracle's;
+    eta = 0 is the setting of Proposition infeas_bound."""
+    wl, C, prob = _problem(96, 80, 2, kind, seed=71, eta=eta)
     T = 80
-    D, _, _ = OL.dt_sequence(C, wl.r, wl.c, OL.Params(eta=wl.eta), T, 1.0)
-    params = P.make_params(eta=wl.eta, tol=0.0, max_iter=T, check_every=16, track_dt=True)
+    D, _, _ = OL.dt_sequence(C, wl.r, wl.c, OL.Params(eta=eta), T, 1.0)
+    params = P.make_params(eta=eta, tol=0.0, max_iter=T, check_every=16, track_dt=True)
     st, rep, status = P.solve(prob, params)
     assert status == 0 and st.t == T
     cert = P.certificate(prob, params, st)
