@@ -1,5 +1,6 @@
-"""The C-ABI library loads and exports every function include/lamp.h declares, and
-the ctypes structures have the C layout (no compute calls: runs without a GPU)."""
+"""The C-ABI library loads and exports every function include/lamp.h declares, the
+ctypes structures have the C layout, and the host-side argument checks return their
+status codes (they run before any device call: no GPU needed)."""
 import ctypes
 import os
 import re
@@ -55,3 +56,70 @@ def test_ctypes_layout_matches_c(tmp_path):
             _lib.Report.row_fallbacks.offset, _lib.Params.track_dt.offset, _lib.State.dt_partial.offset,
             _lib.Cert.midpoint_bound.offset]
     assert got == want
+
+
+# ---------------------------------------------------------------- host argument checks
+
+FAKE = 0x100000          # non-null, 256-byte aligned; never dereferenced by the failing checks
+LAMP_EINVAL, LAMP_ENOMEM = -1, -3
+
+
+def _problem(**kw):
+    f = dict(n=100, m=80, d=3, metric=0, x=FAKE, y=FAKE, r=FAKE, c=FAKE, cost_scale=0.0, cost_norm=0.0)
+    f.update(kw)
+    return _lib.Problem(f["n"], f["m"], f["d"], f["metric"], f["x"], f["y"], f["r"], f["c"],
+                        f["cost_scale"], f["cost_norm"])
+
+
+def _params(**kw):
+    f = dict(eta=1e-2, tol=0.0, max_iter=10, alpha=0.0, beta=0.0, tau1=0.0, tau2=0.0, precision=0,
+             check_every=8, track_dt=0, reserved=0)
+    f.update(kw)
+    return _lib.Params(f["eta"], f["tol"], f["max_iter"], f["alpha"], f["beta"], f["tau1"], f["tau2"],
+                       f["precision"], f["check_every"], f["track_dt"], f["reserved"])
+
+
+def _step(prob, params, state=None, ws=FAKE, ws_bytes=1 << 40):
+    lib = _lib.load()
+    st = state if state is not None else _lib.State(FAKE, FAKE, 0, 0.0, 0.0)
+    return lib.lamp_step(ctypes.byref(prob), ctypes.byref(params), ctypes.byref(st), ws, ws_bytes, None,
+                         None, None)
+
+
+@pytest.mark.parametrize("case,kw", [("n = 0", dict(n=0)), ("m = 0", dict(m=0)), ("d = 0", dict(d=0)),
+                                     ("x NULL", dict(x=None)), ("c NULL", dict(c=None)),
+                                     ("unknown ground cost", dict(metric=7))])
+def test_invalid_problem_is_rejected(case, kw):
+    lib = _lib.load()
+    assert _step(_problem(**kw), _params()) == LAMP_EINVAL, case
+    assert lib.lamp_last_error()
+
+
+@pytest.mark.parametrize("case,kw", [("eta < 0", dict(eta=-1.0)), ("eta inf", dict(eta=float("inf"))),
+                                     ("tol NaN", dict(tol=float("nan"))), ("max_iter < 0", dict(max_iter=-1)),
+                                     ("unknown precision", dict(precision=9)), ("track_dt = 2", dict(track_dt=2)),
+                                     ("tracking in BF16", dict(track_dt=1, precision=_lib.PRECISIONS["bf16_mfma"]))])
+def test_invalid_params_are_rejected(case, kw):
+    assert _step(_problem(), _params(**kw)) == LAMP_EINVAL, case
+
+
+def test_workspace_and_form_checks():
+    lib = _lib.load()
+    prob, params = _problem(), _params()
+    need = lib.lamp_workspace_bytes(ctypes.byref(prob), ctypes.byref(params))
+    assert need > 0
+    big = _problem(n=1000, m=800)
+    assert lib.lamp_workspace_bytes(ctypes.byref(big), ctypes.byref(params)) > need
+    assert _step(prob, params, ws=None) == LAMP_EINVAL
+    assert _step(prob, params, ws=FAKE + 8) == LAMP_EINVAL          # not 256-byte aligned
+    assert _step(prob, params, ws_bytes=need - 1) == LAMP_ENOMEM
+    bf16 = _params(precision=_lib.PRECISIONS["bf16_mfma"])
+    assert _step(_problem(d=200), bf16) == LAMP_EINVAL               # matrix-core forms: d <= 128
+    assert _step(_problem(metric=_lib.METRICS["l1"]), bf16) == LAMP_EINVAL   # inner products only
+
+
+def test_invalid_state_is_rejected():
+    prob, params = _problem(), _params()
+    assert _step(prob, params, state=_lib.State(None, FAKE, 0, 0.0, 0.0)) == LAMP_EINVAL
+    assert _step(prob, params, state=_lib.State(FAKE, FAKE, -1, 0.0, 0.0)) == LAMP_EINVAL
+    assert _step(prob, params, state=_lib.State(FAKE, FAKE, 3, -1.0, 0.0)) == LAMP_EINVAL
