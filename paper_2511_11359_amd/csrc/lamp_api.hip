@@ -246,6 +246,10 @@ lamp_status check_ws(const lamp_problem* p, void* ws, size_t ws_bytes, int prec 
     if (is_mfma(prec) && p->metric != LAMP_SQEUCLID)
         return fail(LAMP_EINVAL, "the matrix-core forms need the squared Euclidean cost (inner products)");
     const Layout L = layout(p->n, p->m, p->d, prec, TARGET_BLOCKS, p->metric);
+    // the matrix-core sweeps address their operand copies with 32-bit buffer offsets
+    if (is_mfma(prec) && (uint64_t)std::max(L.n_pad, L.m_pad) * (uint64_t)(L.KP * L.esize) >= (1ull << 32))
+        return fail(LAMP_EINVAL, "the matrix-core forms need operand copies below 4 GiB (n, m <= %lld at d = %d)",
+                    (long long)((1ll << 32) / (L.KP * L.esize) - 128), p->d);
     if (!ws) return fail(LAMP_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(LAMP_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < L.total)

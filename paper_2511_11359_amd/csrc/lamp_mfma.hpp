@@ -275,12 +275,45 @@ __device__ __forceinline__ void store_tile(char* lds, TileRegs& R) {
     *reinterpret_cast<i32x4*>(lds + ROWS * STRIDE + (threadIdx.x & (ROWS - 1)) * 16) = R.s;
 }
 
+// Sources of the tile loads of the matrix-core forms as buffer resources: operand rows
+// and their per-point scalars (column table or row data, padded to whole tiles).  A load
+// is a wave-uniform byte offset of the tile (scalar) plus a fixed lane offset: no
+// per-lane address arithmetic in the loop.  Byte offsets are 32-bit (the host limits the
+// operand copies to less than 4 GiB); reads past num_bytes return zero.
+struct TileSrc {
+    __amdgpu_buffer_rsrc_t ops, scal;
+};
+
+constexpr int BUFFER_CONFIG = 0x00020000;   // raw buffer, 32-bit data format (gfx9)
+
+__device__ __forceinline__ TileSrc make_tile_src(const void* ops, uint32_t ops_bytes, const void* scal,
+                                                 uint32_t scal_bytes) {
+    return TileSrc{
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(ops), (short)0, (int)ops_bytes, BUFFER_CONFIG),
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(scal), (short)0, (int)scal_bytes, BUFFER_CONFIG)};
+}
+
+// Global -> registers part of the load of tile `tile` (32 points) and its SB-byte scalars.
 template <typename T, int KP, int SB>
-__device__ __forceinline__ void tile_fetch(const T* __restrict__ src_rows, int64_t row0, const void* __restrict__ scal,
-                                           int64_t scal_rows, TileRegs& R) {
+__device__ __forceinline__ void tile_fetch(const TileSrc& src, int tile, TileRegs& R) {
     using L = LdsTile<T, KP>;
-    fetch_tile<32, L::ROW_BYTES, L::PER_THREAD, SB>(reinterpret_cast<const char*>(src_rows + row0 * KP),
-                                                    reinterpret_cast<const char*>(scal), row0, scal_rows, R);
+    constexpr int CHUNKS = 32 * L::ROW_BYTES / 16;
+    const uint32_t tile_off = (uint32_t)tile * (32u * L::ROW_BYTES);
+    unroll_for<0, L::PER_THREAD>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const uint32_t c = threadIdx.x + q * BLOCK;
+        constexpr bool full = (q + 1) * BLOCK <= CHUNKS;   // every thread has a piece
+        if (full || c < (uint32_t)CHUNKS)
+            treg<q>(R) = __builtin_amdgcn_raw_buffer_load_b128(src.ops, c * 16u, tile_off, 0);
+    });
+    const uint32_t lane_s = (threadIdx.x & 31u) * (uint32_t)SB;
+    const uint32_t scal_off = (uint32_t)tile * (32u * SB);
+    if constexpr (SB == 16) {
+        R.s = __builtin_amdgcn_raw_buffer_load_b128(src.scal, lane_s, scal_off, 0);
+    } else {
+        const i32x2 v = __builtin_amdgcn_raw_buffer_load_b64(src.scal, lane_s, scal_off, 0);
+        R.s = i32x4{v.x, v.y, 0, 0};
+    }
 }
 
 template <typename T, int KP>
@@ -319,8 +352,16 @@ __device__ __forceinline__ floatx16 tile_dot(const char* lds, int c32, int hf,
 // and streams column tiles of split p = b mod P (P a multiple of 8 maps each split to
 // one XCD, whose L2 then holds that split's operand rows).
 // LDS-shared column tiles (see above).
+// Waves per SIMD the register allocation of row_sweep_mfma_lds must allow: three for the
+// half-precision forms up to 64 coordinates (their loop fits 168 registers without
+// spilling; the compiler's own choice is a few registers above, i.e. two waves).
 template <typename T, int KP>
-__global__ __launch_bounds__(BLOCK) void row_sweep_mfma_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
+constexpr int row_sweep_min_waves() {
+    return (sizeof(T) == 2 && KP <= 64) ? 3 : 1;
+}
+
+template <typename T, int KP>
+__global__ __launch_bounds__(BLOCK, (row_sweep_min_waves<T, KP>())) void row_sweep_mfma_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                             const T* __restrict__ xop, const T* __restrict__ yop,
                                                             const float2* __restrict__ gtabf, int64_t m_pad,
                                                             const double* __restrict__ H,
@@ -361,25 +402,26 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma_lds(const Ctrl* ctrl, co
 #pragma unroll
     for (int r = 0; r < 16; ++r) accA[r] = accB[r] = 0.f;
 
-    const int64_t jt0 = (int64_t)p * tiles_per_split;
-    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
+    const int jt0 = p * (int)tiles_per_split;
+    const int jt1 = min((int)m_tiles, jt0 + (int)tiles_per_split);
+    const TileSrc src = make_tile_src(yop, (uint32_t)(m_pad * KP * (int64_t)sizeof(T)), g, (uint32_t)(m_pad * 8));
     TileRegs pf;
     if (jt0 < jt1) {
-        const int64_t jl = jt1 - 1;
+        const int jl = jt1 - 1;
         // prologue: tile jt0 through buffer 0 into the matrix core, tile jt0 + 1 into buffer 1
-        tile_fetch<T, KP, 8>(yop, jt0 * 32, g, m_pad, pf);
+        tile_fetch<T, KP, 8>(src, jt0, pf);
         tile_store<T, KP>(lds[0], pf);
         __syncthreads();
         floatx16 dc = tile_dot<T, KP>(lds[0], c32, hf, a, hv);
         float2 gc = *reinterpret_cast<const float2*>(lds[0] + 32 * L::STRIDE + c32 * 16);
-        tile_fetch<T, KP, 8>(yop, min(jt0 + 1, jl) * 32, g, m_pad, pf);
+        tile_fetch<T, KP, 8>(src, min(jt0 + 1, jl), pf);
         tile_store<T, KP>(lds[1], pf);
         __syncthreads();
         loads_done();
 #pragma clang loop unroll(disable)
-        for (int64_t jt = jt0; jt < jt1; ++jt) {
-            const int nxt = (int)((jt + 1 - jt0) & 1);
-            tile_fetch<T, KP, 8>(yop, min(jt + 2, jl) * 32, g, m_pad, pf);
+        for (int jt = jt0; jt < jt1; ++jt) {
+            const int nxt = (jt + 1 - jt0) & 1;
+            tile_fetch<T, KP, 8>(src, min(jt + 2, jl), pf);
             const floatx16 dn = tile_dot<T, KP>(lds[nxt], c32, hf, a, hv);
             const float2 gn = *reinterpret_cast<const float2*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
 #pragma unroll
@@ -449,17 +491,18 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_mfma_lds(const Ctrl* ctrl, 
     float mx[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) mx[r] = -__builtin_inff();
-    const int64_t jt0 = (int64_t)p * tiles_per_split;
-    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
+    const int jt0 = p * (int)tiles_per_split;
+    const int jt1 = min((int)m_tiles, jt0 + (int)tiles_per_split);
+    const TileSrc src = make_tile_src(yop, (uint32_t)(m_pad * KP * (int64_t)sizeof(T)), g, (uint32_t)(m_pad * 8));
     TileRegs pf;
     if (jt0 < jt1) {
-        tile_fetch<T, KP, 8>(yop, jt0 * 32, g, m_pad, pf);
+        tile_fetch<T, KP, 8>(src, jt0, pf);
         tile_store<T, KP>(lds[0], pf);
     }
     __syncthreads();
-    for (int64_t jt = jt0; jt < jt1; ++jt) {
-        const int cur = (int)((jt - jt0) & 1);
-        if (jt + 1 < jt1) tile_fetch<T, KP, 8>(yop, (jt + 1) * 32, g, m_pad, pf);
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int cur = (jt - jt0) & 1;
+        if (jt + 1 < jt1) tile_fetch<T, KP, 8>(src, jt + 1, pf);
         const floatx16 d = tile_dot<T, KP>(lds[cur], c32, hf, a, zero);
         const float2 gg = *reinterpret_cast<const float2*>(lds[cur] + 32 * L::STRIDE + c32 * 16);
 #pragma unroll
@@ -539,12 +582,14 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
     float accA[16], accB[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) accA[r] = accB[r] = 0.f;
-    const int64_t it0 = (int64_t)p * tiles_per_split;
-    const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
+    const int it0 = p * (int)tiles_per_split;
+    const int it1 = min((int)n_tiles, it0 + (int)tiles_per_split);
     const int64_t n_rows = n_tiles * 32;
+    const TileSrc src = make_tile_src(xop, (uint32_t)(n_rows * KP * (int64_t)sizeof(T)), rowq,
+                                      (uint32_t)(n_rows * 16));
     TileRegs pf;
     if (it0 < it1) {
-        const int64_t il = it1 - 1;
+        const int il = it1 - 1;
         auto dots = [&](const char* buf, floatx16& dA, floatx16& dB) {
             typename Op::vec bv[NS];
             tile_operands<T, KP>(buf, c32, hf, bv);
@@ -557,20 +602,20 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
             }
             if constexpr (ONE_CHAIN) dA = dB;
         };
-        tile_fetch<T, KP, 16>(xop, it0 * 32, rowq, n_rows, pf);
+        tile_fetch<T, KP, 16>(src, it0, pf);
         tile_store<T, KP>(lds[0], pf);
         __syncthreads();
         floatx16 dcA, dcB;
         dots(lds[0], dcA, dcB);
         float4 qc = *reinterpret_cast<const float4*>(lds[0] + 32 * L::STRIDE + c32 * 16);
-        tile_fetch<T, KP, 16>(xop, min(it0 + 1, il) * 32, rowq, n_rows, pf);
+        tile_fetch<T, KP, 16>(src, min(it0 + 1, il), pf);
         tile_store<T, KP>(lds[1], pf);
         __syncthreads();
         loads_done();
 #pragma clang loop unroll(disable)
-        for (int64_t it = it0; it < it1; ++it) {
-            const int nxt = (int)((it + 1 - it0) & 1);
-            tile_fetch<T, KP, 16>(xop, min(it + 2, il) * 32, rowq, n_rows, pf);
+        for (int it = it0; it < it1; ++it) {
+            const int nxt = (it + 1 - it0) & 1;
+            tile_fetch<T, KP, 16>(src, min(it + 2, il), pf);
             floatx16 dnA, dnB;
             dots(lds[nxt], dnA, dnB);
             const float4 qn = *reinterpret_cast<const float4*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
