@@ -55,23 +55,32 @@ typedef enum {
 
 /* Ground cost C_ij = s dist(x_i, y_j) generated from the point clouds: the squared
  * Euclidean cost of Sections 1 and 4.1, and the l1 and l_inf costs of the
- * kernelized experiments (Section 5).  The matrix-core forms and the batching form
- * run the squared Euclidean cost only. */
+ * kernelized experiments (Section 5); or C_ij = s cost_ij from a cost matrix the
+ * caller stores (the non-kernelized costs of Appendix E, fused reductions).  The
+ * matrix-core forms and the batching form run the squared Euclidean cost only; the
+ * adjoints need point clouds. */
 typedef enum {
     LAMP_SQEUCLID = 0,   /* ||x - y||_2^2 */
     LAMP_L1 = 1,         /* sum_k |x_k - y_k| */
-    LAMP_LINF = 2        /* max_k |x_k - y_k| */
+    LAMP_LINF = 2,       /* max_k |x_k - y_k| */
+    LAMP_EXPLICIT = 3    /* cost_ij of lamp_problem.cost */
 } lamp_metric;
 
 /* Problem data (Section 1; Algorithm 2, REQUIRE line).
- *   x: n x d, y: m x d, row-major FP32 point clouds (device).
+ *   x: n x d, y: m x d, row-major FP32 point clouds (device).  Not read, and may be
+ *      NULL, with metric LAMP_EXPLICIT; d is then ignored.
  *   metric: lamp_metric of the ground cost.
  *   r: n, c: m, FP64 marginals (device), strictly positive, each summing to 1
  *      (the paper adds 1e-6 and renormalises to get full support, Appendix E).
  *   cost_scale: s in C_ij = s dist(x_i, y_j).  <= 0: s = 1 / max_ij dist(x_i, y_j) is
  *      computed on the device (then ||C||_inf = 1).
  *   cost_norm: ||C||_inf = max_ij C_ij.  <= 0: computed on the device.  Only
- *      trusted as given when both cost_scale and cost_norm are > 0. */
+ *      trusted as given when both cost_scale and cost_norm are > 0.
+ *   cost: with metric LAMP_EXPLICIT, the n x m cost matrix, row-major FP32 (device,
+ *      caller-owned, read only; entry (i, j) at cost[i m + j]).  Entries must be
+ *      finite and >= 0 with a positive maximum; that maximum is checked (LAMP_EDOMAIN
+ *      when it is not positive) only when the library computes the scale, the rest is
+ *      not checked.  Ignored, and may be NULL, for the other ground costs. */
 typedef struct {
     int64_t n, m;
     int32_t d, metric;
@@ -79,6 +88,7 @@ typedef struct {
     const double *r, *c;
     double cost_scale;
     double cost_norm;
+    const float *cost;
 } lamp_problem;
 
 /* Algorithm parameters (Algorithm 2; defaults from Appendix E, "for all LAMP
@@ -169,8 +179,8 @@ typedef struct {
 size_t lamp_workspace_bytes(const lamp_problem *prob, const lamp_params *params);
 
 /* s = 1 / max_ij dist(x_i, y_j) for the problem's ground cost (FP64 from the FP32
- * points), the normalisation that makes ||C||_inf = 1.  *max_sqdist_out (host,
- * nullable) gets the maximum. */
+ * points; max_ij cost_ij for LAMP_EXPLICIT), the normalisation that makes
+ * ||C||_inf = 1.  *max_sqdist_out (host, nullable) gets the maximum. */
 lamp_status lamp_cost_scale(const lamp_problem *prob, void *ws, size_t ws_bytes, void *stream,
                             double *s_out, double *max_sqdist_out);
 
@@ -202,7 +212,8 @@ lamp_status lamp_certificate(const lamp_problem *prob, const lamp_params *params
  *     l1:                grad_x[i, k] = grad_out * s r_i sum_j p_ij sign(x_ik - y_jk),
  *     l_inf:             the same restricted to the coordinate of max_k |x_ik - y_jk|
  *                        (the first on ties), sign(0) = 0 (subgradients at kinks),
- * written to grad_x (device, n x d, FP32, row-major).  Requires state->t >= 1. */
+ * written to grad_x (device, n x d, FP32, row-major).  Requires state->t >= 1 and
+ * point clouds (LAMP_EXPLICIT: LAMP_EINVAL). */
 lamp_status lamp_backward(const lamp_problem *prob, const lamp_params *params,
                           const lamp_state *state, double grad_out, float *grad_x, void *ws,
                           size_t ws_bytes, void *stream);
@@ -212,7 +223,7 @@ lamp_status lamp_backward(const lamp_problem *prob, const lamp_params *params,
  * iterate X^t, i.e. 2 s sum_i X_ij (y_j - x_i) for the squared Euclidean cost and the
  * subgradients -s sign(x_ik - y_jk) (l1; l_inf on the coordinate of the largest
  * |x_k - y_k|) for the others; written to grad_y (device, m x d, FP32, row-major).
- * Requires state->t >= 1. */
+ * Requires state->t >= 1 and point clouds (LAMP_EXPLICIT: LAMP_EINVAL). */
 lamp_status lamp_backward_y(const lamp_problem *prob, const lamp_params *params,
                             const lamp_state *state, double grad_out, float *grad_y, void *ws,
                             size_t ws_bytes, void *stream);

@@ -25,7 +25,7 @@ PRECISIONS = {"fp32": 0, "fp32_mfma": 1, "bf16_mfma": 2, "fp16_mfma": 3}
 LAMP_SQEUCLID = 0
 LAMP_L1 = 1
 LAMP_LINF = 2
-METRICS = {"sqeuclid": 0, "l1": 1, "linf": 2}
+METRICS = {"sqeuclid": 0, "l1": 1, "linf": 2, "explicit": 3}
 
 STATUS_NAMES = {0: "LAMP_OK", 1: "LAMP_NOT_CONVERGED", -1: "LAMP_EINVAL", -2: "LAMP_EDOMAIN",
                 -3: "LAMP_ENOMEM", -4: "LAMP_EDEVICE", -5: "LAMP_ENUMERIC"}
@@ -34,7 +34,7 @@ STATUS_NAMES = {0: "LAMP_OK", 1: "LAMP_NOT_CONVERGED", -1: "LAMP_EINVAL", -2: "L
 class Problem(ctypes.Structure):
     _fields_ = [("n", c_int64), ("m", c_int64), ("d", c_int32), ("metric", c_int32),
                 ("x", c_void_p), ("y", c_void_p), ("r", c_void_p), ("c", c_void_p),
-                ("cost_scale", c_double), ("cost_norm", c_double)]
+                ("cost_scale", c_double), ("cost_norm", c_double), ("cost", c_void_p)]
 
 
 class Params(ctypes.Structure):

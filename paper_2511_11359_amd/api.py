@@ -35,27 +35,43 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 class Problem:
     """Device-resident problem data (Section 1): x (n x d) and y (m x d) FP32 point clouds,
     r and c FP64 marginals, the ground cost (metric: "sqeuclid", "l1" or "linf"), and the
-    workspace the library works in."""
+    workspace the library works in.  Problem.from_cost gives the cost as an n x m matrix
+    instead (metric "explicit")."""
 
     def __init__(self, x, y, r, c, cost_scale: float = 0.0, cost_norm: float = 0.0,
-                 device: str | torch.device = "cuda", metric: str = "sqeuclid"):
+                 device: str | torch.device = "cuda", metric: str = "sqeuclid", cost=None):
         dev = torch.device(device)
         self.device = dev
-        self.x = torch.as_tensor(x, dtype=torch.float32).to(dev).contiguous()
-        self.y = torch.as_tensor(y, dtype=torch.float32).to(dev).contiguous()
         self.r = torch.as_tensor(r, dtype=torch.float64).to(dev).contiguous()
         self.c = torch.as_tensor(c, dtype=torch.float64).to(dev).contiguous()
-        assert self.x.dim() == 2 and self.y.dim() == 2 and self.x.shape[1] == self.y.shape[1]
-        self.n, self.d = self.x.shape
-        self.m = self.y.shape[0]
+        if metric == "explicit":
+            self.x = self.y = None
+            self.cost = torch.as_tensor(cost, dtype=torch.float32).to(dev).contiguous()
+            assert self.cost.dim() == 2
+            self.n, self.m = self.cost.shape
+            self.d = 1
+        else:
+            self.cost = None
+            self.x = torch.as_tensor(x, dtype=torch.float32).to(dev).contiguous()
+            self.y = torch.as_tensor(y, dtype=torch.float32).to(dev).contiguous()
+            assert self.x.dim() == 2 and self.y.dim() == 2 and self.x.shape[1] == self.y.shape[1]
+            self.n, self.d = self.x.shape
+            self.m = self.y.shape[0]
         self.cost_scale = float(cost_scale)
         self.cost_norm = float(cost_norm)
         self.metric = metric
         self._ws = None
 
+    @classmethod
+    def from_cost(cls, cost, r, c, cost_scale: float = 0.0, cost_norm: float = 0.0,
+                  device: str | torch.device = "cuda") -> "Problem":
+        """C_ij = cost_scale * cost[i, j] from an n x m matrix (stored as FP32, row-major)."""
+        return cls(None, None, r, c, cost_scale, cost_norm, device, metric="explicit", cost=cost)
+
     def struct(self) -> L.Problem:
-        return L.Problem(self.n, self.m, self.d, L.METRICS[self.metric], self.x.data_ptr(), self.y.data_ptr(),
-                         self.r.data_ptr(), self.c.data_ptr(), self.cost_scale, self.cost_norm)
+        ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        return L.Problem(self.n, self.m, self.d, L.METRICS[self.metric], ptr(self.x), ptr(self.y),
+                         self.r.data_ptr(), self.c.data_ptr(), self.cost_scale, self.cost_norm, ptr(self.cost))
 
     def workspace(self, params: L.Params) -> tuple[int, int]:
         lib = L.load()

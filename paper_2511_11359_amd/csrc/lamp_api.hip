@@ -21,6 +21,7 @@
 #include "lamp_kernels.hpp"
 #include "lamp_mfma.hpp"
 #include "lamp_batch.hpp"
+#include "lamp_cost.hpp"
 
 using namespace lampk;
 
@@ -82,6 +83,9 @@ struct Layout {
     int KP64;
     int64_t n_pad64, m_pad64, tps_r64, P_r64, tps_c64, P_c64;
     size_t xop64, yop64;
+    // sweeps over an explicit cost matrix
+    bool cost;
+    int64_t split_rx, P_rx, split_cx, P_cx;
 };
 
 bool is_mfma(int prec) { return prec == LAMP_FP32_MFMA || prec == LAMP_BF16_MFMA || prec == LAMP_FP16_MFMA; }
@@ -119,7 +123,8 @@ void mfma_split(int64_t owned_pad, int64_t streamed_tiles, int64_t* tps, int64_t
     *P = cdiv(streamed_tiles, *tps);
 }
 
-static_assert(LAMP_SQEUCLID == METRIC_SQEUCLID && LAMP_L1 == METRIC_L1 && LAMP_LINF == METRIC_LINF,
+static_assert(LAMP_SQEUCLID == METRIC_SQEUCLID && LAMP_L1 == METRIC_L1 && LAMP_LINF == METRIC_LINF &&
+                  LAMP_EXPLICIT == METRIC_EXPLICIT,
               "ground-cost codes of the ABI and the kernels agree");
 
 Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target = TARGET_BLOCKS,
@@ -142,6 +147,19 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     L.use64 = L.KP64 > 0 && metric == METRIC_SQEUCLID;   // FP64 matrix cores compute inner products only
     L.n_pad64 = cdiv(n, 64) * 64;
     L.m_pad64 = cdiv(m, 64) * 64;
+    L.cost = metric == METRIC_EXPLICIT;
+    if (L.cost) {
+        // row sweep: 32 rows per block, column splits in whole steps; column sweep:
+        // COST_COL_BLOCK columns per block, row splits of at least 64 rows
+        const int64_t rb = cdiv(n, 4 * COST_ROWS);
+        int64_t P = std::max<int64_t>(1, std::min<int64_t>(cdiv(target, rb), cdiv(m, COST_ROW_STEP)));
+        L.split_rx = cdiv(cdiv(m, P), COST_ROW_STEP) * COST_ROW_STEP;
+        L.P_rx = cdiv(m, L.split_rx);
+        const int64_t cb = cdiv(m, COST_COL_BLOCK);
+        P = std::max<int64_t>(1, std::min<int64_t>(cdiv(target, cb), cdiv(n, 64)));
+        L.split_cx = cdiv(n, P);
+        L.P_cx = cdiv(n, L.split_cx);
+    }
     if (L.use64) {
         mfma_split(L.n_pad64, L.m_pad64 / 16, &L.tps_r64, &L.P_r64, 64);
         mfma_split(L.m_pad64, L.n_pad64 / 16, &L.tps_c64, &L.P_c64, 64);
@@ -164,6 +182,10 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     if (L.use64) {
         rpart_d = std::max<size_t>(rpart_d, (size_t)L.P_r64 * n * 2);
         cpart_d2 = std::max<size_t>(cpart_d2, (size_t)L.P_c64 * m);
+    }
+    if (L.cost) {
+        rpart_d = std::max<size_t>(rpart_d, (size_t)L.P_rx * n * 2);
+        cpart_d2 = std::max<size_t>(cpart_d2, (size_t)L.P_cx * m);
     }
     L.ctrl = take(sizeof(Ctrl));
     L.sched = take(sizeof(Sched) * (TAB + 2));
@@ -218,13 +240,25 @@ struct Resolved {
 
 lamp_status check_problem(const lamp_problem* p) {
     if (!p) return fail(LAMP_EINVAL, "problem is NULL");
-    if (p->n < 1 || p->m < 1 || p->d < 1)
+    if (p->metric != LAMP_SQEUCLID && p->metric != LAMP_L1 && p->metric != LAMP_LINF &&
+        p->metric != LAMP_EXPLICIT)
+        return fail(LAMP_EINVAL, "unknown ground cost %d", p->metric);
+    const bool expl = p->metric == LAMP_EXPLICIT;
+    if (p->n < 1 || p->m < 1 || (!expl && p->d < 1))
         return fail(LAMP_EINVAL, "n, m and d must be >= 1 (got %lld, %lld, %d)", (long long)p->n,
                     (long long)p->m, p->d);
-    if (!p->x || !p->y || !p->r || !p->c) return fail(LAMP_EINVAL, "a problem array is NULL");
-    if (p->metric != LAMP_SQEUCLID && p->metric != LAMP_L1 && p->metric != LAMP_LINF)
-        return fail(LAMP_EINVAL, "unknown ground cost %d", p->metric);
+    if (!p->r || !p->c || (expl ? !p->cost : (!p->x || !p->y)))
+        return fail(LAMP_EINVAL, "a problem array is NULL");
     return LAMP_OK;
+}
+
+// The explicit-cost form works with one index code per point: d = 1 whatever the
+// caller set.  Returns p itself for the other ground costs.
+const lamp_problem* canonical(const lamp_problem* p, lamp_problem* buf) {
+    if (!p || p->metric != LAMP_EXPLICIT) return p;
+    *buf = *p;
+    buf->d = 1;
+    return buf;
 }
 
 lamp_status check_params(const lamp_params* q) {
@@ -289,6 +323,14 @@ void prep_ops(const lamp_problem* p, const Layout& L, void* ws, hipStream_t st) 
 
 lamp_status prep_L(const lamp_problem* p, const Layout& L, void* ws, hipStream_t st) {
     const int prec = L.prec;
+    if (L.cost) {
+        hipLaunchKernelGGL(prep_cost_codes, grid1(p->n), dim3(BLOCK), 0, st, p->n, 0, at<double>(ws, L.xc),
+                           at<double>(ws, L.xn2));
+        hipLaunchKernelGGL(prep_cost_codes, grid1(p->m), dim3(BLOCK), 0, st, p->m, 1, at<double>(ws, L.yc),
+                           at<double>(ws, L.yn2));
+        HIPCHK(hipGetLastError());
+        return LAMP_OK;
+    }
     hipLaunchKernelGGL(prep_points, grid1(p->n), dim3(BLOCK), 0, st, p->x, p->n, p->d, p->x, p->y,
                        at<double>(ws, L.xc), at<double>(ws, L.xn2), at<float>(ws, L.xcf), p->metric);
     hipLaunchKernelGGL(prep_points, grid1(p->m), dim3(BLOCK), 0, st, p->y, p->m, p->d, p->x, p->y,
@@ -351,6 +393,7 @@ bool valu_dispatch(int d, F&& launch) {
 // f(IC<M>) for the run-time metric.
 template <typename F>
 bool by_metric(int metric, F&& f) {
+    if (metric == METRIC_EXPLICIT) return false;   // the run-time (index code) form
     if (metric == METRIC_L1) return f(IC<METRIC_L1>{});
     if (metric == METRIC_LINF) return f(IC<METRIC_LINF>{});
     return f(IC<METRIC_SQEUCLID>{});
@@ -366,10 +409,18 @@ void row_extreme64(const Layout& L, Consts kc, void* ws, const double* a, double
 }
 
 // Number of partial minima written by launch_row_extreme.
-int extreme_parts(const Layout& L) { return (int)(L.use64 ? L.P_r64 : L.P_r); }
+int extreme_parts(const Layout& L) {
+    if (L.cost) return (int)L.P_rx;
+    return (int)(L.use64 ? L.P_r64 : L.P_r);
+}
 
 void launch_row_extreme(const Layout& L, Consts kc, int d, void* ws, const double* a, double sgn,
                         hipStream_t st) {
+    if (L.cost) {
+        dim3 g((unsigned)cdiv(kc.n, 4 * COST_ROWS), (unsigned)L.P_rx);
+        hipLaunchKernelGGL(row_extreme_cost, g, dim3(BLOCK), 0, st, kc, a, sgn, at<double>(ws, L.rpart), L.split_rx);
+        return;
+    }
     if (L.use64) {
         switch (L.KP64) {
             case 32: row_extreme64<32>(L, kc, ws, a, sgn, st); return;
@@ -467,13 +518,21 @@ void sweep_mfma64(const Layout& L, Consts kc, void* ws, hipStream_t st) {
 
 // Number of row / column partials written by the sweeps of this layout.
 int row_parts(const Layout& L) {
+    if (L.cost) return (int)L.P_rx;
     return (int)(is_mfma(L.prec) ? L.P_rm : (L.use64 ? L.P_r64 : L.P_r));
 }
 int col_parts(const Layout& L) {
+    if (L.cost) return (int)L.P_cx;
     return (int)(is_mfma(L.prec) ? L.P_cm : (L.use64 ? L.P_c64 : L.P_c));
 }
 
 void launch_row_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
+    if (L.cost) {
+        dim3 g((unsigned)cdiv(kc.n, 4 * COST_ROWS), (unsigned)L.P_rx);
+        hipLaunchKernelGGL(row_sweep_cost, g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched), kc,
+                           at<double2>(ws, L.gtab), at<double>(ws, L.H), at<double2>(ws, L.rpart), L.split_rx);
+        return;
+    }
     if (is_mfma(L.prec)) {
         sweep_mfma<true>(L, kc, ws, st);
         return;
@@ -501,6 +560,13 @@ void launch_row_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t s
 }
 
 void launch_col_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
+    if (L.cost) {
+        dim3 g((unsigned)cdiv(kc.m, COST_COL_BLOCK), (unsigned)L.P_cx);
+        hipLaunchKernelGGL(col_sweep_cost, g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched), kc,
+                           at<double2>(ws, L.gtab), at<RowVar>(ws, L.rowvar), at<double2>(ws, L.cpart),
+                           L.split_cx);
+        return;
+    }
     if (is_mfma(L.prec)) {
         sweep_mfma<false>(L, kc, ws, st);
         return;
@@ -555,6 +621,7 @@ lamp_status max_sqdist_L(const lamp_problem* p, const Layout& L, void* ws, hipSt
     kc.n = p->n;
     kc.m = p->m;
     kc.metric = p->metric;
+    kc.cost = p->metric == LAMP_EXPLICIT ? p->cost : nullptr;
     double* a = at<double>(ws, L.scratch);
     double* rowmax = a + std::max(p->n, p->m);
     hipLaunchKernelGGL(fill_scaled, grid1(p->m), dim3(BLOCK), 0, st, p->m, -0.5, at<double>(ws, L.yn2), a);
@@ -614,6 +681,7 @@ Consts make_consts(const lamp_problem* p, const Resolved& R) {
     kc.alpha_m = R.alpha / (double)p->m;
     kc.clipb = R.clipb;
     kc.metric = p->metric;
+    kc.cost = p->metric == LAMP_EXPLICIT ? p->cost : nullptr;
     return kc;
 }
 
@@ -716,6 +784,12 @@ void launch_dt_cost(const lamp_problem* p, const Layout& L, Consts kc, void* ws,
     const double* H = at<double>(ws, L.H);
     double* out = at<double>(ws, L.dtrow);
     const int d = p->d;
+    if (L.cost) {
+        hipLaunchKernelGGL(dt_cost_rows_cost, dim3((unsigned)cdiv(kc.n, 4 * COST_ROWS)), dim3(BLOCK), 0, st, ctrl, sch,
+                           kc, gt, H, p->r, out);
+        hipLaunchKernelGGL(dt_cost_total, dim3(1), dim3(1024), 0, st, ctrl, (const double*)out, kc.n);
+        return;
+    }
     const bool done = by_metric(kc.metric, [&](auto m) {
         return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
             hipLaunchKernelGGL((dt_cost_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0,
@@ -1219,6 +1293,8 @@ extern "C" {
 const char* lamp_last_error(void) { return g_err; }
 
 size_t lamp_workspace_bytes(const lamp_problem* prob, const lamp_params* params) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
     if (!prob || prob->n < 1 || prob->m < 1 || prob->d < 1) return 0;
     const int prec = params ? params->precision : LAMP_FP32;
     if (is_mfma(prec) && mfma_kp(prec, prob->d) == 0) return 0;
@@ -1227,6 +1303,8 @@ size_t lamp_workspace_bytes(const lamp_problem* prob, const lamp_params* params)
 
 lamp_status lamp_cost_scale(const lamp_problem* prob, void* ws, size_t ws_bytes, void* stream,
                             double* s_out, double* max_sqdist_out) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
     hipStream_t st = (hipStream_t)stream;
     lamp_status e;
     if ((e = check_problem(prob)) != LAMP_OK) return e;
@@ -1242,6 +1320,8 @@ lamp_status lamp_cost_scale(const lamp_problem* prob, void* ws, size_t ws_bytes,
 
 lamp_status lamp_step(const lamp_problem* prob, const lamp_params* params, lamp_state* state, void* ws,
                       size_t ws_bytes, void* stream, const lamp_trace* trace, double* res_out) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
     hipStream_t st = (hipStream_t)stream;
     lamp_status e;
     if ((e = check_state(state)) != LAMP_OK) return e;
@@ -1285,6 +1365,8 @@ lamp_status lamp_step(const lamp_problem* prob, const lamp_params* params, lamp_
 
 lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp_state* state, void* ws,
                        size_t ws_bytes, void* stream, lamp_report* out) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
     const auto t_start = std::chrono::steady_clock::now();
     lamp_status e;
     if ((e = check_state(state)) != LAMP_OK) return e;
@@ -1407,6 +1489,8 @@ lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp
 
 lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
                              void* ws, size_t ws_bytes, void* stream, lamp_cert* out) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
     hipStream_t st = (hipStream_t)stream;
     lamp_status e;
     if ((e = check_state(state)) != LAMP_OK) return e;
@@ -1518,11 +1602,15 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
 
 lamp_status lamp_backward(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
                           double grad_out, float* grad_x, void* ws, size_t ws_bytes, void* stream) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
     hipStream_t st = (hipStream_t)stream;
     lamp_status e;
     if ((e = check_state(state)) != LAMP_OK) return e;
     if (state->t < 1 || !(state->inv_eta > 0.0)) return fail(LAMP_EINVAL, "the gradient needs t >= 1");
     if (!grad_x) return fail(LAMP_EINVAL, "grad_x is NULL");
+    if (prob && prob->metric == LAMP_EXPLICIT)
+        return fail(LAMP_EINVAL, "the gradient with respect to the points needs point clouds");
     Resolved R;
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
     const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
@@ -1541,11 +1629,15 @@ lamp_status lamp_backward(const lamp_problem* prob, const lamp_params* params, c
 
 lamp_status lamp_backward_y(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
                             double grad_out, float* grad_y, void* ws, size_t ws_bytes, void* stream) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
     hipStream_t st = (hipStream_t)stream;
     lamp_status e;
     if ((e = check_state(state)) != LAMP_OK) return e;
     if (state->t < 1 || !(state->inv_eta > 0.0)) return fail(LAMP_EINVAL, "the gradient needs t >= 1");
     if (!grad_y) return fail(LAMP_EINVAL, "grad_y is NULL");
+    if (prob && prob->metric == LAMP_EXPLICIT)
+        return fail(LAMP_EINVAL, "the gradient with respect to the points needs point clouds");
     Resolved R;
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
     const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
@@ -1581,6 +1673,8 @@ lamp_status lamp_backward_y(const lamp_problem* prob, const lamp_params* params,
 lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
                              void* ws, size_t ws_bytes, void* stream, int32_t reps, double* row_ms,
                              double* col_ms) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
     hipStream_t st = (hipStream_t)stream;
     lamp_status e;
     if ((e = check_state(state)) != LAMP_OK) return e;

@@ -79,6 +79,7 @@ struct Consts {
     double alpha_m; // alpha / m
     double clipb;   // tanh(beta / 2)
     int metric;     // ground cost, METRIC_*
+    const float* cost;   // METRIC_EXPLICIT: the caller's n x m cost matrix, row-major
 };
 
 // ---------------------------------------------------------------------------
@@ -87,9 +88,13 @@ struct Consts {
 // the inner product with the squared norms for the squared Euclidean cost
 // (Sections 1 and 4.1), and -dist(x, y)/2 with zero norm arrays for the l1 and
 // l_inf costs of the kernelized experiments (Section 5).  The exponent assembly,
-// the offsets, the certificate and the cost maximum are then the same for all three.
+// the offsets, the certificate and the cost maximum are then the same for all of them.
+// A cost matrix given by the caller (METRIC_EXPLICIT) enters the same way, with
+// P_ij = -cost_ij / 2 and zero norms: its points carry index codes instead of
+// coordinates (d = 1), row i the code i and column j the code -(j + 1), so that the
+// generic pair term finds (i, j) whichever of the two points it is given first.
 // ---------------------------------------------------------------------------
-enum : int { METRIC_SQEUCLID = 0, METRIC_L1 = 1, METRIC_LINF = 2 };
+enum : int { METRIC_SQEUCLID = 0, METRIC_L1 = 1, METRIC_LINF = 2, METRIC_EXPLICIT = 3 };
 
 // init + P(x, y) with x in registers and y streamed.
 template <int M, int D>
@@ -110,9 +115,19 @@ __device__ __forceinline__ double pair_term(const double (&x)[D], const double* 
     }
 }
 
+// init - cost_ij / 2 for the index codes a, b of a row and a column (either order).
+__device__ __forceinline__ double pair_term_cost(const Consts& kc, double a, double b, double init) {
+    const bool row_first = a >= 0.0;
+    const int64_t i = (int64_t)(row_first ? a : b);
+    const int64_t j = -(int64_t)(row_first ? b : a) - 1;
+    return fma(-0.5, (double)kc.cost[i * kc.m + j], init);
+}
+
 // init + P(x, y), both operands in memory, metric and dimension at run time.
-__device__ __forceinline__ double pair_term_dyn(int M, int D, const double* __restrict__ x,
+__device__ __forceinline__ double pair_term_dyn(const Consts& kc, int D, const double* __restrict__ x,
                                                 const double* __restrict__ y, double init) {
+    const int M = kc.metric;
+    if (M == METRIC_EXPLICIT) return pair_term_cost(kc, x[0], y[0], init);
     if (M == METRIC_SQEUCLID) {
         double d = init;
         for (int k = 0; k < D; ++k) d = fma(x[k], y[k], d);
@@ -161,6 +176,15 @@ __global__ void prep_points(const float* __restrict__ pts, int64_t cnt, int d,
         acc = fma(v, v, acc);
     }
     nrm2[i] = metric == METRIC_SQEUCLID ? acc : 0.0;   // the l1 / l_inf pair term carries the cost
+}
+
+// Index codes of the points of an explicit cost matrix: i for row i, -(i + 1) for
+// column i (cols = 1); zero norms.
+__global__ void prep_cost_codes(int64_t cnt, int cols, double* __restrict__ out, double* __restrict__ nrm2) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    out[i] = cols ? -(double)(i + 1) : (double)i;
+    nrm2[i] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -268,7 +292,7 @@ __device__ __forceinline__ void row_extreme_dyn_body(Consts kc, int D, const dou
     const int64_t ii = i < kc.n ? i : kc.n - 1;
     double best = __builtin_inf();
     for (int64_t j = j0; j < j1; ++j) {
-        best = fmin(best, fma(sgn, pair_term_dyn(kc.metric, D, xc + ii * D, yc + j * D, 0.0), a[j]));
+        best = fmin(best, fma(sgn, pair_term_dyn(kc, D, xc + ii * D, yc + j * D, 0.0), a[j]));
     }
     if (i < kc.n) part[p * kc.n + i] = best;
 }
@@ -410,7 +434,7 @@ __device__ __forceinline__ void row_sweep_dyn_body(const Ctrl* ctrl, const Sched
         float accA = 0.f, accB = 0.f;
         const int64_t je = min(j1, jb + UNROLL);
         for (int64_t j = jb; j < je; ++j) {
-            const double dot = pair_term_dyn(kc.metric, D, xc + ii * D, yc + j * D, h);
+            const double dot = pair_term_dyn(kc, D, xc + ii * D, yc + j * D, h);
             accA += fexp2(fma(cA, dot, g[j].x));
             accB += fexp2(fma(cB, dot, g[j].y));
         }
@@ -430,17 +454,18 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_dyn(const Ctrl* ctrl, const S
 }
 
 // Exact recomputation of sigma_i = log2 sum_j 2^(g_j + cfac x~_i.y~_j) (two passes, FP64 max).
-__device__ double exact_sigma(int M, const double* __restrict__ xi, const double* __restrict__ yc, int D,
-                              int64_t m, const double2* __restrict__ g, int which, double cfac) {
+__device__ double exact_sigma(const Consts& kc, const double* __restrict__ xi, const double* __restrict__ yc, int D,
+                              const double2* __restrict__ g, int which, double cfac) {
+    const int64_t m = kc.m;
     double mx = -__builtin_inf();
     for (int64_t j = 0; j < m; ++j) {
-        const double dot = pair_term_dyn(M, D, xi, yc + j * D, 0.0);
+        const double dot = pair_term_dyn(kc, D, xi, yc + j * D, 0.0);
         double e = fma(cfac, dot, which ? g[j].y : g[j].x);
         mx = fmax(mx, e);
     }
     double s = 0.0;
     for (int64_t j = 0; j < m; ++j) {
-        const double dot = pair_term_dyn(M, D, xi, yc + j * D, 0.0);
+        const double dot = pair_term_dyn(kc, D, xi, yc + j * D, 0.0);
         double e = fma(cfac, dot, which ? g[j].y : g[j].x);
         s += exp2(e - mx);
     }
@@ -484,8 +509,8 @@ __device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, 
         sigB = log2(SB) - cB * h;
     } else {
         const double2* g = gtab2 + (t & 1) * kc.m;
-        sigA = exact_sigma(kc.metric, xc + i * D, yc, D, kc.m, g, 0, cA);
-        sigB = exact_sigma(kc.metric, xc + i * D, yc, D, kc.m, g, 1, cB);
+        sigA = exact_sigma(kc, xc + i * D, yc, D, g, 0, cA);
+        sigB = exact_sigma(kc, xc + i * D, yc, D, g, 1, cB);
         atomicAdd(&ctrl->fallbacks, 1);
     }
     const double hnew = -sigB / cB;
@@ -616,7 +641,7 @@ __device__ __forceinline__ void col_sweep_dyn_body(const Ctrl* ctrl, const Sched
         const int64_t ie = min(i1, ib + UNROLL);
         for (int64_t i = ib; i < ie; ++i) {
             const RowVar rv = rowvar[i];
-            const double dot = pair_term_dyn(kc.metric, D, yc + jj * D, xc + i * D, rv.k);
+            const double dot = pair_term_dyn(kc, D, yc + jj * D, xc + i * D, rv.k);
             accA = fmaf(rv.wA, fexp2(fma(cA, dot, g.x)), accA);
             accB = fmaf(rv.wB, fexp2(fma(cB, dot, g.y)), accB);
         }
@@ -706,7 +731,7 @@ __global__ __launch_bounds__(BLOCK) void dt_cost_rows_dyn(const Ctrl* ctrl, cons
         float aS = 0.f, aT = 0.f;
         const int64_t je = min(kc.m, jb + UNROLL);
         for (int64_t j = jb; j < je; ++j) {
-            const double dot = pair_term_dyn(kc.metric, D, xc + ii * D, yc + j * D, 0.0);
+            const double dot = pair_term_dyn(kc, D, xc + ii * D, yc + j * D, 0.0);
             const float p = fexp2(fma(cB, h + dot, g[j].y));
             const double cij = fma(-2.0 * kc.s, dot, xa + kc.s * yn2[j]);
             aS += p;
@@ -927,7 +952,7 @@ __global__ void reduce_sums(const double* __restrict__ vals, int64_t n, int64_t 
 template <int M, int D>
 struct OwnPoint {
     double x[D];
-    __device__ __forceinline__ OwnPoint(const double* __restrict__ src, int, int) {
+    __device__ __forceinline__ OwnPoint(const double* __restrict__ src, int, const Consts&) {
 #pragma unroll
         for (int k = 0; k < D; ++k) x[k] = src[k];
     }
@@ -937,11 +962,12 @@ struct OwnPoint {
 template <>
 struct OwnPoint<-1, 0> {
     const double* x;
-    int d, metric;
-    __device__ __forceinline__ OwnPoint(const double* __restrict__ src, int d_, int metric_)
-        : x(src), d(d_), metric(metric_) {}
+    int d;
+    Consts kc;
+    __device__ __forceinline__ OwnPoint(const double* __restrict__ src, int d_, const Consts& kc_)
+        : x(src), d(d_), kc(kc_) {}
     __device__ __forceinline__ double pair(const double* __restrict__ y) const {
-        return pair_term_dyn(metric, d, x, y, 0.0);
+        return pair_term_dyn(kc, d, x, y, 0.0);
     }
 };
 
@@ -970,7 +996,7 @@ __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int Dm, double cA,
                                                    double* __restrict__ vals, double* __restrict__ psum_out) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= kc.n) return;
-    const OwnPoint<M, D> own(xc + i * Dm, Dm, kc.metric);
+    const OwnPoint<M, D> own(xc + i * Dm, Dm, kc);
     const double h = H[i];
     double psum = 0.0, csum = 0.0, mth = __builtin_inf(), mnu = __builtin_inf();
     for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
@@ -1021,7 +1047,7 @@ __global__ __launch_bounds__(BLOCK) void round_cols(Consts kc, int Dm, double cA
                                                     const double* __restrict__ xr, double* __restrict__ colp) {
     const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (j >= kc.m) return;
-    const OwnPoint<M, D> own(yc + j * Dm, Dm, kc.metric);
+    const OwnPoint<M, D> own(yc + j * Dm, Dm, kc);
     const double g = gA[j];
     double acc = 0.0;
     for (int64_t ib = 0; ib < kc.n; ib += UNROLL) {
@@ -1058,7 +1084,7 @@ __global__ __launch_bounds__(BLOCK) void round_rows(Consts kc, int Dm, double cA
                                                     double* __restrict__ dr, double* __restrict__ cpp) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= kc.n) return;
-    const OwnPoint<M, D> own(xc + i * Dm, Dm, kc.metric);
+    const OwnPoint<M, D> own(xc + i * Dm, Dm, kc);
     const double h = H[i];
     double ps = 0.0, pq = 0.0, cs = 0.0;
     for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
@@ -1113,7 +1139,7 @@ __global__ __launch_bounds__(BLOCK) void round_rank_one_pairs(Consts kc, int D, 
     if (i >= kc.n) return;
     double acc = 0.0;
     for (int64_t j = 0; j < kc.m; ++j)
-        acc = fma(-2.0 * kc.s * pair_term_dyn(kc.metric, D, xc + i * D, yc + j * D, 0.0), dc[j], acc);
+        acc = fma(-2.0 * kc.s * pair_term_dyn(kc, D, xc + i * D, yc + j * D, 0.0), dc[j], acc);
     t[i] = dr[i] * acc;
     absdr[i] = fabs(dr[i]);
 }
@@ -1250,7 +1276,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep_dyn(Consts kc, int D, dou
         for (int k = 0; k < D; ++k) o[1 + k] = 0.0;
     for (int64_t j = j0; j < j1; ++j) {
         const double* yj = yc + j * D;
-        const double pij = (double)fexp2(fma(cA, pair_term_dyn(kc.metric, D, xi, yj, h), gA[j]));
+        const double pij = (double)fexp2(fma(cA, pair_term_dyn(kc, D, xi, yj, h), gA[j]));
         if (kc.metric == METRIC_SQEUCLID) {
             s0 += pij;
             if (i < kc.n)
@@ -1375,7 +1401,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_y_sweep_dyn(Consts kc, int D, d
     for (int64_t i = i0; i < i1; ++i) {
         const RowVar rv = rowvar[i];
         const double* xi = xc + i * D;
-        const double xij = (double)rv.wA * (double)fexp2(fma(cA, pair_term_dyn(kc.metric, D, yj, xi, rv.k), g));
+        const double xij = (double)rv.wA * (double)fexp2(fma(cA, pair_term_dyn(kc, D, yj, xi, rv.k), g));
         if (kc.metric == METRIC_SQEUCLID) {
             s0 += xij;
             if (j < kc.m)

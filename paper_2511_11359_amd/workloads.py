@@ -139,6 +139,88 @@ def random_small(n: int, m: int, d: int, seed: int, uniform: bool = False,
     return Workload(f"rand_{n}x{m}x{d}", x, y, r, c, eta=eta, tol=0.0, max_iter=100)
 
 
+@dataclass
+class CostWorkload:
+    """A problem given by its cost matrix (the explicit-cost input) instead of points."""
+    name: str
+    cost: np.ndarray       # n x m, float32, row-major, entries >= 0 (a device tensor for the large ones)
+    r: np.ndarray
+    c: np.ndarray
+    eta: float
+
+
+def image_marginal(k: int, g: np.random.Generator) -> np.ndarray:
+    """A k x k 'image' as a marginal (row-major pixels): a few Gaussian blobs of random
+    centre, width and weight on a faint background, with the full-support fix."""
+    yy, xx = np.mgrid[0:k, 0:k].astype(np.float64)
+    img = np.full((k, k), 0.02)
+    for _ in range(int(g.integers(2, 6))):
+        cy, cx = g.uniform(0, k - 1, 2)
+        w = g.uniform(0.05, 0.3) * k
+        img += g.uniform(0.2, 1.0) * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2.0 * w * w))
+    return full_support(img.ravel())
+
+
+def grid_cost(k: int, kind: str = "sqeuclid") -> np.ndarray:
+    """Ground cost between the pixels of two k x k grids (integer coordinates), the cost of
+    image-pair transport benchmarks: sum_k |di|^2 ("sqeuclid"), sum_k |di| ("l1"),
+    max_k |di| ("linf").  Integer entries, exact in FP32 for k <= 2^11."""
+    yy, xx = np.divmod(np.arange(k * k), k)
+    dy = np.abs(yy[:, None] - yy[None, :]).astype(np.float64)
+    dx = np.abs(xx[:, None] - xx[None, :]).astype(np.float64)
+    if kind == "sqeuclid":
+        cmat = dy * dy + dx * dx
+    elif kind == "l1":
+        cmat = dy + dx
+    else:
+        cmat = np.maximum(dy, dx)
+    return cmat.astype(np.float32)
+
+
+def grid_cost_device(k: int, kind: str, device, rows_per_chunk: int = 4096):
+    """grid_cost(k, kind) built on a torch device in row chunks (n = m = k^2 entries squared:
+    16 GiB of FP32 at k = 256), for sizes whose matrix should not pass through host memory."""
+    import torch
+    n = k * k
+    idx = torch.arange(n, device=device, dtype=torch.int64)
+    yy, xx = idx // k, idx % k
+    out = torch.empty(n, n, dtype=torch.float32, device=device)
+    for i0 in range(0, n, rows_per_chunk):
+        i1 = min(n, i0 + rows_per_chunk)
+        dy = (yy[i0:i1, None] - yy[None, :]).abs()
+        dx = (xx[i0:i1, None] - xx[None, :]).abs()
+        if kind == "sqeuclid":
+            blk = dy * dy + dx * dx
+        elif kind == "l1":
+            blk = dy + dx
+        else:
+            blk = torch.maximum(dy, dx)
+        out[i0:i1] = blk.to(torch.float32)
+    return out
+
+
+def image_pair(k: int, kind: str = "sqeuclid", seed: int = 1101, eta: float = 0.0) -> CostWorkload:
+    """Transport between two random k x k images (n = m = k^2) over the grid cost."""
+    g = _rng(seed)
+    return CostWorkload(f"images_{k}x{k}_{kind}", grid_cost(k, kind), image_marginal(k, g), image_marginal(k, g),
+                        eta)
+
+
+def image_pair_device(k: int = 256, kind: str = "sqeuclid", seed: int = 1201, device="cuda") -> CostWorkload:
+    """image_pair at sizes whose matrix is built on the device (cost is a torch tensor there);
+    k = 256 gives the n = m = 2^16 cost-matrix benchmark (16 GiB of FP32)."""
+    g = _rng(seed)
+    r, c = image_marginal(k, g), image_marginal(k, g)
+    return CostWorkload(f"images_{k}x{k}_{kind}", grid_cost_device(k, kind, device), r, c, 0.0)
+
+
+def random_cost(n: int, m: int, seed: int, eta: float = 1e-2) -> CostWorkload:
+    """Non-metric cost: independent uniform [0, 1) entries, Dirichlet marginals."""
+    g = _rng(seed)
+    cost = g.random((n, m), dtype=np.float32)
+    return CostWorkload(f"randcost_{n}x{m}", cost, dirichlet_ones(g, n), dirichlet_ones(g, m), eta)
+
+
 WORKLOADS = {
     "uniform2d_256": uniform_square,
     "gauss3d_4096": gaussian_pair,

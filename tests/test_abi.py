@@ -40,12 +40,12 @@ def test_ctypes_layout_matches_c(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lamp.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
         "sizeof(lamp_problem), sizeof(lamp_params), sizeof(lamp_state), sizeof(lamp_trace),"
         "sizeof(lamp_cert), sizeof(lamp_report), offsetof(lamp_problem, cost_norm),"
         "offsetof(lamp_params, check_every), offsetof(lamp_report, row_fallbacks),"
         "offsetof(lamp_params, track_dt), offsetof(lamp_state, dt_partial),"
-        "offsetof(lamp_cert, midpoint_bound));return 0;}\n")
+        "offsetof(lamp_cert, midpoint_bound), offsetof(lamp_problem, cost));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
@@ -54,7 +54,7 @@ def test_ctypes_layout_matches_c(tmp_path):
             ctypes.sizeof(_lib.Trace), ctypes.sizeof(_lib.Cert), ctypes.sizeof(_lib.Report),
             _lib.Problem.cost_norm.offset, _lib.Params.check_every.offset,
             _lib.Report.row_fallbacks.offset, _lib.Params.track_dt.offset, _lib.State.dt_partial.offset,
-            _lib.Cert.midpoint_bound.offset]
+            _lib.Cert.midpoint_bound.offset, _lib.Problem.cost.offset]
     assert got == want
 
 
@@ -65,10 +65,11 @@ LAMP_EINVAL, LAMP_ENOMEM = -1, -3
 
 
 def _problem(**kw):
-    f = dict(n=100, m=80, d=3, metric=0, x=FAKE, y=FAKE, r=FAKE, c=FAKE, cost_scale=0.0, cost_norm=0.0)
+    f = dict(n=100, m=80, d=3, metric=0, x=FAKE, y=FAKE, r=FAKE, c=FAKE, cost_scale=0.0, cost_norm=0.0,
+             cost=None)
     f.update(kw)
     return _lib.Problem(f["n"], f["m"], f["d"], f["metric"], f["x"], f["y"], f["r"], f["c"],
-                        f["cost_scale"], f["cost_norm"])
+                        f["cost_scale"], f["cost_norm"], f["cost"])
 
 
 def _params(**kw):
@@ -88,7 +89,8 @@ def _step(prob, params, state=None, ws=FAKE, ws_bytes=1 << 40):
 
 @pytest.mark.parametrize("case,kw", [("n = 0", dict(n=0)), ("m = 0", dict(m=0)), ("d = 0", dict(d=0)),
                                      ("x NULL", dict(x=None)), ("c NULL", dict(c=None)),
-                                     ("unknown ground cost", dict(metric=7))])
+                                     ("unknown ground cost", dict(metric=7)),
+                                     ("cost matrix NULL", dict(metric=3, cost=None))])
 def test_invalid_problem_is_rejected(case, kw):
     lib = _lib.load()
     assert _step(_problem(**kw), _params()) == LAMP_EINVAL, case
@@ -123,3 +125,19 @@ def test_invalid_state_is_rejected():
     assert _step(prob, params, state=_lib.State(None, FAKE, 0, 0.0, 0.0)) == LAMP_EINVAL
     assert _step(prob, params, state=_lib.State(FAKE, FAKE, -1, 0.0, 0.0)) == LAMP_EINVAL
     assert _step(prob, params, state=_lib.State(FAKE, FAKE, 3, -1.0, 0.0)) == LAMP_EINVAL
+
+
+def test_explicit_cost_checks():
+    """A cost-matrix problem needs no point clouds and ignores d; the matrix-core forms and
+    the point adjoints reject it before any device work."""
+    lib = _lib.load()
+    params = _params()
+    expl = _problem(metric=_lib.METRICS["explicit"], x=None, y=None, d=0, cost=FAKE)
+    assert lib.lamp_workspace_bytes(ctypes.byref(expl), ctypes.byref(params)) > 0
+    bf16 = _params(precision=_lib.PRECISIONS["bf16_mfma"])
+    assert _step(expl, bf16) == LAMP_EINVAL
+    st = _lib.State(FAKE, FAKE, 3, 1.0, 0.0)
+    for fn in (lib.lamp_backward, lib.lamp_backward_y):
+        assert fn(ctypes.byref(expl), ctypes.byref(params), ctypes.byref(st), 1.0, FAKE, FAKE, 1 << 40,
+                  None) == LAMP_EINVAL
+        assert b"point clouds" in lib.lamp_last_error()

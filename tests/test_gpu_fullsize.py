@@ -172,3 +172,38 @@ def test_sphere_cube_bf16_forward_then_fp32_adjoint():
         _say(f"grad[{i},{k}] gpu {g[i, k]:.9e} oracle {gi:.9e} fd {fd:.9e}")
         assert abs(g[i, k] - gi) <= 1e-5 * scale + 1e-12
         assert abs(fd - gi) <= 1e-4 * scale + 1e-12
+
+
+def test_images_256_explicit_cost_step():
+    """The cost-matrix benchmark at n = m = 2^16 (two 256 x 256 images, squared Euclidean grid
+    cost, 16 GiB FP32 on the device): the cost maximum against its closed form 2 (k - 1)^2;
+    one iteration at t = 300 from a synthetic state in the launch configuration the benchmark
+    times, sampled rows' log-normalisers against the oracle (cost rows from the pixel
+    coordinates), each column marginal summing to 1."""
+    k = 256
+    wl = W.image_pair_device(k, "sqeuclid", device="cuda")
+    prob = P.Problem.from_cost(wl.cost, wl.r, wl.c)
+    s, cmax = P.cost_scale(prob)
+    assert cmax == 2.0 * (k - 1) ** 2 and s == 1.0 / cmax
+    prob.cost_scale, prob.cost_norm = s, 1.0
+    n = k * k
+    t = 300
+    nu, th = W.synthetic_duals(n, 77)
+    lam = OL.inv_eta_schedule(t + 1, 0.5, wl.eta)
+    st = P.State(torch.tensor(nu, device="cuda"), torch.tensor(th, device="cuda"), t, lam[t])
+    res, tr = P.step(prob, P.make_params(eta=wl.eta), st, trace=True)
+    yy, xx = np.divmod(np.arange(n), k)
+    pts = np.stack([yy, xx], axis=1).astype(np.float64)
+    Crows = OL.ground_cost(pts[SAMPLE], pts, s, "sqeuclid")
+    nubar = nu + (0.5 / lam[t + 1]) * (th - nu)
+    la = OL.log_normaliser(Crows, nu, lam[t], 1.0)
+    lb = OL.log_normaliser(Crows, nubar, lam[t + 1], 1.0)
+    ea = np.max(np.abs(to_np(tr["log_za"])[SAMPLE] - la))
+    eb = np.max(np.abs(to_np(tr["log_zb"])[SAMPLE] - lb))
+    ca, cb = to_np(tr["col_a"]), to_np(tr["col_b"])
+    _say(f"explicit 2^16: logZA err {ea:.2e} logZB err {eb:.2e} sum colA-1 {ca.sum() - 1:.2e} "
+         f"sum colB-1 {cb.sum() - 1:.2e} res {res:.3e}")
+    assert ea <= 2e-6 and eb <= 2e-6
+    assert abs(ca.sum() - 1.0) <= 1e-6 and abs(cb.sum() - 1.0) <= 1e-6
+    assert np.all(ca >= 0) and np.all(cb >= 0)
+    assert np.all(np.abs(to_np(st.theta)) < 1) and np.all(np.abs(to_np(st.nu)) < 1)
