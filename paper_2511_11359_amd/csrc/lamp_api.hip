@@ -681,6 +681,7 @@ Consts make_consts(const lamp_problem* p, const Resolved& R) {
     kc.alpha_m = R.alpha / (double)p->m;
     kc.clipb = R.clipb;
     kc.metric = p->metric;
+    kc.factor_cols = 2.0 * LOG2E * R.K * R.tau1 <= 64.0;
     kc.cost = p->metric == LAMP_EXPLICIT ? p->cost : nullptr;
     return kc;
 }

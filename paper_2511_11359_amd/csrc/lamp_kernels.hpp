@@ -79,6 +79,7 @@ struct Consts {
     double alpha_m; // alpha / m
     double clipb;   // tanh(beta / 2)
     int metric;     // ground cost, METRIC_*
+    int factor_cols;     // one-chain matrix-core column sweep: per-column factor (see there)
     const float* cost;   // METRIC_EXPLICIT: the caller's n x m cost matrix, row-major
 };
 

@@ -16,6 +16,8 @@
 
 #include "lamp_kernels.hpp"
 
+#include <type_traits>
+
 namespace lampk {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -533,9 +535,14 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_mfma_lds(const Ctrl* ctrl, 
 // with one matrix-core step per tile (d <= 16) each coupling gets its own chain; with
 // NS >= 4 steps the second chain costs more than one add per term, and one chain
 // (accumulator G^B) serves both:
-//     e^A = c^A (d^B + k_i) + (g^A_j - c^A G^B_j),   d^B = x~_i . y~_j + G^B_j
+//     e^A = c^A (d^B + k_i) + CA_j,   d^B = x~_i . y~_j + G^B_j,   CA_j = g^A_j - c^A G^B_j
 // (measured: column sweep 1.49 -> 1.30 ms at n = m = 2^16, d = 64; at d = 3 the two
-// chains are 7% faster than one).
+// chains are 7% faster than one).  CA_j does not depend on the streamed row, so the
+// column's sum is accumulated without it and multiplied by 2^CA_j once at the end,
+// which saves the add per term (kc.factor_cols).  The unscaled sums stay in FP32 range:
+// by the column tables of iteration t, CA_j = LOG2E K tau1 (lam_t / lam_{t+1})
+// (theta_j - nu_j), so |CA_j| <= 2 LOG2E K tau1 (2.9 with the default tau1); the host
+// keeps the per-term add when that bound exceeds 64.
 template <typename T, int KP>
 __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                               const T* __restrict__ xop, const T* __restrict__ yop,
@@ -612,27 +619,42 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
         tile_store<T, KP>(lds[1], pf);
         __syncthreads();
         loads_done();
+        auto stream_tiles = [&](auto factor_tag) {
+            constexpr bool FACTOR = decltype(factor_tag)::value;
 #pragma clang loop unroll(disable)
-        for (int it = it0; it < it1; ++it) {
-            const int nxt = (it + 1 - it0) & 1;
-            tile_fetch<T, KP, 16>(src, min(it + 2, il), pf);
-            floatx16 dnA, dnB;
-            dots(lds[nxt], dnA, dnB);
-            const float4 qn = *reinterpret_cast<const float4*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
-            const float ckA = cA * qc.x, ckB = cB * qc.x;
+            for (int it = it0; it < it1; ++it) {
+                const int nxt = (it + 1 - it0) & 1;
+                tile_fetch<T, KP, 16>(src, min(it + 2, il), pf);
+                floatx16 dnA, dnB;
+                dots(lds[nxt], dnA, dnB);
+                const float4 qn = *reinterpret_cast<const float4*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
+                const float ckA = cA * qc.x, ckB = cB * qc.x;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const float eA = ONE_CHAIN ? fmaf(dcB[r], cA, ckA) + CA[r] : fmaf(dcA[r], cA, ckA);
-                accA[r] = fmaf(qc.y, __builtin_amdgcn_exp2f(eA), accA[r]);
-                accB[r] = fmaf(qc.z, __builtin_amdgcn_exp2f(fmaf(dcB[r], cB, ckB)), accB[r]);
+                for (int r = 0; r < 16; ++r) {
+                    const float eA = !ONE_CHAIN ? fmaf(dcA[r], cA, ckA)
+                                                : (FACTOR ? fmaf(dcB[r], cA, ckA) : fmaf(dcB[r], cA, ckA) + CA[r]);
+                    accA[r] = fmaf(qc.y, __builtin_amdgcn_exp2f(eA), accA[r]);
+                    accB[r] = fmaf(qc.z, __builtin_amdgcn_exp2f(fmaf(dcB[r], cB, ckB)), accB[r]);
+                }
+                pin(accA);
+                pin(accB);
+                tile_store<T, KP>(lds[nxt ^ 1], pf);
+                __syncthreads();
+                dcA = dnA;
+                dcB = dnB;
+                qc = qn;
             }
-            pin(accA);
-            pin(accB);
-            tile_store<T, KP>(lds[nxt ^ 1], pf);
-            __syncthreads();
-            dcA = dnA;
-            dcB = dnB;
-            qc = qn;
+        };
+        if constexpr (ONE_CHAIN) {
+            if (kc.factor_cols) {
+                stream_tiles(std::true_type{});
+#pragma unroll
+                for (int r = 0; r < 16; ++r) accA[r] *= __builtin_amdgcn_exp2f(CA[r]);
+            } else {
+                stream_tiles(std::false_type{});
+            }
+        } else {
+            stream_tiles(std::false_type{});
         }
     }
     if (!active) return;
