@@ -24,6 +24,7 @@ from __future__ import annotations
 import argparse
 import glob
 import hashlib
+import re
 import json
 import os
 import sys
@@ -103,10 +104,16 @@ def measure_form(P, prob, wl, form, steps, warmup, reps):
 
 
 def kernel_sources_sha256():
+    """SHA-256 of the kernel headers' code: comments, blank lines and trailing blanks removed,
+    so that a counter summary stays valid across edits that change no kernel."""
     h = hashlib.sha256()
     for f in ("lamp_mfma.hpp", "lamp_kernels.hpp", "lamp_cost.hpp"):
-        with open(os.path.join(ROOT, "paper_2511_11359_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2511_11359_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 
