@@ -925,11 +925,6 @@ constexpr int kNumBatchCands = (int)(sizeof(kBatchCands) / sizeof(kBatchCands[0]
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune_cache;   // batch signature -> candidate index
 
-__global__ void gather_ctrl(const ProbDesc* __restrict__ pd, int count, Ctrl* __restrict__ out) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < count) out[p] = *pd[p].ctrl;
-}
-
 __global__ void set_epoch(const ProbDesc* __restrict__ pd, int count, int64_t t_base, int64_t t_end) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < count) {

@@ -855,7 +855,7 @@ __device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched,
     shd[threadIdx.x] = dtj;
     __syncthreads();
     for (int o = BLOCK / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+        if ((int)threadIdx.x < o) {
             sh[threadIdx.x] += sh[threadIdx.x + o];
             shd[threadIdx.x] += shd[threadIdx.x + o];
         }
@@ -921,7 +921,7 @@ __global__ void reduce_max(const double* __restrict__ v, int64_t n, double* __re
     sh[threadIdx.x] = best;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = sh[0];
@@ -937,7 +937,7 @@ __global__ void reduce_sums(const double* __restrict__ vals, int64_t n, int64_t 
         sh[threadIdx.x] = acc;
         __syncthreads();
         for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-            if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
             __syncthreads();
         }
         if (threadIdx.x == 0) out[q] = sh[0];
@@ -1123,7 +1123,7 @@ __global__ void round_col_sums(Consts kc, int D, const double* __restrict__ yc, 
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int o = BLOCK / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) S[b] = sh[0];
