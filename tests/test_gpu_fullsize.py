@@ -42,7 +42,7 @@ def _synthetic_state(wl, t, seed):
     return nu, th, lam[t], lam[t + 1]
 
 
-def _check_step(wl, key, precision, t, rows, logz_atol, rounded=None):
+def _check_step(wl, key, precision, t, rows, logz_atol, rounded=None, with_trace=False):
     s = GOLD[key]["cost_scale"]
     nu, th, lam_t, lam_t1 = _synthetic_state(wl, t, seed=77)
     prob = P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=s, cost_norm=1.0)
@@ -65,7 +65,25 @@ def _check_step(wl, key, precision, t, rows, logz_atol, rounded=None):
     # marginals are non-negative; a column whose every term lies below FP32's range reads 0
     assert np.all(ca >= 0) and np.all(cb >= 0)
     assert np.all(np.abs(to_np(st.theta)) < 1) and np.all(np.abs(to_np(st.nu)) < 1)
-    return prob, st
+    return (prob, st, tr) if with_trace else (prob, st)
+
+
+def _check_certificate(prob, params, nu, th, t, lam_t, col_a, c):
+    """Certificate of the iterate X^t a step started from (the state before the step), at full
+    size, by properties that hold at any size: its column residual equals ||col(X^t) - c||_1
+    from the sweep's own column marginal of the same iterate (a different kernel path), the
+    row residual vanishes (row feasibility, eq:row_feasible), weak duality puts D(theta) and
+    D(nu) below the cost of the feasible plan Round(X^t), and Round moves the cost by at most
+    ||C||_inf ||X - Round(X)||_1 <= K (row_res + col_res) (Algorithm 3 guarantee)."""
+    st0 = P.State(torch.tensor(nu, device="cuda"), torch.tensor(th, device="cuda"), t, lam_t)
+    cert = P.certificate(prob, params, st0)
+    ref_col = float(np.abs(col_a - c).sum())
+    _say("certificate", {k: cert[k] for k in ["col_res", "row_res", "cost", "rounded_cost", "dual_theta",
+                                              "dual_nu", "primal_penalized"]}, "sweep col_res", ref_col)
+    assert abs(cert["col_res"] - ref_col) <= 1e-6 * max(1.0, ref_col)
+    assert cert["row_res"] <= 1e-6
+    assert max(cert["dual_theta"], cert["dual_nu"]) <= cert["rounded_cost"] + 1e-12
+    assert cert["rounded_cost"] <= cert["primal_penalized"] + 1e-12
 
 
 def test_sphere_cube_262144_step_and_gradient():
@@ -99,8 +117,12 @@ def test_sphere_cube_262144_step_and_gradient():
 
 
 def test_gmm64_65536_fp32_step():
-    """2^16 x 2^16, d = 64: one FP32-form (FP64 argument) iteration at t = 300, sampled rows."""
-    _check_step(W.gmm64(), "gmm64d_65536", "fp32", 300, SAMPLE, 2e-6)
+    """2^16 x 2^16, d = 64: one FP32-form (FP64 argument) iteration at t = 300, sampled rows;
+    the certificate of the iterate the step started from."""
+    wl = W.gmm64()
+    prob, st, tr = _check_step(wl, "gmm64d_65536", "fp32", 300, SAMPLE, 2e-6, with_trace=True)
+    nu, th, lam_t, _ = _synthetic_state(wl, 300, seed=77)
+    _check_certificate(prob, P.make_params(eta=wl.eta), nu, th, 300, lam_t, to_np(tr["col_a"]), wl.c)
 
 
 @pytest.mark.parametrize("form,dtype", [("bf16_mfma", torch.bfloat16), ("fp32_mfma", torch.float32)])
@@ -207,3 +229,4 @@ def test_images_256_explicit_cost_step():
     assert abs(ca.sum() - 1.0) <= 1e-6 and abs(cb.sum() - 1.0) <= 1e-6
     assert np.all(ca >= 0) and np.all(cb >= 0)
     assert np.all(np.abs(to_np(st.theta)) < 1) and np.all(np.abs(to_np(st.nu)) < 1)
+    _check_certificate(prob, P.make_params(eta=wl.eta), nu, th, t, lam[t], ca, wl.c)
