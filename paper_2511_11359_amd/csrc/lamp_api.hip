@@ -1531,30 +1531,55 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
         });
         if (!done) launch(IC<-1>{}, IC<0>{});
     };
-    by_md([&](auto m, auto dd) {
-        hipLaunchKernelGGL((cert_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0, st,
-                           kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double>(ws, L.xn2),
-                           at<double>(ws, L.yn2), gA, at<double>(ws, L.H), prob->r, state->nu, state->theta, vals,
-                           psum);
-    });
+    // explicit cost: the row-wise passes in the row sweep's layout (coalesced reads of C)
+    const dim3 cost_rows_grid((unsigned)cdiv(kc.n, 4 * COST_ROWS));
+    if (L.cost) {
+        hipLaunchKernelGGL(cert_rows_cost, cost_rows_grid, dim3(BLOCK), 0, st, kc, cA, gA, at<double>(ws, L.H),
+                           prob->r, state->nu, state->theta, vals, psum);
+    } else {
+        by_md([&](auto m, auto dd) {
+            hipLaunchKernelGGL((cert_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0,
+                               st, kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc),
+                               at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA, at<double>(ws, L.H), prob->r,
+                               state->nu, state->theta, vals, psum);
+        });
+    }
     hipLaunchKernelGGL(col_products, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->c, state->theta, state->nu, prods);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, vals, kc.n, kc.n, 4, small);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, colres, kc.m, kc.m, 1, small + 4);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, prods, kc.m, kc.m, 2, small + 5);
     // Round (Algorithm 3) of the same X and its cost
     hipLaunchKernelGGL(round_row_factors, grid1(kc.n), dim3(BLOCK), 0, st, kc, psum, xr);
-    by_md([&](auto m, auto dd) {
-        hipLaunchKernelGGL((round_cols<decltype(m)::value, decltype(dd)::value>), grid1(kc.m), dim3(BLOCK), 0, st,
-                           kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc), gA, at<double>(ws, L.H),
-                           prob->r, xr, colp);
-    });
+    // Round step 2 over row splits; the split partials reuse the (consumed) column partials
+    double* rpart = at<double>(ws, L.cpart);
+    if (L.cost) {
+        hipLaunchKernelGGL(round_cols_cost, dim3((unsigned)cdiv(kc.m, COST_COL_BLOCK), (unsigned)L.P_cx), dim3(BLOCK),
+                           0, st, kc, cA, gA, at<double>(ws, L.H), prob->r, xr, rpart, L.split_cx);
+    } else {
+        by_md([&](auto m, auto dd) {
+            hipLaunchKernelGGL((round_cols<decltype(m)::value, decltype(dd)::value>),
+                               dim3((unsigned)cdiv(kc.m, BLOCK), (unsigned)L.P_c), dim3(BLOCK), 0, st, kc, prob->d, cA,
+                               at<double>(ws, L.xc), at<double>(ws, L.yc), gA, at<double>(ws, L.H), prob->r, xr,
+                               rpart, L.split_c);
+        });
+    }
+    hipLaunchKernelGGL(round_cols_merge, grid1(kc.m), dim3(BLOCK), 0, st, kc, (const double*)rpart,
+                       (int)(L.cost ? L.P_cx : L.P_c), colp);
     hipLaunchKernelGGL(round_col_factors, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->c, colp, yf, dc);
-    by_md([&](auto m, auto dd) {
-        hipLaunchKernelGGL((round_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0, st,
-                           kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double>(ws, L.xn2),
-                           at<double>(ws, L.yn2), gA, at<double>(ws, L.H), prob->r, xr, yf, dr, cpp);
-    });
-    if (kc.metric == METRIC_SQEUCLID) {
+    if (L.cost) {
+        hipLaunchKernelGGL(round_rows_cost, cost_rows_grid, dim3(BLOCK), 0, st, kc, cA, gA, at<double>(ws, L.H),
+                           prob->r, xr, yf, dr, cpp);
+    } else {
+        by_md([&](auto m, auto dd) {
+            hipLaunchKernelGGL((round_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0,
+                               st, kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc),
+                               at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA, at<double>(ws, L.H), prob->r, xr,
+                               yf, dr, cpp);
+        });
+    }
+    if (L.cost) {
+        hipLaunchKernelGGL(round_rank_one_cost, cost_rows_grid, dim3(BLOCK), 0, st, kc, dr, dc, tr1, absdr);
+    } else if (kc.metric == METRIC_SQEUCLID) {
         hipLaunchKernelGGL(round_col_sums, dim3(prob->d + 2), dim3(BLOCK), 0, st, kc, prob->d,
                            at<double>(ws, L.yc), at<double>(ws, L.yn2), dc, S);
         hipLaunchKernelGGL(round_rank_one, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, at<double>(ws, L.xc),

@@ -219,6 +219,239 @@ __global__ __launch_bounds__(BLOCK) void dt_cost_rows_cost(const Ctrl* ctrl, con
     }
 }
 
+// ---------------------------------------------------------------------------
+// Certificate and Round passes over whole rows, in the layout of the row sweep (8 rows per
+// wave, 64 consecutive columns per load, one lane reduction per row at the end), with the
+// terms of the generic passes: C_ij = s cost_ij, p_ij = 2^(cA (h_i + P_ij) + g^A_j).
+// ---------------------------------------------------------------------------
+struct CostRows {
+    int64_t i0;
+    int lane;
+    const float* row[COST_ROWS];
+    __device__ __forceinline__ CostRows(const Consts& kc) {
+        lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        i0 = ((int64_t)blockIdx.x * 4 + wave) * COST_ROWS;
+#pragma unroll
+        for (int r_ = 0; r_ < COST_ROWS; ++r_) row[r_] = kc.cost + min(i0 + r_, kc.n - 1) * kc.m;
+    }
+    // the step's columns (clamped to m - 1; valid[u] false past m) and their cost entries
+    __device__ __forceinline__ void load(const Consts& kc, int64_t jb, int64_t (&jj)[COST_U], bool (&valid)[COST_U],
+                                         float (&cv)[COST_ROWS][COST_U]) const {
+#pragma unroll
+        for (int u = 0; u < COST_U; ++u) {
+            const int64_t j = jb + u * 64 + lane;
+            valid[u] = j < kc.m;
+            jj[u] = min(j, kc.m - 1);
+        }
+#pragma unroll
+        for (int r_ = 0; r_ < COST_ROWS; ++r_)
+#pragma unroll
+            for (int u = 0; u < COST_U; ++u) cv[r_][u] = __builtin_nontemporal_load(row[r_] + jj[u]);
+    }
+};
+
+// vals[0..3][i] and psum_out[i] as cert_rows.
+__global__ __launch_bounds__(BLOCK) void cert_rows_cost(Consts kc, double cA, const double* __restrict__ gA,
+                                                        const double* __restrict__ H, const double* __restrict__ r,
+                                                        const double* __restrict__ nu,
+                                                        const double* __restrict__ theta,
+                                                        double* __restrict__ vals, double* __restrict__ psum_out) {
+    const CostRows cr(kc);
+    double h[COST_ROWS], psum[COST_ROWS], csum[COST_ROWS], mth[COST_ROWS], mnu[COST_ROWS];
+#pragma unroll
+    for (int r_ = 0; r_ < COST_ROWS; ++r_) {
+        h[r_] = H[min(cr.i0 + r_, kc.n - 1)];
+        psum[r_] = csum[r_] = 0.0;
+        mth[r_] = mnu[r_] = __builtin_inf();
+    }
+    for (int64_t jb = 0; jb < kc.m; jb += COST_ROW_STEP) {
+        int64_t jj[COST_U];
+        bool valid[COST_U];
+        float cv[COST_ROWS][COST_U];
+        cr.load(kc, jb, jj, valid, cv);
+        double ga[COST_U], th[COST_U], nv[COST_U];
+#pragma unroll
+        for (int u = 0; u < COST_U; ++u) {
+            ga[u] = valid[u] ? gA[jj[u]] : -__builtin_inf();
+            th[u] = valid[u] ? theta[jj[u]] : __builtin_inf();
+            nv[u] = valid[u] ? nu[jj[u]] : __builtin_inf();
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r_ = 0; r_ < COST_ROWS; ++r_) {
+            float ap = 0.f, ac = 0.f;
+#pragma unroll
+            for (int u = 0; u < COST_U; ++u) {
+                const double dot = -0.5 * (double)cv[r_][u];
+                const float p = fexp2(fma(cA, h[r_] + dot, ga[u]));
+                const double cij = kc.s * (double)cv[r_][u];
+                ap += p;
+                ac = fmaf((float)cij, p, ac);
+                mth[r_] = fmin(mth[r_], cij + kc.K * th[u]);
+                mnu[r_] = fmin(mnu[r_], cij + kc.K * nv[u]);
+            }
+            psum[r_] += (double)ap;
+            csum[r_] += (double)ac;
+        }
+    }
+#pragma unroll
+    for (int r_ = 0; r_ < COST_ROWS; ++r_) {
+        const double ps = wave_sum(psum[r_]), cs = wave_sum(csum[r_]);
+        const double a = wave_min(mth[r_]), b = wave_min(mnu[r_]);
+        const int64_t i = cr.i0 + r_;
+        if (cr.lane == r_ && i < kc.n) {
+            const double ri = r[i];
+            vals[i] = ri * fabs(ps - 1.0);
+            vals[kc.n + i] = ri * cs;
+            vals[2 * kc.n + i] = ri * a;
+            vals[3 * kc.n + i] = ri * b;
+            if (psum_out) psum_out[i] = ps;
+        }
+    }
+}
+
+// dr[i], cpp[i] as round_rows.
+__global__ __launch_bounds__(BLOCK) void round_rows_cost(Consts kc, double cA, const double* __restrict__ gA,
+                                                         const double* __restrict__ H, const double* __restrict__ r,
+                                                         const double* __restrict__ xr, const double* __restrict__ y,
+                                                         double* __restrict__ dr, double* __restrict__ cpp) {
+    const CostRows cr(kc);
+    double h[COST_ROWS], ps[COST_ROWS], pq[COST_ROWS], cs[COST_ROWS];
+#pragma unroll
+    for (int r_ = 0; r_ < COST_ROWS; ++r_) {
+        h[r_] = H[min(cr.i0 + r_, kc.n - 1)];
+        ps[r_] = pq[r_] = cs[r_] = 0.0;
+    }
+    for (int64_t jb = 0; jb < kc.m; jb += COST_ROW_STEP) {
+        int64_t jj[COST_U];
+        bool valid[COST_U];
+        float cv[COST_ROWS][COST_U];
+        cr.load(kc, jb, jj, valid, cv);
+        double ga[COST_U], yj[COST_U];
+#pragma unroll
+        for (int u = 0; u < COST_U; ++u) {
+            ga[u] = valid[u] ? gA[jj[u]] : -__builtin_inf();
+            yj[u] = y[jj[u]];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r_ = 0; r_ < COST_ROWS; ++r_) {
+            float a = 0.f, b = 0.f, e = 0.f;
+#pragma unroll
+            for (int u = 0; u < COST_U; ++u) {
+                const double dot = -0.5 * (double)cv[r_][u];
+                const float p = fexp2(fma(cA, h[r_] + dot, ga[u]));
+                const float py = p * (float)yj[u];
+                a += p;
+                b = fmaf(p, (float)(1.0 - yj[u]), b);
+                e = fmaf((float)(kc.s * (double)cv[r_][u]), py, e);
+            }
+            ps[r_] += (double)a;
+            pq[r_] += (double)b;
+            cs[r_] += (double)e;
+        }
+    }
+#pragma unroll
+    for (int r_ = 0; r_ < COST_ROWS; ++r_) {
+        const double sps = wave_sum(ps[r_]), spq = wave_sum(pq[r_]), scs = wave_sum(cs[r_]);
+        const int64_t i = cr.i0 + r_;
+        if (cr.lane == r_ && i < kc.n) {
+            const double w = xr[i] * r[i];
+            dr[i] = r[i] * (1.0 - xr[i] * sps) + w * spq;
+            cpp[i] = w * scs;
+        }
+    }
+}
+
+// t_i = dr_i (C dc)_i and |dr_i| as round_rank_one_pairs.
+__global__ __launch_bounds__(BLOCK) void round_rank_one_cost(Consts kc, const double* __restrict__ dr,
+                                                             const double* __restrict__ dc, double* __restrict__ t,
+                                                             double* __restrict__ absdr) {
+    const CostRows cr(kc);
+    double acc[COST_ROWS];
+#pragma unroll
+    for (int r_ = 0; r_ < COST_ROWS; ++r_) acc[r_] = 0.0;
+    for (int64_t jb = 0; jb < kc.m; jb += COST_ROW_STEP) {
+        int64_t jj[COST_U];
+        bool valid[COST_U];
+        float cv[COST_ROWS][COST_U];
+        cr.load(kc, jb, jj, valid, cv);
+        double dcj[COST_U];
+#pragma unroll
+        for (int u = 0; u < COST_U; ++u) dcj[u] = valid[u] ? dc[jj[u]] : 0.0;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r_ = 0; r_ < COST_ROWS; ++r_)
+#pragma unroll
+            for (int u = 0; u < COST_U; ++u) acc[r_] = fma(kc.s * (double)cv[r_][u], dcj[u], acc[r_]);
+    }
+#pragma unroll
+    for (int r_ = 0; r_ < COST_ROWS; ++r_) {
+        const double a = wave_sum(acc[r_]);
+        const int64_t i = cr.i0 + r_;
+        if (cr.lane == r_ && i < kc.n) {
+            t[i] = dr[i] * a;
+            absdr[i] = fabs(dr[i]);
+        }
+    }
+}
+
+// Round step 2 over the row splits of the column sweep: part[p][j] = sum over the rows i of
+// split p of xr_i r_i p_ij (the terms of round_cols, merged by round_cols_merge).
+__global__ __launch_bounds__(BLOCK) void round_cols_cost(Consts kc, double cA, const double* __restrict__ gA,
+                                                         const double* __restrict__ H, const double* __restrict__ r,
+                                                         const double* __restrict__ xr, double* __restrict__ part,
+                                                         int64_t split) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t jw = ((int64_t)blockIdx.x * 4 + wave) * 64 * COST_Q;
+    const int64_t p = blockIdx.y;
+    const int64_t i0 = p * split;
+    const int64_t i1 = min(kc.n, i0 + split);
+    int64_t jj[COST_Q];
+    double g[COST_Q], acc[COST_Q];
+#pragma unroll
+    for (int q = 0; q < COST_Q; ++q) {
+        jj[q] = min(jw + q * 64 + lane, kc.m - 1);
+        g[q] = gA[jj[q]];
+        acc[q] = 0.0;
+    }
+    auto rows = [&](int64_t i, float (&a)[COST_Q]) {
+        const float w = (float)(xr[i] * r[i]);
+        const double h = H[i];
+        const float* __restrict__ crow = kc.cost + i * kc.m;
+#pragma unroll
+        for (int q = 0; q < COST_Q; ++q) {
+            const double dot = -0.5 * (double)__builtin_nontemporal_load(crow + jj[q]);
+            a[q] = fmaf(w, fexp2(fma(cA, h + dot, g[q])), a[q]);
+        }
+    };
+    int64_t ib = i0;
+    for (; ib + UNROLL <= i1; ib += UNROLL) {
+        float a[COST_Q];
+#pragma unroll
+        for (int q = 0; q < COST_Q; ++q) a[q] = 0.f;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) rows(ib + u, a);
+#pragma unroll
+        for (int q = 0; q < COST_Q; ++q) acc[q] += (double)a[q];
+    }
+    if (ib < i1) {
+        float a[COST_Q];
+#pragma unroll
+        for (int q = 0; q < COST_Q; ++q) a[q] = 0.f;
+        for (; ib < i1; ++ib) rows(ib, a);
+#pragma unroll
+        for (int q = 0; q < COST_Q; ++q) acc[q] += (double)a[q];
+    }
+#pragma unroll
+    for (int q = 0; q < COST_Q; ++q) {
+        const int64_t j = jw + q * 64 + lane;
+        if (j < kc.m) part[p * kc.m + j] = acc[q];
+    }
+}
+
 // Column sweep: cpart[p][j] = (sum_i wA_i 2^(cA (k_i + P_ij) + g^A_j), sum_i wB_i 2^(cB ...))
 // over the rows of split p = blockIdx.y; wave w of block b owns the 64 COST_Q columns
 // from (4 b + w) 64 COST_Q, lane l the columns l + 64 q.

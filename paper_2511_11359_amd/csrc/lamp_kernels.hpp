@@ -1040,19 +1040,24 @@ __global__ void round_row_factors(Consts kc, const double* __restrict__ psum, do
     if (i < kc.n) xr[i] = fmin(1.0 / psum[i], 1.0);
 }
 
-// colp_j = sum_i xr_i r_i p_ij (one thread per column, rows in order).
+// part[p][j] = sum over the rows i of split p = blockIdx.y of xr_i r_i p_ij (one thread per
+// column, rows in order); round_cols_merge adds the splits in order: colp_j.
 template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void round_cols(Consts kc, int Dm, double cA, const double* __restrict__ xc,
                                                     const double* __restrict__ yc, const double* __restrict__ gA,
                                                     const double* __restrict__ H, const double* __restrict__ r,
-                                                    const double* __restrict__ xr, double* __restrict__ colp) {
+                                                    const double* __restrict__ xr, double* __restrict__ part,
+                                                    int64_t split) {
     const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (j >= kc.m) return;
+    const int64_t p = blockIdx.y;
+    const int64_t i0 = p * split;
+    const int64_t i1 = min(kc.n, i0 + split);
     const OwnPoint<M, D> own(yc + j * Dm, Dm, kc);
     const double g = gA[j];
     double acc = 0.0;
-    for (int64_t ib = 0; ib < kc.n; ib += UNROLL) {
-        const int64_t ie = min(kc.n, ib + UNROLL);
+    for (int64_t ib = i0; ib < i1; ib += UNROLL) {
+        const int64_t ie = min(i1, ib + UNROLL);
         float a = 0.f;
         for (int64_t i = ib; i < ie; ++i) {
             const double dot = own.pair(xc + i * Dm);
@@ -1060,7 +1065,15 @@ __global__ __launch_bounds__(BLOCK) void round_cols(Consts kc, int Dm, double cA
         }
         acc += (double)a;
     }
-    colp[j] = acc;
+    part[p * kc.m + j] = acc;
+}
+
+__global__ void round_cols_merge(Consts kc, const double* __restrict__ part, int P, double* __restrict__ colp) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kc.m) return;
+    double a = part[j];
+    for (int p = 1; p < P; ++p) a += part[(int64_t)p * kc.m + j];
+    colp[j] = a;
 }
 
 // y_j = min(c_j / colp_j, 1) and dc_j = c_j - y_j colp_j.
