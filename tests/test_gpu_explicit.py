@@ -50,14 +50,16 @@ CASES = [lambda: W.random_cost(200, 150, seed=501),
          lambda: W.random_cost(517, 1029, seed=504),
          lambda: W.image_pair(6, "sqeuclid", seed=505, eta=1e-2),
          lambda: W.image_pair(5, "l1", seed=506, eta=0.0),
-         lambda: W.image_pair(7, "linf", seed=507, eta=1e-3)]
+         lambda: W.image_pair(7, "linf", seed=507, eta=1e-3),
+         lambda: W.random_cost(13, 1, seed=508),
+         lambda: W.random_cost(1, 1, seed=511)]
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_explicit_first_steps_match_oracle(case):
     """Iterations 0..4 from the fresh state: residual, both column marginals, log-normalisers,
     duals.  Shapes span several row-sweep blocks and column splits with ragged tails, a single
-    row, and the three grid costs."""
+    row, a single column, a 1 x 1 problem, and the three grid costs."""
     wl = CASES[case]()
     C, prob = _problem(wl)
     _say("case", wl.name, "eta", wl.eta)
@@ -170,3 +172,13 @@ def test_explicit_rejected_forms():
         assert "point clouds" in str(ei.value)
     with pytest.raises(P.LampError):
         P.solve_batched([prob], P.make_params(eta=wl.eta, max_iter=3))
+
+
+def test_explicit_zero_cost_is_rejected():
+    """A cost matrix with no positive entry has no normalisation s = 1 / max cost: the library
+    computes the maximum and reports LAMP_EDOMAIN; nothing iterates."""
+    wl = W.random_cost(20, 30, seed=12)
+    prob = P.Problem.from_cost(np.zeros((20, 30), dtype=np.float32), wl.r, wl.c)
+    with pytest.raises(P.LampError) as ei:
+        P.solve(prob, P.make_params(eta=wl.eta, max_iter=3))
+    assert "zero" in str(ei.value)
