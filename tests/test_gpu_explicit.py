@@ -181,4 +181,4 @@ def test_explicit_zero_cost_is_rejected():
     prob = P.Problem.from_cost(np.zeros((20, 30), dtype=np.float32), wl.r, wl.c)
     with pytest.raises(P.LampError) as ei:
         P.solve(prob, P.make_params(eta=wl.eta, max_iter=3))
-    assert "zero" in str(ei.value)
+    assert ei.value.status == -2 and "zero" in str(ei.value)

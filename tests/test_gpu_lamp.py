@@ -242,6 +242,11 @@ def test_status_codes():
     with pytest.raises(P.LampError) as e:
         P.step(P.Problem(wl.x, wl.y, wl.r, wl.c), P.make_params(eta=5.0), P.State.fresh(30))
     assert e.value.status == -1
+    # coincident clouds: every distance is zero, no normalisation s = 1 / max exists
+    with pytest.raises(P.LampError) as e:
+        P.step(P.Problem(np.zeros((20, 2), np.float32), np.zeros((30, 2), np.float32), wl.r, wl.c),
+               P.make_params(), P.State.fresh(30))
+    assert e.value.status == -2
     st = P.State.fresh(30)
     st.theta[3] = 1.0   # atanh(1) = inf
     st.t, st.inv_eta = 5, 2.5
