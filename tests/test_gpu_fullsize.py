@@ -125,7 +125,8 @@ def test_gmm64_65536_fp32_step():
     _check_certificate(prob, P.make_params(eta=wl.eta), nu, th, 300, lam_t, to_np(tr["col_a"]), wl.c)
 
 
-@pytest.mark.parametrize("form,dtype", [("bf16_mfma", torch.bfloat16), ("fp32_mfma", torch.float32)])
+@pytest.mark.parametrize("form,dtype", [("bf16_mfma", torch.bfloat16), ("fp16_mfma", torch.float16),
+                                        ("fp32_mfma", torch.float32)])
 def test_gmm64_65536_mfma_step(form, dtype):
     """2^16 x 2^16, d = 64: one matrix-core iteration at t = 300, sampled rows against the
     oracle evaluated on the rounded operands the form uses (exponent assembled in FP32)."""
