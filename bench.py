@@ -266,8 +266,9 @@ def cost_mode(args):
     """Explicit-cost input at n = m = 2^16: transport between two random 256 x 256 images over
     the squared Euclidean grid cost, a 16 GiB FP32 matrix built on the device (the image
     benchmarks of Section 5 use explicit grid costs, at up to 64 x 64 pixels).  Both sweeps
-    stream the matrix once per launch, so the roofline is HBM bandwidth at 4 bytes per pair;
-    time to the tolerance is capped at --cost-max-iter iterations."""
+    stream the matrix once per launch, so the roofline is HBM bandwidth at 4 bytes per pair (2
+    with --cost-dtype bfloat16, the matrix rounded once); time to the tolerance is capped at
+    --cost-max-iter iterations."""
     import types
 
     import torch
@@ -277,16 +278,19 @@ def cost_mode(args):
     dev = torch.device("cuda:0")
     calibration_copy(args.calib_copy_mib, dev)
     cw = W.image_pair_device(256, "sqeuclid", device=dev)
-    prob = P.Problem.from_cost(cw.cost, cw.r, cw.c, device=dev)
+    cost = cw.cost if args.cost_dtype == "float32" else cw.cost.to(torch.bfloat16)
+    prob = P.Problem.from_cost(cost, cw.r, cw.c, device=dev)
     s, cmax = P.cost_scale(prob)
     prob.cost_scale, prob.cost_norm = s, 1.0
-    wl = types.SimpleNamespace(name=cw.name, n=prob.n, m=prob.m, d=1, eta=cw.eta)
+    esize = cost.element_size()
+    name = cw.name if args.cost_dtype == "float32" else cw.name + "_bf16"
+    wl = types.SimpleNamespace(name=name, n=prob.n, m=prob.m, d=1, eta=cw.eta)
     log(f"{wl.name}: n=m={wl.n}, max cost {cmax:g}, s={s:.9e}")
     mm = measure_form(P, prob, wl, "fp32", args.steps, args.warmup, args.reps)
     dom_name, dom_ms = ("row_sweep", mm["row_sweep_ms"])
     if mm["col_sweep_ms"] > dom_ms:
         dom_name, dom_ms = ("col_sweep", mm["col_sweep_ms"])
-    nbytes = 4.0 * wl.n * wl.m
+    nbytes = float(esize) * wl.n * wl.m
     ach = nbytes / (dom_ms * 1e-3) / 1e9
     ttt = time_to_tol(P, prob, wl, "fp32", args.tol, args.cost_max_iter)[0] if args.cost_max_iter > 0 else None
     out = {"metric": "pair-evals/s", "value": mm["pair_evals_per_s"], "unit": "pair-evals/s", "n_gpus": 1,
@@ -294,11 +298,11 @@ def cost_mode(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64/f32",
            "data": "synthetic",
            "config": {"workload": wl.name, "n": wl.n, "m": wl.m, "input": "explicit cost matrix",
-                      "eta": wl.eta, "form": "fp32"},
+                      "cost_dtype": args.cost_dtype, "eta": wl.eta, "form": "fp32"},
            "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": ach, "peak": HBM_PEAK / 1e9,
                         "unit": "GB/s", "frac": ach * 1e9 / HBM_PEAK,
                         "traffic": measured_traffic(wl.name, "fp32", dom_name),
-                        "per_launch": f"4*n*m = {nbytes:.3e} bytes",
+                        "per_launch": f"{esize}*n*m = {nbytes:.3e} bytes",
                         "row_sweep_ms": mm["row_sweep_ms"], "col_sweep_ms": mm["col_sweep_ms"]},
            "time_to_tol": {"fp32": ttt}}
     print(json.dumps(out), flush=True)
@@ -307,6 +311,8 @@ def cost_mode(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--mode", default="single", choices=["single", "batch", "grad", "cost"])
+    ap.add_argument("--cost-dtype", default="float32", choices=["float32", "bfloat16"],
+                    help="element type of the explicit cost matrix in --mode cost")
     ap.add_argument("--cost-max-iter", type=int, default=3000,
                     help="iteration cap of the time to tolerance in --mode cost (0: skip it)")
     ap.add_argument("--batch-count", type=int, default=64)

@@ -66,6 +66,13 @@ typedef enum {
     LAMP_EXPLICIT = 3    /* cost_ij of lamp_problem.cost */
 } lamp_metric;
 
+/* Element type of an explicit cost matrix. */
+typedef enum {
+    LAMP_COST_F32 = 0,       /* float                                              */
+    LAMP_COST_BF16 = 1,      /* bfloat16 (8-bit significand, FP32 exponent range)  */
+    LAMP_COST_F16 = 2        /* IEEE half (11-bit significand, entries <= 65504)   */
+} lamp_cost_type;
+
 /* Problem data (Section 1; Algorithm 2, REQUIRE line).
  *   x: n x d, y: m x d, row-major FP32 point clouds (device).  Not read, and may be
  *      NULL, with metric LAMP_EXPLICIT; d is then ignored.
@@ -76,11 +83,14 @@ typedef enum {
  *      computed on the device (then ||C||_inf = 1).
  *   cost_norm: ||C||_inf = max_ij C_ij.  <= 0: computed on the device.  Only
  *      trusted as given when both cost_scale and cost_norm are > 0.
- *   cost: with metric LAMP_EXPLICIT, the n x m cost matrix, row-major FP32 (device,
- *      caller-owned, read only; entry (i, j) at cost[i m + j]).  Entries must be
- *      finite and >= 0 with a positive maximum; that maximum is checked (LAMP_EDOMAIN
- *      when it is not positive) only when the library computes the scale, the rest is
- *      not checked.  Ignored, and may be NULL, for the other ground costs. */
+ *   cost: with metric LAMP_EXPLICIT, the n x m cost matrix, row-major, of element type
+ *      cost_type (device, caller-owned, read only; entry (i, j) at element i m + j).
+ *      Entries must be finite and >= 0 with a positive maximum; that maximum is checked
+ *      (LAMP_EDOMAIN when it is not positive) only when the library computes the scale,
+ *      the rest is not checked.  Each entry is widened exactly to FP32 and then to FP64:
+ *      the 2-byte types halve the HBM traffic of the sweeps and solve the problem whose
+ *      cost is the rounded matrix.  Ignored, and may be NULL, for the other ground costs.
+ *   cost_type: lamp_cost_type of cost (LAMP_EXPLICIT only; else ignored). */
 typedef struct {
     int64_t n, m;
     int32_t d, metric;
@@ -88,7 +98,8 @@ typedef struct {
     const double *r, *c;
     double cost_scale;
     double cost_norm;
-    const float *cost;
+    const void *cost;
+    int32_t cost_type, reserved;
 } lamp_problem;
 
 /* Algorithm parameters (Algorithm 2; defaults from Appendix E, "for all LAMP

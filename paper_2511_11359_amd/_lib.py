@@ -26,6 +26,7 @@ LAMP_SQEUCLID = 0
 LAMP_L1 = 1
 LAMP_LINF = 2
 METRICS = {"sqeuclid": 0, "l1": 1, "linf": 2, "explicit": 3}
+COST_TYPES = {"float32": 0, "bfloat16": 1, "float16": 2}
 
 STATUS_NAMES = {0: "LAMP_OK", 1: "LAMP_NOT_CONVERGED", -1: "LAMP_EINVAL", -2: "LAMP_EDOMAIN",
                 -3: "LAMP_ENOMEM", -4: "LAMP_EDEVICE", -5: "LAMP_ENUMERIC"}
@@ -34,7 +35,8 @@ STATUS_NAMES = {0: "LAMP_OK", 1: "LAMP_NOT_CONVERGED", -1: "LAMP_EINVAL", -2: "L
 class Problem(ctypes.Structure):
     _fields_ = [("n", c_int64), ("m", c_int64), ("d", c_int32), ("metric", c_int32),
                 ("x", c_void_p), ("y", c_void_p), ("r", c_void_p), ("c", c_void_p),
-                ("cost_scale", c_double), ("cost_norm", c_double), ("cost", c_void_p)]
+                ("cost_scale", c_double), ("cost_norm", c_double), ("cost", c_void_p),
+                ("cost_type", c_int32), ("reserved", c_int32)]
 
 
 class Params(ctypes.Structure):

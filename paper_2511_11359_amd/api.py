@@ -46,7 +46,9 @@ class Problem:
         self.c = torch.as_tensor(c, dtype=torch.float64).to(dev).contiguous()
         if metric == "explicit":
             self.x = self.y = None
-            self.cost = torch.as_tensor(cost, dtype=torch.float32).to(dev).contiguous()
+            cost = torch.as_tensor(cost)
+            keep = cost.dtype in (torch.bfloat16, torch.float16)   # 2-byte storage is kept as given
+            self.cost = cost.to(dev, dtype=cost.dtype if keep else torch.float32).contiguous()
             assert self.cost.dim() == 2
             self.n, self.m = self.cost.shape
             self.d = 1
@@ -65,13 +67,16 @@ class Problem:
     @classmethod
     def from_cost(cls, cost, r, c, cost_scale: float = 0.0, cost_norm: float = 0.0,
                   device: str | torch.device = "cuda") -> "Problem":
-        """C_ij = cost_scale * cost[i, j] from an n x m matrix (stored as FP32, row-major)."""
+        """C_ij = cost_scale * cost[i, j] from an n x m matrix, row-major: bfloat16 and float16
+        matrices are used as given (2 bytes per entry), any other dtype is stored as float32."""
         return cls(None, None, r, c, cost_scale, cost_norm, device, metric="explicit", cost=cost)
 
     def struct(self) -> L.Problem:
         ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        cost_type = L.COST_TYPES[str(self.cost.dtype).replace("torch.", "")] if self.cost is not None else 0
         return L.Problem(self.n, self.m, self.d, L.METRICS[self.metric], ptr(self.x), ptr(self.y),
-                         self.r.data_ptr(), self.c.data_ptr(), self.cost_scale, self.cost_norm, ptr(self.cost))
+                         self.r.data_ptr(), self.c.data_ptr(), self.cost_scale, self.cost_norm, ptr(self.cost),
+                         cost_type, 0)
 
     def workspace(self, params: L.Params) -> tuple[int, int]:
         lib = L.load()

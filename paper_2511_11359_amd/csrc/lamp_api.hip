@@ -126,6 +126,8 @@ void mfma_split(int64_t owned_pad, int64_t streamed_tiles, int64_t* tps, int64_t
 static_assert(LAMP_SQEUCLID == METRIC_SQEUCLID && LAMP_L1 == METRIC_L1 && LAMP_LINF == METRIC_LINF &&
                   LAMP_EXPLICIT == METRIC_EXPLICIT,
               "ground-cost codes of the ABI and the kernels agree");
+static_assert(LAMP_COST_F32 == COST_F32 && LAMP_COST_BF16 == COST_BF16 && LAMP_COST_F16 == COST_F16,
+              "cost element types of the ABI and the kernels agree");
 
 Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target = TARGET_BLOCKS,
               int metric = METRIC_SQEUCLID) {
@@ -249,6 +251,8 @@ lamp_status check_problem(const lamp_problem* p) {
                     (long long)p->m, p->d);
     if (!p->r || !p->c || (expl ? !p->cost : (!p->x || !p->y)))
         return fail(LAMP_EINVAL, "a problem array is NULL");
+    if (expl && p->cost_type != LAMP_COST_F32 && p->cost_type != LAMP_COST_BF16 && p->cost_type != LAMP_COST_F16)
+        return fail(LAMP_EINVAL, "unknown cost element type %d", p->cost_type);
     return LAMP_OK;
 }
 
@@ -360,6 +364,14 @@ lamp_status prep(const lamp_problem* p, void* ws, hipStream_t st, int prec = LAM
     return prep_L(p, layout(p->n, p->m, p->d, prec, TARGET_BLOCKS, p->metric), ws, st);
 }
 
+// f(tag) with tag a null pointer to the element type of an explicit cost matrix.
+template <typename F>
+void by_cost_type(int cost_type, F&& f) {
+    if (cost_type == COST_BF16) f(static_cast<__bf16*>(nullptr));
+    else if (cost_type == COST_F16) f(static_cast<_Float16*>(nullptr));
+    else f(static_cast<float*>(nullptr));
+}
+
 // ------------------------------------------------------------------ dispatch by d
 #define LAMP_FOR_D(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(16)
 template <int V>
@@ -418,7 +430,10 @@ void launch_row_extreme(const Layout& L, Consts kc, int d, void* ws, const doubl
                         hipStream_t st) {
     if (L.cost) {
         dim3 g((unsigned)cdiv(kc.n, 4 * COST_ROWS), (unsigned)L.P_rx);
-        hipLaunchKernelGGL(row_extreme_cost, g, dim3(BLOCK), 0, st, kc, a, sgn, at<double>(ws, L.rpart), L.split_rx);
+        by_cost_type(kc.cost_type, [&](auto tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((row_extreme_cost<T>), g, dim3(BLOCK), 0, st, kc, a, sgn, at<double>(ws, L.rpart), L.split_rx);
+        });
         return;
     }
     if (L.use64) {
@@ -529,8 +544,11 @@ int col_parts(const Layout& L) {
 void launch_row_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
     if (L.cost) {
         dim3 g((unsigned)cdiv(kc.n, 4 * COST_ROWS), (unsigned)L.P_rx);
-        hipLaunchKernelGGL(row_sweep_cost, g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched), kc,
+        by_cost_type(kc.cost_type, [&](auto tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((row_sweep_cost<T>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched), kc,
                            at<double2>(ws, L.gtab), at<double>(ws, L.H), at<double2>(ws, L.rpart), L.split_rx);
+        });
         return;
     }
     if (is_mfma(L.prec)) {
@@ -562,9 +580,12 @@ void launch_row_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t s
 void launch_col_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t st) {
     if (L.cost) {
         dim3 g((unsigned)cdiv(kc.m, COST_COL_BLOCK), (unsigned)L.P_cx);
-        hipLaunchKernelGGL(col_sweep_cost, g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched), kc,
+        by_cost_type(kc.cost_type, [&](auto tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((col_sweep_cost<T>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched), kc,
                            at<double2>(ws, L.gtab), at<RowVar>(ws, L.rowvar), at<double2>(ws, L.cpart),
                            L.split_cx);
+        });
         return;
     }
     if (is_mfma(L.prec)) {
@@ -622,6 +643,7 @@ lamp_status max_sqdist_L(const lamp_problem* p, const Layout& L, void* ws, hipSt
     kc.m = p->m;
     kc.metric = p->metric;
     kc.cost = p->metric == LAMP_EXPLICIT ? p->cost : nullptr;
+    kc.cost_type = p->metric == LAMP_EXPLICIT ? p->cost_type : COST_F32;
     double* a = at<double>(ws, L.scratch);
     double* rowmax = a + std::max(p->n, p->m);
     hipLaunchKernelGGL(fill_scaled, grid1(p->m), dim3(BLOCK), 0, st, p->m, -0.5, at<double>(ws, L.yn2), a);
@@ -683,6 +705,7 @@ Consts make_consts(const lamp_problem* p, const Resolved& R) {
     kc.metric = p->metric;
     kc.factor_cols = 2.0 * LOG2E * R.K * R.tau1 <= 64.0;
     kc.cost = p->metric == LAMP_EXPLICIT ? p->cost : nullptr;
+    kc.cost_type = p->metric == LAMP_EXPLICIT ? p->cost_type : COST_F32;
     return kc;
 }
 
@@ -786,8 +809,11 @@ void launch_dt_cost(const lamp_problem* p, const Layout& L, Consts kc, void* ws,
     double* out = at<double>(ws, L.dtrow);
     const int d = p->d;
     if (L.cost) {
-        hipLaunchKernelGGL(dt_cost_rows_cost, dim3((unsigned)cdiv(kc.n, 4 * COST_ROWS)), dim3(BLOCK), 0, st, ctrl, sch,
+        by_cost_type(kc.cost_type, [&](auto tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((dt_cost_rows_cost<T>), dim3((unsigned)cdiv(kc.n, 4 * COST_ROWS)), dim3(BLOCK), 0, st, ctrl, sch,
                            kc, gt, H, p->r, out);
+        });
         hipLaunchKernelGGL(dt_cost_total, dim3(1), dim3(1024), 0, st, ctrl, (const double*)out, kc.n);
         return;
     }
@@ -1534,8 +1560,11 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     // explicit cost: the row-wise passes in the row sweep's layout (coalesced reads of C)
     const dim3 cost_rows_grid((unsigned)cdiv(kc.n, 4 * COST_ROWS));
     if (L.cost) {
-        hipLaunchKernelGGL(cert_rows_cost, cost_rows_grid, dim3(BLOCK), 0, st, kc, cA, gA, at<double>(ws, L.H),
+        by_cost_type(kc.cost_type, [&](auto tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((cert_rows_cost<T>), cost_rows_grid, dim3(BLOCK), 0, st, kc, cA, gA, at<double>(ws, L.H),
                            prob->r, state->nu, state->theta, vals, psum);
+        });
     } else {
         by_md([&](auto m, auto dd) {
             hipLaunchKernelGGL((cert_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0,
@@ -1553,8 +1582,11 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     // Round step 2 over row splits; the split partials reuse the (consumed) column partials
     double* rpart = at<double>(ws, L.cpart);
     if (L.cost) {
-        hipLaunchKernelGGL(round_cols_cost, dim3((unsigned)cdiv(kc.m, COST_COL_BLOCK), (unsigned)L.P_cx), dim3(BLOCK),
+        by_cost_type(kc.cost_type, [&](auto tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((round_cols_cost<T>), dim3((unsigned)cdiv(kc.m, COST_COL_BLOCK), (unsigned)L.P_cx), dim3(BLOCK),
                            0, st, kc, cA, gA, at<double>(ws, L.H), prob->r, xr, rpart, L.split_cx);
+        });
     } else {
         by_md([&](auto m, auto dd) {
             hipLaunchKernelGGL((round_cols<decltype(m)::value, decltype(dd)::value>),
@@ -1567,8 +1599,11 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
                        (int)(L.cost ? L.P_cx : L.P_c), colp);
     hipLaunchKernelGGL(round_col_factors, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->c, colp, yf, dc);
     if (L.cost) {
-        hipLaunchKernelGGL(round_rows_cost, cost_rows_grid, dim3(BLOCK), 0, st, kc, cA, gA, at<double>(ws, L.H),
+        by_cost_type(kc.cost_type, [&](auto tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((round_rows_cost<T>), cost_rows_grid, dim3(BLOCK), 0, st, kc, cA, gA, at<double>(ws, L.H),
                            prob->r, xr, yf, dr, cpp);
+        });
     } else {
         by_md([&](auto m, auto dd) {
             hipLaunchKernelGGL((round_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0,
@@ -1578,7 +1613,10 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
         });
     }
     if (L.cost) {
-        hipLaunchKernelGGL(round_rank_one_cost, cost_rows_grid, dim3(BLOCK), 0, st, kc, dr, dc, tr1, absdr);
+        by_cost_type(kc.cost_type, [&](auto tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            hipLaunchKernelGGL((round_rank_one_cost<T>), cost_rows_grid, dim3(BLOCK), 0, st, kc, dr, dc, tr1, absdr);
+        });
     } else if (kc.metric == METRIC_SQEUCLID) {
         hipLaunchKernelGGL(round_col_sums, dim3(prob->d + 2), dim3(BLOCK), 0, st, kc, prob->d,
                            at<double>(ws, L.yc), at<double>(ws, L.yn2), dc, S);

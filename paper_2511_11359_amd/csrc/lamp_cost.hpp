@@ -38,6 +38,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Row sweep: part[p][i] = (sum_j 2^(cA (h_i + P_ij) + g^A_j), same with cB, g^B) over
 // the columns of split p = blockIdx.y, [p split, (p + 1) split) with split a multiple
 // of COST_ROW_STEP; block b owns rows [32 b, 32 b + 32), wave w of it 8 of them.
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void row_sweep_cost(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                         const double2* __restrict__ gtab2,
                                                         const double* __restrict__ H,
@@ -54,12 +55,12 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_cost(const Ctrl* ctrl, const 
     const int64_t p = blockIdx.y;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
-    const float* __restrict__ row[COST_ROWS];
+    const T* __restrict__ row[COST_ROWS];
     double h[COST_ROWS];
 #pragma unroll
     for (int r = 0; r < COST_ROWS; ++r) {
         const int64_t ii = min(i0 + r, kc.n - 1);   // rows past n repeat the last one, unwritten
-        row[r] = kc.cost + ii * kc.m;
+        row[r] = static_cast<const T*>(kc.cost) + ii * kc.m;
         h[r] = H[ii];
     }
     double sA[COST_ROWS], sB[COST_ROWS];
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_cost(const Ctrl* ctrl, const 
 #pragma unroll
         for (int r = 0; r < COST_ROWS; ++r)
 #pragma unroll
-            for (int u = 0; u < COST_U; ++u) cv[r][u] = __builtin_nontemporal_load(row[r] + jj[u]);
+            for (int u = 0; u < COST_U; ++u) cv[r][u] = load_cost(row[r] + jj[u]);
         // every load of the step is issued before the first use: left to itself the
         // scheduler interleaves each load with its use and waits for it, one load in flight
         __builtin_amdgcn_sched_barrier(0);
@@ -114,6 +115,7 @@ __device__ __forceinline__ double wave_min(double v) {
 // Row extreme pass, the layout of the row sweep: part[p][i] = min_j (a_j + sgn P_ij) over the
 // columns of split p, P_ij = -cost_ij / 2 (exact offsets, the cost maximum, D(theta)).  The
 // terms are those of the generic pass and a minimum is exact, so the result is the same.
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void row_extreme_cost(Consts kc, const double* __restrict__ a, double sgn,
                                                           double* __restrict__ part, int64_t split) {
     const int lane = threadIdx.x & 63;
@@ -122,9 +124,9 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_cost(Consts kc, const doubl
     const int64_t p = blockIdx.y;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
-    const float* __restrict__ row[COST_ROWS];
+    const T* __restrict__ row[COST_ROWS];
 #pragma unroll
-    for (int r = 0; r < COST_ROWS; ++r) row[r] = kc.cost + min(i0 + r, kc.n - 1) * kc.m;
+    for (int r = 0; r < COST_ROWS; ++r) row[r] = static_cast<const T*>(kc.cost) + min(i0 + r, kc.n - 1) * kc.m;
     double best[COST_ROWS];
 #pragma unroll
     for (int r = 0; r < COST_ROWS; ++r) best[r] = __builtin_inf();
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_cost(Consts kc, const doubl
 #pragma unroll
         for (int r = 0; r < COST_ROWS; ++r)
 #pragma unroll
-            for (int u = 0; u < COST_U; ++u) cv[r][u] = __builtin_nontemporal_load(row[r] + jj[u]);
+            for (int u = 0; u < COST_U; ++u) cv[r][u] = load_cost(row[r] + jj[u]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int r = 0; r < COST_ROWS; ++r)
@@ -158,6 +160,7 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_cost(Consts kc, const doubl
 // <C, Xbar^{t+1}> per row for the D_t tracking, the layout of the row sweep over whole rows:
 // out_i = r_i T_i / S_i with S_i = sum_j 2^(cB (h_i + P_ij) + g^B_j), T_i the same sum
 // weighted by C_ij = s cost_ij; the terms of the generic pass.
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void dt_cost_rows_cost(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                            const double2* __restrict__ gtab2,
                                                            const double* __restrict__ H,
@@ -171,17 +174,17 @@ __global__ __launch_bounds__(BLOCK) void dt_cost_rows_cost(const Ctrl* ctrl, con
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * COST_ROWS;
-    const float* __restrict__ row[COST_ROWS];
+    const T* __restrict__ row[COST_ROWS];
     double h[COST_ROWS];
 #pragma unroll
     for (int r_ = 0; r_ < COST_ROWS; ++r_) {
         const int64_t ii = min(i0 + r_, kc.n - 1);
-        row[r_] = kc.cost + ii * kc.m;
+        row[r_] = static_cast<const T*>(kc.cost) + ii * kc.m;
         h[r_] = H[ii];
     }
-    double S[COST_ROWS], T[COST_ROWS];
+    double S[COST_ROWS], Tw[COST_ROWS];
 #pragma unroll
-    for (int r_ = 0; r_ < COST_ROWS; ++r_) S[r_] = T[r_] = 0.0;
+    for (int r_ = 0; r_ < COST_ROWS; ++r_) S[r_] = Tw[r_] = 0.0;
     for (int64_t jb = 0; jb < kc.m; jb += COST_ROW_STEP) {
         int64_t jj[COST_U];
         double gB[COST_U];
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(BLOCK) void dt_cost_rows_cost(const Ctrl* ctrl, con
 #pragma unroll
         for (int r_ = 0; r_ < COST_ROWS; ++r_)
 #pragma unroll
-            for (int u = 0; u < COST_U; ++u) cv[r_][u] = __builtin_nontemporal_load(row[r_] + jj[u]);
+            for (int u = 0; u < COST_U; ++u) cv[r_][u] = load_cost(row[r_] + jj[u]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int r_ = 0; r_ < COST_ROWS; ++r_) {
@@ -208,13 +211,13 @@ __global__ __launch_bounds__(BLOCK) void dt_cost_rows_cost(const Ctrl* ctrl, con
                 aT = fmaf(pij, (float)fma(-2.0 * kc.s, dot, 0.0), aT);
             }
             S[r_] += (double)aS;
-            T[r_] += (double)aT;
+            Tw[r_] += (double)aT;
         }
     }
 #pragma unroll
     for (int r_ = 0; r_ < COST_ROWS; ++r_) {
         const double sS = wave_sum(S[r_]);
-        const double sT = wave_sum(T[r_]);
+        const double sT = wave_sum(Tw[r_]);
         if (lane == r_ && i0 + r_ < kc.n) out[i0 + r_] = r[i0 + r_] * sT / sS;
     }
 }
@@ -224,16 +227,17 @@ __global__ __launch_bounds__(BLOCK) void dt_cost_rows_cost(const Ctrl* ctrl, con
 // wave, 64 consecutive columns per load, one lane reduction per row at the end), with the
 // terms of the generic passes: C_ij = s cost_ij, p_ij = 2^(cA (h_i + P_ij) + g^A_j).
 // ---------------------------------------------------------------------------
+template <typename T>
 struct CostRows {
     int64_t i0;
     int lane;
-    const float* row[COST_ROWS];
+    const T* row[COST_ROWS];
     __device__ __forceinline__ CostRows(const Consts& kc) {
         lane = threadIdx.x & 63;
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         i0 = ((int64_t)blockIdx.x * 4 + wave) * COST_ROWS;
 #pragma unroll
-        for (int r_ = 0; r_ < COST_ROWS; ++r_) row[r_] = kc.cost + min(i0 + r_, kc.n - 1) * kc.m;
+        for (int r_ = 0; r_ < COST_ROWS; ++r_) row[r_] = static_cast<const T*>(kc.cost) + min(i0 + r_, kc.n - 1) * kc.m;
     }
     // the step's columns (clamped to m - 1; valid[u] false past m) and their cost entries
     __device__ __forceinline__ void load(const Consts& kc, int64_t jb, int64_t (&jj)[COST_U], bool (&valid)[COST_U],
@@ -247,17 +251,18 @@ struct CostRows {
 #pragma unroll
         for (int r_ = 0; r_ < COST_ROWS; ++r_)
 #pragma unroll
-            for (int u = 0; u < COST_U; ++u) cv[r_][u] = __builtin_nontemporal_load(row[r_] + jj[u]);
+            for (int u = 0; u < COST_U; ++u) cv[r_][u] = load_cost(row[r_] + jj[u]);
     }
 };
 
 // vals[0..3][i] and psum_out[i] as cert_rows.
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void cert_rows_cost(Consts kc, double cA, const double* __restrict__ gA,
                                                         const double* __restrict__ H, const double* __restrict__ r,
                                                         const double* __restrict__ nu,
                                                         const double* __restrict__ theta,
                                                         double* __restrict__ vals, double* __restrict__ psum_out) {
-    const CostRows cr(kc);
+    const CostRows<T> cr(kc);
     double h[COST_ROWS], psum[COST_ROWS], csum[COST_ROWS], mth[COST_ROWS], mnu[COST_ROWS];
 #pragma unroll
     for (int r_ = 0; r_ < COST_ROWS; ++r_) {
@@ -312,11 +317,12 @@ __global__ __launch_bounds__(BLOCK) void cert_rows_cost(Consts kc, double cA, co
 }
 
 // dr[i], cpp[i] as round_rows.
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void round_rows_cost(Consts kc, double cA, const double* __restrict__ gA,
                                                          const double* __restrict__ H, const double* __restrict__ r,
                                                          const double* __restrict__ xr, const double* __restrict__ y,
                                                          double* __restrict__ dr, double* __restrict__ cpp) {
-    const CostRows cr(kc);
+    const CostRows<T> cr(kc);
     double h[COST_ROWS], ps[COST_ROWS], pq[COST_ROWS], cs[COST_ROWS];
 #pragma unroll
     for (int r_ = 0; r_ < COST_ROWS; ++r_) {
@@ -365,10 +371,11 @@ __global__ __launch_bounds__(BLOCK) void round_rows_cost(Consts kc, double cA, c
 }
 
 // t_i = dr_i (C dc)_i and |dr_i| as round_rank_one_pairs.
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void round_rank_one_cost(Consts kc, const double* __restrict__ dr,
                                                              const double* __restrict__ dc, double* __restrict__ t,
                                                              double* __restrict__ absdr) {
-    const CostRows cr(kc);
+    const CostRows<T> cr(kc);
     double acc[COST_ROWS];
 #pragma unroll
     for (int r_ = 0; r_ < COST_ROWS; ++r_) acc[r_] = 0.0;
@@ -399,6 +406,7 @@ __global__ __launch_bounds__(BLOCK) void round_rank_one_cost(Consts kc, const do
 
 // Round step 2 over the row splits of the column sweep: part[p][j] = sum over the rows i of
 // split p of xr_i r_i p_ij (the terms of round_cols, merged by round_cols_merge).
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void round_cols_cost(Consts kc, double cA, const double* __restrict__ gA,
                                                          const double* __restrict__ H, const double* __restrict__ r,
                                                          const double* __restrict__ xr, double* __restrict__ part,
@@ -420,10 +428,10 @@ __global__ __launch_bounds__(BLOCK) void round_cols_cost(Consts kc, double cA, c
     auto rows = [&](int64_t i, float (&a)[COST_Q]) {
         const float w = (float)(xr[i] * r[i]);
         const double h = H[i];
-        const float* __restrict__ crow = kc.cost + i * kc.m;
+        const T* __restrict__ crow = static_cast<const T*>(kc.cost) + i * kc.m;
 #pragma unroll
         for (int q = 0; q < COST_Q; ++q) {
-            const double dot = -0.5 * (double)__builtin_nontemporal_load(crow + jj[q]);
+            const double dot = -0.5 * (double)load_cost(crow + jj[q]);
             a[q] = fmaf(w, fexp2(fma(cA, h + dot, g[q])), a[q]);
         }
     };
@@ -455,6 +463,7 @@ __global__ __launch_bounds__(BLOCK) void round_cols_cost(Consts kc, double cA, c
 // Column sweep: cpart[p][j] = (sum_i wA_i 2^(cA (k_i + P_ij) + g^A_j), sum_i wB_i 2^(cB ...))
 // over the rows of split p = blockIdx.y; wave w of block b owns the 64 COST_Q columns
 // from (4 b + w) 64 COST_Q, lane l the columns l + 64 q.
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void col_sweep_cost(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                         const double2* __restrict__ gtab2,
                                                         const RowVar* __restrict__ rowvar,
@@ -483,10 +492,10 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_cost(const Ctrl* ctrl, const 
     for (int q = 0; q < COST_Q; ++q) sA[q] = sB[q] = 0.0;
     auto rows = [&](int64_t i, float (&aA)[COST_Q], float (&aB)[COST_Q]) {
         const RowVar rv = rowvar[i];
-        const float* __restrict__ crow = kc.cost + i * kc.m;
+        const T* __restrict__ crow = static_cast<const T*>(kc.cost) + i * kc.m;
 #pragma unroll
         for (int q = 0; q < COST_Q; ++q) {
-            const double dot = fma(-0.5, (double)__builtin_nontemporal_load(crow + jj[q]), rv.k);
+            const double dot = fma(-0.5, (double)load_cost(crow + jj[q]), rv.k);
             aA[q] = fmaf(rv.wA, fexp2(fma(cA, dot, gj[q].x)), aA[q]);
             aB[q] = fmaf(rv.wB, fexp2(fma(cB, dot, gj[q].y)), aB[q]);
         }

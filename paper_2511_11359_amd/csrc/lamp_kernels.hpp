@@ -80,8 +80,29 @@ struct Consts {
     double clipb;   // tanh(beta / 2)
     int metric;     // ground cost, METRIC_*
     int factor_cols;     // one-chain matrix-core column sweep: per-column factor (see there)
-    const float* cost;   // METRIC_EXPLICIT: the caller's n x m cost matrix, row-major
+    int cost_type;       // COST_* element type of `cost`
+    const void* cost;    // METRIC_EXPLICIT: the caller's n x m cost matrix, row-major
 };
+
+enum : int { COST_F32 = 0, COST_BF16 = 1, COST_F16 = 2 };
+
+// One cost entry widened exactly to FP32 (a 2-byte entry by its bit pattern).
+__device__ __forceinline__ float widen_cost(float v) { return v; }
+__device__ __forceinline__ float widen_cost(__bf16 v) {
+    return __builtin_bit_cast(float, (uint32_t)__builtin_bit_cast(uint16_t, v) << 16);
+}
+__device__ __forceinline__ float widen_cost(_Float16 v) { return (float)v; }
+
+// Non-temporal load of one entry of type T, widened to FP32.
+template <typename T>
+__device__ __forceinline__ float load_cost(const T* p) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_nontemporal_load(p);
+    } else {
+        const uint16_t bits = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p));
+        return widen_cost(__builtin_bit_cast(T, bits));
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Ground costs.  Every kernel works with a pair term P(x, y) defined so that
@@ -121,7 +142,12 @@ __device__ __forceinline__ double pair_term_cost(const Consts& kc, double a, dou
     const bool row_first = a >= 0.0;
     const int64_t i = (int64_t)(row_first ? a : b);
     const int64_t j = -(int64_t)(row_first ? b : a) - 1;
-    return fma(-0.5, (double)kc.cost[i * kc.m + j], init);
+    const int64_t e = i * kc.m + j;
+    float v;
+    if (kc.cost_type == COST_BF16) v = widen_cost(static_cast<const __bf16*>(kc.cost)[e]);
+    else if (kc.cost_type == COST_F16) v = widen_cost(static_cast<const _Float16*>(kc.cost)[e]);
+    else v = static_cast<const float*>(kc.cost)[e];
+    return fma(-0.5, (double)v, init);
 }
 
 // init + P(x, y), both operands in memory, metric and dimension at run time.

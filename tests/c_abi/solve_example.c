@@ -63,7 +63,7 @@ int main(int argc, char** argv) {
     HIPOK(hipMemset(dnu, 0, sizeof(double) * (size_t)m));   /* t = 0, nu = theta = 0: a fresh start */
     HIPOK(hipMemset(dth, 0, sizeof(double) * (size_t)m));
 
-    lamp_problem prob = {n, m, d, LAMP_SQEUCLID, dx, dy, dr, dc, 0.0, 0.0, NULL};
+    lamp_problem prob = {n, m, d, LAMP_SQEUCLID, dx, dy, dr, dc, 0.0, 0.0, NULL, LAMP_COST_F32, 0};
     lamp_params params = {atof(argv[4]), 0.0, atoll(argv[3]), 0.0, 0.0, 0.0, 0.0, LAMP_FP32, 16, 0, 0};
     lamp_state state = {dnu, dth, 0, 0.0, 0.0};
     const size_t ws_bytes = lamp_workspace_bytes(&prob, &params);

@@ -45,7 +45,7 @@ def test_ctypes_layout_matches_c(tmp_path):
         "sizeof(lamp_cert), sizeof(lamp_report), offsetof(lamp_problem, cost_norm),"
         "offsetof(lamp_params, check_every), offsetof(lamp_report, row_fallbacks),"
         "offsetof(lamp_params, track_dt), offsetof(lamp_state, dt_partial),"
-        "offsetof(lamp_cert, midpoint_bound), offsetof(lamp_problem, cost));return 0;}\n")
+        "offsetof(lamp_cert, midpoint_bound), offsetof(lamp_problem, cost_type));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
@@ -54,7 +54,7 @@ def test_ctypes_layout_matches_c(tmp_path):
             ctypes.sizeof(_lib.Trace), ctypes.sizeof(_lib.Cert), ctypes.sizeof(_lib.Report),
             _lib.Problem.cost_norm.offset, _lib.Params.check_every.offset,
             _lib.Report.row_fallbacks.offset, _lib.Params.track_dt.offset, _lib.State.dt_partial.offset,
-            _lib.Cert.midpoint_bound.offset, _lib.Problem.cost.offset]
+            _lib.Cert.midpoint_bound.offset, _lib.Problem.cost_type.offset]
     assert got == want
 
 
@@ -66,10 +66,10 @@ LAMP_EINVAL, LAMP_ENOMEM = -1, -3
 
 def _problem(**kw):
     f = dict(n=100, m=80, d=3, metric=0, x=FAKE, y=FAKE, r=FAKE, c=FAKE, cost_scale=0.0, cost_norm=0.0,
-             cost=None)
+             cost=None, cost_type=0)
     f.update(kw)
     return _lib.Problem(f["n"], f["m"], f["d"], f["metric"], f["x"], f["y"], f["r"], f["c"],
-                        f["cost_scale"], f["cost_norm"], f["cost"])
+                        f["cost_scale"], f["cost_norm"], f["cost"], f["cost_type"], 0)
 
 
 def _params(**kw):
@@ -90,7 +90,8 @@ def _step(prob, params, state=None, ws=FAKE, ws_bytes=1 << 40):
 @pytest.mark.parametrize("case,kw", [("n = 0", dict(n=0)), ("m = 0", dict(m=0)), ("d = 0", dict(d=0)),
                                      ("x NULL", dict(x=None)), ("c NULL", dict(c=None)),
                                      ("unknown ground cost", dict(metric=7)),
-                                     ("cost matrix NULL", dict(metric=3, cost=None))])
+                                     ("cost matrix NULL", dict(metric=3, cost=None)),
+                                     ("unknown cost element type", dict(metric=3, cost=FAKE, cost_type=5))])
 def test_invalid_problem_is_rejected(case, kw):
     lib = _lib.load()
     assert _step(_problem(**kw), _params()) == LAMP_EINVAL, case

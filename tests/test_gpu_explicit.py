@@ -182,3 +182,61 @@ def test_explicit_zero_cost_is_rejected():
     with pytest.raises(P.LampError) as ei:
         P.solve(prob, P.make_params(eta=wl.eta, max_iter=3))
     assert ei.value.status == -2 and "zero" in str(ei.value)
+
+
+def _rounded(wl, dtype):
+    """The matrix stored in `dtype` and its exact FP64 values (what the library widens to)."""
+    t = torch.tensor(wl.cost).to(getattr(torch, dtype))
+    return t, t.double().numpy()
+
+
+@pytest.mark.parametrize("dtype", ["bfloat16", "float16"])
+@pytest.mark.parametrize("case", [3, 4])
+def test_explicit_half_storage_first_steps(dtype, case):
+    """2-byte cost storage (lamp_problem.cost_type): each entry is widened exactly, so the oracle
+    runs on the FP64 values of the rounded matrix with the tolerances of the FP32 storage;
+    several splits with ragged tails (517 x 1029) and an image-pair grid cost."""
+    wl = CASES[case]()
+    t, cost64 = _rounded(wl, dtype)
+    C = cost64 / float(np.max(cost64))
+    prob = P.Problem.from_cost(t, wl.r, wl.c)
+    assert prob.cost.dtype == getattr(torch, dtype)
+    _say("case", wl.name, dtype)
+    _, tr_or = OL.lamp_dense(C, wl.r, wl.c, OL.Params(eta=wl.eta), 5, 1.0)
+    params = P.make_params(eta=wl.eta)
+    st = P.State.fresh(prob.m)
+    for k in range(5):
+        res, tr = P.step(prob, params, st, trace=True)
+        assert res == pytest.approx(tr_or.res[k], rel=1e-6, abs=COL_TOL)
+        assert rel_l1(to_np(tr["col_a"]), tr_or.colA[k]) <= COL_TOL
+        assert rel_l1(to_np(tr["col_b"]), tr_or.colB[k]) <= COL_TOL
+        assert np.max(np.abs(to_np(tr["log_zb"]) - tr_or.logZB[k])) <= LOGZ_ATOL
+        assert rel_dual(to_np(st.nu), tr_or.nu[k]) <= DUAL_TOL
+        assert rel_dual(to_np(st.theta), tr_or.theta[k]) <= DUAL_TOL
+
+
+@pytest.mark.parametrize("dtype", ["bfloat16", "float16"])
+def test_explicit_half_storage_trajectory_and_certificate(dtype):
+    """60 tracked iterations and the certificate (cost, Round, dual values, D_T) over a 2-byte
+    matrix against the oracle on its exact values."""
+    wl = W.random_cost(180, 150, seed=37)
+    t, cost64 = _rounded(wl, dtype)
+    s = 1.0 / float(np.max(cost64))
+    C = s * cost64
+    prob = P.Problem.from_cost(t, wl.r, wl.c, cost_scale=s, cost_norm=1.0)
+    T = 60
+    prm = OL.Params(eta=wl.eta)
+    st_or, _ = OL.lamp_dense(C, wl.r, wl.c, prm, T, 1.0, trace=False)
+    cert_or = OL.certificate(C, wl.r, wl.c, st_or, prm.resolved(1.0), 1.0)
+    D, _, _ = OL.dt_sequence(C, wl.r, wl.c, prm, T, 1.0)
+    params = P.make_params(eta=wl.eta, tol=0.0, max_iter=T, check_every=20, track_dt=True)
+    st, _, status = P.solve(prob, params)
+    assert status == 0 and st.t == T
+    cert = P.certificate(prob, params, st)
+    traj = max(DUAL_TOL, 2.0 * fp32_trajectory_allowance(C, wl.r, wl.c, prm, T))
+    _say(dtype, rel_dual(to_np(st.nu), st_or.nu), traj, cert["cost"], cert_or["cost"])
+    assert rel_dual(to_np(st.nu), st_or.nu) <= traj
+    assert rel_dual(to_np(st.theta), st_or.theta) <= traj
+    assert abs(cert["cost"] - cert_or["cost"]) <= COST_TOL * abs(cert_or["cost"])
+    assert abs(cert["rounded_cost"] - cert_or["rounded_cost"]) <= 2e-5
+    assert abs(cert["dt"] - D[-1]) <= T * (DT_STEP_TOL + 5e-7)
