@@ -90,7 +90,8 @@ typedef enum {
  *      the rest is not checked.  Each entry is widened exactly to FP32 and then to FP64:
  *      the 2-byte types halve the HBM traffic of the sweeps and solve the problem whose
  *      cost is the rounded matrix.  Ignored, and may be NULL, for the other ground costs.
- *   cost_type: lamp_cost_type of cost (LAMP_EXPLICIT only; else ignored). */
+ *   cost_type: lamp_cost_type of cost (LAMP_EXPLICIT only; else ignored).
+ *   reserved: set to 0 (not read; keeps the struct 8-byte aligned). */
 typedef struct {
     int64_t n, m;
     int32_t d, metric;
@@ -116,7 +117,8 @@ typedef struct {
  *      Proposition infeas_bound(b) (def:sum_condition) into lamp_state.dt_partial; it
  *      adds one pass over the n x m pairs per iteration (the cost <C, Xbar^{t+1}>).
  *      Only with precision LAMP_FP32 and outside the batched solve (else LAMP_EINVAL).
- *      0: no tracking (the state's dt_partial becomes NaN once an iteration runs). */
+ *      0: no tracking (the state's dt_partial becomes NaN once an iteration runs).
+ *   reserved: set to 0 (not read). */
 typedef struct {
     double eta, tol;
     int64_t max_iter;
