@@ -240,3 +240,18 @@ def test_explicit_half_storage_trajectory_and_certificate(dtype):
     assert abs(cert["cost"] - cert_or["cost"]) <= COST_TOL * abs(cert_or["cost"])
     assert abs(cert["rounded_cost"] - cert_or["rounded_cost"]) <= 2e-5
     assert abs(cert["dt"] - D[-1]) <= T * (DT_STEP_TOL + 5e-7)
+
+
+@pytest.mark.parametrize("dtype", ["float32", "bfloat16"])
+def test_explicit_runs_are_bitwise_identical(dtype):
+    """Partials are merged in a fixed order: two solves of the same explicit problem give
+    identical duals and certificates, bit for bit."""
+    wl = W.random_cost(300, 260, seed=77)
+    t = torch.tensor(wl.cost).to(getattr(torch, dtype))
+    prob = P.Problem.from_cost(t, wl.r, wl.c)
+    params = P.make_params(eta=wl.eta, tol=0.0, max_iter=50, check_every=16)
+    a, _, _ = P.solve(prob, params)
+    b, _, _ = P.solve(prob, params)
+    assert torch.equal(a.nu, b.nu) and torch.equal(a.theta, b.theta)
+    ca, cb = P.certificate(prob, params, a), P.certificate(prob, params, b)
+    assert all(ca[k] == cb[k] for k in ("cost", "rounded_cost", "dual_theta", "dual_nu", "col_res"))
