@@ -84,7 +84,8 @@ typedef enum {
  *   cost_norm: ||C||_inf = max_ij C_ij.  <= 0: computed on the device.  Only
  *      trusted as given when both cost_scale and cost_norm are > 0.
  *   cost: with metric LAMP_EXPLICIT, the n x m cost matrix, row-major, of element type
- *      cost_type (device, caller-owned, read only; entry (i, j) at element i m + j).
+ *      cost_type (device, caller-owned, read only; entry (i, j) at element i m + j;
+ *      m <= 2^30, else LAMP_EINVAL).
  *      Entries must be finite and >= 0 with a positive maximum; that maximum is checked
  *      (LAMP_EDOMAIN when it is not positive) only when the library computes the scale,
  *      the rest is not checked.  Each entry is widened exactly to FP32 and then to FP64:

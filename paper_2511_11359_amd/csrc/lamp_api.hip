@@ -253,6 +253,8 @@ lamp_status check_problem(const lamp_problem* p) {
         return fail(LAMP_EINVAL, "a problem array is NULL");
     if (expl && p->cost_type != LAMP_COST_F32 && p->cost_type != LAMP_COST_BF16 && p->cost_type != LAMP_COST_F16)
         return fail(LAMP_EINVAL, "unknown cost element type %d", p->cost_type);
+    if (expl && p->m > (int64_t(1) << 30))   // column offsets within a row are 32-bit byte offsets
+        return fail(LAMP_EINVAL, "an explicit cost matrix has at most 2^30 columns (got %lld)", (long long)p->m);
     return LAMP_OK;
 }
 

@@ -18,6 +18,8 @@
 #pragma once
 #include "lamp_kernels.hpp"
 
+#include <type_traits>
+
 namespace lampk {
 
 constexpr int COST_ROWS = 8;   // rows per wave of the row sweep
@@ -66,22 +68,24 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_cost(const Ctrl* ctrl, const 
     double sA[COST_ROWS], sB[COST_ROWS];
 #pragma unroll
     for (int r = 0; r < COST_ROWS; ++r) sA[r] = sB[r] = 0.0;
-    for (int64_t jb = j0; jb < j1; jb += COST_ROW_STEP) {
-        // columns past the split read its last column and contribute 2^-inf = 0
+    // one step of COST_ROW_STEP columns; only the last step of a split can pass its end (its
+    // columns past the end read the split's last column and contribute 2^-inf = 0)
+    auto step = [&](int64_t jb, auto masked_tag) {
+        constexpr bool MASKED = decltype(masked_tag)::value;
         int64_t jj[COST_U];
         double2 gj[COST_U];
         float cv[COST_ROWS][COST_U];
 #pragma unroll
         for (int u = 0; u < COST_U; ++u) {
             const int64_t j = jb + u * 64 + lane;
-            jj[u] = min(j, j1 - 1);
+            jj[u] = MASKED ? min(j, j1 - 1) : j;
             gj[u] = g[jj[u]];
-            if (j >= j1) gj[u] = make_double2(-__builtin_inf(), -__builtin_inf());
+            if (MASKED && j >= j1) gj[u] = make_double2(-__builtin_inf(), -__builtin_inf());
         }
 #pragma unroll
         for (int r = 0; r < COST_ROWS; ++r)
 #pragma unroll
-            for (int u = 0; u < COST_U; ++u) cv[r][u] = load_cost(row[r] + jj[u]);
+            for (int u = 0; u < COST_U; ++u) cv[r][u] = load_cost_col(row[r], jj[u]);
         // every load of the step is issued before the first use: left to itself the
         // scheduler interleaves each load with its use and waits for it, one load in flight
         __builtin_amdgcn_sched_barrier(0);
@@ -97,7 +101,10 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_cost(const Ctrl* ctrl, const 
             sA[r] += (double)aA;
             sB[r] += (double)aB;
         }
-    }
+    };
+    int64_t jb = j0;
+    for (; jb + COST_ROW_STEP <= j1; jb += COST_ROW_STEP) step(jb, std::false_type{});
+    if (jb < j1) step(jb, std::true_type{});
 #pragma unroll
     for (int r = 0; r < COST_ROWS; ++r) {
         const double a = wave_sum(sA[r]);
@@ -143,7 +150,7 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_cost(Consts kc, const doubl
 #pragma unroll
         for (int r = 0; r < COST_ROWS; ++r)
 #pragma unroll
-            for (int u = 0; u < COST_U; ++u) cv[r][u] = load_cost(row[r] + jj[u]);
+            for (int u = 0; u < COST_U; ++u) cv[r][u] = load_cost_col(row[r], jj[u]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int r = 0; r < COST_ROWS; ++r)
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void dt_cost_rows_cost(const Ctrl* ctrl, con
 #pragma unroll
         for (int r_ = 0; r_ < COST_ROWS; ++r_)
 #pragma unroll
-            for (int u = 0; u < COST_U; ++u) cv[r_][u] = load_cost(row[r_] + jj[u]);
+            for (int u = 0; u < COST_U; ++u) cv[r_][u] = load_cost_col(row[r_], jj[u]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int r_ = 0; r_ < COST_ROWS; ++r_) {
@@ -251,7 +258,7 @@ struct CostRows {
 #pragma unroll
         for (int r_ = 0; r_ < COST_ROWS; ++r_)
 #pragma unroll
-            for (int u = 0; u < COST_U; ++u) cv[r_][u] = load_cost(row[r_] + jj[u]);
+            for (int u = 0; u < COST_U; ++u) cv[r_][u] = load_cost_col(row[r_], jj[u]);
     }
 };
 
@@ -431,7 +438,7 @@ __global__ __launch_bounds__(BLOCK) void round_cols_cost(Consts kc, double cA, c
         const T* __restrict__ crow = static_cast<const T*>(kc.cost) + i * kc.m;
 #pragma unroll
         for (int q = 0; q < COST_Q; ++q) {
-            const double dot = -0.5 * (double)load_cost(crow + jj[q]);
+            const double dot = -0.5 * (double)load_cost_col(crow, jj[q]);
             a[q] = fmaf(w, fexp2(fma(cA, h + dot, g[q])), a[q]);
         }
     };
@@ -495,7 +502,7 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_cost(const Ctrl* ctrl, const 
         const T* __restrict__ crow = static_cast<const T*>(kc.cost) + i * kc.m;
 #pragma unroll
         for (int q = 0; q < COST_Q; ++q) {
-            const double dot = fma(-0.5, (double)load_cost(crow + jj[q]), rv.k);
+            const double dot = fma(-0.5, (double)load_cost_col(crow, jj[q]), rv.k);
             aA[q] = fmaf(rv.wA, fexp2(fma(cA, dot, gj[q].x)), aA[q]);
             aB[q] = fmaf(rv.wB, fexp2(fma(cB, dot, gj[q].y)), aB[q]);
         }

@@ -104,6 +104,15 @@ __device__ __forceinline__ float load_cost(const T* p) {
     }
 }
 
+// The entry at column j of a row: a wave-uniform row base plus a 32-bit byte offset (the
+// explicit cost has m <= 2^30 columns), which the loads take as a scalar base and a vector
+// offset instead of a 64-bit vector address per load.
+template <typename T>
+__device__ __forceinline__ float load_cost_col(const T* row, int64_t j) {
+    const uint32_t off = (uint32_t)j * (uint32_t)sizeof(T);
+    return load_cost(reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + off));
+}
+
 // ---------------------------------------------------------------------------
 // Ground costs.  Every kernel works with a pair term P(x, y) defined so that
 //     C_ij = s (|x~_i|^2 + |y~_j|^2 - 2 P(x~_i, y~_j)):
