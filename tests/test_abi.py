@@ -91,7 +91,9 @@ def _step(prob, params, state=None, ws=FAKE, ws_bytes=1 << 40):
                                      ("x NULL", dict(x=None)), ("c NULL", dict(c=None)),
                                      ("unknown ground cost", dict(metric=7)),
                                      ("cost matrix NULL", dict(metric=3, cost=None)),
-                                     ("unknown cost element type", dict(metric=3, cost=FAKE, cost_type=5))])
+                                     ("unknown cost element type", dict(metric=3, cost=FAKE, cost_type=5)),
+                                     ("explicit cost wider than 2^30 columns",
+                                      dict(metric=3, cost=FAKE, m=(1 << 30) + 1))])
 def test_invalid_problem_is_rejected(case, kw):
     lib = _lib.load()
     assert _step(_problem(**kw), _params()) == LAMP_EINVAL, case
