@@ -156,3 +156,82 @@ def test_mutation_dt_dual_divergence_unweighted(monkeypatch):
     monkeypatch.setattr(L, "bregman_Ha_natural", lambda a, b, w: orig(a, b, np.ones_like(w)))
     _fails(pins.test_dt_summands_match_the_dual_and_primal_identities, 0.0)
     _fails(pins.test_dual_bregman_from_natural_parameters_high_precision)
+
+
+def test_mutation_prop_bound_residual_coefficient(monkeypatch):
+    """8 ||C||_inf in place of 4 ||C||_inf on the column residual."""
+    monkeypatch.setattr(L, "prop_bound",
+                        lambda cr, t, m, cn: 8.0 * cn * cr + 2.0 * cn * math.log(m) / t)
+    _fails(pins.test_prop_bound_exact_value_on_one_step_example)
+
+
+def test_mutation_prop_bound_log_nm(monkeypatch):
+    """log(n m) in place of log m (n = m in the pin)."""
+    monkeypatch.setattr(L, "prop_bound",
+                        lambda cr, t, m, cn: 4.0 * cn * cr + 2.0 * cn * math.log(m * m) / t)
+    _fails(pins.test_prop_bound_exact_value_on_one_step_example)
+
+
+def test_mutation_midpoint_bound_drops_alpha(monkeypatch):
+    """(1 + alpha) log 2 written as log 2."""
+    monkeypatch.setattr(L, "midpoint_bound",
+                        lambda dt, t, m, a, cn: 2.0 * cn * (math.log(m) + math.log(2.0) + dt) / t)
+    _fails(pins.test_midpoint_bound_exact_value_on_one_step_example, 0.5)
+
+
+def test_mutation_midpoint_bound_log_nm(monkeypatch):
+    monkeypatch.setattr(L, "midpoint_bound", lambda dt, t, m, a, cn: 2.0 * cn * (
+        math.log(m * m) + (1.0 + a) * math.log(2.0) + dt) / t)
+    _fails(pins.test_midpoint_bound_exact_value_on_one_step_example, 0.01)
+
+
+def test_mutation_dual_eta_sign_of_theta(monkeypatch):
+    """C - 2||C||_inf theta inside the softmin."""
+    def bad(C, r, c, theta, cnorm, eta):
+        return float(r @ L.softmin(C - 2.0 * cnorm * theta[None, :], eta, axis=1)
+                     - 2.0 * cnorm * (c @ theta))
+    monkeypatch.setattr(L, "dual_D_eta", bad)
+    _fails(pins.test_dual_eta_strong_duality_at_the_sinkhorn_plan)
+    _fails(pins.test_dual_eta_is_the_minimum_over_row_stochastic_plans)
+
+
+def test_mutation_dual_eta_temperature_inverted(monkeypatch):
+    """softmin taken at 1/eta (the inverse temperature) in place of eta."""
+    def bad(C, r, c, theta, cnorm, eta):
+        return float(r @ L.softmin(C + 2.0 * cnorm * theta[None, :], 1.0 / eta, axis=1)
+                     - 2.0 * cnorm * (c @ theta))
+    monkeypatch.setattr(L, "dual_D_eta", bad)
+    _fails(pins.test_dual_eta_sandwich_and_zero_temperature_limit, 1e-3)
+
+
+def test_mutation_dual_eta_drops_linear_term(monkeypatch):
+    def bad(C, r, c, theta, cnorm, eta):
+        return float(r @ L.softmin(C + 2.0 * cnorm * theta[None, :], eta, axis=1))
+    monkeypatch.setattr(L, "dual_D_eta", bad)
+    _fails(pins.test_dual_eta_is_the_minimum_over_row_stochastic_plans)
+
+
+def test_mutation_primal_penalty_factor(monkeypatch):
+    """||C||_inf in place of 2 ||C||_inf on the infeasibility."""
+    def bad(C, X, r, c, cnorm, eta=0.0):
+        rr, cc, _ = L.residuals(X, r, c)
+        return float(np.sum(C * X) + cnorm * (rr + cc) - eta * L.entropy(X))
+    monkeypatch.setattr(L, "primal_penalised", bad)
+    _fails(pins.test_primal_penalised_values_and_weak_duality)
+
+
+def test_mutation_primal_entropy_sign(monkeypatch):
+    def bad(C, X, r, c, cnorm, eta=0.0):
+        rr, cc, _ = L.residuals(X, r, c)
+        return float(np.sum(C * X) + 2.0 * cnorm * (rr + cc) + eta * L.entropy(X))
+    monkeypatch.setattr(L, "primal_penalised", bad)
+    _fails(pins.test_primal_penalised_values_and_weak_duality)
+
+
+def test_mutation_combined_gap_factor(monkeypatch):
+    """The rounding lemma's 2 ||C||_inf in place of the printed ||C||_inf."""
+    def bad(C, X, r, c, opt, cnorm):
+        rr, cc, _ = L.residuals(X, r, c)
+        return float(np.sum(C * X) - opt + 2.0 * cnorm * (rr + cc))
+    monkeypatch.setattr(L, "combined_gap", bad)
+    _fails(pins.test_combined_gap_values)

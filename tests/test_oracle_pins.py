@@ -623,3 +623,160 @@ def test_dual_bregman_from_natural_parameters_high_precision():
         assert got == pytest.approx(dha_exact(a, b, w), rel=1e-12, abs=1e-14)
         if scale <= 3.0:
             assert got == pytest.approx(L.bregman_Ha(np.tanh(a), np.tanh(b), w), rel=1e-10, abs=1e-13)
+
+
+# ---------------------------------------------------------------- value functions and bounds
+
+
+def _row_identical_example(alpha=0.01):
+    """Two identical rows, C = [[0, 2], [0, 2]] (||C||_inf = 2), r = c = (1/2, 1/2), eta = 0.
+    Worked by hand: col(X^0) = c, so thetabar^1 = nu^1 = nubar^1 = 0 and lam_1 = tau1 = 1/4;
+    every row of X^1 (and of Xbar^1) is p/2 with p = softmax(-(0, 2)/4) = ((1 + t)/2, (1 - t)/2),
+    t = tanh(1/4), so ||col(X^1) - c||_1 = tanh(1/4), OPT = 1 (half the mass must pay 2),
+    and the step's natural parameter is thetahat^1 = tanh(a), a = +-(p_1 - 1/2)/c^alpha_j =
+    +-tanh(1/4)/(1 + alpha)."""
+    C = np.array([[0.0, 2.0], [0.0, 2.0]])
+    r = c = np.array([0.5, 0.5])
+    return C, r, c, L.Params(eta=0.0, alpha=alpha)
+
+
+def test_prop_bound_exact_value_on_one_step_example():
+    """Proposition infeas_bound(a) at t = 1 of the two-identical-rows example:
+    4 ||C||_inf tanh(1/4) + 2 ||C||_inf log 2 = 8 tanh(1/4) + 4 log 2 (m = 2; n m = 4 would give
+    4 log 4), and it bounds the rounded cost's error; on the symmetric 2 x 2 example
+    (col(X^t) = c) the certificate's bound is exactly 2 log 2 / t."""
+    C, r, c, prm = _row_identical_example()
+    st = L.lamp_step(C, r, c, L.lamp_init(2), prm.resolved(2.0), 2.0)
+    cert = L.certificate(C, r, c, st, prm.resolved(2.0), 2.0)
+    t1 = math.tanh(0.25)
+    assert cert["col_res"] == pytest.approx(t1, rel=1e-14)
+    assert cert["prop_bound"] == pytest.approx(8.0 * t1 + 4.0 * math.log(2.0), rel=1e-14)
+    assert cert["rounded_cost"] - 1.0 <= cert["prop_bound"]
+
+    C2 = np.array([[0.0, 1.0], [1.0, 0.0]])
+    st = L.lamp_init(2)
+    p2 = L.Params(eta=0.0).resolved(1.0)
+    for t in range(1, 30):
+        st = L.lamp_step(C2, r, c, st, p2, 1.0)
+        cert = L.certificate(C2, r, c, st, p2, 1.0)
+        assert cert["prop_bound"] == pytest.approx(2.0 * math.log(2.0) / t, rel=1e-14)
+
+
+@pytest.mark.parametrize("alpha", [0.01, 0.5])
+def test_midpoint_bound_exact_value_on_one_step_example(alpha):
+    """Proposition infeas_bound(b) at t = 1 of the two-identical-rows example.  thetabar^1 = theta^0
+    = 0 and Xbar^1 = X^1, so D_1 = D_H(0 || thetahat^1) - KL(X^1 || X^0) with
+    D_H(0 || tanh a) = sum_j c^alpha_j ln cosh a_j (def:DHa_explicit) = (1 + alpha) ln cosh(a) and
+    KL(X^1 || X^0) = ln 2 - h(p_1) (h the binary entropy in nats); the bound is
+    2 ||C||_inf (ln 2 + (1 + alpha) ln 2 + D_1) = 4 (ln 2 + (1 + alpha) ln 2 + D_1)."""
+    C, r, c, prm = _row_identical_example(alpha)
+    D, _, _ = L.dt_sequence(C, r, c, prm, 1, 2.0)
+    t1 = math.tanh(0.25)
+    a = t1 / (1.0 + alpha)
+    p1 = 0.5 * (1.0 + t1)
+    h = -p1 * math.log(p1) - (1.0 - p1) * math.log(1.0 - p1)
+    d1 = (1.0 + alpha) * math.log(math.cosh(a)) - (math.log(2.0) - h)
+    assert D[0] == pytest.approx(d1, rel=1e-12, abs=1e-15)
+    ref = 4.0 * (math.log(2.0) + (1.0 + alpha) * math.log(2.0) + d1)
+    assert L.midpoint_bound(D[0], 1, 2, alpha, 2.0) == pytest.approx(ref, rel=1e-14)
+
+
+@pytest.mark.parametrize("eta", [1e-3, 3e-2, 0.3])
+def test_dual_eta_sandwich_and_zero_temperature_limit(eta):
+    """softmin^eta lies in [min - eta log m, min] for every row (Appendix B), and r sums to one,
+    so D(theta) - eta log m <= D^eta(theta) <= D(theta) (def:dual_spp_e against def:dual_spp);
+    with a unique minimiser in every row D^eta -> D faster than eta log m."""
+    C, r, c, *_ = _problem(7, 9, 2, seed=41)
+    cnorm = float(C.max())
+    g = np.random.default_rng(42)
+    for _ in range(5):
+        th = g.uniform(-1.0, 1.0, 9)
+        d0 = L.dual_D(C, r, c, th, cnorm)
+        de = L.dual_D_eta(C, r, c, th, cnorm, eta)
+        assert d0 - eta * math.log(9) - 1e-13 <= de <= d0 + 1e-13
+    th = g.uniform(-1.0, 1.0, 9)
+    assert abs(L.dual_D_eta(C, r, c, th, cnorm, 1e-5) - L.dual_D(C, r, c, th, cnorm)) < 1e-6
+
+
+def test_dual_eta_is_the_minimum_over_row_stochastic_plans():
+    """D^eta(theta) is K^eta minimised over row-stochastic p (problem spp, def:dual_spp_e), up to
+    the constant eta H(r) that H(diag(r) p) carries.  With m = 2 each row of p is (q, 1 - q) and
+    K^eta separates over rows, so the minimum is found here by a 1-D search per row over the
+    logit of q, not from the LogSumExp formula."""
+    C, r, c, *_ = _problem(3, 2, 2, seed=43)
+    cnorm = float(C.max())
+    K = 2.0 * cnorm
+    for eta, th in [(0.1, np.array([0.3, -0.6])), (0.02, np.array([-0.2, 0.45]))]:
+        total = -K * float(c @ th)
+        for i in range(3):
+            def row_obj(u, i=i):      # u = log(q / (1 - q))
+                lq, l1q = -np.logaddexp(0.0, -u), -np.logaddexp(0.0, u)
+                x = r[i] * np.exp([lq, l1q])
+                return float(x @ (C[i] + K * th) + eta * (x @ (np.log(r[i]) + np.array([lq, l1q]))))
+            total += minimize_scalar(row_obj, bracket=(-5.0, 5.0), method="brent",
+                                     options=dict(xtol=1e-14)).fun
+        hr = L.entropy(r[:, None])
+        assert L.dual_D_eta(C, r, c, th, cnorm, eta) == pytest.approx(total + eta * hr, abs=1e-12)
+
+
+def test_dual_eta_strong_duality_at_the_sinkhorn_plan():
+    """At the EOT solution X_eta = exp((f_i + g_j - C_ij)/eta) (Sinkhorn, problem primal_eot) the
+    column potential gives theta* = -g/(2||C||_inf) with D^eta(theta*) = <C, X_eta> - eta H(X_eta)
+    + eta H(r), and theta* maximises D^eta (it is concave): random perturbations only lower it."""
+    C, r, c, *_ = _problem(5, 4, 2, seed=45)
+    cnorm = float(C.max())
+    eta = 0.05
+    Xs = exact.sinkhorn_eot(C, r, c, eta)
+    g = eta * np.log(Xs[0] / Xs[0, 0]) + C[0] - C[0, 0]      # g_j - g_0 from row 0
+    th = -g / (2.0 * cnorm)
+    th -= 0.5 * (th.max() + th.min())
+    val = float(np.sum(C * Xs)) - eta * L.entropy(Xs) + eta * L.entropy(r[:, None])
+    top = L.dual_D_eta(C, r, c, th, cnorm, eta)
+    assert top == pytest.approx(val, rel=1e-10, abs=1e-12)
+    rng = np.random.default_rng(46)
+    for _ in range(20):
+        assert L.dual_D_eta(C, r, c, th + rng.normal(scale=0.05, size=4), cnorm, eta) < top
+
+
+def test_primal_penalised_values_and_weak_duality():
+    """P^eta of problem l1_ot_primal: on the LP plan X* it is OPT (HiGHS); moving eps of mass onto
+    one entry adds eps C_ij and eps to each of the row and column residuals, each priced at
+    2||C||_inf; on the product plan r c^T (feasible) it is <C, r c^T> - eta (H(r) + H(c)); and
+    D^eta(theta) <= P^eta(diag(r) p) + eta H(r) for every theta in [-1, 1]^m and row-stochastic p."""
+    C, r, c, *_ = _problem(5, 6, 2, seed=47)
+    cnorm = float(C.max())
+    opt, Xstar = exact.lp_ot(C, r, c)
+    Xstar = np.maximum(Xstar, 0.0)
+    assert L.primal_penalised(C, Xstar, r, c, cnorm) == pytest.approx(opt, abs=1e-9)
+    eps = 1e-3
+    Xp = Xstar.copy()
+    Xp[2, 4] += eps
+    assert L.primal_penalised(C, Xp, r, c, cnorm) == pytest.approx(
+        opt + eps * C[2, 4] + 4.0 * cnorm * eps, abs=1e-9)
+    eta = 0.07
+    prod = np.outer(r, c)
+    hr, hc = L.entropy(r[:, None]), L.entropy(c[:, None])
+    assert L.primal_penalised(C, prod, r, c, cnorm, eta) == pytest.approx(
+        float(r @ C @ c) - eta * (hr + hc), rel=1e-13)
+    g = np.random.default_rng(48)
+    for _ in range(20):
+        th = g.uniform(-1.0, 1.0, 6)
+        X = r[:, None] * g.dirichlet(np.ones(6), size=5)
+        for e in (0.0, eta):
+            de = L.dual_D(C, r, c, th, cnorm) if e == 0.0 else L.dual_D_eta(C, r, c, th, cnorm, e)
+            assert de <= L.primal_penalised(C, X, r, c, cnorm, e) + e * hr + 1e-12
+
+
+def test_combined_gap_values():
+    """Equation (combined) as printed (coefficient ||C||_inf): zero on the LP plan, and eps C_ij +
+    ||C||_inf (eps + eps) after eps of mass is added to one entry."""
+    C, r, c, *_ = _problem(5, 6, 2, seed=49)
+    cnorm = float(C.max())
+    opt, Xstar = exact.lp_ot(C, r, c)
+    Xstar = np.maximum(Xstar, 0.0)
+    assert L.combined_gap(C, Xstar, r, c, opt, cnorm) == pytest.approx(0.0, abs=1e-9)
+    eps = 2e-3
+    Xp = Xstar.copy()
+    Xp[1, 3] += eps
+    assert L.combined_gap(C, Xp, r, c, opt, cnorm) == pytest.approx(
+        eps * C[1, 3] + 2.0 * cnorm * eps, abs=1e-9)
