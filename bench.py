@@ -55,30 +55,52 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, s, seconds_target: float = 15.0):
-    """The FP64 oracle (row-block evaluation of one marginal pass) timed on a bounded sample of
-    rows of the same workload; pair-evals counted like the GPU's."""
+def cpu_baseline(wl, s, seconds_target: float = 12.0):
+    """The FP64 oracle timed on a bounded sample of rows of the same workload (row log-sum-exp over
+    all m columns and the rows' column terms: one marginal pass), pair-evals counted like the
+    GPU's.  Main figure: the oracle's C pass (oracle/rowpass.c) on every host core it gets;
+    beside it the NumPy row-block form on one thread."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
+    from oracle import rowpass as RP
     from oracle import stream as OS
+    nu = np.zeros(wl.m)
+    cols = np.arange(wl.m)
+    rows = 16
+    while True:
+        cost = RP.Cost(s, 1.0, x=wl.x[:rows], y=wl.y)
+        t0 = time.perf_counter()
+        L = cost.log_normalisers([nu], [10.0])
+        cost.sampled_columns([nu], [10.0], L, wl.r[:rows], cols)
+        dt_c = time.perf_counter() - t0
+        if dt_c >= seconds_target / 3 or rows >= wl.n:
+            break
+        rows = min(wl.n, rows * 4)
+    threads = RP.num_threads()
+    allcore = 2.0 * rows * wl.m / dt_c
+    # NumPy form on one thread (the BLAS pool limited to one)
     x = wl.x.astype(np.float64)
     y = wl.y.astype(np.float64)
-    nu = np.zeros(wl.m)
-    rows = 0
+    nrows = 0
     block = 4 if wl.d > 16 else 16
-    with threadpool_limits(limits=1):   # the BLAS of the block products runs on one thread
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        while time.perf_counter() - t0 < seconds_target and rows < wl.n:
-            idx = np.arange(rows, min(wl.n, rows + block))
+        while time.perf_counter() - t0 < seconds_target / 2 and nrows < wl.n:
+            idx = np.arange(nrows, min(wl.n, nrows + block))
             OS.marginal_pass(x, y, wl.r, s, 1.0, nu, 10.0, rows=idx, block=block)
-            rows += len(idx)
-        dt = time.perf_counter() - t0
-    # marginal_pass evaluates each pair twice (row log-sum-exp, then the column term)
-    pair_evals = 2.0 * rows * wl.m
-    return {"value": pair_evals / dt, "unit": "pair-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"one marginal pass (row LSE + column terms) over {rows} of {wl.n} rows x "
-                      f"{wl.m} columns, d={wl.d}, FP64 NumPy, single thread, {dt:.1f} s"}
+            nrows += len(idx)
+        dt_n = time.perf_counter() - t0
+    single = 2.0 * nrows * wl.m / dt_n
+    log(f"cpu oracle: C pass {allcore:.3e} pair-evals/s on {threads} threads ({rows} rows, {dt_c:.1f} s); "
+        f"NumPy {single:.3e} on 1 thread ({nrows} rows, {dt_n:.1f} s); host cpus {os.cpu_count()}")
+    return {"value": allcore, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"one marginal pass (row LSE + column terms) over {rows} of {wl.n} rows x {wl.m} columns, "
+                      f"d={wl.d}, FP64, the oracle's C pass (oracle/rowpass.c) on {threads} OpenMP threads, "
+                      f"{dt_c:.1f} s",
+            "host_cpus": os.cpu_count(),
+            "numpy_single_thread": {"value": single, "cores": 1,
+                                    "sample": f"{nrows} rows, oracle/stream.py row blocks, {dt_n:.1f} s"}}
 
 
 def measure_form(P, prob, wl, form, steps, warmup, reps):
@@ -136,7 +158,7 @@ def measured_traffic(workload, form, kernel):
     return None
 
 
-def roofline(wl, form, m):
+def roofline(wl, form, m, probe=None):
     """Roofline of the slower sweep kernel of a form: the exponential (VALU) bound for the
     vector-ALU and half-precision forms, the matrix-core bound where the dot products dominate."""
     dom_name, dom_ms = ("row_sweep", m["row_sweep_ms"])
@@ -152,25 +174,56 @@ def roofline(wl, form, m):
                 "row_sweep_ms": m["row_sweep_ms"], "col_sweep_ms": m["col_sweep_ms"]}
     exps = 2.0 * wl.n * wl.m                      # both couplings, one exponential per pair each
     ach = exps / (dom_ms * 1e-3)
-    return {"bound": "alu", "kernel": dom_name, "achieved": ach / 1e12, "peak": EXP_PEAK / 1e12,
-            "unit": "Texp/s", "frac": ach / EXP_PEAK, "traffic": measured_traffic(wl.name, form, dom_name),
-            "per_launch": f"2*n*m = {exps:.3e} exponentials",
-            "row_sweep_ms": m["row_sweep_ms"], "col_sweep_ms": m["col_sweep_ms"]}
+    out = {"bound": "alu", "kernel": dom_name, "achieved": ach / 1e12, "peak": EXP_PEAK / 1e12,
+           "unit": "Texp/s", "frac": ach / EXP_PEAK, "traffic": measured_traffic(wl.name, form, dom_name),
+           "per_launch": f"2*n*m = {exps:.3e} exponentials",
+           "row_sweep_ms": m["row_sweep_ms"], "col_sweep_ms": m["col_sweep_ms"]}
+    if probe:
+        out["probe_exp_per_s"] = probe
+        out["frac_of_probe"] = ach / probe
+    return out
 
 
-def time_to_tol(P, prob, wl, form, tol, max_iter):
+def fresh_problem(P, wl, dev):
+    """The workload's problem with the cost scale left to the solve (cost_scale = 0): a timed
+    solve then includes the device pass that computes max_ij ||x_i - y_j||^2."""
+    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, device=dev)
+    return prob
+
+
+def time_to_tol(P, prob, wl, form, tol, max_iter, start=None):
+    """Wall time of lamp_solve from `start` (default: the beginning, the cost-scale pass included
+    when prob.cost_scale is 0) until ||col(X^t) - c||_1 <= tol, then the certificate of the
+    returned iterate on the exact cost (row and column residuals, <C, X^t>, D(theta), D(nu), gap)."""
     import torch
     params = P.make_params(eta=wl.eta, tol=tol, max_iter=max_iter, check_every=64, precision=form)
+    prob.workspace(params)                       # allocate outside the timed region
+    st0 = start.clone() if start is not None else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st, rep, status = P.solve(prob, params)
+    st, rep, status = P.solve(prob, params, st0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
     cert = P.certificate(prob, P.make_params(eta=wl.eta, precision=form), st)
+    dt_cert = time.perf_counter() - t1
     log(f"{form}: time to ||col - c||_1 <= {tol}: {rep['iters']} iterations, {dt:.2f} s, "
-        f"converged={rep['converged']}, final residual {rep['final_res']:.3e}, cost {cert['cost']:.9e}")
-    return {"tol": tol, "iters": rep["iters"], "seconds": dt, "converged": bool(rep["converged"]),
-            "final_res": rep["final_res"], "cost": cert["cost"], "gap": cert["gap"]}, st
+        f"converged={rep['converged']}, final residual {rep['final_res']:.3e}; certificate on the exact "
+        f"cost: col_res {cert['col_res']:.3e} row_res {cert['row_res']:.3e} cost {cert['cost']:.9e} "
+        f"D(theta) {cert['dual_theta']:.6e} D(nu) {cert['dual_nu']:.6e} gap {cert['gap']:.4e} ({dt_cert:.2f} s)")
+    out = {"tol": tol, "iters": rep["iters"], "t": st.t, "seconds": dt, "converged": bool(rep["converged"]),
+           "final_res": rep["final_res"], "cost_scale_in_timing": prob.cost_scale <= 0,
+           "cert": {k: cert[k] for k in ("col_res", "row_res", "cost", "dual_theta", "dual_nu",
+                                         "primal_penalized", "gap", "rounded_cost", "prop_bound")},
+           "cert_seconds": dt_cert}
+    return out, st
+
+
+def polish(P, prob, wl, st, tol, max_iter):
+    """The FP32 reference form resumed from a matrix-core form's iterate until its own residual
+    (exact cost) meets tol: the certified-gap comparison of the precision forms."""
+    out, st2 = time_to_tol(P, prob, wl, "fp32", tol, max_iter, start=st)
+    return out, st2
 
 
 def batch_mode(args):
@@ -233,18 +286,28 @@ def grad_mode(args):
     P.backward(prob, params, st)                 # warm-up (workspace, code paths)
     torch.cuda.synchronize()
     reps = max(1, args.steps // 10)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record()                                 # the library launches on torch's current stream
     for _ in range(reps):
         g = P.backward(prob, params, st)
+    ev1.record()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    dev_ms = ev0.elapsed_time(ev1) / reps
     pairs = float(wl.n) * wl.m
-    log(f"adjoint: {dt * 1e3:.3f} ms per gradient ({pairs / dt:.3e} pairs/s), |g|_max {float(g.abs().max()):.3e}")
+    ach = pairs / (dev_ms * 1e-3)
+    log(f"adjoint: {dt * 1e3:.3f} ms per gradient (device {dev_ms:.3f} ms, {ach:.3e} exp/s), "
+        f"|g|_max {float(g.abs().max()):.3e}")
     out = {"metric": "pair-evals/s", "value": pairs / dt, "unit": "pair-evals/s", "n_gpus": 1,
            "steps": reps, "warmup": 1, "ms_per_step": dt * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
            "config": {"workload": wl.name + "_gradient", "n": wl.n, "m": wl.m, "d": wl.d,
                       "eta": wl.eta, "forward": "bf16_mfma", "adjoint": "fp32"},
+           "roofline": {"bound": "alu", "kernel": "adjoint (backward call: column term, adjoint sweep, finish)",
+                        "achieved": ach / 1e12, "peak": EXP_PEAK / 1e12, "unit": "Texp/s",
+                        "frac": ach / EXP_PEAK, "traffic": None,
+                        "per_launch": f"n*m = {pairs:.3e} exponentials", "device_ms": dev_ms},
            "forward_time_to_tol": fwd, "adjoint_ms": dt * 1e3}
     print(json.dumps(out), flush=True)
 
@@ -308,9 +371,29 @@ def cost_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def peak_mode(args):
+    """The exponential probe alone (lamp_exp_rate): issue rate of the base-2 exponential at a few
+    launch sizes, against the derived 256 CUs x 32 lanes per clock x 2.4 GHz."""
+    import torch
+
+    import paper_2511_11359_amd as P
+    dev = torch.device("cuda:0")
+    rates = {}
+    for blocks in (1024, 2048, 4096, 8192, 16384):
+        rates[blocks] = P.exp_rate(dev, blocks=blocks, iters=4096, reps=args.reps)
+        log(f"probe {blocks} blocks x 256 threads: {rates[blocks]:.4e} exp/s ({rates[blocks] / EXP_PEAK:.3f})")
+    best = max(rates.values())
+    out = {"metric": "exp/s", "value": best, "unit": "exp/s", "n_gpus": 1, "steps": args.reps, "warmup": 1,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic", "config": {"workload": "exp_probe", "chains": 8, "iters": 4096},
+           "derived_peak": EXP_PEAK, "frac_of_derived": best / EXP_PEAK,
+           "by_blocks": {str(k): v for k, v in rates.items()}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "grad", "cost"])
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "grad", "cost", "peak"])
     ap.add_argument("--cost-dtype", default="float32", choices=["float32", "bfloat16"],
                     help="element type of the explicit cost matrix in --mode cost")
     ap.add_argument("--cost-max-iter", type=int, default=3000,
@@ -325,11 +408,14 @@ def main():
     ap.add_argument("--compare", default="fp32_mfma,fp32",
                     help="other forms measured beside the primary one (comma list, '' for none)")
     ap.add_argument("--compare-steps", type=int, default=10)
-    ap.add_argument("--time-to-tol", default="bf16_mfma,fp32",
+    ap.add_argument("--time-to-tol", default="bf16_mfma,fp16_mfma,fp32",
                     help="forms solved from the start to the tolerance (comma list, '' for none)")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--polish", default="bf16_mfma",
+                    help="matrix-core forms whose time to tolerance is followed by an FP32-form polish "
+                         "to the same tolerance on the exact cost (comma list, '' for none)")
     ap.add_argument("--reps", type=int, default=5, help="launches per kernel for the roofline timing")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
@@ -346,6 +432,9 @@ def main():
         return
     if args.mode == "cost":
         cost_mode(args)
+        return
+    if args.mode == "peak":
+        peak_mode(args)
         return
 
     import torch
@@ -369,8 +458,18 @@ def main():
     ttt = None
     forms_ttt = [f for f in args.time_to_tol.split(",") if f]
     if forms_ttt:
-        ttt = {f: time_to_tol(P, prob, wl, f, args.tol, args.max_iter)[0] for f in forms_ttt}
+        ttt = {}
+        for f in forms_ttt:
+            prob_f = fresh_problem(P, wl, dev)
+            res, st_f = time_to_tol(P, prob_f, wl, f, args.tol, args.max_iter)
+            if f != "fp32" and f in args.polish.split(","):
+                pol, _ = polish(P, prob_f, wl, st_f, args.tol, args.max_iter)
+                res["fp32_polish"] = pol
+                res["seconds_with_polish"] = res["seconds"] + pol["seconds"]
+            ttt[f] = res
     cpu = None if args.no_cpu else cpu_baseline(wl, s)
+    probe = P.exp_rate(dev)
+    log(f"exponential probe: {probe:.4e} exp/s ({probe / EXP_PEAK:.3f} of the derived {EXP_PEAK:.4e})")
 
     out = {
         "metric": "pair-evals/s",
@@ -387,7 +486,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "n": wl.n, "m": wl.m, "d": wl.d, "eta": wl.eta,
                    "form": args.precision, "precision": FORM_DESC[args.precision]},
-        "roofline": roofline(wl, args.precision, main_m),
+        "roofline": roofline(wl, args.precision, main_m, probe),
         "cpu_baseline": cpu,
         "forms": others,
         "time_to_tol": ttt,

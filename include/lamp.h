@@ -250,6 +250,13 @@ lamp_status lamp_sweep_times(const lamp_problem *prob, const lamp_params *params
                              const lamp_state *state, void *ws, size_t ws_bytes, void *stream,
                              int32_t reps, double *row_ms, double *col_ms);
 
+/* Measurement support (not part of the method): the issue rate of the exponential
+ * instruction the sweeps are bound by.  Launches `blocks` blocks of 256 threads, each lane
+ * running 8 independent chains of `iters` base-2 exponentials, `reps` times back to back
+ * between HIP events on `stream` (after one untimed launch); *exp_per_s (host) receives
+ * exponentials per second.  Reads and writes no memory. */
+lamp_status lamp_exp_rate(void *stream, int32_t blocks, int32_t iters, int32_t reps, double *exp_per_s);
+
 /* Batching form: `count` independent problems of any n, m, d advance together.  Each
  * phase of an iteration (row sweep, row finish, column sweep, dual update) is one
  * launch for the whole batch: a persistent grid loops over a work list of

@@ -19,6 +19,9 @@ algorithm's steps from the paper, in FP64, with the paper's notation:
   materialising C (for large sizes: timing and sampled parity).
 * ``cmax``   -- max_ij ||x_i - y_j||^2 in plain C (exact FP64), for the cost
   normalisation at sizes where NumPy is too slow.
+* ``rowpass`` -- one iteration's row log-normalisers on every row and column
+  marginals and dual steps on listed columns, in plain C (FP64, OpenMP), for
+  parity at the full benchmark sizes.
 
 Parity status of each function is stated in its docstring; functions with no
 independent pin say "parity unpinned".

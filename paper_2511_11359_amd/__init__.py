@@ -3,8 +3,8 @@
 The solver lives in liblamp.so (HIP kernels + C ABI, include/lamp.h); this
 package only marshals arguments.  ``workloads`` draws seeded synthetic inputs.
 """
-from .api import (LampError, LampOT, Problem, State, backward, backward_y, certificate, cost_scale, make_params,
-                  solve, solve_batched, step, sweep_times)
+from .api import (LampError, LampOT, Problem, State, backward, backward_y, certificate, cost_scale, exp_rate,
+                  make_params, solve, solve_batched, step, sweep_times)
 
 __all__ = ["LampError", "LampOT", "Problem", "State", "backward", "backward_y", "certificate", "cost_scale",
-           "make_params", "solve", "solve_batched", "step", "sweep_times"]
+           "exp_rate", "make_params", "solve", "solve_batched", "step", "sweep_times"]

@@ -91,6 +91,7 @@ SYMBOLS = {
     "lamp_sweep_times": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params),
                                    ctypes.POINTER(State), c_void_p, c_size_t, c_void_p, c_int32,
                                    ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
+    "lamp_exp_rate": (c_int32, [c_void_p, c_int32, c_int32, c_int32, ctypes.POINTER(c_double)]),
     "lamp_batch_workspace_bytes": (c_size_t, [ctypes.POINTER(Problem), c_int32, ctypes.POINTER(Params)]),
     "lamp_solve_batched": (c_int32, [ctypes.POINTER(Problem), c_int32, ctypes.POINTER(Params),
                                      ctypes.POINTER(State), c_void_p, c_size_t, c_void_p,

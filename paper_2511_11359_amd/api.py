@@ -139,19 +139,23 @@ def cost_scale(prob: Problem) -> tuple[float, float]:
     return s.value, md.value
 
 
+def _trace_buffers(prob: Problem, trace: bool):
+    if not trace:
+        return None, None
+    dd = dict(device=prob.device, dtype=torch.float64)
+    tr = dict(log_za=torch.empty(prob.n, **dd), log_zb=torch.empty(prob.n, **dd),
+              col_a=torch.empty(prob.m, **dd), col_b=torch.empty(prob.m, **dd),
+              theta_bar=torch.empty(prob.m, **dd), theta_hat=torch.empty(prob.m, **dd))
+    trs = L.Trace(*(tr[k].data_ptr() for k in ["log_za", "log_zb", "col_a", "col_b",
+                                                "theta_bar", "theta_hat"]))
+    return tr, trs
+
+
 def step(prob: Problem, params: L.Params, state: State, trace: bool = False):
     """One iteration of Algorithm 2 in place.  Returns (||col(X^t) - c||_1, trace dict or None)."""
     lib = L.load()
     ws, nb = prob.workspace(params)
-    tr = None
-    trs = None
-    if trace:
-        dd = dict(device=prob.device, dtype=torch.float64)
-        tr = dict(log_za=torch.empty(prob.n, **dd), log_zb=torch.empty(prob.n, **dd),
-                  col_a=torch.empty(prob.m, **dd), col_b=torch.empty(prob.m, **dd),
-                  theta_bar=torch.empty(prob.m, **dd), theta_hat=torch.empty(prob.m, **dd))
-        trs = L.Trace(*(tr[k].data_ptr() for k in ["log_za", "log_zb", "col_a", "col_b",
-                                                    "theta_bar", "theta_hat"]))
+    tr, trs = _trace_buffers(prob, trace)
     p = prob.struct()
     s = state.struct()
     res = ctypes.c_double()
@@ -227,6 +231,16 @@ def sweep_times(prob: Problem, params: L.Params, state: State, reps: int = 10) -
                                 _stream_handle(prob.device), int(reps), ctypes.byref(a),
                                 ctypes.byref(b)))
     return a.value, b.value
+
+
+def exp_rate(device="cuda", blocks: int = 8192, iters: int = 4096, reps: int = 5) -> float:
+    """Measured issue rate of the base-2 exponential on this GPU (exponentials per second), from
+    the library's probe kernel (measurement support)."""
+    lib = L.load()
+    out = ctypes.c_double()
+    _check(lib.lamp_exp_rate(_stream_handle(torch.device(device)), int(blocks), int(iters), int(reps),
+                             ctypes.byref(out)))
+    return out.value
 
 
 def solve_batched(probs: list, params: L.Params, states: list | None = None):

@@ -22,8 +22,10 @@
 #include "lamp_mfma.hpp"
 #include "lamp_batch.hpp"
 #include "lamp_cost.hpp"
+#include "lamp_measure.hpp"
 
 using namespace lampk;
+
 
 namespace {
 
@@ -72,7 +74,7 @@ int64_t choose_split(int64_t owned, int64_t len, int64_t target = TARGET_BLOCKS)
 }
 
 struct Layout {
-    size_t ctrl, sched, xc, yc, xcf, ycf, xn2, yn2, gtab, H, rowvar, rpart, cpart, nu1, th1, respart,
+    size_t ctrl, sched, xc, yc, xcf, ycf, xn2, yn2, gtab, H, rowvar, rowck, rpart, cpart, nu1, th1, respart,
         dtrow, dtpart, scratch, small, xop, yop, gtabf, rowq, total;
     int64_t split_r, P_r, split_c, P_c;
     // matrix-core forms
@@ -172,9 +174,9 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
         off += align256(bytes);
         return o;
     };
-    // row partials: [P][n] double2 for the sweeps, [P_r][n][d+1] for the adjoint,
+    // row partials: [P][n] double2 for the sweeps, [P_r][n][d+2] for the adjoint,
     // [4][n] for the certificate rows
-    size_t rpart_d = std::max<size_t>((size_t)L.P_r * n * std::max(2, d + 1), (size_t)4 * n);
+    size_t rpart_d = std::max<size_t>((size_t)L.P_r * n * std::max(2, d + 2), (size_t)4 * n);
     // column partials: [P][m] double2 for the sweeps, [P_c][m][d+1] doubles for the y adjoint
     size_t cpart_d2 = std::max<size_t>((size_t)L.P_c * m, ((size_t)L.P_c * m * (d + 1) + 1) / 2);
     if (is_mfma(prec)) {
@@ -200,6 +202,7 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     L.gtab = take(sizeof(double2) * 2 * m);
     L.H = take(sizeof(double) * n);
     L.rowvar = take(sizeof(RowVar) * n);
+    L.rowck = take(sizeof(double2) * n);
     L.rpart = take(sizeof(double) * rpart_d);
     L.cpart = take(sizeof(double2) * cpart_d2);
     L.nu1 = take(sizeof(double) * m);
@@ -298,19 +301,26 @@ lamp_status check_ws(const lamp_problem* p, void* ws, size_t ws_bytes, int prec 
 }
 
 // Marginals must be strictly positive and sum to 1 (r in Delta^n, c in Delta^m with full support).
-lamp_status check_marginals(const lamp_problem* p) {
-    std::vector<double> h((size_t)std::max(p->n, p->m));
+// Read in chunks through a fixed host buffer, ordered on the call's stream (the marginals may
+// have been written by earlier work on it).
+lamp_status check_marginals(const lamp_problem* p, hipStream_t st) {
+    constexpr int64_t CH = 2048;
+    double h[CH];
     const double* arrs[2] = {p->r, p->c};
     const int64_t lens[2] = {p->n, p->m};
     const char* names[2] = {"r", "c"};
     for (int q = 0; q < 2; ++q) {
-        HIPCHK(hipMemcpy(h.data(), arrs[q], sizeof(double) * lens[q], hipMemcpyDeviceToHost));
         double sum = 0.0;
-        for (int64_t i = 0; i < lens[q]; ++i) {
-            if (!(h[i] > 0.0) || !std::isfinite(h[i]))
-                return fail(LAMP_EDOMAIN, "%s[%lld] = %g is not a positive finite mass", names[q],
-                            (long long)i, h[i]);
-            sum += h[i];
+        for (int64_t i0 = 0; i0 < lens[q]; i0 += CH) {
+            const int64_t cnt = std::min(CH, lens[q] - i0);
+            HIPCHK(hipMemcpyAsync(h, arrs[q] + i0, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t k = 0; k < cnt; ++k) {
+                if (!(h[k] > 0.0) || !std::isfinite(h[k]))
+                    return fail(LAMP_EDOMAIN, "%s[%lld] = %g is not a positive finite mass", names[q],
+                                (long long)(i0 + k), h[k]);
+                sum += h[k];
+            }
         }
         if (std::fabs(sum - 1.0) > 1e-9) return fail(LAMP_EDOMAIN, "%s sums to %.17g, not 1", names[q], sum);
     }
@@ -605,15 +615,16 @@ void launch_col_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t s
     const double* yc = at<double>(ws, L.yc);
     const double2* gt = at<double2>(ws, L.gtab);
     const RowVar* rv = at<RowVar>(ws, L.rowvar);
+    const double2* ck = at<double2>(ws, L.rowck);
     double2* part = at<double2>(ws, L.cpart);
     const bool done = by_metric(kc.metric, [&](auto m) {
         return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
             hipLaunchKernelGGL((col_sweep<decltype(m)::value, decltype(dd)::value>), g, dim3(BLOCK), 0, st, ctrl,
-                               sch, kc, xc, yc, gt, rv, part, L.split_c);
+                               sch, kc, xc, yc, gt, rv, ck, part, L.split_c);
         });
     });
     if (!done)
-        hipLaunchKernelGGL(col_sweep_dyn, g, dim3(BLOCK), 0, st, ctrl, sch, kc, d, xc, yc, gt, rv, part, L.split_c);
+        hipLaunchKernelGGL(col_sweep_dyn, g, dim3(BLOCK), 0, st, ctrl, sch, kc, d, xc, yc, gt, rv, ck, part, L.split_c);
 }
 
 void launch_adjoint(const Layout& L, Consts kc, int d, void* ws, double cA, const double* gA,
@@ -623,15 +634,14 @@ void launch_adjoint(const Layout& L, Consts kc, int d, void* ws, double cA, cons
     const double* xc = at<double>(ws, L.xc);
     const double* yc = at<double>(ws, L.yc);
     const float* ycf = at<float>(ws, L.ycf);
-    const double* H = at<double>(ws, L.H);
     const bool done = by_metric(kc.metric, [&](auto m) {
         return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
             hipLaunchKernelGGL((adjoint_sweep<decltype(m)::value, decltype(dd)::value>), g, dim3(BLOCK), 0, st, kc,
-                               cA, xc, yc, ycf, gA, H, part, L.split_r);
+                               cA, xc, yc, ycf, gA, part, L.split_r);
         });
     });
     if (!done)
-        hipLaunchKernelGGL(adjoint_sweep_dyn, g, dim3(BLOCK), 0, st, kc, d, cA, xc, yc, ycf, gA, H, part, L.split_r);
+        hipLaunchKernelGGL(adjoint_sweep_dyn, g, dim3(BLOCK), 0, st, kc, d, cA, xc, yc, ycf, gA, part, L.split_r);
 }
 
 __global__ void fill_scaled(int64_t cnt, double f, const double* __restrict__ in, double* __restrict__ out) {
@@ -716,13 +726,13 @@ Consts make_consts(const lamp_problem* p, const Resolved& R) {
 double next_lam(double lam, double tau1, double eta) { return tau1 + lam * (1.0 - tau1 * eta); }
 #pragma clang fp contract(on)
 
-// Fills `cnt` schedule entries starting at lam_t0; returns lam_{t0 + cnt}.
-double fill_sched(std::vector<Sched>& tab, int cnt, double lam0, double tau1, double eta) {
-    tab.assign((size_t)cnt, Sched{});
+// Fills `cnt` schedule entries of tab[] starting at lam_t0; returns lam_{t0 + cnt}.
+double fill_sched(Sched* tab, int cnt, double lam0, double tau1, double eta) {
     double l0 = lam0;
     for (int k = 0; k < cnt; ++k) {
         double l1 = next_lam(l0, tau1, eta);
         double l2 = next_lam(l1, tau1, eta);
+        tab[k] = Sched{};
         tab[k].lamA = l0;
         tab[k].lamB = l1;
         tab[k].w = tau1 / l1;
@@ -789,6 +799,16 @@ void launch_offsets(const Layout& L, Consts kc, int d, void* ws, hipStream_t st,
                        extreme_parts(L), (const double*)nullptr, 0, at<double>(ws, L.H));
 }
 
+// Owns the captured iteration graph of a solve call: destroyed on every return path.
+struct GraphGuard {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphGuard() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
 struct IterArgs {
     DualBufs buf;
     TraceCols tc;
@@ -842,7 +862,7 @@ void launch_iteration(const lamp_problem* p, const Layout& L, Consts kc, void* w
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, ctrl, sch, kc, p->d, at<double>(ws, L.xc),
                        at<double>(ws, L.yc), at<double2>(ws, L.gtab), p->r, at<double>(ws, L.xn2),
                        at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H), at<RowVar>(ws, L.rowvar),
-                       ia.log_za, ia.log_zb, rf);
+                       at<double2>(ws, L.rowck), ia.log_za, ia.log_zb, rf);
     launch_col_sweep(L, kc, p->d, ws, st);
     hipLaunchKernelGGL(dual_update, grid1(kc.m), dim3(BLOCK), 0, st, ctrl, sch, kc, at<double2>(ws, L.cpart),
                        col_parts(L), p->c, at<double>(ws, L.yn2), ia.buf, at<double2>(ws, L.gtab),
@@ -874,7 +894,7 @@ lamp_status common_setup(const lamp_problem* p, const lamp_params* q, void* ws, 
     if ((e = check_problem(p)) != LAMP_OK) return e;
     if ((e = check_params(q)) != LAMP_OK) return e;
     if ((e = check_ws(p, ws, ws_bytes, q->precision)) != LAMP_OK) return e;
-    if ((e = check_marginals(p)) != LAMP_OK) return e;
+    if ((e = check_marginals(p, st)) != LAMP_OK) return e;
     if ((e = prep(p, ws, st, q->precision)) != LAMP_OK) return e;
     return resolve(p, q, ws, st, R);
 }
@@ -908,11 +928,18 @@ lamp_status state_normalisers(const lamp_problem* p, const lamp_params* q, const
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
                        kc, p->d, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), p->r,
                        at<double>(ws, L.xn2), at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H),
-                       at<RowVar>(ws, L.rowvar), (double*)nullptr, (double*)nullptr,
+                       at<RowVar>(ws, L.rowvar), at<double2>(ws, L.rowck), (double*)nullptr, (double*)nullptr,
                        RowVarF32{nullptr, 0});
     HIPCHK(hipGetLastError());
     *cA_out = 2.0 * R.s * s->inv_eta * LOG2E;
     return LAMP_OK;
+}
+
+// g^A_j = -lam_t LOG2E (s |y~_j|^2 + K nu_j): the column term of X^t's exponents (base 2).
+__global__ void state_col_term(Consts kc, double lam, const double* __restrict__ yn2,
+                               const double* __restrict__ nu, double* __restrict__ gA) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < kc.m) gA[j] = -lam * LOG2E * (kc.s * yn2[j] + kc.K * nu[j]);
 }
 
 __global__ void gA_extract(int64_t m, int64_t par, const double2* __restrict__ gtab2, double* __restrict__ gA) {
@@ -1122,8 +1149,8 @@ lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params*
     }
     run->tau1 = run->R[0].tau1;
     const int64_t t0 = states[0].t;
-    std::vector<Sched> tab;
-    fill_sched(tab, TAB, states[0].inv_eta, run->tau1, q->eta);
+    std::vector<Sched> tab(TAB);
+    fill_sched(tab.data(), TAB, states[0].inv_eta, run->tau1, q->eta);
     HIPCHK(hipMemcpyAsync(at<Sched>(ws, B.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice, st));
     std::vector<Ctrl> hc(count);
     std::vector<Item> items[4];
@@ -1157,6 +1184,7 @@ lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params*
         D.gtab = at<double2>(w, L.gtab);
         D.H = at<double>(w, L.H);
         D.rowvar = at<RowVar>(w, L.rowvar);
+        D.rowck = at<double2>(w, L.rowck);
         D.rpart = at<double2>(w, L.rpart);
         D.cpart = at<double2>(w, L.cpart);
         run->nu1[p] = at<double>(w, L.nu1);
@@ -1308,6 +1336,50 @@ lamp_status batch_tune(const lamp_problem* probs, int count, const lamp_params* 
     *best = best_c;
     return LAMP_OK;
 }
+// One iteration on workspace `ws`; `prob` is canonical.
+lamp_status step_impl(const lamp_problem* prob, const lamp_params* params, lamp_state* state, void* ws,
+                      size_t ws_bytes, hipStream_t st, const lamp_trace* trace, double* res_out) {
+    lamp_status e;
+    if ((e = check_state(state)) != LAMP_OK) return e;
+    Resolved R;
+    if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
+    const Consts kc = make_consts(prob, R);
+    const int64_t t = state->t;
+    Sched tab[1];
+    fill_sched(tab, 1, state->inv_eta, R.tau1, params->eta);
+    HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab, sizeof(Sched), hipMemcpyHostToDevice, st));
+    Ctrl hc;
+    if ((e = upload_ctrl(ws, L, t, t + 1, t, 0.0, st, &hc, state->dt_partial)) != LAMP_OK) return e;
+    IterArgs ia{};
+    ia.track_dt = params->track_dt != 0;
+    ia.buf.nu[t & 1] = state->nu;
+    ia.buf.theta[t & 1] = state->theta;
+    ia.buf.nu[(t + 1) & 1] = at<double>(ws, L.nu1);
+    ia.buf.theta[(t + 1) & 1] = at<double>(ws, L.th1);
+    if (trace) {
+        ia.tc = TraceCols{trace->col_a, trace->col_b, trace->theta_bar, trace->theta_hat};
+        ia.log_za = trace->log_za;
+        ia.log_zb = trace->log_zb;
+    }
+    hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab), gtabf_ptr(L, ws), L.m_pad);
+    launch_offsets(L, kc, prob->d, ws, st);
+    launch_iteration(prob, L, kc, ws, ia, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(state->nu, at<double>(ws, L.nu1), sizeof(double) * kc.m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(state->theta, at<double>(ws, L.th1), sizeof(double) * kc.m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(&hc, at<Ctrl>(ws, L.ctrl), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hc.err) return fail(LAMP_ENUMERIC, "non-finite value in the dual update at t = %lld", (long long)t);
+    if (res_out) *res_out = hc.res_last;
+    state->t = t + 1;
+    state->inv_eta = tab[0].lamB;
+    state->dt_partial = ia.track_dt ? hc.dt_acc : std::numeric_limits<double>::quiet_NaN();
+    return LAMP_OK;
+}
+
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1346,45 +1418,7 @@ lamp_status lamp_step(const lamp_problem* prob, const lamp_params* params, lamp_
                       size_t ws_bytes, void* stream, const lamp_trace* trace, double* res_out) {
     lamp_problem canon_buf;
     prob = canonical(prob, &canon_buf);
-    hipStream_t st = (hipStream_t)stream;
-    lamp_status e;
-    if ((e = check_state(state)) != LAMP_OK) return e;
-    Resolved R;
-    if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
-    const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
-    const Consts kc = make_consts(prob, R);
-    const int64_t t = state->t;
-    std::vector<Sched> tab;
-    fill_sched(tab, 1, state->inv_eta, R.tau1, params->eta);
-    HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched), hipMemcpyHostToDevice, st));
-    Ctrl hc;
-    if ((e = upload_ctrl(ws, L, t, t + 1, t, 0.0, st, &hc, state->dt_partial)) != LAMP_OK) return e;
-    IterArgs ia{};
-    ia.track_dt = params->track_dt != 0;
-    ia.buf.nu[t & 1] = state->nu;
-    ia.buf.theta[t & 1] = state->theta;
-    ia.buf.nu[(t + 1) & 1] = at<double>(ws, L.nu1);
-    ia.buf.theta[(t + 1) & 1] = at<double>(ws, L.th1);
-    if (trace) {
-        ia.tc = TraceCols{trace->col_a, trace->col_b, trace->theta_bar, trace->theta_hat};
-        ia.log_za = trace->log_za;
-        ia.log_zb = trace->log_zb;
-    }
-    hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
-                       kc, at<double>(ws, L.yn2), state->nu, state->theta, at<double2>(ws, L.gtab), gtabf_ptr(L, ws), L.m_pad);
-    launch_offsets(L, kc, prob->d, ws, st);
-    launch_iteration(prob, L, kc, ws, ia, st);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(state->nu, at<double>(ws, L.nu1), sizeof(double) * kc.m, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(state->theta, at<double>(ws, L.th1), sizeof(double) * kc.m, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(&hc, at<Ctrl>(ws, L.ctrl), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (hc.err) return fail(LAMP_ENUMERIC, "non-finite value in the dual update at t = %lld", (long long)t);
-    if (res_out) *res_out = hc.res_last;
-    state->t = t + 1;
-    state->inv_eta = tab[0].lamB;
-    state->dt_partial = ia.track_dt ? hc.dt_acc : std::numeric_limits<double>::quiet_NaN();
-    return LAMP_OK;
+    return step_impl(prob, params, state, ws, ws_bytes, (hipStream_t)stream, trace, res_out);
 }
 
 lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp_state* state, void* ws,
@@ -1426,10 +1460,10 @@ lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp
     ia.buf.nu[(t0 + 1) & 1] = at<double>(ws, L.nu1);
     ia.buf.theta[(t0 + 1) & 1] = at<double>(ws, L.th1);
 
-    std::vector<Sched> tab;
+    std::vector<Sched> tab(TAB);
     double lam_epoch = state->inv_eta;   // lam at t_base of the current epoch
     int64_t t_base = t0;
-    double lam_next_epoch = fill_sched(tab, TAB, lam_epoch, R.tau1, params->eta);
+    double lam_next_epoch = fill_sched(tab.data(), TAB, lam_epoch, R.tau1, params->eta);
     HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice, st));
     Ctrl hc;
     int64_t t_end = std::min(t_stop, t_base + TAB);
@@ -1442,21 +1476,20 @@ lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp
 
     // capture K iterations once; the kernels read t, the schedule and the stop flag
     // from device memory, so the same graph is replayed for every chunk
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    GraphGuard gg;
     if (t_stop > t0) {
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < K; ++k) launch_iteration(prob, L, kc, ws, ia, st);
-        hipError_t ce = hipStreamEndCapture(st, &graph);
+        hipError_t ce = hipStreamEndCapture(st, &gg.graph);
         if (ce != hipSuccess) return fail(LAMP_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce));
-        HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HIPCHK(hipGraphInstantiate(&gg.exec, gg.graph, nullptr, nullptr, 0));
     }
     int64_t t_cur = t0;
     lamp_status result = LAMP_OK;
     while (t_cur < t_stop) {
         // two chunks in flight: the kernels of a chunk that starts after the stop exit at once
-        HIPCHK(hipGraphLaunch(exec, st));
-        HIPCHK(hipGraphLaunch(exec, st));
+        HIPCHK(hipGraphLaunch(gg.exec, st));
+        HIPCHK(hipGraphLaunch(gg.exec, st));
         HIPCHK(hipMemcpyAsync(&hc, at<Ctrl>(ws, L.ctrl), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (hc.err) {
@@ -1468,23 +1501,23 @@ lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp
             t_cur = hc.t_done;
             break;
         }
-        if (hc.t == t_cur && hc.t < hc.t_end)
-            return fail(LAMP_EDEVICE, "iteration counter did not advance past t = %lld", (long long)t_cur);
+        if (hc.t == t_cur && hc.t < hc.t_end) {
+            result = fail(LAMP_EDEVICE, "iteration counter did not advance past t = %lld", (long long)t_cur);
+            break;
+        }
         t_cur = hc.t;
         if (t_cur >= t_stop) break;
         if (t_cur >= hc.t_end) {
             // new schedule epoch
             t_base = t_cur;
             lam_epoch = lam_next_epoch;
-            lam_next_epoch = fill_sched(tab, TAB, lam_epoch, R.tau1, params->eta);
+            lam_next_epoch = fill_sched(tab.data(), TAB, lam_epoch, R.tau1, params->eta);
             HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice, st));
             hc.t_end = std::min(t_stop, t_base + TAB);
             hc.t_base = t_base;
             HIPCHK(hipMemcpyAsync(at<Ctrl>(ws, L.ctrl), &hc, sizeof(Ctrl), hipMemcpyHostToDevice, st));
         }
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     // the iterate of t_cur lives in buffer t_cur & 1
     if (t_cur != t0 && (t_cur & 1) != (t0 & 1)) {
         HIPCHK(hipMemcpyAsync(state->nu, at<double>(ws, L.nu1), sizeof(double) * kc.m, hipMemcpyDeviceToDevice, st));
@@ -1676,11 +1709,11 @@ lamp_status lamp_backward(const lamp_problem* prob, const lamp_params* params, c
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
     const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
     const Consts kc = make_consts(prob, R);
-    double cA = 0.0;
-    if ((e = state_normalisers(prob, params, R, state, ws, st, &cA)) != LAMP_OK) return e;
+    // one pass: the sweep keeps its own per-row offsets and divides by the row sums at the end
+    const double cA = 2.0 * R.s * state->inv_eta * LOG2E;
     double* gA = at<double>(ws, L.scratch);
-    hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
-                       at<double2>(ws, L.gtab), gA);
+    hipLaunchKernelGGL(state_col_term, grid1(kc.m), dim3(BLOCK), 0, st, kc, state->inv_eta, at<double>(ws, L.yn2),
+                       state->nu, gA);
     launch_adjoint(L, kc, prob->d, ws, cA, gA, st);
     hipLaunchKernelGGL(adjoint_finish, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, (int)L.P_r,
                        grad_out * 2.0 * R.s, at<double>(ws, L.xc), prob->r, at<double>(ws, L.rpart), grad_x);
@@ -1744,9 +1777,9 @@ lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
     const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
     const Consts kc = make_consts(prob, R);
-    std::vector<Sched> tab;
+    Sched tab[1];
     fill_sched(tab, 1, state->inv_eta, R.tau1, params->eta);
-    HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab.data(), sizeof(Sched), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<Sched>(ws, L.sched), tab, sizeof(Sched), hipMemcpyHostToDevice, st));
     Ctrl hc;
     if ((e = upload_ctrl(ws, L, state->t, state->t + 1, state->t, 0.0, st, &hc)) != LAMP_OK) return e;
     hipLaunchKernelGGL(col_table_init, grid1(kc.m), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
@@ -1756,7 +1789,7 @@ lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched), kc,
                        prob->d, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double2>(ws, L.gtab), prob->r,
                        at<double>(ws, L.xn2), at<double2>(ws, L.rpart), row_parts(L), at<double>(ws, L.H),
-                       at<RowVar>(ws, L.rowvar), (double*)nullptr, (double*)nullptr,
+                       at<RowVar>(ws, L.rowvar), at<double2>(ws, L.rowck), (double*)nullptr, (double*)nullptr,
                        is_mfma(L.prec) ? rowvar_f32(L, ws) : RowVarF32{nullptr, 0});
     HIPCHK(hipGetLastError());
     hipEvent_t ev[4];
@@ -1774,6 +1807,34 @@ lamp_status lamp_sweep_times(const lamp_problem* prob, const lamp_params* params
     for (auto& x : ev) (void)hipEventDestroy(x);
     if (row_ms) *row_ms = a / reps;
     if (col_ms) *col_ms = b / reps;
+    return LAMP_OK;
+}
+
+lamp_status lamp_exp_rate(void* stream, int32_t blocks, int32_t iters, int32_t reps, double* exp_per_s) {
+    if (blocks < 1 || iters < 1 || reps < 1 || !exp_per_s)
+        return fail(LAMP_EINVAL, "blocks, iters and reps must be >= 1 and exp_per_s non-NULL");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    struct EventGuard {
+        hipEvent_t a, b;
+        ~EventGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } eg{e0, e1};
+    hipLaunchKernelGGL(exp_rate_probe, dim3((unsigned)blocks), dim3(256), 0, st, iters, 0.5f, (float*)nullptr);
+    HIPCHK(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(exp_rate_probe, dim3((unsigned)blocks), dim3(256), 0, st, iters, 0.5f, (float*)nullptr);
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    const double exps = (double)reps * blocks * 256.0 * (double)iters * EXP_PROBE_CHAINS;
+    *exp_per_s = exps / (ms * 1e-3);
     return LAMP_OK;
 }
 
@@ -1802,7 +1863,6 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
         if ((e = check_state(&states[p])) != LAMP_OK) return e;
         if (states[p].t != states[0].t || states[p].inv_eta != states[0].inv_eta)
             return fail(LAMP_EINVAL, "batched states must share t and inv_eta (problem %d differs)", p);
-        if ((e = check_marginals(&probs[p])) != LAMP_OK) return e;
     }
     if (!ws) return fail(LAMP_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(LAMP_EINVAL, "workspace must be 256-byte aligned");
@@ -1824,6 +1884,8 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
             }
         }
     } guard{own};
+    for (int p = 0; p < count; ++p)
+        if ((e = check_marginals(&probs[p], st)) != LAMP_OK) return e;
 
     int cand = 0;
     if ((e = batch_tune(probs, count, params, states, ws, st, &cand)) != LAMP_OK) return e;
@@ -1833,27 +1895,26 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
     if ((e = batch_setup(probs, count, params, states, ws, st, cand, t_stop, &run)) != LAMP_OK) return e;
     const BatchPlan& B = run.B;
     const int K = params->check_every > 0 ? params->check_every : 64;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    GraphGuard gg;
     if (t_stop > t0) {
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < K; ++k) batch_iteration(run, ws, st);
-        hipError_t ce = hipStreamEndCapture(st, &graph);
+        hipError_t ce = hipStreamEndCapture(st, &gg.graph);
         if (ce != hipSuccess) return fail(LAMP_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce));
-        HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HIPCHK(hipGraphInstantiate(&gg.exec, gg.graph, nullptr, nullptr, 0));
     }
     std::vector<Ctrl> hc(count);
     std::vector<char> active(count, 1);
     Ctrl* hc_dev = at<Ctrl>(ws, B.ctrlv);
     double lam_epoch = states[0].inv_eta;
     int64_t t_base = t0;
-    std::vector<Sched> tab;
-    double lam_next_epoch = fill_sched(tab, TAB, lam_epoch, run.tau1, params->eta);
+    std::vector<Sched> tab(TAB);
+    double lam_next_epoch = fill_sched(tab.data(), TAB, lam_epoch, run.tau1, params->eta);
     int64_t t_cur = t0;
     lamp_status result = LAMP_OK;
     while (t_cur < t_stop) {
-        HIPCHK(hipGraphLaunch(exec, st));
-        HIPCHK(hipGraphLaunch(exec, st));
+        HIPCHK(hipGraphLaunch(gg.exec, st));
+        HIPCHK(hipGraphLaunch(gg.exec, st));
         HIPCHK(hipMemcpyAsync(hc.data(), hc_dev, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         bool all_done = true, any_err = false, newly_done = false;
@@ -1873,17 +1934,22 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
             break;
         }
         if (all_done) break;
-        if (tmax == t_cur) return fail(LAMP_EDEVICE, "batched iteration counter did not advance past %lld",
-                                       (long long)t_cur);
+        if (tmax == t_cur) {
+            result = fail(LAMP_EDEVICE, "batched iteration counter did not advance past %lld", (long long)t_cur);
+            break;
+        }
         t_cur = tmax;
         if (t_cur >= t_stop) break;
         // problems that stopped leave the sweep work lists (no graph change: the kernels read
         // the item counts from device memory)
-        if (newly_done && (e = batch_upload_sweeps(&run, active, ws, st)) != LAMP_OK) return e;
+        if (newly_done && (e = batch_upload_sweeps(&run, active, ws, st)) != LAMP_OK) {
+            result = e;
+            break;
+        }
         if (t_cur >= t_base + TAB) {
             t_base = t_cur;
             lam_epoch = lam_next_epoch;
-            lam_next_epoch = fill_sched(tab, TAB, lam_epoch, run.tau1, params->eta);
+            lam_next_epoch = fill_sched(tab.data(), TAB, lam_epoch, run.tau1, params->eta);
             HIPCHK(hipMemcpyAsync(at<Sched>(ws, B.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice,
                                   st));
             hipLaunchKernelGGL(set_epoch, dim3(cdiv(count, 64)), dim3(64), 0, st, at<ProbDesc>(ws, B.descs), count,
@@ -1891,8 +1957,6 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
             HIPCHK(hipStreamSynchronize(st));
         }
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     HIPCHK(hipMemcpyAsync(hc.data(), hc_dev, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();

@@ -21,6 +21,7 @@ struct ProbDesc {
     double2* gtab;
     double* H;
     RowVar* rowvar;
+    double2* rowck;
     double2* rpart;
     double2* cpart;
     DualBufs buf;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void batch_row_finish(const ProbDesc* __rest
         const Item it = items[k];
         const ProbDesc& P = pd[it.prob];
         row_finish_body(P.ctrl, sched, P.kc, P.d, P.xc, P.yc, P.gtab, P.r, P.xn2, P.rpart, P.P_r, P.H, P.rowvar,
-                        nullptr, nullptr, RowVarF32{nullptr, 0}, it.bx, it.by, 0);
+                        P.rowck, nullptr, nullptr, RowVarF32{nullptr, 0}, it.bx, it.by, 0);
     }
 }
 
@@ -120,11 +121,13 @@ __global__ __launch_bounds__(BLOCK) void batch_col_sweep(const ProbDesc* __restr
         const double* yc = as_global(P.yc);
         const double2* gtab = as_global(P.gtab);
         const RowVar* rowvar = as_const(P.rowvar);
+        const double2* rowck = as_const(P.rowck);
         double2* cpart = as_global(P.cpart);
         if constexpr (D > 0)
-            col_sweep_body<METRIC_SQEUCLID, D>(ctrl, sched, P.kc, xc, yc, gtab, rowvar, cpart, P.split_c, it.bx, it.by, 0);
+            col_sweep_body<METRIC_SQEUCLID, D>(ctrl, sched, P.kc, xc, yc, gtab, rowvar, rowck, cpart, P.split_c, it.bx,
+                                               it.by, 0);
         else
-            col_sweep_dyn_body(ctrl, sched, P.kc, P.d, xc, yc, gtab, rowvar, cpart, P.split_c, it.bx, it.by, 0);
+            col_sweep_dyn_body(ctrl, sched, P.kc, P.d, xc, yc, gtab, rowvar, rowck, cpart, P.split_c, it.bx, it.by, 0);
     }
 }
 

@@ -522,7 +522,7 @@ __device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, 
                            const double* __restrict__ xc, const double* __restrict__ yc,
                            const double2* __restrict__ gtab2, const double* __restrict__ r,
                            const double* __restrict__ xn2, const double2* __restrict__ part, int P,
-                           double* __restrict__ H, RowVar* __restrict__ rowvar,
+                           double* __restrict__ H, RowVar* __restrict__ rowvar, double2* __restrict__ rowck,
                            double* __restrict__ log_za, double* __restrict__ log_zb, RowVarF32 rf, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
     int64_t i = (int64_t)bx_ * blockDim.x + threadIdx.x;
@@ -559,6 +559,9 @@ __device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, 
     rv.wA = (float)(r[i] * exp2(ew));
     rv.wB = (float)r[i];
     rowvar[i] = rv;
+    // the vector-ALU column sweep takes the A coupling's row factor 2^ew in its exponent
+    // (unclamped: no FP32 weight to overflow), both couplings weighted by r_i
+    if (rowck) rowck[i] = make_double2(cA * hnew + (rho * sigB - sigA), cB * hnew);
     if (rf.q) {
         const float kf = (float)hnew;
         const double dk = hnew - (double)kf;
@@ -574,31 +577,56 @@ __global__ void row_finish(Ctrl* ctrl, const Sched* sched, Consts kc, int D,
                            const double* __restrict__ xc, const double* __restrict__ yc,
                            const double2* __restrict__ gtab2, const double* __restrict__ r,
                            const double* __restrict__ xn2, const double2* __restrict__ part, int P,
-                           double* __restrict__ H, RowVar* __restrict__ rowvar,
+                           double* __restrict__ H, RowVar* __restrict__ rowvar, double2* __restrict__ rowck,
                            double* __restrict__ log_za, double* __restrict__ log_zb, RowVarF32 rf) {
-    row_finish_body(ctrl, sched, kc, D, xc, yc, gtab2, r, xn2, part, P, H, rowvar, log_za, log_zb, rf, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    row_finish_body(ctrl, sched, kc, D, xc, yc, gtab2, r, xn2, part, P, H, rowvar, rowck, log_za, log_zb, rf, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
 // Column sweep: col^A_j, col^B_j.  cpart: [P][m] double2.
 // ---------------------------------------------------------------------------
-// One row i of the column sweep for this lane's column: w^A 2^eA, w^B 2^eB are
-// accumulated with the row weights as the scalar multiplicand.
-template <int M, int D>
-__device__ __forceinline__ void col_terms(const double (&y)[D], const double* __restrict__ xi, RowVar rv,
-                                          double gA, double gB, double cA, double cB, float& accA,
-                                          float& accB) {
-    double dot;
-    if constexpr (M == METRIC_SQEUCLID) {
-        dot = y[0] * xi[0];
+// One row i of the column sweep for this lane's column.  With k_i the row's offset,
+// ew_i = rho sigma^B_i - sigma^A_i the A coupling's row factor and G_j = g^B_j / cfac^B this
+// column's term, the base-2 exponents of the normalised couplings are
+//     e^B = cfac^B (P_ij + G_j) + cfac^B k_i,
+//     e^A = cfac^A (P_ij + G_j) + (cfac^A k_i + ew_i) + D_j,   D_j = g^A_j - cfac^A G_j:
+// the dot product starts from G_j (per lane), the row terms come precomputed (rowck,
+// scalar), and D_j, constant down the column, is applied once to the column's A sum
+// (`factor`) or added to each exponent.  Both are weighted by r_i, the scalar multiplicand.
+template <int M, int D, bool FACTOR>
+__device__ __forceinline__ void col_terms(const double (&y)[D], const double* __restrict__ xi, double2 ck,
+                                          float w, double G, double Dj, double cA, double cB,
+                                          float& accA, float& accB) {
+    const double dot = pair_term<M, D>(y, xi, G);   // the distances are symmetric
+    double eA = fma_su(dot, cA, ck.x);
+    if constexpr (!FACTOR) eA += Dj;
+    accA = fmaf(w, fexp2(eA), accA);
+    accB = fmaf(w, fexp2(fma_su(dot, cB, ck.y)), accB);
+}
+
+template <int M, int D, bool FACTOR>
+__device__ __forceinline__ void col_sweep_run(double cA, double cB, const double (&y)[D], double G, double Dj,
+                                              const double* __restrict__ xc, const RowVar* __restrict__ rowvar,
+                                              const double2* __restrict__ rowck, int64_t i0, int64_t i1,
+                                              double& sumA, double& sumB) {
+    const int nfull = (int)((i1 - i0) / UNROLL);
+    const double* __restrict__ xp = xc + i0 * D;
+    const RowVar* __restrict__ rp = rowvar + i0;
+    const double2* __restrict__ kp = rowck + i0;
+    for (int c = 0; c < nfull; ++c, xp += UNROLL * D, rp += UNROLL, kp += UNROLL) {
+        float accA = 0.f, accB = 0.f;
 #pragma unroll
-        for (int k = 1; k < D; ++k) dot = fma(y[k], xi[k], dot);
-    } else {
-        dot = pair_term<M, D>(y, xi, 0.0);   // the distances are symmetric
+        for (int u = 0; u < UNROLL; ++u)
+            col_terms<M, D, FACTOR>(y, xp + u * D, kp[u], rp[u].wB, G, Dj, cA, cB, accA, accB);
+        sumA += (double)accA;
+        sumB += (double)accB;
     }
-    dot = dot + rv.k;
-    accA = fmaf(rv.wA, fexp2(fma(dot, cA, gA)), accA);
-    accB = fmaf(rv.wB, fexp2(fma(dot, cB, gB)), accB);
+    const int rem = (int)((i1 - i0) - (int64_t)nfull * UNROLL);
+    float accA = 0.f, accB = 0.f;
+    for (int u = 0; u < rem; ++u)
+        col_terms<M, D, FACTOR>(y, xp + u * D, kp[u], rp[u].wB, G, Dj, cA, cB, accA, accB);
+    sumA += (double)accA;
+    sumB += (double)accB;
 }
 
 template <int M, int D>
@@ -607,6 +635,7 @@ __device__ __forceinline__ void col_sweep_body(const Ctrl* ctrl, const Sched* sc
                                                    const double* __restrict__ yc,
                                                    const double2* __restrict__ gtab2,
                                                    const RowVar* __restrict__ rowvar,
+                                                   const double2* __restrict__ rowck,
                                                    double2* __restrict__ cpart, int64_t split, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
@@ -622,24 +651,15 @@ __device__ __forceinline__ void col_sweep_body(const Ctrl* ctrl, const Sched* sc
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = yc[jj * D + k];
     const double2 g = gtab2[(t & 1) * kc.m + jj];
+    const double G = g.y / cB;
+    const double Dj = g.x - cA * G;
 
     double sumA = 0.0, sumB = 0.0;
-    const int nfull = (int)((i1 - i0) / UNROLL);
-    const double* __restrict__ xp = xc + i0 * D;
-    const RowVar* __restrict__ rp = rowvar + i0;
-    for (int c = 0; c < nfull; ++c, xp += UNROLL * D, rp += UNROLL) {
-        float accA = 0.f, accB = 0.f;
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) col_terms<M, D>(y, xp + u * D, rp[u], g.x, g.y, cA, cB, accA, accB);
-        sumA += (double)accA;
-        sumB += (double)accB;
-    }
-    {
-        const int rem = (int)((i1 - i0) - (int64_t)nfull * UNROLL);
-        float accA = 0.f, accB = 0.f;
-        for (int u = 0; u < rem; ++u) col_terms<M, D>(y, xp + u * D, rp[u], g.x, g.y, cA, cB, accA, accB);
-        sumA += (double)accA;
-        sumB += (double)accB;
+    if (kc.factor_cols) {
+        col_sweep_run<M, D, true>(cA, cB, y, G, Dj, xc, rowvar, rowck, i0, i1, sumA, sumB);
+        sumA *= exp2(Dj);
+    } else {
+        col_sweep_run<M, D, false>(cA, cB, y, G, Dj, xc, rowvar, rowck, i0, i1, sumA, sumB);
     }
     if (j < kc.m) cpart[p * kc.m + j] = make_double2(sumA, sumB);
 }
@@ -650,8 +670,9 @@ __global__ __launch_bounds__(BLOCK) void col_sweep(const Ctrl* ctrl, const Sched
                                                    const double* __restrict__ yc,
                                                    const double2* __restrict__ gtab2,
                                                    const RowVar* __restrict__ rowvar,
+                                                   const double2* __restrict__ rowck,
                                                    double2* __restrict__ cpart, int64_t split) {
-    col_sweep_body<M, D>(ctrl, sched, kc, xc, yc, gtab2, rowvar, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    col_sweep_body<M, D>(ctrl, sched, kc, xc, yc, gtab2, rowvar, rowck, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 __device__ __forceinline__ void col_sweep_dyn_body(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
@@ -659,6 +680,7 @@ __device__ __forceinline__ void col_sweep_dyn_body(const Ctrl* ctrl, const Sched
                                                        const double* __restrict__ yc,
                                                        const double2* __restrict__ gtab2,
                                                        const RowVar* __restrict__ rowvar,
+                                                       const double2* __restrict__ rowck,
                                                        double2* __restrict__ cpart, int64_t split, int64_t bx_, int64_t by_, int64_t nb_) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
@@ -671,19 +693,25 @@ __device__ __forceinline__ void col_sweep_dyn_body(const Ctrl* ctrl, const Sched
     const int64_t i1 = min(kc.n, i0 + split);
     const int64_t jj = j < kc.m ? j : kc.m - 1;
     const double2 g = gtab2[(t & 1) * kc.m + jj];
+    const double G = g.y / cB;   // the exponent assembly of col_terms
+    const double Dj = g.x - cA * G;
     double sumA = 0.0, sumB = 0.0;
     for (int64_t ib = i0; ib < i1; ib += UNROLL) {
         float accA = 0.f, accB = 0.f;
         const int64_t ie = min(i1, ib + UNROLL);
         for (int64_t i = ib; i < ie; ++i) {
-            const RowVar rv = rowvar[i];
-            const double dot = pair_term_dyn(kc, D, yc + jj * D, xc + i * D, rv.k);
-            accA = fmaf(rv.wA, fexp2(fma(cA, dot, g.x)), accA);
-            accB = fmaf(rv.wB, fexp2(fma(cB, dot, g.y)), accB);
+            const float w = rowvar[i].wB;
+            const double2 ck = rowck[i];
+            const double dot = pair_term_dyn(kc, D, yc + jj * D, xc + i * D, G);
+            double eA = fma(dot, cA, ck.x);
+            if (!kc.factor_cols) eA += Dj;
+            accA = fmaf(w, fexp2(eA), accA);
+            accB = fmaf(w, fexp2(fma(dot, cB, ck.y)), accB);
         }
         sumA += (double)accA;
         sumB += (double)accB;
     }
+    if (kc.factor_cols) sumA *= exp2(Dj);
     if (j < kc.m) cpart[p * kc.m + j] = make_double2(sumA, sumB);
 }
 
@@ -692,8 +720,9 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_dyn(const Ctrl* ctrl, const S
                                                        const double* __restrict__ yc,
                                                        const double2* __restrict__ gtab2,
                                                        const RowVar* __restrict__ rowvar,
+                                                       const double2* __restrict__ rowck,
                                                        double2* __restrict__ cpart, int64_t split) {
-    col_sweep_dyn_body(ctrl, sched, kc, D, xc, yc, gtab2, rowvar, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    col_sweep_dyn_body(ctrl, sched, kc, D, xc, yc, gtab2, rowvar, rowck, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1223,22 +1252,55 @@ __global__ void col_products(Consts kc, const double* __restrict__ c, const doub
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint sweep (envelope gradient): per row i, with p_ij = 2^(cfac (h_i + P_ij) + g_j),
-// partial sums S0_i, S1_i (d values) such that grad_i = 2 s r_i (S0_i x~_i - S1_i):
-//   squared Euclidean (dC/dx = 2 s (x - y)):  S0 = sum_j p_ij,  S1 = sum_j p_ij y~_j;
-//   l1 (dC/dx_k = s sign(x_k - y_k)):       S0 = 0,  S1_k = -1/2 sum_j p_ij sign(x_k - y_jk);
+// Adjoint sweep (envelope gradient), one pass over the pairs: per row i and column split p,
+// with unnormalised weights q_ij = 2^(cfac P_ij + g_j - M_ip) (g_j = g^A_j of X^t), the
+// partial sums Z_ip = sum_j q_ij and S1_ip (d values) and the split's offset M_ip, an
+// integer that each lane raises to ceil(max e) whenever a block of columns exceeds it
+// (the first block sets it), so every term is at most 1 and a raise rescales the sums
+// exactly by a power of two.  grad_i = 2 s r_i (c_x Z_i x~_i - S1_i) / Z_i, the
+// normaliser cancelling in the ratio:
+//   squared Euclidean (dC/dx = 2 s (x - y)):  c_x = 1, S1 = sum_j q_ij y~_j;
+//   l1 (dC/dx_k = s sign(x_k - y_k)):       c_x = 0, S1_k = -1/2 sum_j q_ij sign(x_k - y_jk);
 //   l_inf (the coordinate k* of the largest |x_k - y_k|, the first one on ties):
-//                                           S0 = 0,  S1_k = -1/2 sum_j p_ij sign(x_k - y_jk) [k = k*].
-// (sign(0) = 0: the subgradient at a kink.)  part: [P][n][D+1] partial sums over column splits.
+//                                           c_x = 0, S1_k = -1/2 sum_j q_ij sign(x_k - y_jk) [k = k*].
+// (sign(0) = 0: the subgradient at a kink.)  part: [P][n][D+2] = (M, Z, S1).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float sgnf(double v) { return v > 0.0 ? 1.f : (v < 0.0 ? -1.f : 0.f); }
+
+// Accumulates one column's weight q into the FP32 block sums of the adjoint.
+template <int M, int D>
+__device__ __forceinline__ void adjoint_accumulate(const double (&x)[D], const double* __restrict__ yj,
+                                                   const float* __restrict__ yjf, float q, float& a0,
+                                                   float (&a1)[D]) {
+    a0 += q;
+    if constexpr (M == METRIC_SQEUCLID) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) a1[k] = fmaf(q, yjf[k], a1[k]);
+    } else if constexpr (M == METRIC_L1) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) a1[k] = fmaf(-0.5f * q, sgnf(x[k] - yj[k]), a1[k]);
+    } else {
+        int ks = 0;
+        double best = -1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double t = fabs(x[k] - yj[k]);
+            if (t > best) {
+                best = t;
+                ks = k;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            if (k == ks) a1[k] = fmaf(-0.5f * q, sgnf(x[k] - yj[k]), a1[k]);
+    }
+}
 
 template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, const double* __restrict__ xc,
                                                        const double* __restrict__ yc,
                                                        const float* __restrict__ ycf,
                                                        const double* __restrict__ gA,
-                                                       const double* __restrict__ H,
                                                        double* __restrict__ part, int64_t split) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t p = blockIdx.y;
@@ -1248,60 +1310,79 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, con
     double x[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = xc[ii * D + k];
-    const double h = H[ii];
+    double off = 0.0;      // M: integer offset of this lane's exponents
+    double h = 0.0;        // -M / cfac, the dot products' initial value
+    bool first = true;
     double s0 = 0.0, s1[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) s1[k] = 0.0;
-    // one column's contribution to the FP32 block sums
-    auto term = [&](int64_t j, float& a0, float (&a1)[D]) {
-        const double dot = pair_term<M, D>(x, yc + j * D, h);
-        const float pij = fexp2(fma(cA, dot, gA[j]));
-        if constexpr (M == METRIC_SQEUCLID) {
-            a0 += pij;
+    // raise the offset by ceil(bm) (bm: the largest exponent under the current offset),
+    // rescaling the sums exactly; returns the raise
+    auto raise = [&](double bm) {
+        const double sh = ceil(bm);
+        s0 = ldexp(s0, -(int)sh);
 #pragma unroll
-            for (int k = 0; k < D; ++k) a1[k] = fmaf(pij, ycf[j * D + k], a1[k]);
-        } else if constexpr (M == METRIC_L1) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) a1[k] = fmaf(-0.5f * pij, sgnf(x[k] - yc[j * D + k]), a1[k]);
-        } else {
-            int ks = 0;
-            double best = -1.0;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const double t = fabs(x[k] - yc[j * D + k]);
-                if (t > best) {
-                    best = t;
-                    ks = k;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-                if (k == ks) a1[k] = fmaf(-0.5f * pij, sgnf(x[k] - yc[j * D + k]), a1[k]);
-        }
+        for (int k = 0; k < D; ++k) s1[k] = ldexp(s1[k], -(int)sh);
+        off += sh;
+        h = -off / cA;
+        return sh;
     };
     // blocks of UNROLL columns with a compile-time trip count (the column data are
-    // wave-uniform scalar loads, issued together), then the remainder
+    // wave-uniform scalar loads, issued together); the offset is checked once per block
     const int64_t nfull = (j1 - j0) / UNROLL;
-    for (int64_t c = 0; c <= nfull; ++c) {
-        const int64_t jb = j0 + c * UNROLL;
+    const double* __restrict__ yp = yc + j0 * D;
+    const float* __restrict__ yfp = ycf + j0 * D;
+    const double* __restrict__ gp = gA + j0;
+    for (int64_t c = 0; c < nfull; ++c, yp += UNROLL * D, yfp += UNROLL * D, gp += UNROLL) {
+        double e[UNROLL];
+        float ef[UNROLL];
+        float bm = -__builtin_inff();
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            e[u] = fma_su(pair_term<M, D>(x, yp + u * D, h), cA, gp[u]);
+            ef[u] = (float)e[u];
+            bm = fmaxf(bm, ef[u]);
+        }
+        if (first || bm > 0.f) {   // rare after the first block
+            double bmd = e[0];
+#pragma unroll
+            for (int u = 1; u < UNROLL; ++u) bmd = fmax(bmd, e[u]);
+            const double sh = raise(bmd);
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) ef[u] = (float)(e[u] - sh);
+            first = false;
+        }
         float a0 = 0.f, a1[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) a1[k] = 0.f;
-        if (c < nfull) {
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) term(jb + u, a0, a1);
-        } else {
-            for (int64_t j = jb; j < j1; ++j) term(j, a0, a1);
+        for (int u = 0; u < UNROLL; ++u)
+            adjoint_accumulate<M, D>(x, yp + u * D, yfp + u * D, __builtin_amdgcn_exp2f(ef[u]), a0, a1);
+        s0 += (double)a0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s1[k] += (double)a1[k];
+    }
+    // the remaining columns one at a time
+    for (int64_t j = j0 + nfull * UNROLL; j < j1; ++j) {
+        double e = fma_su(pair_term<M, D>(x, yc + j * D, h), cA, gA[j]);
+        if (first || e > 0.0) {
+            e -= raise(e);
+            first = false;
         }
+        float a0 = 0.f, a1[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) a1[k] = 0.f;
+        adjoint_accumulate<M, D>(x, yc + j * D, ycf + j * D, fexp2(e), a0, a1);
         s0 += (double)a0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s1[k] += (double)a1[k];
     }
     if (i < kc.n) {
-        double* o = part + (p * kc.n + i) * (D + 1);
-        o[0] = s0;
+        double* o = part + (p * kc.n + i) * (D + 2);
+        o[0] = first ? -__builtin_inf() : off;   // an empty split contributes nothing
+        o[1] = s0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) o[1 + k] = s1[k];
+        for (int k = 0; k < D; ++k) o[2 + k] = s1[k];
     }
 }
 
@@ -1310,29 +1391,32 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep_dyn(Consts kc, int D, dou
                                                            const double* __restrict__ yc,
                                                            const float* __restrict__ ycf,
                                                            const double* __restrict__ gA,
-                                                           const double* __restrict__ H,
                                                            double* __restrict__ part, int64_t split) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t p = blockIdx.y;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
-    const int64_t ii = i < kc.n ? i : kc.n - 1;
-    const double h = H[ii];
-    const double* xi = xc + ii * D;
-    double* o = part + (p * kc.n + ii) * (D + 1);
-    double s0 = 0.0;
-    if (i < kc.n)
-        for (int k = 0; k < D; ++k) o[1 + k] = 0.0;
+    if (i >= kc.n) return;
+    const double* xi = xc + i * D;
+    double* o = part + (p * kc.n + i) * (D + 2);
+    for (int k = 0; k < D; ++k) o[2 + k] = 0.0;
+    double off = -__builtin_inf(), s0 = 0.0;
     for (int64_t j = j0; j < j1; ++j) {
         const double* yj = yc + j * D;
-        const double pij = (double)fexp2(fma(cA, pair_term_dyn(kc, D, xi, yj, h), gA[j]));
+        double e = fma(cA, pair_term_dyn(kc, D, xi, yj, 0.0), gA[j]);
+        if (e > off) {   // raise the offset to ceil(e), rescaling the sums exactly
+            const double nm = ceil(e);
+            const int sh = j == j0 ? 0 : (int)(off - nm);
+            s0 = ldexp(s0, sh);
+            for (int k = 0; k < D; ++k) o[2 + k] = ldexp(o[2 + k], sh);
+            off = nm;
+        }
+        const double q = (double)fexp2(e - off);
+        s0 += q;
         if (kc.metric == METRIC_SQEUCLID) {
-            s0 += pij;
-            if (i < kc.n)
-                for (int k = 0; k < D; ++k) o[1 + k] += pij * (double)ycf[j * D + k];
+            for (int k = 0; k < D; ++k) o[2 + k] += q * (double)ycf[j * D + k];
         } else if (kc.metric == METRIC_L1) {
-            if (i < kc.n)
-                for (int k = 0; k < D; ++k) o[1 + k] += -0.5 * pij * (double)sgnf(xi[k] - yj[k]);
+            for (int k = 0; k < D; ++k) o[2 + k] += -0.5 * q * (double)sgnf(xi[k] - yj[k]);
         } else {
             int ks = 0;
             double best = -1.0;
@@ -1343,10 +1427,11 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep_dyn(Consts kc, int D, dou
                     ks = k;
                 }
             }
-            if (i < kc.n) o[1 + ks] += -0.5 * pij * (double)sgnf(xi[ks] - yj[ks]);
+            o[2 + ks] += -0.5 * q * (double)sgnf(xi[ks] - yj[ks]);
         }
     }
-    if (i < kc.n) o[0] = s0;
+    o[0] = off;
+    o[1] = s0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1492,12 +1577,23 @@ __global__ void adjoint_finish(Consts kc, int D, int P, double scale, const doub
                                float* __restrict__ grad) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
+    const int W = D + 2;
+    double off = -__builtin_inf();
+    for (int p = 0; p < P; ++p) off = fmax(off, part[((int64_t)p * kc.n + i) * W]);
+    // split p's sums are scaled by 2^-M_p: bring them to the common offset (exact)
     double s0 = 0.0;
-    for (int p = 0; p < P; ++p) s0 += part[((int64_t)p * kc.n + i) * (D + 1)];
+    for (int p = 0; p < P; ++p) {
+        const double* o = part + ((int64_t)p * kc.n + i) * W;
+        if (o[0] > -__builtin_inf()) s0 += ldexp(o[1], (int)(o[0] - off));
+    }
+    const double cx = kc.metric == METRIC_SQEUCLID ? 1.0 : 0.0;
     for (int k = 0; k < D; ++k) {
         double s1 = 0.0;
-        for (int p = 0; p < P; ++p) s1 += part[((int64_t)p * kc.n + i) * (D + 1) + 1 + k];
-        grad[i * D + k] = (float)(scale * r[i] * (s0 * xc[i * D + k] - s1));
+        for (int p = 0; p < P; ++p) {
+            const double* o = part + ((int64_t)p * kc.n + i) * W;
+            if (o[0] > -__builtin_inf()) s1 += ldexp(o[2 + k], (int)(o[0] - off));
+        }
+        grad[i * D + k] = (float)(scale * r[i] * (cx * xc[i * D + k] - s1 / s0));
     }
 }
 

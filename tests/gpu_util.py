@@ -88,3 +88,38 @@ def fp32_trajectory_allowance(C, r, c, prm, T, cnorm=1.0, eps=2.0 ** -24, seeds=
     finally:
         OL.col_r = orig
     return worst
+
+
+U32 = 2.0 ** -24        # unit roundoff of FP32
+LOG2E = 1.4426950408889634
+
+
+def sample_columns(m, seed=11, extra=64):
+    """Columns for full-size parity: the ends of 32- and 128-column tiles at both ends of the
+    range, around m/2 and 4096, plus `extra` seeded random ones (at least 64 in all)."""
+    fixed = [0, 1, 31, 32, 63, 64, 127, 128, 255, 256, 4095, 4096, m // 2 - 1, m // 2,
+             m - 129, m - 128, m - 33, m - 32, m - 2, m - 1]
+    rng = np.random.default_rng(seed)
+    cols = np.concatenate([[j for j in fixed if 0 <= j < m], rng.choice(m, min(extra, m), replace=False)])
+    return np.unique(cols)
+
+
+def mfma_term_bound(xr, yr, yn2, s, lam, duals, kp, kstep, cnorm=1.0, erange=64.0):
+    """Worst-case relative error of one exponential term of a matrix-core form, from its FP32
+    exponent assembly: the dot product x~_i . y~_j of operands rounded to the form's type is
+    accumulated in FP32 onto an offset of magnitude up to Q (kp / kstep matrix instructions, each
+    rounding once, plus the offset's own rounding), multiplied by c = 2 s lam log2(e) rounded to
+    FP32, and added to a column term of magnitude c Q rounded to FP32 (three such roundings: the
+    table entry, its A/B correction and the row term), with a final rounding of the exponent
+    itself (|e| <= erange).  Every FP32 rounding moves a value v by at most U32 |v|, so the base-2
+    exponent moves by at most
+        U32 (c A (kp / kstep + 3) + 3 c Q + erange),   A = Q + 2 max|x~| max|y~|,
+    Q = max_j (|y~_j|^2 / 2 + 2 ||C||_inf max|v_j| / (2 s)), and the term by ln 2 times that."""
+    X = float(np.max(np.sqrt(np.sum(np.asarray(xr) ** 2, axis=1))))
+    Y = float(np.max(np.sqrt(np.sum(np.asarray(yr) ** 2, axis=1))))
+    vmax = max(float(np.max(np.abs(v))) for v in duals)
+    Q = float(np.max(yn2)) / 2.0 + 2.0 * cnorm * vmax / (2.0 * s)
+    A = Q + 2.0 * X * Y
+    c = 2.0 * s * lam * LOG2E
+    de = U32 * (c * A * (kp // kstep + 3) + 3.0 * c * Q + erange)
+    return float(np.log(2.0) * de)

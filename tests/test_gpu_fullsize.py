@@ -1,23 +1,38 @@
 """Full-size GPU checks in the launch configuration the benchmark times.
 
-At n = m = 2^16 (d = 64) and n = m = 2^18 (d = 3) the oracle cannot run whole
-iterations, so one GPU iteration from a seeded synthetic state is checked on
-sampled rows the oracle computes one by one (row log-normalisers, gradient
-rows), and on properties that hold at any size (each column marginal sums to
-sum(r) = 1, duals stay in (-1, 1)).  The cost normalisation comes from
+At n = m = 2^16 (d = 64) and n = m = 2^18 (d = 3) one GPU iteration from a seeded
+synthetic state is checked element by element against the oracle's full-size C pass
+(oracle/rowpass.c, FP64, threaded over the host's cores): the row log-normalisers of
+both couplings on every row, and on at least 64 sampled columns (tile and range ends
+included) both column marginals, both dual mirror steps and the updated duals.  Beside
+those, properties that hold at any size (each column marginal sums to sum(r) = 1, duals
+stay in (-1, 1)), gradient rows, and the certificate.  The cost normalisation comes from
 tests/golden/cost_scales.json, written by the oracle's exact C routine.
+
+Tolerances.  FP32 form (FP64 exponent arguments): row log-normalisers 2e-6 absolute; a
+column marginal is a sum of terms r_i exp(a_ij - log Z_i), so its relative error is at
+most the normalisers' error plus the per-term error of an FP32 exponential of an FP64
+argument of magnitude <= 30 (30 x 2^-24 x ln 2 = 1.2e-6) plus FP32 partial sums of 8 terms
+(8 x 2^-24): 4e-6 per column.  Matrix-core forms: per-term bound of
+tests.gpu_util.mfma_term_bound (FP32 exponent assembly) plus the FP32 sums of a split; a
+column marginal twice that.  A dual step moves with its column: |d thetabar_j| <=
+kappa |d col_j| / c^alpha_j (def:closed_form_opt), and nu^{t+1}_j by w times that.
 """
 import json
 import os
 import sys
+import time
 
 import numpy as np
 import pytest
 
+from oracle import cmax
 from oracle import lamp as OL
+from oracle import rowpass as RP
 from oracle import stream as OS
 from paper_2511_11359_amd import workloads as W
-from tests.gpu_util import rel_inf, round_to_type, to_np
+from tests.gpu_util import (U32, mfma_term_bound, rel_dual, rel_inf, round_to_type, sample_columns,
+                            to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,30 +57,67 @@ def _synthetic_state(wl, t, seed):
     return nu, th, lam[t], lam[t + 1]
 
 
-def _check_step(wl, key, precision, t, rows, logz_atol, rounded=None, with_trace=False):
+def _check_step(wl, key, precision, t, cost, logz_tol, col_tol, with_trace=False):
+    """One GPU iteration at t from the seeded synthetic state, against the oracle's full-size
+    pass over `cost` (every row, sampled columns), plus size-independent properties."""
     s = GOLD[key]["cost_scale"]
     nu, th, lam_t, lam_t1 = _synthetic_state(wl, t, seed=77)
     prob = P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=s, cost_norm=1.0)
     st = P.State(torch.tensor(nu, device="cuda"), torch.tensor(th, device="cuda"), t, lam_t)
     _say("case", key, precision, "t", t, "lam", lam_t)
     res, tr = P.step(prob, P.make_params(eta=wl.eta, precision=precision), st, trace=True)
-    x = wl.x.astype(np.float64) if rounded is None else rounded[0]
-    y = wl.y.astype(np.float64) if rounded is None else rounded[1]
-    w = 1.0 / 2.0 / lam_t1                                  # tau1 * eta_{t+1}
-    nubar = nu + w * (th - nu)
-    la = OS.row_log_normalisers(x, y, s, 1.0, nu, lam_t, rows)
-    lb = OS.row_log_normalisers(x, y, s, 1.0, nubar, lam_t1, rows)
-    ea = np.max(np.abs(to_np(tr["log_za"])[rows] - la))
-    eb = np.max(np.abs(to_np(tr["log_zb"])[rows] - lb))
+    torch.cuda.synchronize()
+    cols = sample_columns(wl.m)
+    t0 = time.time()
+    ref = RP.step_sampled(cost, wl.r, wl.c, lam_t, nu, th, OL.Params(eta=wl.eta), 1.0, cols)
+    _say(f"  oracle full-size pass {time.time() - t0:.1f} s")
+    assert ref["lam_next"] == pytest.approx(lam_t1, rel=1e-15)
+    assert res == pytest.approx(float(np.abs(to_np(tr["col_a"]) - wl.c).sum()), rel=1e-12)
+    _full_parity(f"{key} {precision}", st, tr, ref, cols, wl.c, 0.01, logz_tol, col_tol, 0.5 / lam_t1)
     ca, cb = to_np(tr["col_a"]), to_np(tr["col_b"])
-    _say(key, precision, f"logZA err {ea:.2e} logZB err {eb:.2e} sum colA-1 {ca.sum() - 1:.2e} "
-                         f"sum colB-1 {cb.sum() - 1:.2e} res {res:.3e}")
-    assert ea <= logz_atol and eb <= logz_atol
+    _say(key, precision, f"sum colA-1 {ca.sum() - 1:.2e} sum colB-1 {cb.sum() - 1:.2e} res {res:.3e}")
     assert abs(ca.sum() - 1.0) <= 1e-6 and abs(cb.sum() - 1.0) <= 1e-6
     # marginals are non-negative; a column whose every term lies below FP32's range reads 0
     assert np.all(ca >= 0) and np.all(cb >= 0)
     assert np.all(np.abs(to_np(st.theta)) < 1) and np.all(np.abs(to_np(st.nu)) < 1)
     return (prob, st, tr) if with_trace else (prob, st)
+
+
+FP32_LOGZ_ATOL = 2e-6
+FP32_COL_RTOL = 4e-6
+COL_FLOOR = 1e-30
+
+
+def _full_parity(tag, st, tr, ref, cols, c, alpha, logz_tol, col_tol, w):
+    """GPU iteration (state after the step, trace) against the oracle's full-size pass `ref`
+    (rowpass.step_sampled): every row's log-normalisers, and the sampled columns."""
+    m = c.shape[0]
+    ea = np.max(np.abs(to_np(tr["log_za"]) - ref["logZA"]))
+    eb = np.max(np.abs(to_np(tr["log_zb"]) - ref["logZB"]))
+    got = dict(colA=to_np(tr["col_a"])[cols], colB=to_np(tr["col_b"])[cols],
+               theta_bar=to_np(tr["theta_bar"])[cols], theta_hat=to_np(tr["theta_hat"])[cols],
+               nu=to_np(st.nu)[cols], theta=to_np(st.theta)[cols])
+    # a column whose every term lies below FP32's normal range sums to (nearly) zero on the GPU:
+    # its mass is below n 2^-126 < COL_FLOOR, an absolute allowance beside the relative one
+    rc = {k: np.max(np.abs(got[k] - ref[k]) / np.maximum(ref[k], COL_FLOOR / col_tol)) for k in ("colA", "colB")}
+    calpha = c[cols] + alpha / m
+    kappa = 1.0                                   # 2 tau2 ||C||_inf at the default tau2
+    lim_bar = 1e-14 + kappa * (col_tol * ref["colA"] + COL_FLOOR) / calpha
+    lim_hat = 1e-14 + kappa * (col_tol * ref["colB"] + COL_FLOOR) / calpha
+    d = {k: np.abs(got[k] - ref[k]) for k in ("theta_bar", "theta_hat", "nu", "theta")}
+    plain = {k: rel_inf(got[k], ref[k]) for k in d}
+    floored = {k: rel_dual(got[k], ref[k]) for k in d}
+    _say(tag, f"rows: logZA {ea:.2e} logZB {eb:.2e} (tol {logz_tol:.1e}); {len(cols)} columns: "
+              f"colA {rc['colA']:.2e} colB {rc['colB']:.2e} (tol {col_tol:.1e}); duals plain rel "
+         + " ".join(f"{k} {v:.2e}" for k, v in plain.items())
+         + "; floored " + " ".join(f"{k} {v:.2e}" for k, v in floored.items())
+         + f"; worst dual / bound {max(np.max(d['theta_bar'] / lim_bar), np.max(d['theta_hat'] / lim_hat)):.3f}")
+    assert ea <= logz_tol and eb <= logz_tol, (ea, eb)
+    assert rc["colA"] <= col_tol and rc["colB"] <= col_tol, rc
+    assert np.all(d["theta_bar"] <= lim_bar)
+    assert np.all(d["theta_hat"] <= lim_hat)
+    assert np.all(d["nu"] <= 1e-14 + w * lim_bar)
+    assert np.all(d["theta"] <= lim_hat)
 
 
 def _check_certificate(prob, params, nu, th, t, lam_t, col_a, c):
@@ -87,14 +139,14 @@ def _check_certificate(prob, params, nu, th, t, lam_t, col_a, c):
 
 
 def test_sphere_cube_262144_step_and_gradient():
-    """2^18 x 2^18, d = 3: one FP32-form iteration at t = 400, sampled rows; then the adjoint
+    """2^18 x 2^18, d = 3: one FP32-form iteration at t = 400 (every row, sampled columns); then the adjoint
     at the resulting state: 16 random gradient coordinates against the oracle's per-row
     envelope gradient and against central finite differences of the row term (h = 1e-4)."""
     key = "sphere_cube_262144"
     wl = W.sphere_cube()
-    rows = np.array([0, 1, 63, 64, 100000, 200001, 262143])
-    prob, st = _check_step(wl, key, "fp32", 400, rows, 2e-6)
     s = GOLD[key]["cost_scale"]
+    prob, st = _check_step(wl, key, "fp32", 400, RP.Cost(s, 1.0, x=wl.x, y=wl.y), FP32_LOGZ_ATOL,
+                           FP32_COL_RTOL)
     g = to_np(P.backward(prob, P.make_params(eta=wl.eta), st, grad_out=1.0))
     rng = np.random.default_rng(5)
     coords = [(int(rng.integers(0, wl.n)), int(rng.integers(0, 3))) for _ in range(16)]
@@ -117,50 +169,39 @@ def test_sphere_cube_262144_step_and_gradient():
 
 
 def test_gmm64_65536_fp32_step():
-    """2^16 x 2^16, d = 64: one FP32-form (FP64 argument) iteration at t = 300, sampled rows;
+    """2^16 x 2^16, d = 64: one FP32-form (FP64 argument) iteration at t = 300 (every row, sampled
+    columns);
     the certificate of the iterate the step started from."""
     wl = W.gmm64()
-    prob, st, tr = _check_step(wl, "gmm64d_65536", "fp32", 300, SAMPLE, 2e-6, with_trace=True)
+    s = GOLD["gmm64d_65536"]["cost_scale"]
+    prob, st, tr = _check_step(wl, "gmm64d_65536", "fp32", 300, RP.Cost(s, 1.0, x=wl.x, y=wl.y),
+                               FP32_LOGZ_ATOL, FP32_COL_RTOL, with_trace=True)
     nu, th, lam_t, _ = _synthetic_state(wl, 300, seed=77)
     _check_certificate(prob, P.make_params(eta=wl.eta), nu, th, 300, lam_t, to_np(tr["col_a"]), wl.c)
 
 
-@pytest.mark.parametrize("form,dtype", [("bf16_mfma", torch.bfloat16), ("fp16_mfma", torch.float16),
-                                        ("fp32_mfma", torch.float32)])
-def test_gmm64_65536_mfma_step(form, dtype):
-    """2^16 x 2^16, d = 64: one matrix-core iteration at t = 300, sampled rows against the
-    oracle evaluated on the rounded operands the form uses (exponent assembled in FP32)."""
+@pytest.mark.parametrize("form,dtype,kstep", [("bf16_mfma", "bfloat16", 16), ("fp16_mfma", "float16", 16),
+                                              ("fp32_mfma", "float32", 2)])
+def test_gmm64_65536_mfma_step(form, dtype, kstep):
+    """2^16 x 2^16, d = 64: one matrix-core iteration at t = 300 (every row, sampled columns)
+    against the oracle evaluated on the cost the form computes: each centred coordinate rounded
+    once to the operand type, FP64 inner products of the rounded operands, unrounded squared norms,
+    C_ij = s (|x~_i|^2 + |y~_j|^2 - 2 xr_i . yr_j)."""
+    key = "gmm64d_65536"
     wl = W.gmm64()
     x = wl.x.astype(np.float64)
     y = wl.y.astype(np.float64)
     mu = 0.5 * (x[0] + y[0])
     xc, yc = x - mu, y - mu
-    xr = round_to_type(xc, str(dtype).replace("torch.", ""))
-    yr = round_to_type(yc, str(dtype).replace("torch.", ""))
-    # the rounded dot products with the unrounded norms are the cost of points whose
-    # difference form reproduces them: feed the oracle the exact cost through an offset
-    # representation, C_ij = s (|xc_i|^2 + |yc_j|^2 - 2 xr_i . yr_j)
-    s = GOLD["gmm64d_65536"]["cost_scale"]
+    xr, yr = round_to_type(xc, dtype), round_to_type(yc, dtype)
+    nx, ny = np.sum(xc * xc, axis=1), np.sum(yc * yc, axis=1)
+    s = GOLD[key]["cost_scale"]
     nu, th, lam_t, lam_t1 = _synthetic_state(wl, 300, seed=77)
-    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=s, cost_norm=1.0)
-    st = P.State(torch.tensor(nu, device="cuda"), torch.tensor(th, device="cuda"), 300, lam_t)
-    res, tr = P.step(prob, P.make_params(eta=wl.eta, precision=form), st, trace=True)
-    nx = np.sum(xc * xc, axis=1)
-    ny = np.sum(yc * yc, axis=1)
-    w = 0.5 / lam_t1
-    nubar = nu + w * (th - nu)
-    errs = []
-    for i in SAMPLE:
-        Ci = s * (nx[i] + ny - 2.0 * yr @ xr[i])
-        la = np.logaddexp.reduce(-lam_t * (Ci + 2.0 * nu))
-        lb = np.logaddexp.reduce(-lam_t1 * (Ci + 2.0 * nubar))
-        errs.append(max(abs(to_np(tr["log_za"])[i] - la), abs(to_np(tr["log_zb"])[i] - lb)))
-    ca = to_np(tr["col_a"])
-    _say(form, "max logZ err on sampled rows", max(errs), "sum colA - 1", ca.sum() - 1)
-    # FP32 exponent assembly: |e| carries ~ c * 2^-24 * (|h| + |x.y|) + ulp(g)/2; at lam ~ 150,
-    # c ~ 0.37 and |h|, |x.y| ~ 1e3 this is ~1e-4 per term
-    assert max(errs) <= 2e-3
-    assert abs(ca.sum() - 1.0) <= 1e-5
+    term = mfma_term_bound(xr, yr, ny, s, lam_t1, [nu, th], 64, kstep)
+    logz_tol = term + (wl.m / 256 + 6) * U32
+    col_tol = logz_tol + term + (wl.n / 256 + 6) * U32
+    _say(form, f"per-term bound {term:.2e}: logZ tol {logz_tol:.2e}, column tol {col_tol:.2e}")
+    _check_step(wl, key, form, 300, RP.Cost(s, 1.0, gram=(xr, yr, nx, ny)), logz_tol, col_tol)
 
 
 def test_sphere_cube_bf16_forward_then_fp32_adjoint():
@@ -231,3 +272,37 @@ def test_images_256_explicit_cost_step():
     assert np.all(ca >= 0) and np.all(cb >= 0)
     assert np.all(np.abs(to_np(st.theta)) < 1) and np.all(np.abs(to_np(st.nu)) < 1)
     _check_certificate(prob, P.make_params(eta=wl.eta), nu, th, t, lam[t], ca, wl.c)
+
+
+@pytest.mark.parametrize("shape", [(4096, 65536), (65536, 4096)])
+@pytest.mark.parametrize("form,dtype,kstep", [("bf16_mfma", "bfloat16", 16), ("fp16_mfma", "float16", 16),
+                                              ("fp32_mfma", "float32", 2)])
+def test_gmm64_medium_mfma_step_every_row_and_column(shape, form, dtype, kstep):
+    """d = 64 GMM points at n x m = 4096 x 65536 and 65536 x 4096: each split of both sweeps
+    streams 16 tiles, so the pipelined tile loop (prefetch two tiles ahead, buffer swap, clamped
+    last tile) runs in steady state; one step at t = 300 against the oracle's pass over the
+    rounded-operand cost, on every row and every column."""
+    n, m = shape
+    wl = W.gmm64(n, m)
+    x = wl.x.astype(np.float64)
+    y = wl.y.astype(np.float64)
+    s = 1.0 / cmax.max_sqdist(wl.x, wl.y)
+    mu = 0.5 * (x[0] + y[0])
+    xc, yc = x - mu, y - mu
+    xr, yr = round_to_type(xc, dtype), round_to_type(yc, dtype)
+    nx, ny = np.sum(xc * xc, axis=1), np.sum(yc * yc, axis=1)
+    t = 300
+    nu, th = W.synthetic_duals(m, 78)
+    lam = OL.inv_eta_schedule(t + 1, 0.5, wl.eta)
+    term = mfma_term_bound(xr, yr, ny, s, lam[t + 1], [nu, th], 64, kstep)
+    logz_tol = term + (m / 256 + 6) * U32
+    col_tol = logz_tol + term + (n / 256 + 6) * U32
+    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=s, cost_norm=1.0)
+    st = P.State(torch.tensor(nu, device="cuda"), torch.tensor(th, device="cuda"), t, lam[t])
+    _say("case", form, shape, f"per-term bound {term:.2e}")
+    res, tr = P.step(prob, P.make_params(eta=wl.eta, precision=form), st, trace=True)
+    torch.cuda.synchronize()
+    cols = np.arange(m)
+    ref = RP.step_sampled(RP.Cost(s, 1.0, gram=(xr, yr, nx, ny)), wl.r, wl.c, lam[t], nu, th,
+                          OL.Params(eta=wl.eta), 1.0, cols)
+    _full_parity(f"{form} {n}x{m}", st, tr, ref, cols, wl.c, 0.01, logz_tol, col_tol, 0.5 / lam[t + 1])

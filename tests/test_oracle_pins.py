@@ -372,6 +372,41 @@ def test_stream_step_matches_dense_step():
                                tr2.logZA[0][rows], rtol=1e-13)
 
 
+@pytest.mark.parametrize("eta", [0.0, 1e-2])
+def test_rowpass_c_step_matches_dense_step(eta):
+    """The C full-size pass (every row's log-normaliser, listed columns' marginals and dual
+    steps) gives the dense iteration, for the difference-form cost of FP32 points and for a cost
+    given by separate norms and FP64 inner products (here built from the same points, so both
+    define the same C up to rounding)."""
+    from oracle import rowpass
+    wl = W.random_small(150, 97, 4, seed=18)
+    x, y = wl.x.astype(np.float64), wl.y.astype(np.float64)
+    s = 1.0 / L.max_sqdist(x, y)
+    C = L.sqeuclid_cost(x, y, s)
+    prm = L.Params(eta=eta)
+    st, _ = L.lamp_dense(C, wl.r, wl.c, prm, 30, 1.0, trace=False)
+    st2, tr = L.lamp_dense(C, wl.r, wl.c, prm, 1, 1.0, state=st)
+    cols = np.array([0, 1, 31, 32, 63, 64, 95, 96])
+    gram = (x, y, np.sum(x * x, axis=1), np.sum(y * y, axis=1))
+    for cost, rtol in [(rowpass.Cost(s, 1.0, x=wl.x, y=wl.y), 1e-12), (rowpass.Cost(s, 1.0, gram=gram), 1e-9)]:
+        out = rowpass.step_sampled(cost, wl.r, wl.c, st.lam, st.nu, st.theta, prm, 1.0, cols)
+        np.testing.assert_allclose(out["logZA"], tr.logZA[0], rtol=rtol, atol=1e-13)
+        np.testing.assert_allclose(out["logZB"], tr.logZB[0], rtol=rtol, atol=1e-13)
+        for key, ref in [("colA", tr.colA[0]), ("colB", tr.colB[0]), ("theta_bar", tr.theta_bar[0]),
+                         ("theta_hat", tr.theta_hat[0]), ("nu", st2.nu), ("theta", st2.theta)]:
+            np.testing.assert_allclose(out[key], ref[cols], rtol=rtol, atol=1e-14, err_msg=key)
+        assert out["lam_next"] == st2.lam
+    # whole runs to a tolerance: the same stopping iterate as the dense run
+    st_d, _ = L.lamp_dense(C, wl.r, wl.c, prm, 3000, 1.0, tol=1e-4, trace=False)
+    run = rowpass.solve(rowpass.Cost(s, 1.0, x=wl.x, y=wl.y), wl.r, wl.c, prm, 1.0, 3000, tol=1e-4, keep=(7,))
+    assert run["t"] == st_d.t and run["res"] <= 1e-4
+    np.testing.assert_allclose(run["nu"], st_d.nu, rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(run["theta"], st_d.theta, rtol=1e-10, atol=1e-13)
+    assert run["lam"] == pytest.approx(st_d.lam, rel=1e-15)
+    st7, _ = L.lamp_dense(C, wl.r, wl.c, prm, 7, 1.0, trace=False)
+    np.testing.assert_allclose(run["saved"][7][1], st7.nu, rtol=1e-11, atol=1e-14)
+
+
 def test_cmax_c_routine_matches_numpy():
     from oracle import cmax
     wl = W.random_small(300, 211, 5, seed=16)
