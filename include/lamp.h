@@ -205,6 +205,20 @@ lamp_status lamp_step(const lamp_problem *prob, const lamp_params *params, lamp_
                       void *ws, size_t ws_bytes, void *stream, const lamp_trace *trace,
                       double *res_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lamp_step with the workspace taken
+ * from a fixed device array of LAMP_NOALLOC_WS_BYTES bytes that the library holds, one
+ * per device, until the process ends.  Same arguments, kernels and results as lamp_step
+ * without ws / ws_bytes.  The call allocates nothing (no hipMalloc, no allocating library
+ * routine); it looks the array's address up once per device on its first call there.
+ * Problems whose lamp_workspace_bytes exceeds LAMP_NOALLOC_WS_BYTES are rejected with
+ * LAMP_ENOMEM (64 MiB: enough for n = m = 2^16 at d = 3 in LAMP_FP32, 49 MiB).  Every call
+ * on one device shares that array, so calls that overlap in time on one device race
+ * (serialise them, e.g. on one stream); nothing in it has to start at zero. */
+#define LAMP_NOALLOC_WS_BYTES ((size_t)64 << 20)
+lamp_status lamp_step_noalloc(const lamp_problem *prob, const lamp_params *params, lamp_state *state,
+                              void *stream, const lamp_trace *trace, double *res_out);
+
 /* Runs Algorithm 2 from `state` (t = 0: a fresh start; t > 0: resumes) until
  * ||col(X^t) - c||_1 <= tol or max_iter iterations of this call.  On LAMP_OK the
  * state holds the iterate that met the tolerance (that iteration's update is not

@@ -27,6 +27,7 @@ LAMP_L1 = 1
 LAMP_LINF = 2
 METRICS = {"sqeuclid": 0, "l1": 1, "linf": 2, "explicit": 3}
 COST_TYPES = {"float32": 0, "bfloat16": 1, "float16": 2}
+NOALLOC_WS_BYTES = 64 << 20        # LAMP_NOALLOC_WS_BYTES: the fixed scratch of lamp_step_noalloc
 
 STATUS_NAMES = {0: "LAMP_OK", 1: "LAMP_NOT_CONVERGED", -1: "LAMP_EINVAL", -2: "LAMP_EDOMAIN",
                 -3: "LAMP_ENOMEM", -4: "LAMP_EDEVICE", -5: "LAMP_ENUMERIC"}
@@ -77,6 +78,9 @@ SYMBOLS = {
     "lamp_step": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(State),
                             c_void_p, c_size_t, c_void_p, ctypes.POINTER(Trace),
                             ctypes.POINTER(c_double)]),
+    "lamp_step_noalloc": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params),
+                                    ctypes.POINTER(State), c_void_p, ctypes.POINTER(Trace),
+                                    ctypes.POINTER(c_double)]),
     "lamp_solve": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(State),
                              c_void_p, c_size_t, c_void_p, ctypes.POINTER(Report)]),
     "lamp_certificate": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params),

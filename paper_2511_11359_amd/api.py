@@ -166,6 +166,22 @@ def step(prob: Problem, params: L.Params, state: State, trace: bool = False):
     return res.value, tr
 
 
+def step_noalloc(prob: Problem, params: L.Params, state: State, trace: bool = False):
+    """step() through lamp_step_noalloc: the library's fixed device scratch replaces the
+    workspace (problems up to LAMP_NOALLOC_WS_BYTES of workspace).  The trace buffers, when asked
+    for, are the caller's outputs and are allocated here, before the call."""
+    lib = L.load()
+    tr, trs = _trace_buffers(prob, trace)
+    p = prob.struct()
+    s = state.struct()
+    res = ctypes.c_double()
+    _check(lib.lamp_step_noalloc(ctypes.byref(p), ctypes.byref(params), ctypes.byref(s),
+                                 _stream_handle(prob.device),
+                                 ctypes.byref(trs) if trs is not None else None, ctypes.byref(res)))
+    state.update(s)
+    return res.value, tr
+
+
 def solve(prob: Problem, params: L.Params, state: State | None = None):
     """Runs Algorithm 2 (resuming from `state` if given).  Returns (state, report dict, status)."""
     lib = L.load()

@@ -26,6 +26,9 @@
 
 using namespace lampk;
 
+// Fixed workspace of lamp_step_noalloc (see scratch_address below).
+static_assert(LAMP_NOALLOC_WS_BYTES % 256 == 0, "scratch size is a multiple of 256 bytes");
+static __device__ __align__(256) unsigned char scratch[LAMP_NOALLOC_WS_BYTES];
 
 namespace {
 
@@ -1336,7 +1339,7 @@ lamp_status batch_tune(const lamp_problem* probs, int count, const lamp_params* 
     *best = best_c;
     return LAMP_OK;
 }
-// One iteration on workspace `ws`; `prob` is canonical.
+// One iteration on workspace `ws` (lamp_step and lamp_step_noalloc); `prob` is canonical.
 lamp_status step_impl(const lamp_problem* prob, const lamp_params* params, lamp_state* state, void* ws,
                       size_t ws_bytes, hipStream_t st, const lamp_trace* trace, double* res_out) {
     lamp_status e;
@@ -1380,6 +1383,28 @@ lamp_status step_impl(const lamp_problem* prob, const lamp_params* params, lamp_
 }
 
 
+// Fixed workspace of lamp_step_noalloc: one copy per device, held until the process ends.
+// Host code never uses the array's name as an address: scratch_address() returns the
+// device address of the current device's copy (hipGetSymbolAddress, once per device).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+lamp_status scratch_address(void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LAMP_EDEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(LAMP_EDEVICE, "no device address for the scratch array on device %d", dev);
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LAMP_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1419,6 +1444,22 @@ lamp_status lamp_step(const lamp_problem* prob, const lamp_params* params, lamp_
     lamp_problem canon_buf;
     prob = canonical(prob, &canon_buf);
     return step_impl(prob, params, state, ws, ws_bytes, (hipStream_t)stream, trace, res_out);
+}
+
+lamp_status lamp_step_noalloc(const lamp_problem* prob, const lamp_params* params, lamp_state* state,
+                              void* stream, const lamp_trace* trace, double* res_out) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
+    lamp_status e;
+    if ((e = check_problem(prob)) != LAMP_OK) return e;
+    if ((e = check_params(params)) != LAMP_OK) return e;
+    const size_t need = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric).total;
+    if (need > LAMP_NOALLOC_WS_BYTES)
+        return fail(LAMP_ENOMEM, "lamp_step_noalloc: this problem needs %zu bytes of workspace, the fixed device "
+                    "scratch holds %zu (use lamp_step with a caller workspace)", need, (size_t)LAMP_NOALLOC_WS_BYTES);
+    void* ws = nullptr;
+    if ((e = scratch_address(&ws)) != LAMP_OK) return e;
+    return step_impl(prob, params, state, ws, LAMP_NOALLOC_WS_BYTES, (hipStream_t)stream, trace, res_out);
 }
 
 lamp_status lamp_solve(const lamp_problem* prob, const lamp_params* params, lamp_state* state, void* ws,

@@ -144,3 +144,26 @@ def test_explicit_cost_checks():
         assert fn(ctypes.byref(expl), ctypes.byref(params), ctypes.byref(st), 1.0, FAKE, FAKE, 1 << 40,
                   None) == LAMP_EINVAL
         assert b"point clouds" in lib.lamp_last_error()
+
+
+def _step_noalloc(prob, params):
+    lib = _lib.load()
+    st = _lib.State(FAKE, FAKE, 0, 0.0, 0.0)
+    return lib.lamp_step_noalloc(ctypes.byref(prob), ctypes.byref(params), ctypes.byref(st), None, None,
+                                 None)
+
+
+def test_noalloc_step_host_checks():
+    """lamp_step_noalloc rejects bad arguments, and problems whose workspace exceeds the fixed
+    device scratch, before any device call."""
+    lib = _lib.load()
+    params = _params()
+    assert _step_noalloc(_problem(n=0), params) == LAMP_EINVAL
+    assert _step_noalloc(_problem(), _params(eta=-1.0)) == LAMP_EINVAL
+    big = _problem(n=1 << 18, m=1 << 18)
+    assert lib.lamp_workspace_bytes(ctypes.byref(big), ctypes.byref(params)) > _lib.NOALLOC_WS_BYTES
+    assert _step_noalloc(big, params) == LAMP_ENOMEM
+    assert b"fixed device scratch" in lib.lamp_last_error()
+    src = open(HEADER).read()
+    assert f"#define LAMP_NOALLOC_WS_BYTES ((size_t)64 << 20)" in src
+    assert _lib.NOALLOC_WS_BYTES == 64 << 20
