@@ -176,6 +176,10 @@ typedef struct {
                                 - log m; NaN unless every iteration tracked it        */
     double midpoint_bound;   /* 2||C||_inf (log m + (1 + alpha) log 2 + D_t) / t, the
                                 right-hand side of ineq:spp_midpoint_conv (eta = 0)  */
+    double dual_eta_theta;   /* D^eta(theta^t) (def:dual_spp_e) at the params' eta > 0:
+                                sum_i r_i softmin^eta_j (C_ij + 2||C||_inf theta_j)
+                                - 2||C||_inf <c, theta>; NaN when eta = 0           */
+    double dual_eta_nu;      /* D^eta(nu^t), likewise                                 */
 } lamp_cert;
 
 typedef struct {

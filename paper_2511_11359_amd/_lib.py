@@ -62,7 +62,8 @@ class Cert(ctypes.Structure):
                 ("dual_theta", c_double), ("dual_nu", c_double), ("primal_penalized", c_double),
                 ("gap", c_double), ("prop_bound", c_double), ("cost_scale", c_double),
                 ("cost_norm", c_double), ("t", c_int64), ("rounded_cost", c_double),
-                ("dt", c_double), ("midpoint_bound", c_double)]
+                ("dt", c_double), ("midpoint_bound", c_double), ("dual_eta_theta", c_double),
+                ("dual_eta_nu", c_double)]
 
 
 class Report(ctypes.Structure):

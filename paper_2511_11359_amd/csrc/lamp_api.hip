@@ -215,7 +215,9 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     L.dtrow = take(sizeof(double) * n);
     L.dtpart = take(sizeof(double) * cdiv(m, BLOCK));
     // certificate: 4 arrays of max(n, m), Round: 9 more and d + 2 column sums
-    L.scratch = take(sizeof(double) * (13 * std::max(n, m) + d + 2));
+    // (the adjoint: g^A and one record of 12 d + 8 bytes per column, 16-byte aligned)
+    L.scratch = take(std::max(sizeof(double) * (13 * std::max(n, m) + d + 2),
+                              align256(sizeof(double) * m) + (size_t)m * (size_t)((12 * d + 8 + 15) / 16 * 16)));
     L.small = take(sizeof(double) * 64);
     if (is_mfma(prec)) {
         L.xop = take((size_t)L.esize * L.n_pad * L.KP);
@@ -304,28 +306,21 @@ lamp_status check_ws(const lamp_problem* p, void* ws, size_t ws_bytes, int prec 
 }
 
 // Marginals must be strictly positive and sum to 1 (r in Delta^n, c in Delta^m with full support).
-// Read in chunks through a fixed host buffer, ordered on the call's stream (the marginals may
-// have been written by earlier work on it).
-lamp_status check_marginals(const lamp_problem* p, hipStream_t st) {
-    constexpr int64_t CH = 2048;
-    double h[CH];
-    const double* arrs[2] = {p->r, p->c};
-    const int64_t lens[2] = {p->n, p->m};
+// Checked on the device, ordered on the call's stream (the marginals may have been written by
+// earlier work on it); `dev6` is 6 doubles of device scratch for the two results.
+lamp_status check_marginals(const lamp_problem* p, double* dev6, hipStream_t st) {
+    hipLaunchKernelGGL(marginal_stats, dim3(1), dim3(1024), 0, st, p->r, p->n, dev6);
+    hipLaunchKernelGGL(marginal_stats, dim3(1), dim3(1024), 0, st, p->c, p->m, dev6 + 3);
+    HIPCHK(hipGetLastError());
+    double h[6];
+    HIPCHK(hipMemcpyAsync(h, dev6, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     const char* names[2] = {"r", "c"};
     for (int q = 0; q < 2; ++q) {
-        double sum = 0.0;
-        for (int64_t i0 = 0; i0 < lens[q]; i0 += CH) {
-            const int64_t cnt = std::min(CH, lens[q] - i0);
-            HIPCHK(hipMemcpyAsync(h, arrs[q] + i0, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            for (int64_t k = 0; k < cnt; ++k) {
-                if (!(h[k] > 0.0) || !std::isfinite(h[k]))
-                    return fail(LAMP_EDOMAIN, "%s[%lld] = %g is not a positive finite mass", names[q],
-                                (long long)(i0 + k), h[k]);
-                sum += h[k];
-            }
-        }
-        if (std::fabs(sum - 1.0) > 1e-9) return fail(LAMP_EDOMAIN, "%s sums to %.17g, not 1", names[q], sum);
+        const double* v = h + 3 * q;
+        if (v[1] >= 0.0)
+            return fail(LAMP_EDOMAIN, "%s[%lld] = %g is not a positive finite mass", names[q], (long long)v[1], v[2]);
+        if (std::fabs(v[0] - 1.0) > 1e-9) return fail(LAMP_EDOMAIN, "%s sums to %.17g, not 1", names[q], v[0]);
     }
     return LAMP_OK;
 }
@@ -639,8 +634,12 @@ void launch_adjoint(const Layout& L, Consts kc, int d, void* ws, double cA, cons
     const float* ycf = at<float>(ws, L.ycf);
     const bool done = by_metric(kc.metric, [&](auto m) {
         return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
-            hipLaunchKernelGGL((adjoint_sweep<decltype(m)::value, decltype(dd)::value>), g, dim3(BLOCK), 0, st, kc,
-                               cA, xc, yc, ycf, gA, part, L.split_r);
+            constexpr int D = decltype(dd)::value;
+            // the column records follow gA in the scratch region (sized for them in layout())
+            auto* cols = reinterpret_cast<AdjCol<D>*>(at<char>(ws, L.scratch) + align256(sizeof(double) * kc.m));
+            hipLaunchKernelGGL((adjoint_pack<D>), grid1(kc.m), dim3(BLOCK), 0, st, kc.m, yc, ycf, gA, cols);
+            hipLaunchKernelGGL((adjoint_sweep<decltype(m)::value, D>), g, dim3(BLOCK), 0, st, kc, cA, xc,
+                               (const AdjCol<D>*)cols, part, L.split_r);
         });
     });
     if (!done)
@@ -897,7 +896,9 @@ lamp_status common_setup(const lamp_problem* p, const lamp_params* q, void* ws, 
     if ((e = check_problem(p)) != LAMP_OK) return e;
     if ((e = check_params(q)) != LAMP_OK) return e;
     if ((e = check_ws(p, ws, ws_bytes, q->precision)) != LAMP_OK) return e;
-    if ((e = check_marginals(p, st)) != LAMP_OK) return e;
+    if ((e = check_marginals(p, at<double>(ws, layout(p->n, p->m, p->d, q->precision, TARGET_BLOCKS, p->metric).small),
+                             st)) != LAMP_OK)
+        return e;
     if ((e = prep(p, ws, st, q->precision)) != LAMP_OK) return e;
     return resolve(p, q, ws, st, R);
 }
@@ -1710,9 +1711,20 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     hipLaunchKernelGGL(normaliser_terms, grid1(kc.n), dim3(BLOCK), 0, st, kc, cA, state->inv_eta, psum,
                        at<double>(ws, L.H), at<double>(ws, L.xn2), prob->r, rlz);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, rlz, kc.n, kc.n, 1, small + 10);
+    // D^eta(theta), D^eta(nu) at the problem's eta (def:dual_spp_e); NaN at eta = 0
+    const bool soft = params->eta > 0.0;
+    if (soft) {
+        double* sv = at<double>(ws, L.rpart);   // 2n (the row sums above are reduced)
+        by_md([&](auto m, auto dd) {
+            hipLaunchKernelGGL((cert_soft_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK),
+                               0, st, kc, prob->d, 1.0 / params->eta, at<double>(ws, L.xc), at<double>(ws, L.yc),
+                               at<double>(ws, L.xn2), at<double>(ws, L.yn2), prob->r, state->nu, state->theta, sv);
+        });
+        hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, sv, kc.n, kc.n, 2, small + 11);
+    }
     HIPCHK(hipGetLastError());
-    double h[11];
-    HIPCHK(hipMemcpyAsync(h, small, sizeof(h), hipMemcpyDeviceToHost, st));
+    double h[13];
+    HIPCHK(hipMemcpyAsync(h, small, sizeof(double) * (soft ? 13 : 11), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     out->row_res = h[0];
     out->cost = h[1];
@@ -1729,6 +1741,9 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     out->dt = state->dt_partial + h[10] - logm;
     out->midpoint_bound =
         2.0 * R.cnorm * (logm + (1.0 + R.alpha) * std::log(2.0) + out->dt) / (double)state->t;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    out->dual_eta_theta = soft ? h[11] - R.K * h[5] : nan;
+    out->dual_eta_nu = soft ? h[12] - R.K * h[6] : nan;
     out->cost_scale = R.s;
     out->cost_norm = R.cnorm;
     out->t = state->t;
@@ -1925,8 +1940,14 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
             }
         }
     } guard{own};
-    for (int p = 0; p < count; ++p)
-        if ((e = check_marginals(&probs[p], st)) != LAMP_OK) return e;
+    // the first problem's sub-workspace is laid out at offset 0 of a batch plan's problem region;
+    // its small-scalar area is scratch here (every problem's preparation rewrites it later)
+    {
+        const BatchPlan B0 = batch_plan(probs, count, 0);
+        double* dev6 = at<double>(static_cast<char*>(ws) + B0.sub[0], B0.L[0].small);
+        for (int p = 0; p < count; ++p)
+            if ((e = check_marginals(&probs[p], dev6, st)) != LAMP_OK) return e;
+    }
 
     int cand = 0;
     if ((e = batch_tune(probs, count, params, states, ws, st, &cand)) != LAMP_OK) return e;

@@ -559,9 +559,13 @@ __device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, 
     rv.wA = (float)(r[i] * exp2(ew));
     rv.wB = (float)r[i];
     rowvar[i] = rv;
-    // the vector-ALU column sweep takes the A coupling's row factor 2^ew in its exponent
-    // (unclamped: no FP32 weight to overflow), both couplings weighted by r_i
-    if (rowck) rowck[i] = make_double2(cA * hnew + (rho * sigB - sigA), cB * hnew);
+    // the vector-ALU column sweep takes the row weights into its exponents: the A coupling's
+    // row factor 2^ew (unclamped: no FP32 weight to overflow) and n r_i (1 for uniform r; the
+    // sweep multiplies its sums by 1/n)
+    if (rowck) {
+        const double lw = log2((double)kc.n * r[i]);
+        rowck[i] = make_double2(cA * hnew + (rho * sigB - sigA) + lw, cB * hnew + lw);
+    }
     if (rf.q) {
         const float kf = (float)hnew;
         const double dk = hnew - (double)kf;
@@ -591,40 +595,36 @@ __global__ void row_finish(Ctrl* ctrl, const Sched* sched, Consts kc, int D,
 //     e^B = cfac^B (P_ij + G_j) + cfac^B k_i,
 //     e^A = cfac^A (P_ij + G_j) + (cfac^A k_i + ew_i) + D_j,   D_j = g^A_j - cfac^A G_j:
 // the dot product starts from G_j (per lane), the row terms come precomputed (rowck,
-// scalar), and D_j, constant down the column, is applied once to the column's A sum
-// (`factor`) or added to each exponent.  Both are weighted by r_i, the scalar multiplicand.
+// scalar, with the row weight as log2(n r_i) in both), and D_j, constant down the column,
+// is applied once to the column's A sum (`factor`) or added to each exponent; the sums are
+// plain FP32 adds, multiplied by 1/n at the end.
 template <int M, int D, bool FACTOR>
 __device__ __forceinline__ void col_terms(const double (&y)[D], const double* __restrict__ xi, double2 ck,
-                                          float w, double G, double Dj, double cA, double cB,
-                                          float& accA, float& accB) {
+                                          double G, double Dj, double cA, double cB, float& accA, float& accB) {
     const double dot = pair_term<M, D>(y, xi, G);   // the distances are symmetric
     double eA = fma_su(dot, cA, ck.x);
     if constexpr (!FACTOR) eA += Dj;
-    accA = fmaf(w, fexp2(eA), accA);
-    accB = fmaf(w, fexp2(fma_su(dot, cB, ck.y)), accB);
+    accA += fexp2(eA);
+    accB += fexp2(fma_su(dot, cB, ck.y));
 }
 
 template <int M, int D, bool FACTOR>
 __device__ __forceinline__ void col_sweep_run(double cA, double cB, const double (&y)[D], double G, double Dj,
-                                              const double* __restrict__ xc, const RowVar* __restrict__ rowvar,
-                                              const double2* __restrict__ rowck, int64_t i0, int64_t i1,
-                                              double& sumA, double& sumB) {
+                                              const double* __restrict__ xc, const double2* __restrict__ rowck,
+                                              int64_t i0, int64_t i1, double& sumA, double& sumB) {
     const int nfull = (int)((i1 - i0) / UNROLL);
     const double* __restrict__ xp = xc + i0 * D;
-    const RowVar* __restrict__ rp = rowvar + i0;
     const double2* __restrict__ kp = rowck + i0;
-    for (int c = 0; c < nfull; ++c, xp += UNROLL * D, rp += UNROLL, kp += UNROLL) {
+    for (int c = 0; c < nfull; ++c, xp += UNROLL * D, kp += UNROLL) {
         float accA = 0.f, accB = 0.f;
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-            col_terms<M, D, FACTOR>(y, xp + u * D, kp[u], rp[u].wB, G, Dj, cA, cB, accA, accB);
+        for (int u = 0; u < UNROLL; ++u) col_terms<M, D, FACTOR>(y, xp + u * D, kp[u], G, Dj, cA, cB, accA, accB);
         sumA += (double)accA;
         sumB += (double)accB;
     }
     const int rem = (int)((i1 - i0) - (int64_t)nfull * UNROLL);
     float accA = 0.f, accB = 0.f;
-    for (int u = 0; u < rem; ++u)
-        col_terms<M, D, FACTOR>(y, xp + u * D, kp[u], rp[u].wB, G, Dj, cA, cB, accA, accB);
+    for (int u = 0; u < rem; ++u) col_terms<M, D, FACTOR>(y, xp + u * D, kp[u], G, Dj, cA, cB, accA, accB);
     sumA += (double)accA;
     sumB += (double)accB;
 }
@@ -655,12 +655,15 @@ __device__ __forceinline__ void col_sweep_body(const Ctrl* ctrl, const Sched* sc
     const double Dj = g.x - cA * G;
 
     double sumA = 0.0, sumB = 0.0;
+    const double inv_n = 1.0 / (double)kc.n;   // the row weights r_i enter as n r_i (rowck)
     if (kc.factor_cols) {
-        col_sweep_run<M, D, true>(cA, cB, y, G, Dj, xc, rowvar, rowck, i0, i1, sumA, sumB);
-        sumA *= exp2(Dj);
+        col_sweep_run<M, D, true>(cA, cB, y, G, Dj, xc, rowck, i0, i1, sumA, sumB);
+        sumA *= exp2(Dj) * inv_n;
     } else {
-        col_sweep_run<M, D, false>(cA, cB, y, G, Dj, xc, rowvar, rowck, i0, i1, sumA, sumB);
+        col_sweep_run<M, D, false>(cA, cB, y, G, Dj, xc, rowck, i0, i1, sumA, sumB);
+        sumA *= inv_n;
     }
+    sumB *= inv_n;
     if (j < kc.m) cpart[p * kc.m + j] = make_double2(sumA, sumB);
 }
 
@@ -700,18 +703,19 @@ __device__ __forceinline__ void col_sweep_dyn_body(const Ctrl* ctrl, const Sched
         float accA = 0.f, accB = 0.f;
         const int64_t ie = min(i1, ib + UNROLL);
         for (int64_t i = ib; i < ie; ++i) {
-            const float w = rowvar[i].wB;
             const double2 ck = rowck[i];
             const double dot = pair_term_dyn(kc, D, yc + jj * D, xc + i * D, G);
             double eA = fma(dot, cA, ck.x);
             if (!kc.factor_cols) eA += Dj;
-            accA = fmaf(w, fexp2(eA), accA);
-            accB = fmaf(w, fexp2(fma(dot, cB, ck.y)), accB);
+            accA += fexp2(eA);
+            accB += fexp2(fma(dot, cB, ck.y));
         }
         sumA += (double)accA;
         sumB += (double)accB;
     }
-    if (kc.factor_cols) sumA *= exp2(Dj);
+    const double inv_n = 1.0 / (double)kc.n;
+    sumA *= (kc.factor_cols ? exp2(Dj) : 1.0) * inv_n;
+    sumB *= inv_n;
     if (j < kc.m) cpart[p * kc.m + j] = make_double2(sumA, sumB);
 }
 
@@ -1009,6 +1013,36 @@ __global__ void reduce_sums(const double* __restrict__ vals, int64_t n, int64_t 
     }
 }
 
+// Checks of a marginal a[0..len) in one block: out[0] = sum (fixed order), out[1] = the
+// first index whose entry is not a positive finite number (-1: none), out[2] = that entry.
+__global__ void marginal_stats(const double* __restrict__ a, int64_t len, double* __restrict__ out) {
+    __shared__ double sh[1024];
+    __shared__ long long bad[1024];
+    double acc = 0.0;
+    long long first = -1;
+    for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
+        const double v = a[i];
+        acc += v;
+        if (first < 0 && !(v > 0.0 && v <= 1.7976931348623157e308)) first = (long long)i;
+    }
+    sh[threadIdx.x] = acc;
+    bad[threadIdx.x] = first;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sh[threadIdx.x] += sh[threadIdx.x + o];
+            const long long b = bad[threadIdx.x + o];
+            if (b >= 0 && (bad[threadIdx.x] < 0 || b < bad[threadIdx.x])) bad[threadIdx.x] = b;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sh[0];
+        out[1] = (double)bad[0];
+        out[2] = bad[0] >= 0 ? a[bad[0]] : 0.0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The pair term of the thread's own point against streamed points: coordinates in
 // registers for a compile-time dimension (M, D), read from memory for the run-time
@@ -1085,6 +1119,51 @@ __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int Dm, double cA,
     vals[2 * kc.n + i] = ri * mth;
     vals[3 * kc.n + i] = ri * mnu;
     if (psum_out) psum_out[i] = psum;
+}
+
+// ---------------------------------------------------------------------------
+// Entropic dual values at eta = 1/lam > 0 (def:dual_spp_e): per row i and dual v in {theta, nu},
+//   softmin_i(v) = mu_i - eta ln sum_j exp(-(C_ij + K v_j - mu_i) / eta),  mu_i = min_j (C_ij + K v_j),
+// the minimum in FP64 (a first pass), the terms (each <= 1, one of them 1) as FP32 exponentials of
+// FP64 arguments summed in FP32 over blocks of UNROLL columns and in FP64 across them.
+//   vals[0][i] = r_i softmin_i(theta),  vals[1][i] = r_i softmin_i(nu).
+// ---------------------------------------------------------------------------
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void cert_soft_rows(Consts kc, int Dm, double lam,
+                                                        const double* __restrict__ xc,
+                                                        const double* __restrict__ yc,
+                                                        const double* __restrict__ xn2,
+                                                        const double* __restrict__ yn2,
+                                                        const double* __restrict__ r,
+                                                        const double* __restrict__ nu,
+                                                        const double* __restrict__ theta,
+                                                        double* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= kc.n) return;
+    const OwnPoint<M, D> own(xc + i * Dm, Dm, kc);
+    auto cost = [&](int64_t j) { return kc.s * (xn2[i] + yn2[j] - 2.0 * own.pair(yc + j * Dm)); };
+    double mth = __builtin_inf(), mnu = __builtin_inf();
+    for (int64_t j = 0; j < kc.m; ++j) {
+        const double cij = cost(j);
+        mth = fmin(mth, cij + kc.K * theta[j]);
+        mnu = fmin(mnu, cij + kc.K * nu[j]);
+    }
+    const double f = -lam * LOG2E;
+    double sth = 0.0, snu = 0.0;
+    for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
+        const int64_t je = min(kc.m, jb + UNROLL);
+        float at = 0.f, an = 0.f;
+        for (int64_t j = jb; j < je; ++j) {
+            const double cij = cost(j);
+            at += fexp2(f * (cij + kc.K * theta[j] - mth));
+            an += fexp2(f * (cij + kc.K * nu[j] - mnu));
+        }
+        sth += (double)at;
+        snu += (double)an;
+    }
+    const double ri = r[i];
+    vals[i] = ri * (mth - log(sth) / lam);
+    vals[kc.n + i] = ri * (mnu - log(snu) / lam);
 }
 
 // ---------------------------------------------------------------------------
@@ -1296,11 +1375,33 @@ __device__ __forceinline__ void adjoint_accumulate(const double (&x)[D], const d
     }
 }
 
+// One column's data for the adjoint sweep in one record (read with a few wide scalar loads):
+// y~_j in FP64 (dot product), g^A_j, y~_j in FP32 (the S1 sums).
+template <int D>
+struct alignas(16) AdjCol {
+    double y[D];
+    double g;
+    float yf[D];
+};
+
+template <int D>
+__global__ void adjoint_pack(int64_t m, const double* __restrict__ yc, const float* __restrict__ ycf,
+                             const double* __restrict__ gA, AdjCol<D>* __restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    AdjCol<D> c;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        c.y[k] = yc[j * D + k];
+        c.yf[k] = ycf[j * D + k];
+    }
+    c.g = gA[j];
+    out[j] = c;
+}
+
 template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, const double* __restrict__ xc,
-                                                       const double* __restrict__ yc,
-                                                       const float* __restrict__ ycf,
-                                                       const double* __restrict__ gA,
+                                                       const AdjCol<D>* __restrict__ cols,
                                                        double* __restrict__ part, int64_t split) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t p = blockIdx.y;
@@ -1330,16 +1431,14 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, con
     // blocks of UNROLL columns with a compile-time trip count (the column data are
     // wave-uniform scalar loads, issued together); the offset is checked once per block
     const int64_t nfull = (j1 - j0) / UNROLL;
-    const double* __restrict__ yp = yc + j0 * D;
-    const float* __restrict__ yfp = ycf + j0 * D;
-    const double* __restrict__ gp = gA + j0;
-    for (int64_t c = 0; c < nfull; ++c, yp += UNROLL * D, yfp += UNROLL * D, gp += UNROLL) {
+    const AdjCol<D>* __restrict__ cp = cols + j0;
+    for (int64_t c = 0; c < nfull; ++c, cp += UNROLL) {
         double e[UNROLL];
         float ef[UNROLL];
         float bm = -__builtin_inff();
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            e[u] = fma_su(pair_term<M, D>(x, yp + u * D, h), cA, gp[u]);
+            e[u] = fma_su(pair_term<M, D>(x, cp[u].y, h), cA, cp[u].g);
             ef[u] = (float)e[u];
             bm = fmaxf(bm, ef[u]);
         }
@@ -1357,14 +1456,14 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, con
         for (int k = 0; k < D; ++k) a1[k] = 0.f;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-            adjoint_accumulate<M, D>(x, yp + u * D, yfp + u * D, __builtin_amdgcn_exp2f(ef[u]), a0, a1);
+            adjoint_accumulate<M, D>(x, cp[u].y, cp[u].yf, __builtin_amdgcn_exp2f(ef[u]), a0, a1);
         s0 += (double)a0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s1[k] += (double)a1[k];
     }
     // the remaining columns one at a time
     for (int64_t j = j0 + nfull * UNROLL; j < j1; ++j) {
-        double e = fma_su(pair_term<M, D>(x, yc + j * D, h), cA, gA[j]);
+        double e = fma_su(pair_term<M, D>(x, cols[j].y, h), cA, cols[j].g);
         if (first || e > 0.0) {
             e -= raise(e);
             first = false;
@@ -1372,7 +1471,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, con
         float a0 = 0.f, a1[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) a1[k] = 0.f;
-        adjoint_accumulate<M, D>(x, yc + j * D, ycf + j * D, fexp2(e), a0, a1);
+        adjoint_accumulate<M, D>(x, cols[j].y, cols[j].yf, fexp2(e), a0, a1);
         s0 += (double)a0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s1[k] += (double)a1[k];

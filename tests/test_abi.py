@@ -45,7 +45,7 @@ def test_ctypes_layout_matches_c(tmp_path):
         "sizeof(lamp_cert), sizeof(lamp_report), offsetof(lamp_problem, cost_norm),"
         "offsetof(lamp_params, check_every), offsetof(lamp_report, row_fallbacks),"
         "offsetof(lamp_params, track_dt), offsetof(lamp_state, dt_partial),"
-        "offsetof(lamp_cert, midpoint_bound), offsetof(lamp_problem, cost_type));return 0;}\n")
+        "offsetof(lamp_cert, dual_eta_nu), offsetof(lamp_problem, cost_type));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
@@ -54,7 +54,7 @@ def test_ctypes_layout_matches_c(tmp_path):
             ctypes.sizeof(_lib.Trace), ctypes.sizeof(_lib.Cert), ctypes.sizeof(_lib.Report),
             _lib.Problem.cost_norm.offset, _lib.Params.check_every.offset,
             _lib.Report.row_fallbacks.offset, _lib.Params.track_dt.offset, _lib.State.dt_partial.offset,
-            _lib.Cert.midpoint_bound.offset, _lib.Problem.cost_type.offset]
+            _lib.Cert.dual_eta_nu.offset, _lib.Problem.cost_type.offset]
     assert got == want
 
 

@@ -204,6 +204,27 @@ def test_gmm64_65536_mfma_step(form, dtype, kstep):
     _check_step(wl, key, form, 300, RP.Cost(s, 1.0, gram=(xr, yr, nx, ny)), logz_tol, col_tol)
 
 
+def test_sphere_cube_262144_bf16_step():
+    """2^18 x 2^18, d = 3: one BF16 matrix-core iteration at t = 400 (every row, sampled columns)
+    against the oracle's pass over the cost the form computes (centred coordinates rounded to
+    BF16, FP64 inner products, unrounded squared norms); tolerances from the FP32-assembly bound."""
+    key = "sphere_cube_262144"
+    wl = W.sphere_cube()
+    x = wl.x.astype(np.float64)
+    y = wl.y.astype(np.float64)
+    mu = 0.5 * (x[0] + y[0])
+    xc, yc = x - mu, y - mu
+    xr, yr = round_to_type(xc, "bfloat16"), round_to_type(yc, "bfloat16")
+    nx, ny = np.sum(xc * xc, axis=1), np.sum(yc * yc, axis=1)
+    s = GOLD[key]["cost_scale"]
+    nu, th, lam_t, lam_t1 = _synthetic_state(wl, 400, seed=77)
+    term = mfma_term_bound(xr, yr, ny, s, lam_t1, [nu, th], 16, 16)
+    logz_tol = term + (wl.m / 256 + 6) * U32
+    col_tol = logz_tol + term + (wl.n / 256 + 6) * U32
+    _say(f"per-term bound {term:.2e}: logZ tol {logz_tol:.2e}, column tol {col_tol:.2e}")
+    _check_step(wl, key, "bf16_mfma", 400, RP.Cost(s, 1.0, gram=(xr, yr, nx, ny)), logz_tol, col_tol)
+
+
 def test_sphere_cube_bf16_forward_then_fp32_adjoint():
     """The differentiation workload end to end: 2^18 x 2^18, d = 3, BF16-MFMA forward from the
     start until ||col(X^t) - c||_1 <= 1e-4, then the FP32 adjoint at the final state; 16 random

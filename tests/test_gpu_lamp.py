@@ -242,7 +242,13 @@ def test_status_codes():
     assert e.value.status == -2
     with pytest.raises(P.LampError) as e:
         P.step(P.Problem(wl.x, wl.y, wl.r * 1.01, wl.c), P.make_params(), P.State.fresh(30))
-    assert e.value.status == -2
+    assert e.value.status == -2 and "sums to" in str(e.value)
+    bad_c = wl.c.copy()
+    bad_c[7] = np.nan
+    bad_c[19] = 0.0
+    with pytest.raises(P.LampError) as e:   # the first entry that is not a positive finite mass
+        P.step(P.Problem(wl.x, wl.y, wl.r, bad_c), P.make_params(), P.State.fresh(30))
+    assert e.value.status == -2 and "c[7]" in str(e.value)
     with pytest.raises(P.LampError) as e:
         P.step(P.Problem(wl.x, wl.y, wl.r, wl.c), P.make_params(eta=5.0), P.State.fresh(30))
     assert e.value.status == -1
@@ -502,3 +508,33 @@ def test_row_fallback_path_at_large_tau1():
         g = _gpu_state(st_k.nu, st_k.theta, st_k.t, st_k.lam)
         res, tr = P.step(prob, params, g, trace=True)
         _compare_step(tr, tr_n, 0, g, st_n, f"tau1 = 100, step from t = {k}")
+
+
+@pytest.mark.parametrize("kind,eta", [("sqeuclid", 1e-2), ("sqeuclid", 0.05), ("l1", 0.02)])
+def test_certificate_entropic_dual_values(kind, eta):
+    """D^eta(theta^t) and D^eta(nu^t) (def:dual_spp_e) from the certificate against the oracle's
+    dual_D_eta evaluated at the GPU's own state (so only the D^eta evaluation is compared): each row's
+    softmin is mu_i - eta ln S_i with the minimum mu_i exact in FP64 and S_i a sum of FP32
+    exponentials (each <= 1, one of them 1), whose relative error is a few 2^-24: a row moves by
+    eta x 3 x 2^-24, the weighted sum by as much; allowed eta 1e-6.  At eta = 0 both are NaN."""
+    wl = W.random_small(120, 90, 2, seed=91, eta=eta)
+    x = wl.x.astype(np.float64)
+    y = wl.y.astype(np.float64)
+    s = 1.0 / OL.max_cost(x, y, kind)
+    C = OL.ground_cost(x, y, s, kind)
+    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=s, cost_norm=1.0, metric=kind)
+    params = P.make_params(eta=eta, max_iter=60, check_every=20)
+    st, rep, status = P.solve(prob, params)
+    assert status == 0 and st.t == 60
+    cert = P.certificate(prob, params, st)
+    th, nu = to_np(st.theta), to_np(st.nu)
+    ref_t = OL.dual_D_eta(C, wl.r, wl.c, th, 1.0, eta)
+    ref_n = OL.dual_D_eta(C, wl.r, wl.c, nu, 1.0, eta)
+    _say(kind, eta, f"D^eta(theta) gpu {cert['dual_eta_theta']:.12e} oracle {ref_t:.12e}; "
+                    f"D^eta(nu) gpu {cert['dual_eta_nu']:.12e} oracle {ref_n:.12e}")
+    assert abs(cert["dual_eta_theta"] - ref_t) <= eta * 1e-6
+    assert abs(cert["dual_eta_nu"] - ref_n) <= eta * 1e-6
+    # def:dual_spp_e against def:dual_spp: D - eta log m <= D^eta <= D
+    assert cert["dual_theta"] - eta * math.log(90) - 1e-12 <= cert["dual_eta_theta"] <= cert["dual_theta"] + 1e-12
+    plain = P.certificate(prob, P.make_params(eta=0.0), st)
+    assert math.isnan(plain["dual_eta_theta"]) and math.isnan(plain["dual_eta_nu"])
