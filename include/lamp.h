@@ -237,6 +237,17 @@ lamp_status lamp_certificate(const lamp_problem *prob, const lamp_params *params
                              const lamp_state *state, void *ws, size_t ws_bytes, void *stream,
                              lamp_cert *out);
 
+/* Transport cost <C, X^t> = sum_i r_i sum_j p_ij C_ij of the state's iterate (the cost
+ * term of the certificate, Proposition infeas_bound(a), without its other passes) in one
+ * pass over the pairs: per row, unnormalised weights with a running integer offset and the
+ * sums Z_i, S_i = sum_j q_ij C_ij (FP32 within blocks of 8 columns, FP64 across them), then
+ * s r_i S_i / Z_i summed in a fixed order.  *cost (device, one double) is written
+ * stream-ordered; the call returns without waiting for it.  Requires state->t >= 1 and
+ * point clouds (LAMP_EXPLICIT: LAMP_EINVAL; lamp_certificate reports that cost). */
+lamp_status lamp_transport_cost(const lamp_problem *prob, const lamp_params *params,
+                                const lamp_state *state, void *ws, size_t ws_bytes, void *stream,
+                                double *cost);
+
 /* Envelope gradient of the transport cost with respect to the source points at
  * the state's iterate (not in the paper; the derivative sum_j X_ij dC_ij/dx_i of
  * <C, X> with X = X^t held fixed, at fixed s):

@@ -90,6 +90,8 @@ SYMBOLS = {
     "lamp_backward": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params),
                                 ctypes.POINTER(State), c_double, c_void_p, c_void_p, c_size_t,
                                 c_void_p]),
+    "lamp_transport_cost": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params),
+                                      ctypes.POINTER(State), c_void_p, c_size_t, c_void_p, c_void_p]),
     "lamp_backward_y": (c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Params),
                                   ctypes.POINTER(State), c_double, c_void_p, c_void_p, c_size_t,
                                   c_void_p]),

@@ -210,6 +210,19 @@ def certificate(prob: Problem, params: L.Params, state: State) -> dict:
     return {k: getattr(cert, k) for k, _ in L.Cert._fields_}
 
 
+def transport_cost(prob: Problem, params: L.Params, state: State) -> torch.Tensor:
+    """<C, X^t> of the state's iterate in one pass over the pairs, as a 0-dim FP64 device tensor
+    (written stream-ordered; no host synchronisation)."""
+    lib = L.load()
+    ws, nb = prob.workspace(params)
+    out = torch.empty((), dtype=torch.float64, device=prob.device)
+    p = prob.struct()
+    s = state.struct()
+    _check(lib.lamp_transport_cost(ctypes.byref(p), ctypes.byref(params), ctypes.byref(s), ws, nb,
+                                   _stream_handle(prob.device), out.data_ptr()))
+    return out
+
+
 def backward(prob: Problem, params: L.Params, state: State, grad_out: float = 1.0) -> torch.Tensor:
     """grad_out * sum_j X_ij dC_ij/dx_i at the state's iterate (envelope gradient), n x d FP32."""
     lib = L.load()
@@ -294,9 +307,8 @@ class LampOT(torch.autograd.Function):
             prob.cost_norm = 1.0
         params = make_params(eta=eta, tol=tol, max_iter=max_iter)
         state, report, _ = solve(prob, params)
-        cert = certificate(prob, params, state)
         ctx.lamp = (prob, params, state)
-        return torch.tensor(cert["cost"], dtype=torch.float64, device=x.device)
+        return transport_cost(prob, params, state)
 
     @staticmethod
     def backward(ctx, g):

@@ -646,6 +646,32 @@ void launch_adjoint(const Layout& L, Consts kc, int d, void* ws, double cA, cons
         hipLaunchKernelGGL(adjoint_sweep_dyn, g, dim3(BLOCK), 0, st, kc, d, cA, xc, yc, ycf, gA, part, L.split_r);
 }
 
+// <C, X^t> in one pass over the pairs: per row the split sums (M, Z, S_C), then s r_i S_C / Z
+// per row into rows (n doubles) and their fixed-order sum into *out (device).
+void launch_cost(const Layout& L, Consts kc, int d, void* ws, double cA, const double* gA, const double* r,
+                 double* rows, double* out, hipStream_t st) {
+    dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
+    double* part = at<double>(ws, L.rpart);
+    const double* xc = at<double>(ws, L.xc);
+    const double* yc = at<double>(ws, L.yc);
+    const double* xn2 = at<double>(ws, L.xn2);
+    const double* yn2 = at<double>(ws, L.yn2);
+    const bool done = by_metric(kc.metric, [&](auto m) {
+        return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
+            constexpr int D = decltype(dd)::value;
+            // the column records follow gA in the scratch region (sized for them in layout())
+            auto* cols = reinterpret_cast<CostCol<D>*>(at<char>(ws, L.scratch) + align256(sizeof(double) * kc.m));
+            hipLaunchKernelGGL((cost_pack<D>), grid1(kc.m), dim3(BLOCK), 0, st, kc.m, yc, yn2, gA, cols);
+            hipLaunchKernelGGL((cost_sweep<decltype(m)::value, D>), g, dim3(BLOCK), 0, st, kc, cA, xc, xn2,
+                               (const CostCol<D>*)cols, part, L.split_r);
+        });
+    });
+    if (!done)
+        hipLaunchKernelGGL(cost_sweep_dyn, g, dim3(BLOCK), 0, st, kc, d, cA, xc, yc, xn2, yn2, gA, part, L.split_r);
+    hipLaunchKernelGGL(cost_finish, grid1(kc.n), dim3(BLOCK), 0, st, kc, (int)L.P_r, r, (const double*)part, rows);
+    hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, (const double*)rows, kc.n, kc.n, 1, out);
+}
+
 __global__ void fill_scaled(int64_t cnt, double f, const double* __restrict__ in, double* __restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) out[i] = f * in[i];
@@ -1773,6 +1799,31 @@ lamp_status lamp_backward(const lamp_problem* prob, const lamp_params* params, c
     launch_adjoint(L, kc, prob->d, ws, cA, gA, st);
     hipLaunchKernelGGL(adjoint_finish, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->d, (int)L.P_r,
                        grad_out * 2.0 * R.s, at<double>(ws, L.xc), prob->r, at<double>(ws, L.rpart), grad_x);
+    HIPCHK(hipGetLastError());
+    return LAMP_OK;
+}
+
+lamp_status lamp_transport_cost(const lamp_problem* prob, const lamp_params* params, const lamp_state* state,
+                                void* ws, size_t ws_bytes, void* stream, double* cost) {
+    lamp_problem canon_buf;
+    prob = canonical(prob, &canon_buf);
+    hipStream_t st = (hipStream_t)stream;
+    lamp_status e;
+    if ((e = check_state(state)) != LAMP_OK) return e;
+    if (state->t < 1 || !(state->inv_eta > 0.0)) return fail(LAMP_EINVAL, "the transport cost needs t >= 1");
+    if (!cost) return fail(LAMP_EINVAL, "cost is NULL");
+    if (prob && prob->metric == LAMP_EXPLICIT)
+        return fail(LAMP_EINVAL, "an explicit cost matrix takes lamp_certificate for <C, X^t>");
+    Resolved R;
+    if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
+    const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
+    const Consts kc = make_consts(prob, R);
+    // the same weights as the adjoint: the sweep keeps its own per-row offsets
+    const double cA = 2.0 * R.s * state->inv_eta * LOG2E;
+    double* gA = at<double>(ws, L.scratch);
+    hipLaunchKernelGGL(state_col_term, grid1(kc.m), dim3(BLOCK), 0, st, kc, state->inv_eta, at<double>(ws, L.yn2),
+                       state->nu, gA);
+    launch_cost(L, kc, prob->d, ws, cA, gA, prob->r, at<double>(ws, L.dtrow), cost, st);
     HIPCHK(hipGetLastError());
     return LAMP_OK;
 }

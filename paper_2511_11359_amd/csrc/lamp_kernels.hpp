@@ -1346,42 +1346,78 @@ __global__ void col_products(Consts kc, const double* __restrict__ c, const doub
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float sgnf(double v) { return v > 0.0 ? 1.f : (v < 0.0 ? -1.f : 0.f); }
 
-// Accumulates one column's weight q into the FP32 block sums of the adjoint.
-template <int M, int D>
-__device__ __forceinline__ void adjoint_accumulate(const double (&x)[D], const double* __restrict__ yj,
-                                                   const float* __restrict__ yjf, float q, float& a0,
-                                                   float (&a1)[D]) {
-    a0 += q;
-    if constexpr (M == METRIC_SQEUCLID) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) a1[k] = fmaf(q, yjf[k], a1[k]);
-    } else if constexpr (M == METRIC_L1) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) a1[k] = fmaf(-0.5f * q, sgnf(x[k] - yj[k]), a1[k]);
-    } else {
-        int ks = 0;
-        double best = -1.0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const double t = fabs(x[k] - yj[k]);
-            if (t > best) {
-                best = t;
-                ks = k;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < D; ++k)
-            if (k == ks) a1[k] = fmaf(-0.5f * q, sgnf(x[k] - yj[k]), a1[k]);
-    }
-}
+// The one-pass row sweeps at X^t -- the adjoint above and the transport cost
+// <C, X^t> = sum_i r_i sum_j p_ij C_ij -- share the exponent assembly and the offset
+// handling; what each adds per column is a policy:
+//   Col     the column record, read with a few wide scalar loads;
+//   W       the number of sums (FP32 within a block of columns, FP64 across blocks);
+//   block   called with the dot products' initial value hb of each block of columns;
+//   add     accumulates one column with weight q, given ph = hb + P_ij.
 
-// One column's data for the adjoint sweep in one record (read with a few wide scalar loads):
-// y~_j in FP64 (dot product), g^A_j, y~_j in FP32 (the S1 sums).
+// One column's data for the adjoint: y~_j in FP64 (dot product), g^A_j, y~_j in FP32 (S1).
 template <int D>
 struct alignas(16) AdjCol {
     double y[D];
     double g;
     float yf[D];
+};
+
+// The adjoint's sums: Z and S1 (d values, in the form of the metric).
+template <int M, int D>
+struct GradSums {
+    using Col = AdjCol<D>;
+    static constexpr int W = D + 1;
+    __device__ __forceinline__ void block(double) {}
+    __device__ __forceinline__ void add(const double (&x)[D], const Col& c, double, float q, float (&a)[W]) const {
+        a[0] += q;
+        if constexpr (M == METRIC_SQEUCLID) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) a[1 + k] = fmaf(q, c.yf[k], a[1 + k]);
+        } else if constexpr (M == METRIC_L1) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) a[1 + k] = fmaf(-0.5f * q, sgnf(x[k] - c.y[k]), a[1 + k]);
+        } else {
+            int ks = 0;
+            double best = -1.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double t = fabs(x[k] - c.y[k]);
+                if (t > best) {
+                    best = t;
+                    ks = k;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (k == ks) a[1 + k] = fmaf(-0.5f * q, sgnf(x[k] - c.y[k]), a[1 + k]);
+        }
+    }
+};
+
+// One column's data for the transport cost: y~_j (FP64), g^A_j, |y~_j|^2.
+template <int D>
+struct alignas(16) CostCol {
+    double y[D];
+    double g;
+    double yn2;
+};
+
+// The transport cost's sums: Z and S_C = sum_j q_ij C_ij / s.  C_ij / s = |x~_i|^2 + |y~_j|^2
+// - 2 P_ij is taken from the exponent's dot product ph = hb + P_ij as
+// (|x~_i|^2 + 2 hb + |y~_j|^2) - 2 ph, two FP64 operations per pair (the norms are zero
+// for l1 / l_inf, where P_ij = -dist / 2); each term is nonnegative, so the FP32 block sums
+// lose no digits to cancellation.
+template <int M, int D>
+struct CostSums {
+    using Col = CostCol<D>;
+    static constexpr int W = 2;
+    double xn2 = 0.0, a = 0.0;
+    __device__ __forceinline__ void block(double hb) { a = xn2 + 2.0 * hb; }
+    __device__ __forceinline__ void add(const double (&)[D], const Col& c, double ph, float q, float (&s)[W]) const {
+        s[0] += q;
+        const double cs = fma(-2.0, ph, M == METRIC_SQEUCLID ? a + c.yn2 : a);
+        s[1] = fmaf(q, (float)cs, s[1]);
+    }
 };
 
 template <int D>
@@ -1399,10 +1435,29 @@ __global__ void adjoint_pack(int64_t m, const double* __restrict__ yc, const flo
     out[j] = c;
 }
 
-template <int M, int D>
-__global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, const double* __restrict__ xc,
-                                                       const AdjCol<D>* __restrict__ cols,
-                                                       double* __restrict__ part, int64_t split) {
+template <int D>
+__global__ void cost_pack(int64_t m, const double* __restrict__ yc, const double* __restrict__ yn2,
+                          const double* __restrict__ gA, CostCol<D>* __restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    CostCol<D> c;
+#pragma unroll
+    for (int k = 0; k < D; ++k) c.y[k] = yc[j * D + k];
+    c.g = gA[j];
+    c.yn2 = yn2[j];
+    out[j] = c;
+}
+
+// Per row i and column split p: the split's offset M_ip, an integer that each lane raises to
+// ceil(max e) whenever a block of columns exceeds it (the first block sets it), so every
+// term is at most 1 and a raise rescales the sums exactly by a power of two; then the W sums
+// of the policy.  part: [P][n][W + 1] = (M, sums); an empty split writes M = -inf.
+template <int M, int D, class Pol>
+__device__ __forceinline__ void weighted_row_sums(const Consts& kc, double cA, const double* __restrict__ xc,
+                                                  const typename Pol::Col* __restrict__ cols, Pol pol,
+                                                  double* __restrict__ part, int64_t split) {
+    constexpr int W = Pol::W;
+    using Col = typename Pol::Col;
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t p = blockIdx.y;
     const int64_t j0 = p * split;
@@ -1414,16 +1469,15 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, con
     double off = 0.0;      // M: integer offset of this lane's exponents
     double h = 0.0;        // -M / cfac, the dot products' initial value
     bool first = true;
-    double s0 = 0.0, s1[D];
+    double s[W];
 #pragma unroll
-    for (int k = 0; k < D; ++k) s1[k] = 0.0;
+    for (int w = 0; w < W; ++w) s[w] = 0.0;
     // raise the offset by ceil(bm) (bm: the largest exponent under the current offset),
     // rescaling the sums exactly; returns the raise
     auto raise = [&](double bm) {
         const double sh = ceil(bm);
-        s0 = ldexp(s0, -(int)sh);
 #pragma unroll
-        for (int k = 0; k < D; ++k) s1[k] = ldexp(s1[k], -(int)sh);
+        for (int w = 0; w < W; ++w) s[w] = ldexp(s[w], -(int)sh);
         off += sh;
         h = -off / cA;
         return sh;
@@ -1431,14 +1485,16 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, con
     // blocks of UNROLL columns with a compile-time trip count (the column data are
     // wave-uniform scalar loads, issued together); the offset is checked once per block
     const int64_t nfull = (j1 - j0) / UNROLL;
-    const AdjCol<D>* __restrict__ cp = cols + j0;
+    const Col* __restrict__ cp = cols + j0;
     for (int64_t c = 0; c < nfull; ++c, cp += UNROLL) {
-        double e[UNROLL];
+        const double hb = h;
+        double ph[UNROLL], e[UNROLL];
         float ef[UNROLL];
         float bm = -__builtin_inff();
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            e[u] = fma_su(pair_term<M, D>(x, cp[u].y, h), cA, cp[u].g);
+            ph[u] = pair_term<M, D>(x, cp[u].y, hb);
+            e[u] = fma_su(ph[u], cA, cp[u].g);
             ef[u] = (float)e[u];
             bm = fmaxf(bm, ef[u]);
         }
@@ -1451,38 +1507,112 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, con
             for (int u = 0; u < UNROLL; ++u) ef[u] = (float)(e[u] - sh);
             first = false;
         }
-        float a0 = 0.f, a1[D];
+        pol.block(hb);
+        float a[W];
 #pragma unroll
-        for (int k = 0; k < D; ++k) a1[k] = 0.f;
+        for (int w = 0; w < W; ++w) a[w] = 0.f;
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-            adjoint_accumulate<M, D>(x, cp[u].y, cp[u].yf, __builtin_amdgcn_exp2f(ef[u]), a0, a1);
-        s0 += (double)a0;
+        for (int u = 0; u < UNROLL; ++u) pol.add(x, cp[u], ph[u], __builtin_amdgcn_exp2f(ef[u]), a);
 #pragma unroll
-        for (int k = 0; k < D; ++k) s1[k] += (double)a1[k];
+        for (int w = 0; w < W; ++w) s[w] += (double)a[w];
     }
     // the remaining columns one at a time
     for (int64_t j = j0 + nfull * UNROLL; j < j1; ++j) {
-        double e = fma_su(pair_term<M, D>(x, cols[j].y, h), cA, cols[j].g);
+        const double hb = h;
+        const double ph = pair_term<M, D>(x, cols[j].y, hb);
+        double e = fma_su(ph, cA, cols[j].g);
         if (first || e > 0.0) {
             e -= raise(e);
             first = false;
         }
-        float a0 = 0.f, a1[D];
+        pol.block(hb);
+        float a[W];
 #pragma unroll
-        for (int k = 0; k < D; ++k) a1[k] = 0.f;
-        adjoint_accumulate<M, D>(x, cols[j].y, cols[j].yf, fexp2(e), a0, a1);
-        s0 += (double)a0;
+        for (int w = 0; w < W; ++w) a[w] = 0.f;
+        pol.add(x, cols[j], ph, fexp2(e), a);
 #pragma unroll
-        for (int k = 0; k < D; ++k) s1[k] += (double)a1[k];
+        for (int w = 0; w < W; ++w) s[w] += (double)a[w];
     }
     if (i < kc.n) {
-        double* o = part + (p * kc.n + i) * (D + 2);
+        double* o = part + (p * kc.n + i) * (W + 1);
         o[0] = first ? -__builtin_inf() : off;   // an empty split contributes nothing
-        o[1] = s0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) o[2 + k] = s1[k];
+        for (int w = 0; w < W; ++w) o[1 + w] = s[w];
     }
+}
+
+// part: [P][n][D + 2] = (M, Z, S1).
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void adjoint_sweep(Consts kc, double cA, const double* __restrict__ xc,
+                                                       const AdjCol<D>* __restrict__ cols,
+                                                       double* __restrict__ part, int64_t split) {
+    weighted_row_sums<M, D>(kc, cA, xc, cols, GradSums<M, D>{}, part, split);
+}
+
+// part: [P][n][3] = (M, Z, S_C).
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void cost_sweep(Consts kc, double cA, const double* __restrict__ xc,
+                                                    const double* __restrict__ xn2,
+                                                    const CostCol<D>* __restrict__ cols,
+                                                    double* __restrict__ part, int64_t split) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    CostSums<M, D> pol;
+    if constexpr (M == METRIC_SQEUCLID) pol.xn2 = xn2[i < kc.n ? i : kc.n - 1];
+    weighted_row_sums<M, D>(kc, cA, xc, cols, pol, part, split);
+}
+
+// The transport cost for any dimension and metric at run time, FP64 sums.  part as above.
+__global__ __launch_bounds__(BLOCK) void cost_sweep_dyn(Consts kc, int D, double cA,
+                                                        const double* __restrict__ xc,
+                                                        const double* __restrict__ yc,
+                                                        const double* __restrict__ xn2,
+                                                        const double* __restrict__ yn2,
+                                                        const double* __restrict__ gA,
+                                                        double* __restrict__ part, int64_t split) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t p = blockIdx.y;
+    const int64_t j0 = p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
+    if (i >= kc.n) return;
+    const double* xi = xc + i * D;
+    double off = -__builtin_inf(), s0 = 0.0, sc = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        const double pij = pair_term_dyn(kc, D, xi, yc + j * D, 0.0);
+        const double e = fma(cA, pij, gA[j]);
+        if (e > off) {   // raise the offset to ceil(e), rescaling the sums exactly
+            const double nm = ceil(e);
+            const int sh = j == j0 ? 0 : (int)(off - nm);
+            s0 = ldexp(s0, sh);
+            sc = ldexp(sc, sh);
+            off = nm;
+        }
+        const double q = (double)fexp2(e - off);
+        s0 += q;
+        sc += q * fma(-2.0, pij, xn2[i] + yn2[j]);
+    }
+    double* o = part + (p * kc.n + i) * 3;
+    o[0] = off;
+    o[1] = s0;
+    o[2] = sc;
+}
+
+// Row i's share of the transport cost, s r_i S_C / Z, from the splits' (M, Z, S_C) brought to
+// their common offset (exact powers of two).
+__global__ void cost_finish(Consts kc, int P, const double* __restrict__ r, const double* __restrict__ part,
+                            double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    double off = -__builtin_inf();
+    for (int p = 0; p < P; ++p) off = fmax(off, part[((int64_t)p * kc.n + i) * 3]);
+    double z = 0.0, c = 0.0;
+    for (int p = 0; p < P; ++p) {
+        const double* o = part + ((int64_t)p * kc.n + i) * 3;
+        if (o[0] > -__builtin_inf()) {
+            z += ldexp(o[1], (int)(o[0] - off));
+            c += ldexp(o[2], (int)(o[0] - off));
+        }
+    }
+    out[i] = kc.s * r[i] * (c / z);
 }
 
 __global__ __launch_bounds__(BLOCK) void adjoint_sweep_dyn(Consts kc, int D, double cA,
