@@ -896,6 +896,9 @@ void launch_iteration(const lamp_problem* p, const Layout& L, Consts kc, void* w
                        col_parts(L), p->c, at<double>(ws, L.yn2), ia.buf, at<double2>(ws, L.gtab),
                        gtabf_ptr(L, ws), L.m_pad, at<double>(ws, L.respart), ia.tc,
                        ia.track_dt ? at<double>(ws, L.dtpart) : (double*)nullptr);
+    hipLaunchKernelGGL(dual_finish, dim3(1), dim3(BLOCK), 0, st, ctrl, sch, (const double*)at<double>(ws, L.respart),
+                       ia.track_dt ? (const double*)at<double>(ws, L.dtpart) : (const double*)nullptr,
+                       cdiv(kc.m, BLOCK));
 }
 
 lamp_status upload_ctrl(void* ws, const Layout& L, int64_t t, int64_t t_end, int64_t t_base, double tol,
@@ -909,7 +912,6 @@ lamp_status upload_ctrl(void* ws, const Layout& L, int64_t t, int64_t t_end, int
     host->done = 0;
     host->err = 0;
     host->fallbacks = 0;
-    host->counter = 0;
     host->tol = tol;
     host->res_last = -1.0;
     HIPCHK(hipMemcpyAsync(at<Ctrl>(ws, L.ctrl), host, sizeof(Ctrl), hipMemcpyHostToDevice, st));
@@ -1003,7 +1005,7 @@ struct BatchCand {
     int64_t target_total;   // sweep blocks per phase over the whole batch
     int grid;               // persistent grid size of the phase kernels
 };
-const BatchCand kBatchCands[] = {{2048, 1024}, {4096, 1024}, {4096, 2048}, {8192, 2048}, {16384, 2048},
+constexpr BatchCand kBatchCands[] = {{2048, 1024}, {4096, 1024}, {4096, 2048}, {8192, 2048}, {16384, 2048},
                                  {16384, 4096}};
 constexpr int kNumBatchCands = (int)(sizeof(kBatchCands) / sizeof(kBatchCands[0]));
 
@@ -1028,72 +1030,64 @@ __global__ void rewind_ctrl(const ProbDesc* __restrict__ pd, int count, int64_t 
         c->t_end = t_end;
         c->done = 0;
         c->err = 0;
-        c->counter = 0u;
     }
 }
 
-// Point dimensions with their own batch sweep kernels (0: every other dimension).
-constexpr int kBatchDims[] = {1, 2, 3, 4, 8, 16, 0};
-constexpr int kNumBatchDims = (int)(sizeof(kBatchDims) / sizeof(kBatchDims[0]));
-
-int batch_dim_group(int d) {
-    for (int g = 0; g < kNumBatchDims - 1; ++g)
-        if (kBatchDims[g] == d) return g;
-    return kNumBatchDims - 1;
+// The most sweep blocks any candidate spreads over a batch: the capacity of the sweep
+// partials and work lists, whatever share of it a problem gets.
+constexpr int64_t max_target() {
+    int64_t t = 0;
+    for (const BatchCand& c : kBatchCands) t = c.target_total > t ? c.target_total : t;
+    return t;
 }
+constexpr int64_t kMaxTarget = max_target();
 
 struct BatchPlan {
-    std::vector<Layout> L;
-    std::vector<size_t> sub;      // per-problem sub-workspace offsets
+    std::vector<Layout> L;                // per-problem buffers and set-up passes
+    std::vector<size_t> sub;              // per-problem sub-workspace offsets
+    std::vector<size_t> rpartB, cpartB;   // per-problem sweep partials, room for the most splits
     size_t descs, items[4], ctrlv, sched, counters, nact, total;
-    int n_items[4];
-    // sweep items (phases 0 and 2) are grouped by dimension: group g occupies
-    // [grp_off[k][g], grp_off[k][g] + grp_cnt[k][g]) of the phase's list
-    int grp_off[4][kNumBatchDims], grp_cnt[4][kNumBatchDims];
+    int cap_items[4];                     // list capacities; lists 1 and 3 are always full
 };
 
 // Relative cost of one pair in the vector-ALU sweeps: d FP64 FMAs for the dot product
 // plus about 10 issue slots for the two exponents (assembly, conversion, exp, sum).
 double pair_cost(int d) { return (double)(d + 10); }
 
-BatchPlan batch_plan(const lamp_problem* probs, int count, int cand) {
+BatchPlan batch_plan(const lamp_problem* probs, int count) {
     BatchPlan B;
-    double wsum = 0.0;
-    for (int p = 0; p < count; ++p) wsum += (double)probs[p].n * (double)probs[p].m * pair_cost(probs[p].d);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off += align256(bytes);
         return o;
     };
-    for (int k = 0; k < 4; ++k) B.n_items[k] = 0;
+    for (int k = 0; k < 4; ++k) B.cap_items[k] = 0;
     B.L.resize(count);
+    std::vector<int64_t> pr(count), pc(count);
     for (int p = 0; p < count; ++p) {
-        // sweep items of about equal cost across the batch
-        const double share = (double)probs[p].n * (double)probs[p].m * pair_cost(probs[p].d) / wsum;
-        const int64_t target = std::max<int64_t>(1, (int64_t)std::llround(kBatchCands[cand].target_total * share));
-        B.L[p] = layout(probs[p].n, probs[p].m, probs[p].d, LAMP_FP32, target);
-        const int64_t rb = cdiv(probs[p].n, BLOCK), cb = cdiv(probs[p].m, BLOCK);
-        B.n_items[0] += (int)(rb * B.L[p].P_r);
-        B.n_items[1] += (int)rb;
-        B.n_items[2] += (int)(cb * B.L[p].P_c);
-        B.n_items[3] += (int)cb;
+        const lamp_problem& q = probs[p];
+        B.L[p] = layout(q.n, q.m, q.d, LAMP_FP32);
+        pr[p] = cdiv(q.m, choose_split(q.n, q.m, kMaxTarget));
+        pc[p] = cdiv(q.n, choose_split(q.m, q.n, kMaxTarget));
+        const int64_t rb = cdiv(q.n, BLOCK), cb = cdiv(q.m, BLOCK);
+        B.cap_items[0] += (int)(rb * pr[p]);
+        B.cap_items[1] += (int)rb;
+        B.cap_items[2] += (int)(cb * pc[p]);
+        B.cap_items[3] += (int)cb;
     }
     B.descs = take(sizeof(ProbDesc) * count);
-    for (int k = 0; k < 4; ++k) B.items[k] = take(sizeof(Item) * B.n_items[k]);
-    for (int k = 0; k < 4; ++k)
-        for (int g = 0; g < kNumBatchDims; ++g) B.grp_off[k][g] = B.grp_cnt[k][g] = 0;
-    for (int k : {0, 2}) {
-        for (int p = 0; p < count; ++p) {
-            const int64_t blocks = cdiv(k == 0 ? probs[p].n : probs[p].m, BLOCK);
-            B.grp_cnt[k][batch_dim_group(probs[p].d)] += (int)(blocks * (k == 0 ? B.L[p].P_r : B.L[p].P_c));
-        }
-        for (int g = 1; g < kNumBatchDims; ++g) B.grp_off[k][g] = B.grp_off[k][g - 1] + B.grp_cnt[k][g - 1];
-    }
-    B.counters = take(sizeof(unsigned) * 2 * kNumBatchDims);
-    B.nact = take(sizeof(int) * 2 * kNumBatchDims);
+    for (int k = 0; k < 4; ++k) B.items[k] = take(sizeof(Item) * B.cap_items[k]);
+    B.counters = take(sizeof(unsigned) * 2);
+    B.nact = take(sizeof(int) * 2);
     B.ctrlv = take(sizeof(Ctrl) * count);
     B.sched = take(sizeof(Sched) * (TAB + 2));
+    B.rpartB.resize(count);
+    B.cpartB.resize(count);
+    for (int p = 0; p < count; ++p) {
+        B.rpartB[p] = take(sizeof(double2) * probs[p].n * pr[p]);
+        B.cpartB[p] = take(sizeof(double2) * probs[p].m * pc[p]);
+    }
     B.sub.resize(count);
     for (int p = 0; p < count; ++p) B.sub[p] = take(B.L[p].total);
     B.total = off;
@@ -1109,51 +1103,76 @@ std::string batch_signature(const lamp_problem* probs, int count) {
 
 struct BatchRun {
     BatchPlan B;
-    std::vector<Item> sweep_items[2];       // all row / column sweep items, grouped and sorted
-    std::vector<Item> upload[2];            // the active part, as last uploaded
-    std::vector<int> nact_host;             // active item count per (phase, group)
+    std::vector<Item> lists[2];   // row / column sweep items of the running problems, largest first
     std::vector<ProbDesc> desc;
     std::vector<Resolved> R;
     std::vector<double*> nu1, th1;
     int grid;
+    int64_t target_total;
     double tau1;
 };
 
 void* sub_ws(void* ws, const BatchPlan& B, int p) { return static_cast<char*>(ws) + B.sub[p]; }
 
-// Uploads the sweep items of the running problems (active[p] != 0) to the front of each
-// dimension group's segment, in the stored order, and the per-group counts the sweep
-// kernels read; the graph's launch arguments stay valid.  Synchronises the stream.
-lamp_status batch_upload_sweeps(BatchRun* run, const std::vector<char>& active, void* ws, hipStream_t st) {
-    const BatchPlan& B = run->B;
-    run->nact_host.assign(2 * kNumBatchDims, 0);
-    for (int h = 0; h < 2; ++h) {
-        const int k = h == 0 ? 0 : 2;
-        std::vector<Item>& up = run->upload[h];
-        up.clear();
-        const std::vector<Item>& all = run->sweep_items[h];
-        for (int g = 0; g < kNumBatchDims; ++g) {
-            const int beg = B.grp_off[k][g], end = beg + B.grp_cnt[k][g];
-            int n = 0;
-            for (int i = beg; i < end; ++i)
-                if (active[all[i].prob]) {
-                    up.push_back(all[i]);
-                    ++n;
+// The running problems (active[p] != 0) share the candidate's sweep blocks in proportion to
+// their work (n m times the pair cost of the dimension): each gets the splits of its share,
+// and the two sweep lists hold all their items, largest first (an item's cost: its rows x
+// its columns x the pair cost), so that the persistent sweeps end on small items.
+void batch_assign(BatchRun* run, const lamp_problem* probs, const std::vector<char>& active) {
+    const int count = (int)run->desc.size();
+    double wsum = 0.0;
+    for (int p = 0; p < count; ++p)
+        if (active[p]) wsum += (double)probs[p].n * (double)probs[p].m * pair_cost(probs[p].d);
+    std::vector<double> icost[2];
+    for (int h = 0; h < 2; ++h) run->lists[h].clear();
+    for (int p = 0; p < count; ++p) {
+        if (!active[p]) continue;
+        const lamp_problem& q = probs[p];
+        const double w = (double)q.n * (double)q.m * pair_cost(q.d);
+        const int64_t target = std::max<int64_t>(1, (int64_t)std::llround((double)run->target_total * w / wsum));
+        ProbDesc& D = run->desc[p];
+        D.split_r = choose_split(q.n, q.m, target);
+        D.P_r = (int)cdiv(q.m, D.split_r);
+        D.split_c = choose_split(q.m, q.n, target);
+        D.P_c = (int)cdiv(q.n, D.split_c);
+        for (int h = 0; h < 2; ++h) {
+            const int64_t own = h == 0 ? q.n : q.m, other = h == 0 ? q.m : q.n;
+            const int64_t split = h == 0 ? D.split_r : D.split_c;
+            const int64_t P = h == 0 ? D.P_r : D.P_c;
+            for (int64_t y = 0; y < P; ++y)
+                for (int64_t x = 0; x < cdiv(own, BLOCK); ++x) {
+                    run->lists[h].push_back(Item{p, (int)x, (int)y, 0});
+                    const double rows = (double)std::min<int64_t>(BLOCK, own - x * BLOCK);
+                    const double cols = (double)std::min<int64_t>(split, other - y * split);
+                    icost[h].push_back(rows * cols * pair_cost(q.d));
                 }
-            run->nact_host[h * kNumBatchDims + g] = n;
-        }
-        // group g's active items start at its segment offset
-        int pos = 0;
-        for (int g = 0; g < kNumBatchDims; ++g) {
-            const int n = run->nact_host[h * kNumBatchDims + g];
-            if (n > 0)
-                HIPCHK(hipMemcpyAsync(at<Item>(ws, B.items[k]) + B.grp_off[k][g], up.data() + pos, sizeof(Item) * n,
-                                      hipMemcpyHostToDevice, st));
-            pos += n;
         }
     }
-    HIPCHK(hipMemcpyAsync(at<int>(ws, B.nact), run->nact_host.data(), sizeof(int) * run->nact_host.size(),
+    for (int h = 0; h < 2; ++h) {
+        std::vector<int> ord(run->lists[h].size());
+        for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return icost[h][a] > icost[h][b]; });
+        std::vector<Item> sorted(ord.size());
+        for (size_t i = 0; i < ord.size(); ++i) sorted[i] = run->lists[h][ord[i]];
+        run->lists[h].swap(sorted);
+    }
+}
+
+// Uploads the descriptors (their splits), the two sweep lists and their lengths, which the
+// sweep kernels read from device memory (the captured graph's launch arguments stay valid).
+// Synchronises the stream: the copies read host vectors of the run.
+lamp_status batch_upload(const BatchRun& run, void* ws, hipStream_t st) {
+    const BatchPlan& B = run.B;
+    HIPCHK(hipMemcpyAsync(at<ProbDesc>(ws, B.descs), run.desc.data(), sizeof(ProbDesc) * run.desc.size(),
                           hipMemcpyHostToDevice, st));
+    int nact[2];
+    for (int h = 0; h < 2; ++h) {
+        nact[h] = (int)run.lists[h].size();
+        if (nact[h] > 0)
+            HIPCHK(hipMemcpyAsync(at<Item>(ws, B.items[h == 0 ? 0 : 2]), run.lists[h].data(), sizeof(Item) * nact[h],
+                                  hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipMemcpyAsync(at<int>(ws, B.nact), nact, sizeof(nact), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     return LAMP_OK;
 }
@@ -1162,9 +1181,10 @@ lamp_status batch_upload_sweeps(BatchRun* run, const std::vector<char>& active, 
 // shared schedule, control blocks, column tables, exact offsets, descriptors and work lists.
 lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params* q, const lamp_state* states,
                         void* ws, hipStream_t st, int cand, int64_t t_stop, BatchRun* run) {
-    run->B = batch_plan(probs, count, cand);
+    run->B = batch_plan(probs, count);
     const BatchPlan& B = run->B;
     run->grid = kBatchCands[cand].grid;
+    run->target_total = kBatchCands[cand].target_total;
     run->desc.resize(count);
     run->R.resize(count);
     run->nu1.resize(count);
@@ -1183,7 +1203,7 @@ lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params*
     fill_sched(tab.data(), TAB, states[0].inv_eta, run->tau1, q->eta);
     HIPCHK(hipMemcpyAsync(at<Sched>(ws, B.sched), tab.data(), sizeof(Sched) * TAB, hipMemcpyHostToDevice, st));
     std::vector<Ctrl> hc(count);
-    std::vector<Item> items[4];
+    std::vector<Item> fin[2];   // row finish / dual update items: one per block of rows / columns
     for (int p = 0; p < count; ++p) {
         const Layout& L = B.L[p];
         void* w = sub_ws(ws, B, p);
@@ -1200,11 +1220,7 @@ lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params*
         D.ctrl = at<Ctrl>(ws, B.ctrlv) + p;
         D.kc = kc;
         D.d = probs[p].d;
-        D.P_r = (int)L.P_r;
-        D.P_c = (int)L.P_c;
         D.n_dual_blocks = (int)cdiv(probs[p].m, BLOCK);
-        D.split_r = L.split_r;
-        D.split_c = L.split_c;
         D.xc = at<double>(w, L.xc);
         D.yc = at<double>(w, L.yc);
         D.xn2 = at<double>(w, L.xn2);
@@ -1215,8 +1231,8 @@ lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params*
         D.H = at<double>(w, L.H);
         D.rowvar = at<RowVar>(w, L.rowvar);
         D.rowck = at<double2>(w, L.rowck);
-        D.rpart = at<double2>(w, L.rpart);
-        D.cpart = at<double2>(w, L.cpart);
+        D.rpart = at<double2>(ws, B.rpartB[p]);
+        D.cpart = at<double2>(ws, B.cpartB[p]);
         run->nu1[p] = at<double>(w, L.nu1);
         run->th1[p] = at<double>(w, L.th1);
         D.buf.nu[t0 & 1] = states[p].nu;
@@ -1224,46 +1240,18 @@ lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params*
         D.buf.nu[(t0 + 1) & 1] = run->nu1[p];
         D.buf.theta[(t0 + 1) & 1] = run->th1[p];
         D.respart = at<double>(w, L.respart);
-        const int64_t rb = cdiv(probs[p].n, BLOCK), cb = cdiv(probs[p].m, BLOCK);
-        for (int64_t y = 0; y < L.P_r; ++y)
-            for (int64_t x = 0; x < rb; ++x) items[0].push_back(Item{p, (int)x, (int)y, 0});
-        for (int64_t x = 0; x < rb; ++x) items[1].push_back(Item{p, (int)x, 0, 0});
-        for (int64_t y = 0; y < L.P_c; ++y)
-            for (int64_t x = 0; x < cb; ++x) items[2].push_back(Item{p, (int)x, (int)y, 0});
-        for (int64_t x = 0; x < cb; ++x) items[3].push_back(Item{p, (int)x, 0, 0});
+        for (int64_t x = 0; x < cdiv(probs[p].n, BLOCK); ++x) fin[0].push_back(Item{p, (int)x, 0, 0});
+        for (int64_t x = 0; x < cdiv(probs[p].m, BLOCK); ++x) fin[1].push_back(Item{p, (int)x, 0, 0});
     }
-    // sweep lists: grouped by dimension (the order of kBatchDims), largest items first within
-    // a group; an item's cost is its rows x its columns x the per-pair cost of its dimension.
-    // Only the items of running problems are uploaded (batch_upload_sweeps).
-    for (int k : {0, 2}) {
-        auto cost = [&](const Item& it) {
-            const lamp_problem& q = probs[it.prob];
-            const Layout& L = B.L[it.prob];
-            const int64_t own = k == 0 ? q.n : q.m, other = k == 0 ? q.m : q.n;
-            const int64_t split = k == 0 ? L.split_r : L.split_c;
-            const int64_t rows = std::min<int64_t>(BLOCK, own - (int64_t)it.bx * BLOCK);
-            const int64_t cols = std::min<int64_t>(split, other - (int64_t)it.by * split);
-            return (double)rows * (double)std::max<int64_t>(cols, 0) * pair_cost(q.d);
-        };
-        std::stable_sort(items[k].begin(), items[k].end(), [&](const Item& a, const Item& b) {
-            const int ga = batch_dim_group(probs[a.prob].d), gb = batch_dim_group(probs[b.prob].d);
-            if (ga != gb) return ga < gb;
-            return cost(a) > cost(b);
-        });
-    }
-    const std::vector<unsigned> zeros(2 * kNumBatchDims, 0u);
-    HIPCHK(hipMemcpyAsync(at<unsigned>(ws, B.counters), zeros.data(), sizeof(unsigned) * zeros.size(),
-                          hipMemcpyHostToDevice, st));
-    run->sweep_items[0] = items[0];
-    run->sweep_items[1] = items[2];
+    batch_assign(run, probs, std::vector<char>(count, 1));
+    const unsigned zeros[2] = {0u, 0u};
+    HIPCHK(hipMemcpyAsync(at<unsigned>(ws, B.counters), zeros, sizeof(zeros), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(at<Ctrl>(ws, B.ctrlv), hc.data(), sizeof(Ctrl) * count, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(at<ProbDesc>(ws, B.descs), run->desc.data(), sizeof(ProbDesc) * count,
-                          hipMemcpyHostToDevice, st));
-    for (int k : {1, 3})
-        HIPCHK(hipMemcpyAsync(at<Item>(ws, B.items[k]), items[k].data(), sizeof(Item) * items[k].size(),
-                              hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));   // the uploads read host vectors of this frame
-    if ((e = batch_upload_sweeps(run, std::vector<char>(count, 1), ws, st)) != LAMP_OK) return e;
+    HIPCHK(hipMemcpyAsync(at<Item>(ws, B.items[1]), fin[0].data(), sizeof(Item) * fin[0].size(), hipMemcpyHostToDevice,
+                          st));
+    HIPCHK(hipMemcpyAsync(at<Item>(ws, B.items[3]), fin[1].data(), sizeof(Item) * fin[1].size(), hipMemcpyHostToDevice,
+                          st));
+    if ((e = batch_upload(*run, ws, st)) != LAMP_OK) return e;   // synchronises: the vectors above are read
     for (int p = 0; p < count; ++p) {
         const Layout& L = B.L[p];
         void* w = sub_ws(ws, B, p);
@@ -1277,46 +1265,24 @@ lamp_status batch_setup(const lamp_problem* probs, int count, const lamp_params*
     return LAMP_OK;
 }
 
-template <bool ROW>
-void batch_sweeps(const BatchRun& run, void* ws, hipStream_t st) {
-    const BatchPlan& B = run.B;
-    const int k = ROW ? 0 : 2;
-    const ProbDesc* pd = at<ProbDesc>(ws, B.descs);
-    const Sched* sch = at<Sched>(ws, B.sched);
-    unsigned* ctr = at<unsigned>(ws, B.counters) + (ROW ? 0 : kNumBatchDims);
-    for (int g = 0; g < kNumBatchDims; ++g) {
-        const int cnt = B.grp_cnt[k][g];
-        if (cnt == 0) continue;
-        const dim3 grid((unsigned)std::max(1, std::min(run.grid, cnt)));
-        const Item* it = at<Item>(ws, B.items[k]) + B.grp_off[k][g];
-        const int* na = at<int>(ws, B.nact) + (ROW ? 0 : kNumBatchDims) + g;
-        switch (kBatchDims[g]) {
-#define CASE(D)                                                                                             \
-    case D:                                                                                                 \
-        if (ROW) hipLaunchKernelGGL(batch_row_sweep<D>, grid, dim3(BLOCK), 0, st, pd, it, na, sch, ctr + g); \
-        else hipLaunchKernelGGL(batch_col_sweep<D>, grid, dim3(BLOCK), 0, st, pd, it, na, sch, ctr + g);    \
-        break;
-            LAMP_BATCH_D(CASE)
-#undef CASE
-            default:
-                if (ROW) hipLaunchKernelGGL(batch_row_sweep<0>, grid, dim3(BLOCK), 0, st, pd, it, na, sch, ctr + g);
-                else hipLaunchKernelGGL(batch_col_sweep<0>, grid, dim3(BLOCK), 0, st, pd, it, na, sch, ctr + g);
-        }
-    }
-}
-
+// One iteration of every running problem: the row sweep, the row finish, the column sweep,
+// the dual update and its finish, one launch each.
 void batch_iteration(const BatchRun& run, void* ws, hipStream_t st) {
     const BatchPlan& B = run.B;
+    const int count = (int)run.desc.size();
     const ProbDesc* pd = at<ProbDesc>(ws, B.descs);
     const Sched* sch = at<Sched>(ws, B.sched);
     unsigned* ctr = at<unsigned>(ws, B.counters);
-    auto g = [&](int n) { return dim3((unsigned)std::max(1, std::min(run.grid, n))); };
-    batch_sweeps<true>(run, ws, st);
-    hipLaunchKernelGGL(batch_row_finish, g(B.n_items[1]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[1]),
-                       B.n_items[1], sch, ctr, kNumBatchDims);
-    batch_sweeps<false>(run, ws, st);
-    hipLaunchKernelGGL(batch_dual_update, g(B.n_items[3]), dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[3]),
-                       B.n_items[3], sch, ctr + kNumBatchDims, kNumBatchDims);
+    const int* na = at<int>(ws, B.nact);
+    const dim3 gr((unsigned)std::max(1, std::min(run.grid, B.cap_items[0])));
+    const dim3 gc((unsigned)std::max(1, std::min(run.grid, B.cap_items[2])));
+    hipLaunchKernelGGL(batch_row_sweep, gr, dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[0]), na, sch, ctr);
+    hipLaunchKernelGGL(batch_row_finish, dim3((unsigned)B.cap_items[1]), dim3(BLOCK), 0, st, pd,
+                       at<Item>(ws, B.items[1]), B.cap_items[1], sch, ctr);
+    hipLaunchKernelGGL(batch_col_sweep, gc, dim3(BLOCK), 0, st, pd, at<Item>(ws, B.items[2]), na + 1, sch, ctr + 1);
+    hipLaunchKernelGGL(batch_dual_update, dim3((unsigned)B.cap_items[3]), dim3(BLOCK), 0, st, pd,
+                       at<Item>(ws, B.items[3]), B.cap_items[3], sch, ctr + 1);
+    hipLaunchKernelGGL(batch_dual_finish, dim3((unsigned)count), dim3(BLOCK), 0, st, pd, sch);
 }
 
 // Autotuner: every candidate launch shape runs a few iterations from the callers' start
@@ -1950,9 +1916,7 @@ size_t lamp_batch_workspace_bytes(const lamp_problem* probs, int32_t count, cons
     if (!probs || count < 1) return 0;
     for (int p = 0; p < count; ++p)
         if (probs[p].n < 1 || probs[p].m < 1 || probs[p].d < 1) return 0;
-    size_t best = 0;
-    for (int c = 0; c < kNumBatchCands; ++c) best = std::max(best, batch_plan(probs, count, c).total);
-    return best + 256;
+    return batch_plan(probs, count).total + 256;
 }
 
 lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const lamp_params* params,
@@ -1994,7 +1958,7 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
     // the first problem's sub-workspace is laid out at offset 0 of a batch plan's problem region;
     // its small-scalar area is scratch here (every problem's preparation rewrites it later)
     {
-        const BatchPlan B0 = batch_plan(probs, count, 0);
+        const BatchPlan B0 = batch_plan(probs, count);
         double* dev6 = at<double>(static_cast<char*>(ws) + B0.sub[0], B0.L[0].small);
         for (int p = 0; p < count; ++p)
             if ((e = check_marginals(&probs[p], dev6, st)) != LAMP_OK) return e;
@@ -2053,11 +2017,15 @@ lamp_status lamp_solve_batched(const lamp_problem* probs, int32_t count, const l
         }
         t_cur = tmax;
         if (t_cur >= t_stop) break;
-        // problems that stopped leave the sweep work lists (no graph change: the kernels read
-        // the item counts from device memory)
-        if (newly_done && (e = batch_upload_sweeps(&run, active, ws, st)) != LAMP_OK) {
-            result = e;
-            break;
+        // problems that stopped leave the sweep work lists and the running ones take over their
+        // share of the sweep blocks (no graph change: the kernels read the splits and the item
+        // counts from device memory)
+        if (newly_done) {
+            batch_assign(&run, probs, active);
+            if ((e = batch_upload(run, ws, st)) != LAMP_OK) {
+                result = e;
+                break;
+            }
         }
         if (t_cur >= t_base + TAB) {
             t_base = t_cur;

@@ -1,11 +1,11 @@
 // Batching form: many independent problems advance together, each phase of the
-// iteration launched once for all of them (the sweeps once per point dimension present,
-// so that every sweep kernel is compiled for its own dimension).  Each phase kernel is a
-// persistent loop of a machine-sized grid over a work list of (problem, tile) items; an
-// item runs the same device body as the single-problem kernels, with that problem's
-// descriptor.  Sweep items are handed out by an atomic counter, largest first.  Every
-// problem keeps its own control block, so a problem that meets its tolerance stops
-// (its items exit at once) while the others continue.
+// iteration launched once for all of them.  Each sweep is a persistent loop of a
+// machine-sized grid over one work list of (problem, tile) items of every dimension; an
+// item runs the same device body as the single-problem kernels, compiled for its problem's
+// dimension, with that problem's descriptor.  Sweep items are handed out by an atomic
+// counter, largest first.  Every problem keeps its own control block, so a problem that
+// meets its tolerance stops (its items exit at once) while the others continue; the host
+// then hands its share of the sweep blocks to the problems still running.
 #pragma once
 
 #include "lamp_kernels.hpp"
@@ -61,12 +61,12 @@ __device__ __forceinline__ int next_item(unsigned* counter) {
     return k;
 }
 
-__device__ __forceinline__ void reset_counters(unsigned* counters, int n) {
-    if (blockIdx.x == 0 && (int)threadIdx.x < n) counters[threadIdx.x] = 0u;
+__device__ __forceinline__ void reset_counter(unsigned* counter) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
 }
 
-// Row sweep items of the problems with dimension D (D = 0: any other dimension).
-template <int D>
+// Row sweep items of every running problem; each item runs the body compiled for its
+// problem's dimension (the run-time form for any other dimension).
 __global__ __launch_bounds__(BLOCK) void batch_row_sweep(const ProbDesc* __restrict__ pd,
                                                          const Item* __restrict__ items,
                                                          const int* __restrict__ n_active,
@@ -84,17 +84,23 @@ __global__ __launch_bounds__(BLOCK) void batch_row_sweep(const ProbDesc* __restr
         const double2* gtab = as_const(P.gtab);
         const double* H = as_global(P.H);
         double2* rpart = as_global(P.rpart);
-        if constexpr (D > 0)
-            row_sweep_body<METRIC_SQEUCLID, D>(ctrl, sched, P.kc, xc, yc, gtab, H, rpart, P.split_r, it.bx, it.by, 0);
-        else
-            row_sweep_dyn_body(ctrl, sched, P.kc, P.d, xc, yc, gtab, H, rpart, P.split_r, it.bx, it.by, 0);
+        switch (P.d) {
+#define CASE(D)                                                                                                  \
+    case D:                                                                                                      \
+        row_sweep_body<METRIC_SQEUCLID, D>(ctrl, sched, P.kc, xc, yc, gtab, H, rpart, P.split_r, it.bx, it.by, 0); \
+        break;
+            LAMP_BATCH_D(CASE)
+#undef CASE
+            default:
+                row_sweep_dyn_body(ctrl, sched, P.kc, P.d, xc, yc, gtab, H, rpart, P.split_r, it.bx, it.by, 0);
+        }
     }
 }
 
 __global__ __launch_bounds__(BLOCK) void batch_row_finish(const ProbDesc* __restrict__ pd,
                                                           const Item* __restrict__ items, int n_items,
-                                                          const Sched* sched, unsigned* counters, int n_counters) {
-    reset_counters(counters, n_counters);   // the row sweeps of this iteration are complete
+                                                          const Sched* sched, unsigned* counter) {
+    reset_counter(counter);   // the row sweep of this iteration is complete
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
         const Item it = items[k];
         const ProbDesc& P = pd[it.prob];
@@ -103,8 +109,7 @@ __global__ __launch_bounds__(BLOCK) void batch_row_finish(const ProbDesc* __rest
     }
 }
 
-// Column sweep items of the problems with dimension D (D = 0: any other dimension).
-template <int D>
+// Column sweep items of every running problem, as the row sweep.
 __global__ __launch_bounds__(BLOCK) void batch_col_sweep(const ProbDesc* __restrict__ pd,
                                                          const Item* __restrict__ items,
                                                          const int* __restrict__ n_active,
@@ -123,25 +128,37 @@ __global__ __launch_bounds__(BLOCK) void batch_col_sweep(const ProbDesc* __restr
         const RowVar* rowvar = as_const(P.rowvar);
         const double2* rowck = as_const(P.rowck);
         double2* cpart = as_global(P.cpart);
-        if constexpr (D > 0)
-            col_sweep_body<METRIC_SQEUCLID, D>(ctrl, sched, P.kc, xc, yc, gtab, rowvar, rowck, cpart, P.split_c, it.bx,
-                                               it.by, 0);
-        else
-            col_sweep_dyn_body(ctrl, sched, P.kc, P.d, xc, yc, gtab, rowvar, rowck, cpart, P.split_c, it.bx, it.by, 0);
+        switch (P.d) {
+#define CASE(D)                                                                                                 \
+    case D:                                                                                                     \
+        col_sweep_body<METRIC_SQEUCLID, D>(ctrl, sched, P.kc, xc, yc, gtab, rowvar, rowck, cpart, P.split_c, it.bx, \
+                                           it.by, 0);                                                           \
+        break;
+            LAMP_BATCH_D(CASE)
+#undef CASE
+            default:
+                col_sweep_dyn_body(ctrl, sched, P.kc, P.d, xc, yc, gtab, rowvar, rowck, cpart, P.split_c, it.bx, it.by,
+                                   0);
+        }
     }
 }
 
 __global__ __launch_bounds__(BLOCK) void batch_dual_update(const ProbDesc* __restrict__ pd,
                                                            const Item* __restrict__ items, int n_items,
-                                                           const Sched* sched, unsigned* counters,
-                                                           int n_counters) {
-    reset_counters(counters, n_counters);   // the column sweeps of this iteration are complete
+                                                           const Sched* sched, unsigned* counter) {
+    reset_counter(counter);   // the column sweep of this iteration is complete
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
         const Item it = items[k];
         const ProbDesc& P = pd[it.prob];
         dual_update_body(P.ctrl, sched, P.kc, P.cpart, P.P_c, P.c, P.yn2, P.buf, P.gtab, nullptr, 0, P.respart,
-                         TraceCols{nullptr, nullptr, nullptr, nullptr}, nullptr, it.bx, 0, P.n_dual_blocks);
+                         TraceCols{nullptr, nullptr, nullptr, nullptr}, nullptr, it.bx);
     }
+}
+
+// Block p completes the iteration of problem p (residual, stop decision, t + 1).
+__global__ __launch_bounds__(BLOCK) void batch_dual_finish(const ProbDesc* __restrict__ pd, const Sched* sched) {
+    const ProbDesc& P = pd[blockIdx.x];
+    dual_finish_body(P.ctrl, sched, P.respart, nullptr, P.n_dual_blocks);
 }
 
 }  // namespace lampk

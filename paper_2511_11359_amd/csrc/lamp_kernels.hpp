@@ -53,7 +53,7 @@ struct Ctrl {
     int32_t done;       // 1 once res_t <= tol
     int32_t err;        // bit 0: non-finite value in the dual update
     int32_t fallbacks;  // rows recomputed exactly
-    uint32_t counter;   // last-block detection of dual_update
+    uint32_t pad0;
     double tol;         // 0: never stop early
     double res_last;    // ||col(X^t) - c||_1 of the last completed iteration
     double dt_acc;      // accumulated D_t summands without the normaliser telescope
@@ -861,7 +861,7 @@ __device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched,
                                                      double2* __restrict__ gtab2,
                                                      float2* __restrict__ gtabf, int64_t m_pad,
                                                      double* __restrict__ respart, TraceCols tr,
-                                                     double* __restrict__ dtpart, int64_t bx_, int64_t by_, int64_t nb_) {
+                                                     double* __restrict__ dtpart, int64_t bx_) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
@@ -929,42 +929,62 @@ __device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched,
         }
         __syncthreads();
     }
-    __shared__ bool last;
     if (threadIdx.x == 0) {
         respart[bx_] = sh[0];
         if (dtpart) dtpart[bx_] = shd[0];
         if (shbad) atomicOr(&ctrl->err, 1);
-        __threadfence();
-        unsigned prev = atomicAdd(&ctrl->counter, 1u);
-        last = (prev == nb_ - 1);
     }
+}
+
+// Completes iteration t after the dual update (a kernel of its own: the block partials are
+// visible at the kernel boundary, so the dual update needs no device-scope fence and no
+// last-block counter -- on a chip whose XCDs keep separate L2 caches every such fence writes
+// back the L2).  One block: the residual ||col(X^t) - c||_1 as a fixed-order tree over the
+// block partials, the stop decision (iterates t >= 1 only; t = 0 is the product coupling of
+// eta_0 = infinity), and otherwise the D_t summand of the step and t + 1.
+__device__ __forceinline__ void dual_finish_body(Ctrl* ctrl, const Sched* sched, const double* __restrict__ respart,
+                                                 const double* __restrict__ dtpart, int64_t nb) {
+    if (halted(ctrl)) return;   // the same control block for every thread: uniform
+    const int64_t t = ctrl->t;
+    __shared__ double sh[BLOCK];
+    __shared__ double shd[BLOCK];
+    double a = 0.0, b = 0.0;
+    for (int64_t k = threadIdx.x; k < nb; k += BLOCK) {
+        a += respart[k];
+        if (dtpart) b += dtpart[k];
+    }
+    sh[threadIdx.x] = a;
+    shd[threadIdx.x] = b;
     __syncthreads();
-    if (!last) return;
-    // the last block: total residual in block order, stop decision, advance t
-    __threadfence();
-    double tot = 0.0;
-    if (threadIdx.x == 0) {
-        for (unsigned b = 0; b < nb_; ++b) tot += __hip_atomic_load(&respart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ctrl->res_last = tot;
-        ctrl->counter = 0;
-        if (ctrl->err) {
-            ctrl->done = 1;
-            ctrl->t_done = t;
-        } else if (ctrl->tol > 0.0 && t >= 1 && tot <= ctrl->tol) {
-            // t = 0 is the product coupling (eta_0 = infinity), not an iterate: never tested
-            ctrl->done = 1;
-            ctrl->t_done = t;
-        } else {
-            if (dtpart) {
-                // the step is taken: its D_t summand joins the sum
-                double d = (sc.lamB - sc.lamA) * ctrl->dt_cost;
-                for (unsigned b = 0; b < nb_; ++b) d += __hip_atomic_load(&dtpart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ctrl->dt_acc += d;
-            }
-            ctrl->t = t + 1;
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sh[threadIdx.x] += sh[threadIdx.x + o];
+            shd[threadIdx.x] += shd[threadIdx.x + o];
         }
-        __threadfence();
+        __syncthreads();
     }
+    if (threadIdx.x != 0) return;
+    const double tot = sh[0];
+    ctrl->res_last = tot;
+    if (ctrl->err) {
+        ctrl->done = 1;
+        ctrl->t_done = t;
+    } else if (ctrl->tol > 0.0 && t >= 1 && tot <= ctrl->tol) {
+        ctrl->done = 1;
+        ctrl->t_done = t;
+    } else {
+        if (dtpart) {
+            // the step is taken: its D_t summand joins the sum
+            const Sched sc = sched[t - ctrl->t_base];
+            ctrl->dt_acc += (sc.lamB - sc.lamA) * ctrl->dt_cost + shd[0];
+        }
+        ctrl->t = t + 1;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void dual_finish(Ctrl* ctrl, const Sched* sched, const double* __restrict__ respart,
+                                                     const double* __restrict__ dtpart, int64_t nb) {
+    dual_finish_body(ctrl, sched, respart, dtpart, nb);
 }
 
 __global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sched, Consts kc,
@@ -975,7 +995,7 @@ __global__ __launch_bounds__(BLOCK) void dual_update(Ctrl* ctrl, const Sched* sc
                                                      float2* __restrict__ gtabf, int64_t m_pad,
                                                      double* __restrict__ respart, TraceCols tr,
                                                      double* __restrict__ dtpart) {
-    dual_update_body(ctrl, sched, kc, cpart, P, c, yn2, buf, gtab2, gtabf, m_pad, respart, tr, dtpart, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    dual_update_body(ctrl, sched, kc, cpart, P, c, yn2, buf, gtab2, gtabf, m_pad, respart, tr, dtpart, (int64_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
