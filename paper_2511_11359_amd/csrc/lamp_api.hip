@@ -151,9 +151,13 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
         mfma_split(L.m_pad, L.n_pad / 32, &L.tps_c, &L.P_cm);
     }
     L.KP64 = fp64_kp(d);
-    L.use64 = L.KP64 > 0 && metric == METRIC_SQEUCLID;   // FP64 matrix cores compute inner products only
     L.n_pad64 = cdiv(n, 64) * 64;
     L.m_pad64 = cdiv(m, 64) * 64;
+    // FP64 matrix cores compute inner products only; their tile loads take 32-bit byte offsets
+    // (operand copies and 16-byte point tables below 4 GiB; otherwise the vector-ALU sweeps run)
+    L.use64 = L.KP64 > 0 && metric == METRIC_SQEUCLID &&
+              (uint64_t)std::max(L.n_pad64, L.m_pad64) * (uint64_t)(L.KP64 * 8) < (1ull << 32) &&
+              std::max(n, m) < ((int64_t)1 << 28);
     L.cost = metric == METRIC_EXPLICIT;
     if (L.cost) {
         // row sweep: 32 rows per block, column splits in whole steps; column sweep:

@@ -688,12 +688,22 @@ struct LdsTile64 {
     static_assert(PER_THREAD <= 4, "tile larger than the prefetch registers");
 };
 
+// Global -> registers part of the load of tile `tile` (16 points) and their 16-byte scalars,
+// as buffer loads: a wave-uniform tile offset plus a fixed lane offset (the host keeps the
+// operand copies below 4 GiB).  Scalars past the end of their table read as zero; the
+// consumers mask the points past the end on the last tile of the range.
 template <int KP>
-__device__ __forceinline__ void tile64_fetch(const double* __restrict__ src, int64_t row0, const void* __restrict__ scal,
-                                             int64_t scal_rows, TileRegs& R) {
+__device__ __forceinline__ void tile64_fetch(const TileSrc& src, int tile, TileRegs& R) {
     using L = LdsTile64<KP>;
-    fetch_tile<16, L::ROW_BYTES, L::PER_THREAD, 16>(reinterpret_cast<const char*>(src + row0 * KP),
-                                                    reinterpret_cast<const char*>(scal), row0, scal_rows, R);
+    const uint32_t tile_off = (uint32_t)tile * (uint32_t)L::TILE_BYTES;
+    unroll_for<0, L::PER_THREAD>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const uint32_t c = threadIdx.x + q * BLOCK;
+        constexpr bool full = (q + 1) * BLOCK <= L::CHUNKS;   // every thread has a piece
+        if (full || c < (uint32_t)L::CHUNKS)
+            treg<q>(R) = __builtin_amdgcn_raw_buffer_load_b128(src.ops, c * 16u, tile_off, 0);
+    });
+    R.s = __builtin_amdgcn_raw_buffer_load_b128(src.scal, (threadIdx.x & 15u) * 16u, (uint32_t)tile * 256u, 0);
 }
 
 template <int KP>
@@ -716,6 +726,24 @@ __device__ __forceinline__ doublex4 tile_dot64(const char* lds, int c16, int grp
 #pragma unroll
     for (int s = 1; s < NS; ++s) d = mma64(a[s], bv[s], d);
     return d;
+}
+
+// The tile loop of both FP64 sweeps is software-pipelined over two LDS buffers: iteration
+// `it` prefetches tile it + 2, computes the products of tile it + 1 from buffer NXT and the
+// exponentials of tile it, then stores the prefetch into the other buffer.  Pairs of
+// iterations run with NXT fixed at compile time (constant LDS offsets, the pipeline's values
+// kept in place instead of copied); only the iterations whose next tile reaches past the end
+// of the points (at most the last three of a range) mask the scalars of those points, with
+// NXT at run time.
+template <typename Step>
+__device__ __forceinline__ void pipelined_tiles(int it0, int it1, int it_mask, Step&& step) {
+    int it = it0;
+#pragma clang loop unroll(disable)
+    for (; it + 2 <= it_mask; it += 2) {
+        step(it, std::integral_constant<int, 1>{}, std::false_type{});
+        step(it + 1, std::integral_constant<int, 0>{}, std::false_type{});
+    }
+    for (; it < it1; ++it) step(it, (it + 1 - it0) & 1, std::true_type{});
 }
 
 template <int KP>
@@ -756,33 +784,34 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, 
     }
     float accA[4] = {0.f, 0.f, 0.f, 0.f}, accB[4] = {0.f, 0.f, 0.f, 0.f};
     double sumA[4] = {0.0, 0.0, 0.0, 0.0}, sumB[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t jt0 = (int64_t)p * tiles_per_split;
-    const int64_t jt1 = min(m_tiles, jt0 + tiles_per_split);
+    const int jt0 = (int)((int64_t)p * tiles_per_split);
+    const int jt1 = (int)min(m_tiles, (int64_t)jt0 + tiles_per_split);
+    const TileSrc src = make_tile_src(yop, (uint32_t)(m_tiles * L::TILE_BYTES), g, (uint32_t)(kc.m * 16));
     TileRegs pf;
     // column j's table entry; columns past m (padding) never contribute
-    auto scal = [&](const char* buf, int64_t jt) {
+    auto scal = [&](const char* buf, int jt, auto check) {
         double2 gg = *reinterpret_cast<const double2*>(buf + 16 * L::STRIDE + c16 * 16);
-        if (jt * 16 + c16 >= kc.m) gg = make_double2(-1e300, -1e300);
+        if constexpr (decltype(check)::value)
+            if ((int64_t)jt * 16 + c16 >= kc.m) gg = make_double2(-1e300, -1e300);
         return gg;
     };
     if (jt0 < jt1) {
-        const int64_t jl = jt1 - 1;
-        tile64_fetch<KP>(yop, jt0 * 16, g, kc.m, pf);
+        const int jl = jt1 - 1;
+        tile64_fetch<KP>(src, jt0, pf);
         tile64_store<KP>(lds[0], pf);
         __syncthreads();
         doublex4 dc = tile_dot64<KP>(lds[0], c16, grp, a, hv);
-        double2 gc = scal(lds[0], jt0);
-        tile64_fetch<KP>(yop, min(jt0 + 1, jl) * 16, g, kc.m, pf);
+        double2 gc = scal(lds[0], jt0, std::true_type{});
+        tile64_fetch<KP>(src, min(jt0 + 1, jl), pf);
         tile64_store<KP>(lds[1], pf);
         __syncthreads();
         loads_done();
         int cnt = 0;
-#pragma clang loop unroll(disable)
-        for (int64_t jt = jt0; jt < jt1; ++jt) {
-            const int nxt = (int)((jt + 1 - jt0) & 1);
-            tile64_fetch<KP>(yop, min(jt + 2, jl) * 16, g, kc.m, pf);
+        auto step = [&](int jt, auto nxtc, auto check) {
+            const int nxt = nxtc;   // a constant in the paired iterations
+            tile64_fetch<KP>(src, min(jt + 2, jl), pf);
             const doublex4 dn = tile_dot64<KP>(lds[nxt], c16, grp, a, hv);
-            const double2 gn = scal(lds[nxt], min(jt + 1, jl));
+            const double2 gn = scal(lds[nxt], min(jt + 1, jl), check);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 accA[q] += fexp2(fma(dc[q], cA, gc.x));
@@ -803,7 +832,9 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, 
             __syncthreads();
             dc = dn;
             gc = gn;
-        }
+        };
+        // iteration jt reads the scalars of tile jt + 1: whole tiles (16 columns below m) for jt < m / 16 - 1
+        pipelined_tiles(jt0, jt1, max(jt0, min(jt1, (int)(kc.m / 16) - 1)), step);
     }
     if (!active) return;
 #pragma unroll
@@ -867,23 +898,30 @@ __global__ __launch_bounds__(BLOCK, (col64_min_waves<KP>())) void col_sweep_mfma
     }
     float accA = 0.f, accB = 0.f;
     double sumA = 0.0, sumB = 0.0;
-    const int64_t it0 = (int64_t)p * tiles_per_split;
-    const int64_t it1 = min(n_tiles, it0 + tiles_per_split);
+    const int it0 = (int)((int64_t)p * tiles_per_split);
+    const int it1 = (int)min(n_tiles, (int64_t)it0 + tiles_per_split);
+    const TileSrc src = make_tile_src(xop, (uint32_t)(n_tiles * L::TILE_BYTES), rowvar, (uint32_t)(kc.n * 16));
     // rows of the tile: offsets k (accumulator input of the dot products) and weights
     struct RowTerms {
         doublex4 k;
         float wa[4], wb[4];
     };
-    auto row_terms = [&](const char* buf, int64_t it) {
+    auto row_terms = [&](const char* buf, int it, auto check) {
         RowTerms rt;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = 4 * q + grp;
             const RowVar rv = *reinterpret_cast<const RowVar*>(buf + 16 * L::STRIDE + r * 16);
-            const bool valid = it * 16 + r < kc.n;
-            rt.k[q] = valid ? rv.k : -1e300;
-            rt.wa[q] = valid ? rv.wA : 0.f;
-            rt.wb[q] = valid ? rv.wB : 0.f;
+            if constexpr (decltype(check)::value) {
+                const bool valid = (int64_t)it * 16 + r < kc.n;
+                rt.k[q] = valid ? rv.k : -1e300;
+                rt.wa[q] = valid ? rv.wA : 0.f;
+                rt.wb[q] = valid ? rv.wB : 0.f;
+            } else {
+                rt.k[q] = rv.k;
+                rt.wa[q] = rv.wA;
+                rt.wb[q] = rv.wB;
+            }
         }
         return rt;
     };
@@ -899,21 +937,20 @@ __global__ __launch_bounds__(BLOCK, (col64_min_waves<KP>())) void col_sweep_mfma
     };
     TileRegs pf;
     if (it0 < it1) {
-        const int64_t il = it1 - 1;
-        tile64_fetch<KP>(xop, it0 * 16, rowvar, kc.n, pf);
+        const int il = it1 - 1;
+        tile64_fetch<KP>(src, it0, pf);
         tile64_store<KP>(lds[0], pf);
         __syncthreads();
-        RowTerms rc = row_terms(lds[0], it0);
+        RowTerms rc = row_terms(lds[0], it0, std::true_type{});
         doublex4 dc = dot(lds[0], rc.k);
-        tile64_fetch<KP>(xop, min(it0 + 1, il) * 16, rowvar, kc.n, pf);
+        tile64_fetch<KP>(src, min(it0 + 1, il), pf);
         tile64_store<KP>(lds[1], pf);
         __syncthreads();
         loads_done();
-#pragma clang loop unroll(disable)
-        for (int64_t it = it0; it < it1; ++it) {
-            const int nxt = (int)((it + 1 - it0) & 1);
-            tile64_fetch<KP>(xop, min(it + 2, il) * 16, rowvar, kc.n, pf);
-            const RowTerms rn = row_terms(lds[nxt], min(it + 1, il));
+        auto step = [&](int it, auto nxtc, auto check) {
+            const int nxt = nxtc;   // a constant in the paired iterations
+            tile64_fetch<KP>(src, min(it + 2, il), pf);
+            const RowTerms rn = row_terms(lds[nxt], min(it + 1, il), check);
             const doublex4 dn = dot(lds[nxt], rn.k);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -921,7 +958,8 @@ __global__ __launch_bounds__(BLOCK, (col64_min_waves<KP>())) void col_sweep_mfma
                 accB = fmaf(rc.wb[q], fexp2(fma(dc[q], cB, gB)), accB);
             }
             pin(accA, accB);
-            if (((it - it0) & 1) == 1) {
+            // carry in FP64 after every second tile of the range (nxt = 0 on those)
+            if (nxt == 0) {
                 sumA += (double)accA;
                 sumB += (double)accB;
                 accA = accB = 0.f;
@@ -930,7 +968,9 @@ __global__ __launch_bounds__(BLOCK, (col64_min_waves<KP>())) void col_sweep_mfma
             __syncthreads();
             dc = dn;
             rc = rn;
-        }
+        };
+        // iteration it reads the row data of tile it + 1: whole tiles (16 rows below n) for it < n / 16 - 1
+        pipelined_tiles(it0, it1, max(it0, min(it1, (int)(kc.n / 16) - 1)), step);
     }
     if (!active) return;
     sumA += (double)accA;
