@@ -69,12 +69,22 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Split of the streamed extent `len` for `owned` lanes: returns elements per split.
-int64_t choose_split(int64_t owned, int64_t len, int64_t target = TARGET_BLOCKS) {
+// Split of the streamed range of a vector-ALU sweep: about `target` blocks in all, splits of
+// at least 128 points.  With xcd, the count is rounded up to a multiple of 8 where the range
+// allows it: the sweeps run split p of a block on XCD p mod 8 (sweep_block), so each XCD's
+// L2 holds the data of its own splits only.  (The batching form hands its items to any block
+// and skips the rounding.)
+int64_t choose_split(int64_t owned, int64_t len, int64_t target = TARGET_BLOCKS, bool xcd = true) {
     const int64_t blocks = cdiv(owned, BLOCK);
     int64_t P = cdiv(target, blocks);
-    P = std::max<int64_t>(1, std::min<int64_t>(P, cdiv(len, 128)));
+    const int64_t cap = cdiv(len, 128);
+    if (xcd && cap >= 8) P = cdiv(P, 8) * 8;
+    P = std::max<int64_t>(1, std::min<int64_t>(P, cap));
     return cdiv(len, P);
 }
+
+// One-dimensional grid of a sweep over the blocks of `owned` points times P splits.
+unsigned sweep_grid(int64_t owned, int64_t P) { return (unsigned)(cdiv(owned, BLOCK) * P); }
 
 struct Layout {
     size_t ctrl, sched, xc, yc, xcf, ycf, xn2, yn2, gtab, H, rowvar, rowck, rpart, cpart, nu1, th1, respart,
@@ -457,7 +467,7 @@ void launch_row_extreme(const Layout& L, Consts kc, int d, void* ws, const doubl
             default: row_extreme64<128>(L, kc, ws, a, sgn, st); return;
         }
     }
-    dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
+    const dim3 g(sweep_grid(kc.n, L.P_r));
     double* part = at<double>(ws, L.rpart);
     const double* xc = at<double>(ws, L.xc);
     const double* yc = at<double>(ws, L.yc);
@@ -573,7 +583,7 @@ void launch_row_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t s
         sweep_mfma64<true>(L, kc, ws, st);
         return;
     }
-    dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
+    const dim3 g(sweep_grid(kc.n, L.P_r));
     const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
     const Sched* sch = at<Sched>(ws, L.sched);
     const double* xc = at<double>(ws, L.xc);
@@ -610,7 +620,7 @@ void launch_col_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t s
         sweep_mfma64<false>(L, kc, ws, st);
         return;
     }
-    dim3 g((unsigned)cdiv(kc.m, BLOCK), (unsigned)L.P_c);
+    const dim3 g(sweep_grid(kc.m, L.P_c));
     const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
     const Sched* sch = at<Sched>(ws, L.sched);
     const double* xc = at<double>(ws, L.xc);
@@ -631,7 +641,7 @@ void launch_col_sweep(const Layout& L, Consts kc, int d, void* ws, hipStream_t s
 
 void launch_adjoint(const Layout& L, Consts kc, int d, void* ws, double cA, const double* gA,
                     hipStream_t st) {
-    dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
+    const dim3 g(sweep_grid(kc.n, L.P_r));
     double* part = at<double>(ws, L.rpart);
     const double* xc = at<double>(ws, L.xc);
     const double* yc = at<double>(ws, L.yc);
@@ -654,7 +664,7 @@ void launch_adjoint(const Layout& L, Consts kc, int d, void* ws, double cA, cons
 // per row into rows (n doubles) and their fixed-order sum into *out (device).
 void launch_cost(const Layout& L, Consts kc, int d, void* ws, double cA, const double* gA, const double* r,
                  double* rows, double* out, hipStream_t st) {
-    dim3 g((unsigned)cdiv(kc.n, BLOCK), (unsigned)L.P_r);
+    const dim3 g(sweep_grid(kc.n, L.P_r));
     double* part = at<double>(ws, L.rpart);
     const double* xc = at<double>(ws, L.xc);
     const double* yc = at<double>(ws, L.yc);
@@ -1072,8 +1082,8 @@ BatchPlan batch_plan(const lamp_problem* probs, int count) {
     for (int p = 0; p < count; ++p) {
         const lamp_problem& q = probs[p];
         B.L[p] = layout(q.n, q.m, q.d, LAMP_FP32);
-        pr[p] = cdiv(q.m, choose_split(q.n, q.m, kMaxTarget));
-        pc[p] = cdiv(q.n, choose_split(q.m, q.n, kMaxTarget));
+        pr[p] = cdiv(q.m, choose_split(q.n, q.m, kMaxTarget, false));
+        pc[p] = cdiv(q.n, choose_split(q.m, q.n, kMaxTarget, false));
         const int64_t rb = cdiv(q.n, BLOCK), cb = cdiv(q.m, BLOCK);
         B.cap_items[0] += (int)(rb * pr[p]);
         B.cap_items[1] += (int)rb;
@@ -1135,9 +1145,9 @@ void batch_assign(BatchRun* run, const lamp_problem* probs, const std::vector<ch
         const double w = (double)q.n * (double)q.m * pair_cost(q.d);
         const int64_t target = std::max<int64_t>(1, (int64_t)std::llround((double)run->target_total * w / wsum));
         ProbDesc& D = run->desc[p];
-        D.split_r = choose_split(q.n, q.m, target);
+        D.split_r = choose_split(q.n, q.m, target, false);
         D.P_r = (int)cdiv(q.m, D.split_r);
-        D.split_c = choose_split(q.m, q.n, target);
+        D.split_c = choose_split(q.m, q.n, target, false);
         D.P_c = (int)cdiv(q.n, D.split_c);
         for (int h = 0; h < 2; ++h) {
             const int64_t own = h == 0 ? q.n : q.m, other = h == 0 ? q.m : q.n;
@@ -1663,7 +1673,7 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     } else {
         by_md([&](auto m, auto dd) {
             hipLaunchKernelGGL((round_cols<decltype(m)::value, decltype(dd)::value>),
-                               dim3((unsigned)cdiv(kc.m, BLOCK), (unsigned)L.P_c), dim3(BLOCK), 0, st, kc, prob->d, cA,
+                               dim3(sweep_grid(kc.m, L.P_c)), dim3(BLOCK), 0, st, kc, prob->d, cA,
                                at<double>(ws, L.xc), at<double>(ws, L.yc), gA, at<double>(ws, L.H), prob->r, xr,
                                rpart, L.split_c);
         });
@@ -1819,7 +1829,7 @@ lamp_status lamp_backward_y(const lamp_problem* prob, const lamp_params* params,
     double* gA = at<double>(ws, L.scratch);
     hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
                        at<double2>(ws, L.gtab), gA);
-    dim3 g((unsigned)cdiv(kc.m, BLOCK), (unsigned)L.P_c);
+    const dim3 g(sweep_grid(kc.m, L.P_c));
     double* part = at<double>(ws, L.cpart);
     const double* xc = at<double>(ws, L.xc);
     const float* xcf = at<float>(ws, L.xcf);

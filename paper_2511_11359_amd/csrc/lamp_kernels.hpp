@@ -188,6 +188,18 @@ __device__ __forceinline__ bool halted(const Ctrl* ctrl) {
     return ctrl->done != 0 || ctrl->t >= ctrl->t_end;
 }
 
+// Sweeps over (blocks of the owned points) x (P splits of the streamed range of length len,
+// `split` points each) run on a one-dimensional grid: block b takes split b mod P of owned
+// block b / P.  Consecutive block indices go to the eight XCDs in turn, so with P a multiple
+// of 8 every XCD streams the same P / 8 splits, whose data then stay in its L2.
+struct SweepBlock {
+    int64_t bx, p;
+};
+__device__ __forceinline__ SweepBlock sweep_block(int64_t len, int64_t split) {
+    const int64_t P = (len + split - 1) / split;
+    return SweepBlock{(int64_t)blockIdx.x / P, (int64_t)blockIdx.x % P};
+}
+
 __device__ __forceinline__ float fexp2(double e) {
     return __builtin_amdgcn_exp2f(static_cast<float>(e));
 }
@@ -313,7 +325,8 @@ __global__ __launch_bounds__(BLOCK) void row_extreme(Consts kc, const double* __
                                                      const double* __restrict__ yc,
                                                      const double* __restrict__ a, double sgn,
                                                      double* __restrict__ part, int64_t split) {
-    row_extreme_body<M, D>(kc, xc, yc, a, sgn, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    const SweepBlock sb = sweep_block(kc.m, split);
+    row_extreme_body<M, D>(kc, xc, yc, a, sgn, part, split, sb.bx, sb.p, 0);
 }
 
 // Generic-d version: coordinates read per pair.
@@ -337,7 +350,8 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_dyn(Consts kc, int D, const
                                                          const double* __restrict__ yc,
                                                          const double* __restrict__ a, double sgn,
                                                          double* __restrict__ part, int64_t split) {
-    row_extreme_dyn_body(kc, D, xc, yc, a, sgn, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    const SweepBlock sb = sweep_block(kc.m, split);
+    row_extreme_dyn_body(kc, D, xc, yc, a, sgn, part, split, sb.bx, sb.p, 0);
 }
 
 // Merge the partial minima (exact, order independent); optionally transform.
@@ -444,7 +458,8 @@ __global__ __launch_bounds__(BLOCK) void row_sweep(const Ctrl* ctrl, const Sched
                                                    const double2* __restrict__ gtab2,
                                                    const double* __restrict__ H,
                                                    double2* __restrict__ part, int64_t split) {
-    row_sweep_body<M, D>(ctrl, sched, kc, xc, yc, gtab2, H, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    const SweepBlock sb = sweep_block(kc.m, split);
+    row_sweep_body<M, D>(ctrl, sched, kc, xc, yc, gtab2, H, part, split, sb.bx, sb.p, 0);
 }
 
 __device__ __forceinline__ void row_sweep_dyn_body(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
@@ -486,7 +501,8 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_dyn(const Ctrl* ctrl, const S
                                                        const double2* __restrict__ gtab2,
                                                        const double* __restrict__ H,
                                                        double2* __restrict__ part, int64_t split) {
-    row_sweep_dyn_body(ctrl, sched, kc, D, xc, yc, gtab2, H, part, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    const SweepBlock sb = sweep_block(kc.m, split);
+    row_sweep_dyn_body(ctrl, sched, kc, D, xc, yc, gtab2, H, part, split, sb.bx, sb.p, 0);
 }
 
 // Exact recomputation of sigma_i = log2 sum_j 2^(g_j + cfac x~_i.y~_j) (two passes, FP64 max).
@@ -675,7 +691,8 @@ __global__ __launch_bounds__(BLOCK) void col_sweep(const Ctrl* ctrl, const Sched
                                                    const RowVar* __restrict__ rowvar,
                                                    const double2* __restrict__ rowck,
                                                    double2* __restrict__ cpart, int64_t split) {
-    col_sweep_body<M, D>(ctrl, sched, kc, xc, yc, gtab2, rowvar, rowck, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    const SweepBlock sb = sweep_block(kc.n, split);
+    col_sweep_body<M, D>(ctrl, sched, kc, xc, yc, gtab2, rowvar, rowck, cpart, split, sb.bx, sb.p, 0);
 }
 
 __device__ __forceinline__ void col_sweep_dyn_body(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
@@ -726,7 +743,8 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_dyn(const Ctrl* ctrl, const S
                                                        const RowVar* __restrict__ rowvar,
                                                        const double2* __restrict__ rowck,
                                                        double2* __restrict__ cpart, int64_t split) {
-    col_sweep_dyn_body(ctrl, sched, kc, D, xc, yc, gtab2, rowvar, rowck, cpart, split, (int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x);
+    const SweepBlock sb = sweep_block(kc.n, split);
+    col_sweep_dyn_body(ctrl, sched, kc, D, xc, yc, gtab2, rowvar, rowck, cpart, split, sb.bx, sb.p, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1203,7 +1221,7 @@ __global__ void round_row_factors(Consts kc, const double* __restrict__ psum, do
     if (i < kc.n) xr[i] = fmin(1.0 / psum[i], 1.0);
 }
 
-// part[p][j] = sum over the rows i of split p = blockIdx.y of xr_i r_i p_ij (one thread per
+// part[p][j] = sum over the rows i of split p of xr_i r_i p_ij (one thread per
 // column, rows in order); round_cols_merge adds the splits in order: colp_j.
 template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void round_cols(Consts kc, int Dm, double cA, const double* __restrict__ xc,
@@ -1211,9 +1229,10 @@ __global__ __launch_bounds__(BLOCK) void round_cols(Consts kc, int Dm, double cA
                                                     const double* __restrict__ H, const double* __restrict__ r,
                                                     const double* __restrict__ xr, double* __restrict__ part,
                                                     int64_t split) {
-    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const SweepBlock sb = sweep_block(kc.n, split);
+    const int64_t j = sb.bx * BLOCK + threadIdx.x;
     if (j >= kc.m) return;
-    const int64_t p = blockIdx.y;
+    const int64_t p = sb.p;
     const int64_t i0 = p * split;
     const int64_t i1 = min(kc.n, i0 + split);
     const OwnPoint<M, D> own(yc + j * Dm, Dm, kc);
@@ -1478,8 +1497,9 @@ __device__ __forceinline__ void weighted_row_sums(const Consts& kc, double cA, c
                                                   double* __restrict__ part, int64_t split) {
     constexpr int W = Pol::W;
     using Col = typename Pol::Col;
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+    const SweepBlock sb = sweep_block(kc.m, split);
+    const int64_t i = sb.bx * BLOCK + threadIdx.x;
+    const int64_t p = sb.p;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
     const int64_t ii = i < kc.n ? i : kc.n - 1;
@@ -1575,7 +1595,7 @@ __global__ __launch_bounds__(BLOCK) void cost_sweep(Consts kc, double cA, const 
                                                     const double* __restrict__ xn2,
                                                     const CostCol<D>* __restrict__ cols,
                                                     double* __restrict__ part, int64_t split) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t i = sweep_block(kc.m, split).bx * BLOCK + threadIdx.x;
     CostSums<M, D> pol;
     if constexpr (M == METRIC_SQEUCLID) pol.xn2 = xn2[i < kc.n ? i : kc.n - 1];
     weighted_row_sums<M, D>(kc, cA, xc, cols, pol, part, split);
@@ -1589,8 +1609,9 @@ __global__ __launch_bounds__(BLOCK) void cost_sweep_dyn(Consts kc, int D, double
                                                         const double* __restrict__ yn2,
                                                         const double* __restrict__ gA,
                                                         double* __restrict__ part, int64_t split) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+    const SweepBlock sb = sweep_block(kc.m, split);
+    const int64_t i = sb.bx * BLOCK + threadIdx.x;
+    const int64_t p = sb.p;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
     if (i >= kc.n) return;
@@ -1641,8 +1662,9 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep_dyn(Consts kc, int D, dou
                                                            const float* __restrict__ ycf,
                                                            const double* __restrict__ gA,
                                                            double* __restrict__ part, int64_t split) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+    const SweepBlock sb = sweep_block(kc.m, split);
+    const int64_t i = sb.bx * BLOCK + threadIdx.x;
+    const int64_t p = sb.p;
     const int64_t j0 = p * split;
     const int64_t j1 = min(kc.m, j0 + split);
     if (i >= kc.n) return;
@@ -1699,8 +1721,9 @@ __global__ __launch_bounds__(BLOCK) void adjoint_y_sweep(Consts kc, double cA, c
                                                          const double* __restrict__ gA,
                                                          const RowVar* __restrict__ rowvar,
                                                          double* __restrict__ part, int64_t split) {
-    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+    const SweepBlock sb = sweep_block(kc.n, split);
+    const int64_t j = sb.bx * BLOCK + threadIdx.x;
+    const int64_t p = sb.p;
     const int64_t i0 = p * split;
     const int64_t i1 = min(kc.n, i0 + split);
     const int64_t jj = j < kc.m ? j : kc.m - 1;
@@ -1770,8 +1793,9 @@ __global__ __launch_bounds__(BLOCK) void adjoint_y_sweep_dyn(Consts kc, int D, d
                                                              const double* __restrict__ gA,
                                                              const RowVar* __restrict__ rowvar,
                                                              double* __restrict__ part, int64_t split) {
-    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t p = blockIdx.y;
+    const SweepBlock sb = sweep_block(kc.n, split);
+    const int64_t j = sb.bx * BLOCK + threadIdx.x;
+    const int64_t p = sb.p;
     const int64_t i0 = p * split;
     const int64_t i1 = min(kc.n, i0 + split);
     const int64_t jj = j < kc.m ? j : kc.m - 1;

@@ -64,10 +64,14 @@ def _gpu_state(nu, theta, t, lam):
 
 @pytest.mark.parametrize("shape", [(256, 256, 2), (300, 173, 3), (97, 1031, 1), (517, 64, 5),
                                    (130, 260, 16), (70, 90, 20),
-                                   (1, 1, 1), (1, 7, 2), (9, 1, 3), (33, 47, 128)])
+                                   (1, 1, 1), (1, 7, 2), (9, 1, 3), (33, 47, 128),
+                                   (700, 1037, 24), (9000, 1300, 64), (9000, 700, 100)])
 def test_first_steps_match_oracle(shape):
     """Iterations 0..4 from the fresh state, several tiles and ragged tails, each dimension path,
-    the degenerate single-row / single-column problems and the largest supported d."""
+    the degenerate single-row / single-column problems and the largest supported d.  The last
+    three run the FP64 matrix-core sweeps (operand widths 32, 64, 128) with n and m off the
+    16-point tiles; at n = 9000 the split ranges hold two or three tiles, so that the paired
+    iterations, the masked last iterations of a range and both LDS buffers all run."""
     n, m, d = shape
     wl = W.random_small(n, m, d, seed=100 + d, eta=1e-2)
     _say("case", wl.name)
