@@ -428,7 +428,7 @@ def main():
     ap.add_argument("--compare", default="fp32_mfma,fp32",
                     help="other forms measured beside the primary one (comma list, '' for none)")
     ap.add_argument("--compare-steps", type=int, default=10)
-    ap.add_argument("--time-to-tol", default="bf16_mfma,fp16_mfma,fp32",
+    ap.add_argument("--time-to-tol", default="bf16_mfma,fp16_mfma,fp32_mfma,fp32",
                     help="forms solved from the start to the tolerance (comma list, '' for none)")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=20000)
