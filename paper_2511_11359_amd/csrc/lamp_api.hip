@@ -426,6 +426,26 @@ bool valu_dispatch(int d, F&& launch) {
     return false;
 }
 
+// The certificate's pair passes: the compiled dimensions of the vector-ALU sweeps and, for the
+// squared Euclidean cost, 32 and 64 (the thread's own point in registers and the streamed
+// point through scalar loads; the run-time form loads both points' coordinates per pair,
+// 6.6 s for a certificate at n = m = 2^16, d = 64).
+template <int M, typename F>
+bool cert_dispatch(int d, F&& launch) {
+    if (valu_dispatch<M>(d, launch)) return true;
+    if constexpr (M == METRIC_SQEUCLID) {
+        if (d == 32) {
+            launch(IC<32>{});
+            return true;
+        }
+        if (d == 64) {
+            launch(IC<64>{});
+            return true;
+        }
+    }
+    return false;
+}
+
 // f(IC<M>) for the run-time metric.
 template <typename F>
 bool by_metric(int metric, F&& f) {
@@ -1636,7 +1656,7 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     // thread's own point in registers where compiled (run-time form otherwise)
     auto by_md = [&](auto&& launch) {
         const bool done = by_metric(kc.metric, [&](auto m) {
-            return valu_dispatch<decltype(m)::value>(prob->d, [&](auto dd) { launch(m, dd); });
+            return cert_dispatch<decltype(m)::value>(prob->d, [&](auto dd) { launch(m, dd); });
         });
         if (!done) launch(IC<-1>{}, IC<0>{});
     };

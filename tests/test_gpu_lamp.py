@@ -542,3 +542,33 @@ def test_certificate_entropic_dual_values(kind, eta):
     assert cert["dual_theta"] - eta * math.log(90) - 1e-12 <= cert["dual_eta_theta"] <= cert["dual_theta"] + 1e-12
     plain = P.certificate(prob, P.make_params(eta=0.0), st)
     assert math.isnan(plain["dual_eta_theta"]) and math.isnan(plain["dual_eta_nu"])
+
+
+@pytest.mark.parametrize("d", [20, 32, 64])
+def test_certificate_fields_at_wide_dimensions(d):
+    """Every certificate field against the oracle's certificate of the GPU's own state (so only
+    the certificate's evaluation is compared) at d = 32 and 64, the dimensions with compiled
+    certificate passes beyond the sweeps' own, and d = 20 (run-time form).  Bounds: the minima
+    of D(theta), D(nu) are FP64 (1e-12); <C, X^t> and the row sums carry FP32 exponentials of
+    FP64 arguments, 22 x 2^-24 relative at most per row (derived in test_gpu_cost.py), so
+    2e-6; the column residual comes from the FP32 column sweep (its 1e-6 l1 tolerance);
+    <C, Round X> as in test_certificate_round_matches_oracle; D^eta as in
+    test_certificate_entropic_dual_values."""
+    wl = W.random_small(230, 170, d, seed=700 + d, eta=1e-2)
+    x, y, s, C = oracle_problem(wl)
+    prob = gpu_problem(wl, s)
+    params = P.make_params(eta=wl.eta, tol=0.0, max_iter=30)
+    st, _, _ = P.solve(prob, params)
+    cert = P.certificate(prob, params, st)
+    ost = OL.LampState(st.t, st.inv_eta, to_np(st.nu), to_np(st.theta))
+    ref = OL.certificate(C, wl.r, wl.c, ost, OL.Params(eta=wl.eta).resolved(1.0), 1.0)
+    _say(f"d = {d}: cost {cert['cost']:.12e} / {ref['cost']:.12e}, row_res {cert['row_res']:.3e} / "
+         f"{ref['row_res']:.3e}, col_res {cert['col_res']:.6e} / {ref['col_res']:.6e}, round "
+         f"{cert['rounded_cost']:.9e} / {ref['rounded_cost']:.9e}")
+    assert abs(cert["cost"] - ref["cost"]) <= 2e-6 * ref["cost"]
+    assert abs(cert["row_res"] - ref["row_res"]) <= 2e-6
+    assert abs(cert["col_res"] - ref["col_res"]) <= 2e-6
+    for key in ("dual_theta", "dual_nu"):
+        assert abs(cert[key] - ref[key]) <= 1e-12, key
+    assert abs(cert["rounded_cost"] - ref["rounded_cost"]) <= 2e-5
+    assert abs(cert["dual_eta_theta"] - ref["dual_eta_theta"]) <= wl.eta * 1e-6
