@@ -192,8 +192,8 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
         return o;
     };
     // row partials: [P][n] double2 for the sweeps, [P_r][n][d+2] for the adjoint,
-    // [4][n] for the certificate rows
-    size_t rpart_d = std::max<size_t>((size_t)L.P_r * n * std::max(2, d + 2), (size_t)4 * n);
+    // [P_r][n][4] for the certificate's row passes
+    size_t rpart_d = std::max<size_t>((size_t)L.P_r * n * std::max(4, d + 2), (size_t)4 * n);
     // column partials: [P][m] double2 for the sweeps, [P_c][m][d+1] doubles for the y adjoint
     size_t cpart_d2 = std::max<size_t>((size_t)L.P_c * m, ((size_t)L.P_c * m * (d + 1) + 1) / 2);
     if (is_mfma(prec)) {
@@ -228,9 +228,10 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     // D_t tracking: per-row cost terms and per-block summands
     L.dtrow = take(sizeof(double) * n);
     L.dtpart = take(sizeof(double) * cdiv(m, BLOCK));
-    // certificate: 4 arrays of max(n, m), Round: 9 more and d + 2 column sums
+    // certificate: 4 arrays of max(n, m), Round: 9 more, the row values (4) and minima (2),
+    // and d + 2 column sums
     // (the adjoint: g^A and one record of 12 d + 8 bytes per column, 16-byte aligned)
-    L.scratch = take(std::max(sizeof(double) * (13 * std::max(n, m) + d + 2),
+    L.scratch = take(std::max(sizeof(double) * (19 * std::max(n, m) + d + 2),
                               align256(sizeof(double) * m) + (size_t)m * (size_t)((12 * d + 8 + 15) / 16 * 16)));
     L.small = take(sizeof(double) * 64);
     if (is_mfma(prec)) {
@@ -1002,6 +1003,16 @@ lamp_status state_normalisers(const lamp_problem* p, const lamp_params* q, const
 }
 
 // g^A_j = -lam_t LOG2E (s |y~_j|^2 + K nu_j): the column term of X^t's exponents (base 2).
+// mu_i = vals[2 + k][i] / r_i: the row minima of the explicit-cost certificate pass (which
+// reports them weighted by r_i > 0), the shifts of the entropic pass.
+__global__ void row_minima_of_vals(Consts kc, const double* __restrict__ r, const double* __restrict__ vals,
+                                   double* __restrict__ mu) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    mu[i] = vals[2 * kc.n + i] / r[i];
+    mu[kc.n + i] = vals[3 * kc.n + i] / r[i];
+}
+
 __global__ void state_col_term(Consts kc, double lam, const double* __restrict__ yn2,
                                const double* __restrict__ nu, double* __restrict__ gA) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1636,7 +1647,7 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     double* gA = sc;                 // m
     double* colres = sc + nm;        // m
     double* prods = sc + 2 * nm;     // 2m
-    double* vals = at<double>(ws, L.rpart);  // 4n
+    double* part = at<double>(ws, L.rpart);  // per-split partials of the row passes: P_r x n x 4
     double* small = at<double>(ws, L.small);
     double* psum = sc + 4 * nm;      // n
     double* xr = sc + 5 * nm;        // n
@@ -1647,7 +1658,10 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     double* cpp = sc + 10 * nm;      // n
     double* tr1 = sc + 11 * nm;      // n
     double* absdr = sc + 12 * nm;    // n
-    double* S = sc + 13 * nm;        // d + 2
+    double* vals = sc + 13 * nm;     // 4n
+    double* mu = sc + 17 * nm;       // 2n: the row minima of C_ij + K theta_j, C_ij + K nu_j
+    double* S = sc + 19 * nm;        // d + 2
+    const dim3 split_grid(sweep_grid(kc.n, L.P_r));
     hipLaunchKernelGGL(col_residual, grid1(kc.m), dim3(BLOCK), 0, st, kc, at<double2>(ws, L.cpart), col_parts(LV),
                        prob->c, colres);
     hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
@@ -1670,11 +1684,13 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
         });
     } else {
         by_md([&](auto m, auto dd) {
-            hipLaunchKernelGGL((cert_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0,
+            hipLaunchKernelGGL((cert_rows<decltype(m)::value, decltype(dd)::value>), split_grid, dim3(BLOCK), 0,
                                st, kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc),
-                               at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA, at<double>(ws, L.H), prob->r,
-                               state->nu, state->theta, vals, psum);
+                               at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA, at<double>(ws, L.H), state->nu,
+                               state->theta, part, L.split_r);
         });
+        hipLaunchKernelGGL(cert_rows_merge, grid1(kc.n), dim3(BLOCK), 0, st, kc, (int)L.P_r, prob->r,
+                           (const double*)part, vals, psum, mu);
     }
     hipLaunchKernelGGL(col_products, grid1(kc.m), dim3(BLOCK), 0, st, kc, prob->c, state->theta, state->nu, prods);
     hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, vals, kc.n, kc.n, 4, small);
@@ -1709,11 +1725,13 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
         });
     } else {
         by_md([&](auto m, auto dd) {
-            hipLaunchKernelGGL((round_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK), 0,
+            hipLaunchKernelGGL((round_rows<decltype(m)::value, decltype(dd)::value>), split_grid, dim3(BLOCK), 0,
                                st, kc, prob->d, cA, at<double>(ws, L.xc), at<double>(ws, L.yc),
-                               at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA, at<double>(ws, L.H), prob->r, xr,
-                               yf, dr, cpp);
+                               at<double>(ws, L.xn2), at<double>(ws, L.yn2), gA, at<double>(ws, L.H), yf, part,
+                               L.split_r);
         });
+        hipLaunchKernelGGL(round_rows_merge, grid1(kc.n), dim3(BLOCK), 0, st, kc, (int)L.P_r, prob->r, xr,
+                           (const double*)part, dr, cpp);
     }
     if (L.cost) {
         by_cost_type(kc.cost_type, [&](auto tag) {
@@ -1740,12 +1758,17 @@ lamp_status lamp_certificate(const lamp_problem* prob, const lamp_params* params
     // D^eta(theta), D^eta(nu) at the problem's eta (def:dual_spp_e); NaN at eta = 0
     const bool soft = params->eta > 0.0;
     if (soft) {
-        double* sv = at<double>(ws, L.rpart);   // 2n (the row sums above are reduced)
+        double* sv = vals;   // 2n (the row values above are reduced)
+        // the minima: from the certificate row pass (recovered from r_i min for the explicit cost)
+        if (L.cost) hipLaunchKernelGGL(row_minima_of_vals, grid1(kc.n), dim3(BLOCK), 0, st, kc, prob->r, vals, mu);
         by_md([&](auto m, auto dd) {
-            hipLaunchKernelGGL((cert_soft_rows<decltype(m)::value, decltype(dd)::value>), grid1(kc.n), dim3(BLOCK),
+            hipLaunchKernelGGL((cert_soft_rows<decltype(m)::value, decltype(dd)::value>), split_grid, dim3(BLOCK),
                                0, st, kc, prob->d, 1.0 / params->eta, at<double>(ws, L.xc), at<double>(ws, L.yc),
-                               at<double>(ws, L.xn2), at<double>(ws, L.yn2), prob->r, state->nu, state->theta, sv);
+                               at<double>(ws, L.xn2), at<double>(ws, L.yn2), state->nu, state->theta,
+                               (const double*)mu, part, L.split_r);
         });
+        hipLaunchKernelGGL(cert_soft_merge, grid1(kc.n), dim3(BLOCK), 0, st, kc, (int)L.P_r, 1.0 / params->eta,
+                           prob->r, (const double*)mu, (const double*)part, sv);
         hipLaunchKernelGGL(reduce_sums, dim3(1), dim3(1024), 0, st, sv, kc.n, kc.n, 2, small + 11);
     }
     HIPCHK(hipGetLastError());

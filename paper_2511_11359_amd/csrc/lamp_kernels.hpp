@@ -1117,7 +1117,9 @@ struct OwnPoint<-1, 0> {
 //   vals[3][i] = r_i min_j (C_ij + K nu_j)            (D(nu))
 //   psum_out[i] = sum_j p_ij                          (row sum of p, for Round)
 // Terms as in the sweeps: FP64 exponent, FP32 exponential and sums over blocks of
-// UNROLL columns, FP64 across blocks; the two minima in FP64.  Dm = run-time d.
+// UNROLL columns, FP64 across blocks; the two minima in FP64.  Dm = run-time d.  Over XCD-aware
+// column splits (sweep_block): part[p][i] = (sum_j p_ij, sum_j C_ij p_ij, the two minima) of
+// split p, combined in order by cert_rows_merge.
 // ---------------------------------------------------------------------------
 template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int Dm, double cA,
@@ -1127,17 +1129,19 @@ __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int Dm, double cA,
                                                    const double* __restrict__ yn2,
                                                    const double* __restrict__ gA,
                                                    const double* __restrict__ H,
-                                                   const double* __restrict__ r,
                                                    const double* __restrict__ nu,
                                                    const double* __restrict__ theta,
-                                                   double* __restrict__ vals, double* __restrict__ psum_out) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+                                                   double* __restrict__ part, int64_t split) {
+    const SweepBlock sb = sweep_block(kc.m, split);
+    const int64_t i = sb.bx * BLOCK + threadIdx.x;
     if (i >= kc.n) return;
+    const int64_t j0 = sb.p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
     const OwnPoint<M, D> own(xc + i * Dm, Dm, kc);
     const double h = H[i];
     double psum = 0.0, csum = 0.0, mth = __builtin_inf(), mnu = __builtin_inf();
-    for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
-        const int64_t je = min(kc.m, jb + UNROLL);
+    for (int64_t jb = j0; jb < j1; jb += UNROLL) {
+        const int64_t je = min(j1, jb + UNROLL);
         float ap = 0.f, ac = 0.f;
         for (int64_t j = jb; j < je; ++j) {
             const double dot = own.pair(yc + j * Dm);
@@ -1151,20 +1155,44 @@ __global__ __launch_bounds__(BLOCK) void cert_rows(Consts kc, int Dm, double cA,
         psum += (double)ap;
         csum += (double)ac;
     }
+    double* o = part + (sb.p * kc.n + i) * 4;
+    o[0] = psum;
+    o[1] = csum;
+    o[2] = mth;
+    o[3] = mnu;
+}
+
+// The splits of the certificate row pass in order: the two sums added, the minima taken;
+// mu (2 x n) keeps the minima for the entropic pass.
+__global__ void cert_rows_merge(Consts kc, int P, const double* __restrict__ r, const double* __restrict__ part,
+                                double* __restrict__ vals, double* __restrict__ psum_out, double* __restrict__ mu) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    double psum = 0.0, csum = 0.0, mth = __builtin_inf(), mnu = __builtin_inf();
+    for (int p = 0; p < P; ++p) {
+        const double* o = part + ((int64_t)p * kc.n + i) * 4;
+        psum += o[0];
+        csum += o[1];
+        mth = fmin(mth, o[2]);
+        mnu = fmin(mnu, o[3]);
+    }
     const double ri = r[i];
     vals[i] = ri * fabs(psum - 1.0);
     vals[kc.n + i] = ri * csum;
     vals[2 * kc.n + i] = ri * mth;
     vals[3 * kc.n + i] = ri * mnu;
-    if (psum_out) psum_out[i] = psum;
+    psum_out[i] = psum;
+    mu[i] = mth;
+    mu[kc.n + i] = mnu;
 }
 
 // ---------------------------------------------------------------------------
 // Entropic dual values at eta = 1/lam > 0 (def:dual_spp_e): per row i and dual v in {theta, nu},
 //   softmin_i(v) = mu_i - eta ln sum_j exp(-(C_ij + K v_j - mu_i) / eta),  mu_i = min_j (C_ij + K v_j),
-// the minimum in FP64 (a first pass), the terms (each <= 1, one of them 1) as FP32 exponentials of
-// FP64 arguments summed in FP32 over blocks of UNROLL columns and in FP64 across them.
-//   vals[0][i] = r_i softmin_i(theta),  vals[1][i] = r_i softmin_i(nu).
+// with the minimum exact in FP64 (from the certificate row pass), the terms (each <= 1, one of
+// them 1) FP32 exponentials of FP64 arguments summed in FP32 over blocks of UNROLL columns and in
+// FP64 across them and across the splits (in order).
+//   part[p][i] = (split p's sum for theta, for nu);  vals[0][i] = r_i softmin_i(theta), vals[1][i] likewise.
 // ---------------------------------------------------------------------------
 template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void cert_soft_rows(Consts kc, int Dm, double lam,
@@ -1172,36 +1200,48 @@ __global__ __launch_bounds__(BLOCK) void cert_soft_rows(Consts kc, int Dm, doubl
                                                         const double* __restrict__ yc,
                                                         const double* __restrict__ xn2,
                                                         const double* __restrict__ yn2,
-                                                        const double* __restrict__ r,
                                                         const double* __restrict__ nu,
                                                         const double* __restrict__ theta,
-                                                        double* __restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+                                                        const double* __restrict__ mu,
+                                                        double* __restrict__ part, int64_t split) {
+    const SweepBlock sb = sweep_block(kc.m, split);
+    const int64_t i = sb.bx * BLOCK + threadIdx.x;
     if (i >= kc.n) return;
+    const int64_t j0 = sb.p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
     const OwnPoint<M, D> own(xc + i * Dm, Dm, kc);
-    auto cost = [&](int64_t j) { return kc.s * (xn2[i] + yn2[j] - 2.0 * own.pair(yc + j * Dm)); };
-    double mth = __builtin_inf(), mnu = __builtin_inf();
-    for (int64_t j = 0; j < kc.m; ++j) {
-        const double cij = cost(j);
-        mth = fmin(mth, cij + kc.K * theta[j]);
-        mnu = fmin(mnu, cij + kc.K * nu[j]);
-    }
+    const double mth = mu[i], mnu = mu[kc.n + i];
     const double f = -lam * LOG2E;
     double sth = 0.0, snu = 0.0;
-    for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
-        const int64_t je = min(kc.m, jb + UNROLL);
+    for (int64_t jb = j0; jb < j1; jb += UNROLL) {
+        const int64_t je = min(j1, jb + UNROLL);
         float at = 0.f, an = 0.f;
         for (int64_t j = jb; j < je; ++j) {
-            const double cij = cost(j);
+            const double cij = kc.s * (xn2[i] + yn2[j] - 2.0 * own.pair(yc + j * Dm));
             at += fexp2(f * (cij + kc.K * theta[j] - mth));
             an += fexp2(f * (cij + kc.K * nu[j] - mnu));
         }
         sth += (double)at;
         snu += (double)an;
     }
+    double* o = part + (sb.p * kc.n + i) * 2;
+    o[0] = sth;
+    o[1] = snu;
+}
+
+__global__ void cert_soft_merge(Consts kc, int P, double lam, const double* __restrict__ r,
+                                const double* __restrict__ mu, const double* __restrict__ part,
+                                double* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    double sth = 0.0, snu = 0.0;
+    for (int p = 0; p < P; ++p) {
+        sth += part[((int64_t)p * kc.n + i) * 2];
+        snu += part[((int64_t)p * kc.n + i) * 2 + 1];
+    }
     const double ri = r[i];
-    vals[i] = ri * (mth - log(sth) / lam);
-    vals[kc.n + i] = ri * (mnu - log(snu) / lam);
+    vals[i] = ri * (mu[i] - log(sth) / lam);
+    vals[kc.n + i] = ri * (mu[kc.n + i] - log(snu) / lam);
 }
 
 // ---------------------------------------------------------------------------
@@ -1270,21 +1310,24 @@ __global__ void round_col_factors(Consts kc, const double* __restrict__ c, const
 
 // Rows of X'': dr_i = r_i - xr_i r_i sum_j p_ij y_j and cpp_i = xr_i r_i sum_j C_ij p_ij y_j.
 // dr is formed as r_i (1 - xr_i psum_i) + xr_i r_i sum_j p_ij (1 - y_j) (the same value)
-// with psum_i recomputed in this pass: no difference of two nearly equal sums.
+// with psum_i recomputed in this pass: no difference of two nearly equal sums.  Over XCD-aware
+// column splits: part[p][i] = split p's three sums, combined in order by round_rows_merge.
 template <int M, int D>
 __global__ __launch_bounds__(BLOCK) void round_rows(Consts kc, int Dm, double cA, const double* __restrict__ xc,
                                                     const double* __restrict__ yc, const double* __restrict__ xn2,
                                                     const double* __restrict__ yn2, const double* __restrict__ gA,
-                                                    const double* __restrict__ H, const double* __restrict__ r,
-                                                    const double* __restrict__ xr, const double* __restrict__ y,
-                                                    double* __restrict__ dr, double* __restrict__ cpp) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+                                                    const double* __restrict__ H, const double* __restrict__ y,
+                                                    double* __restrict__ part, int64_t split) {
+    const SweepBlock sb = sweep_block(kc.m, split);
+    const int64_t i = sb.bx * BLOCK + threadIdx.x;
     if (i >= kc.n) return;
+    const int64_t j0 = sb.p * split;
+    const int64_t j1 = min(kc.m, j0 + split);
     const OwnPoint<M, D> own(xc + i * Dm, Dm, kc);
     const double h = H[i];
     double ps = 0.0, pq = 0.0, cs = 0.0;
-    for (int64_t jb = 0; jb < kc.m; jb += UNROLL) {
-        const int64_t je = min(kc.m, jb + UNROLL);
+    for (int64_t jb = j0; jb < j1; jb += UNROLL) {
+        const int64_t je = min(j1, jb + UNROLL);
         float a = 0.f, b = 0.f, e = 0.f;
         for (int64_t j = jb; j < je; ++j) {
             const double dot = own.pair(yc + j * Dm);
@@ -1298,6 +1341,23 @@ __global__ __launch_bounds__(BLOCK) void round_rows(Consts kc, int Dm, double cA
         ps += (double)a;
         pq += (double)b;
         cs += (double)e;
+    }
+    double* o = part + (sb.p * kc.n + i) * 3;
+    o[0] = ps;
+    o[1] = pq;
+    o[2] = cs;
+}
+
+__global__ void round_rows_merge(Consts kc, int P, const double* __restrict__ r, const double* __restrict__ xr,
+                                 const double* __restrict__ part, double* __restrict__ dr, double* __restrict__ cpp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    double ps = 0.0, pq = 0.0, cs = 0.0;
+    for (int p = 0; p < P; ++p) {
+        const double* o = part + ((int64_t)p * kc.n + i) * 3;
+        ps += o[0];
+        pq += o[1];
+        cs += o[2];
     }
     const double w = xr[i] * r[i];
     dr[i] = r[i] * (1.0 - xr[i] * ps) + w * pq;
