@@ -40,7 +40,8 @@ CUS, CLOCK = 256, 2.4e9
 EXP_PEAK = CUS * 32 * CLOCK          # 1.966e13 exp/s
 HBM_PEAK = 8.0e12                    # bytes/s, HBM3E
 MFMA_PEAK = {"fp32": 78.6e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2500e12, "fp16_mfma": 2500e12}
-FORM_DTYPE = {"fp32": "f64/f32", "fp32_mfma": "f32", "bf16_mfma": "bf16/f32", "fp16_mfma": "f16/f32"}
+FORM_DTYPE = {"fp32": "f64/f32", "fp32_mfma": "f32", "bf16_mfma": "bf16/f32", "fp16_mfma": "f16/f32",
+              "fp16x3_mfma": "f16x3/f32"}
 FORM_DESC = {
     "fp32": "x.y and exponent arguments in FP64, exponentials and sums FP32, duals FP64",
     "fp32_mfma": "x.y tiles on FP32 matrix cores, exponent assembled in FP32, duals FP64",
@@ -48,6 +49,8 @@ FORM_DESC = {
                  "and sums, FP64 duals",
     "fp16_mfma": "x.y tiles from FP16 points on matrix cores (FP32 accumulate), FP32 exponent "
                  "and sums, FP64 duals",
+    "fp16x3_mfma": "x.y as x_hi.y_hi + x_hi.y_lo + x_lo.y_hi from split FP16 points on matrix cores "
+                   "(FP32 accumulate), FP32 exponent and sums, FP64 duals",
 }
 
 
@@ -424,11 +427,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", default="gmm64d_65536")
     ap.add_argument("--precision", default="bf16_mfma",
-                    choices=["fp32", "fp32_mfma", "bf16_mfma", "fp16_mfma"])
-    ap.add_argument("--compare", default="fp32_mfma,fp32",
+                    choices=["fp32", "fp32_mfma", "bf16_mfma", "fp16_mfma", "fp16x3_mfma"])
+    ap.add_argument("--compare", default="fp16x3_mfma,fp32_mfma,fp32",
                     help="other forms measured beside the primary one (comma list, '' for none)")
     ap.add_argument("--compare-steps", type=int, default=10)
-    ap.add_argument("--time-to-tol", default="bf16_mfma,fp16_mfma,fp32_mfma,fp32",
+    ap.add_argument("--time-to-tol", default="bf16_mfma,fp16_mfma,fp16x3_mfma,fp32_mfma,fp32",
                     help="forms solved from the start to the tolerance (comma list, '' for none)")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=20000)

@@ -50,8 +50,15 @@ typedef enum {
                                 in FP32, duals FP64                               */
     LAMP_BF16_MFMA = 2,      /* x.y^T tiles from BF16 points on matrix cores with
                                 FP32 accumulation; exponentials and sums FP32      */
-    LAMP_FP16_MFMA = 3       /* as LAMP_BF16_MFMA with FP16 points                 */
-} lamp_precision;           /* matrix-core forms need d <= 128                     */
+    LAMP_FP16_MFMA = 3,      /* as LAMP_BF16_MFMA with FP16 points                 */
+    LAMP_FP16X3_MFMA = 4     /* x.y^T from split FP16 points on matrix cores: each
+                                centred coordinate, times a power-of-two range
+                                scale, as hi + lo (two FP16 roundings), and
+                                x_hi.y_hi + x_hi.y_lo + x_lo.y_hi in one FP16
+                                contraction over 3 d entries with FP32
+                                accumulation (about 22 significant bits against
+                                FP16's 11); exponentials and sums FP32; d <= 64   */
+} lamp_precision;           /* the other matrix-core forms need d <= 128           */
 
 /* Ground cost C_ij = s dist(x_i, y_j) generated from the point clouds: the squared
  * Euclidean cost of Sections 1 and 4.1, and the l1 and l_inf costs of the

@@ -21,7 +21,7 @@ LAMP_FP32 = 0
 LAMP_FP32_MFMA = 1
 LAMP_BF16_MFMA = 2
 LAMP_FP16_MFMA = 3
-PRECISIONS = {"fp32": 0, "fp32_mfma": 1, "bf16_mfma": 2, "fp16_mfma": 3}
+PRECISIONS = {"fp32": 0, "fp32_mfma": 1, "bf16_mfma": 2, "fp16_mfma": 3, "fp16x3_mfma": 4}
 LAMP_SQEUCLID = 0
 LAMP_L1 = 1
 LAMP_LINF = 2

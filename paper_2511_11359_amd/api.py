@@ -93,7 +93,7 @@ def make_params(eta: float = 0.0, tol: float = 0.0, max_iter: int = 1000, alpha:
                 beta: float = 0.0, tau1: float = 0.0, tau2: float = 0.0,
                 check_every: int = 64, precision: str = "fp32", track_dt: bool = False) -> L.Params:
     """Algorithm 2 parameters; zeros select the defaults of Appendix E.  precision is one of
-    fp32 (FP64 arguments, FP32 exponentials), fp32_mfma, bf16_mfma, fp16_mfma.  track_dt
+    fp32 (FP64 arguments, FP32 exponentials), fp32_mfma, bf16_mfma, fp16_mfma, fp16x3_mfma.  track_dt
     accumulates the partial sums D_t of Proposition infeas_bound(b) in the state (fp32 only)."""
     return L.Params(eta, tol, int(max_iter), alpha, beta, tau1, tau2, L.PRECISIONS[precision],
                     int(check_every), int(bool(track_dt)), 0)

@@ -103,13 +103,20 @@ struct Layout {
     int64_t split_rx, P_rx, split_cx, P_cx;
 };
 
-bool is_mfma(int prec) { return prec == LAMP_FP32_MFMA || prec == LAMP_BF16_MFMA || prec == LAMP_FP16_MFMA; }
+bool is_mfma(int prec) {
+    return prec == LAMP_FP32_MFMA || prec == LAMP_BF16_MFMA || prec == LAMP_FP16_MFMA || prec == LAMP_FP16X3_MFMA;
+}
 
 // Smallest supported operand width >= d for the matrix-core forms (0: unsupported).
 int mfma_kp(int prec, int d) {
     if (prec == LAMP_FP32_MFMA) {
         for (int kp : {4, 16, 64, 128})
             if (d <= kp) return kp;
+        return 0;
+    }
+    if (prec == LAMP_FP16X3_MFMA) {   // three parts of d coordinates per point (split operands)
+        for (int kp : {16, 64, 128, 192})
+            if (3 * d <= kp) return kp;
         return 0;
     }
     for (int kp : {16, 64, 128})
@@ -261,7 +268,11 @@ RowVarF32 rowvar_f32(const Layout& L, void* ws) {
 
 struct Resolved {
     double s, cnorm, K, tau1, tau2, alpha, beta, kappa, clipb;
+    double dscale = 1.0;   // 1 / (range scale)^2 of the split FP16 operands, else 1
 };
+
+// Slot of the small-scalar area holding the split FP16 form's range scale (prep -> resolve).
+constexpr int SPLIT_SCALE_SLOT = 40;
 
 lamp_status check_problem(const lamp_problem* p) {
     if (!p) return fail(LAMP_EINVAL, "problem is NULL");
@@ -305,7 +316,8 @@ lamp_status check_params(const lamp_params* q) {
 
 lamp_status check_ws(const lamp_problem* p, void* ws, size_t ws_bytes, int prec = LAMP_FP32) {
     if (is_mfma(prec) && mfma_kp(prec, p->d) == 0)
-        return fail(LAMP_EINVAL, "the matrix-core forms support d <= 128 (got %d)", p->d);
+        return fail(LAMP_EINVAL, "the matrix-core forms support d <= 128, the split FP16 form d <= 64 (got %d)",
+                    p->d);
     if (is_mfma(prec) && p->metric != LAMP_SQEUCLID)
         return fail(LAMP_EINVAL, "the matrix-core forms need the squared Euclidean cost (inner products)");
     const Layout L = layout(p->n, p->m, p->d, prec, TARGET_BLOCKS, p->metric);
@@ -371,9 +383,23 @@ lamp_status prep_L(const lamp_problem* p, const Layout& L, void* ws, hipStream_t
                            p->m, p->d, L.KP64, L.m_pad64, at<double>(ws, L.yop64));
     }
     if (is_mfma(prec)) {
-        if (prec == LAMP_FP32_MFMA) prep_ops<float>(p, L, ws, st);
-        else if (prec == LAMP_BF16_MFMA) prep_ops<__bf16>(p, L, ws, st);
-        else prep_ops<_Float16>(p, L, ws, st);
+        if (prec == LAMP_FP32_MFMA) {
+            prep_ops<float>(p, L, ws, st);
+        } else if (prec == LAMP_BF16_MFMA) {
+            prep_ops<__bf16>(p, L, ws, st);
+        } else if (prec == LAMP_FP16X3_MFMA) {
+            double* scale = at<double>(ws, L.small) + SPLIT_SCALE_SLOT;
+            hipLaunchKernelGGL(split_scale, dim3(1), dim3(1024), 0, st, (const double*)at<double>(ws, L.xc),
+                               p->n * p->d, (const double*)at<double>(ws, L.yc), p->m * p->d, scale);
+            hipLaunchKernelGGL(prep_operands_split, grid1(L.n_pad * L.KP), dim3(BLOCK), 0, st,
+                               (const double*)at<double>(ws, L.xc), p->n, p->d, L.KP, L.n_pad, (const double*)scale,
+                               0, at<_Float16>(ws, L.xop));
+            hipLaunchKernelGGL(prep_operands_split, grid1(L.m_pad * L.KP), dim3(BLOCK), 0, st,
+                               (const double*)at<double>(ws, L.yc), p->m, p->d, L.KP, L.m_pad, (const double*)scale,
+                               1, at<_Float16>(ws, L.yop));
+        } else {
+            prep_ops<_Float16>(p, L, ws, st);
+        }
         if (L.m_pad > p->m)
             hipLaunchKernelGGL(pad_gtabf, grid1(L.m_pad - p->m), dim3(BLOCK), 0, st, p->m, L.m_pad,
                                at<float2>(ws, L.gtabf));
@@ -541,7 +567,8 @@ void sweep_mfma(const Layout& L, Consts kc, void* ws, hipStream_t st) {
         switch (L.KP) {
             case 16: MF(_Float16, 16)
             case 64: MF(_Float16, 64)
-            default: MF(_Float16, 128)
+            case 128: MF(_Float16, 128)
+            default: MF(_Float16, 192)
         }
     }
 #undef MF
@@ -761,6 +788,14 @@ lamp_status resolve_L(const lamp_problem* p, const lamp_params* q, const Layout&
     R->kappa = 2.0 * R->tau2 * cn;
     R->clipb = std::tanh(R->beta / 2.0);
     if (R->tau1 * q->eta > 1.0) return fail(LAMP_EINVAL, "tau1 * eta = %g > 1", R->tau1 * q->eta);
+    R->dscale = 1.0;
+    if (L.prec == LAMP_FP16X3_MFMA) {
+        double sc = 0.0;
+        HIPCHK(hipMemcpyAsync(&sc, at<double>(ws, L.small) + SPLIT_SCALE_SLOT, sizeof(double), hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipStreamSynchronize(st));
+        R->dscale = 1.0 / (sc * sc);
+    }
     return LAMP_OK;
 }
 
@@ -779,6 +814,7 @@ Consts make_consts(const lamp_problem* p, const Resolved& R) {
     kc.clipb = R.clipb;
     kc.metric = p->metric;
     kc.factor_cols = 2.0 * LOG2E * R.K * R.tau1 <= 64.0;
+    kc.dscale = R.dscale;
     kc.cost = p->metric == LAMP_EXPLICIT ? p->cost : nullptr;
     kc.cost_type = p->metric == LAMP_EXPLICIT ? p->cost_type : COST_F32;
     return kc;
@@ -836,7 +872,8 @@ void launch_extreme_mfma(const Layout& L, Consts kc, void* ws, const Ctrl* ctrl,
         switch (L.KP) {
             case 16: EX(_Float16, 16)
             case 64: EX(_Float16, 64)
-            default: EX(_Float16, 128)
+            case 128: EX(_Float16, 128)
+            default: EX(_Float16, 192)
         }
     }
 #undef EX

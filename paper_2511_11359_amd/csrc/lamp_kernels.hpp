@@ -80,6 +80,8 @@ struct Consts {
     double clipb;   // tanh(beta / 2)
     int metric;     // ground cost, METRIC_*
     int factor_cols;     // one-chain matrix-core column sweep: per-column factor (see there)
+    double dscale;       // matrix-core dot products are dscale^-1 times x~.y~ (a power of two; 1 but
+                         // for the split FP16 form, whose operands carry a range scale)
     int cost_type;       // COST_* element type of `cost`
     const void* cost;    // METRIC_EXPLICIT: the caller's n x m cost matrix, row-major
 };

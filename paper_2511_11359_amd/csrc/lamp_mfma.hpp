@@ -71,6 +71,48 @@ __global__ void prep_operands(const double* __restrict__ src, int64_t cnt, int d
     out[idx] = (i < cnt && k < d) ? (T)src[i * d + k] : (T)0.f;
 }
 
+// Split FP16 operands: with v the FP64 centred coordinate times the range scale (a power of
+// two), hi = fp16(v) and lo = fp16(v - hi), each a single rounding to nearest even.  A point's
+// row of KP entries holds [hi, hi, lo] (side 0, the source points) or [hi, lo, hi] (side 1,
+// the targets), d entries each, zero padded, so that one FP16 contraction over 3 d entries is
+//     x_hi . y_hi + x_hi . y_lo + x_lo . y_hi
+// (the dot product of the scaled points but for x_lo . y_lo and the parts below lo).
+__global__ void prep_operands_split(const double* __restrict__ src, int64_t cnt, int d, int KP, int64_t cnt_pad,
+                                    const double* __restrict__ scale, int side, _Float16* __restrict__ out) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= cnt_pad * KP) return;
+    const int64_t i = idx / KP;
+    const int k = (int)(idx % KP);
+    _Float16 v = (_Float16)0.f;
+    if (i < cnt && k < 3 * d) {
+        const int part = k / d;   // 0, 1, 2
+        const double x = src[i * d + (k - part * d)] * *scale;
+        const _Float16 hi = (_Float16)x;
+        const bool lo = side == 0 ? part == 2 : part == 1;
+        v = lo ? (_Float16)(x - (double)hi) : hi;
+    }
+    out[idx] = v;
+}
+
+// The range scale of the split FP16 operands: *scale = 2^(7 - e) with 2^e <= max |coordinate|
+// < 2^(e+1) over both centred clouds, so that every scaled coordinate is below 256 (its hi
+// part far from the FP16 limit, its lo part resolved to 2^-24 absolute or better); 1 if all
+// coordinates are zero.  One block, a max-reduction in any order (the maximum is exact).
+__global__ void split_scale(const double* __restrict__ xc, int64_t nx, const double* __restrict__ yc, int64_t ny,
+                            double* __restrict__ scale) {
+    __shared__ double sh[1024];
+    double mx = 0.0;
+    for (int64_t k = threadIdx.x; k < nx; k += blockDim.x) mx = fmax(mx, fabs(xc[k]));
+    for (int64_t k = threadIdx.x; k < ny; k += blockDim.x) mx = fmax(mx, fabs(yc[k]));
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *scale = sh[0] > 0.0 ? ldexp(1.0, 7 - ilogb(sh[0])) : 1.0;
+}
+
 // Padded entries of the FP32 column tables (both parities): zero weight in every sum.
 __global__ void pad_gtabf(int64_t m, int64_t m_pad, float2* __restrict__ gtabf) {
     int64_t j = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -377,8 +419,10 @@ __global__ __launch_bounds__(BLOCK, (row_sweep_min_waves<T, KP>())) void row_swe
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
-    const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E);
-    const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
+    // the products come scaled by 1 / dscale (a power of two): the factors of the products
+    // take dscale, the offsets entering the accumulator 1 / dscale (exact scalings)
+    const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E * kc.dscale);
+    const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E * kc.dscale);
     const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
     const int lane = threadIdx.x & 63;
     const int hf = lane >> 5, c32 = lane & 31;
@@ -398,7 +442,7 @@ __global__ __launch_bounds__(BLOCK, (row_sweep_min_waves<T, KP>())) void row_swe
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         int64_t ii = i0 + mfma_row(r, hf);
-        hv[r] = (float)H[ii < kc.n ? ii : kc.n - 1];
+        hv[r] = (float)(H[ii < kc.n ? ii : kc.n - 1] / kc.dscale);
     }
     float accA[16], accB[16];
 #pragma unroll
@@ -473,6 +517,7 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_mfma_lds(const Ctrl* ctrl, 
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
     const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
+    const float cBd = (float)(2.0 * kc.s * sc.lamB * LOG2E * kc.dscale);   // the factor of the scaled products
     const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
     const int lane = threadIdx.x & 63;
     const int hf = lane >> 5, c32 = lane & 31;
@@ -508,7 +553,7 @@ __global__ __launch_bounds__(BLOCK) void row_extreme_mfma_lds(const Ctrl* ctrl, 
         const floatx16 d = tile_dot<T, KP>(lds[cur], c32, hf, a, zero);
         const float2 gg = *reinterpret_cast<const float2*>(lds[cur] + 32 * L::STRIDE + c32 * 16);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) mx[r] = fmaxf(mx[r], fmaf(d[r], cB, gg.y));
+        for (int r = 0; r < 16; ++r) mx[r] = fmaxf(mx[r], fmaf(d[r], cBd, gg.y));
         if (jt + 1 < jt1) tile_store<T, KP>(lds[cur ^ 1], pf);
         __syncthreads();
     }
@@ -560,6 +605,10 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
     const Sched sc = sched[t - ctrl->t_base];
     const float cA = (float)(2.0 * kc.s * sc.lamA * LOG2E);
     const float cB = (float)(2.0 * kc.s * sc.lamB * LOG2E);
+    // factors of the products, which come scaled by 1 / dscale (a power of two); the column
+    // terms G below are in the same scaled units, the row offsets k_i are not
+    const float cAd = (float)(2.0 * kc.s * sc.lamA * LOG2E * kc.dscale);
+    const float cBd = (float)(2.0 * kc.s * sc.lamB * LOG2E * kc.dscale);
     const int lane = threadIdx.x & 63;
     const int hf = lane >> 5, c32 = lane & 31;
     const int64_t b = blockIdx.x;
@@ -580,11 +629,11 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const float2 gg = g[j0 + mfma_row(r, hf)];
-        GA[r] = cA > 0.f ? gg.x / cA : 0.f;
-        GB[r] = gg.y / cB;
+        GA[r] = cAd > 0.f ? gg.x / cAd : 0.f;
+        GB[r] = gg.y / cBd;
         if (gg.x <= PAD_NEG) GA[r] = PAD_NEG;
         if (gg.y <= PAD_NEG) GB[r] = PAD_NEG;
-        CA[r] = gg.x <= PAD_NEG ? PAD_NEG : gg.x - cA * GB[r];
+        CA[r] = gg.x <= PAD_NEG ? PAD_NEG : gg.x - cAd * GB[r];
     }
     float accA[16], accB[16];
 #pragma unroll
@@ -631,10 +680,10 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
                 const float ckA = cA * qc.x, ckB = cB * qc.x;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const float eA = !ONE_CHAIN ? fmaf(dcA[r], cA, ckA)
-                                                : (FACTOR ? fmaf(dcB[r], cA, ckA) : fmaf(dcB[r], cA, ckA) + CA[r]);
+                    const float eA = !ONE_CHAIN ? fmaf(dcA[r], cAd, ckA)
+                                                : (FACTOR ? fmaf(dcB[r], cAd, ckA) : fmaf(dcB[r], cAd, ckA) + CA[r]);
                     accA[r] = fmaf(qc.y, __builtin_amdgcn_exp2f(eA), accA[r]);
-                    accB[r] = fmaf(qc.z, __builtin_amdgcn_exp2f(fmaf(dcB[r], cB, ckB)), accB[r]);
+                    accB[r] = fmaf(qc.z, __builtin_amdgcn_exp2f(fmaf(dcB[r], cBd, ckB)), accB[r]);
                 }
                 pin(accA);
                 pin(accB);

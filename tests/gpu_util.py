@@ -123,3 +123,22 @@ def mfma_term_bound(xr, yr, yn2, s, lam, duals, kp, kstep, cnorm=1.0, erange=64.
     c = 2.0 * s * lam * LOG2E
     de = U32 * (c * A * (kp // kstep + 3) + 3.0 * c * Q + erange)
     return float(np.log(2.0) * de)
+
+
+def split_fp16_scale(xc, yc):
+    """Range scale of the split FP16 form (a power of two): 2^(7 - e) with 2^e <= max |coordinate|
+    < 2^(e+1) over both centred clouds, 1 when every coordinate is zero."""
+    mx = max(float(np.max(np.abs(xc))), float(np.max(np.abs(yc))))
+    if mx == 0.0:
+        return 1.0
+    _, e = np.frexp(mx)                      # mx = f 2^e, 1/2 <= f < 1: floor(log2 mx) = e - 1
+    return float(np.ldexp(1.0, 7 - (int(e) - 1)))
+
+
+def split_fp16(v, scale):
+    """(hi, lo) of the split FP16 form for FP64 values v: hi = fp16(v scale), lo = fp16(v scale - hi),
+    each one rounding to nearest even (the scaled value and the difference are exact in FP64)."""
+    vs = np.asarray(v, dtype=np.float64) * scale
+    hi = round_to_type(vs, "float16")
+    lo = round_to_type(vs - hi, "float16")
+    return hi, lo

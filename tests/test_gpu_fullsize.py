@@ -32,6 +32,7 @@ from oracle import rowpass as RP
 from oracle import stream as OS
 from paper_2511_11359_amd import workloads as W
 from tests.gpu_util import (U32, mfma_term_bound, rel_dual, rel_inf, round_to_type, sample_columns,
+                            split_fp16, split_fp16_scale,
                             to_np)
 
 pytestmark = pytest.mark.gpu
@@ -45,6 +46,21 @@ import paper_2511_11359_amd as P  # noqa: E402
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cost_scales.json")))
 SAMPLE = np.array([0, 1, 31, 32, 4095, 12345, 33333, 65535])
 
+
+
+def _operands(dtype, xc, yc):
+    """The operands whose FP64 inner products give the cost a matrix-core form computes, and the
+    operand width: each centred coordinate rounded once to the operand type; for the split FP16
+    form ("fp16x3") the three-part vectors [x_hi, x_hi, x_lo] and [y_hi, y_lo, y_hi] of the
+    range-scaled points, divided back by the scale (exact, a power of two)."""
+    if dtype == "fp16x3":
+        sc = split_fp16_scale(xc, yc)
+        xh, xl = split_fp16(xc, sc)
+        yh, yl = split_fp16(yc, sc)
+        d = xc.shape[1]
+        kp = next(k for k in (16, 64, 128, 192) if 3 * d <= k)
+        return np.hstack([xh, xh, xl]) / sc, np.hstack([yh, yl, yh]) / sc, kp
+    return round_to_type(xc, dtype), round_to_type(yc, dtype), 64
 
 def _say(*a):
     print(*a, flush=True)
@@ -181,23 +197,23 @@ def test_gmm64_65536_fp32_step():
 
 
 @pytest.mark.parametrize("form,dtype,kstep", [("bf16_mfma", "bfloat16", 16), ("fp16_mfma", "float16", 16),
-                                              ("fp32_mfma", "float32", 2)])
+                                              ("fp32_mfma", "float32", 2), ("fp16x3_mfma", "fp16x3", 16)])
 def test_gmm64_65536_mfma_step(form, dtype, kstep):
     """2^16 x 2^16, d = 64: one matrix-core iteration at t = 300 (every row, sampled columns)
     against the oracle evaluated on the cost the form computes: each centred coordinate rounded
-    once to the operand type, FP64 inner products of the rounded operands, unrounded squared norms,
-    C_ij = s (|x~_i|^2 + |y~_j|^2 - 2 xr_i . yr_j)."""
+    once to the operand type (for the split FP16 form: its three-part operands), FP64 inner
+    products of the operands, unrounded squared norms, C_ij = s (|x~_i|^2 + |y~_j|^2 - 2 xr_i . yr_j)."""
     key = "gmm64d_65536"
     wl = W.gmm64()
     x = wl.x.astype(np.float64)
     y = wl.y.astype(np.float64)
     mu = 0.5 * (x[0] + y[0])
     xc, yc = x - mu, y - mu
-    xr, yr = round_to_type(xc, dtype), round_to_type(yc, dtype)
+    xr, yr, kp = _operands(dtype, xc, yc)
     nx, ny = np.sum(xc * xc, axis=1), np.sum(yc * yc, axis=1)
     s = GOLD[key]["cost_scale"]
     nu, th, lam_t, lam_t1 = _synthetic_state(wl, 300, seed=77)
-    term = mfma_term_bound(xr, yr, ny, s, lam_t1, [nu, th], 64, kstep)
+    term = mfma_term_bound(xr, yr, ny, s, lam_t1, [nu, th], kp, kstep)
     logz_tol = term + (wl.m / 256 + 6) * U32
     col_tol = logz_tol + term + (wl.n / 256 + 6) * U32
     _say(form, f"per-term bound {term:.2e}: logZ tol {logz_tol:.2e}, column tol {col_tol:.2e}")
@@ -297,7 +313,7 @@ def test_images_256_explicit_cost_step():
 
 @pytest.mark.parametrize("shape", [(4096, 65536), (65536, 4096)])
 @pytest.mark.parametrize("form,dtype,kstep", [("bf16_mfma", "bfloat16", 16), ("fp16_mfma", "float16", 16),
-                                              ("fp32_mfma", "float32", 2)])
+                                              ("fp32_mfma", "float32", 2), ("fp16x3_mfma", "fp16x3", 16)])
 def test_gmm64_medium_mfma_step_every_row_and_column(shape, form, dtype, kstep):
     """d = 64 GMM points at n x m = 4096 x 65536 and 65536 x 4096: each split of both sweeps
     streams 16 tiles, so the pipelined tile loop (prefetch two tiles ahead, buffer swap, clamped
@@ -310,12 +326,12 @@ def test_gmm64_medium_mfma_step_every_row_and_column(shape, form, dtype, kstep):
     s = 1.0 / cmax.max_sqdist(wl.x, wl.y)
     mu = 0.5 * (x[0] + y[0])
     xc, yc = x - mu, y - mu
-    xr, yr = round_to_type(xc, dtype), round_to_type(yc, dtype)
+    xr, yr, kp = _operands(dtype, xc, yc)
     nx, ny = np.sum(xc * xc, axis=1), np.sum(yc * yc, axis=1)
     t = 300
     nu, th = W.synthetic_duals(m, 78)
     lam = OL.inv_eta_schedule(t + 1, 0.5, wl.eta)
-    term = mfma_term_bound(xr, yr, ny, s, lam[t + 1], [nu, th], 64, kstep)
+    term = mfma_term_bound(xr, yr, ny, s, lam[t + 1], [nu, th], kp, kstep)
     logz_tol = term + (m / 256 + 6) * U32
     col_tol = logz_tol + term + (n / 256 + 6) * U32
     prob = P.Problem(wl.x, wl.y, wl.r, wl.c, cost_scale=s, cost_norm=1.0)

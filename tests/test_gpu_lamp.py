@@ -15,6 +15,7 @@ from oracle import lamp as OL
 from oracle import stream as OS
 from paper_2511_11359_amd import workloads as W
 from tests.gpu_util import (U32, fp32_trajectory_allowance, gpu_problem, mfma_term_bound, oracle_problem,
+                            split_fp16, split_fp16_scale,
                             rel_dual, rel_inf, rel_l1, round_to_type, to_np)
 
 pytestmark = pytest.mark.gpu
@@ -309,7 +310,25 @@ def _rounded_cost(wl, s, dtype, parts=False):
     return (C, (xr, yr, nx, ny)) if parts else C
 
 
-MFMA_KSTEP = {"fp32_mfma": 2, "bf16_mfma": 16, "fp16_mfma": 16}
+def _split_cost(wl, s):
+    """The cost the split FP16 form evaluates: centred points times the range scale, split as
+    hi + lo in FP16, the dot product x_hi.y_hi + x_hi.y_lo + x_lo.y_hi divided by the scale
+    squared, norms from the unrounded centred points.  Also (effective x, effective y, nx, ny)."""
+    x = wl.x.astype(np.float64)
+    y = wl.y.astype(np.float64)
+    mu = 0.5 * (x[0] + y[0])
+    xc, yc = x - mu, y - mu
+    sc = split_fp16_scale(xc, yc)
+    xh, xl = split_fp16(xc, sc)
+    yh, yl = split_fp16(yc, sc)
+    dot = (xh @ yh.T + xh @ yl.T + xl @ yh.T) / (sc * sc)
+    nx = np.sum(xc * xc, axis=1)
+    ny = np.sum(yc * yc, axis=1)
+    C = s * (nx[:, None] + ny[None, :] - 2.0 * dot)
+    return C, ((xh + xl) / sc, (yh + yl) / sc, nx, ny)
+
+
+MFMA_KSTEP = {"fp32_mfma": 2, "bf16_mfma": 16, "fp16_mfma": 16, "fp16x3_mfma": 16}
 
 
 def _mfma_tolerances(form, parts, s, lam, duals, n, m, d):
@@ -319,6 +338,8 @@ def _mfma_tolerances(form, parts, s, lam, duals, n, m, d):
     kp = 16 if d <= 16 else (64 if d <= 64 else 128)
     if form == "fp32_mfma" and d <= 4:
         kp = 4
+    if form == "fp16x3_mfma":   # three parts of d entries per point
+        kp = next(k for k in (16, 64, 128, 192) if 3 * d <= k)
     term = mfma_term_bound(xr, yr, ny, s, lam, duals, kp, MFMA_KSTEP[form])
     logz = term + (m / 32 + 6) * U32
     return logz, logz + term + (n / 32 + 6) * U32
@@ -336,6 +357,35 @@ def test_mfma_step_matches_oracle_on_rounded_cost(form, dtype, shape):
     oracle run on the cost those forms evaluate (operands rounded to the operand type).  The
     remaining differences are FP32 accumulation and exponent assembly: tolerance 1e-4."""
     _mfma_step_check(form, dtype, shape)
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 2), (300, 173, 3), (160, 200, 64), (97, 130, 16), (3, 5, 1),
+                                   (200, 150, 40), (5, 4, 21)])
+def test_split_fp16_step_matches_oracle_on_its_cost(shape):
+    """One step of the split FP16 form (x.y as x_hi.y_hi + x_hi.y_lo + x_lo.y_hi from FP16
+    parts of the range-scaled centred points) against the oracle run on the cost that form
+    evaluates, with the same derived tolerances as the other matrix-core forms (its
+    contraction runs over 3 d entries: 16, 64, 128 or 192)."""
+    _mfma_step_check("fp16x3_mfma", None, shape)
+
+
+def test_split_fp16_cost_is_close_to_exact():
+    """The split form's cost against the exact one.  hi + lo carries each scaled coordinate to
+    2^-23 relative and the dropped x_lo.y_lo is 2^-22 of a product, so 2 s x.y moves by at most
+    6 x 2^-22 s sum_k |x_k y_k| <= 1.5e-6 s diam^2 (centred points lie within one diameter of the
+    origin), under 2^-19 max C; measured about 5e-8 (FP16 points: 1e-4); and d = 65 is
+    rejected."""
+    wl = W.random_small(300, 280, 64, seed=77, eta=1e-2)
+    x, y, s, C = oracle_problem(wl)
+    Cs, _ = _split_cost(wl, s)
+    Ch, _ = _rounded_cost(wl, s, torch.float16, parts=True)
+    e_split, e_half = np.max(np.abs(Cs - C)), np.max(np.abs(Ch - C))
+    _say(f"max |C~ - C|: split {e_split:.3e}, FP16 points {e_half:.3e}")
+    assert e_split <= 2.0 ** -19 * np.max(C)
+    bad = W.random_small(10, 10, 65, seed=1)
+    with pytest.raises(P.LampError):
+        P.step(P.Problem(bad.x, bad.y, bad.r, bad.c), P.make_params(eta=1e-2, precision="fp16x3_mfma"),
+               P.State.fresh(10))
 
 
 @pytest.mark.parametrize("form,dtype", [("bf16_mfma", torch.bfloat16), ("fp32_mfma", torch.float32)])
@@ -356,7 +406,7 @@ def _mfma_step_check(form, dtype, shape, tau1=None, eta=1e-2, t=20):
     wl = W.random_small(n, m, d, seed=300 + d, eta=eta)
     _say("case", form, wl.name, "tau1", tau1)
     x, y, s, C = oracle_problem(wl)
-    Cr, parts = _rounded_cost(wl, s, dtype, parts=True)
+    Cr, parts = _split_cost(wl, s) if form == "fp16x3_mfma" else _rounded_cost(wl, s, dtype, parts=True)
     prm = OL.Params(eta=wl.eta, tau1=tau1)
     st_or, _ = OL.lamp_dense(Cr, wl.r, wl.c, prm, t, 1.0, trace=False)
     st_next, tr_or = OL.lamp_dense(Cr, wl.r, wl.c, prm, 1, 1.0, state=st_or)
