@@ -271,7 +271,8 @@ struct Resolved {
     double dscale = 1.0;   // 1 / (range scale)^2 of the split FP16 operands, else 1
 };
 
-// Slot of the small-scalar area holding the split FP16 form's range scale (prep -> resolve).
+// Slot of the small-scalar area holding the split FP16 form's range scale (prep -> resolve);
+// the next slot holds the running maximum its reduction folds into.
 constexpr int SPLIT_SCALE_SLOT = 40;
 
 lamp_status check_problem(const lamp_problem* p) {
@@ -389,8 +390,13 @@ lamp_status prep_L(const lamp_problem* p, const Layout& L, void* ws, hipStream_t
             prep_ops<__bf16>(p, L, ws, st);
         } else if (prec == LAMP_FP16X3_MFMA) {
             double* scale = at<double>(ws, L.small) + SPLIT_SCALE_SLOT;
-            hipLaunchKernelGGL(split_scale, dim3(1), dim3(1024), 0, st, (const double*)at<double>(ws, L.xc),
-                               p->n * p->d, (const double*)at<double>(ws, L.yc), p->m * p->d, scale);
+            auto* mbits = reinterpret_cast<unsigned long long*>(scale + 1);
+            const int64_t cnt = std::max(p->n, p->m) * p->d;
+            const int blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, cdiv(cnt, BLOCK)));
+            hipLaunchKernelGGL(split_scale_clear, dim3(1), dim3(1), 0, st, mbits);
+            hipLaunchKernelGGL(split_scale_max, dim3(blocks), dim3(BLOCK), 0, st, (const double*)at<double>(ws, L.xc),
+                               p->n * p->d, (const double*)at<double>(ws, L.yc), p->m * p->d, mbits);
+            hipLaunchKernelGGL(split_scale_final, dim3(1), dim3(1), 0, st, (const unsigned long long*)mbits, scale);
             hipLaunchKernelGGL(prep_operands_split, grid1(L.n_pad * L.KP), dim3(BLOCK), 0, st,
                                (const double*)at<double>(ws, L.xc), p->n, p->d, L.KP, L.n_pad, (const double*)scale,
                                0, at<_Float16>(ws, L.xop));

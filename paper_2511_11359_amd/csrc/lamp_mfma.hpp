@@ -97,20 +97,31 @@ __global__ void prep_operands_split(const double* __restrict__ src, int64_t cnt,
 // The range scale of the split FP16 operands: *scale = 2^(7 - e) with 2^e <= max |coordinate|
 // < 2^(e+1) over both centred clouds, so that every scaled coordinate is below 256 (its hi
 // part far from the FP16 limit, its lo part resolved to 2^-24 absolute or better); 1 if all
-// coordinates are zero.  One block, a max-reduction in any order (the maximum is exact).
-__global__ void split_scale(const double* __restrict__ xc, int64_t nx, const double* __restrict__ yc, int64_t ny,
-                            double* __restrict__ scale) {
-    __shared__ double sh[1024];
+// coordinates are zero.  Three launches: split_scale_clear zeroes the running maximum,
+// split_scale_max (any grid) folds each block's maximum into it with a 64-bit atomic max on
+// the bit pattern (non-negative doubles order as their bits do, so the result is the exact
+// maximum whatever the order), split_scale_final turns it into the scale.
+__global__ void split_scale_clear(unsigned long long* __restrict__ mbits) { *mbits = 0ull; }
+
+__global__ void split_scale_max(const double* __restrict__ xc, int64_t nx, const double* __restrict__ yc,
+                                int64_t ny, unsigned long long* __restrict__ mbits) {
+    __shared__ double sh[BLOCK / 64];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
     double mx = 0.0;
-    for (int64_t k = threadIdx.x; k < nx; k += blockDim.x) mx = fmax(mx, fabs(xc[k]));
-    for (int64_t k = threadIdx.x; k < ny; k += blockDim.x) mx = fmax(mx, fabs(yc[k]));
-    sh[threadIdx.x] = mx;
+    for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < nx; k += stride) mx = fmax(mx, fabs(xc[k]));
+    for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < ny; k += stride) mx = fmax(mx, fabs(yc[k]));
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
     __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLOCK / 64; ++w) mx = fmax(mx, sh[w]);
+        if (mx > 0.0) atomicMax(mbits, (unsigned long long)__double_as_longlong(mx));
     }
-    if (threadIdx.x == 0) *scale = sh[0] > 0.0 ? ldexp(1.0, 7 - ilogb(sh[0])) : 1.0;
+}
+
+__global__ void split_scale_final(const unsigned long long* __restrict__ mbits, double* __restrict__ scale) {
+    const double mx = __longlong_as_double((long long)*mbits);
+    *scale = mx > 0.0 ? ldexp(1.0, 7 - ilogb(mx)) : 1.0;
 }
 
 // Padded entries of the FP32 column tables (both parities): zero weight in every sum.
@@ -264,6 +275,27 @@ __device__ __forceinline__ void loads_done() {
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0); expcnt and lgkmcnt at their maxima (no wait)
 }
 
+// One tile step of the half-precision sweeps with the matrix chain of the next tile and the
+// vector work of the current one interleaved in issue order: the vector work is cut into
+// NS + 1 equal shares of ITEMS items (item(q) for each); share s is issued ahead of matrix
+// instruction s and runs while instruction s - 1 executes (the first one covers the LDS
+// latency of the operands, the last one the final instruction).  A scheduling barrier
+// after each share keeps the compiler from regrouping the two phases, which in-order
+// issue would then run one after the other.  d enters as the chain's initial value and
+// leaves as its result.  Used where the chain is long (NS >= 12): with 4 instructions
+// per tile the extra live registers cost more than the overlap gains.
+template <int NS, int ITEMS, typename Op, typename Item>
+__device__ __forceinline__ void mma_chain_interleaved(const typename Op::vec (&a)[NS],
+                                                      const typename Op::vec (&b)[NS], floatx16& d,
+                                                      Item&& item) {
+    unroll_for<0, NS + 1>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        unroll_for<s * ITEMS / (NS + 1), (s + 1) * ITEMS / (NS + 1)>([&](auto qc) { item(qc); });
+        if constexpr (s < NS) d = Op::mma(a[s], b[s], d);
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
 template <int N>
 __device__ __forceinline__ void pin(float (&v)[N]) {
 #pragma unroll
@@ -415,6 +447,7 @@ __global__ __launch_bounds__(BLOCK, (row_sweep_min_waves<T, KP>())) void row_swe
     using Op = MfmaOp<T>;
     using vec = typename Op::vec;
     constexpr int NS = KP / Op::KSTEP;
+    constexpr bool INTERLEAVE = sizeof(T) == 2 && NS >= 12;   // measured: +1.5% at NS = 12, -8% at NS = 4
     __shared__ __align__(16) char lds[2][L::BUF];
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
@@ -468,12 +501,28 @@ __global__ __launch_bounds__(BLOCK, (row_sweep_min_waves<T, KP>())) void row_swe
         for (int jt = jt0; jt < jt1; ++jt) {
             const int nxt = (jt + 1 - jt0) & 1;
             tile_fetch<T, KP, 8>(src, min(jt + 2, jl), pf);
-            const floatx16 dn = tile_dot<T, KP>(lds[nxt], c32, hf, a, hv);
-            const float2 gn = *reinterpret_cast<const float2*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
+            floatx16 dn;
+            float2 gn;
+            if constexpr (INTERLEAVE) {
+                vec bv[NS];
+                tile_operands<T, KP>(lds[nxt], c32, hf, bv);
+                dn = hv;
+                mma_chain_interleaved<NS, 32, Op>(a, bv, dn, [&](auto qc) {
+                    constexpr int q = decltype(qc)::value, r = q >> 1;
+                    if constexpr (q & 1)
+                        accB[r] += __builtin_amdgcn_exp2f(fmaf(dc[r], cB, gc.y));
+                    else
+                        accA[r] += __builtin_amdgcn_exp2f(fmaf(dc[r], cA, gc.x));
+                });
+                gn = *reinterpret_cast<const float2*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
+            } else {
+                dn = tile_dot<T, KP>(lds[nxt], c32, hf, a, hv);
+                gn = *reinterpret_cast<const float2*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                accA[r] += __builtin_amdgcn_exp2f(fmaf(dc[r], cA, gc.x));
-                accB[r] += __builtin_amdgcn_exp2f(fmaf(dc[r], cB, gc.y));
+                for (int r = 0; r < 16; ++r) {
+                    accA[r] += __builtin_amdgcn_exp2f(fmaf(dc[r], cA, gc.x));
+                    accB[r] += __builtin_amdgcn_exp2f(fmaf(dc[r], cB, gc.y));
+                }
             }
             pin(accA);
             pin(accB);
@@ -623,6 +672,7 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
         for (int s = 0; s < NS; ++s) a[s] = ap[s];
     }
     constexpr bool ONE_CHAIN = NS >= 4;
+    constexpr bool INTERLEAVE = sizeof(T) == 2 && NS >= 12;   // as in the row sweep
     const float2* __restrict__ g = gtabf + (t & 1) * m_pad;
     floatx16 GA, GB;
     float CA[16];   // g^A_j - c^A G^B_j (one-chain form)
@@ -675,15 +725,34 @@ __global__ __launch_bounds__(BLOCK) void col_sweep_mfma_t_lds(const Ctrl* ctrl, 
                 const int nxt = (it + 1 - it0) & 1;
                 tile_fetch<T, KP, 16>(src, min(it + 2, il), pf);
                 floatx16 dnA, dnB;
-                dots(lds[nxt], dnA, dnB);
-                const float4 qn = *reinterpret_cast<const float4*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
-                const float ckA = cA * qc.x, ckB = cB * qc.x;
+                float4 qn;
+                if constexpr (INTERLEAVE) {
+                    const float ckA = cA * qc.x, ckB = cB * qc.x;
+                    typename Op::vec bv[NS];
+                    tile_operands<T, KP>(lds[nxt], c32, hf, bv);
+                    dnB = GB;
+                    mma_chain_interleaved<NS, 32, Op>(a, bv, dnB, [&](auto qi) {
+                        constexpr int q = decltype(qi)::value, r = q >> 1;
+                        if constexpr (q & 1) {
+                            accB[r] = fmaf(qc.z, __builtin_amdgcn_exp2f(fmaf(dcB[r], cBd, ckB)), accB[r]);
+                        } else {
+                            const float eA = FACTOR ? fmaf(dcB[r], cAd, ckA) : fmaf(dcB[r], cAd, ckA) + CA[r];
+                            accA[r] = fmaf(qc.y, __builtin_amdgcn_exp2f(eA), accA[r]);
+                        }
+                    });
+                    dnA = dnB;
+                    qn = *reinterpret_cast<const float4*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
+                } else {
+                    dots(lds[nxt], dnA, dnB);
+                    qn = *reinterpret_cast<const float4*>(lds[nxt] + 32 * L::STRIDE + c32 * 16);
+                    const float ckA = cA * qc.x, ckB = cB * qc.x;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float eA = !ONE_CHAIN ? fmaf(dcA[r], cAd, ckA)
-                                                : (FACTOR ? fmaf(dcB[r], cAd, ckA) : fmaf(dcB[r], cAd, ckA) + CA[r]);
-                    accA[r] = fmaf(qc.y, __builtin_amdgcn_exp2f(eA), accA[r]);
-                    accB[r] = fmaf(qc.z, __builtin_amdgcn_exp2f(fmaf(dcB[r], cBd, ckB)), accB[r]);
+                    for (int r = 0; r < 16; ++r) {
+                        const float eA = !ONE_CHAIN ? fmaf(dcA[r], cAd, ckA)
+                                                    : (FACTOR ? fmaf(dcB[r], cAd, ckA) : fmaf(dcB[r], cAd, ckA) + CA[r]);
+                        accA[r] = fmaf(qc.y, __builtin_amdgcn_exp2f(eA), accA[r]);
+                        accB[r] = fmaf(qc.z, __builtin_amdgcn_exp2f(fmaf(dcB[r], cBd, ckB)), accB[r]);
+                    }
                 }
                 pin(accA);
                 pin(accB);
