@@ -1,7 +1,8 @@
 """Benchmark of the LAMP iteration on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision P]
-                    [--compare FORMS] [--time-to-tol FORMS] [--no-cpu] [--mode batch|grad]
+                    [--compare FORMS] [--time-to-tol FORMS] [--no-cpu] [--metric sqeuclid|l1|linf]
+                    [--track-dt] [--mode batch|grad|cost|peak]
 
 A step is one LAMP iteration t -> t+1 (Algorithm 2: both marginal sweeps of
 Section 4.1, the dual mirror steps, averaging, clipping and the residual) over
@@ -106,16 +107,17 @@ def cpu_baseline(wl, s, seconds_target: float = 12.0):
                                     "sample": f"{nrows} rows, oracle/stream.py row blocks, {dt_n:.1f} s"}}
 
 
-def measure_form(P, prob, wl, form, steps, warmup, reps):
-    """Throughput of `steps` iterations of one precision form, and its sweep kernel times."""
+def measure_form(P, prob, wl, form, steps, warmup, reps, track_dt=False):
+    """Throughput of `steps` iterations of one precision form, and its sweep kernel times.
+    track_dt: the iterations also accumulate the D_t summands (FP32 form)."""
     import torch
     dev = prob.device
     st = P.State.fresh(wl.m, dev)
     if warmup:
-        st, _, _ = P.solve(prob, P.make_params(eta=wl.eta, max_iter=warmup,
-                                               check_every=max(1, warmup // 2), precision=form), st)
+        st, _, _ = P.solve(prob, P.make_params(eta=wl.eta, max_iter=warmup, check_every=max(1, warmup // 2),
+                                               precision=form, track_dt=track_dt), st)
     params = P.make_params(eta=wl.eta, tol=0.0, max_iter=steps, check_every=max(1, steps // 2),
-                           precision=form)
+                           precision=form, track_dt=track_dt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, rep, _ = P.solve(prob, params, st)
@@ -123,8 +125,9 @@ def measure_form(P, prob, wl, form, steps, warmup, reps):
     dt = time.perf_counter() - t0
     assert rep["iters"] == steps, rep
     row_ms, col_ms = P.sweep_times(prob, params, st, reps=reps)
-    log(f"{form}: {steps} iterations in {dt:.3f} s ({dt * 1e3 / steps:.3f} ms/iteration), "
-        f"row sweep {row_ms:.3f} ms, column sweep {col_ms:.3f} ms, residual {rep['final_res']:.3e}")
+    log(f"{form}{' (D_t tracked)' if track_dt else ''}: {steps} iterations in {dt:.3f} s "
+        f"({dt * 1e3 / steps:.3f} ms/iteration), row sweep {row_ms:.3f} ms, column sweep {col_ms:.3f} ms, "
+        f"residual {rep['final_res']:.3e}")
     return {"pair_evals_per_s": 4.0 * wl.n * wl.m * steps / dt, "ms_per_step": dt * 1e3 / steps,
             "row_sweep_ms": row_ms, "col_sweep_ms": col_ms, "residual_after": rep["final_res"],
             "t_after": st.t}
@@ -187,10 +190,10 @@ def roofline(wl, form, m, probe=None):
     return out
 
 
-def fresh_problem(P, wl, dev):
+def fresh_problem(P, wl, dev, metric="sqeuclid"):
     """The workload's problem with the cost scale left to the solve (cost_scale = 0): a timed
-    solve then includes the device pass that computes max_ij ||x_i - y_j||^2."""
-    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, device=dev)
+    solve then includes the device pass that computes the largest ground cost."""
+    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, device=dev, metric=metric)
     return prob
 
 
@@ -312,6 +315,17 @@ def grad_mode(args):
     ach = pairs / (dev_ms * 1e-3)
     log(f"adjoint: {dt * 1e3:.3f} ms per gradient (device {dev_ms:.3f} ms, {ach:.3e} exp/s), "
         f"|g|_max {float(g.abs().max()):.3e}")
+    # the gradient with respect to y (column side)
+    P.backward_y(prob, params, st)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        gy = P.backward_y(prob, params, st)
+    ev1.record()
+    torch.cuda.synchronize()
+    dev_ms_y = ev0.elapsed_time(ev1) / reps
+    log(f"adjoint with respect to y: {dev_ms_y:.3f} ms per gradient (device, {pairs / (dev_ms_y * 1e-3):.3e} "
+        f"exp/s), |g|_max {float(gy.abs().max()):.3e}")
     # the autograd forward's value: <C, X^t> in one pass (lamp_transport_cost)
     cost = P.transport_cost(prob, params, st)
     torch.cuda.synchronize()
@@ -331,7 +345,8 @@ def grad_mode(args):
                         "achieved": ach / 1e12, "peak": EXP_PEAK / 1e12, "unit": "Texp/s",
                         "frac": ach / EXP_PEAK, "traffic": None,
                         "per_launch": f"n*m = {pairs:.3e} exponentials", "device_ms": dev_ms},
-           "forward_time_to_tol": fwd, "adjoint_ms": dt * 1e3, "transport_cost_ms": cost_ms}
+           "forward_time_to_tol": fwd, "adjoint_ms": dt * 1e3, "adjoint_y_ms": dev_ms_y,
+           "transport_cost_ms": cost_ms}
     print(json.dumps(out), flush=True)
 
 
@@ -426,6 +441,10 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", default="gmm64d_65536")
+    ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "l1", "linf"],
+                    help="ground cost generated from the points (l1 / linf: FP32 form only)")
+    ap.add_argument("--track-dt", action="store_true",
+                    help="also time the primary form with D_t tracking (FP32 form)")
     ap.add_argument("--precision", default="bf16_mfma",
                     choices=["fp32", "fp32_mfma", "bf16_mfma", "fp16_mfma", "fp16x3_mfma"])
     ap.add_argument("--compare", default="fp16x3_mfma,fp32_mfma,fp32",
@@ -468,12 +487,23 @@ def main():
     wl = W.WORKLOADS[args.workload]()
     dev = torch.device("cuda:0")
     calibration_copy(args.calib_copy_mib, dev)
-    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, device=dev)   # cost scale computed on the device
+    if args.metric != "sqeuclid":
+        if args.precision != "fp32":
+            print("bench.py: the l1 / linf costs run in the FP32 form only (--precision fp32)", file=sys.stderr)
+            sys.exit(2)
+        wl.name = f"{wl.name}_{args.metric}"
+    prob = P.Problem(wl.x, wl.y, wl.r, wl.c, device=dev, metric=args.metric)   # cost scale on the device
     s, _ = P.cost_scale(prob)
     prob.cost_scale, prob.cost_norm = s, 1.0
-    log(f"{wl.name}: n={wl.n} m={wl.m} d={wl.d} eta={wl.eta} s={s:.9e}")
+    log(f"{wl.name}: n={wl.n} m={wl.m} d={wl.d} eta={wl.eta} metric={args.metric} s={s:.9e}")
 
     main_m = measure_form(P, prob, wl, args.precision, args.steps, args.warmup, args.reps)
+    dt_track = None
+    if args.track_dt:
+        tr = measure_form(P, prob, wl, args.precision, args.steps, args.warmup, args.reps, track_dt=True)
+        dt_track = {"ms_per_step": tr["ms_per_step"], "overhead_ms": tr["ms_per_step"] - main_m["ms_per_step"]}
+        log(f"D_t tracking: {tr['ms_per_step']:.3f} ms per iteration, "
+            f"{dt_track['overhead_ms']:.3f} ms more than untracked")
     others = {}
     for form in [f for f in args.compare.split(",") if f and f != args.precision]:
         others[form] = measure_form(P, prob, wl, form, args.compare_steps, 2, max(2, args.reps // 2))
@@ -483,14 +513,14 @@ def main():
     if forms_ttt:
         ttt = {}
         for f in forms_ttt:
-            prob_f = fresh_problem(P, wl, dev)
+            prob_f = fresh_problem(P, wl, dev, args.metric)
             res, st_f = time_to_tol(P, prob_f, wl, f, args.tol, args.max_iter)
             if f != "fp32" and f in args.polish.split(","):
                 pol, _ = polish(P, prob_f, wl, st_f, args.tol, args.max_iter)
                 res["fp32_polish"] = pol
                 res["seconds_with_polish"] = res["seconds"] + pol["seconds"]
             ttt[f] = res
-    cpu = None if args.no_cpu else cpu_baseline(wl, s)
+    cpu = None if (args.no_cpu or args.metric != "sqeuclid") else cpu_baseline(wl, s)   # C pass: squared Euclidean
     probe = P.exp_rate(dev)
     log(f"exponential probe: {probe:.4e} exp/s ({probe / EXP_PEAK:.3f} of the derived {EXP_PEAK:.4e})")
 
@@ -507,13 +537,15 @@ def main():
         "vs_baseline": None,
         "dtype": FORM_DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": wl.n, "m": wl.m, "d": wl.d, "eta": wl.eta,
+        "config": {"workload": wl.name, "n": wl.n, "m": wl.m, "d": wl.d, "eta": wl.eta, "metric": args.metric,
                    "form": args.precision, "precision": FORM_DESC[args.precision]},
         "roofline": roofline(wl, args.precision, main_m, probe),
         "cpu_baseline": cpu,
         "forms": others,
         "time_to_tol": ttt,
     }
+    if dt_track is not None:
+        out["dt_tracking"] = dt_track
     print(json.dumps(out), flush=True)
 
 

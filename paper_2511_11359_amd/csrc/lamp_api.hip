@@ -957,12 +957,44 @@ void launch_dt_cost(const lamp_problem* p, const Layout& L, Consts kc, void* ws,
     hipLaunchKernelGGL(dt_cost_total, dim3(1), dim3(1024), 0, st, ctrl, (const double*)out, kc.n);
 }
 
+// The row sweep of a D_t-tracked iteration with <C, Xbar^{t+1}> fused into it (vector-ALU
+// sweeps of a templated dimension): row_sweep_dt, then dt_rows_finish and dt_cost_total.  The
+// cost partials sit behind the sweep's [P_r][n] double2 partials in the row partial buffer
+// (sized for 4 P_r n doubles).  Returns false, launching nothing, for the other sweeps.
+bool launch_row_sweep_dt(const lamp_problem* p, const Layout& L, Consts kc, void* ws, hipStream_t st) {
+    if (L.cost || is_mfma(L.prec) || L.use64) return false;
+    const dim3 g(sweep_grid(kc.n, L.P_r));
+    Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+    const Sched* sch = at<Sched>(ws, L.sched);
+    const double* xc = at<double>(ws, L.xc);
+    const double* yc = at<double>(ws, L.yc);
+    const double* xn2 = at<double>(ws, L.xn2);
+    const double* yn2 = at<double>(ws, L.yn2);
+    const double2* gt = at<double2>(ws, L.gtab);
+    const double* H = at<double>(ws, L.H);
+    double2* part = at<double2>(ws, L.rpart);
+    double* tpart = at<double>(ws, L.rpart) + 2 * L.P_r * kc.n;
+    double* out = at<double>(ws, L.dtrow);
+    return by_metric(kc.metric, [&](auto m) {
+        return valu_dispatch<decltype(m)::value>(p->d, [&](auto dd) {
+            constexpr int M = decltype(m)::value, D = decltype(dd)::value;
+            hipLaunchKernelGGL((row_sweep_dt<M, D>), g, dim3(BLOCK), 0, st, ctrl, sch, kc, xc, yc, gt, H, part,
+                               L.split_r, xn2, yn2, tpart);
+            hipLaunchKernelGGL((dt_rows_finish<M, D>), grid1(kc.n), dim3(BLOCK), 0, st, ctrl, sch, kc, xc, yc, xn2,
+                               yn2, gt, p->r, (const double2*)part, (const double*)tpart, (int)L.P_r, out);
+            hipLaunchKernelGGL(dt_cost_total, dim3(1), dim3(1024), 0, st, ctrl, (const double*)out, kc.n);
+        });
+    });
+}
+
 void launch_iteration(const lamp_problem* p, const Layout& L, Consts kc, void* ws, const IterArgs& ia,
                       hipStream_t st) {
     Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
     const Sched* sch = at<Sched>(ws, L.sched);
-    launch_row_sweep(L, kc, p->d, ws, st);
-    if (ia.track_dt) launch_dt_cost(p, L, kc, ws, st);
+    if (!(ia.track_dt && launch_row_sweep_dt(p, L, kc, ws, st))) {
+        launch_row_sweep(L, kc, p->d, ws, st);
+        if (ia.track_dt) launch_dt_cost(p, L, kc, ws, st);
+    }
     RowVarF32 rf{nullptr, 0};
     if (is_mfma(L.prec)) rf = rowvar_f32(L, ws);
     hipLaunchKernelGGL(row_finish, grid1(kc.n), dim3(BLOCK), 0, st, ctrl, sch, kc, p->d, at<double>(ws, L.xc),

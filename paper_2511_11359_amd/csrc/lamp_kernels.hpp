@@ -397,13 +397,33 @@ __device__ __forceinline__ void row_terms(const double (&x)[D], double h, const 
     pB = fexp2(fma_su(dot, cB, g.y));
 }
 
+// The same with the cost term of the B coupling for D_t tracking: tB = 2^eB C_ij / s, with
+// C_ij / s = |x~_i|^2 + |y~_j|^2 - 2 P_ij taken from the exponent's dot product
+// dot = h + P_ij as (|x~_i|^2 + 2 h + |y~_j|^2) - 2 dot (xa = |x~_i|^2 + 2 h; the norms are
+// zero for l1 / l_inf, where P_ij = -dist / 2): two FP64 operations, a conversion and an FMA.
 template <int M, int D>
+__device__ __forceinline__ void row_terms_dt(const double (&x)[D], double h, double xa, const double* __restrict__ yj,
+                                             double yn2j, double2 g, double cA, double cB, float& pA, float& pB,
+                                             float& tB) {
+    const double dot = pair_term<M, D>(x, yj, h);
+    pA = fexp2(fma_su(dot, cA, g.x));
+    pB = fexp2(fma_su(dot, cB, g.y));
+    const double cs = fma(-2.0, dot, M == METRIC_SQEUCLID ? xa + yn2j : xa);
+    tB = pB * (float)cs;
+}
+
+// Row sweep body; with DT the sweep also sums the B coupling's cost terms for D_t tracking
+// (tpart[p][i], under the same row offset as the B sums, so the splits add up directly).
+template <int M, int D, bool DT = false>
 __device__ __forceinline__ void row_sweep_body(const Ctrl* ctrl, const Sched* sched, Consts kc,
                                                    const double* __restrict__ xc,
                                                    const double* __restrict__ yc,
                                                    const double2* __restrict__ gtab2,
                                                    const double* __restrict__ H,
-                                                   double2* __restrict__ part, int64_t split, int64_t bx_, int64_t by_, int64_t nb_) {
+                                                   double2* __restrict__ part, int64_t split, int64_t bx_, int64_t by_, int64_t nb_,
+                                                   const double* __restrict__ xn2 = nullptr,
+                                                   const double* __restrict__ yn2 = nullptr,
+                                                   double* __restrict__ tpart = nullptr) {
     if (halted(ctrl)) return;
     const int64_t t = ctrl->t;
     const Sched sc = sched[t - ctrl->t_base];
@@ -421,14 +441,25 @@ __device__ __forceinline__ void row_sweep_body(const Ctrl* ctrl, const Sched* sc
     for (int k = 0; k < D; ++k) x[k] = xc[ii * D + k];
     const double h = H[ii];
 
-    double sumA = 0.0, sumB = 0.0;
+    double sumA = 0.0, sumB = 0.0, sumT = 0.0;
+    double xa = 0.0;
+    if constexpr (DT) xa = (M == METRIC_SQEUCLID ? xn2[ii] : 0.0) + 2.0 * h;
     const int nfull = (int)((j1 - j0) / UNROLL);
     const double* __restrict__ yp = yc + j0 * D;
     const double2* __restrict__ gp = g + j0;
+    const double* __restrict__ np = DT ? yn2 + j0 : nullptr;
     for (int c = 0; c < nfull; ++c, yp += UNROLL * D, gp += UNROLL) {
-        float pA[UNROLL], pB[UNROLL];
+        float pA[UNROLL], pB[UNROLL], tB[UNROLL];
+        if constexpr (DT) {
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) row_terms<M, D>(x, h, yp + u * D, gp[u], cA, cB, pA[u], pB[u]);
+            for (int u = 0; u < UNROLL; ++u)
+                row_terms_dt<M, D>(x, h, xa, yp + u * D, M == METRIC_SQEUCLID ? np[u] : 0.0, gp[u], cA, cB, pA[u],
+                                   pB[u], tB[u]);
+            np += UNROLL;
+        } else {
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) row_terms<M, D>(x, h, yp + u * D, gp[u], cA, cB, pA[u], pB[u]);
+        }
         float accA = pA[0], accB = pB[0];
 #pragma unroll
         for (int u = 1; u < UNROLL; ++u) {
@@ -437,20 +468,37 @@ __device__ __forceinline__ void row_sweep_body(const Ctrl* ctrl, const Sched* sc
         }
         sumA += (double)accA;
         sumB += (double)accB;
+        if constexpr (DT) {
+            float accT = tB[0];
+#pragma unroll
+            for (int u = 1; u < UNROLL; ++u) accT += tB[u];
+            sumT += (double)accT;
+        }
     }
     {
         const int rem = (int)((j1 - j0) - (int64_t)nfull * UNROLL);
-        float accA = 0.f, accB = 0.f;
+        float accA = 0.f, accB = 0.f, accT = 0.f;
         for (int u = 0; u < rem; ++u) {
             float a, b;
-            row_terms<M, D>(x, h, yp + u * D, gp[u], cA, cB, a, b);
+            if constexpr (DT) {
+                float tb;
+                row_terms_dt<M, D>(x, h, xa, yp + u * D, M == METRIC_SQEUCLID ? np[u] : 0.0, gp[u], cA, cB, a, b,
+                                   tb);
+                accT += tb;
+            } else {
+                row_terms<M, D>(x, h, yp + u * D, gp[u], cA, cB, a, b);
+            }
             accA += a;
             accB += b;
         }
         sumA += (double)accA;
         sumB += (double)accB;
+        sumT += (double)accT;
     }
-    if (i < kc.n) part[p * kc.n + i] = make_double2(sumA, sumB);
+    if (i < kc.n) {
+        part[p * kc.n + i] = make_double2(sumA, sumB);
+        if constexpr (DT) tpart[p * kc.n + i] = sumT;
+    }
 }
 
 template <int M, int D>
@@ -462,6 +510,22 @@ __global__ __launch_bounds__(BLOCK) void row_sweep(const Ctrl* ctrl, const Sched
                                                    double2* __restrict__ part, int64_t split) {
     const SweepBlock sb = sweep_block(kc.m, split);
     row_sweep_body<M, D>(ctrl, sched, kc, xc, yc, gtab2, H, part, split, sb.bx, sb.p, 0);
+}
+
+// The row sweep of a D_t-tracked iteration: the row sweep above plus the B coupling's cost
+// sums, tpart: [P][n].
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void row_sweep_dt(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                      const double* __restrict__ xc,
+                                                      const double* __restrict__ yc,
+                                                      const double2* __restrict__ gtab2,
+                                                      const double* __restrict__ H,
+                                                      double2* __restrict__ part, int64_t split,
+                                                      const double* __restrict__ xn2,
+                                                      const double* __restrict__ yn2,
+                                                      double* __restrict__ tpart) {
+    const SweepBlock sb = sweep_block(kc.m, split);
+    row_sweep_body<M, D, true>(ctrl, sched, kc, xc, yc, gtab2, H, part, split, sb.bx, sb.p, 0, xn2, yn2, tpart);
 }
 
 __device__ __forceinline__ void row_sweep_dyn_body(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
@@ -830,6 +894,48 @@ __global__ __launch_bounds__(BLOCK) void dt_cost_rows_dyn(const Ctrl* ctrl, cons
         T += (double)aT;
     }
     if (i < kc.n) out[i] = r[i] * T / S;
+}
+
+// Row i's share of <C, Xbar^{t+1}> from the D_t-tracked row sweep's splits: s r_i T_i / S^B_i
+// (both sums under the row's offset h_i, so the splits add directly).  A row whose S^B leaves
+// [2^-60, 2^60] -- the rows whose normalisers row_finish recomputes -- is evaluated again in
+// FP64 under its exact largest exponent.
+template <int M, int D>
+__global__ void dt_rows_finish(const Ctrl* ctrl, const Sched* sched, Consts kc, const double* __restrict__ xc,
+                               const double* __restrict__ yc, const double* __restrict__ xn2,
+                               const double* __restrict__ yn2, const double2* __restrict__ gtab2,
+                               const double* __restrict__ r, const double2* __restrict__ part,
+                               const double* __restrict__ tpart, int P, double* __restrict__ out) {
+    if (halted(ctrl)) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    double SB = 0.0, T = 0.0;
+    for (int p = 0; p < P; ++p) {
+        SB += part[(int64_t)p * kc.n + i].y;
+        T += tpart[(int64_t)p * kc.n + i];
+    }
+    if (SB >= 0x1p-60 && SB <= 0x1p+60) {
+        out[i] = kc.s * r[i] * (T / SB);
+        return;
+    }
+    const int64_t t = ctrl->t;
+    const Sched sc = sched[t - ctrl->t_base];
+    const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
+    const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
+    double x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = xc[i * D + k];
+    double emax = -__builtin_inf();
+    for (int64_t j = 0; j < kc.m; ++j) emax = fmax(emax, fma(cB, pair_term<M, D>(x, yc + j * D, 0.0), g[j].y));
+    const double xa = M == METRIC_SQEUCLID ? xn2[i] : 0.0;
+    double S = 0.0, Tx = 0.0;
+    for (int64_t j = 0; j < kc.m; ++j) {
+        const double dot = pair_term<M, D>(x, yc + j * D, 0.0);
+        const double q = exp2(fma(cB, dot, g[j].y) - emax);
+        S += q;
+        Tx += q * fma(-2.0, dot, M == METRIC_SQEUCLID ? xa + yn2[j] : xa);
+    }
+    out[i] = kc.s * r[i] * (Tx / S);
 }
 
 // ctrl->dt_cost = sum_i out_i, one block, fixed order (deterministic).

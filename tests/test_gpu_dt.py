@@ -61,9 +61,9 @@ def _problem(n, m, d, kind, seed, eta=1e-2):
                                               ((1, 9, 2), "sqeuclid", [0, 3])])
 def test_dt_summand_of_one_step_matches_oracle(shape, kind, steps):
     """One GPU step from the oracle's FP64 state at s, dt_partial starting at 0: the increment is
-    the summand of D_{s+1} without its normaliser telescope.  Covers the templated and generic-d
-    cost passes (d = 20 runs the row sweep on FP64 matrix cores), each ground cost and a single
-    row."""
+    the summand of D_{s+1} without its normaliser telescope.  Covers the D_t sums fused into the
+    vector-ALU row sweep (d = 2, 3), the separate cost pass beside the FP64 matrix-core sweeps
+    (d = 20), each ground cost and a single row."""
     n, m, d = shape
     wl, C, prob = _problem(n, m, d, kind, seed=300 + n)
     _say("case", wl.name, kind)
@@ -105,6 +105,31 @@ def test_dt_along_a_solve_and_midpoint_bound(kind, eta):
          f"bound gpu {cert['midpoint_bound']:.6e} oracle {ref_bound:.6e}")
     assert abs(cert["dt"] - D[-1]) <= tol
     assert abs(cert["midpoint_bound"] - ref_bound) <= 2.0 * tol / T + 1e-12
+
+
+def test_dt_summands_at_recomputed_rows():
+    """tau1 = 100 at eta = 0 (lam grows by 100 per iteration): in a two-iteration solve from an
+    oracle state the second iteration's row offsets, taken from the first, leave rows outside
+    [2^-60, 2^60]; row_finish recomputes their normalisers exactly (row_fallbacks > 0) and the
+    D_t pass of the tracked row sweep evaluates their <C, Xbar> share again in FP64.  The two
+    summands (without the normaliser telescope) against the oracle's."""
+    wl, C, prob = _problem(64, 80, 2, "sqeuclid", seed=71, eta=0.0)
+    prm = OL.Params(eta=0.0, tau1=100.0)
+    k = 5
+    T = k + 2
+    D, _, traces = OL.dt_sequence(C, wl.r, wl.c, prm, T, 1.0)
+    lam = OL.inv_eta_schedule(T, 100.0, 0.0)
+    nu, th, nu_n = traces[k - 1].nu[0], traces[k - 1].theta[0], traces[k + 1].nu[0]
+    telescope = float(wl.r @ (OL.log_normaliser(C, nu_n, lam[k + 2], 1.0) - OL.log_normaliser(C, nu, lam[k], 1.0)))
+    ref = (D[k + 1] - D[k - 1]) - telescope
+    st = P.State(torch.tensor(nu, device="cuda"), torch.tensor(th, device="cuda"), k, float(lam[k]), 0.0)
+    params = P.make_params(eta=0.0, tau1=100.0, max_iter=2, check_every=2, track_dt=True)
+    st, rep, status = P.solve(prob, params, st)
+    err = abs(st.dt_partial - ref)
+    _say(f"tau1 = 100: fallbacks {rep['row_fallbacks']}, gpu {st.dt_partial:.9e} oracle {ref:.9e} err {err:.2e}")
+    assert status == 0 and st.t == k + 2
+    assert rep["row_fallbacks"] > 0
+    assert err <= 2.0 * DT_STEP_TOL * max(1.0, abs(ref))
 
 
 def test_dt_resume_untracked_and_rejected_forms():
