@@ -237,9 +237,11 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
     L.dtpart = take(sizeof(double) * cdiv(m, BLOCK));
     // certificate: 4 arrays of max(n, m), Round: 9 more, the row values (4) and minima (2),
     // and d + 2 column sums
-    // (the adjoint: g^A and one record of 12 d + 8 bytes per column, 16-byte aligned)
-    L.scratch = take(std::max(sizeof(double) * (19 * std::max(n, m) + d + 2),
-                              align256(sizeof(double) * m) + (size_t)m * (size_t)((12 * d + 8 + 15) / 16 * 16)));
+    // (the adjoint: g^A and one record of 12 d + 8 bytes per column, 16-byte aligned; the
+    // adjoint with respect to y: g^A and one record of 12 d + 12 bytes per row)
+    L.scratch = take(std::max({sizeof(double) * (19 * std::max(n, m) + d + 2),
+                               align256(sizeof(double) * m) + (size_t)m * (size_t)((12 * d + 8 + 15) / 16 * 16),
+                               align256(sizeof(double) * m) + (size_t)n * (size_t)((12 * d + 12 + 15) / 16 * 16)}));
     L.small = take(sizeof(double) * 64);
     if (is_mfma(prec)) {
         L.xop = take((size_t)L.esize * L.n_pad * L.KP);
@@ -1941,23 +1943,47 @@ lamp_status lamp_backward_y(const lamp_problem* prob, const lamp_params* params,
     if ((e = common_setup(prob, params, ws, ws_bytes, st, &R)) != LAMP_OK) return e;
     const Layout L = layout(prob->n, prob->m, prob->d, params->precision, TARGET_BLOCKS, prob->metric);
     const Consts kc = make_consts(prob, R);
-    double cA = 0.0;
-    // row offsets k_i and weights w_i = r_i of X^t (both halves of the set-up are p^{eta_t}(nu^t))
-    if ((e = state_normalisers(prob, params, R, state, ws, st, &cA)) != LAMP_OK) return e;
+    const int d = prob->d;
+    // row offsets k_i and weights w_i = r_i of X^t: one pass of row sums under per-lane integer
+    // offsets (templated dimensions), else the normaliser set-up of the certificate
+    const double cA = 2.0 * R.s * state->inv_eta * LOG2E;
     double* gA = at<double>(ws, L.scratch);
-    hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
-                       at<double2>(ws, L.gtab), gA);
+    hipLaunchKernelGGL(state_col_term, grid1(kc.m), dim3(BLOCK), 0, st, kc, state->inv_eta, at<double>(ws, L.yn2),
+                       state->nu, gA);
+    const bool one_pass = by_metric(kc.metric, [&](auto m) {
+        return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
+            constexpr int D = decltype(dd)::value;
+            // the column records follow gA in the scratch region (sized for them in layout())
+            auto* cols = reinterpret_cast<CostCol<D>*>(at<char>(ws, L.scratch) + align256(sizeof(double) * kc.m));
+            hipLaunchKernelGGL((cost_pack<D>), grid1(kc.m), dim3(BLOCK), 0, st, kc.m, at<double>(ws, L.yc),
+                               at<double>(ws, L.yn2), (const double*)gA, cols);
+            hipLaunchKernelGGL((norm_sweep<decltype(m)::value, D>), dim3(sweep_grid(kc.n, L.P_r)), dim3(BLOCK), 0,
+                               st, kc, cA, at<double>(ws, L.xc), (const CostCol<D>*)cols, at<double>(ws, L.rpart),
+                               L.split_r);
+            hipLaunchKernelGGL(norm_finish, grid1(kc.n), dim3(BLOCK), 0, st, kc, (int)L.P_r, cA, prob->r,
+                               (const double*)at<double>(ws, L.rpart), at<RowVar>(ws, L.rowvar));
+        });
+    });
+    if (!one_pass) {
+        double cA2 = 0.0;
+        if ((e = state_normalisers(prob, params, R, state, ws, st, &cA2)) != LAMP_OK) return e;
+        hipLaunchKernelGGL(gA_extract, grid1(kc.m), dim3(BLOCK), 0, st, kc.m, (int64_t)(state->t & 1),
+                           at<double2>(ws, L.gtab), gA);
+    }
     const dim3 g(sweep_grid(kc.m, L.P_c));
     double* part = at<double>(ws, L.cpart);
     const double* xc = at<double>(ws, L.xc);
     const float* xcf = at<float>(ws, L.xcf);
     const double* yc = at<double>(ws, L.yc);
     const RowVar* rv = at<RowVar>(ws, L.rowvar);
-    const int d = prob->d;
     const bool done = by_metric(kc.metric, [&](auto m) {
         return valu_dispatch<decltype(m)::value>(d, [&](auto dd) {
-            hipLaunchKernelGGL((adjoint_y_sweep<decltype(m)::value, decltype(dd)::value>), g, dim3(BLOCK), 0, st,
-                               kc, cA, xc, xcf, yc, gA, rv, part, L.split_c);
+            constexpr int D = decltype(dd)::value;
+            // the row records follow gA in the scratch region, over the norm pass's column records
+            auto* rows = reinterpret_cast<AdjRow<D>*>(at<char>(ws, L.scratch) + align256(sizeof(double) * kc.m));
+            hipLaunchKernelGGL((adjoint_y_pack<D>), grid1(kc.n), dim3(BLOCK), 0, st, kc.n, cA, xc, xcf, rv, rows);
+            hipLaunchKernelGGL((adjoint_y_sweep<decltype(m)::value, D>), g, dim3(BLOCK), 0, st, kc, cA,
+                               (const AdjRow<D>*)rows, yc, (const double*)gA, part, L.split_c);
         });
     });
     if (!done)

@@ -1627,6 +1627,18 @@ struct CostSums {
     }
 };
 
+// The row sums alone (Z): X^t's row normalisers in one pass, for the adjoint with respect to
+// y, whose column pass weights each row by r_i / Z_i.
+template <int D>
+struct NormSums {
+    using Col = CostCol<D>;
+    static constexpr int W = 1;
+    __device__ __forceinline__ void block(double) {}
+    __device__ __forceinline__ void add(const double (&)[D], const Col&, double, float q, float (&s)[W]) const {
+        s[0] += q;
+    }
+};
+
 template <int D>
 __global__ void adjoint_pack(int64_t m, const double* __restrict__ yc, const float* __restrict__ ycf,
                              const double* __restrict__ gA, AdjCol<D>* __restrict__ out) {
@@ -1769,6 +1781,34 @@ __global__ __launch_bounds__(BLOCK) void cost_sweep(Consts kc, double cA, const 
     weighted_row_sums<M, D>(kc, cA, xc, cols, pol, part, split);
 }
 
+// part: [P][n][2] = (M, Z).
+template <int M, int D>
+__global__ __launch_bounds__(BLOCK) void norm_sweep(Consts kc, double cA, const double* __restrict__ xc,
+                                                    const CostCol<D>* __restrict__ cols,
+                                                    double* __restrict__ part, int64_t split) {
+    weighted_row_sums<M, D>(kc, cA, xc, cols, NormSums<D>{}, part, split);
+}
+
+// X^t's row data for the column-side adjoint from the splits' (M, Z) at their common offset:
+// sigma_i = M + log2 Z (base 2), k_i = -sigma_i / cfac, so that
+// X_ij = r_i 2^(cfac (k_i + P_ij) + g_j); wA = wB = r_i.
+__global__ void norm_finish(Consts kc, int P, double cA, const double* __restrict__ r,
+                            const double* __restrict__ part, RowVar* __restrict__ rowvar) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    double off = -__builtin_inf();
+    for (int p = 0; p < P; ++p) off = fmax(off, part[((int64_t)p * kc.n + i) * 2]);
+    double z = 0.0;
+    for (int p = 0; p < P; ++p) {
+        const double* o = part + ((int64_t)p * kc.n + i) * 2;
+        if (o[0] > -__builtin_inf()) z += ldexp(o[1], (int)(o[0] - off));
+    }
+    RowVar rv;
+    rv.k = -(off + log2(z)) / cA;
+    rv.wA = rv.wB = (float)r[i];
+    rowvar[i] = rv;
+}
+
 // The transport cost for any dimension and metric at run time, FP64 sums.  part as above.
 __global__ __launch_bounds__(BLOCK) void cost_sweep_dyn(Consts kc, int D, double cA,
                                                         const double* __restrict__ xc,
@@ -1882,12 +1922,37 @@ __global__ __launch_bounds__(BLOCK) void adjoint_sweep_dyn(Consts kc, int D, dou
 //   l_inf: the same on the coordinate of the largest |x_k - y_k| (first on ties).
 // part: [P][m][D+1] partial sums over row splits.
 // ---------------------------------------------------------------------------
+// One row's data for the column-side adjoint: x~_i in FP64 (dot product), the row's exponent
+// term cfac k_i, x~_i in FP32 (S1) and the weight w_i, read with a few wide scalar loads.
+template <int D>
+struct alignas(16) AdjRow {
+    double x[D];
+    double ck;
+    float xf[D];
+    float w;
+};
+
+template <int D>
+__global__ void adjoint_y_pack(int64_t n, double cA, const double* __restrict__ xc, const float* __restrict__ xcf,
+                               const RowVar* __restrict__ rowvar, AdjRow<D>* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    AdjRow<D> a;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        a.x[k] = xc[i * D + k];
+        a.xf[k] = xcf[i * D + k];
+    }
+    const RowVar rv = rowvar[i];
+    a.ck = cA * rv.k;
+    a.w = rv.wA;
+    out[i] = a;
+}
+
 template <int M, int D>
-__global__ __launch_bounds__(BLOCK) void adjoint_y_sweep(Consts kc, double cA, const double* __restrict__ xc,
-                                                         const float* __restrict__ xcf,
+__global__ __launch_bounds__(BLOCK) void adjoint_y_sweep(Consts kc, double cA, const AdjRow<D>* __restrict__ rows,
                                                          const double* __restrict__ yc,
                                                          const double* __restrict__ gA,
-                                                         const RowVar* __restrict__ rowvar,
                                                          double* __restrict__ part, int64_t split) {
     const SweepBlock sb = sweep_block(kc.n, split);
     const int64_t j = sb.bx * BLOCK + threadIdx.x;
@@ -1898,19 +1963,21 @@ __global__ __launch_bounds__(BLOCK) void adjoint_y_sweep(Consts kc, double cA, c
     double y[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) y[k] = yc[jj * D + k];
-    const double g = gA[jj];
+    // e_ij = cfac (G_j + P_ij) + cfac k_i with G_j = g_j / cfac: the dot product starts from
+    // the lane's term and the row's term enters as the scalar addend of the exponent FMA
+    const double G = gA[jj] / cA;
     double s0 = 0.0, s1[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) s1[k] = 0.0;
     auto term = [&](int64_t i, float& a0, float (&a1)[D]) {
-        const RowVar rv = rowvar[i];
-        const double* xi = xc + i * D;
-        const double dot = pair_term<M, D>(y, xi, rv.k);   // P is symmetric
-        const float xij = rv.wA * fexp2(fma(cA, dot, g));
+        const AdjRow<D>& rw = rows[i];
+        const double* xi = rw.x;
+        const double dot = pair_term<M, D>(y, xi, G);   // P is symmetric
+        const float xij = rw.w * fexp2(fma_su(dot, cA, rw.ck));
         if constexpr (M == METRIC_SQEUCLID) {
             a0 += xij;
 #pragma unroll
-            for (int k = 0; k < D; ++k) a1[k] = fmaf(xij, xcf[i * D + k], a1[k]);
+            for (int k = 0; k < D; ++k) a1[k] = fmaf(xij, rw.xf[k], a1[k]);
         } else if constexpr (M == METRIC_L1) {
 #pragma unroll
             for (int k = 0; k < D; ++k) a1[k] = fmaf(0.5f * xij, sgnf(xi[k] - y[k]), a1[k]);

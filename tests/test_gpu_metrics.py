@@ -142,6 +142,21 @@ def test_backward_y_matches_oracle_gradient(kind, d):
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("kind,d,n,m", [("sqeuclid", 3, 3000, 2200), ("l1", 2, 1800, 2600)])
+def test_backward_y_across_splits(kind, d, n, m):
+    """The y-adjoint where both of its passes run many splits with ragged last splits (the row
+    sums over 18-24 column splits, the column pass over row splits), against the oracle's
+    gradient at the state after 40 iterations."""
+    wl, x, y, s, C, prob = _problem(n, m, d, kind, seed=91 + d)
+    params = P.make_params(eta=wl.eta, tol=0.0, max_iter=40)
+    st, _, _ = P.solve(prob, params)
+    g = to_np(P.backward_y(prob, params, st, grad_out=1.0))
+    g_or = OL.envelope_grad_y(x, y, wl.r, s, to_np(st.nu), st.inv_eta, 1.0, kind)
+    err = rel_inf(g, g_or)
+    _say(kind, d, n, m, "y-gradient rel err", err)
+    assert err <= 1e-5
+
+
 def test_autograd_gradients_wrt_both_clouds():
     """LampOT returns the x and y envelope gradients through the two adjoint entry points."""
     wl, x, y, s, C, prob = _problem(70, 60, 2, "sqeuclid", seed=71)
