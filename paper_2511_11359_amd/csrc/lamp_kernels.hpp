@@ -614,6 +614,7 @@ __device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, 
     const double cA = 2.0 * kc.s * sc.lamA * LOG2E;
     const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
     double SA = 0.0, SB = 0.0;
+#pragma unroll 8   // independent loads in flight; the sum order is unchanged
     for (int p = 0; p < P; ++p) {
         double2 v = part[(int64_t)p * kc.n + i];
         SA += v.x;
@@ -910,6 +911,7 @@ __global__ void dt_rows_finish(const Ctrl* ctrl, const Sched* sched, Consts kc, 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     double SB = 0.0, T = 0.0;
+#pragma unroll 8   // independent loads in flight; the sum order is unchanged
     for (int p = 0; p < P; ++p) {
         SB += part[(int64_t)p * kc.n + i].y;
         T += tpart[(int64_t)p * kc.n + i];
@@ -996,6 +998,7 @@ __device__ __forceinline__ void dual_update_body(Ctrl* ctrl, const Sched* sched,
     int bad = 0;
     if (j < kc.m) {
         double colA = 0.0, colB = 0.0;
+#pragma unroll 8   // independent loads in flight; the sum order is unchanged
         for (int p = 0; p < P; ++p) {
             double2 v = cpart[(int64_t)p * kc.m + j];
             colA += v.x;
