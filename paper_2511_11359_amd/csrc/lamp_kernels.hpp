@@ -365,6 +365,7 @@ __device__ __forceinline__ void row_extreme_merge_body(Consts kc, const double* 
     int64_t i = (int64_t)bx_ * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     double best = part[i];
+#pragma unroll 8
     for (int p = 1; p < P; ++p) best = fmin(best, part[(int64_t)p * kc.n + i]);
     out[i] = (mode == 0) ? best : xn2[i] - 2.0 * best;
 }
@@ -1280,6 +1281,7 @@ __global__ void cert_rows_merge(Consts kc, int P, const double* __restrict__ r, 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     double psum = 0.0, csum = 0.0, mth = __builtin_inf(), mnu = __builtin_inf();
+#pragma unroll 8
     for (int p = 0; p < P; ++p) {
         const double* o = part + ((int64_t)p * kc.n + i) * 4;
         psum += o[0];
@@ -1346,6 +1348,7 @@ __global__ void cert_soft_merge(Consts kc, int P, double lam, const double* __re
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     double sth = 0.0, snu = 0.0;
+#pragma unroll 8
     for (int p = 0; p < P; ++p) {
         sth += part[((int64_t)p * kc.n + i) * 2];
         snu += part[((int64_t)p * kc.n + i) * 2 + 1];
@@ -1464,6 +1467,7 @@ __global__ void round_rows_merge(Consts kc, int P, const double* __restrict__ r,
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     double ps = 0.0, pq = 0.0, cs = 0.0;
+#pragma unroll 8
     for (int p = 0; p < P; ++p) {
         const double* o = part + ((int64_t)p * kc.n + i) * 3;
         ps += o[0];
@@ -1800,8 +1804,10 @@ __global__ void norm_finish(Consts kc, int P, double cA, const double* __restric
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     double off = -__builtin_inf();
+#pragma unroll 8
     for (int p = 0; p < P; ++p) off = fmax(off, part[((int64_t)p * kc.n + i) * 2]);
     double z = 0.0;
+#pragma unroll 8
     for (int p = 0; p < P; ++p) {
         const double* o = part + ((int64_t)p * kc.n + i) * 2;
         if (o[0] > -__builtin_inf()) z += ldexp(o[1], (int)(o[0] - off));
@@ -1855,8 +1861,10 @@ __global__ void cost_finish(Consts kc, int P, const double* __restrict__ r, cons
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kc.n) return;
     double off = -__builtin_inf();
+#pragma unroll 8
     for (int p = 0; p < P; ++p) off = fmax(off, part[((int64_t)p * kc.n + i) * 3]);
     double z = 0.0, c = 0.0;
+#pragma unroll 8
     for (int p = 0; p < P; ++p) {
         const double* o = part + ((int64_t)p * kc.n + i) * 3;
         if (o[0] > -__builtin_inf()) {
@@ -2075,9 +2083,11 @@ __global__ void adjoint_y_finish(Consts kc, int D, int P, double scale, const do
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= kc.m) return;
     double s0 = 0.0;
+#pragma unroll 8
     for (int p = 0; p < P; ++p) s0 += part[((int64_t)p * kc.m + j) * (D + 1)];
     for (int k = 0; k < D; ++k) {
         double s1 = 0.0;
+#pragma unroll 8
         for (int p = 0; p < P; ++p) s1 += part[((int64_t)p * kc.m + j) * (D + 1) + 1 + k];
         grad[j * D + k] = (float)(scale * (s0 * yc[j * D + k] - s1));
     }
@@ -2090,9 +2100,11 @@ __global__ void adjoint_finish(Consts kc, int D, int P, double scale, const doub
     if (i >= kc.n) return;
     const int W = D + 2;
     double off = -__builtin_inf();
+#pragma unroll 8
     for (int p = 0; p < P; ++p) off = fmax(off, part[((int64_t)p * kc.n + i) * W]);
     // split p's sums are scaled by 2^-M_p: bring them to the common offset (exact)
     double s0 = 0.0;
+#pragma unroll 8
     for (int p = 0; p < P; ++p) {
         const double* o = part + ((int64_t)p * kc.n + i) * W;
         if (o[0] > -__builtin_inf()) s0 += ldexp(o[1], (int)(o[0] - off));
@@ -2100,6 +2112,7 @@ __global__ void adjoint_finish(Consts kc, int D, int P, double scale, const doub
     const double cx = kc.metric == METRIC_SQEUCLID ? 1.0 : 0.0;
     for (int k = 0; k < D; ++k) {
         double s1 = 0.0;
+#pragma unroll 8
         for (int p = 0; p < P; ++p) {
             const double* o = part + ((int64_t)p * kc.n + i) * W;
             if (o[0] > -__builtin_inf()) s1 += ldexp(o[2 + k], (int)(o[0] - off));
