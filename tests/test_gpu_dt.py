@@ -58,12 +58,15 @@ def _problem(n, m, d, kind, seed, eta=1e-2):
                                               ((64, 64, 3), "l1", [0, 5, 40]),
                                               ((50, 61, 2), "linf", [0, 9]),
                                               ((45, 38, 20), "sqeuclid", [0, 7]),
-                                              ((1, 9, 2), "sqeuclid", [0, 3])])
+                                              ((1, 9, 2), "sqeuclid", [0, 3]),
+                                              ((300, 1100, 3), "sqeuclid", [0, 2]),
+                                              ((260, 900, 2), "l1", [0, 1])])
 def test_dt_summand_of_one_step_matches_oracle(shape, kind, steps):
     """One GPU step from the oracle's FP64 state at s, dt_partial starting at 0: the increment is
     the summand of D_{s+1} without its normaliser telescope.  Covers the D_t sums fused into the
-    vector-ALU row sweep (d = 2, 3), the separate cost pass beside the FP64 matrix-core sweeps
-    (d = 20), each ground cost and a single row."""
+    vector-ALU row sweep (d = 2, 3; 300 x 1100 and 260 x 900 split the columns 9 and 8 ways with
+    a ragged last split), the separate cost pass beside the FP64 matrix-core sweeps (d = 20),
+    each ground cost and a single row."""
     n, m, d = shape
     wl, C, prob = _problem(n, m, d, kind, seed=300 + n)
     _say("case", wl.name, kind)
