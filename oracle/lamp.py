@@ -488,6 +488,32 @@ def envelope_grad_y(x: np.ndarray, y: np.ndarray, r: np.ndarray, s: float, nu: n
     return g
 
 
+def envelope_grad_y_columns(x: np.ndarray, y: np.ndarray, r: np.ndarray, s: float, nu: np.ndarray,
+                            lam: float, cnorm: float, cols, log_z: np.ndarray,
+                            kind: str = "sqeuclid") -> np.ndarray:
+    """The rows `cols` of envelope_grad_y, one column j at a time over every row i, given the row
+    log-normalisers log Z_i = LSE_j(-lam (C_ij + 2||C||_inf nu_j)) of the same coupling (a full
+    row pass supplies them at sizes where no n x m array fits; a column's gradient needs only
+    its own column beside them): X_ij = r_i exp(-lam (C_ij + 2||C||_inf nu_j) - log Z_i)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    cols = np.asarray(cols, dtype=np.int64)
+    g = np.zeros((cols.shape[0], y.shape[1]))
+    for a, j in enumerate(cols):
+        Cj = ground_cost(x, y[j:j + 1], s, kind)[:, 0]
+        Xj = r * np.exp(-lam * (Cj + 2.0 * cnorm * nu[j]) - log_z)
+        diff = y[j][None, :] - x
+        if kind == "sqeuclid":
+            g[a] = 2.0 * s * (Xj @ diff)
+        elif kind == "l1":
+            g[a] = s * (Xj @ np.sign(diff))
+        else:
+            k = np.argmax(np.abs(diff), axis=1)
+            sg = np.sign(diff[np.arange(x.shape[0]), k])
+            np.add.at(g[a], k, s * Xj * sg)
+    return g
+
+
 def envelope_grad_x(x: np.ndarray, y: np.ndarray, r: np.ndarray, s: float, nu: np.ndarray,
                     lam: float, cnorm: float) -> np.ndarray:
     """grad_{x_i} = sum_j X_ij dC_ij/dx_i = sum_j X_ij * 2 s (x_i - y_j), X = diag(r) p^{1/lam}(nu).

@@ -73,7 +73,7 @@ def _synthetic_state(wl, t, seed):
     return nu, th, lam[t], lam[t + 1]
 
 
-def _check_step(wl, key, precision, t, cost, logz_tol, col_tol, with_trace=False):
+def _check_step(wl, key, precision, t, cost, logz_tol, col_tol, with_trace=False, with_ref=False):
     """One GPU iteration at t from the seeded synthetic state, against the oracle's full-size
     pass over `cost` (every row, sampled columns), plus size-independent properties."""
     s = GOLD[key]["cost_scale"]
@@ -96,6 +96,8 @@ def _check_step(wl, key, precision, t, cost, logz_tol, col_tol, with_trace=False
     # marginals are non-negative; a column whose every term lies below FP32's range reads 0
     assert np.all(ca >= 0) and np.all(cb >= 0)
     assert np.all(np.abs(to_np(st.theta)) < 1) and np.all(np.abs(to_np(st.nu)) < 1)
+    if with_ref:
+        return prob, st, ref
     return (prob, st, tr) if with_trace else (prob, st)
 
 
@@ -157,12 +159,32 @@ def _check_certificate(prob, params, nu, th, t, lam_t, col_a, c):
 def test_sphere_cube_262144_step_and_gradient():
     """2^18 x 2^18, d = 3: one FP32-form iteration at t = 400 (every row, sampled columns); then the adjoint
     at the resulting state: 16 random gradient coordinates against the oracle's per-row
-    envelope gradient and against central finite differences of the row term (h = 1e-4)."""
+    envelope gradient and against central finite differences of the row term (h = 1e-4); and
+    the adjoint with respect to y at the state the step started from, on 34 columns (the 16
+    of largest gradient, both ends, 16 random ones), against the oracle's column gradient
+    over every row, with the row log-normalisers of that state from the oracle's full-size
+    pass."""
     key = "sphere_cube_262144"
     wl = W.sphere_cube()
     s = GOLD[key]["cost_scale"]
-    prob, st = _check_step(wl, key, "fp32", 400, RP.Cost(s, 1.0, x=wl.x, y=wl.y), FP32_LOGZ_ATOL,
-                           FP32_COL_RTOL)
+    prob, st, ref = _check_step(wl, key, "fp32", 400, RP.Cost(s, 1.0, x=wl.x, y=wl.y), FP32_LOGZ_ATOL,
+                                FP32_COL_RTOL, with_ref=True)
+    nu0, th0, lam0, _ = _synthetic_state(wl, 400, seed=77)
+    st0 = P.State(torch.tensor(nu0, device="cuda"), torch.tensor(th0, device="cuda"), 400, lam0)
+    gy = to_np(P.backward_y(prob, P.make_params(eta=wl.eta), st0, grad_out=1.0))
+    # most target points far from the sphere carry no mass at this temperature (gradient 0 on
+    # both sides): the sample takes the 16 columns of largest gradient, both ends and 16
+    # random ones
+    big = np.argsort(-np.linalg.norm(gy, axis=1))[:16]
+    ycols = np.concatenate([[0, wl.m - 1], big, np.random.default_rng(9).integers(0, wl.m, 16)])
+    gy_or = OL.envelope_grad_y_columns(wl.x.astype(np.float64), wl.y.astype(np.float64), wl.r, s, nu0, lam0,
+                                       1.0, ycols, ref["logZA"])
+    yscale = np.maximum(np.abs(gy_or), 1e-3 * np.max(np.abs(gy)))
+    yerr = np.abs(gy[ycols] - gy_or) / yscale
+    _say(f"y-gradient on {len(ycols)} columns: |g| up to {np.max(np.abs(gy_or)):.3e}, "
+         f"max scaled error {np.max(yerr):.2e} (on the 16 largest {np.max(yerr[2:18]):.2e})")
+    assert np.max(np.abs(gy_or[2:18])) > 0.1 * np.max(np.abs(gy))
+    assert np.max(yerr) <= 1e-5
     g = to_np(P.backward(prob, P.make_params(eta=wl.eta), st, grad_out=1.0))
     rng = np.random.default_rng(5)
     coords = [(int(rng.integers(0, wl.n)), int(rng.integers(0, 3))) for _ in range(16)]

@@ -136,6 +136,22 @@ def test_mutation_gradient_factor(monkeypatch):
     _fails(pins.test_envelope_gradient_matches_finite_differences)
 
 
+def test_mutation_column_gradient_without_normaliser(monkeypatch):
+    """Forgetting the row log-normaliser in X_ij (the unnormalised coupling)."""
+    orig = L.envelope_grad_y_columns
+    monkeypatch.setattr(L, "envelope_grad_y_columns",
+                        lambda x, y, r, s, nu, lam, cn, cols, lz, kind="sqeuclid":
+                        orig(x, y, r, s, nu, lam, cn, cols, np.zeros_like(lz), kind))
+    _fails(pins.test_envelope_gradient_columns_by_finite_differences, "sqeuclid")
+
+
+def test_mutation_column_gradient_sign(monkeypatch):
+    """x - y in place of y - x."""
+    orig = L.envelope_grad_y_columns
+    monkeypatch.setattr(L, "envelope_grad_y_columns", lambda *a, **k: -orig(*a, **k))
+    _fails(pins.test_envelope_gradient_columns_by_finite_differences, "l1")
+
+
 def test_mutation_dt_kl_arguments_swapped(monkeypatch):
     """KL(X^{s+1} || Xbar) in place of KL(Xbar || X^{s+1}) in the D_t summand."""
     orig = L.kl

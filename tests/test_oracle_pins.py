@@ -496,6 +496,30 @@ def test_envelope_gradient_wrt_targets_by_finite_differences(kind):
             assert g[j, k] == pytest.approx(fd, rel=1e-5, abs=1e-9)
 
 
+@pytest.mark.parametrize("kind", ["sqeuclid", "l1", "linf"])
+def test_envelope_gradient_columns_by_finite_differences(kind):
+    """The column-at-a-time y-gradient (given the row log-normalisers) against central differences
+    of the whole dual value, on listed columns, for each ground cost."""
+    wl = W.random_small(7, 9, 3, seed=29, eta=1e-1)
+    x, y = wl.x.astype(np.float64), wl.y.astype(np.float64)
+    s = 1.0 / L.max_cost(x, y, kind)
+    rng = np.random.default_rng(6)
+    nu = 0.3 * rng.standard_normal(wl.m)
+    lam = 4.0
+    C = L.ground_cost(x, y, s, kind)
+    cols = [0, 4, 8]
+    g = L.envelope_grad_y_columns(x, y, wl.r, s, nu, lam, 1.0, cols, L.log_normaliser(C, nu, lam, 1.0), kind)
+    h = 1e-6
+    for a, j in enumerate(cols):
+        for k in range(3):
+            yp, ym = y.copy(), y.copy()
+            yp[j, k] += h
+            ym[j, k] -= h
+            fd = (np.sum(L.envelope_value_rows(x, yp, wl.r, s, nu, lam, 1.0, kind))
+                  - np.sum(L.envelope_value_rows(x, ym, wl.r, s, nu, lam, 1.0, kind))) / (2 * h)
+            assert g[a, k] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
 # ---------------------------------------------------------------- D_t (Proposition infeas_bound(b))
 
 
