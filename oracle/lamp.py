@@ -6,8 +6,9 @@ K = 2 ||C||_inf is the factor in front of the dual in the saddle objective
 (problem spp), lam_t = 1/eta_t is the inverse temperature with lam_0 = 0
 (eta_0 = infinity, Algorithm 2).
 
-Everything here materialises the n x m cost matrix, so it is meant for n*m up
-to a few million.  ``oracle.stream`` evaluates the same iteration in row blocks.
+Everything here but envelope_grad_y_columns (one column at a time) materialises the
+n x m cost matrix, so it is meant for n*m up to a few million.  ``oracle.stream``
+evaluates the same iteration in row blocks.
 """
 from __future__ import annotations
 
