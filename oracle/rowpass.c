@@ -13,6 +13,8 @@
  *   a^q_ij = -lam_q (C_ij + K v_q,j),
  *   logZ^q_i = max_j a^q_ij + log sum_j exp(a^q_ij - max_j a^q_ij)      (oracle_log_normalisers)
  *   col^q_j = sum_i r_i exp(a^q_ij - logZ^q_i)   for the listed columns  (oracle_sampled_columns)
+ *   E^q_i = sum_j exp(a^q_ij - logZ^q_i) C_ij    for every row          (oracle_row_costs),
+ *           so that <C, diag(r) p^{1/lam_q}(v_q)> = sum_i r_i E^q_i
  * Each row (each listed column) is evaluated by one thread, so results do not
  * depend on the number of threads.  Built with -ffast-math so that the sum of
  * exponentials vectorises (partial sums in SIMD lanes): a change of rounding order
@@ -141,6 +143,37 @@ void oracle_sampled_columns(const cost_def *c, int32_t nc, const double *v, cons
             for (int64_t i = 0; i < c->n; ++i) column_terms(c, i, cols + k0, cnt, vq, lam[q], Lq[i], r[i], acc);
             for (int64_t k = 0; k < cnt; ++k) out[(int64_t)q * ncols + k0 + k] = acc[k];
         }
+    }
+}
+
+/* sum_j exp(a_j - L) w_j */
+__attribute__((target_clones("avx2", "default")))
+static double sum_exp_weighted(const double *a, const double *w, int64_t m, double L)
+{
+    double sum = 0.0;
+#pragma omp simd reduction(+ : sum)
+    for (int64_t j = 0; j < m; ++j) sum += exp(a[j] - L) * w[j];
+    return sum;
+}
+
+void oracle_row_costs(const cost_def *c, int32_t nc, const double *v, const double *lam, const double *logZ,
+                      double *out)
+{
+#pragma omp parallel
+    {
+        double *row = (double *)malloc(sizeof(double) * (size_t)c->m);
+        double *arg = (double *)malloc(sizeof(double) * (size_t)c->m);
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t i = 0; i < c->n; ++i) {
+            cost_row(c, i, row);
+            for (int32_t q = 0; q < nc; ++q) {
+                const double *vq = v + (int64_t)q * c->m;
+                for (int64_t j = 0; j < c->m; ++j) arg[j] = -lam[q] * (row[j] + c->K * vq[j]);
+                out[(int64_t)q * c->n + i] = sum_exp_weighted(arg, row, c->m, logZ[(int64_t)q * c->n + i]);
+            }
+        }
+        free(arg);
+        free(row);
     }
 }
 

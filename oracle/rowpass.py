@@ -49,6 +49,8 @@ def _load():
         lib.oracle_sampled_columns.restype = None
         lib.oracle_sampled_columns.argtypes = [ctypes.POINTER(_CostDef), ctypes.c_int32, _vp, _vp, _vp,
                                                _vp, _vp, ctypes.c_int64, _vp]
+        lib.oracle_row_costs.restype = None
+        lib.oracle_row_costs.argtypes = [ctypes.POINTER(_CostDef), ctypes.c_int32, _vp, _vp, _vp, _vp]
         _lib = lib
     return _lib
 
@@ -99,6 +101,18 @@ class Cost:
         _load().oracle_sampled_columns(ctypes.byref(self.cd), v.shape[0], v.ctypes.data, lam.ctypes.data,
                                        lz.ctypes.data, rr.ctypes.data, cj.ctypes.data, cj.shape[0],
                                        out.ctypes.data)
+        return out
+
+
+    def row_costs(self, duals, lams, logZ) -> np.ndarray:
+        """E^q_i = sum_j p^{1/lam_q}(v_q)_ij C_ij for every row i, one row per coupling q, given the
+        row log-normalisers; <C, diag(r) p> = r . E."""
+        v = np.ascontiguousarray(np.stack(duals), dtype=np.float64)
+        lam = np.ascontiguousarray(lams, dtype=np.float64)
+        lz = np.ascontiguousarray(logZ, dtype=np.float64)
+        out = np.empty((v.shape[0], self.n))
+        _load().oracle_row_costs(ctypes.byref(self.cd), v.shape[0], v.ctypes.data, lam.ctypes.data,
+                                 lz.ctypes.data, out.ctypes.data)
         return out
 
 

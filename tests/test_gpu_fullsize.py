@@ -163,7 +163,7 @@ def test_sphere_cube_262144_step_and_gradient():
     the adjoint with respect to y at the state the step started from, on 34 columns (the 16
     of largest gradient, both ends, 16 random ones), against the oracle's column gradient
     over every row, with the row log-normalisers of that state from the oracle's full-size
-    pass."""
+    pass; and the transport cost of that state against the oracle's full-size row costs."""
     key = "sphere_cube_262144"
     wl = W.sphere_cube()
     s = GOLD[key]["cost_scale"]
@@ -185,6 +185,14 @@ def test_sphere_cube_262144_step_and_gradient():
          f"max scaled error {np.max(yerr):.2e} (on the 16 largest {np.max(yerr[2:18]):.2e})")
     assert np.max(np.abs(gy_or[2:18])) > 0.1 * np.max(np.abs(gy))
     assert np.max(yerr) <= 1e-5
+    # the transport cost <C, X^t> of the same state (the autograd forward's value): every row's
+    # expected cost from the oracle's full-size pass; relative tolerance 2e-6, the per-row
+    # bound of the transport-cost tests (FP32 exponentials of FP64 arguments, FP32 block sums)
+    E = RP.Cost(s, 1.0, x=wl.x, y=wl.y).row_costs([nu0], [lam0], ref["logZA"][None, :])[0]
+    ref_cost = float(wl.r @ E)
+    got_cost = float(P.transport_cost(prob, P.make_params(eta=wl.eta), st0))
+    _say(f"transport cost gpu {got_cost:.12e} oracle {ref_cost:.12e} rel {abs(got_cost / ref_cost - 1):.2e}")
+    assert abs(got_cost - ref_cost) <= 2e-6 * abs(ref_cost)
     g = to_np(P.backward(prob, P.make_params(eta=wl.eta), st, grad_out=1.0))
     rng = np.random.default_rng(5)
     coords = [(int(rng.integers(0, wl.n)), int(rng.integers(0, 3))) for _ in range(16)]

@@ -407,6 +407,28 @@ def test_rowpass_c_step_matches_dense_step(eta):
     np.testing.assert_allclose(run["saved"][7][1], st7.nu, rtol=1e-11, atol=1e-14)
 
 
+@pytest.mark.parametrize("eta", [0.0, 1e-2])
+def test_rowpass_c_row_costs_give_the_plan_cost(eta):
+    """The C pass's per-row expected costs E_i = sum_j p_ij C_ij (given its row log-normalisers):
+    r . E equals <C, X^t> of the dense certificate, and E_i equals the row's share, for both
+    cost forms, at the state after 30 iterations (n != m)."""
+    from oracle import rowpass
+    wl = W.random_small(150, 97, 4, seed=19)
+    x, y = wl.x.astype(np.float64), wl.y.astype(np.float64)
+    s = 1.0 / L.max_sqdist(x, y)
+    C = L.sqeuclid_cost(x, y, s)
+    prm = L.Params(eta=eta)
+    st, _ = L.lamp_dense(C, wl.r, wl.c, prm, 30, 1.0, trace=False)
+    ref = L.certificate(C, wl.r, wl.c, st, prm, 1.0)["cost"]
+    rows_ref = np.sum(L.plan(C, wl.r, st, 1.0) * C, axis=1) / wl.r
+    gram = (x, y, np.sum(x * x, axis=1), np.sum(y * y, axis=1))
+    for cost, rtol in [(rowpass.Cost(s, 1.0, x=wl.x, y=wl.y), 1e-12), (rowpass.Cost(s, 1.0, gram=gram), 1e-9)]:
+        lz = cost.log_normalisers([st.nu], [st.lam])
+        E = cost.row_costs([st.nu], [st.lam], lz)[0]
+        np.testing.assert_allclose(E, rows_ref, rtol=rtol, atol=1e-15)
+        assert float(wl.r @ E) == pytest.approx(ref, rel=rtol)
+
+
 def test_cmax_c_routine_matches_numpy():
     from oracle import cmax
     wl = W.random_small(300, 211, 5, seed=16)
