@@ -494,7 +494,7 @@ def test_autograd_function_gradient():
     st_or, _ = OL.lamp_dense(C, wl.r, wl.c, OL.Params(eta=1e-2), 80, 1.0, trace=False)
     g_or = OL.envelope_grad_x(x, y, wl.r, s, st_or.nu, st_or.lam, 1.0)
     cost_or = float(np.sum(C * OL.plan(C, wl.r, st_or, 1.0)))
-    assert float(cost) == pytest.approx(cost_or, rel=1e-5)
+    assert float(cost.detach()) == pytest.approx(cost_or, rel=1e-5)
     assert rel_inf(to_np(xt.grad), g_or) <= 1e-4
 
 
