@@ -207,8 +207,8 @@ Layout layout(int64_t n, int64_t m, int d, int prec = LAMP_FP32, int64_t target 
         rpart_d = std::max<size_t>(rpart_d, (size_t)L.P_rm * n * 2);
         cpart_d2 = std::max<size_t>(cpart_d2, (size_t)L.P_cm * m);
     }
-    if (L.use64) {
-        rpart_d = std::max<size_t>(rpart_d, (size_t)L.P_r64 * n * 2);
+    if (L.use64) {   // D_t tracking: [P][n] double2 sums, then [P][n] cost sums
+        rpart_d = std::max<size_t>(rpart_d, (size_t)L.P_r64 * n * 3);
         cpart_d2 = std::max<size_t>(cpart_d2, (size_t)L.P_c64 * m);
     }
     if (L.cost) {
@@ -592,6 +592,17 @@ void row_mfma64(const Layout& L, Consts kc, void* ws, hipStream_t st) {
                        n_waves);
 }
 
+// The D_t-tracked FP64 matrix-core row sweep: cost sums into tpart ([P_r64][n]).
+template <int KP>
+void row_mfma64_dt(const Layout& L, Consts kc, void* ws, double* tpart, hipStream_t st) {
+    const int64_t n_waves = L.n_pad64 / 16;
+    dim3 g((unsigned)(cdiv(n_waves, 4) * L.P_r64));
+    hipLaunchKernelGGL((row_sweep_mfma64_dt<KP>), g, dim3(BLOCK), 0, st, at<Ctrl>(ws, L.ctrl), at<Sched>(ws, L.sched),
+                       kc, at<double>(ws, L.xop64), at<double>(ws, L.yop64), at<double2>(ws, L.gtab),
+                       at<double>(ws, L.H), at<double2>(ws, L.rpart), L.tps_r64, (int)L.P_r64, L.m_pad64 / 16,
+                       n_waves, at<double>(ws, L.xn2), at<double>(ws, L.yn2), tpart);
+}
+
 template <int KP>
 void col_mfma64(const Layout& L, Consts kc, void* ws, hipStream_t st) {
     const int64_t m_waves = L.m_pad64 / 16;
@@ -959,12 +970,29 @@ void launch_dt_cost(const lamp_problem* p, const Layout& L, Consts kc, void* ws,
     hipLaunchKernelGGL(dt_cost_total, dim3(1), dim3(1024), 0, st, ctrl, (const double*)out, kc.n);
 }
 
-// The row sweep of a D_t-tracked iteration with <C, Xbar^{t+1}> fused into it (vector-ALU
-// sweeps of a templated dimension): row_sweep_dt, then dt_rows_finish and dt_cost_total.  The
-// cost partials sit behind the sweep's [P_r][n] double2 partials in the row partial buffer
-// (sized for 4 P_r n doubles).  Returns false, launching nothing, for the other sweeps.
+// The row sweep of a D_t-tracked iteration with <C, Xbar^{t+1}> fused into it (FP64
+// matrix-core sweeps, and vector-ALU sweeps of a templated dimension): the sweep, then
+// dt_rows_finish and dt_cost_total.  The cost partials sit behind the sweep's [P][n] double2
+// partials in the row partial buffer (sized for 4 P_r n and 3 P_r64 n doubles).  Returns false,
+// launching nothing, for the other sweeps.
 bool launch_row_sweep_dt(const lamp_problem* p, const Layout& L, Consts kc, void* ws, hipStream_t st) {
-    if (L.cost || is_mfma(L.prec) || L.use64) return false;
+    if (L.cost || is_mfma(L.prec)) return false;
+    if (L.use64) {
+        double* tpart = at<double>(ws, L.rpart) + 2 * L.P_r64 * kc.n;
+        switch (L.KP64) {
+            case 32: row_mfma64_dt<32>(L, kc, ws, tpart, st); break;
+            case 64: row_mfma64_dt<64>(L, kc, ws, tpart, st); break;
+            default: row_mfma64_dt<128>(L, kc, ws, tpart, st); break;
+        }
+        Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+        double* out = at<double>(ws, L.dtrow);
+        hipLaunchKernelGGL(dt_rows_finish_dyn, grid1(kc.n), dim3(BLOCK), 0, st, ctrl, at<Sched>(ws, L.sched), kc,
+                           p->d, at<double>(ws, L.xc), at<double>(ws, L.yc), at<double>(ws, L.xn2),
+                           at<double>(ws, L.yn2), at<double2>(ws, L.gtab), p->r, at<double2>(ws, L.rpart),
+                           (const double*)tpart, (int)L.P_r64, out);
+        hipLaunchKernelGGL(dt_cost_total, dim3(1), dim3(1024), 0, st, ctrl, (const double*)out, kc.n);
+        return true;
+    }
     const dim3 g(sweep_grid(kc.n, L.P_r));
     Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
     const Sched* sch = at<Sched>(ws, L.sched);

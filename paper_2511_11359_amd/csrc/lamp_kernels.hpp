@@ -902,15 +902,14 @@ __global__ __launch_bounds__(BLOCK) void dt_cost_rows_dyn(const Ctrl* ctrl, cons
 // (both sums under the row's offset h_i, so the splits add directly).  A row whose S^B leaves
 // [2^-60, 2^60] -- the rows whose normalisers row_finish recomputes -- is evaluated again in
 // FP64 under its exact largest exponent.
-template <int M, int D>
-__global__ void dt_rows_finish(const Ctrl* ctrl, const Sched* sched, Consts kc, const double* __restrict__ xc,
-                               const double* __restrict__ yc, const double* __restrict__ xn2,
-                               const double* __restrict__ yn2, const double2* __restrict__ gtab2,
-                               const double* __restrict__ r, const double2* __restrict__ part,
-                               const double* __restrict__ tpart, int P, double* __restrict__ out) {
-    if (halted(ctrl)) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kc.n) return;
+// pair(j) = P(x_i, y_j); sq: squared Euclidean (the norms enter the cost).
+template <typename Pair>
+__device__ __forceinline__ void dt_rows_finish_body(const Ctrl* ctrl, const Sched* sched, Consts kc, bool sq,
+                                                    const double* __restrict__ xn2, const double* __restrict__ yn2,
+                                                    const double2* __restrict__ gtab2, const double* __restrict__ r,
+                                                    const double2* __restrict__ part,
+                                                    const double* __restrict__ tpart, int P, int64_t i,
+                                                    double* __restrict__ out, Pair&& pair) {
     double SB = 0.0, T = 0.0;
 #pragma unroll 8   // independent loads in flight; the sum order is unchanged
     for (int p = 0; p < P; ++p) {
@@ -925,20 +924,48 @@ __global__ void dt_rows_finish(const Ctrl* ctrl, const Sched* sched, Consts kc, 
     const Sched sc = sched[t - ctrl->t_base];
     const double cB = 2.0 * kc.s * sc.lamB * LOG2E;
     const double2* __restrict__ g = gtab2 + (t & 1) * kc.m;
+    double emax = -__builtin_inf();
+    for (int64_t j = 0; j < kc.m; ++j) emax = fmax(emax, fma(cB, pair(j), g[j].y));
+    const double xa = sq ? xn2[i] : 0.0;
+    double S = 0.0, Tx = 0.0;
+    for (int64_t j = 0; j < kc.m; ++j) {
+        const double dot = pair(j);
+        const double q = exp2(fma(cB, dot, g[j].y) - emax);
+        S += q;
+        Tx += q * fma(-2.0, dot, sq ? xa + yn2[j] : xa);
+    }
+    out[i] = kc.s * r[i] * (Tx / S);
+}
+
+template <int M, int D>
+__global__ void dt_rows_finish(const Ctrl* ctrl, const Sched* sched, Consts kc, const double* __restrict__ xc,
+                               const double* __restrict__ yc, const double* __restrict__ xn2,
+                               const double* __restrict__ yn2, const double2* __restrict__ gtab2,
+                               const double* __restrict__ r, const double2* __restrict__ part,
+                               const double* __restrict__ tpart, int P, double* __restrict__ out) {
+    if (halted(ctrl)) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
     double x[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = xc[i * D + k];
-    double emax = -__builtin_inf();
-    for (int64_t j = 0; j < kc.m; ++j) emax = fmax(emax, fma(cB, pair_term<M, D>(x, yc + j * D, 0.0), g[j].y));
-    const double xa = M == METRIC_SQEUCLID ? xn2[i] : 0.0;
-    double S = 0.0, Tx = 0.0;
-    for (int64_t j = 0; j < kc.m; ++j) {
-        const double dot = pair_term<M, D>(x, yc + j * D, 0.0);
-        const double q = exp2(fma(cB, dot, g[j].y) - emax);
-        S += q;
-        Tx += q * fma(-2.0, dot, M == METRIC_SQEUCLID ? xa + yn2[j] : xa);
-    }
-    out[i] = kc.s * r[i] * (Tx / S);
+    dt_rows_finish_body(ctrl, sched, kc, M == METRIC_SQEUCLID, xn2, yn2, gtab2, r, part, tpart, P, i, out,
+                        [&](int64_t j) { return pair_term<M, D>(x, yc + j * D, 0.0); });
+}
+
+// The same with the metric and the dimension at run time (the FP64 matrix-core sweeps).
+__global__ void dt_rows_finish_dyn(const Ctrl* ctrl, const Sched* sched, Consts kc, int D,
+                                   const double* __restrict__ xc, const double* __restrict__ yc,
+                                   const double* __restrict__ xn2, const double* __restrict__ yn2,
+                                   const double2* __restrict__ gtab2, const double* __restrict__ r,
+                                   const double2* __restrict__ part, const double* __restrict__ tpart, int P,
+                                   double* __restrict__ out) {
+    if (halted(ctrl)) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kc.n) return;
+    const double* __restrict__ xi = xc + i * D;
+    dt_rows_finish_body(ctrl, sched, kc, kc.metric == METRIC_SQEUCLID, xn2, yn2, gtab2, r, part, tpart, P, i, out,
+                        [&](int64_t j) { return pair_term_dyn(kc, D, xi, yc + j * D, 0.0); });
 }
 
 // ctrl->dt_cost = sum_i out_i, one block, fixed order (deterministic).

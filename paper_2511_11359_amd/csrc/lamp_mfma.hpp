@@ -864,14 +864,19 @@ __device__ __forceinline__ void pipelined_tiles(int it0, int it1, int it_mask, S
     for (; it < it1; ++it) step(it, (it + 1 - it0) & 1, std::true_type{});
 }
 
-template <int KP>
-__global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
-                                                              const double* __restrict__ xop,
-                                                              const double* __restrict__ yop,
-                                                              const double2* __restrict__ gtab2,
-                                                              const double* __restrict__ H,
-                                                              double2* __restrict__ part, int64_t tiles_per_split,
-                                                              int P, int64_t m_tiles, int64_t n_waves) {
+// Body of the FP64 matrix-core row sweep; with DT it also sums the B coupling's cost terms
+// for D_t tracking, 2^eB C_ij / s with C_ij / s = (|x~_i|^2 + 2 h_i) + |y~_j|^2 - 2 dot from the
+// accumulator dot = h_i + x~_i . y~_j (tpart[p][i], under the row offset of the B sums).
+template <int KP, bool DT>
+__device__ __forceinline__ void row_sweep_mfma64_body(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                      const double* __restrict__ xop,
+                                                      const double* __restrict__ yop,
+                                                      const double2* __restrict__ gtab2,
+                                                      const double* __restrict__ H,
+                                                      double2* __restrict__ part, int64_t tiles_per_split,
+                                                      int P, int64_t m_tiles, int64_t n_waves,
+                                                      const double* __restrict__ xn2, const double* __restrict__ yn2,
+                                                      double* __restrict__ tpart) {
     using L = LdsTile64<KP>;
     constexpr int NS = KP / 4;
     __shared__ __align__(16) char lds[2][L::BUF];
@@ -902,6 +907,21 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, 
     }
     float accA[4] = {0.f, 0.f, 0.f, 0.f}, accB[4] = {0.f, 0.f, 0.f, 0.f};
     double sumA[4] = {0.0, 0.0, 0.0, 0.0}, sumB[4] = {0.0, 0.0, 0.0, 0.0};
+    [[maybe_unused]] float accT[4] = {0.f, 0.f, 0.f, 0.f};
+    [[maybe_unused]] double sumT[4] = {0.0, 0.0, 0.0, 0.0};
+    [[maybe_unused]] doublex4 xa;
+    if constexpr (DT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t ii = i0 + 4 * q + grp;
+            xa[q] = xn2[ii < kc.n ? ii : kc.n - 1] + 2.0 * hv[q];
+        }
+    }
+    // |y~_j|^2 of this lane's column in tile jt (clamped past m: those columns weigh 0)
+    [[maybe_unused]] auto ycol = [&](int jt) {
+        const int64_t j = (int64_t)jt * 16 + c16;
+        return yn2[j < kc.m ? j : kc.m - 1];
+    };
     const int jt0 = (int)((int64_t)p * tiles_per_split);
     const int jt1 = (int)min(m_tiles, (int64_t)jt0 + tiles_per_split);
     const TileSrc src = make_tile_src(yop, (uint32_t)(m_tiles * L::TILE_BYTES), g, (uint32_t)(kc.m * 16));
@@ -920,6 +940,8 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, 
         __syncthreads();
         doublex4 dc = tile_dot64<KP>(lds[0], c16, grp, a, hv);
         double2 gc = scal(lds[0], jt0, std::true_type{});
+        [[maybe_unused]] double yc = 0.0;
+        if constexpr (DT) yc = ycol(jt0);
         tile64_fetch<KP>(src, min(jt0 + 1, jl), pf);
         tile64_store<KP>(lds[1], pf);
         __syncthreads();
@@ -930,10 +952,23 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, 
             tile64_fetch<KP>(src, min(jt + 2, jl), pf);
             const doublex4 dn = tile_dot64<KP>(lds[nxt], c16, grp, a, hv);
             const double2 gn = scal(lds[nxt], min(jt + 1, jl), check);
+            [[maybe_unused]] double yn = 0.0;
+            if constexpr (DT) {
+                yn = ycol(min(jt + 1, jl));
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                accA[q] += fexp2(fma(dc[q], cA, gc.x));
-                accB[q] += fexp2(fma(dc[q], cB, gc.y));
+                for (int q = 0; q < 4; ++q) {
+                    accA[q] += fexp2(fma(dc[q], cA, gc.x));
+                    const float pB = fexp2(fma(dc[q], cB, gc.y));
+                    accB[q] += pB;
+                    accT[q] = fmaf(pB, (float)fma(-2.0, dc[q], xa[q] + yc), accT[q]);
+                }
+                pin(accT);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    accA[q] += fexp2(fma(dc[q], cA, gc.x));
+                    accB[q] += fexp2(fma(dc[q], cB, gc.y));
+                }
             }
             pin(accA);
             pin(accB);
@@ -944,12 +979,17 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, 
                     sumA[q] += (double)accA[q];
                     sumB[q] += (double)accB[q];
                     accA[q] = accB[q] = 0.f;
+                    if constexpr (DT) {
+                        sumT[q] += (double)accT[q];
+                        accT[q] = 0.f;
+                    }
                 }
             }
             tile64_store<KP>(lds[nxt ^ 1], pf);
             __syncthreads();
             dc = dn;
             gc = gn;
+            if constexpr (DT) yc = yn;
         };
         // iteration jt reads the scalars of tile jt + 1: whole tiles (16 columns below m) for jt < m / 16 - 1
         pipelined_tiles(jt0, jt1, max(jt0, min(jt1, (int)(kc.m / 16) - 1)), step);
@@ -959,17 +999,50 @@ __global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, 
     for (int q = 0; q < 4; ++q) {
         sumA[q] += (double)accA[q];
         sumB[q] += (double)accB[q];
+        if constexpr (DT) sumT[q] += (double)accT[q];
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) {
             sumA[q] += __shfl_xor(sumA[q], o, 64);
             sumB[q] += __shfl_xor(sumB[q], o, 64);
+            if constexpr (DT) sumT[q] += __shfl_xor(sumT[q], o, 64);
         }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int64_t row = i0 + 4 * q + grp;
-        if (c16 == q && row < kc.n) part[(int64_t)p * kc.n + row] = make_double2(sumA[q], sumB[q]);
+        if (c16 == q && row < kc.n) {
+            part[(int64_t)p * kc.n + row] = make_double2(sumA[q], sumB[q]);
+            if constexpr (DT) tpart[(int64_t)p * kc.n + row] = sumT[q];
+        }
     }
+}
+
+template <int KP>
+__global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_lds(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                              const double* __restrict__ xop,
+                                                              const double* __restrict__ yop,
+                                                              const double2* __restrict__ gtab2,
+                                                              const double* __restrict__ H,
+                                                              double2* __restrict__ part, int64_t tiles_per_split,
+                                                              int P, int64_t m_tiles, int64_t n_waves) {
+    row_sweep_mfma64_body<KP, false>(ctrl, sched, kc, xop, yop, gtab2, H, part, tiles_per_split, P, m_tiles, n_waves,
+                                     nullptr, nullptr, nullptr);
+}
+
+// The FP64 matrix-core row sweep of a D_t-tracked iteration, tpart: [P][n].
+template <int KP>
+__global__ __launch_bounds__(BLOCK) void row_sweep_mfma64_dt(const Ctrl* ctrl, const Sched* sched, Consts kc,
+                                                             const double* __restrict__ xop,
+                                                             const double* __restrict__ yop,
+                                                             const double2* __restrict__ gtab2,
+                                                             const double* __restrict__ H,
+                                                             double2* __restrict__ part, int64_t tiles_per_split,
+                                                             int P, int64_t m_tiles, int64_t n_waves,
+                                                             const double* __restrict__ xn2,
+                                                             const double* __restrict__ yn2,
+                                                             double* __restrict__ tpart) {
+    row_sweep_mfma64_body<KP, true>(ctrl, sched, kc, xop, yop, gtab2, H, part, tiles_per_split, P, m_tiles, n_waves,
+                                    xn2, yn2, tpart);
 }
 
 // Four waves per SIMD for KP <= 64 (128 VGPRs, no spills): 10.59 -> 10.35 ms at
