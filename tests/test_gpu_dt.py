@@ -58,6 +58,9 @@ def _problem(n, m, d, kind, seed, eta=1e-2):
                                               ((64, 64, 3), "l1", [0, 5, 40]),
                                               ((50, 61, 2), "linf", [0, 9]),
                                               ((45, 38, 20), "sqeuclid", [0, 7]),
+                                              ((300, 1100, 20), "sqeuclid", [0, 2]),
+                                              ((200, 530, 64), "sqeuclid", [0, 3]),
+                                              ((90, 170, 100), "sqeuclid", [0, 1]),
                                               ((1, 9, 2), "sqeuclid", [0, 3]),
                                               ((300, 1100, 3), "sqeuclid", [0, 2]),
                                               ((260, 900, 2), "l1", [0, 1])])
@@ -65,8 +68,9 @@ def test_dt_summand_of_one_step_matches_oracle(shape, kind, steps):
     """One GPU step from the oracle's FP64 state at s, dt_partial starting at 0: the increment is
     the summand of D_{s+1} without its normaliser telescope.  Covers the D_t sums fused into the
     vector-ALU row sweep (d = 2, 3; 300 x 1100 and 260 x 900 split the columns 9 and 8 ways with
-    a ragged last split), the separate cost pass beside the FP64 matrix-core sweeps (d = 20),
-    each ground cost and a single row."""
+    a ragged last split) and into the FP64 matrix-core row sweep (d = 20, 64, 100: operand widths
+    32, 64 and 128; 1100 and 530 columns are 69 and 34 tiles of 16 with ragged last tiles over
+    several splits, 300 rows a ragged last wave), each ground cost and a single row."""
     n, m, d = shape
     wl, C, prob = _problem(n, m, d, kind, seed=300 + n)
     _say("case", wl.name, kind)
@@ -110,26 +114,31 @@ def test_dt_along_a_solve_and_midpoint_bound(kind, eta):
     assert abs(cert["midpoint_bound"] - ref_bound) <= 2.0 * tol / T + 1e-12
 
 
-def test_dt_summands_at_recomputed_rows():
-    """tau1 = 100 at eta = 0 (lam grows by 100 per iteration): in a two-iteration solve from an
-    oracle state the second iteration's row offsets, taken from the first, leave rows outside
+@pytest.mark.parametrize("d,tau1", [(2, 100.0), (24, 40.0)])
+def test_dt_summands_at_recomputed_rows(d, tau1):
+    """tau1 = 100 (40) at eta = 0 (lam grows by tau1 per iteration): in a two-iteration solve
+    from an oracle state the row offsets, taken from the previous iteration, leave rows outside
     [2^-60, 2^60]; row_finish recomputes their normalisers exactly (row_fallbacks > 0) and the
-    D_t pass of the tracked row sweep evaluates their <C, Xbar> share again in FP64.  The two
+    D_t pass of the tracked row sweep evaluates their <C, Xbar> share again in FP64 where its
+    B sums left that range (d = 2: the vector-ALU sweep's finish; d = 24: the FP64 matrix-core
+    sweep's, dimension at run time).  At d = 24 tau1 stays at 40: the matrix-core column
+    sweeps carry the A coupling's row factor 2^ew as an FP32 weight, |ew| up to
+    LOG2E (2 K tau1 max|theta - nu| + ln m), which overflows FP32 near tau1 = 100.  The two
     summands (without the normaliser telescope) against the oracle's."""
-    wl, C, prob = _problem(64, 80, 2, "sqeuclid", seed=71, eta=0.0)
-    prm = OL.Params(eta=0.0, tau1=100.0)
+    wl, C, prob = _problem(64, 80, d, "sqeuclid", seed=71, eta=0.0)
+    prm = OL.Params(eta=0.0, tau1=tau1)
     k = 5
     T = k + 2
     D, _, traces = OL.dt_sequence(C, wl.r, wl.c, prm, T, 1.0)
-    lam = OL.inv_eta_schedule(T, 100.0, 0.0)
+    lam = OL.inv_eta_schedule(T, tau1, 0.0)
     nu, th, nu_n = traces[k - 1].nu[0], traces[k - 1].theta[0], traces[k + 1].nu[0]
     telescope = float(wl.r @ (OL.log_normaliser(C, nu_n, lam[k + 2], 1.0) - OL.log_normaliser(C, nu, lam[k], 1.0)))
     ref = (D[k + 1] - D[k - 1]) - telescope
     st = P.State(torch.tensor(nu, device="cuda"), torch.tensor(th, device="cuda"), k, float(lam[k]), 0.0)
-    params = P.make_params(eta=0.0, tau1=100.0, max_iter=2, check_every=2, track_dt=True)
+    params = P.make_params(eta=0.0, tau1=tau1, max_iter=2, check_every=2, track_dt=True)
     st, rep, status = P.solve(prob, params, st)
     err = abs(st.dt_partial - ref)
-    _say(f"tau1 = 100: fallbacks {rep['row_fallbacks']}, gpu {st.dt_partial:.9e} oracle {ref:.9e} err {err:.2e}")
+    _say(f"d = {d}, tau1 = {tau1}: fallbacks {rep['row_fallbacks']}, gpu {st.dt_partial:.9e} oracle {ref:.9e} err {err:.2e}")
     assert status == 0 and st.t == k + 2
     assert rep["row_fallbacks"] > 0
     assert err <= 2.0 * DT_STEP_TOL * max(1.0, abs(ref))
