@@ -123,7 +123,7 @@ def test_dt_summands_at_recomputed_rows(d, tau1):
     B sums left that range (d = 2: the vector-ALU sweep's finish; d = 24: the FP64 matrix-core
     sweep's, dimension at run time).  At d = 24 tau1 stays at 40: the matrix-core column
     sweeps carry the A coupling's row factor 2^ew as an FP32 weight, |ew| up to
-    LOG2E (2 K tau1 max|theta - nu| + ln m), which overflows FP32 near tau1 = 100.  The two
+    LOG2E (K tau1 max|theta - nu| + ln m), which overflows FP32 near tau1 = 100.  The two
     summands (without the normaliser telescope) against the oracle's."""
     wl, C, prob = _problem(64, 80, d, "sqeuclid", seed=71, eta=0.0)
     prm = OL.Params(eta=0.0, tau1=tau1)
