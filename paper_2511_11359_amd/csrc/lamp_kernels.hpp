@@ -638,10 +638,21 @@ __device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, 
     double ew = rho * sigB - sigA;
     ew = fmin(fmax(ew, -1000.0), 1000.0);
     H[i] = hnew;
+    // The column sweeps that take FP32 row weights see the A factor 2^ew in w^A; a row with
+    // |ew| > 100 (large tau1: ew grows with K tau1 (theta - nu)) moves their shared offset by
+    // dl = ew / (c^A + c^B), which leaves |ew| / (1 + rho) in each weight's exponent
+    // (w^A 2^(c^A (x.y + k)) and w^B 2^(c^B (x.y + k)) are unchanged).
+    double kw = hnew, ea = ew, eb = 0.0;
+    if (fabs(ew) > 100.0) {
+        const double dl = ew / (cA + cB);
+        kw = hnew + dl;
+        ea = ew - cA * dl;
+        eb = -cB * dl;
+    }
     RowVar rv;
-    rv.k = hnew;
-    rv.wA = (float)(r[i] * exp2(ew));
-    rv.wB = (float)r[i];
+    rv.k = kw;
+    rv.wA = (float)(r[i] * exp2(ea));
+    rv.wB = (float)(r[i] * exp2(eb));
     rowvar[i] = rv;
     // the vector-ALU column sweep takes the row weights into its exponents: the A coupling's
     // row factor 2^ew (unclamped: no FP32 weight to overflow) and n r_i (1 for uniform r; the
@@ -651,10 +662,10 @@ __device__ __forceinline__ void row_finish_body(Ctrl* ctrl, const Sched* sched, 
         rowck[i] = make_double2(cA * hnew + (rho * sigB - sigA) + lw, cB * hnew + lw);
     }
     if (rf.q) {
-        const float kf = (float)hnew;
-        const double dk = hnew - (double)kf;
-        const float wa = (float)(r[i] * exp2(fmin(fmax(ew + cA * dk, -1000.0), 1000.0)));
-        const float wb = (float)(r[i] * exp2(cB * dk));
+        const float kf = (float)kw;
+        const double dk = kw - (double)kf;
+        const float wa = (float)(r[i] * exp2(fmin(fmax(ea + cA * dk, -1000.0), 1000.0)));
+        const float wb = (float)(r[i] * exp2(eb + cB * dk));
         rf.q[i] = make_float4(kf, wa, wb, 0.f);
     }
     if (log_za) log_za[i] = LN2 * (-sc.lamA * LOG2E * kc.s * xn2[i] + sigA);

@@ -121,10 +121,9 @@ def test_dt_summands_at_recomputed_rows(d, tau1):
     [2^-60, 2^60]; row_finish recomputes their normalisers exactly (row_fallbacks > 0) and the
     D_t pass of the tracked row sweep evaluates their <C, Xbar> share again in FP64 where its
     B sums left that range (d = 2: the vector-ALU sweep's finish; d = 24: the FP64 matrix-core
-    sweep's, dimension at run time).  At d = 24 tau1 stays at 40: the matrix-core column
-    sweeps carry the A coupling's row factor 2^ew as an FP32 weight, |ew| up to
-    LOG2E (K tau1 max|theta - nu| + ln m), which overflows FP32 near tau1 = 100.  The two
-    summands (without the normaliser telescope) against the oracle's."""
+    sweep's, dimension at run time).  The two summands (without the normaliser telescope)
+    against the oracle's (at d = 24 and tau1 = 100 the oracle's dense FP64 couplings underflow
+    inside its Bregman terms; that case is pinned through the duals below)."""
     wl, C, prob = _problem(64, 80, d, "sqeuclid", seed=71, eta=0.0)
     prm = OL.Params(eta=0.0, tau1=tau1)
     k = 5
@@ -142,6 +141,31 @@ def test_dt_summands_at_recomputed_rows(d, tau1):
     assert status == 0 and st.t == k + 2
     assert rep["row_fallbacks"] > 0
     assert err <= 2.0 * DT_STEP_TOL * max(1.0, abs(ref))
+
+
+def test_matrix_core_row_weights_at_large_tau1():
+    """d = 24 (FP64 matrix-core sweeps), tau1 = 100 at eta = 0: the A coupling's row factor
+    2^ew, |ew| up to LOG2E (K tau1 max|theta - nu| + ln m) (about 144 here), exceeds FP32 as a
+    weight of the matrix-core column sweep; row_finish shares it between both couplings'
+    weights by moving that sweep's offset for rows with |ew| > 100.  Two iterations from the
+    oracle's state at t = 5, the duals against the oracle's.  The columns carry FP32 sums of
+    relative error ~1e-6 and c^alpha_j ~ 1/m, so a dual moves by ~1e-6 (columns whose mass
+    underflows FP32 read 0 against ~1e-245 in FP64, which moves their duals by less)."""
+    wl, C, prob = _problem(64, 80, 24, "sqeuclid", seed=71, eta=0.0)
+    prm = OL.Params(eta=0.0, tau1=100.0)
+    k = 5
+    _, _, traces = OL.dt_sequence(C, wl.r, wl.c, prm, k + 2, 1.0)
+    lam = OL.inv_eta_schedule(k + 2, 100.0, 0.0)
+    st = P.State(torch.tensor(traces[k - 1].nu[0], device="cuda"),
+                 torch.tensor(traces[k - 1].theta[0], device="cuda"), k, float(lam[k]), 0.0)
+    params = P.make_params(eta=0.0, tau1=100.0, max_iter=2, check_every=2)
+    st, rep, status = P.solve(prob, params, st)
+    e_nu = np.max(np.abs(st.nu.cpu().numpy() - traces[k + 1].nu[0]))
+    e_th = np.max(np.abs(st.theta.cpu().numpy() - traces[k + 1].theta[0]))
+    _say(f"d = 24, tau1 = 100: fallbacks {rep['row_fallbacks']}, nu err {e_nu:.2e}, theta err {e_th:.2e}")
+    assert status == 0 and st.t == k + 2
+    assert rep["row_fallbacks"] > 0
+    assert e_nu <= 1e-5 and e_th <= 1e-5
 
 
 def test_dt_resume_untracked_and_rejected_forms():
