@@ -61,6 +61,8 @@ def _problem(n, m, d, kind, seed, eta=1e-2):
                                               ((300, 1100, 20), "sqeuclid", [0, 2]),
                                               ((200, 530, 64), "sqeuclid", [0, 3]),
                                               ((90, 170, 100), "sqeuclid", [0, 1]),
+                                              ((40, 50, 6), "l1", [0, 3]),
+                                              ((30, 40, 150), "sqeuclid", [0, 2]),
                                               ((1, 9, 2), "sqeuclid", [0, 3]),
                                               ((300, 1100, 3), "sqeuclid", [0, 2]),
                                               ((260, 900, 2), "l1", [0, 1])])
@@ -70,7 +72,9 @@ def test_dt_summand_of_one_step_matches_oracle(shape, kind, steps):
     vector-ALU row sweep (d = 2, 3; 300 x 1100 and 260 x 900 split the columns 9 and 8 ways with
     a ragged last split) and into the FP64 matrix-core row sweep (d = 20, 64, 100: operand widths
     32, 64 and 128; 1100 and 530 columns are 69 and 34 tiles of 16 with ragged last tiles over
-    several splits, 300 rows a ragged last wave), each ground cost and a single row."""
+    several splits, 300 rows a ragged last wave), the separate cost pass of the dimensions
+    without either (l1 at d = 6, squared Euclidean at d = 150), each ground cost and a single
+    row."""
     n, m, d = shape
     wl, C, prob = _problem(n, m, d, kind, seed=300 + n)
     _say("case", wl.name, kind)
